@@ -1,0 +1,80 @@
+"""Pins of the oracle's solvers on the 8^3 sphere case: FGMRES against LAPACK's
+dense LU (numpy.linalg.solve) of the explicitly assembled reduced system of
+section 2.4, the matrix-free Jacobian against that dense matrix, the block
+diagonal against the dense diagonal blocks, and Newton's convergence."""
+import numpy as np
+import pytest
+
+import fsi_workloads as W
+from oracle import dlm, jacobian, krylov, newton, vms
+
+
+def c1_problem(mask=True):
+    cfg = W.CONFIGS["c1"]
+    g = cfg.grid
+    prm = vms.params_array(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
+    a = W.advection_field(g, cfg.seed_fields)
+    X = W.sphere_points()
+    cell, xi = dlm.locate(g, X)
+    kappa = W.kappa_weights(X.shape[1], W.sphere_volume(), cfg.c_m, cfg.alpha)
+    s = dlm.s_field(g, cell, cfg.s_max)
+    m = W.channel_dirichlet_mask(g) if mask else None
+    return cfg, g, prm, a, cell, xi, kappa, s, m
+
+
+def test_matrix_free_jacobian_equals_dense_and_blocks():
+    cfg, g, prm, a, cell, xi, kappa, s, m = c1_problem()
+    N = g.num_nodes
+    J = jacobian.dense(g, prm, a, cell, xi, kappa, s=s, mask=m)
+    x = W.random_vector(4 * N, cfg.seed_vectors)
+    y = jacobian.apply(g, prm, a, x, cell, xi, kappa, s=s, mask=m).ravel()
+    assert np.abs(J @ x - y).max() <= 1e-13 * np.abs(y).max()
+    blocks = jacobian.diag_blocks(g, prm, a, cell, xi, kappa, s=s, mask=m)
+    for node in [0, 100, 364, 500, N - 1]:
+        idx = [f * N + node for f in range(4)]
+        assert np.allclose(blocks[node], J[np.ix_(idx, idx)], rtol=0, atol=1e-13 * np.abs(J).max())
+
+
+def test_fgmres_matches_dense_lu():
+    cfg, g, prm, a, cell, xi, kappa, s, m = c1_problem()
+    N = g.num_nodes
+    J = jacobian.dense(g, prm, a, cell, xi, kappa, s=s, mask=m)
+    b = W.smooth_fourier_field(g, cfg.seed_vectors).ravel()
+    mm = np.concatenate([m.ravel(), np.zeros(N, bool)])
+    b[mm] = 0.0
+    x_ref = np.linalg.solve(J, b)
+    blocks = jacobian.diag_blocks(g, prm, a, cell, xi, kappa, s=s, mask=m)
+    x, info = krylov.fgmres(lambda v: J @ v, b,
+                            precond=lambda v: jacobian.block_jacobi_apply(blocks, v).ravel(),
+                            restart=50, rtol=1e-10, max_iters=2000)
+    assert info["res"] <= 1e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(b - J @ x) <= 1e-10 * np.linalg.norm(b)
+    cond = np.linalg.cond(J)
+    assert np.linalg.norm(x - x_ref) <= 10 * cond * 1e-10 * np.linalg.norm(x_ref)
+    assert info["iters"] < 2000
+
+
+def test_newton_step_converges_dense_and_fgmres_agree():
+    cfg, g, prm, a, cell, xi, kappa, s, m = c1_problem()
+    N = g.num_nodes
+    X, Y, Z = W.node_coords(g)
+    u_old = 0.5 * W.advection_field(g, cfg.seed_fields)
+    gD = np.zeros((3, N))
+    gD[0] = np.where(X == 0.0, 1.0, 0.0)          # plug inflow on x = 0
+    gD[:, ~m[0]] = 0.0
+    g_pts = np.zeros((3, cell.size))               # solid at rest
+    x0 = np.concatenate([u_old, np.zeros((1, N))])
+    x0[:3][m] = gD[m]
+    x1, info1 = newton.solve_step(g, prm, x0, u_old, cell, xi, kappa, g_pts, s=s, mask=m, gD=gD,
+                                  linear="dense")
+    assert info1["converged"], info1["history"]
+    h = info1["history"]
+    assert h[-1] <= 1e-8 * h[0]
+    assert len(h) <= 12
+    x2, info2 = newton.solve_step(g, prm, x0, u_old, cell, xi, kappa, g_pts, s=s, mask=m, gD=gD,
+                                  linear="fgmres", tol_abs=info1["tol_abs"])
+    assert info2["converged"]
+    # both satisfy the same absolute residual bound; the states agree accordingly
+    assert np.linalg.norm(x1 - x2) <= 1e-6 * np.linalg.norm(x1)
+    R = newton.residual(g, prm, x1, u_old, cell, xi, kappa, g_pts, s=s, mask=m, gD=gD)
+    assert np.linalg.norm(R) <= info1["tol_abs"]
