@@ -1,0 +1,216 @@
+/*
+ * fsi.h - C ABI of the MI355X (gfx950) library for the Jacobian hot path of
+ * the fully implicit, monolithic fictitious-domain / distributed-Lagrange-
+ * multiplier (FD/DLM) immersed FSI method of arXiv 2601.08266.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Array pointers are DEVICE pointers owned by the caller, unless an argument
+ *   says "host".  The library never allocates, frees or retains caller memory.
+ * - Work that needs scratch memory takes an explicit workspace (ws, ws_bytes)
+ *   whose minimum size the matching *_workspace() query returns; a smaller
+ *   workspace is rejected with FSI_ERR_WORKSPACE before anything is launched.
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Calls enqueue work on it and return without synchronising, unless the
+ *   comment says SYNCS.
+ * - Arguments are validated before any launch; a bad argument returns
+ *   FSI_ERR_ARG and launches nothing.  A failed HIP call returns FSI_ERR_HIP.
+ *   fsi_last_error() returns a thread-local message for the last failure.
+ *   No C++ exception crosses the ABI.
+ * - Grids are uniform hexahedral: n[d] cells per axis, cell size h[d], origin
+ *   x0[d]; Lagrange order p = `order` (1 or 2) for all four fields (the
+ *   equal-order velocity/pressure pairs of section 2.1).  Nodes per axis
+ *   N_d = p n[d] + 1, node id = i + N_0 (j + N_1 k).  Cells are numbered the
+ *   same way with n[d].  Vectors are structure-of-arrays, field-major:
+ *   x[f * N + node] with f = 0,1,2 the velocity components and f = 3 the
+ *   pressure; velocity-only arrays are [3][N].
+ * - Precision: `dtype` selects FP64 (double) or FP32 (float) for the floating
+ *   point arrays named "T" below; the same call computes in that precision.
+ */
+#ifndef FSI_H
+#define FSI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FSI_OK = 0,
+    FSI_ERR_ARG = -1,            /* invalid argument (nothing launched) */
+    FSI_ERR_HIP = -2,            /* a HIP runtime call failed */
+    FSI_ERR_WORKSPACE = -3,      /* workspace missing or too small */
+    FSI_ERR_NOT_CONVERGED = -4,  /* iteration cap reached */
+    FSI_ERR_BREAKDOWN = -5,      /* Krylov breakdown */
+    FSI_ERR_NAN = -6,            /* NaN/Inf detected in a norm */
+    FSI_ERR_UNSUPPORTED = -7     /* valid but not implemented combination */
+} fsi_status;
+
+typedef enum { FSI_F64 = 0, FSI_F32 = 1 } fsi_dtype;
+
+typedef struct {
+    int32_t n[3];      /* cells per axis, >= 1 */
+    int32_t order;     /* 1 (Q1-Q1) or 2 (Q2-Q2) */
+    double x0[3];      /* origin of the box */
+    double h[3];       /* cell size per axis, > 0 */
+} fsi_grid;
+
+/*
+ * Parameters of the Oseen-VMS operator (section 2.1, per unit density so the
+ * paper's mu/rho is nu):
+ *   nu   kinematic viscosity
+ *   c_m  mass coefficient of the time discretisation (1/dt for backward Euler)
+ *   dt   time step entering tau_m through C_T/dt^2
+ *   C_T, C_I  constants of tau_m (4 and 36 in the paper)
+ *   visc_strong  nonzero: the strong momentum residual keeps -nu(lap u + grad div u)
+ */
+typedef struct {
+    double nu, c_m, dt, C_T, C_I;
+    int32_t visc_strong;
+} fsi_vms_params;
+
+/* Static description of a status code (never NULL). */
+const char *fsi_status_string(int status);
+/* Thread-local message describing the last failure on this thread ("" if none). */
+const char *fsi_last_error(void);
+/* Library version string. */
+const char *fsi_version(void);
+
+/*
+ * fsi_vms_apply - y = A(a, s) x, the VMS-stabilised Oseen operator.
+ *
+ * Section 2.1: the Galerkin weak form (eq. fluid_weak_form) linearised about
+ * the advection field a, plus residual-based SUPG, PSPG and grad-div (LSIC)
+ * terms with tau_m = (s (C_T/dt^2 + a.G a + C_I nu^2 G:G))^(-1/2),
+ * tau_c = (tau_m tr G)^(-1), G_ij = sum_k dxi_k/dx_i dxi_k/dx_j (the
+ * stabilisation-parameter equations; reference element [0,1]^3 so G = I/h^2).
+ * These are the momentum/continuity blocks of the reduced system of section
+ * 2.4.  Gauss quadrature with p+1 points per axis; a and s are interpolated
+ * with the element basis, s clamped below by the cell's smallest nodal s.
+ *
+ *   grid, prm  host pointers
+ *   a          T [3][N] advection field (device)
+ *   s          T [N] interface scaling field, or NULL for s = 1 (device)
+ *   dir_mask   uint32 bitmask over the 3N velocity DOFs (bit k of the stream
+ *              = word k/32, bit k%32; k = f*N + node), or NULL.  Masked DOFs
+ *              are Dirichlet: their columns are treated as zero and their rows
+ *              as the identity (y_k = x_k).
+ *   x          T [4][N] input (device);  y  T [4][N] output, overwritten.
+ *              x and y must not overlap.
+ *   ws         workspace of at least fsi_vms_apply_workspace(grid, dtype) bytes.
+ * Deterministic: identical inputs give bitwise identical outputs.
+ */
+size_t fsi_vms_apply_workspace(const fsi_grid *grid, fsi_dtype dtype);
+int fsi_vms_apply(const fsi_grid *grid, const fsi_vms_params *prm, fsi_dtype dtype,
+                  const void *a, const void *s, const uint32_t *dir_mask,
+                  const void *x, void *y, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * fsi_dlm_locate - find the background cell and parametric position of each
+ * solid point, sort the points by cell, and mark the interface band of s.
+ *
+ * Section 2.3 (eq. nodal_solid_velo evaluates fluid shape functions at the
+ * current solid point positions) and appendix A (point search -> element
+ * number and parametric position xi -> shape function evaluation).  Cell rule:
+ * with breakpoints b_k = x0 + k h (FP64, as written, no fused multiply-add),
+ * a coordinate X lies in cell i when b_i <= X <= b_{i+1}; the largest such i
+ * is taken; X outside [b_0, b_n] on any axis marks the point outside
+ * (cell = -1, not an error).  xi_d = (X_d - (x0_d + i_d h_d)) / h_d, computed
+ * in FP64 and stored in `dtype`.
+ *
+ *   X          double [3][M] point positions (device)
+ *   cell       int32 [M] out: cell id or -1
+ *   xi         T [3][M] out: parametric position (0 for outside points)
+ *   perm       int32 [M] out: point indices sorted by cell, stable (ties keep
+ *              increasing point index), outside points last
+ *   occ_cell   int32 [E] out: ascending ids of occupied cells (first n_occ used)
+ *   occ_start  int32 [E+1] out: perm[occ_start[k] .. occ_start[k+1]) are the
+ *              points of occ_cell[k]
+ *   occ_index  int32 [E] out: k for the cell occ_cell[k], -1 for empty cells
+ *   s_out      T [N] out or NULL: s = s_max on every node of an occupied cell,
+ *              1 elsewhere (section 2.1's interface band, O(h) wide)
+ *   n_occ_host, n_outside_host  HOST int64 out (may be NULL).  SYNCS the stream.
+ *   ws         at least fsi_dlm_locate_workspace(grid, m) bytes.
+ * M must be < 2^31 and the number of cells E < 2^31 - 1.
+ */
+size_t fsi_dlm_locate_workspace(const fsi_grid *grid, int64_t m);
+int fsi_dlm_locate(const fsi_grid *grid, int64_t m, const double *X, fsi_dtype dtype,
+                   int32_t *cell, void *xi, int32_t *perm, int32_t *occ_cell,
+                   int32_t *occ_start, int32_t *occ_index, void *s_out, double s_max,
+                   int64_t *n_occ_host, int64_t *n_outside_host,
+                   void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * fsi_dlm_B - interpolate the fluid velocity at the solid points:
+ * (B u)_B = sum_A N_A(xi_B) u_A, per component (section 2.3, eq.
+ * nodal_solid_velo; also the solid acceleration increment of section 2.4,
+ * Delta U = (C^lambda)^T Delta V).
+ *   cell, xi   from fsi_dlm_locate (device); points with cell = -1 give 0
+ *   u          T [3][N] (device; the velocity part of a [4][N] vector works)
+ *   Bu         T [3][M] out, overwritten
+ */
+int fsi_dlm_B(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const int32_t *cell,
+              const void *xi, const void *u, void *Bu, void *stream);
+
+/*
+ * fsi_dlm_BT - spread point forces to the fluid nodes:
+ * y_A += sum_B N_A(xi_B) kappa_B lam_B, per component (section 2.3, eq.
+ * fsi_constraint_matrix: C^lambda_AB = N_A(phi(X_B)) I, "force spreading").
+ * Segmented: points are reduced per occupied cell in perm order, then each
+ * node gathers the corner sums of its occupied neighbour cells in a fixed
+ * order, so the result is deterministic without floating-point atomics.
+ *   perm, occ_cell, occ_start, occ_index, n_occ  from fsi_dlm_locate
+ *   lam        T [3][M];  kappa  T [M] or NULL (kappa = 1)
+ *   y          T [3][N], ACCUMULATED (y += ...)
+ *   ws         at least fsi_dlm_BT_workspace(grid, n_occ, dtype) bytes
+ */
+size_t fsi_dlm_BT_workspace(const fsi_grid *grid, int64_t n_occ, fsi_dtype dtype);
+int fsi_dlm_BT(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const int32_t *cell,
+               const void *xi, const int32_t *perm, const int32_t *occ_cell,
+               const int32_t *occ_start, const int32_t *occ_index, int64_t n_occ,
+               const void *lam, const void *kappa, void *y, void *ws, size_t ws_bytes,
+               void *stream);
+
+/*
+ * Everything the Jacobian of the reduced system needs (section 2.4):
+ *   J = A_VMS(a, s) + [[B^T diag(kappa) B, 0], [0, 0]],
+ * i.e. the paper's dR^{f,m}/dV + C^lambda dR^s/dU (C^lambda)^T block with the
+ * solid tangent replaced by the per-point diagonal stand-in kappa_B I.
+ * Dirichlet velocity DOFs (dir_mask) have identity rows and zero columns.
+ * All arrays are device pointers in precision `dtype`, except the integer
+ * point tables.  m = 0 (no solid) is allowed.
+ */
+typedef struct {
+    fsi_grid grid;
+    fsi_vms_params prm;
+    fsi_dtype dtype;
+    const void *a;             /* T [3][N] */
+    const void *s;             /* T [N] or NULL */
+    const uint32_t *dir_mask;  /* or NULL */
+    int64_t m;                 /* number of solid points */
+    const int32_t *cell;       /* [M] */
+    const void *xi;            /* T [3][M] */
+    const int32_t *perm;       /* [M] */
+    const int32_t *occ_cell;   /* [n_occ] */
+    const int32_t *occ_start;  /* [n_occ + 1] */
+    const int32_t *occ_index;  /* [E] */
+    int64_t n_occ;
+    const void *kappa;         /* T [M] */
+} fsi_problem;
+
+/*
+ * fsi_jacobian_apply - y = J x for the problem above (x, y: T [4][N] device,
+ * not overlapping).  ws: at least fsi_jacobian_workspace(problem) bytes.
+ * Deterministic.
+ */
+size_t fsi_jacobian_workspace(const fsi_problem *problem);
+int fsi_jacobian_apply(const fsi_problem *problem, const void *x, void *y, void *ws,
+                       size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSI_H */

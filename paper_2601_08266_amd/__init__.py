@@ -1,0 +1,272 @@
+"""MI355X (gfx950) library for the Jacobian hot path of the immersed FD/DLM FSI
+method of arXiv 2601.08266 - Python binding.
+
+The binding only marshals arguments: every step of the path runs in the HIP
+kernels of libfsi.so behind the C ABI of include/fsi.h.  PyTorch tensors
+supply device memory and the current stream.  Names follow the C ABI
+(fsi_vms_apply -> vms_apply, ...).  There is no CPU fallback: if the library
+is missing, importing a function that needs it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+from . import _lib as L
+from ._lib import FSI_F32, FSI_F64, FsiError, FsiGrid, FsiProblem, FsiVmsParams
+
+__all__ = [
+    "FSI_F64", "FSI_F32", "FsiError", "make_grid", "make_params", "version",
+    "vms_apply_workspace", "vms_apply", "PointTables", "dlm_locate", "dlm_B", "dlm_BT",
+    "Problem", "jacobian_apply", "jacobian_workspace",
+]
+
+_TORCH_OF = {FSI_F64: torch.float64, FSI_F32: torch.float32}
+
+
+def version() -> str:
+    return L.lib().fsi_version().decode()
+
+
+def dtype_code(t: torch.dtype) -> int:
+    if t == torch.float64:
+        return FSI_F64
+    if t == torch.float32:
+        return FSI_F32
+    raise TypeError(f"unsupported dtype {t}")
+
+
+def make_grid(n, order=1, x0=(0.0, 0.0, 0.0), h=None) -> FsiGrid:
+    """Grid struct from cell counts, order, origin and cell size (default 1/n)."""
+    if h is None:
+        h = tuple(1.0 / float(v) for v in n)
+    g = FsiGrid()
+    for d in range(3):
+        g.n[d] = int(n[d])
+        g.x0[d] = float(x0[d])
+        g.h[d] = float(h[d])
+    g.order = int(order)
+    return g
+
+
+def grid_from(obj) -> FsiGrid:
+    if isinstance(obj, FsiGrid):
+        return obj
+    return make_grid(obj.n, obj.order, obj.x0, obj.h)
+
+
+def make_params(nu, c_m, dt, C_T=4.0, C_I=36.0, visc_strong=True) -> FsiVmsParams:
+    p = FsiVmsParams()
+    p.nu, p.c_m, p.dt, p.C_T, p.C_I = float(nu), float(c_m), float(dt), float(C_T), float(C_I)
+    p.visc_strong = 1 if visc_strong else 0
+    return p
+
+
+def num_nodes(g: FsiGrid) -> int:
+    return (g.order * g.n[0] + 1) * (g.order * g.n[1] + 1) * (g.order * g.n[2] + 1)
+
+
+def num_cells(g: FsiGrid) -> int:
+    return g.n[0] * g.n[1] * g.n[2]
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t: torch.Tensor, name: str, dtype=None, numel=None):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+
+
+def _workspace(nbytes: int, device, ws: Optional[torch.Tensor]):
+    if ws is not None:
+        if ws.numel() * ws.element_size() < nbytes:
+            raise ValueError("workspace too small")
+        return ws
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+# --------------------------------------------------------------------------- VMS
+def vms_apply_workspace(grid, dtype: torch.dtype) -> int:
+    g = grid_from(grid)
+    return int(L.lib().fsi_vms_apply_workspace(ctypes.byref(g), dtype_code(dtype)))
+
+
+def vms_apply(grid, prm: FsiVmsParams, a: torch.Tensor, x: torch.Tensor,
+              s: Optional[torch.Tensor] = None, mask: Optional[torch.Tensor] = None,
+              y: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None):
+    """y = A(a, s) x (fsi_vms_apply)."""
+    g = grid_from(grid)
+    N = num_nodes(g)
+    dt = x.dtype
+    _need(x, "x", dt, 4 * N)
+    _need(a, "a", dt, 3 * N)
+    if s is not None:
+        _need(s, "s", dt, N)
+    if mask is not None:
+        _need(mask, "mask", torch.int32)
+    if y is None:
+        y = torch.empty_like(x)
+    _need(y, "y", dt, 4 * N)
+    nbytes = vms_apply_workspace(g, dt)
+    ws = _workspace(nbytes, x.device, ws)
+    L.check("fsi_vms_apply", L.lib().fsi_vms_apply(
+        ctypes.byref(g), ctypes.byref(prm), dtype_code(dt), _ptr(a), _ptr(s), _ptr(mask), _ptr(x),
+        _ptr(y), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+    return y
+
+
+# --------------------------------------------------------------------------- DLM
+@dataclass
+class PointTables:
+    """Output of fsi_dlm_locate (device tensors) plus the two host counts."""
+
+    m: int
+    cell: torch.Tensor
+    xi: torch.Tensor
+    perm: torch.Tensor
+    occ_cell: torch.Tensor
+    occ_start: torch.Tensor
+    occ_index: torch.Tensor
+    n_occ: int
+    n_outside: int
+    s: Optional[torch.Tensor] = None
+
+
+def dlm_locate(grid, X: torch.Tensor, dtype: torch.dtype = torch.float64,
+               s_max: Optional[float] = None, ws: Optional[torch.Tensor] = None,
+               stream=None) -> PointTables:
+    """Cell, parametric position, cell-sorted order and occupied-cell CSR (fsi_dlm_locate)."""
+    g = grid_from(grid)
+    _need(X, "X", torch.float64)
+    if X.numel() % 3:
+        raise ValueError("X must be [3][M]")
+    m = X.numel() // 3
+    dev = X.device
+    E = num_cells(g)
+    cell = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    xi = torch.empty(3 * max(m, 1), dtype=dtype, device=dev)
+    perm = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    occ_cell = torch.empty(E, dtype=torch.int32, device=dev)
+    occ_start = torch.zeros(E + 1, dtype=torch.int32, device=dev)
+    occ_index = torch.empty(E, dtype=torch.int32, device=dev)
+    s = torch.empty(num_nodes(g), dtype=dtype, device=dev) if s_max is not None else None
+    nbytes = int(L.lib().fsi_dlm_locate_workspace(ctypes.byref(g), m))
+    ws = _workspace(nbytes, dev, ws)
+    n_occ = ctypes.c_int64(0)
+    n_out = ctypes.c_int64(0)
+    L.check("fsi_dlm_locate", L.lib().fsi_dlm_locate(
+        ctypes.byref(g), m, _ptr(X), dtype_code(dtype), _ptr(cell), _ptr(xi), _ptr(perm),
+        _ptr(occ_cell), _ptr(occ_start), _ptr(occ_index), _ptr(s),
+        float(s_max if s_max is not None else 1.0), ctypes.byref(n_occ), ctypes.byref(n_out),
+        _ptr(ws), ws.numel(), _stream(stream)))
+    return PointTables(m, cell[:m], xi[:3 * m], perm[:m], occ_cell, occ_start, occ_index,
+                       int(n_occ.value), int(n_out.value), s)
+
+
+def dlm_B(grid, tables: PointTables, u: torch.Tensor, Bu: Optional[torch.Tensor] = None,
+          stream=None) -> torch.Tensor:
+    """(B u)_B = sum_A N_A(xi_B) u_A (fsi_dlm_B).  u: [3][N] (or the first 3N of a [4][N])."""
+    g = grid_from(grid)
+    N = num_nodes(g)
+    dt = tables.xi.dtype
+    _need(u, "u", dt)
+    if u.numel() < 3 * N:
+        raise ValueError("u must hold at least 3N values")
+    m = tables.m
+    if Bu is None:
+        Bu = torch.empty(3 * max(m, 1), dtype=dt, device=u.device)
+    L.check("fsi_dlm_B", L.lib().fsi_dlm_B(
+        ctypes.byref(g), dtype_code(dt), m, _ptr(tables.cell), _ptr(tables.xi), _ptr(u), _ptr(Bu),
+        _stream(stream)))
+    return Bu[:3 * m]
+
+
+def dlm_BT(grid, tables: PointTables, lam: torch.Tensor, y: torch.Tensor,
+           kappa: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+           stream=None) -> torch.Tensor:
+    """y += B^T (kappa * lam) (fsi_dlm_BT); y: [3][N] (or a [4][N] whose first 3N are used)."""
+    g = grid_from(grid)
+    dt = tables.xi.dtype
+    _need(lam, "lam", dt, 3 * tables.m)
+    _need(y, "y", dt)
+    if kappa is not None:
+        _need(kappa, "kappa", dt, tables.m)
+    nbytes = int(L.lib().fsi_dlm_BT_workspace(ctypes.byref(g), tables.n_occ, dtype_code(dt)))
+    ws = _workspace(nbytes, y.device, ws)
+    L.check("fsi_dlm_BT", L.lib().fsi_dlm_BT(
+        ctypes.byref(g), dtype_code(dt), tables.m, _ptr(tables.cell), _ptr(tables.xi),
+        _ptr(tables.perm), _ptr(tables.occ_cell), _ptr(tables.occ_start), _ptr(tables.occ_index),
+        tables.n_occ, _ptr(lam), _ptr(kappa), _ptr(y), _ptr(ws), ws.numel(), _stream(stream)))
+    return y
+
+
+# --------------------------------------------------------------------------- Jacobian
+class Problem:
+    """fsi_problem: everything J = A_VMS + B^T diag(kappa) B needs, in one precision."""
+
+    def __init__(self, grid, prm: FsiVmsParams, a: torch.Tensor, tables: Optional[PointTables],
+                 kappa: Optional[torch.Tensor], s: Optional[torch.Tensor] = None,
+                 mask: Optional[torch.Tensor] = None):
+        g = grid_from(grid)
+        dt = a.dtype
+        self.grid, self.prm, self.dtype = g, prm, dt
+        self.a, self.s, self.mask, self.tables, self.kappa = a, s, mask, tables, kappa
+        st = FsiProblem()
+        st.grid = g
+        st.prm = prm
+        st.dtype = dtype_code(dt)
+        st.a = a.data_ptr()
+        st.s = s.data_ptr() if s is not None else None
+        st.dir_mask = mask.data_ptr() if mask is not None else None
+        if tables is not None and tables.m > 0:
+            if tables.xi.dtype != dt or (kappa is not None and kappa.dtype != dt):
+                raise TypeError("point tables and kappa must match the problem precision")
+            st.m = tables.m
+            st.cell = tables.cell.data_ptr()
+            st.xi = tables.xi.data_ptr()
+            st.perm = tables.perm.data_ptr()
+            st.occ_cell = tables.occ_cell.data_ptr()
+            st.occ_start = tables.occ_start.data_ptr()
+            st.occ_index = tables.occ_index.data_ptr()
+            st.n_occ = tables.n_occ
+            st.kappa = kappa.data_ptr() if kappa is not None else None
+        self.struct = st
+        self.N = num_nodes(g)
+
+    def workspace_bytes(self) -> int:
+        return int(L.lib().fsi_jacobian_workspace(ctypes.byref(self.struct)))
+
+
+def jacobian_workspace(problem: Problem) -> int:
+    return problem.workspace_bytes()
+
+
+def jacobian_apply(problem: Problem, x: torch.Tensor, y: Optional[torch.Tensor] = None,
+                   ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """y = J x (fsi_jacobian_apply)."""
+    _need(x, "x", problem.dtype, 4 * problem.N)
+    if y is None:
+        y = torch.empty_like(x)
+    _need(y, "y", problem.dtype, 4 * problem.N)
+    ws = _workspace(problem.workspace_bytes(), x.device, ws)
+    L.check("fsi_jacobian_apply", L.lib().fsi_jacobian_apply(
+        ctypes.byref(problem.struct), _ptr(x), _ptr(y), _ptr(ws), ws.numel(), _stream(stream)))
+    return y

@@ -1,0 +1,97 @@
+"""ctypes declarations of the C ABI in include/fsi.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfsi.so")
+
+FSI_OK = 0
+FSI_ERR_ARG = -1
+FSI_ERR_HIP = -2
+FSI_ERR_WORKSPACE = -3
+FSI_ERR_NOT_CONVERGED = -4
+FSI_ERR_BREAKDOWN = -5
+FSI_ERR_NAN = -6
+FSI_ERR_UNSUPPORTED = -7
+
+FSI_F64 = 0
+FSI_F32 = 1
+
+
+class FsiGrid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("order", ctypes.c_int32),
+                ("x0", ctypes.c_double * 3), ("h", ctypes.c_double * 3)]
+
+
+class FsiVmsParams(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_double), ("c_m", ctypes.c_double), ("dt", ctypes.c_double),
+                ("C_T", ctypes.c_double), ("C_I", ctypes.c_double),
+                ("visc_strong", ctypes.c_int32)]
+
+
+class FsiProblem(ctypes.Structure):
+    _fields_ = [("grid", FsiGrid), ("prm", FsiVmsParams), ("dtype", ctypes.c_int),
+                ("a", ctypes.c_void_p), ("s", ctypes.c_void_p), ("dir_mask", ctypes.c_void_p),
+                ("m", ctypes.c_int64), ("cell", ctypes.c_void_p), ("xi", ctypes.c_void_p),
+                ("perm", ctypes.c_void_p), ("occ_cell", ctypes.c_void_p),
+                ("occ_start", ctypes.c_void_p), ("occ_index", ctypes.c_void_p),
+                ("n_occ", ctypes.c_int64), ("kappa", ctypes.c_void_p)]
+
+
+class FsiError(RuntimeError):
+    def __init__(self, func, code, msg):
+        super().__init__(f"{func} failed with status {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+P = ctypes.c_void_p
+I64 = ctypes.c_int64
+SZ = ctypes.c_size_t
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "fsi_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "fsi_last_error": (ctypes.c_char_p, []),
+    "fsi_version": (ctypes.c_char_p, []),
+    "fsi_vms_apply_workspace": (SZ, [ctypes.POINTER(FsiGrid), ctypes.c_int]),
+    "fsi_vms_apply": (ctypes.c_int, [ctypes.POINTER(FsiGrid), ctypes.POINTER(FsiVmsParams),
+                                     ctypes.c_int, P, P, P, P, P, P, SZ, P]),
+    "fsi_dlm_locate_workspace": (SZ, [ctypes.POINTER(FsiGrid), I64]),
+    "fsi_dlm_locate": (ctypes.c_int, [ctypes.POINTER(FsiGrid), I64, P, ctypes.c_int, P, P, P, P, P,
+                                      P, P, ctypes.c_double, ctypes.POINTER(I64),
+                                      ctypes.POINTER(I64), P, SZ, P]),
+    "fsi_dlm_B": (ctypes.c_int, [ctypes.POINTER(FsiGrid), ctypes.c_int, I64, P, P, P, P, P]),
+    "fsi_dlm_BT_workspace": (SZ, [ctypes.POINTER(FsiGrid), I64, ctypes.c_int]),
+    "fsi_dlm_BT": (ctypes.c_int, [ctypes.POINTER(FsiGrid), ctypes.c_int, I64, P, P, P, P, P, P, I64,
+                                  P, P, P, P, SZ, P]),
+    "fsi_jacobian_workspace": (SZ, [ctypes.POINTER(FsiProblem)]),
+    "fsi_jacobian_apply": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, P, SZ, P]),
+}
+
+
+def lib():
+    """Load libfsi.so (built in-tree by build.py); fail loudly if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} not found: build the HIP library first "
+                "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(func: str, code: int):
+    if code != FSI_OK:
+        msg = lib().fsi_last_error().decode(errors="replace")
+        raise FsiError(func, code, msg)
+    return code

@@ -1,0 +1,325 @@
+// C ABI entry points: argument validation, workspace layout and dispatch.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+
+#include "dlm.hpp"
+#include "kernels.hpp"
+
+namespace fsi {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = 0; }
+
+int check_grid(const fsi_grid *g)
+{
+    FSI_CHECK_ARG(g != nullptr, "grid is NULL");
+    FSI_CHECK_ARG(g->order == 1 || g->order == 2, "order must be 1 or 2 (got %d)", g->order);
+    int64_t N = 1, E = 1;
+    for (int d = 0; d < 3; ++d) {
+        FSI_CHECK_ARG(g->n[d] >= 1, "n[%d] must be >= 1", d);
+        FSI_CHECK_ARG(std::isfinite(g->h[d]) && g->h[d] > 0.0, "h[%d] must be finite and > 0", d);
+        FSI_CHECK_ARG(std::isfinite(g->x0[d]), "x0[%d] must be finite", d);
+        N *= (int64_t)g->order * g->n[d] + 1;
+        E *= g->n[d];
+    }
+    FSI_CHECK_ARG(E < ((int64_t)1 << 31) - 1, "too many cells (%lld)", (long long)E);
+    FSI_CHECK_ARG(N < ((int64_t)1 << 40), "too many nodes");
+    return FSI_OK;
+}
+
+static int check_params(const fsi_vms_params *p)
+{
+    FSI_CHECK_ARG(p != nullptr, "params are NULL");
+    FSI_CHECK_ARG(std::isfinite(p->nu) && p->nu >= 0.0, "nu must be finite and >= 0");
+    FSI_CHECK_ARG(std::isfinite(p->c_m) && p->c_m >= 0.0, "c_m must be finite and >= 0");
+    FSI_CHECK_ARG(std::isfinite(p->dt) && p->dt > 0.0, "dt must be finite and > 0");
+    FSI_CHECK_ARG(std::isfinite(p->C_T) && p->C_T >= 0.0, "C_T must be finite and >= 0");
+    FSI_CHECK_ARG(std::isfinite(p->C_I) && p->C_I >= 0.0, "C_I must be finite and >= 0");
+    return FSI_OK;
+}
+
+template <typename T>
+VmsConst<T> make_vms_const(const Geo &g, const fsi_vms_params &prm, bool has_s)
+{
+    VmsConst<T> k;
+    double GG = 0.0, trG = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const double ih2 = 1.0 / (g.h[d] * g.h[d]);
+        GG += ih2 * ih2;
+        trG += ih2;
+        k.ih[d] = (T)(1.0 / g.h[d]);
+        k.ih2[d] = (T)ih2;
+    }
+    k.c_m = (T)prm.c_m;
+    k.nu = (T)prm.nu;
+    k.K1 = (T)(prm.C_T / (prm.dt * prm.dt) + prm.C_I * prm.nu * prm.nu * GG);
+    k.inv_trG = (T)(1.0 / trG);
+    k.detJ = (T)(g.h[0] * g.h[1] * g.h[2]);
+    k.visc_strong = prm.visc_strong ? 1 : 0;
+    k.has_s = has_s ? 1 : 0;
+    return k;
+}
+template VmsConst<double> make_vms_const<double>(const Geo &, const fsi_vms_params &, bool);
+template VmsConst<float> make_vms_const<float>(const Geo &, const fsi_vms_params &, bool);
+
+BrickLayout brick_layout(const Geo &g)
+{
+    BrickLayout b;
+    if (g.p == 1) {
+        b.bx = Q1_BX; b.by = Q1_BY; b.bz = Q1_BZ; b.nl = Q1_NL;
+    } else {
+        b.bx = Q2_BX; b.by = Q2_BY; b.bz = Q2_BZ; b.nl = Q2_NL;
+    }
+    b.nbx = (g.n[0] + b.bx - 1) / b.bx;
+    b.nby = (g.n[1] + b.by - 1) / b.by;
+    b.nbz = (g.n[2] + b.bz - 1) / b.bz;
+    b.nb = (int64_t)b.nbx * b.nby * b.nbz;
+    return b;
+}
+
+size_t vms_workspace_bytes(const Geo &g, fsi_dtype dt)
+{
+    const BrickLayout b = brick_layout(g);
+    return align_up((size_t)b.nb * 4 * b.nl * (dt == FSI_F64 ? 8 : 4));
+}
+
+// declared in the kernel translation units
+template <typename T>
+int launch_q1_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, const T *s,
+                    const uint32_t *mask, T *part, const BrickLayout &bl, hipStream_t st);
+template <typename T>
+int launch_q2_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, const T *s,
+                    const uint32_t *mask, T *part, const BrickLayout &bl, hipStream_t st);
+template <typename T, int P, int BX, int BY, int BZ>
+int launch_gather(const Geo &g, const T *part, const BrickLayout &bl, const T *x,
+                  const uint32_t *mask, T *y, const T *csum, const int32_t *occ_index,
+                  hipStream_t st);
+
+template <typename T>
+static int vms_apply_t(const Geo &g, const fsi_vms_params &prm, const T *a, const T *s,
+                       const uint32_t *mask, const T *x, T *y, const DlmView *dlm, void *ws,
+                       hipStream_t st)
+{
+    const BrickLayout bl = brick_layout(g);
+    const VmsConst<T> k = make_vms_const<T>(g, prm, s != nullptr);
+    T *part = reinterpret_cast<T *>(ws);
+    const size_t vbytes = vms_workspace_bytes(g, sizeof(T) == 8 ? FSI_F64 : FSI_F32);
+    T *csum = nullptr;
+    int rc;
+    if (g.p == 1)
+        rc = launch_q1_cells<T>(g, k, x, a, s, mask, part, bl, st);
+    else
+        rc = launch_q2_cells<T>(g, k, x, a, s, mask, part, bl, st);
+    if (rc) return rc;
+    if (dlm != nullptr && dlm->n_occ > 0) {
+        csum = reinterpret_cast<T *>(reinterpret_cast<char *>(ws) + vbytes);
+        rc = launch_dlm_cell_reduce(g, sizeof(T) == 8 ? FSI_F64 : FSI_F32, true, dlm->m, dlm->n_occ,
+                                    dlm->occ_cell, dlm->occ_start, dlm->perm, dlm->xi, dlm->kappa, x,
+                                    mask, csum, st);
+        if (rc) return rc;
+    }
+    const int32_t *occ_index = csum ? dlm->occ_index : nullptr;
+    if (g.p == 1)
+        return launch_gather<T, 1, Q1_BX, Q1_BY, Q1_BZ>(g, part, bl, x, mask, y, csum, occ_index, st);
+    return launch_gather<T, 2, Q2_BX, Q2_BY, Q2_BZ>(g, part, bl, x, mask, y, csum, occ_index, st);
+}
+
+int launch_vms_apply(const Geo &g, const fsi_vms_params &prm, fsi_dtype dt, const void *a,
+                     const void *s, const uint32_t *mask, const void *x, void *y,
+                     const DlmView *dlm, void *ws, size_t ws_bytes, hipStream_t st)
+{
+    (void)ws_bytes;
+    if (dt == FSI_F64)
+        return vms_apply_t<double>(g, prm, (const double *)a, (const double *)s, mask,
+                                   (const double *)x, (double *)y, dlm, ws, st);
+    return vms_apply_t<float>(g, prm, (const float *)a, (const float *)s, mask, (const float *)x,
+                              (float *)y, dlm, ws, st);
+}
+
+}  // namespace fsi
+
+using namespace fsi;
+
+#define FSI_API extern "C" __attribute__((visibility("default")))
+
+FSI_API const char *fsi_status_string(int status)
+{
+    switch (status) {
+    case FSI_OK: return "ok";
+    case FSI_ERR_ARG: return "invalid argument";
+    case FSI_ERR_HIP: return "HIP runtime error";
+    case FSI_ERR_WORKSPACE: return "workspace missing or too small";
+    case FSI_ERR_NOT_CONVERGED: return "not converged";
+    case FSI_ERR_BREAKDOWN: return "Krylov breakdown";
+    case FSI_ERR_NAN: return "NaN or Inf detected";
+    case FSI_ERR_UNSUPPORTED: return "unsupported combination";
+    default: return "unknown status";
+    }
+}
+
+FSI_API const char *fsi_last_error(void) { return g_err; }
+
+FSI_API const char *fsi_version(void) { return "fsi-mi355x 0.1 (gfx950)"; }
+
+static bool dtype_ok(fsi_dtype d) { return d == FSI_F64 || d == FSI_F32; }
+
+FSI_API size_t fsi_vms_apply_workspace(const fsi_grid *grid, fsi_dtype dtype)
+{
+    if (check_grid(grid) != FSI_OK || !dtype_ok(dtype)) return 0;
+    return vms_workspace_bytes(make_geo(*grid), dtype);
+}
+
+FSI_API int fsi_vms_apply(const fsi_grid *grid, const fsi_vms_params *prm, fsi_dtype dtype,
+                          const void *a, const void *s, const uint32_t *dir_mask, const void *x,
+                          void *y, void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    rc = check_params(prm);
+    if (rc) return rc;
+    FSI_CHECK_ARG(dtype_ok(dtype), "bad dtype %d", (int)dtype);
+    FSI_CHECK_ARG(a && x && y, "a, x and y must be non-NULL");
+    FSI_CHECK_ARG(x != y, "x and y must not alias");
+    const Geo g = make_geo(*grid);
+    const size_t need = vms_workspace_bytes(g, dtype);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+        return FSI_ERR_WORKSPACE;
+    }
+    return launch_vms_apply(g, *prm, dtype, a, s, dir_mask, x, y, nullptr, ws, ws_bytes,
+                            as_stream(stream));
+}
+
+FSI_API size_t fsi_dlm_locate_workspace(const fsi_grid *grid, int64_t m)
+{
+    if (check_grid(grid) != FSI_OK || m < 0) return 0;
+    return locate_workspace_bytes(make_geo(*grid), m);
+}
+
+FSI_API int fsi_dlm_locate(const fsi_grid *grid, int64_t m, const double *X, fsi_dtype dtype,
+                           int32_t *cell, void *xi, int32_t *perm, int32_t *occ_cell,
+                           int32_t *occ_start, int32_t *occ_index, void *s_out, double s_max,
+                           int64_t *n_occ_host, int64_t *n_outside_host, void *ws,
+                           size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    FSI_CHECK_ARG(dtype_ok(dtype), "bad dtype %d", (int)dtype);
+    FSI_CHECK_ARG(m >= 0 && m < ((int64_t)1 << 31) - 1, "m out of range");
+    FSI_CHECK_ARG(m == 0 || (X && cell && xi && perm), "X, cell, xi and perm must be non-NULL");
+    FSI_CHECK_ARG(occ_cell && occ_start && occ_index, "occ_cell, occ_start and occ_index must be non-NULL");
+    FSI_CHECK_ARG(std::isfinite(s_max), "s_max must be finite");
+    const Geo g = make_geo(*grid);
+    const size_t need = locate_workspace_bytes(g, m);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+        return FSI_ERR_WORKSPACE;
+    }
+    return launch_locate(g, m, X, dtype, cell, xi, perm, occ_cell, occ_start, occ_index, s_out, s_max,
+                         n_occ_host, n_outside_host, ws, as_stream(stream));
+}
+
+FSI_API int fsi_dlm_B(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const int32_t *cell,
+                      const void *xi, const void *u, void *Bu, void *stream)
+{
+    clear_error();
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    FSI_CHECK_ARG(dtype_ok(dtype), "bad dtype %d", (int)dtype);
+    FSI_CHECK_ARG(m >= 0 && m < ((int64_t)1 << 31) - 1, "m out of range");
+    FSI_CHECK_ARG(m == 0 || (cell && xi && u && Bu), "cell, xi, u and Bu must be non-NULL");
+    return launch_dlm_B(make_geo(*grid), dtype, m, cell, xi, u, Bu, as_stream(stream));
+}
+
+FSI_API size_t fsi_dlm_BT_workspace(const fsi_grid *grid, int64_t n_occ, fsi_dtype dtype)
+{
+    if (check_grid(grid) != FSI_OK || n_occ < 0 || !dtype_ok(dtype)) return 0;
+    return dlm_csum_bytes(make_geo(*grid), n_occ, dtype);
+}
+
+FSI_API int fsi_dlm_BT(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const int32_t *cell,
+                       const void *xi, const int32_t *perm, const int32_t *occ_cell,
+                       const int32_t *occ_start, const int32_t *occ_index, int64_t n_occ,
+                       const void *lam, const void *kappa, void *y, void *ws, size_t ws_bytes,
+                       void *stream)
+{
+    clear_error();
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    FSI_CHECK_ARG(dtype_ok(dtype), "bad dtype %d", (int)dtype);
+    FSI_CHECK_ARG(m >= 0 && m < ((int64_t)1 << 31) - 1, "m out of range");
+    const Geo g = make_geo(*grid);
+    FSI_CHECK_ARG(n_occ >= 0 && n_occ <= g.E && n_occ <= m, "n_occ out of range");
+    FSI_CHECK_ARG(y != nullptr, "y must be non-NULL");
+    (void)cell;
+    if (n_occ == 0) return FSI_OK;
+    FSI_CHECK_ARG(xi && perm && occ_cell && occ_start && occ_index && lam,
+                  "point tables and lam must be non-NULL");
+    const size_t need = dlm_csum_bytes(g, n_occ, dtype);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+        return FSI_ERR_WORKSPACE;
+    }
+    hipStream_t st = as_stream(stream);
+    rc = launch_dlm_cell_reduce(g, dtype, false, m, n_occ, occ_cell, occ_start, perm, xi, kappa, lam,
+                                nullptr, ws, st);
+    if (rc) return rc;
+    return launch_dlm_node_gather(g, dtype, ws, occ_index, y, st);
+}
+
+static int check_problem(const fsi_problem *p)
+{
+    FSI_CHECK_ARG(p != nullptr, "problem is NULL");
+    int rc = check_grid(&p->grid);
+    if (rc) return rc;
+    rc = check_params(&p->prm);
+    if (rc) return rc;
+    FSI_CHECK_ARG(dtype_ok(p->dtype), "bad dtype %d", (int)p->dtype);
+    FSI_CHECK_ARG(p->a != nullptr, "advection field a is NULL");
+    FSI_CHECK_ARG(p->m >= 0 && p->m < ((int64_t)1 << 31) - 1, "m out of range");
+    const Geo g = make_geo(p->grid);
+    FSI_CHECK_ARG(p->n_occ >= 0 && p->n_occ <= g.E && p->n_occ <= p->m, "n_occ out of range");
+    if (p->n_occ > 0)
+        FSI_CHECK_ARG(p->xi && p->perm && p->occ_cell && p->occ_start && p->occ_index,
+                      "point tables must be non-NULL when n_occ > 0");
+    return FSI_OK;
+}
+
+FSI_API size_t fsi_jacobian_workspace(const fsi_problem *p)
+{
+    if (check_problem(p) != FSI_OK) return 0;
+    const Geo g = make_geo(p->grid);
+    return vms_workspace_bytes(g, p->dtype) + dlm_csum_bytes(g, p->n_occ, p->dtype);
+}
+
+FSI_API int fsi_jacobian_apply(const fsi_problem *p, const void *x, void *y, void *ws,
+                               size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_problem(p);
+    if (rc) return rc;
+    FSI_CHECK_ARG(x && y, "x and y must be non-NULL");
+    FSI_CHECK_ARG(x != y, "x and y must not alias");
+    const Geo g = make_geo(p->grid);
+    const size_t need = vms_workspace_bytes(g, p->dtype) + dlm_csum_bytes(g, p->n_occ, p->dtype);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+        return FSI_ERR_WORKSPACE;
+    }
+    DlmView v{p->m, p->cell, p->xi, p->perm, p->occ_cell, p->occ_start, p->n_occ, p->occ_index,
+              p->kappa};
+    return launch_vms_apply(g, p->prm, p->dtype, p->a, p->s, p->dir_mask, x, y,
+                            p->n_occ > 0 ? &v : nullptr, ws, ws_bytes, as_stream(stream));
+}

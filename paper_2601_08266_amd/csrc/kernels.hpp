@@ -1,0 +1,61 @@
+// Internal launcher declarations (host side), one namespace for the library.
+#pragma once
+
+#include "common.hpp"
+
+namespace fsi {
+
+// Pre-computed constants of the Oseen-VMS operator in the compute precision.
+template <typename T>
+struct VmsConst {
+    T c_m, nu, K1;     // K1 = C_T/dt^2 + C_I nu^2 G:G
+    T ih[3];           // 1/h
+    T ih2[3];          // 1/h^2
+    T inv_trG;         // 1/tr G
+    T detJ;            // hx hy hz
+    int32_t visc_strong;
+    int32_t has_s;
+};
+
+template <typename T>
+VmsConst<T> make_vms_const(const Geo &g, const fsi_vms_params &prm, bool has_s);
+
+// ---- Q1 operator: brick partials + node gather ----
+constexpr int Q1_BX = 8, Q1_BY = 8, Q1_BZ = 4;
+constexpr int Q1_NL = (Q1_BX + 1) * (Q1_BY + 1) * (Q1_BZ + 1);
+
+// ---- Q2 operator ----
+constexpr int Q2_BX = 4, Q2_BY = 4, Q2_BZ = 4;
+constexpr int Q2_NL = (2 * Q2_BX + 1) * (2 * Q2_BY + 1) * (2 * Q2_BZ + 1);
+
+struct BrickLayout {
+    int bx, by, bz;   // cells per brick
+    int nbx, nby, nbz;
+    int64_t nb;
+    int nl;           // local nodes per brick
+};
+
+BrickLayout brick_layout(const Geo &g);
+size_t vms_workspace_bytes(const Geo &g, fsi_dtype dt);
+
+// Point-table view used by the DLM kernels of the Jacobian.
+struct DlmView {
+    int64_t m;
+    const int32_t *cell;
+    const void *xi;
+    const int32_t *perm;
+    const int32_t *occ_cell;
+    const int32_t *occ_start;
+    int64_t n_occ;
+    const int32_t *occ_index;   // [E] occupied index per cell or -1
+    const void *kappa;
+};
+
+// y = A x (+ B^T kappa B x_u if dlm != nullptr), Dirichlet rows -> x.
+int launch_vms_apply(const Geo &g, const fsi_vms_params &prm, fsi_dtype dt, const void *a,
+                     const void *s, const uint32_t *mask, const void *x, void *y,
+                     const DlmView *dlm, void *ws, size_t ws_bytes, hipStream_t st);
+
+size_t dlm_csum_bytes(const Geo &g, int64_t n_occ, fsi_dtype dt);
+
+}  // namespace fsi

@@ -1,0 +1,54 @@
+"""The C-ABI library loads on the CPU host and exports every entry point that
+include/fsi.h declares (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fsi.h")
+LIB = os.path.join(ROOT, "paper_2601_08266_amd", "libfsi.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(fsi_[A-Za-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_core_entry_points():
+    names = declared_functions()
+    for core in ["fsi_vms_apply", "fsi_dlm_locate", "fsi_dlm_B", "fsi_dlm_BT",
+                 "fsi_jacobian_apply"]:
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.fail("libfsi.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, f"not exported: {missing}"
+
+
+def test_binding_signatures_cover_the_header():
+    import paper_2601_08266_amd._lib as L
+    assert set(declared_functions()) <= set(L.SIGNATURES)
+
+
+def test_status_strings_and_argument_errors_without_gpu():
+    import paper_2601_08266_amd._lib as L
+    lib = L.lib()
+    assert lib.fsi_status_string(0) == b"ok"
+    assert b"gfx950" in lib.fsi_version()
+    # invalid grids are rejected before any device work
+    g = L.FsiGrid()
+    g.order = 3
+    assert lib.fsi_vms_apply_workspace(ctypes.byref(g), 0) == 0
+    p = L.FsiVmsParams()
+    rc = lib.fsi_vms_apply(ctypes.byref(g), ctypes.byref(p), 0, None, None, None, None, None,
+                           None, 0, None)
+    assert rc == L.FSI_ERR_ARG
+    assert b"order" in lib.fsi_last_error()

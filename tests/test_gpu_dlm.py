@@ -1,0 +1,189 @@
+"""GPU parity of fsi_dlm_locate / fsi_dlm_B / fsi_dlm_BT / fsi_jacobian_apply against
+the oracle (section 2.3 eqs. nodal_solid_velo and fsi_constraint_matrix, the
+reduced system of section 2.4, appendix A's per-point steps).
+
+Integer and index outputs (cell, perm, occupied-cell CSR, s) must be bitwise
+equal; FP64 xi must be bitwise equal (same FP64 operations in the same order);
+floating-point sums within 1e-12 (FP64) / 1e-5 (FP32) relative per field.
+"""
+import numpy as np
+import pytest
+
+import fsi_workloads as W
+from oracle import dlm as odlm
+from oracle import jacobian as ojac
+from oracle import vms as ovms
+
+from helpers import field_rel_err, points_for, rows_rel_err, sample_rows
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def _t(arr, dtype="f64"):
+    import torch
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    return torch.tensor(np.ascontiguousarray(arr).ravel(), dtype=tdt, device="cuda")
+
+
+def special_cloud(grid, rng, m):
+    """Random points plus points on faces, edges, vertices, the boundary and outside."""
+    X = rng.uniform(-0.05, 1.05, size=(3, m))
+    k = 0
+    for i in range(0, grid.n[0] + 1, 3):
+        for j in range(0, grid.n[1] + 1, 5):
+            X[:, k] = [grid.x0[0] + i * grid.h[0], grid.x0[1] + j * grid.h[1], 0.5]
+            k += 1
+    X[:, k] = [1.0, 1.0, 1.0]
+    X[:, k + 1] = [0.0, 0.0, 0.0]
+    X[:, k + 2] = [np.nextafter(1.0, 2.0), 0.5, 0.5]
+    X[:, k + 3] = [np.nan, 0.5, 0.5]
+    return np.ascontiguousarray(X)
+
+
+@pytest.mark.parametrize("case", ["c1", "c2", "special8", "special_q2", "empty"])
+def test_locate_bitwise(case):
+    import paper_2601_08266_amd as fsi
+    rng = np.random.default_rng(4)
+    if case in ("c1", "c2"):
+        cfg = W.CONFIGS[case]
+        g = cfg.grid
+        X, _ = points_for(cfg)
+    elif case == "special8":
+        g = W.Grid((8, 8, 8), 1)
+        X = special_cloud(g, rng, 5000)
+    elif case == "special_q2":
+        g = W.Grid((7, 5, 6), 2, x0=(-0.1, 0.0, 0.2), h=(0.17, 0.2, 0.13))
+        X = special_cloud(g, rng, 3000)
+        X = X * 1.2 - 0.1
+    else:
+        g = W.Grid((4, 4, 4), 1)
+        X = np.zeros((3, 0))
+    Xt = _t(X) if X.size else __import__("torch").zeros(0, dtype=__import__("torch").float64, device="cuda")
+    tab = fsi.dlm_locate(g, Xt, s_max=100.0)
+    c_ref, xi_ref = odlm.locate(g, X)
+    perm_ref, occ_ref, start_ref = odlm.sort_by_cell(g, c_ref)
+    m = X.shape[1]
+    assert tab.m == m
+    assert tab.n_outside == int((c_ref < 0).sum())
+    assert tab.n_occ == occ_ref.size
+    assert np.array_equal(tab.cell.cpu().numpy(), c_ref.astype(np.int32))
+    assert np.array_equal(tab.xi.cpu().numpy().reshape(3, -1).view(np.int64) if m else np.zeros(0),
+                          xi_ref.view(np.int64) if m else np.zeros(0))
+    assert np.array_equal(tab.perm.cpu().numpy(), perm_ref.astype(np.int32))
+    assert np.array_equal(tab.occ_cell.cpu().numpy()[:tab.n_occ], occ_ref.astype(np.int32))
+    assert np.array_equal(tab.occ_start.cpu().numpy()[:tab.n_occ + 1], start_ref.astype(np.int32))
+    occ_index = tab.occ_index.cpu().numpy()
+    ref_index = np.full(g.num_cells, -1, dtype=np.int32)
+    ref_index[occ_ref] = np.arange(occ_ref.size)
+    assert np.array_equal(occ_index, ref_index)
+    s_ref = odlm.s_field(g, c_ref, 100.0)
+    assert np.array_equal(tab.s.cpu().numpy(), s_ref)
+    print(f"{case}: m={m} n_occ={tab.n_occ} outside={tab.n_outside}")
+
+
+@pytest.mark.parametrize("case", ["c1", "c2", "q2"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_B_BT_parity_and_adjoint(case, dtype):
+    import paper_2601_08266_amd as fsi
+    import torch
+    if case == "q2":
+        cfg = W.CONFIGS["c1"]
+        g = W.Grid((9, 7, 8), 2)
+        X = np.random.default_rng(1).uniform(0.0, 1.0, (3, 4000))
+        kappa = np.random.default_rng(2).uniform(0.5, 2.0, 4000)
+    else:
+        cfg = W.CONFIGS[case]
+        g = cfg.grid
+        X, kappa = points_for(cfg)
+    N, m = g.num_nodes, X.shape[1]
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    tab = fsi.dlm_locate(g, _t(X), dtype=tdt)
+    rng = np.random.default_rng(7)
+    u = rng.standard_normal((3, N))
+    lam = rng.standard_normal((3, m))
+    npdt = np.float64 if dtype == "f64" else np.float32
+    u = u.astype(npdt).astype(np.float64)
+    lam = lam.astype(npdt).astype(np.float64)
+    kappa = kappa.astype(npdt).astype(np.float64)
+    cell, xi = odlm.locate(g, X)
+    xi_used = xi.astype(npdt).astype(np.float64)
+    Bu = fsi.dlm_B(g, tab, _t(u, dtype)).cpu().numpy()
+    Bu_ref = odlm.apply_B(g, cell, xi_used, u)
+    e1 = field_rel_err(Bu, Bu_ref, 3)
+    y0 = rng.standard_normal((3, N)).astype(npdt).astype(np.float64)
+    yt = _t(y0, dtype)
+    fsi.dlm_BT(g, tab, _t(lam, dtype), yt, kappa=_t(kappa, dtype))
+    BT = yt.cpu().numpy().reshape(3, N) - y0
+    BT_ref = odlm.apply_BT(g, cell, xi_used, lam, kappa)
+    e2 = field_rel_err(BT, BT_ref, 3)
+    print(f"{case} {dtype}: B {e1:.3e}  B^T {e2:.3e}")
+    assert e1 <= TOL[dtype] and e2 <= TOL[dtype] * (10 if dtype == "f32" else 1)
+    # adjoint identity between the two GPU kernels: <B u, k lam> = <u, B^T (k lam)>
+    y1 = torch.zeros(3 * N, dtype=tdt, device="cuda")
+    fsi.dlm_BT(g, tab, _t(lam, dtype), y1, kappa=_t(kappa, dtype))
+    lhs = float(np.sum(Bu.reshape(3, -1) * lam * kappa))
+    rhs = float(np.sum(u * y1.cpu().numpy().reshape(3, N)))
+    assert abs(lhs - rhs) <= (1e-11 if dtype == "f64" else 1e-4) * max(abs(lhs), 1.0)
+    # determinism of B^T (no floating-point atomics)
+    y2 = torch.zeros(3 * N, dtype=tdt, device="cuda")
+    fsi.dlm_BT(g, tab, _t(lam, dtype), y2, kappa=_t(kappa, dtype))
+    assert torch.equal(y1, y2)
+
+
+def _jacobian_case(cfg, dtype, mask_on):
+    import paper_2601_08266_amd as fsi
+    import torch
+    g = cfg.grid
+    N = g.num_nodes
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    npdt = np.float64 if dtype == "f64" else np.float32
+    X, kappa = points_for(cfg)
+    tab = fsi.dlm_locate(g, _t(X), dtype=tdt, s_max=cfg.s_max)
+    a = W.advection_field(g, cfg.seed_fields).astype(npdt).astype(np.float64)
+    x = W.random_vector(4 * N, cfg.seed_vectors).astype(npdt).astype(np.float64)
+    kappa = kappa.astype(npdt).astype(np.float64)
+    cell, xi = odlm.locate(g, X)
+    s = odlm.s_field(g, cell, cfg.s_max)
+    mask = W.channel_dirichlet_mask(g) if mask_on else None
+    mt = torch.tensor(W.mask_to_bits(mask).view(np.int32), device="cuda") if mask_on else None
+    prm_g = fsi.make_params(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
+    prob = fsi.Problem(g, prm_g, _t(a, dtype), tab, _t(kappa, dtype), s=tab.s, mask=mt)
+    y = fsi.jacobian_apply(prob, _t(x, dtype)).cpu().numpy()
+    prm_o = ovms.params_array(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
+    return g, a, x, s, mask, cell, xi.astype(npdt).astype(np.float64), kappa, prm_o, y
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("mask_on", [False, True])
+def test_jacobian_c1_full(dtype, mask_on):
+    cfg = W.CONFIGS["c1"]
+    g, a, x, s, mask, cell, xi, kappa, prm_o, y = _jacobian_case(cfg, dtype, mask_on)
+    ref = ojac.apply(g, prm_o, a, x, cell, xi, kappa, s=s, mask=mask)
+    err = field_rel_err(y, ref, 4)
+    print(f"J c1 {dtype} mask={mask_on}: {err:.3e}")
+    assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_jacobian_c2_sampled(dtype):
+    """Full 64^3 / 200k-point size: VMS rows from the oracle's per-row recomputation,
+    DLM term from the oracle's point-by-point B and B^T over all points."""
+    cfg = W.CONFIGS["c2"]
+    g, a, x, s, mask, cell, xi, kappa, prm_o, y = _jacobian_case(cfg, dtype, False)
+    N = g.num_nodes
+    rows = sample_rows(g, 3000, seed=2)
+    ref = ovms.apply_rows(g, prm_o, a, x, rows, s=s)
+    dlm_full = np.zeros(4 * N)
+    dlm_full[:3 * N] = odlm.apply_BT(g, cell, xi, odlm.apply_B(g, cell, xi, x.reshape(4, N)[:3]),
+                                     kappa).ravel()
+    ref = ref + dlm_full[rows]
+    err = rows_rel_err(y[rows], ref)
+    # rows near the solid, where the DLM term dominates
+    near = np.nonzero(np.abs(dlm_full) > 0)[0]
+    near = np.random.default_rng(3).choice(near, min(2000, near.size), replace=False)
+    ref2 = ovms.apply_rows(g, prm_o, a, x, near, s=s) + dlm_full[near]
+    err2 = rows_rel_err(y[near], ref2)
+    print(f"J c2 {dtype}: sampled {err:.3e}, near-solid {err2:.3e}")
+    assert err <= TOL[dtype] and err2 <= TOL[dtype]
