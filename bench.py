@@ -1,0 +1,236 @@
+#!/usr/bin/env python
+"""Benchmark of the immersed FD/DLM Jacobian hot path on one MI355X.
+
+Metric: GDOF/s of the VMS+DLM Jacobian apply, GDOF/s = 4 N_nodes / t_apply.
+Workload (default): 64^3 Q1-Q1 grid (274,625 nodes, 1,098,500 DOF), Oseen
+linearisation about a seeded smooth advection field (nu = 1e-2, dt = 1e-3),
+three thin curved plates with 200,000 solid points (apply mode, no Dirichlet
+mask).  One step = one J x: the VMS operator (Galerkin + SUPG/PSPG/LSIC,
+section 2.1) plus the DLM block B^T diag(kappa) B (section 2.3/2.4), in FP64;
+the FP32 rate is reported beside it.  Inputs are synthetic and resident in
+HBM before timing starts.
+
+Extra fields: FP32 apply rate, the point-location time, the HBM-byte rate of
+the VMS kernel, and the roofline of the dominant kernel (vms_q1_cells, FP64
+vector-ALU bound) from library-side hipEvents recorded on its launch stream
+over the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (fma) x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+
+
+def q1_cell_flops(has_s=True, visc_strong=True):
+    """FP64/FP32 flops one vms_q1_cells lane spends on one Q1 cell (fma = 2, sqrt = div = 1).
+
+    Per cell: 8 nodal fields to monomial form (12 subtractions each), 4 output
+    fields back from moments (12 each).  Per Gauss point (8 per cell):
+    velocity value + gradient 3 x 35, pressure 35, advection 3 x 14, s 14,
+    tau bracket 10, sqrt/div/mul 3, divergence 2, grad div u 21, strong
+    residual and tau_m r 33, pressure/LSIC diagonal 2, momentum fluxes 39,
+    weighting and monomial moments 4 x 40.
+    """
+    per_qp = 105 + 35 + 42 + 10 + 3 + 2 + 33 + 2 + 39 + 160
+    if has_s:
+        per_qp += 14
+    if visc_strong:
+        per_qp += 21
+    nfields_in = 7 + (1 if has_s else 0)
+    return 8 * per_qp + 12 * nfields_in + 12 * 4
+
+
+def build_problem(cfg, dtype, dev):
+    import numpy as np
+    import torch
+
+    import fsi_workloads as W
+    import paper_2601_08266_amd as fsi
+
+    g = cfg.grid
+    N = g.num_nodes
+    if cfg.solid == "sphere":
+        X = W.sphere_points()
+        vol = W.sphere_volume()
+    else:
+        X = W.plate_points(cfg.m_points, cfg.seed_fields)
+        vol = W.plate_volume()
+    kappa = W.kappa_weights(X.shape[1], vol, cfg.c_m, cfg.alpha)
+    a = W.advection_field(g, cfg.seed_fields)
+    x = W.random_vector(4 * N, cfg.seed_vectors)
+
+    def t(v, dt=dtype):
+        return torch.tensor(np.ascontiguousarray(v).ravel(), dtype=dt, device=dev)
+
+    Xt = t(X, torch.float64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tab = fsi.dlm_locate(g, Xt, dtype=dtype, s_max=cfg.s_max)
+    torch.cuda.synchronize()
+    locate_ms = (time.perf_counter() - t0) * 1e3
+    prm = fsi.make_params(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
+    prob = fsi.Problem(g, prm, t(a), tab, t(kappa), s=tab.s, mask=None)
+    xt = t(x)
+    y = torch.empty_like(xt)
+    ws = torch.empty(prob.workspace_bytes(), dtype=torch.uint8, device=dev)
+    return dict(prob=prob, x=xt, y=y, ws=ws, tab=tab, locate_ms=locate_ms, Xt=Xt, N=N,
+                a_np=a, x_np=x, X_np=X, kappa_np=kappa)
+
+
+def time_applies(fsi, torch, case, steps, warmup, profile):
+    prob, x, y, ws = case["prob"], case["x"], case["y"], case["ws"]
+    for _ in range(warmup):
+        fsi.jacobian_apply(prob, x, y, ws)
+    torch.cuda.synchronize()
+    if profile:
+        fsi.profile_enable(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        fsi.jacobian_apply(prob, x, y, ws)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = start.elapsed_time(stop) / steps
+    kern = {}
+    if profile:
+        for name in ("vms_q1_cells", "vms_gather", "dlm_cell_reduce"):
+            tot, n = fsi.profile_read(name)
+            kern[name] = (tot / n if n else 0.0, n)
+        fsi.profile_enable(False)
+    return ms, wall / steps * 1e3, kern
+
+
+def cpu_baseline(cfg, case):
+    """The FP64 oracle's Jacobian apply (dense element matrices, point-by-point DLM) on
+    the full workload, once, on the host cores."""
+    import numpy as np
+
+    from oracle import dlm as odlm
+    from oracle import jacobian as ojac
+    from oracle import vms as ovms
+
+    g = cfg.grid
+    prm = ovms.params_array(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
+    cell, xi = odlm.locate(g, case["X_np"])
+    s = odlm.s_field(g, cell, cfg.s_max)
+    ovms.lib()
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        y = ojac.apply(g, prm, case["a_np"], case["x_np"], cell, xi, case["kappa_np"], s=s)
+        times.append(time.perf_counter() - t0)
+        assert np.all(np.isfinite(y))
+    dt = sorted(times)[1]
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(4 * g.num_nodes / dt / 1e9, 6), "unit": "GDOF/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"full FP64 Jacobian apply of the same workload ({g.n[0]}^3 Q1, "
+                      f"{cfg.m_points} points), median of 3 = {dt:.2f} s wall; OpenMP element "
+                      f"loop + numpy DLM"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 512 MiB device copy (for counter calibration)")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in the design notes)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import fsi_workloads as W
+    import paper_2601_08266_amd as fsi
+
+    dev = torch.device("cuda:0")
+    cfg = W.CONFIGS[args.workload]
+    g = cfg.grid
+    case64 = build_problem(cfg, torch.float64, dev)
+    case32 = build_problem(cfg, torch.float32, dev)
+    N = case64["N"]
+
+    if args.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    ms64, wall64, kern = time_applies(fsi, torch, case64, args.steps, args.warmup, profile=True)
+    ms32, wall32, kern32 = time_applies(fsi, torch, case32, args.steps, args.warmup, profile=True)
+
+    gdofs64 = 4 * N / (ms64 * 1e-3) / 1e9
+    gdofs32 = 4 * N / (ms32 * 1e-3) / 1e9
+    cell_ms, launches = kern.get("vms_q1_cells", (0.0, 0))
+    flops = q1_cell_flops() * g.num_cells
+    achieved_tf = flops / (cell_ms * 1e-3) / 1e12 if cell_ms > 0 else 0.0
+    hbm_bytes = 96 * N          # x in, y out, a, s: 4*8 + 4*8 + 3*8 + 8 per node (FP64)
+    hbm_gbs = hbm_bytes / (cell_ms * 1e-3) / 1e9 if cell_ms > 0 else 0.0
+
+    out = {
+        "metric": "GDOF/s of VMS+DLM Jacobian apply",
+        "value": round(gdofs64, 4),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms64, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{cfg.name}: {g.n[0]}x{g.n[1]}x{g.n[2]} Q{g.order}-Q{g.order} VMS+DLM "
+                        f"Jacobian apply, {cfg.m_points} solid points ({cfg.solid})",
+            "dof": 4 * N, "cells": g.num_cells, "points": cfg.m_points,
+            "nu": cfg.nu, "dt": cfg.dt, "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "alu", "kernel": "vms_q1_cells<double>",
+            "achieved": round(achieved_tf, 3), "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved_tf / PEAK_FP64_VALU_TFLOPS, 4),
+            "traffic": None,
+            "flops_per_launch": flops, "kernel_ms_avg": round(cell_ms, 6),
+            "launches": launches,
+            "hbm_algorithmic_GBs": round(hbm_gbs, 1),
+            "hbm_frac": round(hbm_gbs / PEAK_HBM_GBS, 4),
+        },
+        "extra": {
+            "fp32_gdofs": round(gdofs32, 4), "fp32_ms_per_step": round(ms32, 6),
+            "host_wall_ms_per_step_f64": round(wall64, 6),
+            "kernels_f64_ms": {k: round(v[0], 6) for k, v in kern.items()},
+            "kernels_f32_ms": {k: round(v[0], 6) for k, v in kern32.items()},
+            "locate_ms": round(case64["locate_ms"], 3),
+            "n_occupied_cells": case64["tab"].n_occ,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, case64)
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

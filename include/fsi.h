@@ -209,6 +209,18 @@ size_t fsi_jacobian_workspace(const fsi_problem *problem);
 int fsi_jacobian_apply(const fsi_problem *problem, const void *x, void *y, void *ws,
                        size_t ws_bytes, void *stream);
 
+/*
+ * Kernel timing (tracing aid, not part of the method).  fsi_profile_enable(1)
+ * resets the totals and brackets each later launch of an instrumented kernel
+ * with two hipEvents recorded on that launch's stream; fsi_profile_enable(0)
+ * stops recording.  fsi_profile_read(name, ...) waits for the recorded events
+ * (SYNCS) and returns the summed elapsed milliseconds and the number of
+ * launches of the kernel `name` ("vms_q1_cells", "vms_q2_cells",
+ * "vms_gather", "dlm_cell_reduce", "dlm_locate", ...; unknown names read 0).
+ */
+int fsi_profile_enable(int on);
+int fsi_profile_read(const char *kernel, double *total_ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -270,3 +270,18 @@ def jacobian_apply(problem: Problem, x: torch.Tensor, y: Optional[torch.Tensor] 
     L.check("fsi_jacobian_apply", L.lib().fsi_jacobian_apply(
         ctypes.byref(problem.struct), _ptr(x), _ptr(y), _ptr(ws), ws.numel(), _stream(stream)))
     return y
+
+
+# --------------------------------------------------------------------------- timing
+def profile_enable(on: bool = True) -> None:
+    """Start (and reset) or stop per-kernel hipEvent timing inside the library."""
+    L.check("fsi_profile_enable", L.lib().fsi_profile_enable(1 if on else 0))
+
+
+def profile_read(kernel: str):
+    """(total milliseconds, launches) recorded for `kernel` since profile_enable(True)."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    L.check("fsi_profile_read", L.lib().fsi_profile_read(kernel.encode(), ctypes.byref(ms),
+                                                         ctypes.byref(n)))
+    return float(ms.value), int(n.value)

@@ -70,6 +70,9 @@ SIGNATURES = {
                                   P, P, P, P, SZ, P]),
     "fsi_jacobian_workspace": (SZ, [ctypes.POINTER(FsiProblem)]),
     "fsi_jacobian_apply": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, P, SZ, P]),
+    "fsi_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+    "fsi_profile_read": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(I64)]),
 }
 
 

@@ -19,6 +19,7 @@
 #include <utility>
 
 #include "dlm.hpp"
+#include "profile.hpp"
 
 namespace fsi {
 
@@ -35,8 +36,11 @@ constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
 
 __device__ __forceinline__ double bp(double x0, int64_t k, double h)
 {
-    // breakpoint x0 + k h rounded as written (no contraction into an fma)
-    return __dadd_rn(x0, __dmul_rn((double)k, h));
+    // breakpoint x0 + k h rounded as written: the product is rounded before the sum
+    // (the _rn helpers alone do not stop the compiler from forming an fma)
+#pragma clang fp contract(off)
+    const double kh = (double)k * h;
+    return x0 + kh;
 }
 
 template <typename T>
@@ -46,6 +50,7 @@ __global__ __launch_bounds__(256) void locate_kernel(Geo g, int64_t m, const dou
                                                      int32_t *__restrict__ vals,
                                                      int32_t *__restrict__ n_outside)
 {
+#pragma clang fp contract(off)
     const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (b >= m) return;
     int idx[3];
@@ -521,6 +526,7 @@ int launch_locate(const Geo &g, int64_t m, const double *X, fsi_dtype dt, int32_
                   hipStream_t st)
 {
     LocateWs w = locate_ws_layout(g, m, reinterpret_cast<char *>(ws));
+    ProfileScope prof("dlm_locate", st);
     FSI_HIP(hipMemsetAsync(w.counters, 0, 4 * sizeof(int32_t), st));
     // occ_index = -1 everywhere
     hipLaunchKernelGGL(fill_i32, dim3(nblk(g.E)), dim3(256), 0, st, occ_index, g.E, -1);
@@ -629,6 +635,7 @@ static int launch_reduce_t(const Geo &g, bool from_u, int64_t m, int64_t n_occ, 
 {
     if (n_occ == 0) return FSI_OK;
     const unsigned blocks = (unsigned)((n_occ + 3) / 4);
+    ProfileScope prof("dlm_cell_reduce", st);
     if (g.p == 1) {
         if (from_u)
             hipLaunchKernelGGL((dlm_cell_reduce<T, 1, true>), dim3(blocks), dim3(256), 0, st, g, m, n_occ,

@@ -17,6 +17,7 @@
 //    adds the DLM corner sums of occupied neighbour cells if requested, and
 //    applies the Dirichlet rows.
 #include "kernels.hpp"
+#include "profile.hpp"
 
 namespace fsi {
 
@@ -331,6 +332,7 @@ template <typename T>
 int launch_q1_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, const T *s,
                     const uint32_t *mask, T *part, const BrickLayout &bl, hipStream_t st)
 {
+    ProfileScope prof("vms_q1_cells", st);
     hipLaunchKernelGGL(vms_q1_cells<T>, dim3((unsigned)bl.nb), dim3(256), 0, st, g, k, x, a, s, mask,
                        part, bl.nbx, bl.nby);
     FSI_LAUNCH_CHECK();
@@ -343,6 +345,7 @@ int launch_gather(const Geo &g, const T *part, const BrickLayout &bl, const T *x
                   hipStream_t st)
 {
     const unsigned blocks = (unsigned)((g.N + 255) / 256);
+    ProfileScope prof("vms_gather", st);
     hipLaunchKernelGGL((vms_gather<T, P, BX, BY, BZ>), dim3(blocks), dim3(256), 0, st, g, part,
                        bl.nbx, bl.nby, bl.nbz, x, mask, y, csum, occ_index);
     FSI_LAUNCH_CHECK();
