@@ -174,6 +174,23 @@ int fsi_dlm_BT(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const int32_t *
                void *stream);
 
 /*
+ * fsi_dlm_gram - per occupied cell o, the block of B^T diag(kappa) B that
+ * couples the cell's own (p+1)^3 nodes:
+ *   gram[o][A][C] = sum_{B in cell o} kappa_B N_A(xi_B) N_C(xi_B)
+ * (section 2.4: the C^lambda dR^s/dU (C^lambda)^T block with the per-point
+ * stand-in kappa_B I; B from eq. nodal_solid_velo).  Because every point
+ * couples only the nodes of its own cell, B^T diag(kappa) B u is the sum over
+ * occupied cells of these blocks applied to the cell's nodal u.  Computed once
+ * per point configuration and reused by every Jacobian apply.
+ *   xi, perm, occ_start, n_occ  from fsi_dlm_locate; kappa T [M] or NULL (1)
+ *   gram       T [n_occ][(p+1)^3][(p+1)^3] out (symmetric, row-major)
+ * Deterministic (points summed in cell-sorted order).
+ */
+int fsi_dlm_gram(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const void *xi,
+                 const int32_t *perm, const int32_t *occ_start, int64_t n_occ,
+                 const void *kappa, void *gram, void *stream);
+
+/*
  * Everything the Jacobian of the reduced system needs (section 2.4):
  *   J = A_VMS(a, s) + [[B^T diag(kappa) B, 0], [0, 0]],
  * i.e. the paper's dR^{f,m}/dV + C^lambda dR^s/dU (C^lambda)^T block with the
@@ -198,6 +215,8 @@ typedef struct {
     const int32_t *occ_index;  /* [E] */
     int64_t n_occ;
     const void *kappa;         /* T [M] */
+    const void *dlm_gram;      /* T [n_occ][nen][nen] from fsi_dlm_gram, or NULL: then the
+                                  DLM block is applied point by point (B, kappa, B^T) */
 } fsi_problem;
 
 /*

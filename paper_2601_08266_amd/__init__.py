@@ -21,7 +21,8 @@ from ._lib import FSI_F32, FSI_F64, FsiError, FsiGrid, FsiProblem, FsiVmsParams
 __all__ = [
     "FSI_F64", "FSI_F32", "FsiError", "make_grid", "make_params", "version",
     "vms_apply_workspace", "vms_apply", "PointTables", "dlm_locate", "dlm_B", "dlm_BT",
-    "Problem", "jacobian_apply", "jacobian_workspace",
+    "Problem", "jacobian_apply", "jacobian_workspace", "dlm_gram", "profile_enable",
+    "profile_read",
 ]
 
 _TORCH_OF = {FSI_F64: torch.float64, FSI_F32: torch.float32}
@@ -218,17 +219,34 @@ def dlm_BT(grid, tables: PointTables, lam: torch.Tensor, y: torch.Tensor,
     return y
 
 
+def dlm_gram(grid, tables: PointTables, kappa: Optional[torch.Tensor] = None,
+             out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Per occupied cell, the block sum_B kappa_B N_A(xi_B) N_C(xi_B) (fsi_dlm_gram)."""
+    g = grid_from(grid)
+    dt = tables.xi.dtype
+    nen = (g.order + 1) ** 3
+    if kappa is not None:
+        _need(kappa, "kappa", dt, tables.m)
+    if out is None:
+        out = torch.empty(max(tables.n_occ, 1) * nen * nen, dtype=dt, device=tables.xi.device)
+    L.check("fsi_dlm_gram", L.lib().fsi_dlm_gram(
+        ctypes.byref(g), dtype_code(dt), tables.m, _ptr(tables.xi), _ptr(tables.perm),
+        _ptr(tables.occ_start), tables.n_occ, _ptr(kappa), _ptr(out), _stream(stream)))
+    return out
+
+
 # --------------------------------------------------------------------------- Jacobian
 class Problem:
     """fsi_problem: everything J = A_VMS + B^T diag(kappa) B needs, in one precision."""
 
     def __init__(self, grid, prm: FsiVmsParams, a: torch.Tensor, tables: Optional[PointTables],
                  kappa: Optional[torch.Tensor], s: Optional[torch.Tensor] = None,
-                 mask: Optional[torch.Tensor] = None):
+                 mask: Optional[torch.Tensor] = None, gram: Optional[torch.Tensor] = None):
         g = grid_from(grid)
         dt = a.dtype
         self.grid, self.prm, self.dtype = g, prm, dt
         self.a, self.s, self.mask, self.tables, self.kappa = a, s, mask, tables, kappa
+        self.gram = gram
         st = FsiProblem()
         st.grid = g
         st.prm = prm
@@ -248,11 +266,29 @@ class Problem:
             st.occ_index = tables.occ_index.data_ptr()
             st.n_occ = tables.n_occ
             st.kappa = kappa.data_ptr() if kappa is not None else None
+            st.dlm_gram = gram.data_ptr() if gram is not None else None
         self.struct = st
         self.N = num_nodes(g)
 
     def workspace_bytes(self) -> int:
         return int(L.lib().fsi_jacobian_workspace(ctypes.byref(self.struct)))
+
+    def bind(self, x: torch.Tensor, y: torch.Tensor, ws: torch.Tensor, stream=None):
+        """A zero-argument callable running y = J x with pre-marshalled arguments
+        (for tight loops where per-call Python checks would dominate)."""
+        _need(x, "x", self.dtype, 4 * self.N)
+        _need(y, "y", self.dtype, 4 * self.N)
+        if ws.numel() * ws.element_size() < self.workspace_bytes():
+            raise ValueError("workspace too small")
+        f = L.lib().fsi_jacobian_apply
+        args = (ctypes.byref(self.struct), _ptr(x), _ptr(y), _ptr(ws),
+                ws.numel() * ws.element_size(), _stream(stream))
+
+        def run():
+            rc = f(*args)
+            if rc:
+                L.check("fsi_jacobian_apply", rc)
+        return run
 
 
 def jacobian_workspace(problem: Problem) -> int:

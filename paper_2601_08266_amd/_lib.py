@@ -37,7 +37,8 @@ class FsiProblem(ctypes.Structure):
                 ("m", ctypes.c_int64), ("cell", ctypes.c_void_p), ("xi", ctypes.c_void_p),
                 ("perm", ctypes.c_void_p), ("occ_cell", ctypes.c_void_p),
                 ("occ_start", ctypes.c_void_p), ("occ_index", ctypes.c_void_p),
-                ("n_occ", ctypes.c_int64), ("kappa", ctypes.c_void_p)]
+                ("n_occ", ctypes.c_int64), ("kappa", ctypes.c_void_p),
+                ("dlm_gram", ctypes.c_void_p)]
 
 
 class FsiError(RuntimeError):
@@ -68,6 +69,8 @@ SIGNATURES = {
     "fsi_dlm_BT_workspace": (SZ, [ctypes.POINTER(FsiGrid), I64, ctypes.c_int]),
     "fsi_dlm_BT": (ctypes.c_int, [ctypes.POINTER(FsiGrid), ctypes.c_int, I64, P, P, P, P, P, P, I64,
                                   P, P, P, P, SZ, P]),
+    "fsi_dlm_gram": (ctypes.c_int, [ctypes.POINTER(FsiGrid), ctypes.c_int, I64, P, P, P, I64, P, P,
+                                    P]),
     "fsi_jacobian_workspace": (SZ, [ctypes.POINTER(FsiProblem)]),
     "fsi_jacobian_apply": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, P, SZ, P]),
     "fsi_profile_enable": (ctypes.c_int, [ctypes.c_int]),

@@ -96,10 +96,12 @@ size_t vms_workspace_bytes(const Geo &g, fsi_dtype dt)
 // declared in the kernel translation units
 template <typename T>
 int launch_q1_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, const T *s,
-                    const uint32_t *mask, T *part, const BrickLayout &bl, hipStream_t st);
+                    const uint32_t *mask, const T *gram, const int32_t *occ_index, T *part,
+                    const BrickLayout &bl, hipStream_t st);
 template <typename T>
 int launch_q2_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, const T *s,
-                    const uint32_t *mask, T *part, const BrickLayout &bl, hipStream_t st);
+                    const uint32_t *mask, const T *gram, const int32_t *occ_index, T *part,
+                    const BrickLayout &bl, hipStream_t st);
 template <typename T, int P, int BX, int BY, int BZ>
 int launch_gather(const Geo &g, const T *part, const BrickLayout &bl, const T *x,
                   const uint32_t *mask, T *y, const T *csum, const int32_t *occ_index,
@@ -115,13 +117,17 @@ static int vms_apply_t(const Geo &g, const fsi_vms_params &prm, const T *a, cons
     T *part = reinterpret_cast<T *>(ws);
     const size_t vbytes = vms_workspace_bytes(g, sizeof(T) == 8 ? FSI_F64 : FSI_F32);
     T *csum = nullptr;
+    // DLM block: per-cell blocks folded into the cell kernel when available
+    const bool use_gram = dlm != nullptr && dlm->n_occ > 0 && dlm->gram != nullptr;
+    const T *gram = use_gram ? reinterpret_cast<const T *>(dlm->gram) : nullptr;
+    const int32_t *gidx = use_gram ? dlm->occ_index : nullptr;
     int rc;
     if (g.p == 1)
-        rc = launch_q1_cells<T>(g, k, x, a, s, mask, part, bl, st);
+        rc = launch_q1_cells<T>(g, k, x, a, s, mask, gram, gidx, part, bl, st);
     else
-        rc = launch_q2_cells<T>(g, k, x, a, s, mask, part, bl, st);
+        rc = launch_q2_cells<T>(g, k, x, a, s, mask, gram, gidx, part, bl, st);
     if (rc) return rc;
-    if (dlm != nullptr && dlm->n_occ > 0) {
+    if (dlm != nullptr && dlm->n_occ > 0 && !use_gram) {
         csum = reinterpret_cast<T *>(reinterpret_cast<char *>(ws) + vbytes);
         rc = launch_dlm_cell_reduce(g, sizeof(T) == 8 ? FSI_F64 : FSI_F32, true, dlm->m, dlm->n_occ,
                                     dlm->occ_cell, dlm->occ_start, dlm->perm, dlm->xi, dlm->kappa, x,
@@ -279,6 +285,22 @@ FSI_API int fsi_dlm_BT(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const i
     return launch_dlm_node_gather(g, dtype, ws, occ_index, y, st);
 }
 
+FSI_API int fsi_dlm_gram(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const void *xi,
+                         const int32_t *perm, const int32_t *occ_start, int64_t n_occ,
+                         const void *kappa, void *gram, void *stream)
+{
+    clear_error();
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    FSI_CHECK_ARG(dtype_ok(dtype), "bad dtype %d", (int)dtype);
+    FSI_CHECK_ARG(m >= 0 && m < ((int64_t)1 << 31) - 1, "m out of range");
+    const Geo g = make_geo(*grid);
+    FSI_CHECK_ARG(n_occ >= 0 && n_occ <= g.E && n_occ <= m, "n_occ out of range");
+    if (n_occ == 0) return FSI_OK;
+    FSI_CHECK_ARG(xi && perm && occ_start && gram, "xi, perm, occ_start and gram must be non-NULL");
+    return launch_dlm_gram(g, dtype, m, n_occ, occ_start, perm, xi, kappa, gram, as_stream(stream));
+}
+
 static int check_problem(const fsi_problem *p)
 {
     FSI_CHECK_ARG(p != nullptr, "problem is NULL");
@@ -318,8 +340,8 @@ FSI_API int fsi_jacobian_apply(const fsi_problem *p, const void *x, void *y, voi
         set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
         return FSI_ERR_WORKSPACE;
     }
-    DlmView v{p->m, p->cell, p->xi, p->perm, p->occ_cell, p->occ_start, p->n_occ, p->occ_index,
-              p->kappa};
+    DlmView v{p->m,     p->cell,  p->xi,        p->perm,  p->occ_cell, p->occ_start,
+              p->n_occ, p->occ_index, p->kappa, p->dlm_gram};
     return launch_vms_apply(g, p->prm, p->dtype, p->a, p->s, p->dir_mask, x, y,
                             p->n_occ > 0 ? &v : nullptr, ws, ws_bytes, as_stream(stream));
 }

@@ -427,6 +427,65 @@ __global__ __launch_bounds__(256) void dlm_cell_reduce(Geo g, int64_t m, int64_t
         }
 }
 
+// Per occupied cell o, the (p+1)^3 x (p+1)^3 block of B^T diag(kappa) B restricted to the
+// cell's nodes: gram[o][A][C] = sum_{B in cell} kappa_B N_A(xi_B) N_C(xi_B).  One wave per cell:
+// lanes stage 64 points' shape values in LDS, then each lane sums its entries over the staged
+// points in point order (deterministic; the two triangles are bitwise equal).
+template <typename T, int P>
+__global__ __launch_bounds__(64) void dlm_gram_kernel(int64_t m, const int32_t *__restrict__ occ_start,
+                                                      const int32_t *__restrict__ perm,
+                                                      const T *__restrict__ xi,
+                                                      const T *__restrict__ kappa,
+                                                      T *__restrict__ gram)
+{
+    constexpr int Q = P + 1, NEN = Q * Q * Q, NE = NEN * NEN;
+    constexpr int PER = (NE + 63) / 64;
+    __shared__ T sN[NEN][64];
+    __shared__ T sK[64];
+    const int64_t o = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int32_t j0 = occ_start[o], j1 = occ_start[o + 1];
+    T acc[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) acc[r] = T(0);
+    for (int32_t base = j0; base < j1; base += 64) {
+        const int32_t j = base + lane;
+        if (j < j1) {
+            const int32_t b = perm[j];
+            T Nx[Q], Ny[Q], Nz[Q];
+            lagrange<T, P>(xi[b], Nx);
+            lagrange<T, P>(xi[m + b], Ny);
+            lagrange<T, P>(xi[2 * m + b], Nz);
+#pragma unroll
+            for (int A = 0; A < NEN; ++A) sN[A][lane] = Nx[A % Q] * Ny[(A / Q) % Q] * Nz[A / (Q * Q)];
+            sK[lane] = kappa ? kappa[b] : T(1);
+        }
+        __syncthreads();
+        const int cnt = (j1 - base) < 64 ? (j1 - base) : 64;
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int e = lane + 64 * r;
+            if (e < NE) {
+                const int A = e / NEN, C = e % NEN;
+                T v = acc[r];
+                for (int k = 0; k < cnt; ++k) {
+                    // the product kappa N_A N_C is formed symmetrically in A and C
+                    const T na = sN[A][k], nc = sN[C][k];
+                    const T w = (A <= C) ? (sK[k] * na) * nc : (sK[k] * nc) * na;
+                    v += w;
+                }
+                acc[r] = v;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int e = lane + 64 * r;
+        if (e < NE) gram[o * NE + e] = acc[r];
+    }
+}
+
 // y[3][N] += corner sums of the occupied neighbour cells (standalone B^T)
 template <typename T, int P>
 __global__ __launch_bounds__(256) void dlm_node_gather(Geo g, const T *__restrict__ csum,
@@ -665,6 +724,30 @@ int launch_dlm_cell_reduce(const Geo &g, fsi_dtype dt, bool from_u, int64_t m, i
                                        (const double *)kappa, (const double *)src, mask, (double *)csum, st);
     return launch_reduce_t<float>(g, from_u, m, n_occ, occ_cell, occ_start, perm, (const float *)xi,
                                   (const float *)kappa, (const float *)src, mask, (float *)csum, st);
+}
+
+int launch_dlm_gram(const Geo &g, fsi_dtype dt, int64_t m, int64_t n_occ, const int32_t *occ_start,
+                    const int32_t *perm, const void *xi, const void *kappa, void *gram, hipStream_t st)
+{
+    if (n_occ == 0) return FSI_OK;
+    ProfileScope prof("dlm_gram", st);
+    if (dt == FSI_F64) {
+        if (g.p == 1)
+            hipLaunchKernelGGL((dlm_gram_kernel<double, 1>), dim3((unsigned)n_occ), dim3(64), 0, st, m,
+                               occ_start, perm, (const double *)xi, (const double *)kappa, (double *)gram);
+        else
+            hipLaunchKernelGGL((dlm_gram_kernel<double, 2>), dim3((unsigned)n_occ), dim3(64), 0, st, m,
+                               occ_start, perm, (const double *)xi, (const double *)kappa, (double *)gram);
+    } else {
+        if (g.p == 1)
+            hipLaunchKernelGGL((dlm_gram_kernel<float, 1>), dim3((unsigned)n_occ), dim3(64), 0, st, m,
+                               occ_start, perm, (const float *)xi, (const float *)kappa, (float *)gram);
+        else
+            hipLaunchKernelGGL((dlm_gram_kernel<float, 2>), dim3((unsigned)n_occ), dim3(64), 0, st, m,
+                               occ_start, perm, (const float *)xi, (const float *)kappa, (float *)gram);
+    }
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
 }
 
 int launch_dlm_node_gather(const Geo &g, fsi_dtype dt, const void *csum, const int32_t *occ_index,

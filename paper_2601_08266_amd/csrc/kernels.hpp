@@ -49,6 +49,7 @@ struct DlmView {
     int64_t n_occ;
     const int32_t *occ_index;   // [E] occupied index per cell or -1
     const void *kappa;
+    const void *gram;           // [n_occ][nen][nen] or nullptr
 };
 
 // y = A x (+ B^T kappa B x_u if dlm != nullptr), Dirichlet rows -> x.

@@ -45,6 +45,15 @@ __device__ __forceinline__ void from_moments(T v[8])
     v[0] -= v[1]; v[2] -= v[3]; v[4] -= v[5]; v[6] -= v[7];
 }
 
+// inverse of from_moments: a nodal vector -> the moments that from_moments maps back onto it
+template <typename T>
+__device__ __forceinline__ void to_moments(T v[8])
+{
+    v[0] += v[1]; v[2] += v[3]; v[4] += v[5]; v[6] += v[7];
+    v[0] += v[2]; v[1] += v[3]; v[4] += v[6]; v[5] += v[7];
+    v[0] += v[4]; v[1] += v[5]; v[2] += v[6]; v[3] += v[7];
+}
+
 template <typename T>
 struct QP {
     T x, y, z, xy, xz, yz, xyz;
@@ -87,21 +96,41 @@ __device__ __forceinline__ void moments(T m[8], T F0, T G0, T G1, T G2, const QP
 }
 
 // Full element computation for one Q1 cell: in[f][A] nodal x (masked), a, s; out[f][A].
+// If dlm != nullptr, the cell's 8x8 block of B^T diag(kappa) B is applied to the
+// velocity and added to the momentum outputs.
 template <typename T>
 __device__ __forceinline__ void q1_cell(const VmsConst<T> &k, T cu[4][8], T ca[3][8], T cs[8],
-                                        T smin, T out[4][8])
+                                        T smin, const T *__restrict__ dlm, T out[4][8])
 {
-#pragma unroll
-    for (int f = 0; f < 4; ++f) to_monomial(cu[f]);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) to_monomial(ca[d]);
-    if (k.has_s) to_monomial(cs);
-
     T mom[4][8];
 #pragma unroll
     for (int f = 0; f < 4; ++f)
 #pragma unroll
         for (int i = 0; i < 8; ++i) mom[f][i] = T(0);
+    if (dlm != nullptr) {
+        // DLM block on the nodal (Dirichlet-masked) velocity, carried in moment form
+#pragma unroll
+        for (int A = 0; A < 8; ++A) {
+            T r0 = T(0), r1 = T(0), r2 = T(0);
+#pragma unroll
+            for (int C = 0; C < 8; ++C) {
+                const T gAC = dlm[A * 8 + C];
+                r0 += gAC * cu[0][C];
+                r1 += gAC * cu[1][C];
+                r2 += gAC * cu[2][C];
+            }
+            mom[0][A] = r0;
+            mom[1][A] = r1;
+            mom[2][A] = r2;
+        }
+#pragma unroll
+        for (int f = 0; f < 3; ++f) to_moments(mom[f]);
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) to_monomial(cu[f]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) to_monomial(ca[d]);
+    if (k.has_s) to_monomial(cs);
 
     const T W = k.detJ * T(0.125);
     const T Wh0 = W * k.ih[0], Wh1 = W * k.ih[1], Wh2 = W * k.ih[2];
@@ -194,6 +223,8 @@ __global__ __launch_bounds__(256) void vms_q1_cells(Geo g, VmsConst<T> k, const 
                                                     const T *__restrict__ a,
                                                     const T *__restrict__ s,
                                                     const uint32_t *__restrict__ mask,
+                                                    const T *__restrict__ gram,
+                                                    const int32_t *__restrict__ occ_index,
                                                     T *__restrict__ part, int nbx, int nby)
 {
     __shared__ T acc[4 * Q1_NL];
@@ -229,7 +260,12 @@ __global__ __launch_bounds__(256) void vms_q1_cells(Geo g, VmsConst<T> k, const 
 #pragma unroll
             for (int A = 1; A < 8; ++A) smin = cs[A] < smin ? cs[A] : smin;
         }
-        q1_cell(k, cu, ca, cs, smin, out);
+        const T *dlm = nullptr;
+        if (gram != nullptr) {
+            const int32_t ko = occ_index[cx + (int64_t)g.n[0] * (cy + (int64_t)g.n[1] * cz)];
+            if (ko >= 0) dlm = gram + (int64_t)ko * 64;
+        }
+        q1_cell(k, cu, ca, cs, smin, dlm, out);
     }
     __syncthreads();
 #pragma unroll
@@ -330,11 +366,12 @@ __global__ __launch_bounds__(256) void vms_gather(Geo g, const T *__restrict__ p
 
 template <typename T>
 int launch_q1_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, const T *s,
-                    const uint32_t *mask, T *part, const BrickLayout &bl, hipStream_t st)
+                    const uint32_t *mask, const T *gram, const int32_t *occ_index, T *part,
+                    const BrickLayout &bl, hipStream_t st)
 {
     ProfileScope prof("vms_q1_cells", st);
     hipLaunchKernelGGL(vms_q1_cells<T>, dim3((unsigned)bl.nb), dim3(256), 0, st, g, k, x, a, s, mask,
-                       part, bl.nbx, bl.nby);
+                       gram, occ_index, part, bl.nbx, bl.nby);
     FSI_LAUNCH_CHECK();
     return FSI_OK;
 }
@@ -353,11 +390,12 @@ int launch_gather(const Geo &g, const T *part, const BrickLayout &bl, const T *x
 }
 
 template int launch_q1_cells<double>(const Geo &, const VmsConst<double> &, const double *,
-                                     const double *, const double *, const uint32_t *, double *,
+                                     const double *, const double *, const uint32_t *,
+                                     const double *, const int32_t *, double *,
                                      const BrickLayout &, hipStream_t);
 template int launch_q1_cells<float>(const Geo &, const VmsConst<float> &, const float *,
-                                    const float *, const float *, const uint32_t *, float *,
-                                    const BrickLayout &, hipStream_t);
+                                    const float *, const float *, const uint32_t *, const float *,
+                                    const int32_t *, float *, const BrickLayout &, hipStream_t);
 template int launch_gather<double, 1, Q1_BX, Q1_BY, Q1_BZ>(const Geo &, const double *,
                                                            const BrickLayout &, const double *,
                                                            const uint32_t *, double *,

@@ -132,7 +132,43 @@ def test_B_BT_parity_and_adjoint(case, dtype):
     assert torch.equal(y1, y2)
 
 
-def _jacobian_case(cfg, dtype, mask_on):
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_dlm_gram_parity(order, dtype):
+    """Per occupied cell, sum_B kappa_B N_A(xi_B) N_C(xi_B) against the oracle's shape values."""
+    import paper_2601_08266_amd as fsi
+    import torch
+    if order == 1:
+        cfg = W.CONFIGS["c2"]
+        g = cfg.grid
+        X, kappa = points_for(cfg)
+    else:
+        g = W.Grid((9, 7, 8), 2)
+        X = np.random.default_rng(5).uniform(-0.05, 1.05, (3, 6000))
+        kappa = np.random.default_rng(6).uniform(0.5, 2.0, 6000)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    npdt = np.float64 if dtype == "f64" else np.float32
+    kappa = kappa.astype(npdt).astype(np.float64)
+    tab = fsi.dlm_locate(g, _t(X), dtype=tdt)
+    gram = fsi.dlm_gram(g, tab, _t(kappa, dtype)).cpu().numpy()
+    nen = (g.order + 1) ** 3
+    cell, xi = odlm.locate(g, X)
+    xi = xi.astype(npdt).astype(np.float64)
+    perm, occ, start = odlm.sort_by_cell(g, cell)
+    vals, _ = odlm.point_shapes(g, cell, xi)
+    ref = np.zeros((occ.size, nen, nen))
+    for o in range(occ.size):
+        pts = perm[start[o]:start[o + 1]]
+        Nm = vals[:, pts]
+        ref[o] = (Nm * kappa[pts]) @ Nm.T
+    got = gram[:occ.size * nen * nen].reshape(occ.size, nen, nen)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"gram order {order} {dtype}: {err:.3e}")
+    assert err <= TOL[dtype]
+    assert np.array_equal(got, np.transpose(got, (0, 2, 1)))
+
+
+def _jacobian_case(cfg, dtype, mask_on, use_gram=True):
     import paper_2601_08266_amd as fsi
     import torch
     g = cfg.grid
@@ -149,7 +185,9 @@ def _jacobian_case(cfg, dtype, mask_on):
     mask = W.channel_dirichlet_mask(g) if mask_on else None
     mt = torch.tensor(W.mask_to_bits(mask).view(np.int32), device="cuda") if mask_on else None
     prm_g = fsi.make_params(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
-    prob = fsi.Problem(g, prm_g, _t(a, dtype), tab, _t(kappa, dtype), s=tab.s, mask=mt)
+    kt = _t(kappa, dtype)
+    gram = fsi.dlm_gram(g, tab, kt) if use_gram else None
+    prob = fsi.Problem(g, prm_g, _t(a, dtype), tab, kt, s=tab.s, mask=mt, gram=gram)
     y = fsi.jacobian_apply(prob, _t(x, dtype)).cpu().numpy()
     prm_o = ovms.params_array(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
     return g, a, x, s, mask, cell, xi.astype(npdt).astype(np.float64), kappa, prm_o, y
@@ -157,9 +195,10 @@ def _jacobian_case(cfg, dtype, mask_on):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("mask_on", [False, True])
-def test_jacobian_c1_full(dtype, mask_on):
+@pytest.mark.parametrize("use_gram", [True, False])
+def test_jacobian_c1_full(dtype, mask_on, use_gram):
     cfg = W.CONFIGS["c1"]
-    g, a, x, s, mask, cell, xi, kappa, prm_o, y = _jacobian_case(cfg, dtype, mask_on)
+    g, a, x, s, mask, cell, xi, kappa, prm_o, y = _jacobian_case(cfg, dtype, mask_on, use_gram)
     ref = ojac.apply(g, prm_o, a, x, cell, xi, kappa, s=s, mask=mask)
     err = field_rel_err(y, ref, 4)
     print(f"J c1 {dtype} mask={mask_on}: {err:.3e}")
@@ -167,11 +206,13 @@ def test_jacobian_c1_full(dtype, mask_on):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_jacobian_c2_sampled(dtype):
-    """Full 64^3 / 200k-point size: VMS rows from the oracle's per-row recomputation,
-    DLM term from the oracle's point-by-point B and B^T over all points."""
+@pytest.mark.parametrize("use_gram", [True, False])
+def test_jacobian_c2_sampled(dtype, use_gram):
+    """Full 64^3 / 200k-point size in the benchmark's launch configuration: VMS rows from
+    the oracle's per-row recomputation, DLM term from the oracle's point-by-point B and
+    B^T over all points."""
     cfg = W.CONFIGS["c2"]
-    g, a, x, s, mask, cell, xi, kappa, prm_o, y = _jacobian_case(cfg, dtype, False)
+    g, a, x, s, mask, cell, xi, kappa, prm_o, y = _jacobian_case(cfg, dtype, False, use_gram)
     N = g.num_nodes
     rows = sample_rows(g, 3000, seed=2)
     ref = ovms.apply_rows(g, prm_o, a, x, rows, s=s)
