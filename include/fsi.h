@@ -229,6 +229,122 @@ int fsi_jacobian_apply(const fsi_problem *problem, const void *x, void *y, void 
                        size_t ws_bytes, void *stream);
 
 /*
+ * fsi_vms_residual - nonlinear residual of one implicit step (Q1 grids), the
+ * right-hand side of the Newton corrections of section 2.4:
+ *   R = A(a = u, tau(u)) x - F(f) + [B^T diag(kappa) (B u - g); 0]
+ * with A the operator of fsi_vms_apply evaluated with the velocity itself as
+ * advection field (eq. fluid_weak_form's convective term and tau_m of the
+ * stabilisation equations use v^f), F(f) = int (w + tau_m((u.grad)w + grad q)).f
+ * the Galerkin/SUPG/PSPG weighting of the nodal source f = c_m u_old + body
+ * force, and the DLM term from the per-cell blocks (problem->dlm_gram, needed
+ * when n_occ > 0) minus lamg = B^T (kappa g) (g: prescribed solid-point
+ * velocities, precomputed once per step with fsi_dlm_BT).  Dirichlet rows:
+ * R = u - gD.  problem->a is ignored.
+ *   f     T [3][N];  lamg  T [3][N] or NULL;  gD  T [3][N] (needed if dir_mask)
+ *   x     T [4][N] current iterate (unmasked);  R  T [4][N] out
+ *   ws    at least fsi_jacobian_workspace(problem) bytes
+ */
+int fsi_vms_residual(const fsi_problem *problem, const void *f, const void *lamg, const void *gD,
+                     const void *x, void *R, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Nodal 4x4 block-Jacobi preconditioner: for every node, the (u,v,w,p) x
+ * (u,v,w,p) diagonal block of J (element contributions of the operator plus the
+ * diagonal of the DLM block, Dirichlet rows/columns replaced by the identity),
+ * inverted in FP64.  Section 2.4 preconditions the reduced 2x2 block system
+ * with blocks taken from its sub-matrices; this is the node-local member of
+ * that family.
+ *   problem   FP64 problem (dtype FSI_F64; dlm_gram required when n_occ > 0)
+ *   pinv64    double [16][N] out or NULL (entry (i,j) of node k at (4i+j)*N+k)
+ *   pinv32    float  [16][N] out or NULL (the FP32 copy)
+ *   blocks    double [16][N] out or NULL (the blocks before inversion)
+ *   n_singular_host  HOST out or NULL: blocks that could not be inverted (set to
+ *             the identity); SYNCS when non-NULL
+ *   ws        at least fsi_bjacobi_workspace(grid) bytes
+ * fsi_bjacobi_apply: z = P^{-1} v on [4][N] vectors in precision dtype.
+ */
+size_t fsi_bjacobi_workspace(const fsi_grid *grid);
+int fsi_bjacobi_setup(const fsi_problem *problem, double *pinv64, float *pinv32, double *blocks,
+                      int64_t *n_singular_host, void *ws, size_t ws_bytes, void *stream);
+int fsi_bjacobi_apply(const fsi_grid *grid, fsi_dtype dtype, const void *pinv, const void *v,
+                      void *z, void *stream);
+
+/*
+ * fsi_fgmres_solve - solve J x = b with restarted flexible GMRES, right
+ * preconditioned by the nodal block-Jacobi blocks (section 2.4: the reduced
+ * system is solved iteratively with block preconditioners).
+ * FP64: Krylov basis, classical Gram-Schmidt with re-orthogonalisation, Givens
+ * rotations, x, and the residual b - J x recomputed at every restart.
+ * Inner precision (opts->inner): the preconditioner and Jacobian applies of
+ * each cycle and the stored preconditioned vectors; with FSI_F32 the restarts
+ * are iterative-refinement steps (a cycle stops once its residual estimate
+ * fell by opts->inner_reduction or reached the target).
+ *   J64   FP64 problem (true residuals; also the inner applies if inner = F64)
+ *   J32   FP32 problem (same data rounded to FP32) when inner = F32, else NULL
+ *   pinv  [16][N] inverse blocks in the inner precision, or NULL (no preconditioner)
+ *   b     double [4][N];  x  double [4][N] in: initial guess, out: solution
+ *   stats HOST out (may be NULL).  SYNCS (once per Arnoldi step).
+ * Returns FSI_OK when ||b - J x||_2 <= rtol ||b||_2 (FP64 residual),
+ * FSI_ERR_NOT_CONVERGED (x = last iterate) on the iteration cap or stagnation,
+ * FSI_ERR_NAN, FSI_ERR_BREAKDOWN.
+ */
+typedef struct {
+    int32_t restart;          /* Krylov vectors per cycle (e.g. 50) */
+    int32_t max_iters;        /* total Arnoldi steps */
+    double rtol;              /* relative FP64 residual target */
+    fsi_dtype inner;          /* FSI_F32 (mixed precision) or FSI_F64 */
+    double inner_reduction;   /* FP32 cycles stop at this relative reduction (e.g. 1e-5) */
+} fsi_solve_opts;
+
+typedef struct {
+    int32_t iters, cycles, status;
+    double bnorm, res0, res_final;   /* ||b||, initial and final FP64 residual norms */
+    double t_total_ms;
+} fsi_solve_stats;
+
+size_t fsi_fgmres_workspace(const fsi_problem *J64, const fsi_problem *J32,
+                            const fsi_solve_opts *opts);
+int fsi_fgmres_solve(const fsi_problem *J64, const fsi_problem *J32, const void *pinv,
+                     const double *b, double *x, const fsi_solve_opts *opts,
+                     fsi_solve_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * fsi_newton_solve - one implicit time step: Newton's method on
+ * R(x) = 0 (fsi_vms_residual), each correction from J(u_k) dx = -R(x_k)
+ * solved by fsi_fgmres_solve with the nodal block-Jacobi preconditioner of
+ * J(u_k) (section 2.4: Newton iterations on the monolithic system, each solving
+ * the reduced block system).  J(u_k) is the Picard/Oseen linearisation: the
+ * operator of fsi_vms_apply with advection field u_k plus the DLM block.
+ *   P64   FP64 problem: s, dir_mask, point tables, kappa, dlm_gram (a ignored)
+ *   P32   FP32 copy of the same data when opts->inner = FSI_F32, else NULL
+ *   f, lamg, gD  as in fsi_vms_residual (FP64)
+ *   x     double [4][N] in: guess (Dirichlet values imposed), out: solution
+ * Stops when ||R||_2 <= opts->tol_abs; each linear solve uses the relative
+ * tolerance max(eta, 0.5 tol_abs / ||R||).  stats: HOST out.  SYNCS.
+ */
+typedef struct {
+    int32_t max_newton;       /* Newton iterations cap (e.g. 20) */
+    double tol_abs;           /* absolute residual target */
+    double eta;               /* linear forcing term (e.g. 1e-3) */
+    int32_t restart, max_krylov;
+    fsi_dtype inner;          /* inner precision of the Krylov cycles */
+    double inner_reduction;
+} fsi_newton_opts;
+
+typedef struct {
+    int32_t newton_iters, krylov_iters, status;
+    double res_hist[32];      /* ||R|| before each Newton iteration, then the final one */
+    double t_total_ms, t_residual_ms, t_setup_ms, t_krylov_ms;
+} fsi_newton_stats;
+
+size_t fsi_newton_workspace(const fsi_problem *P64, const fsi_problem *P32,
+                            const fsi_newton_opts *opts);
+int fsi_newton_solve(const fsi_problem *P64, const fsi_problem *P32, const double *f,
+                     const double *lamg, const double *gD, double *x,
+                     const fsi_newton_opts *opts, fsi_newton_stats *stats, void *ws,
+                     size_t ws_bytes, void *stream);
+
+/*
  * Kernel timing (tracing aid, not part of the method).  fsi_profile_enable(1)
  * resets the totals and brackets each later launch of an instrumented kernel
  * with two hipEvents recorded on that launch's stream; fsi_profile_enable(0)

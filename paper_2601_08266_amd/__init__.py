@@ -16,13 +16,15 @@ from typing import Optional
 import torch
 
 from . import _lib as L
-from ._lib import FSI_F32, FSI_F64, FsiError, FsiGrid, FsiProblem, FsiVmsParams
+from ._lib import (FSI_F32, FSI_F64, FsiError, FsiGrid, FsiNewtonOpts, FsiNewtonStats, FsiProblem,
+                   FsiSolveOpts, FsiSolveStats, FsiVmsParams)
 
 __all__ = [
     "FSI_F64", "FSI_F32", "FsiError", "make_grid", "make_params", "version",
     "vms_apply_workspace", "vms_apply", "PointTables", "dlm_locate", "dlm_B", "dlm_BT",
     "Problem", "jacobian_apply", "jacobian_workspace", "dlm_gram", "profile_enable",
-    "profile_read",
+    "profile_read", "vms_residual", "bjacobi_setup", "bjacobi_apply", "fgmres_solve",
+    "newton_solve", "solve_opts", "newton_opts",
 ]
 
 _TORCH_OF = {FSI_F64: torch.float64, FSI_F32: torch.float32}
@@ -306,6 +308,114 @@ def jacobian_apply(problem: Problem, x: torch.Tensor, y: Optional[torch.Tensor] 
     L.check("fsi_jacobian_apply", L.lib().fsi_jacobian_apply(
         ctypes.byref(problem.struct), _ptr(x), _ptr(y), _ptr(ws), ws.numel(), _stream(stream)))
     return y
+
+
+# --------------------------------------------------------------------------- solvers
+def vms_residual(problem: Problem, f: torch.Tensor, x: torch.Tensor, gD=None, lamg=None,
+                 R: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None):
+    """Nonlinear step residual (fsi_vms_residual); problem.a is ignored (a = u)."""
+    N = problem.N
+    _need(x, "x", problem.dtype, 4 * N)
+    _need(f, "f", problem.dtype, 3 * N)
+    if gD is not None:
+        _need(gD, "gD", problem.dtype, 3 * N)
+    if lamg is not None:
+        _need(lamg, "lamg", problem.dtype, 3 * N)
+    if R is None:
+        R = torch.empty_like(x)
+    ws = _workspace(problem.workspace_bytes(), x.device, ws)
+    L.check("fsi_vms_residual", L.lib().fsi_vms_residual(
+        ctypes.byref(problem.struct), _ptr(f), _ptr(lamg), _ptr(gD), _ptr(x), _ptr(R), _ptr(ws),
+        ws.numel(), _stream(stream)))
+    return R
+
+
+def bjacobi_setup(problem: Problem, want32: bool = True, want_blocks: bool = False, stream=None):
+    """Inverse nodal 4x4 blocks of J (fsi_bjacobi_setup): returns (pinv64, pinv32, blocks, n_sing)."""
+    if problem.dtype != torch.float64:
+        raise TypeError("block-Jacobi setup takes the FP64 problem")
+    N = problem.N
+    dev = problem.a.device
+    pinv64 = torch.empty(16 * N, dtype=torch.float64, device=dev)
+    pinv32 = torch.empty(16 * N, dtype=torch.float32, device=dev) if want32 else None
+    blocks = torch.empty(16 * N, dtype=torch.float64, device=dev) if want_blocks else None
+    nbytes = int(L.lib().fsi_bjacobi_workspace(ctypes.byref(problem.grid)))
+    ws = _workspace(nbytes, dev, None)
+    nsing = ctypes.c_int64(0)
+    L.check("fsi_bjacobi_setup", L.lib().fsi_bjacobi_setup(
+        ctypes.byref(problem.struct), _ptr(pinv64), _ptr(pinv32), _ptr(blocks), ctypes.byref(nsing),
+        _ptr(ws), ws.numel(), _stream(stream)))
+    return pinv64, pinv32, blocks, int(nsing.value)
+
+
+def bjacobi_apply(grid, pinv: torch.Tensor, v: torch.Tensor, z: Optional[torch.Tensor] = None,
+                  stream=None):
+    g = grid_from(grid)
+    _need(v, "v", pinv.dtype, 4 * num_nodes(g))
+    if z is None:
+        z = torch.empty_like(v)
+    L.check("fsi_bjacobi_apply", L.lib().fsi_bjacobi_apply(
+        ctypes.byref(g), dtype_code(pinv.dtype), _ptr(pinv), _ptr(v), _ptr(z), _stream(stream)))
+    return z
+
+
+def solve_opts(restart=50, max_iters=2000, rtol=1e-10, inner=torch.float32,
+               inner_reduction=1e-5) -> FsiSolveOpts:
+    o = FsiSolveOpts()
+    o.restart, o.max_iters, o.rtol = int(restart), int(max_iters), float(rtol)
+    o.inner = dtype_code(inner)
+    o.inner_reduction = float(inner_reduction)
+    return o
+
+
+def fgmres_solve(J64: Problem, b: torch.Tensor, x: torch.Tensor, opts: FsiSolveOpts,
+                 J32: Optional[Problem] = None, pinv: Optional[torch.Tensor] = None,
+                 ws: Optional[torch.Tensor] = None, stream=None, check: bool = True):
+    """Mixed-precision FGMRES (fsi_fgmres_solve); x is updated in place. Returns (status, stats)."""
+    _need(b, "b", torch.float64, 4 * J64.N)
+    _need(x, "x", torch.float64, 4 * J64.N)
+    p32 = ctypes.byref(J32.struct) if J32 is not None else None
+    nbytes = int(L.lib().fsi_fgmres_workspace(ctypes.byref(J64.struct), p32, ctypes.byref(opts)))
+    if nbytes == 0:
+        raise ValueError("invalid FGMRES arguments: " + L.lib().fsi_last_error().decode())
+    ws = _workspace(nbytes, x.device, ws)
+    st = FsiSolveStats()
+    rc = L.lib().fsi_fgmres_solve(ctypes.byref(J64.struct), p32, _ptr(pinv), _ptr(b), _ptr(x),
+                                  ctypes.byref(opts), ctypes.byref(st), _ptr(ws), ws.numel(),
+                                  _stream(stream))
+    if check:
+        L.check("fsi_fgmres_solve", rc)
+    return rc, st
+
+
+def newton_opts(tol_abs, max_newton=20, eta=1e-3, restart=50, max_krylov=2000,
+                inner=torch.float32, inner_reduction=1e-5) -> FsiNewtonOpts:
+    o = FsiNewtonOpts()
+    o.max_newton, o.tol_abs, o.eta = int(max_newton), float(tol_abs), float(eta)
+    o.restart, o.max_krylov = int(restart), int(max_krylov)
+    o.inner = dtype_code(inner)
+    o.inner_reduction = float(inner_reduction)
+    return o
+
+
+def newton_solve(P64: Problem, f: torch.Tensor, x: torch.Tensor, opts: FsiNewtonOpts,
+                 P32: Optional[Problem] = None, lamg=None, gD=None,
+                 ws: Optional[torch.Tensor] = None, stream=None, check: bool = True):
+    """One implicit step by Newton (fsi_newton_solve); x updated in place. Returns (status, stats)."""
+    _need(x, "x", torch.float64, 4 * P64.N)
+    _need(f, "f", torch.float64, 3 * P64.N)
+    p32 = ctypes.byref(P32.struct) if P32 is not None else None
+    nbytes = int(L.lib().fsi_newton_workspace(ctypes.byref(P64.struct), p32, ctypes.byref(opts)))
+    if nbytes == 0:
+        raise ValueError("invalid Newton arguments: " + L.lib().fsi_last_error().decode())
+    ws = _workspace(nbytes, x.device, ws)
+    st = FsiNewtonStats()
+    rc = L.lib().fsi_newton_solve(ctypes.byref(P64.struct), p32, _ptr(f), _ptr(lamg), _ptr(gD),
+                                  _ptr(x), ctypes.byref(opts), ctypes.byref(st), _ptr(ws),
+                                  ws.numel(), _stream(stream))
+    if check:
+        L.check("fsi_newton_solve", rc)
+    return rc, st
 
 
 # --------------------------------------------------------------------------- timing

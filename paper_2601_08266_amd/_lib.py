@@ -41,6 +41,32 @@ class FsiProblem(ctypes.Structure):
                 ("dlm_gram", ctypes.c_void_p)]
 
 
+class FsiSolveOpts(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+                ("rtol", ctypes.c_double), ("inner", ctypes.c_int),
+                ("inner_reduction", ctypes.c_double)]
+
+
+class FsiSolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("cycles", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("bnorm", ctypes.c_double), ("res0", ctypes.c_double),
+                ("res_final", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
+
+
+class FsiNewtonOpts(ctypes.Structure):
+    _fields_ = [("max_newton", ctypes.c_int32), ("tol_abs", ctypes.c_double),
+                ("eta", ctypes.c_double), ("restart", ctypes.c_int32),
+                ("max_krylov", ctypes.c_int32), ("inner", ctypes.c_int),
+                ("inner_reduction", ctypes.c_double)]
+
+
+class FsiNewtonStats(ctypes.Structure):
+    _fields_ = [("newton_iters", ctypes.c_int32), ("krylov_iters", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("res_hist", ctypes.c_double * 32),
+                ("t_total_ms", ctypes.c_double), ("t_residual_ms", ctypes.c_double),
+                ("t_setup_ms", ctypes.c_double), ("t_krylov_ms", ctypes.c_double)]
+
+
 class FsiError(RuntimeError):
     def __init__(self, func, code, msg):
         super().__init__(f"{func} failed with status {code}: {msg}")
@@ -73,6 +99,21 @@ SIGNATURES = {
                                     P]),
     "fsi_jacobian_workspace": (SZ, [ctypes.POINTER(FsiProblem)]),
     "fsi_jacobian_apply": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, P, SZ, P]),
+    "fsi_vms_residual": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, P, P, P, P, SZ, P]),
+    "fsi_bjacobi_workspace": (SZ, [ctypes.POINTER(FsiGrid)]),
+    "fsi_bjacobi_setup": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, P, ctypes.POINTER(I64),
+                                         P, SZ, P]),
+    "fsi_bjacobi_apply": (ctypes.c_int, [ctypes.POINTER(FsiGrid), ctypes.c_int, P, P, P, P]),
+    "fsi_fgmres_workspace": (SZ, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiProblem),
+                                  ctypes.POINTER(FsiSolveOpts)]),
+    "fsi_fgmres_solve": (ctypes.c_int, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiProblem), P,
+                                        P, P, ctypes.POINTER(FsiSolveOpts),
+                                        ctypes.POINTER(FsiSolveStats), P, SZ, P]),
+    "fsi_newton_workspace": (SZ, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiProblem),
+                                  ctypes.POINTER(FsiNewtonOpts)]),
+    "fsi_newton_solve": (ctypes.c_int, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiProblem), P, P,
+                                        P, P, ctypes.POINTER(FsiNewtonOpts),
+                                        ctypes.POINTER(FsiNewtonStats), P, SZ, P]),
     "fsi_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "fsi_profile_read": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(I64)]),

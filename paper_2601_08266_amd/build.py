@@ -16,8 +16,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfsi.so")
-SOURCES = ["api.cpp", "profile.cpp", "vms_q1.hip", "vms_q2.hip", "dlm.hip"]
-HEADERS = ["common.hpp", "kernels.hpp", "dlm.hpp", "profile.hpp"]
+SOURCES = ["api.cpp", "profile.cpp", "fgmres.cpp", "newton.cpp", "vms_q1.hip", "vms_q2.hip", "dlm.hip",
+           "bjacobi.hip", "krylov.hip"]
+HEADERS = ["common.hpp", "kernels.hpp", "dlm.hpp", "profile.hpp", "bjacobi.hpp", "krylov.hpp",
+           "fgmres.hpp", "newton.hpp"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

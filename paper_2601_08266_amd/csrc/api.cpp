@@ -3,8 +3,11 @@
 #include <cstdarg>
 #include <cstring>
 
+#include "bjacobi.hpp"
 #include "dlm.hpp"
+#include "fgmres.hpp"
 #include "kernels.hpp"
+#include "newton.hpp"
 
 namespace fsi {
 
@@ -93,20 +96,6 @@ size_t vms_workspace_bytes(const Geo &g, fsi_dtype dt)
     return align_up((size_t)b.nb * 4 * b.nl * (dt == FSI_F64 ? 8 : 4));
 }
 
-// declared in the kernel translation units
-template <typename T>
-int launch_q1_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, const T *s,
-                    const uint32_t *mask, const T *gram, const int32_t *occ_index, T *part,
-                    const BrickLayout &bl, hipStream_t st);
-template <typename T>
-int launch_q2_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, const T *s,
-                    const uint32_t *mask, const T *gram, const int32_t *occ_index, T *part,
-                    const BrickLayout &bl, hipStream_t st);
-template <typename T, int P, int BX, int BY, int BZ>
-int launch_gather(const Geo &g, const T *part, const BrickLayout &bl, const T *x,
-                  const uint32_t *mask, T *y, const T *csum, const int32_t *occ_index,
-                  hipStream_t st);
-
 template <typename T>
 static int vms_apply_t(const Geo &g, const fsi_vms_params &prm, const T *a, const T *s,
                        const uint32_t *mask, const T *x, T *y, const DlmView *dlm, void *ws,
@@ -123,7 +112,7 @@ static int vms_apply_t(const Geo &g, const fsi_vms_params &prm, const T *a, cons
     const int32_t *gidx = use_gram ? dlm->occ_index : nullptr;
     int rc;
     if (g.p == 1)
-        rc = launch_q1_cells<T>(g, k, x, a, s, mask, gram, gidx, part, bl, st);
+        rc = launch_q1_cells<T>(g, k, x, a, s, mask, gram, gidx, part, bl, st, false);
     else
         rc = launch_q2_cells<T>(g, k, x, a, s, mask, gram, gidx, part, bl, st);
     if (rc) return rc;
@@ -134,10 +123,47 @@ static int vms_apply_t(const Geo &g, const fsi_vms_params &prm, const T *a, cons
                                     mask, csum, st);
         if (rc) return rc;
     }
-    const int32_t *occ_index = csum ? dlm->occ_index : nullptr;
+    GatherOpts<T> o;
+    o.csum = csum;
+    o.occ_index = csum ? dlm->occ_index : nullptr;
     if (g.p == 1)
-        return launch_gather<T, 1, Q1_BX, Q1_BY, Q1_BZ>(g, part, bl, x, mask, y, csum, occ_index, st);
-    return launch_gather<T, 2, Q2_BX, Q2_BY, Q2_BZ>(g, part, bl, x, mask, y, csum, occ_index, st);
+        return launch_gather<T, 1, Q1_BX, Q1_BY, Q1_BZ>(g, part, bl, x, mask, y, o, st);
+    return launch_gather<T, 2, Q2_BX, Q2_BY, Q2_BZ>(g, part, bl, x, mask, y, o, st);
+}
+
+template <typename T>
+static int vms_residual_t(const Geo &g, const fsi_vms_params &prm, const T *s, const uint32_t *mask,
+                          const T *gD, const T *x, const T *f, const DlmView *dlm, const T *lamg,
+                          T *R, void *ws, hipStream_t st)
+{
+    const BrickLayout bl = brick_layout(g);
+    const VmsConst<T> k = make_vms_const<T>(g, prm, s != nullptr);
+    T *part = reinterpret_cast<T *>(ws);
+    const bool use_gram = dlm != nullptr && dlm->n_occ > 0 && dlm->gram != nullptr;
+    const T *gram = use_gram ? reinterpret_cast<const T *>(dlm->gram) : nullptr;
+    const int32_t *gidx = use_gram ? dlm->occ_index : nullptr;
+    int rc = launch_q1_cells<T>(g, k, x, f, s, mask, gram, gidx, part, bl, st, true);
+    if (rc) return rc;
+    GatherOpts<T> o;
+    o.sub3 = lamg;
+    o.gD = gD;
+    if (o.gD == nullptr && mask != nullptr) {
+        set_error("residual with a Dirichlet mask needs the Dirichlet values gD");
+        return FSI_ERR_ARG;
+    }
+    return launch_gather<T, 1, Q1_BX, Q1_BY, Q1_BZ>(g, part, bl, x, mask, R, o, st);
+}
+
+int launch_vms_residual(const Geo &g, const fsi_vms_params &prm, fsi_dtype dt, const void *s,
+                        const uint32_t *mask, const void *gD, const void *x, const void *f,
+                        const DlmView *dlm, const void *lamg, void *R, void *ws, hipStream_t st)
+{
+    if (dt == FSI_F64)
+        return vms_residual_t<double>(g, prm, (const double *)s, mask, (const double *)gD,
+                                      (const double *)x, (const double *)f, dlm,
+                                      (const double *)lamg, (double *)R, ws, st);
+    return vms_residual_t<float>(g, prm, (const float *)s, mask, (const float *)gD, (const float *)x,
+                                 (const float *)f, dlm, (const float *)lamg, (float *)R, ws, st);
 }
 
 int launch_vms_apply(const Geo &g, const fsi_vms_params &prm, fsi_dtype dt, const void *a,
@@ -344,4 +370,216 @@ FSI_API int fsi_jacobian_apply(const fsi_problem *p, const void *x, void *y, voi
               p->n_occ, p->occ_index, p->kappa, p->dlm_gram};
     return launch_vms_apply(g, p->prm, p->dtype, p->a, p->s, p->dir_mask, x, y,
                             p->n_occ > 0 ? &v : nullptr, ws, ws_bytes, as_stream(stream));
+}
+
+static DlmView view_of(const fsi_problem *p)
+{
+    return DlmView{p->m,     p->cell,      p->xi,    p->perm,     p->occ_cell, p->occ_start,
+                   p->n_occ, p->occ_index, p->kappa, p->dlm_gram};
+}
+
+FSI_API int fsi_vms_residual(const fsi_problem *p, const void *f, const void *lamg, const void *gD,
+                             const void *x, void *R, void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    FSI_CHECK_ARG(p != nullptr, "problem is NULL");
+    int rc = check_grid(&p->grid);
+    if (rc) return rc;
+    rc = check_params(&p->prm);
+    if (rc) return rc;
+    FSI_CHECK_ARG(dtype_ok(p->dtype), "bad dtype");
+    if (p->grid.order != 1) {
+        set_error("the residual kernel is implemented for Q1 grids");
+        return FSI_ERR_UNSUPPORTED;
+    }
+    FSI_CHECK_ARG(f && x && R && x != R, "f, x, R must be non-NULL and x != R");
+    FSI_CHECK_ARG(p->dir_mask == nullptr || gD != nullptr, "gD required with a Dirichlet mask");
+    if (p->n_occ > 0 && p->dlm_gram == nullptr) {
+        set_error("the residual needs the per-cell DLM blocks (fsi_dlm_gram) when n_occ > 0");
+        return FSI_ERR_UNSUPPORTED;
+    }
+    const Geo g = make_geo(p->grid);
+    const size_t need = vms_workspace_bytes(g, p->dtype) + dlm_csum_bytes(g, p->n_occ, p->dtype);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+        return FSI_ERR_WORKSPACE;
+    }
+    DlmView v = view_of(p);
+    return launch_vms_residual(g, p->prm, p->dtype, p->s, p->dir_mask, gD, x, f,
+                               p->n_occ > 0 ? &v : nullptr, lamg, R, ws, as_stream(stream));
+}
+
+FSI_API size_t fsi_bjacobi_workspace(const fsi_grid *grid)
+{
+    if (check_grid(grid) != FSI_OK) return 0;
+    return bjacobi_workspace_bytes(make_geo(*grid));
+}
+
+FSI_API int fsi_bjacobi_setup(const fsi_problem *p, double *pinv64, float *pinv32, double *blocks,
+                              int64_t *n_singular_host, void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_problem(p);
+    if (rc) return rc;
+    FSI_CHECK_ARG(p->dtype == FSI_F64, "block-Jacobi setup takes the FP64 problem");
+    FSI_CHECK_ARG(pinv64 || pinv32 || blocks, "no output requested");
+    if (p->n_occ > 0 && p->dlm_gram == nullptr) {
+        set_error("block-Jacobi setup needs the per-cell DLM blocks (fsi_dlm_gram) when n_occ > 0");
+        return FSI_ERR_UNSUPPORTED;
+    }
+    const Geo g = make_geo(p->grid);
+    const size_t need = bjacobi_workspace_bytes(g);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+        return FSI_ERR_WORKSPACE;
+    }
+    return launch_bjacobi_setup(g, p->prm, (const double *)p->a, (const double *)p->s, p->dir_mask,
+                                p->n_occ > 0 ? (const double *)p->dlm_gram : nullptr, p->occ_index,
+                                blocks, pinv64, pinv32, n_singular_host, ws, as_stream(stream));
+}
+
+FSI_API int fsi_bjacobi_apply(const fsi_grid *grid, fsi_dtype dtype, const void *pinv, const void *v,
+                              void *z, void *stream)
+{
+    clear_error();
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    FSI_CHECK_ARG(dtype_ok(dtype), "bad dtype");
+    FSI_CHECK_ARG(pinv && v && z, "pinv, v and z must be non-NULL");
+    return launch_bjacobi_apply(make_geo(*grid).N, dtype, pinv, v, z, as_stream(stream));
+}
+
+static int check_solve(const fsi_problem *J64, const fsi_problem *J32, const fsi_solve_opts *o)
+{
+    int rc = check_problem(J64);
+    if (rc) return rc;
+    FSI_CHECK_ARG(J64->dtype == FSI_F64, "J64 must be an FP64 problem");
+    FSI_CHECK_ARG(o != nullptr, "opts is NULL");
+    FSI_CHECK_ARG(o->restart >= 1 && o->restart <= 400, "restart must be in [1, 400]");
+    FSI_CHECK_ARG(o->max_iters >= 1, "max_iters must be >= 1");
+    FSI_CHECK_ARG(std::isfinite(o->rtol) && o->rtol > 0.0 && o->rtol < 1.0, "rtol must be in (0,1)");
+    FSI_CHECK_ARG(dtype_ok(o->inner), "bad inner dtype");
+    if (o->inner == FSI_F32) {
+        FSI_CHECK_ARG(J32 != nullptr, "inner FP32 needs the FP32 problem");
+        rc = check_problem(J32);
+        if (rc) return rc;
+        FSI_CHECK_ARG(J32->dtype == FSI_F32, "J32 must be an FP32 problem");
+        FSI_CHECK_ARG(std::memcmp(&J32->grid, &J64->grid, sizeof(fsi_grid)) == 0,
+                      "J32 and J64 grids differ");
+        FSI_CHECK_ARG(std::isfinite(o->inner_reduction) && o->inner_reduction > 0.0 &&
+                          o->inner_reduction < 1.0,
+                      "inner_reduction must be in (0,1)");
+    }
+    return FSI_OK;
+}
+
+static size_t jac_ws(const fsi_problem *p)
+{
+    const Geo g = make_geo(p->grid);
+    return vms_workspace_bytes(g, p->dtype) + dlm_csum_bytes(g, p->n_occ, p->dtype);
+}
+
+FSI_API size_t fsi_fgmres_workspace(const fsi_problem *J64, const fsi_problem *J32,
+                                    const fsi_solve_opts *o)
+{
+    if (check_solve(J64, J32, o) != FSI_OK) return 0;
+    size_t jw = jac_ws(J64);
+    if (o->inner == FSI_F32) jw = std::max(jw, jac_ws(J32));
+    return fgmres_workspace_bytes(4 * make_geo(J64->grid).N, o->restart, o->inner, jw);
+}
+
+FSI_API int fsi_fgmres_solve(const fsi_problem *J64, const fsi_problem *J32, const void *pinv,
+                             const double *b, double *x, const fsi_solve_opts *o,
+                             fsi_solve_stats *stats, void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_solve(J64, J32, o);
+    if (rc) return rc;
+    FSI_CHECK_ARG(b && x && b != x, "b and x must be non-NULL and distinct");
+    size_t jw = jac_ws(J64);
+    if (o->inner == FSI_F32) jw = std::max(jw, jac_ws(J32));
+    const Geo g = make_geo(J64->grid);
+    const size_t need = fgmres_workspace_bytes(4 * g.N, o->restart, o->inner, jw);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+        return FSI_ERR_WORKSPACE;
+    }
+    const DlmView v64 = view_of(J64);
+    JacobianCall c64{[&](const void *xx, void *yy, void *w, hipStream_t s) {
+        return launch_vms_apply(g, J64->prm, FSI_F64, J64->a, J64->s, J64->dir_mask, xx, yy,
+                                J64->n_occ > 0 ? &v64 : nullptr, w, jw, s);
+    }};
+    DlmView v32{};
+    JacobianCall c32;
+    if (o->inner == FSI_F32) {
+        v32 = view_of(J32);
+        c32.apply = [&](const void *xx, void *yy, void *w, hipStream_t s) {
+            return launch_vms_apply(g, J32->prm, FSI_F32, J32->a, J32->s, J32->dir_mask, xx, yy,
+                                    J32->n_occ > 0 ? &v32 : nullptr, w, jw, s);
+        };
+    }
+    return fgmres_solve(g, c64, o->inner == FSI_F32 ? &c32 : nullptr, pinv, b, x, *o, stats, ws, jw,
+                        as_stream(stream));
+}
+
+static int check_newton(const fsi_problem *P64, const fsi_problem *P32, const fsi_newton_opts *o)
+{
+    int rc = check_problem(P64);
+    if (rc) return rc;
+    FSI_CHECK_ARG(P64->dtype == FSI_F64, "P64 must be an FP64 problem");
+    FSI_CHECK_ARG(o != nullptr, "opts is NULL");
+    FSI_CHECK_ARG(o->max_newton >= 0 && o->max_newton <= 200, "max_newton out of range");
+    FSI_CHECK_ARG(std::isfinite(o->tol_abs) && o->tol_abs >= 0.0, "tol_abs must be finite and >= 0");
+    FSI_CHECK_ARG(std::isfinite(o->eta) && o->eta > 0.0 && o->eta < 1.0, "eta must be in (0,1)");
+    FSI_CHECK_ARG(o->restart >= 1 && o->restart <= 400, "restart must be in [1, 400]");
+    FSI_CHECK_ARG(o->max_krylov >= 1, "max_krylov must be >= 1");
+    FSI_CHECK_ARG(dtype_ok(o->inner), "bad inner dtype");
+    if (P64->grid.order != 1) {
+        set_error("Newton steps are implemented for Q1 grids");
+        return FSI_ERR_UNSUPPORTED;
+    }
+    if (P64->n_occ > 0) FSI_CHECK_ARG(P64->dlm_gram != nullptr, "P64->dlm_gram required");
+    if (o->inner == FSI_F32) {
+        FSI_CHECK_ARG(P32 != nullptr, "inner FP32 needs the FP32 problem");
+        rc = check_problem(P32);
+        if (rc) return rc;
+        FSI_CHECK_ARG(P32->dtype == FSI_F32, "P32 must be an FP32 problem");
+        FSI_CHECK_ARG(std::memcmp(&P32->grid, &P64->grid, sizeof(fsi_grid)) == 0, "grids differ");
+        if (P32->n_occ > 0) FSI_CHECK_ARG(P32->dlm_gram != nullptr, "P32->dlm_gram required");
+        FSI_CHECK_ARG(std::isfinite(o->inner_reduction) && o->inner_reduction > 0.0 &&
+                          o->inner_reduction < 1.0,
+                      "inner_reduction must be in (0,1)");
+    }
+    return FSI_OK;
+}
+
+FSI_API size_t fsi_newton_workspace(const fsi_problem *P64, const fsi_problem *P32,
+                                    const fsi_newton_opts *o)
+{
+    if (check_newton(P64, P32, o) != FSI_OK) return 0;
+    size_t jw = jac_ws(P64);
+    if (o->inner == FSI_F32) jw = std::max(jw, jac_ws(P32));
+    return newton_workspace_bytes(make_geo(P64->grid), *o, jw);
+}
+
+FSI_API int fsi_newton_solve(const fsi_problem *P64, const fsi_problem *P32, const double *f,
+                             const double *lamg, const double *gD, double *x,
+                             const fsi_newton_opts *o, fsi_newton_stats *stats, void *ws,
+                             size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_newton(P64, P32, o);
+    if (rc) return rc;
+    FSI_CHECK_ARG(f && x, "f and x must be non-NULL");
+    FSI_CHECK_ARG(P64->dir_mask == nullptr || gD != nullptr, "gD required with a Dirichlet mask");
+    size_t jw = jac_ws(P64);
+    if (o->inner == FSI_F32) jw = std::max(jw, jac_ws(P32));
+    const Geo g = make_geo(P64->grid);
+    const size_t need = newton_workspace_bytes(g, *o, jw);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+        return FSI_ERR_WORKSPACE;
+    }
+    return newton_solve(g, *P64, o->inner == FSI_F32 ? P32 : nullptr, f, lamg, gD, x, *o, stats, ws, jw,
+                        as_stream(stream));
 }

@@ -1,0 +1,221 @@
+// Flexible GMRES with right preconditioning, restarted, host-driven.
+//
+// Precision split: the Krylov basis V, the CGS2 orthogonalisation, the
+// Hessenberg/Givens recurrences, the solution x and the restart residual
+// b - J x are FP64; the preconditioner and Jacobian applies inside a cycle
+// run in the inner precision (FP32 or FP64) and the preconditioned vectors Z
+// are stored in that precision.  Every restart begins from the true FP64
+// residual, so the FP32 inner cycles act as iterative refinement steps.
+// Section 2.4 solves the reduced block system with block-preconditioned
+// Krylov iterations; this is that loop for the nodal block-Jacobi choice.
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "bjacobi.hpp"
+#include "fgmres.hpp"
+#include "krylov.hpp"
+#include "profile.hpp"
+
+namespace fsi {
+
+namespace {
+
+struct Layout {
+    size_t V, Z, w64, t32a, t32b, partial, hdev, jws, total;
+};
+
+Layout layout(int64_t n, int m, fsi_dtype inner, size_t jws_bytes)
+{
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    L.V = take((size_t)(m + 1) * n * sizeof(double));
+    L.Z = take((size_t)m * n * (inner == FSI_F64 ? sizeof(double) : sizeof(float)));
+    L.w64 = take((size_t)n * sizeof(double));
+    L.t32a = take((size_t)n * sizeof(float));
+    L.t32b = take((size_t)n * sizeof(float));
+    L.partial = take((size_t)(m + 2) * KRY_NB * sizeof(double));
+    L.hdev = take((size_t)(2 * (m + 2)) * sizeof(double));
+    L.jws = take(jws_bytes);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+size_t fgmres_workspace_bytes(int64_t ndof, int restart, fsi_dtype inner, size_t jws_bytes)
+{
+    return layout(ndof, restart, inner, jws_bytes).total;
+}
+
+int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32, const void *pinv,
+                 const double *b, double *x, const fsi_solve_opts &o, fsi_solve_stats *stats,
+                 void *ws, size_t jws_bytes, hipStream_t st)
+{
+    ProfileScope prof("fgmres_solve", st);
+    const auto t_start = std::chrono::steady_clock::now();
+    const int64_t N = g.N, n = 4 * N;
+    const int m = o.restart;
+    const fsi_dtype inner = o.inner;
+    const Layout L = layout(n, m, inner, jws_bytes);
+    char *base = reinterpret_cast<char *>(ws);
+    double *V = reinterpret_cast<double *>(base + L.V);
+    void *Z = base + L.Z;
+    double *w64 = reinterpret_cast<double *>(base + L.w64);
+    float *t32a = reinterpret_cast<float *>(base + L.t32a);
+    float *t32b = reinterpret_cast<float *>(base + L.t32b);
+    double *partial = reinterpret_cast<double *>(base + L.partial);
+    double *hdev = reinterpret_cast<double *>(base + L.hdev);
+    void *jws = base + L.jws;
+    const size_t zel = inner == FSI_F64 ? sizeof(double) : sizeof(float);
+
+    fsi_solve_stats S{};
+    int rc = FSI_OK;
+    auto fetch = [&](double *host, const double *dev, int count) -> int {
+        FSI_HIP(hipMemcpyAsync(host, dev, count * sizeof(double), hipMemcpyDeviceToHost, st));
+        FSI_HIP(hipStreamSynchronize(st));
+        return FSI_OK;
+    };
+#define TRY(expr)            \
+    do {                     \
+        rc = (expr);         \
+        if (rc) goto done;   \
+    } while (0)
+
+    {
+        double bnorm = 0.0;
+        TRY(kry_norm(n, b, partial, hdev, st));
+        TRY(fetch(&bnorm, hdev, 1));
+        S.bnorm = bnorm;
+        if (!std::isfinite(bnorm)) {
+            set_error("right-hand side contains NaN/Inf");
+            rc = FSI_ERR_NAN;
+            goto done;
+        }
+        if (bnorm == 0.0) {
+            FSI_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), st));
+            S.res0 = S.res_final = 0.0;
+            goto done;
+        }
+        const double target = o.rtol * bnorm;
+        std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), h1(m + 1), h2(m + 1);
+        double prev_beta = -1.0;
+        int stalls = 0;
+        for (;;) {
+            // true residual r = b - J64 x in FP64 (stored in V[0])
+            TRY(J64.apply(x, w64, jws, st));
+            FSI_HIP(hipMemcpyAsync(V, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+            TRY(kry_axpby(n, -1.0, w64, 1.0, V, st));
+            double beta = 0.0;
+            TRY(kry_norm(n, V, partial, hdev, st));
+            TRY(fetch(&beta, hdev, 1));
+            if (S.cycles == 0) S.res0 = beta;
+            S.res_final = beta;
+            if (!std::isfinite(beta)) {
+                set_error("residual norm is NaN/Inf");
+                rc = FSI_ERR_NAN;
+                goto done;
+            }
+            if (beta <= target) break;
+            if (S.iters >= o.max_iters) {
+                set_error("no convergence in %d iterations (residual %.3e, target %.3e)", S.iters,
+                          beta, target);
+                rc = FSI_ERR_NOT_CONVERGED;
+                goto done;
+            }
+            if (prev_beta >= 0.0 && beta > 0.999 * prev_beta) {
+                if (++stalls >= 3) {
+                    set_error("stagnation at residual %.3e (target %.3e)", beta, target);
+                    rc = FSI_ERR_NOT_CONVERGED;
+                    goto done;
+                }
+            }
+            prev_beta = beta;
+            TRY(kry_scale_inv(n, V, hdev, V, st));
+            std::fill(gv.begin(), gv.end(), 0.0);
+            gv[0] = beta;
+            // an FP32 inner cycle cannot resolve much below its own rounding level
+            double cycle_target = target;
+            if (inner == FSI_F32) cycle_target = std::max(target, o.inner_reduction * beta);
+            int kk = 0;
+            for (int j = 0; j < m && S.iters < o.max_iters; ++j) {
+                double *Vj = V + (size_t)j * n;
+                char *Zj = reinterpret_cast<char *>(Z) + (size_t)j * n * zel;
+                if (inner == FSI_F32) {
+                    TRY(kry_cast_f64_f32(n, Vj, t32a, st));
+                    if (pinv) TRY(launch_bjacobi_apply(N, FSI_F32, pinv, t32a, Zj, st));
+                    else FSI_HIP(hipMemcpyAsync(Zj, t32a, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
+                    TRY(J32->apply(Zj, t32b, jws, st));
+                    TRY(kry_cast_f32_f64(n, t32b, w64, st));
+                } else {
+                    if (pinv) TRY(launch_bjacobi_apply(N, FSI_F64, pinv, Vj, Zj, st));
+                    else FSI_HIP(hipMemcpyAsync(Zj, Vj, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+                    TRY(J64.apply(Zj, w64, jws, st));
+                }
+                // classical Gram-Schmidt, twice
+                TRY(kry_multidot(n, j + 1, V, n, w64, partial, hdev, st));
+                TRY(kry_multi_axpy(n, j + 1, V, n, hdev, w64, st));
+                TRY(fetch(h1.data(), hdev, j + 1));
+                TRY(kry_multidot(n, j + 1, V, n, w64, partial, hdev, st));
+                TRY(kry_multi_axpy(n, j + 1, V, n, hdev, w64, st));
+                TRY(fetch(h2.data(), hdev, j + 1));
+                double hn = 0.0;
+                TRY(kry_norm(n, w64, partial, hdev, st));
+                TRY(fetch(&hn, hdev, 1));
+                for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h1[i] + h2[i];
+                H[(size_t)(j + 1) * m + j] = hn;
+                if (!std::isfinite(hn)) {
+                    set_error("Arnoldi vector norm is NaN/Inf");
+                    rc = FSI_ERR_NAN;
+                    goto done;
+                }
+                if (hn > 0.0) TRY(kry_scale_inv(n, w64, hdev, V + (size_t)(j + 1) * n, st));
+                for (int i = 0; i < j; ++i) {
+                    const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
+                    H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
+                    H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+                }
+                const double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
+                const double den = std::hypot(a, c);
+                if (den == 0.0) {
+                    set_error("Krylov breakdown (zero Hessenberg column)");
+                    rc = FSI_ERR_BREAKDOWN;
+                    goto done;
+                }
+                cs[j] = a / den;
+                sn[j] = c / den;
+                H[(size_t)j * m + j] = den;
+                H[(size_t)(j + 1) * m + j] = 0.0;
+                gv[j + 1] = -sn[j] * gv[j];
+                gv[j] = cs[j] * gv[j];
+                ++S.iters;
+                kk = j + 1;
+                if (std::fabs(gv[j + 1]) <= cycle_target || hn == 0.0) break;
+            }
+            // y = H^{-1} g (upper triangular), x += Z y
+            for (int i = kk - 1; i >= 0; --i) {
+                double s = gv[i];
+                for (int k2 = i + 1; k2 < kk; ++k2) s -= H[(size_t)i * m + k2] * y[k2];
+                y[i] = s / H[(size_t)i * m + i];
+            }
+            FSI_HIP(hipMemcpyAsync(hdev, y.data(), kk * sizeof(double), hipMemcpyHostToDevice, st));
+            TRY(kry_update(n, kk, inner, Z, n, hdev, x, st));
+            FSI_HIP(hipStreamSynchronize(st));   // y lives on the host stack frame
+            ++S.cycles;
+        }
+    }
+done:
+#undef TRY
+    S.status = rc;
+    (void)hipStreamSynchronize(st);
+    S.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (stats) *stats = S;
+    return rc;
+}
+
+}  // namespace fsi

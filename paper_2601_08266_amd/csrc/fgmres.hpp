@@ -1,0 +1,20 @@
+// Internal declarations of the FGMRES driver.
+#pragma once
+
+#include <functional>
+
+#include "kernels.hpp"
+
+namespace fsi {
+
+// A bound Jacobian apply y = J x (x, y in the call's precision) with its workspace.
+struct JacobianCall {
+    std::function<int(const void *x, void *y, void *ws, hipStream_t st)> apply;
+};
+
+size_t fgmres_workspace_bytes(int64_t ndof, int restart, fsi_dtype inner, size_t jws_bytes);
+int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32, const void *pinv,
+                 const double *b, double *x, const fsi_solve_opts &o, fsi_solve_stats *stats,
+                 void *ws, size_t jws_bytes, hipStream_t st);
+
+}  // namespace fsi

@@ -28,6 +28,15 @@ constexpr int Q1_NL = (Q1_BX + 1) * (Q1_BY + 1) * (Q1_BZ + 1);
 constexpr int Q2_BX = 4, Q2_BY = 4, Q2_BZ = 4;
 constexpr int Q2_NL = (2 * Q2_BX + 1) * (2 * Q2_BY + 1) * (2 * Q2_BZ + 1);
 
+// How the node gather finishes each row.
+template <typename T>
+struct GatherOpts {
+    const T *csum = nullptr;          // per-occupied-cell DLM corner sums (pointwise path)
+    const int32_t *occ_index = nullptr;
+    const T *sub3 = nullptr;          // [3][N] subtracted from the momentum rows
+    const T *gD = nullptr;            // [3][N]: Dirichlet rows become x - gD instead of x
+};
+
 struct BrickLayout {
     int bx, by, bz;   // cells per brick
     int nbx, nby, nbz;
@@ -58,5 +67,23 @@ int launch_vms_apply(const Geo &g, const fsi_vms_params &prm, fsi_dtype dt, cons
                      const DlmView *dlm, void *ws, size_t ws_bytes, hipStream_t st);
 
 size_t dlm_csum_bytes(const Geo &g, int64_t n_occ, fsi_dtype dt);
+
+template <typename T>
+int launch_q1_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, const T *s,
+                    const uint32_t *mask, const T *gram, const int32_t *occ_index, T *part,
+                    const BrickLayout &bl, hipStream_t st, bool resid);
+template <typename T>
+int launch_q2_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, const T *s,
+                    const uint32_t *mask, const T *gram, const int32_t *occ_index, T *part,
+                    const BrickLayout &bl, hipStream_t st);
+template <typename T, int P, int BX, int BY, int BZ>
+int launch_gather(const Geo &g, const T *part, const BrickLayout &bl, const T *x,
+                  const uint32_t *mask, T *y, const GatherOpts<T> &o, hipStream_t st);
+
+// Nonlinear residual of one implicit step (Q1):
+//   R = A(a = u) x - F(f) + B^T kappa B u - lamg,   Dirichlet rows R = u - gD
+int launch_vms_residual(const Geo &g, const fsi_vms_params &prm, fsi_dtype dt, const void *s,
+                        const uint32_t *mask, const void *gD, const void *x, const void *f,
+                        const DlmView *dlm, const void *lamg, void *R, void *ws, hipStream_t st);
 
 }  // namespace fsi

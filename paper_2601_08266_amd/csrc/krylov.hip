@@ -1,0 +1,200 @@
+// Vector kernels of the Krylov solver: casts, axpby, deterministic multi-dot
+// (fixed-order block partials + fixed-order final sum), multi-axpy (CGS2
+// projections, solution update from the preconditioned basis).
+#include "krylov.hpp"
+
+namespace fsi {
+
+namespace {
+
+constexpr int KT = 256;      // threads per block
+constexpr int KG = 8;        // vectors per group in the multi-dot
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(KT) void cast_k(int64_t n, const TI *__restrict__ in, TO *__restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x; i < n; i += (int64_t)gridDim.x * KT)
+        out[i] = (TO)in[i];
+}
+
+// y = alpha x + beta y
+__global__ __launch_bounds__(KT) void axpby_k(int64_t n, double alpha, const double *__restrict__ x,
+                                              double beta, double *__restrict__ y)
+{
+    for (int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x; i < n; i += (int64_t)gridDim.x * KT)
+        y[i] = alpha * x[i] + beta * y[i];
+}
+
+// y = alpha x
+__global__ __launch_bounds__(KT) void scale_k(int64_t n, double alpha, const double *__restrict__ x,
+                                              double *__restrict__ y)
+{
+    for (int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x; i < n; i += (int64_t)gridDim.x * KT)
+        y[i] = alpha * x[i];
+}
+
+// out = x * s, s = 1 / dev[0] computed on the device side
+__global__ __launch_bounds__(KT) void scale_inv_k(int64_t n, const double *__restrict__ x,
+                                                  const double *__restrict__ dev, double *__restrict__ out)
+{
+    const double s = 1.0 / dev[0];
+    for (int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x; i < n; i += (int64_t)gridDim.x * KT)
+        out[i] = x[i] * s;
+}
+
+// partial[k][block] = sum over this block's contiguous chunk of V[k][i] * w[i], k < nk
+__global__ __launch_bounds__(KT) void multidot_k(int64_t n, int nk, const double *__restrict__ V,
+                                                 int64_t ldv, const double *__restrict__ w,
+                                                 double *__restrict__ partial)
+{
+    __shared__ double red[KG][KT];
+    const int t = threadIdx.x;
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    for (int g0 = 0; g0 < nk; g0 += KG) {
+        double acc[KG];
+#pragma unroll
+        for (int k = 0; k < KG; ++k) acc[k] = 0.0;
+        for (int64_t i = lo + t; i < hi; i += KT) {
+            const double wi = w[i];
+#pragma unroll
+            for (int k = 0; k < KG; ++k)
+                if (g0 + k < nk) acc[k] += V[(int64_t)(g0 + k) * ldv + i] * wi;
+        }
+#pragma unroll
+        for (int k = 0; k < KG; ++k) red[k][t] = acc[k];
+        __syncthreads();
+        for (int off = KT / 2; off > 0; off >>= 1) {
+            if (t < off)
+#pragma unroll
+                for (int k = 0; k < KG; ++k) red[k][t] += red[k][t + off];
+            __syncthreads();
+        }
+        if (t < KG && g0 + t < nk) partial[(int64_t)(g0 + t) * gridDim.x + blockIdx.x] = red[t][0];
+        __syncthreads();
+    }
+}
+
+// out[k] = sum_b partial[k][b] in block order (one thread per k)
+__global__ void reduce_partials_k(int nk, int nb, const double *__restrict__ partial,
+                                  double *__restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nk) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[(int64_t)k * nb + b];
+    out[k] = s;
+}
+
+// sqrt of a device scalar, in place
+__global__ void sqrt_k(double *v) { v[0] = sqrt(v[0]); }
+
+// w[i] -= sum_k h[k] V[k][i]
+__global__ __launch_bounds__(KT) void multi_axpy_k(int64_t n, int nk, const double *__restrict__ V,
+                                                   int64_t ldv, const double *__restrict__ h,
+                                                   double *__restrict__ w)
+{
+    for (int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x; i < n; i += (int64_t)gridDim.x * KT) {
+        double s = w[i];
+        for (int k = 0; k < nk; ++k) s -= h[k] * V[(int64_t)k * ldv + i];
+        w[i] = s;
+    }
+}
+
+// x[i] += sum_k y[k] Z[k][i]   (Z in the inner precision)
+template <typename TZ>
+__global__ __launch_bounds__(KT) void update_k(int64_t n, int nk, const TZ *__restrict__ Z, int64_t ldz,
+                                               const double *__restrict__ y, double *__restrict__ x)
+{
+    for (int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x; i < n; i += (int64_t)gridDim.x * KT) {
+        double s = 0.0;
+        for (int k = 0; k < nk; ++k) s += y[k] * (double)Z[(int64_t)k * ldz + i];
+        x[i] += s;
+    }
+}
+
+inline unsigned grid_for(int64_t n)
+{
+    int64_t b = (n + KT - 1) / KT;
+    return (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+}  // namespace
+
+int kry_cast_f64_f32(int64_t n, const double *in, float *out, hipStream_t st)
+{
+    hipLaunchKernelGGL((cast_k<double, float>), dim3(grid_for(n)), dim3(KT), 0, st, n, in, out);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+
+int kry_cast_f32_f64(int64_t n, const float *in, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL((cast_k<float, double>), dim3(grid_for(n)), dim3(KT), 0, st, n, in, out);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+
+int kry_axpby(int64_t n, double alpha, const double *x, double beta, double *y, hipStream_t st)
+{
+    hipLaunchKernelGGL(axpby_k, dim3(grid_for(n)), dim3(KT), 0, st, n, alpha, x, beta, y);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+
+int kry_scale(int64_t n, double alpha, const double *x, double *y, hipStream_t st)
+{
+    hipLaunchKernelGGL(scale_k, dim3(grid_for(n)), dim3(KT), 0, st, n, alpha, x, y);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+
+int kry_scale_inv(int64_t n, const double *x, const double *dev_scalar, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(scale_inv_k, dim3(grid_for(n)), dim3(KT), 0, st, n, x, dev_scalar, out);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+
+int kry_multidot(int64_t n, int nk, const double *V, int64_t ldv, const double *w, double *partial,
+                 double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(multidot_k, dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, w, partial);
+    FSI_LAUNCH_CHECK();
+    hipLaunchKernelGGL(reduce_partials_k, dim3((nk + 63) / 64), dim3(64), 0, st, nk, KRY_NB, partial, out);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+
+int kry_norm(int64_t n, const double *w, double *partial, double *out, hipStream_t st)
+{
+    int rc = kry_multidot(n, 1, w, n, w, partial, out, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(sqrt_k, dim3(1), dim3(1), 0, st, out);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+
+int kry_multi_axpy(int64_t n, int nk, const double *V, int64_t ldv, const double *h, double *w,
+                   hipStream_t st)
+{
+    hipLaunchKernelGGL(multi_axpy_k, dim3(grid_for(n)), dim3(KT), 0, st, n, nk, V, ldv, h, w);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+
+int kry_update(int64_t n, int nk, fsi_dtype dz, const void *Z, int64_t ldz, const double *y, double *x,
+               hipStream_t st)
+{
+    if (dz == FSI_F64)
+        hipLaunchKernelGGL(update_k<double>, dim3(grid_for(n)), dim3(KT), 0, st, n, nk,
+                           (const double *)Z, ldz, y, x);
+    else
+        hipLaunchKernelGGL(update_k<float>, dim3(grid_for(n)), dim3(KT), 0, st, n, nk,
+                           (const float *)Z, ldz, y, x);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+
+}  // namespace fsi

@@ -1,0 +1,23 @@
+// Internal declarations of the Krylov vector kernels and the FGMRES driver.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace fsi {
+
+constexpr int KRY_NB = 1024;   // blocks of the multi-dot (partials per vector)
+
+int kry_cast_f64_f32(int64_t n, const double *in, float *out, hipStream_t st);
+int kry_cast_f32_f64(int64_t n, const float *in, double *out, hipStream_t st);
+int kry_axpby(int64_t n, double alpha, const double *x, double beta, double *y, hipStream_t st);
+int kry_scale(int64_t n, double alpha, const double *x, double *y, hipStream_t st);
+int kry_scale_inv(int64_t n, const double *x, const double *dev_scalar, double *out, hipStream_t st);
+int kry_multidot(int64_t n, int nk, const double *V, int64_t ldv, const double *w, double *partial,
+                 double *out, hipStream_t st);
+int kry_norm(int64_t n, const double *w, double *partial, double *out, hipStream_t st);
+int kry_multi_axpy(int64_t n, int nk, const double *V, int64_t ldv, const double *h, double *w,
+                   hipStream_t st);
+int kry_update(int64_t n, int nk, fsi_dtype dz, const void *Z, int64_t ldz, const double *y, double *x,
+               hipStream_t st);
+
+}  // namespace fsi

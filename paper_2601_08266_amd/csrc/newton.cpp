@@ -1,0 +1,166 @@
+// Newton's method for one implicit step (section 2.4), host-driven:
+//   R_k = R(x_k)                      (residual kernel, FP64)
+//   P_k = nodal blocks of J(u_k)^-1   (block-Jacobi setup, FP64, FP32 copy)
+//   J(u_k) dx = -R_k                  (flexible GMRES, FP64 outer / inner precision)
+//   x_{k+1} = x_k + dx
+#include <chrono>
+#include <cmath>
+
+#include "bjacobi.hpp"
+#include "fgmres.hpp"
+#include "krylov.hpp"
+#include "newton.hpp"
+#include "profile.hpp"
+
+namespace fsi {
+
+namespace {
+
+struct NLayout {
+    size_t R, dx, pinv64, pinv32, a32, scratch, bjws, kws, total;
+};
+
+NLayout nlayout(const Geo &g, const fsi_newton_opts &o, size_t jws)
+{
+    NLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = off;
+        off += align_up(bytes);
+        return r;
+    };
+    L.R = take((size_t)4 * g.N * sizeof(double));
+    L.dx = take((size_t)4 * g.N * sizeof(double));
+    L.pinv64 = take((size_t)16 * g.N * sizeof(double));
+    L.pinv32 = take((size_t)16 * g.N * sizeof(float));
+    L.a32 = take((size_t)3 * g.N * sizeof(float));
+    L.scratch = take((size_t)(KRY_NB + 16) * sizeof(double));
+    L.bjws = take(bjacobi_workspace_bytes(g));
+    L.kws = take(fgmres_workspace_bytes(4 * g.N, o.restart, o.inner, jws));
+    L.total = off;
+    return L;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t)
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
+}
+
+}  // namespace
+
+size_t newton_workspace_bytes(const Geo &g, const fsi_newton_opts &o, size_t jws)
+{
+    return nlayout(g, o, jws).total;
+}
+
+int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, const double *f,
+                 const double *lamg, const double *gD, double *x, const fsi_newton_opts &o,
+                 fsi_newton_stats *stats, void *ws, size_t jws, hipStream_t st)
+{
+    ProfileScope prof("newton_solve", st);
+    const auto t0 = std::chrono::steady_clock::now();
+    const NLayout L = nlayout(g, o, jws);
+    char *base = reinterpret_cast<char *>(ws);
+    double *R = reinterpret_cast<double *>(base + L.R);
+    double *dx = reinterpret_cast<double *>(base + L.dx);
+    double *pinv64 = reinterpret_cast<double *>(base + L.pinv64);
+    float *pinv32 = reinterpret_cast<float *>(base + L.pinv32);
+    float *a32 = reinterpret_cast<float *>(base + L.a32);
+    void *bjws = base + L.bjws;
+    void *kws = base + L.kws;
+    const int64_t n = 4 * g.N;
+
+    fsi_newton_stats S{};
+    int rc = FSI_OK;
+    const DlmView v64{P64.m,     P64.cell,      P64.xi,    P64.perm,     P64.occ_cell, P64.occ_start,
+                      P64.n_occ, P64.occ_index, P64.kappa, P64.dlm_gram};
+    DlmView v32{};
+    if (P32) v32 = DlmView{P32->m,     P32->cell,      P32->xi,    P32->perm,     P32->occ_cell,
+                           P32->occ_start, P32->n_occ, P32->occ_index, P32->kappa, P32->dlm_gram};
+    double *scratch = reinterpret_cast<double *>(base + L.scratch);
+    auto rnorm = [&](double &out) -> int {
+        int r = kry_norm(n, R, scratch, scratch + KRY_NB, st);
+        if (r) return r;
+        FSI_HIP(hipMemcpyAsync(&out, scratch + KRY_NB, sizeof(double), hipMemcpyDeviceToHost, st));
+        FSI_HIP(hipStreamSynchronize(st));
+        return FSI_OK;
+    };
+    for (int it = 0;; ++it) {
+        auto tr = std::chrono::steady_clock::now();
+        rc = launch_vms_residual(g, P64.prm, FSI_F64, P64.s, P64.dir_mask, gD, x, f,
+                                 P64.n_occ > 0 ? &v64 : nullptr, lamg, R, kws, st);
+        if (rc) break;
+        double rn = 0.0;
+        rc = rnorm(rn);
+        if (rc) break;
+        S.t_residual_ms += ms_since(tr);
+        if (it < 32) S.res_hist[it] = rn;
+        if (!std::isfinite(rn)) {
+            set_error("Newton residual is NaN/Inf");
+            rc = FSI_ERR_NAN;
+            break;
+        }
+        if (rn <= o.tol_abs) break;
+        if (it >= o.max_newton) {
+            set_error("Newton: no convergence in %d iterations (||R|| = %.3e, target %.3e)", it, rn,
+                      o.tol_abs);
+            rc = FSI_ERR_NOT_CONVERGED;
+            break;
+        }
+        // J(u_k): advection field = current velocity (first 3N of x)
+        auto ts = std::chrono::steady_clock::now();
+        fsi_problem J64 = P64;
+        J64.a = x;
+        rc = launch_bjacobi_setup(g, J64.prm, x, (const double *)J64.s, J64.dir_mask,
+                                  J64.n_occ > 0 ? (const double *)J64.dlm_gram : nullptr, J64.occ_index,
+                                  nullptr, pinv64, o.inner == FSI_F32 ? pinv32 : nullptr, nullptr, bjws,
+                                  st);
+        if (rc) break;
+        fsi_problem J32{};
+        if (o.inner == FSI_F32) {
+            rc = kry_cast_f64_f32(3 * g.N, x, a32, st);
+            if (rc) break;
+            J32 = *P32;
+            J32.a = a32;
+        }
+        S.t_setup_ms += ms_since(ts);
+        // b = -R, dx = 0
+        auto tk = std::chrono::steady_clock::now();
+        rc = kry_scale(n, -1.0, R, R, st);
+        if (rc) break;
+        FSI_HIP(hipMemsetAsync(dx, 0, (size_t)n * sizeof(double), st));
+        fsi_solve_opts so{};
+        so.restart = o.restart;
+        so.max_iters = o.max_krylov;
+        so.rtol = std::max(o.eta, 0.5 * o.tol_abs / rn);
+        if (so.rtol >= 1.0) so.rtol = 0.5;
+        so.inner = o.inner;
+        so.inner_reduction = o.inner_reduction;
+        JacobianCall c64{[&](const void *xx, void *yy, void *w, hipStream_t s2) {
+            return launch_vms_apply(g, J64.prm, FSI_F64, J64.a, J64.s, J64.dir_mask, xx, yy,
+                                    J64.n_occ > 0 ? &v64 : nullptr, w, jws, s2);
+        }};
+        JacobianCall c32{[&](const void *xx, void *yy, void *w, hipStream_t s2) {
+            return launch_vms_apply(g, J32.prm, FSI_F32, J32.a, J32.s, J32.dir_mask, xx, yy,
+                                    J32.n_occ > 0 ? &v32 : nullptr, w, jws, s2);
+        }};
+        fsi_solve_stats ks{};
+        rc = fgmres_solve(g, c64, o.inner == FSI_F32 ? &c32 : nullptr,
+                          o.inner == FSI_F32 ? (const void *)pinv32 : (const void *)pinv64, R, dx, so,
+                          &ks, kws, jws, st);
+        S.krylov_iters += ks.iters;
+        S.t_krylov_ms += ms_since(tk);
+        if (rc == FSI_ERR_NOT_CONVERGED) rc = FSI_OK;   // inexact Newton: take the step anyway
+        if (rc) break;
+        rc = kry_axpby(n, 1.0, dx, 1.0, x, st);
+        if (rc) break;
+        ++S.newton_iters;
+    }
+    S.status = rc;
+    (void)hipStreamSynchronize(st);
+    S.t_total_ms = ms_since(t0);
+    if (stats) *stats = S;
+    return rc;
+}
+
+}  // namespace fsi

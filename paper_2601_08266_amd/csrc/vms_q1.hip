@@ -98,7 +98,10 @@ __device__ __forceinline__ void moments(T m[8], T F0, T G0, T G1, T G2, const QP
 // Full element computation for one Q1 cell: in[f][A] nodal x (masked), a, s; out[f][A].
 // If dlm != nullptr, the cell's 8x8 block of B^T diag(kappa) B is applied to the
 // velocity and added to the momentum outputs.
-template <typename T>
+// RESID = true: nonlinear residual of a time step instead of the linear apply: the
+// advection field is the velocity itself (a = u) and ca holds the nodal source
+// f = c_m u_old + body force, whose Galerkin/SUPG/PSPG weighting is subtracted.
+template <typename T, bool RESID>
 __device__ __forceinline__ void q1_cell(const VmsConst<T> &k, T cu[4][8], T ca[3][8], T cs[8],
                                         T smin, const T *__restrict__ dlm, T out[4][8])
 {
@@ -159,7 +162,19 @@ __device__ __forceinline__ void q1_cell(const VmsConst<T> &k, T cu[4][8], T ca[3
         const T dP0 = mdx(cu[3], q) * k.ih[0];
         const T dP1 = mdy(cu[3], q) * k.ih[1];
         const T dP2 = mdz(cu[3], q) * k.ih[2];
-        const T A0 = mval(ca[0], q), A1 = mval(ca[1], q), A2 = mval(ca[2], q);
+        T A0, A1, A2, Fs[3] = {T(0), T(0), T(0)};
+        if constexpr (RESID) {
+            A0 = U[0];
+            A1 = U[1];
+            A2 = U[2];
+            Fs[0] = mval(ca[0], q);
+            Fs[1] = mval(ca[1], q);
+            Fs[2] = mval(ca[2], q);
+        } else {
+            A0 = mval(ca[0], q);
+            A1 = mval(ca[1], q);
+            A2 = mval(ca[2], q);
+        }
         T S = T(1);
         if (k.has_s) {
             S = mval(cs, q);
@@ -191,7 +206,8 @@ __device__ __forceinline__ void q1_cell(const VmsConst<T> &k, T cu[4][8], T ca[3
         T F0[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            const T g = k.c_m * U[i] + (A0 * dU[i][0] + A1 * dU[i][1] + A2 * dU[i][2]);
+            T g = k.c_m * U[i] + (A0 * dU[i][0] + A1 * dU[i][1] + A2 * dU[i][2]);
+            if constexpr (RESID) g -= Fs[i];
             F0[i] = g;
             const T r = g + dP[i] - k.nu * gd[i];
             tr[i] = tau_m * r;
@@ -218,7 +234,7 @@ __device__ __forceinline__ void q1_cell(const VmsConst<T> &k, T cu[4][8], T ca[3
     }
 }
 
-template <typename T>
+template <typename T, bool RESID>
 __global__ __launch_bounds__(256) void vms_q1_cells(Geo g, VmsConst<T> k, const T *__restrict__ x,
                                                     const T *__restrict__ a,
                                                     const T *__restrict__ s,
@@ -248,7 +264,7 @@ __global__ __launch_bounds__(256) void vms_q1_cells(Geo g, VmsConst<T> k, const 
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
                 T v = x[f * N + node];
-                if (mask_bit(mask, f * N + node)) v = T(0);
+                if (!RESID && mask_bit(mask, f * N + node)) v = T(0);
                 cu[f][A] = v;
                 ca[f][A] = a[f * N + node];
             }
@@ -265,7 +281,7 @@ __global__ __launch_bounds__(256) void vms_q1_cells(Geo g, VmsConst<T> k, const 
             const int32_t ko = occ_index[cx + (int64_t)g.n[0] * (cy + (int64_t)g.n[1] * cz)];
             if (ko >= 0) dlm = gram + (int64_t)ko * 64;
         }
-        q1_cell(k, cu, ca, cs, smin, dlm, out);
+        q1_cell<T, RESID>(k, cu, ca, cs, smin, dlm, out);
     }
     __syncthreads();
 #pragma unroll
@@ -295,9 +311,10 @@ template <typename T, int P, int BX, int BY, int BZ>
 __global__ __launch_bounds__(256) void vms_gather(Geo g, const T *__restrict__ part, int nbx,
                                                   int nby, int nbz, const T *__restrict__ x,
                                                   const uint32_t *__restrict__ mask,
-                                                  T *__restrict__ y, const T *__restrict__ csum,
-                                                  const int32_t *__restrict__ occ_index)
+                                                  T *__restrict__ y, GatherOpts<T> o)
 {
+    const T *__restrict__ csum = o.csum;
+    const int32_t *__restrict__ occ_index = o.occ_index;
     constexpr int LX = P * BX + 1, LY = P * BY + 1, LZ = P * BZ + 1, NL = LX * LY * LZ;
     constexpr int NEN = (P + 1) * (P + 1) * (P + 1);
     const int64_t node = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -359,7 +376,12 @@ __global__ __launch_bounds__(256) void vms_gather(Geo g, const T *__restrict__ p
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
         T v = acc[f];
-        if (f < 3 && mask_bit(mask, f * g.N + node)) v = x[f * g.N + node];
+        if (f < 3 && o.sub3 != nullptr) v -= o.sub3[f * g.N + node];
+        if (f < 3 && mask_bit(mask, f * g.N + node)) {
+            // Dirichlet rows: identity (apply) or u - g_D (residual)
+            v = x[f * g.N + node];
+            if (o.gD != nullptr) v -= o.gD[f * g.N + node];
+        }
         y[f * g.N + node] = v;
     }
 }
@@ -367,24 +389,27 @@ __global__ __launch_bounds__(256) void vms_gather(Geo g, const T *__restrict__ p
 template <typename T>
 int launch_q1_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, const T *s,
                     const uint32_t *mask, const T *gram, const int32_t *occ_index, T *part,
-                    const BrickLayout &bl, hipStream_t st)
+                    const BrickLayout &bl, hipStream_t st, bool resid)
 {
-    ProfileScope prof("vms_q1_cells", st);
-    hipLaunchKernelGGL(vms_q1_cells<T>, dim3((unsigned)bl.nb), dim3(256), 0, st, g, k, x, a, s, mask,
-                       gram, occ_index, part, bl.nbx, bl.nby);
+    ProfileScope prof(resid ? "vms_q1_residual" : "vms_q1_cells", st);
+    if (resid)
+        hipLaunchKernelGGL((vms_q1_cells<T, true>), dim3((unsigned)bl.nb), dim3(256), 0, st, g, k, x, a,
+                           s, mask, gram, occ_index, part, bl.nbx, bl.nby);
+    else
+        hipLaunchKernelGGL((vms_q1_cells<T, false>), dim3((unsigned)bl.nb), dim3(256), 0, st, g, k, x,
+                           a, s, mask, gram, occ_index, part, bl.nbx, bl.nby);
     FSI_LAUNCH_CHECK();
     return FSI_OK;
 }
 
 template <typename T, int P, int BX, int BY, int BZ>
 int launch_gather(const Geo &g, const T *part, const BrickLayout &bl, const T *x,
-                  const uint32_t *mask, T *y, const T *csum, const int32_t *occ_index,
-                  hipStream_t st)
+                  const uint32_t *mask, T *y, const GatherOpts<T> &o, hipStream_t st)
 {
     const unsigned blocks = (unsigned)((g.N + 255) / 256);
     ProfileScope prof("vms_gather", st);
     hipLaunchKernelGGL((vms_gather<T, P, BX, BY, BZ>), dim3(blocks), dim3(256), 0, st, g, part,
-                       bl.nbx, bl.nby, bl.nbz, x, mask, y, csum, occ_index);
+                       bl.nbx, bl.nby, bl.nbz, x, mask, y, o);
     FSI_LAUNCH_CHECK();
     return FSI_OK;
 }
@@ -392,29 +417,17 @@ int launch_gather(const Geo &g, const T *part, const BrickLayout &bl, const T *x
 template int launch_q1_cells<double>(const Geo &, const VmsConst<double> &, const double *,
                                      const double *, const double *, const uint32_t *,
                                      const double *, const int32_t *, double *,
-                                     const BrickLayout &, hipStream_t);
+                                     const BrickLayout &, hipStream_t, bool);
 template int launch_q1_cells<float>(const Geo &, const VmsConst<float> &, const float *,
                                     const float *, const float *, const uint32_t *, const float *,
-                                    const int32_t *, float *, const BrickLayout &, hipStream_t);
-template int launch_gather<double, 1, Q1_BX, Q1_BY, Q1_BZ>(const Geo &, const double *,
-                                                           const BrickLayout &, const double *,
-                                                           const uint32_t *, double *,
-                                                           const double *, const int32_t *,
-                                                           hipStream_t);
-template int launch_gather<float, 1, Q1_BX, Q1_BY, Q1_BZ>(const Geo &, const float *,
-                                                          const BrickLayout &, const float *,
-                                                          const uint32_t *, float *,
-                                                          const float *, const int32_t *,
-                                                          hipStream_t);
-template int launch_gather<double, 2, Q2_BX, Q2_BY, Q2_BZ>(const Geo &, const double *,
-                                                           const BrickLayout &, const double *,
-                                                           const uint32_t *, double *,
-                                                           const double *, const int32_t *,
-                                                           hipStream_t);
-template int launch_gather<float, 2, Q2_BX, Q2_BY, Q2_BZ>(const Geo &, const float *,
-                                                          const BrickLayout &, const float *,
-                                                          const uint32_t *, float *,
-                                                          const float *, const int32_t *,
-                                                          hipStream_t);
+                                    const int32_t *, float *, const BrickLayout &, hipStream_t, bool);
+#define FSI_GATHER_INST(T, P, BX, BY, BZ)                                                           \
+    template int launch_gather<T, P, BX, BY, BZ>(const Geo &, const T *, const BrickLayout &,     \
+                                                 const T *, const uint32_t *, T *,                \
+                                                 const GatherOpts<T> &, hipStream_t);
+FSI_GATHER_INST(double, 1, Q1_BX, Q1_BY, Q1_BZ)
+FSI_GATHER_INST(float, 1, Q1_BX, Q1_BY, Q1_BZ)
+FSI_GATHER_INST(double, 2, Q2_BX, Q2_BY, Q2_BZ)
+FSI_GATHER_INST(float, 2, Q2_BX, Q2_BY, Q2_BZ)
 
 }  // namespace fsi

@@ -1,15 +1,398 @@
-// Q2-Q2 Oseen-VMS operator (placeholder until the kernel lands).
+// Matrix-free Q2-Q2 Oseen-VMS operator on gfx950 (section 2.1: Galerkin weak
+// form + residual-based SUPG/PSPG/LSIC with the paper's tau_m, tau_c, G).
+//
+// Design
+//  * One workgroup = a brick of 4x4x4 cells (9x9x9 nodes), processed in 8
+//    rounds of a 2x2x2 group of cells.  In a round, lane l < 216 owns
+//    (cell l/27, index j = l%27) where j is read as a node (a,b,c), an
+//    intermediate (q,b,c) / (q,q',c) or a quadrature point (q,q',q'')
+//    depending on the pass.
+//  * Interpolation is sum-factorised through LDS: nodal values -> x-line
+//    values (N, N', N'') -> xy-plane values -> quadrature-point values,
+//    value/gradient/second derivatives as each field needs them (velocity:
+//    all 10, pressure: 4, advection and s: values).  3 FMAs per output per
+//    pass instead of 27 per output for direct evaluation.
+//  * The test side is the transposed contraction: per quadrature point the
+//    4 weighted flux components (value, d/dx, d/dy, d/dz) of each output
+//    field go through z, y, x passes back to the 27 nodes.
+//  * Nodes of the 8 cells of a round are added into the brick's LDS node
+//    accumulator one cell at a time (ordered, deterministic), brick faces
+//    are finished by the shared node-gather kernel.
 #include "kernels.hpp"
+#include "profile.hpp"
 
 namespace fsi {
 
+namespace {
+
+constexpr int CPR = 8;           // cells per round
+constexpr int LANES = CPR * 27;  // active lanes per round
+constexpr int BN = 2 * Q2_BX + 1;
+
+// 3-point Gauss-Legendre on [0,1]
+constexpr double G3_0 = 0.11270166537925831148;
+constexpr double G3_1 = 0.5;
+constexpr double G3_2 = 0.88729833462074168852;
+constexpr double W3_0 = 0.27777777777777777778;   // 5/18
+constexpr double W3_1 = 0.44444444444444444444;   // 8/18
+
 template <typename T>
-int launch_q2_cells(const Geo &, const VmsConst<T> &, const T *, const T *, const T *,
-                    const uint32_t *, const T *, const int32_t *, T *, const BrickLayout &,
-                    hipStream_t)
+struct Tab {
+    T N[3][3], D[3][3], D2[3][3];   // [node a][point q]: value, first, second reference derivative
+    T w[3];
+};
+
+template <typename T>
+__device__ __forceinline__ void fill_tab(Tab<T> &tb, int t)
 {
-    set_error("Q2 operator not built yet");
-    return FSI_ERR_UNSUPPORTED;
+    if (t < 9) {
+        const int a = t / 3, q = t % 3;
+        const T x = q == 0 ? T(G3_0) : (q == 1 ? T(G3_1) : T(G3_2));
+        T n, d, d2;
+        if (a == 0) {
+            n = T(2) * (x - T(0.5)) * (x - T(1)); d = T(4) * x - T(3); d2 = T(4);
+        } else if (a == 1) {
+            n = T(-4) * x * (x - T(1)); d = T(-8) * x + T(4); d2 = T(-8);
+        } else {
+            n = T(2) * x * (x - T(0.5)); d = T(4) * x - T(1); d2 = T(4);
+        }
+        tb.N[a][q] = n;
+        tb.D[a][q] = d;
+        tb.D2[a][q] = d2;
+    }
+    if (t == 9) {
+        tb.w[0] = T(W3_0);
+        tb.w[1] = T(W3_1);
+        tb.w[2] = T(W3_0);
+    }
+}
+
+// Interpolate one nodal field (this lane's node value v) to this lane's quadrature point.
+// nder: 0 = value only, 1 = value + gradient, 2 = value + gradient + second derivatives.
+// Outputs (reference derivatives): out[0] value, out[1..3] d/dxi_k, out[4..6] d2/dxi_k^2,
+// out[7] d2/dxi0 dxi1, out[8] d2/dxi0 dxi2, out[9] d2/dxi1 dxi2.
+template <typename T, int NDER>
+__device__ __forceinline__ void interp(const Tab<T> &tb, T (*nod)[27], T (*bx)[3][27],
+                                       T (*by)[6][27], int lc, int j, bool act, T v, T out[10])
+{
+    const int i0 = j % 3, i1 = (j / 3) % 3, i2 = j / 9;
+    if (act) nod[lc][j] = v;
+    __syncthreads();
+    // pass x: (q, b, c) <- nodes (a, b, c)
+    if (act) {
+        T s0 = T(0), s1 = T(0), s2 = T(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const T nv = nod[lc][a + 3 * i1 + 9 * i2];
+            s0 += tb.N[a][i0] * nv;
+            if (NDER >= 1) s1 += tb.D[a][i0] * nv;
+            if (NDER >= 2) s2 += tb.D2[a][i0] * nv;
+        }
+        bx[lc][0][j] = s0;
+        if (NDER >= 1) bx[lc][1][j] = s1;
+        if (NDER >= 2) bx[lc][2][j] = s2;
+    }
+    __syncthreads();
+    // pass y: (q, q', c) <- (q, b, c); derivative orders (x, y):
+    // 0:(0,0) 1:(1,0) 2:(0,1) 3:(2,0) 4:(1,1) 5:(0,2)
+    if (act) {
+        T r[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const int src = i0 + 3 * b + 9 * i2;
+            const T n = tb.N[b][i1];
+            const T v0 = bx[lc][0][src];
+            r[0] += n * v0;
+            if (NDER >= 1) {
+                const T d = tb.D[b][i1];
+                const T v1 = bx[lc][1][src];
+                r[1] += n * v1;
+                r[2] += d * v0;
+                if (NDER >= 2) {
+                    r[3] += n * bx[lc][2][src];
+                    r[4] += d * v1;
+                    r[5] += tb.D2[b][i1] * v0;
+                }
+            }
+        }
+        by[lc][0][j] = r[0];
+        if (NDER >= 1) {
+            by[lc][1][j] = r[1];
+            by[lc][2][j] = r[2];
+        }
+        if (NDER >= 2) {
+            by[lc][3][j] = r[3];
+            by[lc][4][j] = r[4];
+            by[lc][5][j] = r[5];
+        }
+    }
+    __syncthreads();
+    // pass z: (q, q', q'') <- (q, q', c)
+#pragma unroll
+    for (int k = 0; k < 10; ++k) out[k] = T(0);
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int src = i0 + 3 * i1 + 9 * c;
+            const T n = tb.N[c][i2];
+            out[0] += n * by[lc][0][src];
+            if (NDER >= 1) {
+                const T d = tb.D[c][i2];
+                out[1] += n * by[lc][1][src];
+                out[2] += n * by[lc][2][src];
+                out[3] += d * by[lc][0][src];
+                if (NDER >= 2) {
+                    out[4] += n * by[lc][3][src];
+                    out[5] += n * by[lc][5][src];
+                    out[6] += tb.D2[c][i2] * by[lc][0][src];
+                    out[7] += n * by[lc][4][src];
+                    out[8] += d * by[lc][1][src];
+                    out[9] += d * by[lc][2][src];
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Transposed contraction of one output field: this lane holds the weighted flux
+// components at its quadrature point (f0 for the test value, g0..g2 for the reference
+// test derivatives); returns the contribution to this lane's node.
+template <typename T>
+__device__ __forceinline__ T project(const Tab<T> &tb, T (*fl)[4][27], T (*bx)[3][27],
+                                     T (*by)[6][27], int lc, int j, bool act, T f0, T g0, T g1,
+                                     T g2)
+{
+    const int i0 = j % 3, i1 = (j / 3) % 3, i2 = j / 9;
+    if (act) {
+        fl[lc][0][j] = f0;
+        fl[lc][1][j] = g0;
+        fl[lc][2][j] = g1;
+        fl[lc][3][j] = g2;
+    }
+    __syncthreads();
+    // z^T: (q, q', c) <- points (q, q', q'')
+    if (act) {
+        T p0 = T(0), p1 = T(0), p2 = T(0);
+#pragma unroll
+        for (int qz = 0; qz < 3; ++qz) {
+            const int src = i0 + 3 * i1 + 9 * qz;
+            const T n = tb.N[i2][qz];
+            p0 += n * fl[lc][0][src] + tb.D[i2][qz] * fl[lc][3][src];
+            p1 += n * fl[lc][1][src];
+            p2 += n * fl[lc][2][src];
+        }
+        bx[lc][0][j] = p0;
+        bx[lc][1][j] = p1;
+        bx[lc][2][j] = p2;
+    }
+    __syncthreads();
+    // y^T: (q, b, c) <- (q, q', c)
+    if (act) {
+        T r0 = T(0), r1 = T(0);
+#pragma unroll
+        for (int qy = 0; qy < 3; ++qy) {
+            const int src = i0 + 3 * qy + 9 * i2;
+            const T n = tb.N[i1][qy];
+            r0 += n * bx[lc][0][src] + tb.D[i1][qy] * bx[lc][2][src];
+            r1 += n * bx[lc][1][src];
+        }
+        by[lc][0][j] = r0;
+        by[lc][1][j] = r1;
+    }
+    __syncthreads();
+    // x^T: node (a, b, c) <- (q, b, c)
+    T y = T(0);
+    if (act) {
+#pragma unroll
+        for (int qx = 0; qx < 3; ++qx) {
+            const int src = qx + 3 * i1 + 9 * i2;
+            y += tb.N[i0][qx] * by[lc][0][src] + tb.D[i0][qx] * by[lc][1][src];
+        }
+    }
+    __syncthreads();
+    return y;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void vms_q2_cells(Geo g, VmsConst<T> k, const T *__restrict__ x,
+                                                    const T *__restrict__ a,
+                                                    const T *__restrict__ s,
+                                                    const uint32_t *__restrict__ mask,
+                                                    const T *__restrict__ gram,
+                                                    const int32_t *__restrict__ occ_index,
+                                                    T *__restrict__ part, int nbx, int nby)
+{
+    __shared__ T acc[4 * Q2_NL];
+    __shared__ T nod[CPR][27];
+    __shared__ T nodu[CPR][3][27];
+    __shared__ T bx[CPR][3][27];
+    __shared__ T by[CPR][6][27];
+    __shared__ T fl[CPR][4][27];
+    __shared__ T smin_s[CPR];
+    __shared__ Tab<T> tb;
+
+    const int t = threadIdx.x;
+    const int64_t bid = blockIdx.x;
+    const int bxi = (int)(bid % nbx), byi = (int)((bid / nbx) % nby), bzi = (int)(bid / ((int64_t)nbx * nby));
+    const int lc = t / 27, j = t % 27;
+    const bool lane_on = t < LANES;
+    fill_tab(tb, t);
+    for (int i = t; i < 4 * Q2_NL; i += 256) acc[i] = T(0);
+    __syncthreads();
+
+    const int64_t N = g.N;
+    const int na = j % 3, nb = (j / 3) % 3, nc = j / 9;   // this lane's node in its cell
+    for (int r = 0; r < 8; ++r) {
+        const int cxl = 2 * (r & 1) + (lc & 1), cyl = 2 * ((r >> 1) & 1) + ((lc >> 1) & 1),
+                  czl = 2 * (r >> 2) + (lc >> 2);
+        const int cx = bxi * Q2_BX + cxl, cy = byi * Q2_BY + cyl, cz = bzi * Q2_BZ + czl;
+        const bool act = lane_on && cx < g.n[0] && cy < g.n[1] && cz < g.n[2];
+        // this lane's node values
+        T v[8] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(1)};
+        if (act) {
+            const int64_t node = (int64_t)(2 * cx + na) +
+                                 (int64_t)g.nn[0] * ((2 * cy + nb) + (int64_t)g.nn[1] * (2 * cz + nc));
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                T u = x[f * N + node];
+                if (mask_bit(mask, f * N + node)) u = T(0);
+                v[f] = u;
+                v[4 + f] = a[f * N + node];
+                nodu[lc][f][j] = u;
+            }
+            v[3] = x[3 * N + node];
+            if (k.has_s) v[7] = s[node];
+        }
+        // quadrature-point values
+        T qu[3][10], qp[10], qa[3][10], qs[10];
+        interp<T, 2>(tb, nod, bx, by, lc, j, act, v[0], qu[0]);
+        interp<T, 2>(tb, nod, bx, by, lc, j, act, v[1], qu[1]);
+        interp<T, 2>(tb, nod, bx, by, lc, j, act, v[2], qu[2]);
+        interp<T, 1>(tb, nod, bx, by, lc, j, act, v[3], qp);
+        interp<T, 0>(tb, nod, bx, by, lc, j, act, v[4], qa[0]);
+        interp<T, 0>(tb, nod, bx, by, lc, j, act, v[5], qa[1]);
+        interp<T, 0>(tb, nod, bx, by, lc, j, act, v[6], qa[2]);
+        T S = T(1);
+        if (k.has_s) {
+            if (act) nod[lc][j] = v[7];
+            __syncthreads();
+            if (act && j == 0) {
+                T m = nod[lc][0];
+                for (int i = 1; i < 27; ++i) m = nod[lc][i] < m ? nod[lc][i] : m;
+                smin_s[lc] = m;
+            }
+            __syncthreads();
+            interp<T, 0>(tb, nod, bx, by, lc, j, act, v[7], qs);
+            if (act) S = qs[0] < smin_s[lc] ? smin_s[lc] : qs[0];
+        }
+
+        // pointwise quantities at quadrature point (i0, i1, i2) = (j%3, (j/3)%3, j/9)
+        T F0[4], G[4][3];
+        {
+            const T ih[3] = {k.ih[0], k.ih[1], k.ih[2]};
+            T U[3], dU[3][3], lap[3], hes[3][3][3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                U[i] = qu[i][0];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) dU[i][d] = qu[i][1 + d] * ih[d];
+                hes[i][0][0] = qu[i][4] * k.ih2[0];
+                hes[i][1][1] = qu[i][5] * k.ih2[1];
+                hes[i][2][2] = qu[i][6] * k.ih2[2];
+                hes[i][0][1] = hes[i][1][0] = qu[i][7] * (ih[0] * ih[1]);
+                hes[i][0][2] = hes[i][2][0] = qu[i][8] * (ih[0] * ih[2]);
+                hes[i][1][2] = hes[i][2][1] = qu[i][9] * (ih[1] * ih[2]);
+                lap[i] = hes[i][0][0] + hes[i][1][1] + hes[i][2][2];
+            }
+            const T P = qp[0];
+            const T dP[3] = {qp[1] * ih[0], qp[2] * ih[1], qp[3] * ih[2]};
+            const T Aq[3] = {qa[0][0], qa[1][0], qa[2][0]};
+            const T tbk = S * (k.K1 + Aq[0] * Aq[0] * k.ih2[0] + Aq[1] * Aq[1] * k.ih2[1] +
+                               Aq[2] * Aq[2] * k.ih2[2]);
+            const T sq = sqrt(tbk);
+            const T tau_m = T(1) / sq;
+            const T tau_c = sq * k.inv_trG;
+            const T div = dU[0][0] + dU[1][1] + dU[2][2];
+            T tr[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const T gi = k.c_m * U[i] + (Aq[0] * dU[i][0] + Aq[1] * dU[i][1] + Aq[2] * dU[i][2]);
+                F0[i] = gi;
+                T visc = T(0);
+                if (k.visc_strong) visc = lap[i] + (hes[0][i][0] + hes[1][i][1] + hes[2][i][2]);
+                tr[i] = tau_m * (gi + dP[i] - k.nu * visc);
+            }
+            const T diag = tau_c * div - P;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    T fl2 = k.nu * (dU[i][d] + dU[d][i]) + Aq[d] * tr[i];
+                    if (d == i) fl2 += diag;
+                    G[i][d] = fl2;
+                }
+            F0[3] = div;
+            G[3][0] = tr[0];
+            G[3][1] = tr[1];
+            G[3][2] = tr[2];
+        }
+        const int q0 = j % 3, q1 = (j / 3) % 3, q2 = j / 9;
+        const T W = act ? tb.w[q0] * tb.w[q1] * tb.w[q2] * k.detJ : T(0);
+        T out[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+            out[f] = project(tb, fl, bx, by, lc, j, act, W * F0[f], W * k.ih[0] * G[f][0],
+                             W * k.ih[1] * G[f][1], W * k.ih[2] * G[f][2]);
+        // DLM block of an occupied cell on its nodal (masked) velocity
+        if (act && gram != nullptr) {
+            const int32_t ko = occ_index[cx + (int64_t)g.n[0] * (cy + (int64_t)g.n[1] * cz)];
+            if (ko >= 0) {
+                const T *gr = gram + ((int64_t)ko * 27 + j) * 27;
+                T r0 = T(0), r1 = T(0), r2 = T(0);
+                for (int C = 0; C < 27; ++C) {
+                    const T gv = gr[C];
+                    r0 += gv * nodu[lc][0][C];
+                    r1 += gv * nodu[lc][1][C];
+                    r2 += gv * nodu[lc][2][C];
+                }
+                out[0] += r0;
+                out[1] += r1;
+                out[2] += r2;
+            }
+        }
+        // ordered accumulation of the round's 8 cells into the brick's nodes
+        const int l = (2 * cxl + na) + BN * ((2 * cyl + nb) + BN * (2 * czl + nc));
+        for (int pc = 0; pc < CPR; ++pc) {
+            if (act && lc == pc) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f) acc[f * Q2_NL + l] += out[f];
+            }
+            __syncthreads();
+        }
+    }
+    for (int l = t; l < Q2_NL; l += 256) {
+        const int lx = l % BN, ly = (l / BN) % BN, lz = l / (BN * BN);
+        const int gx = 2 * bxi * Q2_BX + lx, gy = 2 * byi * Q2_BY + ly, gz = 2 * bzi * Q2_BZ + lz;
+        if (gx < g.nn[0] && gy < g.nn[1] && gz < g.nn[2]) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) part[(bid * 4 + f) * Q2_NL + l] = acc[f * Q2_NL + l];
+        }
+    }
+}
+
+}  // namespace
+
+template <typename T>
+int launch_q2_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, const T *s,
+                    const uint32_t *mask, const T *gram, const int32_t *occ_index, T *part,
+                    const BrickLayout &bl, hipStream_t st)
+{
+    ProfileScope prof("vms_q2_cells", st);
+    hipLaunchKernelGGL(vms_q2_cells<T>, dim3((unsigned)bl.nb), dim3(256), 0, st, g, k, x, a, s, mask,
+                       gram, occ_index, part, bl.nbx, bl.nby);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
 }
 
 template int launch_q2_cells<double>(const Geo &, const VmsConst<double> &, const double *,

@@ -1,0 +1,211 @@
+"""GPU parity of the solver rows: nodal block-Jacobi blocks, mixed-precision FGMRES,
+the nonlinear step residual and Newton (section 2.4: Newton on the monolithic
+system, Krylov solves of the reduced block system with block preconditioners).
+
+Oracles: jacobian.diag_blocks (element matrices), numpy.linalg.solve of the
+dense reduced matrix, newton.residual, and the oracle's dense Newton.
+"""
+import numpy as np
+import pytest
+
+import fsi_workloads as W
+from oracle import dlm as odlm
+from oracle import jacobian as ojac
+from oracle import newton as onewton
+from oracle import vms as ovms
+
+from helpers import field_rel_err, points_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(arr, dt="f64"):
+    import torch
+    return torch.tensor(np.ascontiguousarray(arr).ravel(),
+                        dtype=torch.float64 if dt == "f64" else torch.float32, device="cuda")
+
+
+def build(cfg, a, mask_on=True, grid=None, X=None, kappa=None):
+    """FP64 and FP32 problems on the same (FP32-representable) data."""
+    import torch
+    import paper_2601_08266_amd as fsi
+    g = grid or cfg.grid
+    if X is None:
+        X, kappa = points_for(cfg)
+    kappa32 = kappa.astype(np.float32).astype(np.float64)
+    a32 = np.asarray(a).astype(np.float32).astype(np.float64)
+    mask = W.channel_dirichlet_mask(g) if mask_on else None
+    mt = torch.tensor(W.mask_to_bits(mask).view(np.int32), device="cuda") if mask_on else None
+    prm = fsi.make_params(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
+    Xt = _t(X)
+    tab64 = fsi.dlm_locate(g, Xt, dtype=torch.float64, s_max=cfg.s_max)
+    tab32 = fsi.dlm_locate(g, Xt, dtype=torch.float32, s_max=cfg.s_max)
+    k64, k32 = _t(kappa32), _t(kappa32, "f32")
+    gram64 = fsi.dlm_gram(g, tab64, k64)
+    gram32 = fsi.dlm_gram(g, tab32, k32)
+    J64 = fsi.Problem(g, prm, _t(a32), tab64, k64, s=tab64.s, mask=mt, gram=gram64)
+    J32 = fsi.Problem(g, prm, _t(a32, "f32"), tab32, k32, s=tab32.s, mask=mt, gram=gram32)
+    cell, xi = odlm.locate(g, X)
+    s = odlm.s_field(g, cell, cfg.s_max)
+    return dict(g=g, J64=J64, J32=J32, mask=mask, cell=cell, xi=xi, s=s, kappa=kappa32, a=a32,
+                prm_o=ovms.params_array(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I), X=X)
+
+
+@pytest.mark.parametrize("case", ["c1", "q2"])
+def test_bjacobi_blocks_and_inverse(case):
+    import paper_2601_08266_amd as fsi
+    cfg = W.CONFIGS["c1"]
+    if case == "q2":
+        g = W.Grid((4, 5, 3), 2)
+        X = np.random.default_rng(3).uniform(0.1, 0.9, (3, 800))
+        kappa = np.random.default_rng(4).uniform(1.0, 50.0, 800)
+        P = build(cfg, W.advection_field(g, cfg.seed_fields), grid=g, X=X, kappa=kappa)
+    else:
+        P = build(cfg, W.advection_field(cfg.grid, cfg.seed_fields))
+    g = P["g"]
+    N = g.num_nodes
+    pinv64, pinv32, blocks, nsing = fsi.bjacobi_setup(P["J64"], want_blocks=True)
+    assert nsing == 0
+    ref = ojac.diag_blocks(g, P["prm_o"], P["a"], P["cell"], P["xi"], P["kappa"], s=P["s"],
+                           mask=P["mask"])
+    got = blocks.cpu().numpy().reshape(4, 4, N).transpose(2, 0, 1)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"bjacobi {case}: block rel err {err:.3e}")
+    assert err <= 1e-12
+    inv = pinv64.cpu().numpy().reshape(4, 4, N).transpose(2, 0, 1)
+    eye = np.einsum("nij,njk->nik", inv, ref)
+    assert np.abs(eye - np.eye(4)).max() <= 1e-9
+    # apply matches the per-node product
+    v = np.random.default_rng(1).standard_normal(4 * N)
+    z = fsi.bjacobi_apply(g, pinv64, _t(v)).cpu().numpy().reshape(4, N)
+    zr = np.einsum("nij,jn->in", inv, v.reshape(4, N))
+    assert np.abs(z - zr).max() <= 1e-12 * np.abs(zr).max()
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_fgmres_c1_matches_dense_lu(inner):
+    import torch
+    import paper_2601_08266_amd as fsi
+    cfg = W.CONFIGS["c1"]
+    P = build(cfg, W.advection_field(cfg.grid, cfg.seed_fields))
+    g = P["g"]
+    N = g.num_nodes
+    b = W.smooth_fourier_field(g, cfg.seed_vectors).ravel()
+    b[:3 * N][P["mask"].ravel()] = 0.0
+    J = ojac.dense(g, P["prm_o"], P["a"], P["cell"], P["xi"], P["kappa"], s=P["s"], mask=P["mask"])
+    x_ref = np.linalg.solve(J, b)
+    pinv64, pinv32, _, _ = fsi.bjacobi_setup(P["J64"])
+    x = torch.zeros(4 * N, dtype=torch.float64, device="cuda")
+    tdt = torch.float64 if inner == "f64" else torch.float32
+    opts = fsi.solve_opts(restart=50, max_iters=3000, rtol=1e-10, inner=tdt)
+    rc, st = fsi.fgmres_solve(P["J64"], _t(b), x, opts, J32=P["J32"] if inner == "f32" else None,
+                              pinv=pinv32 if inner == "f32" else pinv64)
+    xs = x.cpu().numpy()
+    res = np.linalg.norm(b - J @ xs) / np.linalg.norm(b)
+    err = np.linalg.norm(xs - x_ref) / np.linalg.norm(x_ref)
+    print(f"fgmres c1 inner={inner}: iters {st.iters} cycles {st.cycles} oracle residual {res:.3e} "
+          f"x err {err:.3e}")
+    assert res <= 1.5e-10
+    assert err <= 1e-6
+
+
+def test_fgmres_c2_mixed_precision_reaches_1e10():
+    """64^3, 200k points, channel boundary conditions: FP32-inner FGMRES to 1e-10 (FP64 residual),
+    the final residual re-checked with the oracle's own full Jacobian apply."""
+    import torch
+    import paper_2601_08266_amd as fsi
+    cfg = W.CONFIGS["c2"]
+    P = build(cfg, W.advection_field(cfg.grid, cfg.seed_fields))
+    g = P["g"]
+    N = g.num_nodes
+    b = W.smooth_fourier_field(g, cfg.seed_vectors).ravel()
+    b[:3 * N][P["mask"].ravel()] = 0.0
+    pinv64, pinv32, _, _ = fsi.bjacobi_setup(P["J64"])
+    x = torch.zeros(4 * N, dtype=torch.float64, device="cuda")
+    opts = fsi.solve_opts(restart=50, max_iters=4000, rtol=1e-10, inner=torch.float32)
+    rc, st = fsi.fgmres_solve(P["J64"], _t(b), x, opts, J32=P["J32"], pinv=pinv32)
+    xs = x.cpu().numpy()
+    Jx = ojac.apply(g, P["prm_o"], P["a"], xs, P["cell"], P["xi"], P["kappa"], s=P["s"],
+                    mask=P["mask"]).ravel()
+    res = np.linalg.norm(b - Jx) / np.linalg.norm(b)
+    print(f"fgmres c2 mixed: iters {st.iters} cycles {st.cycles} {st.t_total_ms:.1f} ms, "
+          f"oracle residual {res:.3e}, solver residual {st.res_final / st.bnorm:.3e}")
+    assert res <= 2e-10
+
+
+def newton_case(cfg, t_step=0.05):
+    g = cfg.grid
+    N = g.num_nodes
+    X, g_pts = W.rotating_plate_points(cfg.m_points, cfg.seed_fields, t_step) if cfg.solid == "plates" \
+        else (W.sphere_points(), None)
+    if g_pts is None:
+        rel = X - 0.5
+        g_pts = np.stack([np.zeros(X.shape[1]), -rel[2], rel[1]]) * 0.5
+    vol = W.plate_volume() if cfg.solid == "plates" else W.sphere_volume()
+    kappa = W.kappa_weights(X.shape[1], vol, cfg.c_m, cfg.alpha)
+    Xn, Yn, Zn = W.node_coords(g)
+    u_old = 0.3 * W.advection_field(g, cfg.seed_fields)
+    mask = W.channel_dirichlet_mask(g)
+    gD = np.zeros((3, N))
+    gD[0] = np.where(Xn == 0.0, np.sin(2 * np.pi * t_step / 0.8), 0.0)
+    gD[:, ~mask[0]] = 0.0
+    x0 = np.concatenate([u_old, np.zeros((1, N))])
+    x0[:3][mask] = gD[mask]
+    return X, g_pts, kappa, u_old, mask, gD, x0
+
+
+def test_residual_c1_matches_oracle():
+    import torch
+    import paper_2601_08266_amd as fsi
+    cfg = W.CONFIGS["c1"]
+    X, g_pts, kappa, u_old, mask, gD, x0 = newton_case(cfg)
+    g = cfg.grid
+    N = g.num_nodes
+    P = build(cfg, u_old, X=X, kappa=kappa)
+    kappa = P["kappa"]
+    rng = np.random.default_rng(9)
+    x = x0 + 0.01 * rng.standard_normal(x0.shape)
+    x[:3][mask] = gD[mask]
+    f = cfg.c_m * u_old
+    lamg = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
+    fsi.dlm_BT(g, P["J64"].tables, _t(g_pts), lamg, kappa=_t(kappa))
+    R = fsi.vms_residual(P["J64"], _t(f), _t(x), gD=_t(gD), lamg=lamg).cpu().numpy()
+    ref = onewton.residual(g, P["prm_o"], x, u_old, P["cell"], P["xi"], kappa, g_pts, s=P["s"],
+                           mask=mask, gD=gD)
+    err = field_rel_err(R, ref, 4)
+    print(f"residual c1: {err:.3e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_newton_c1_matches_dense_newton(inner):
+    import torch
+    import paper_2601_08266_amd as fsi
+    cfg = W.CONFIGS["c1"]
+    X, g_pts, kappa, u_old, mask, gD, x0 = newton_case(cfg)
+    g = cfg.grid
+    N = g.num_nodes
+    P = build(cfg, u_old, X=X, kappa=kappa)
+    kappa = P["kappa"]
+    R0 = onewton.residual(g, P["prm_o"], x0, u_old, P["cell"], P["xi"], kappa, g_pts, s=P["s"],
+                          mask=mask, gD=gD)
+    tol = 1e-8 * np.linalg.norm(R0)
+    x_ref, info = onewton.solve_step(g, P["prm_o"], x0, u_old, P["cell"], P["xi"], kappa, g_pts,
+                                     s=P["s"], mask=mask, gD=gD, tol_abs=tol, linear="dense")
+    assert info["converged"]
+    lamg = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
+    fsi.dlm_BT(g, P["J64"].tables, _t(g_pts), lamg, kappa=_t(kappa))
+    x = _t(x0)
+    tdt = torch.float64 if inner == "f64" else torch.float32
+    opts = fsi.newton_opts(tol_abs=tol, inner=tdt)
+    rc, st = fsi.newton_solve(P["J64"], _t(cfg.c_m * u_old), x, opts,
+                              P32=P["J32"] if inner == "f32" else None, lamg=lamg, gD=_t(gD))
+    xs = x.cpu().numpy()
+    R = onewton.residual(g, P["prm_o"], xs, u_old, P["cell"], P["xi"], kappa, g_pts, s=P["s"],
+                         mask=mask, gD=gD)
+    hist = list(st.res_hist[:st.newton_iters + 1])
+    print(f"newton c1 inner={inner}: {st.newton_iters} Newton / {st.krylov_iters} Krylov, "
+          f"{st.t_total_ms:.1f} ms, hist {['%.2e' % h for h in hist]}, oracle ||R|| "
+          f"{np.linalg.norm(R):.3e} (tol {tol:.3e})")
+    assert np.linalg.norm(R) <= tol * 1.01
+    assert np.linalg.norm(xs - x_ref) <= 1e-6 * np.linalg.norm(x_ref)

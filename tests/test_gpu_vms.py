@@ -104,3 +104,39 @@ def test_vms_q1_c2_sampled_rows(dtype):
     # bitwise determinism over repeated applies
     y2 = fsi.vms_apply(g, prm_g, t["a"], t["x"], s=t["s"]).cpu().numpy()
     assert np.array_equal(y.view(np.uint8), y2.view(np.uint8))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [(3, 2, 2), (5, 4, 6), (4, 4, 4), (1, 1, 1), (9, 3, 5)])
+def test_vms_q2_small_grids(dtype, n):
+    """Q2: one brick, several bricks with ragged tails, a single cell; s with jumps."""
+    import paper_2601_08266_amd as fsi
+    torch = _torch()
+    cfg = W.CONFIGS["c1"]
+    grid = W.Grid(n, 2, x0=(0.1, -0.2, 0.05), h=(0.13, 0.09, 0.11))
+    g, a, x, s, mask, t, prm_o, prm_g = setup_case(cfg, dtype, with_s=False, with_mask=True,
+                                                   grid=grid)
+    rng = np.random.default_rng(sum(n) + 7)
+    s = np.where(rng.uniform(size=grid.num_nodes) < 0.3, 100.0, 1.0)
+    ts = torch.tensor(s, dtype=t["x"].dtype, device="cuda")
+    y = fsi.vms_apply(g, prm_g, t["a"], t["x"], s=ts, mask=t["mask"]).cpu().numpy()
+    ref = ovms.apply(g, prm_o, a, x, s=s, mask=mask)
+    err = field_rel_err(y, ref, 4)
+    print(f"q2 grid {n} {dtype}: rel err {err:.3e}")
+    assert err <= TOL[dtype]
+    y2 = fsi.vms_apply(g, prm_g, t["a"], t["x"], s=ts, mask=t["mask"]).cpu().numpy()
+    assert np.array_equal(y, y2)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_vms_q2_c3_sampled_rows(dtype):
+    """96^3 Q2 (28.8M DOF): sampled rows recomputed by the oracle, brick faces included."""
+    import paper_2601_08266_amd as fsi
+    cfg = W.CONFIGS["c3"]
+    g, a, x, s, mask, t, prm_o, prm_g = setup_case(cfg, dtype, with_s=True, with_mask=True)
+    y = fsi.vms_apply(g, prm_g, t["a"], t["x"], s=t["s"], mask=t["mask"]).cpu().numpy()
+    rows = sample_rows(g, 400, seed=3, brick=(4, 4, 4))
+    ref = ovms.apply_rows(g, prm_o, a, x, rows, s=s, mask=mask)
+    err = rows_rel_err(y[rows], ref)
+    print(f"c3 {dtype} sampled rows: rel err {err:.3e}")
+    assert err <= TOL[dtype]
