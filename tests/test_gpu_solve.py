@@ -208,4 +208,4 @@ def test_newton_c1_matches_dense_newton(inner):
           f"{st.t_total_ms:.1f} ms, hist {['%.2e' % h for h in hist]}, oracle ||R|| "
           f"{np.linalg.norm(R):.3e} (tol {tol:.3e})")
     assert np.linalg.norm(R) <= tol * 1.01
-    assert np.linalg.norm(xs - x_ref) <= 1e-6 * np.linalg.norm(x_ref)
+    assert np.linalg.norm(xs - x_ref.ravel()) <= 1e-6 * np.linalg.norm(x_ref)
