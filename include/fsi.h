@@ -345,6 +345,78 @@ int fsi_newton_solve(const fsi_problem *P64, const fsi_problem *P32, const doubl
                      size_t ws_bytes, void *stream);
 
 /*
+ * Learned warm start (an addition to the method: a better Newton initial
+ * guess for the predictor of section 2.4; it never changes the converged
+ * answer, which the residual tolerance decides).  A stack of 3x3x3
+ * convolutions on the fluid node lattice, BF16 operands with FP32
+ * accumulation on the matrix cores, trained with MSE and Adam.
+ *
+ * Layouts: activations channels-last [V][C] (uint16 = bfloat16 bits, or
+ * float), V = dims[0] dims[1] dims[2], voxel v = i + dims[0] (j + dims[1] k);
+ * C (cin, cout) a multiple of 32.  Weights [27][cout][cin] with tap =
+ * dx + 3 (dy + 3 dz) reading the neighbour at offset (dx-1, dy-1, dz-1); zero
+ * padding outside the lattice.
+ *
+ * fsi_conv3d_fwd     Y[v][o] = bias[o] + sum_tap sum_i X[v+off][i] W[tap][o][i];
+ *                    then, if gate != NULL, Y = 0 where gate[v][o] <= 0 (ReLU
+ *                    backward mask); then ReLU if relu != 0.  Y_bf16 and/or
+ *                    Y_f32 receive the result (either may be NULL).
+ *                    With W from fsi_conv3d_flip_transpose (Wd[tap][i][o] =
+ *                    W[26-tap][o][i]) the same call is the data gradient.
+ * fsi_conv3d_wgrad   dW[tap][o][i] = sum_v dY[v][o] X[v+off][i] (float),
+ *                    db[o] = sum_v dY[v][o] (float, or db = NULL).  Split over
+ *                    voxel ranges summed in a fixed order: deterministic.
+ * fsi_mse_loss       over channels < used: loss = mean (pred - target)^2 (HOST
+ *                    out, SYNCS if non-NULL), dpred = 2 (pred - target) / count
+ *                    as bfloat16 (0 in unused channels).
+ * fsi_adam_step      w, m, v float [n]; t >= 1; w_bf16 (optional) gets the
+ *                    rounded copy of the updated w.
+ * fsi_nn_pack        out[v][c] = (a_c[v] - b_c[v] - shift_c) * scale_c for
+ *                    c < nch (a_c NULL: the constant cst_c; b_c NULL: 0), 0 for
+ *                    nch <= c < C; a_c, b_c are double [V] device arrays.
+ * fsi_nn_moments     per channel, sum and sum of squares over V (HOST out
+ *                    [C][2] doubles, SYNCS).
+ * fsi_nn_unpack      x[f][v] = base[f][v] + out[v][f] / scale_f + shift_f for
+ *                    f < 4; Dirichlet velocity DOFs (dir_mask) take gD (or 0).
+ */
+typedef struct {
+    const double *a[32];
+    const double *b[32];
+    double cst[32];
+    double shift[32];
+    double scale[32];
+    int32_t nch;
+} fsi_nn_pack_spec;
+
+typedef struct {
+    double shift[4];
+    double scale[4];
+} fsi_nn_unpack_spec;
+
+int fsi_conv3d_fwd(const int32_t *dims, int32_t cin, int32_t cout, const uint16_t *X,
+                   const uint16_t *W, const float *bias, int32_t relu, const uint16_t *gate,
+                   uint16_t *Y_bf16, float *Y_f32, void *stream);
+size_t fsi_conv3d_wgrad_workspace(const int32_t *dims, int32_t cin, int32_t cout);
+int fsi_conv3d_wgrad(const int32_t *dims, int32_t cin, int32_t cout, const uint16_t *dY,
+                     const uint16_t *X, float *dW, float *db, void *ws, size_t ws_bytes,
+                     void *stream);
+int fsi_conv3d_flip_transpose(int32_t cin, int32_t cout, const uint16_t *W, uint16_t *Wd,
+                              void *stream);
+size_t fsi_mse_workspace(void);
+int fsi_mse_loss(int64_t nvox, int32_t c, int32_t used, const float *pred, const float *target,
+                 uint16_t *dpred, double *loss_host, void *ws, size_t ws_bytes, void *stream);
+int fsi_adam_step(int64_t n, float *w, const float *g, float *m, float *v, uint16_t *w_bf16,
+                  int32_t t, float lr, float b1, float b2, float eps, void *stream);
+int fsi_to_bf16(int64_t n, const float *in, uint16_t *out, void *stream);
+int fsi_nn_pack(int64_t nvox, int32_t c, const fsi_nn_pack_spec *p, float *out, void *stream);
+size_t fsi_nn_moments_workspace(int32_t c);
+int fsi_nn_moments(int64_t nvox, int32_t c, const float *data, double *sums_host, void *ws,
+                   size_t ws_bytes, void *stream);
+int fsi_nn_unpack(int64_t nvox, int32_t c, const float *out, const double *base,
+                  const fsi_nn_unpack_spec *u, const uint32_t *dir_mask, const double *gD, double *x,
+                  void *stream);
+
+/*
  * Kernel timing (tracing aid, not part of the method).  fsi_profile_enable(1)
  * resets the totals and brackets each later launch of an instrumented kernel
  * with two hipEvents recorded on that launch's stream; fsi_profile_enable(0)

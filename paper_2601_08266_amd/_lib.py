@@ -67,6 +67,16 @@ class FsiNewtonStats(ctypes.Structure):
                 ("t_setup_ms", ctypes.c_double), ("t_krylov_ms", ctypes.c_double)]
 
 
+class FsiNnPackSpec(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_void_p * 32), ("b", ctypes.c_void_p * 32),
+                ("cst", ctypes.c_double * 32), ("shift", ctypes.c_double * 32),
+                ("scale", ctypes.c_double * 32), ("nch", ctypes.c_int32)]
+
+
+class FsiNnUnpackSpec(ctypes.Structure):
+    _fields_ = [("shift", ctypes.c_double * 4), ("scale", ctypes.c_double * 4)]
+
+
 class FsiError(RuntimeError):
     def __init__(self, func, code, msg):
         super().__init__(f"{func} failed with status {code}: {msg}")
@@ -114,6 +124,22 @@ SIGNATURES = {
     "fsi_newton_solve": (ctypes.c_int, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiProblem), P, P,
                                         P, P, ctypes.POINTER(FsiNewtonOpts),
                                         ctypes.POINTER(FsiNewtonStats), P, SZ, P]),
+    "fsi_conv3d_fwd": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int32, P,
+                                      P, P, P]),
+    "fsi_conv3d_wgrad_workspace": (SZ, [P, ctypes.c_int32, ctypes.c_int32]),
+    "fsi_conv3d_wgrad": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, SZ, P]),
+    "fsi_conv3d_flip_transpose": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, P, P, P]),
+    "fsi_mse_workspace": (SZ, []),
+    "fsi_mse_loss": (ctypes.c_int, [I64, ctypes.c_int32, ctypes.c_int32, P, P, P,
+                                    ctypes.POINTER(ctypes.c_double), P, SZ, P]),
+    "fsi_adam_step": (ctypes.c_int, [I64, P, P, P, P, P, ctypes.c_int32, ctypes.c_float,
+                                     ctypes.c_float, ctypes.c_float, ctypes.c_float, P]),
+    "fsi_to_bf16": (ctypes.c_int, [I64, P, P, P]),
+    "fsi_nn_pack": (ctypes.c_int, [I64, ctypes.c_int32, ctypes.POINTER(FsiNnPackSpec), P, P]),
+    "fsi_nn_moments_workspace": (SZ, [ctypes.c_int32]),
+    "fsi_nn_moments": (ctypes.c_int, [I64, ctypes.c_int32, P, P, P, SZ, P]),
+    "fsi_nn_unpack": (ctypes.c_int, [I64, ctypes.c_int32, P, P, ctypes.POINTER(FsiNnUnpackSpec), P,
+                                     P, P, P]),
     "fsi_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "fsi_profile_read": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(I64)]),

@@ -8,6 +8,7 @@
 #include "fgmres.hpp"
 #include "kernels.hpp"
 #include "newton.hpp"
+#include "nn.hpp"
 
 namespace fsi {
 
@@ -582,4 +583,122 @@ FSI_API int fsi_newton_solve(const fsi_problem *P64, const fsi_problem *P32, con
     }
     return newton_solve(g, *P64, o->inner == FSI_F32 ? P32 : nullptr, f, lamg, gD, x, *o, stats, ws, jw,
                         as_stream(stream));
+}
+
+// ---------------------------------------------------------------- warm-start network
+static int check_dims(const int32_t *dims)
+{
+    FSI_CHECK_ARG(dims != nullptr, "dims is NULL");
+    FSI_CHECK_ARG(dims[0] >= 1 && dims[1] >= 1 && dims[2] >= 1, "dims must be >= 1");
+    FSI_CHECK_ARG((int64_t)dims[0] * dims[1] * dims[2] < ((int64_t)1 << 31), "lattice too large");
+    return FSI_OK;
+}
+
+static bool chan_ok(int32_t c) { return c >= 32 && c % 32 == 0 && c <= 1024; }
+
+FSI_API int fsi_conv3d_fwd(const int32_t *dims, int32_t cin, int32_t cout, const uint16_t *X,
+                           const uint16_t *W, const float *bias, int32_t relu, const uint16_t *gate,
+                           uint16_t *Y_bf16, float *Y_f32, void *stream)
+{
+    clear_error();
+    int rc = check_dims(dims);
+    if (rc) return rc;
+    FSI_CHECK_ARG(chan_ok(cin) && chan_ok(cout), "cin and cout must be multiples of 32 in [32, 1024]");
+    FSI_CHECK_ARG(X && W && (Y_bf16 || Y_f32), "X, W and an output must be non-NULL");
+    return nn_conv_fwd(dims, cin, cout, X, W, bias, relu, gate, Y_bf16, Y_f32, as_stream(stream));
+}
+
+FSI_API size_t fsi_conv3d_wgrad_workspace(const int32_t *dims, int32_t cin, int32_t cout)
+{
+    if (check_dims(dims) != FSI_OK || !chan_ok(cin) || !chan_ok(cout)) return 0;
+    return nn_wgrad_workspace(dims, cin, cout);
+}
+
+FSI_API int fsi_conv3d_wgrad(const int32_t *dims, int32_t cin, int32_t cout, const uint16_t *dY,
+                             const uint16_t *X, float *dW, float *db, void *ws, size_t ws_bytes,
+                             void *stream)
+{
+    clear_error();
+    int rc = check_dims(dims);
+    if (rc) return rc;
+    FSI_CHECK_ARG(chan_ok(cin) && chan_ok(cout), "cin and cout must be multiples of 32 in [32, 1024]");
+    FSI_CHECK_ARG(dY && X && dW, "dY, X and dW must be non-NULL");
+    const size_t need = nn_wgrad_workspace(dims, cin, cout);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+        return FSI_ERR_WORKSPACE;
+    }
+    return nn_conv_wgrad(dims, cin, cout, dY, X, dW, db, ws, as_stream(stream));
+}
+
+FSI_API int fsi_conv3d_flip_transpose(int32_t cin, int32_t cout, const uint16_t *W, uint16_t *Wd,
+                                      void *stream)
+{
+    clear_error();
+    FSI_CHECK_ARG(chan_ok(cin) && chan_ok(cout), "cin and cout must be multiples of 32 in [32, 1024]");
+    FSI_CHECK_ARG(W && Wd && W != Wd, "W and Wd must be non-NULL and distinct");
+    return nn_flip_transpose(cin, cout, W, Wd, as_stream(stream));
+}
+
+FSI_API size_t fsi_mse_workspace(void) { return nn_mse_workspace(); }
+
+FSI_API int fsi_mse_loss(int64_t nvox, int32_t c, int32_t used, const float *pred, const float *target,
+                         uint16_t *dpred, double *loss_host, void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    FSI_CHECK_ARG(nvox >= 1 && c >= 1 && used >= 1 && used <= c, "bad sizes");
+    FSI_CHECK_ARG(pred && target, "pred and target must be non-NULL");
+    if (ws == nullptr || ws_bytes < nn_mse_workspace()) {
+        set_error("workspace of %zu bytes needed", nn_mse_workspace());
+        return FSI_ERR_WORKSPACE;
+    }
+    return nn_mse(nvox, c, used, pred, target, dpred, loss_host, ws, as_stream(stream));
+}
+
+FSI_API int fsi_adam_step(int64_t n, float *w, const float *g, float *m, float *v, uint16_t *w_bf16,
+                          int32_t t, float lr, float b1, float b2, float eps, void *stream)
+{
+    clear_error();
+    FSI_CHECK_ARG(n >= 1 && w && g && m && v, "bad arguments");
+    FSI_CHECK_ARG(t >= 1, "t counts from 1");
+    FSI_CHECK_ARG(b1 >= 0.f && b1 < 1.f && b2 >= 0.f && b2 < 1.f && eps >= 0.f, "bad Adam constants");
+    return nn_adam(n, w, g, m, v, w_bf16, t, lr, b1, b2, eps, as_stream(stream));
+}
+
+FSI_API int fsi_to_bf16(int64_t n, const float *in, uint16_t *out, void *stream)
+{
+    clear_error();
+    FSI_CHECK_ARG(n >= 1 && in && out, "bad arguments");
+    return nn_to_bf16(n, in, out, as_stream(stream));
+}
+
+FSI_API int fsi_nn_pack(int64_t nvox, int32_t c, const fsi_nn_pack_spec *p, float *out, void *stream)
+{
+    clear_error();
+    FSI_CHECK_ARG(p && out && nvox >= 1, "bad arguments");
+    FSI_CHECK_ARG(p->nch >= 0 && p->nch <= 32 && p->nch <= c && c >= 1, "bad channel counts");
+    return nn_pack(nvox, c, *p, out, as_stream(stream));
+}
+
+FSI_API size_t fsi_nn_moments_workspace(int32_t c) { return c >= 1 ? nn_moments_workspace(c) : 0; }
+
+FSI_API int fsi_nn_moments(int64_t nvox, int32_t c, const float *data, double *sums_host, void *ws,
+                           size_t ws_bytes, void *stream)
+{
+    clear_error();
+    FSI_CHECK_ARG(nvox >= 1 && c >= 1 && data && sums_host, "bad arguments");
+    if (ws == nullptr || ws_bytes < nn_moments_workspace(c)) {
+        set_error("workspace of %zu bytes needed", nn_moments_workspace(c));
+        return FSI_ERR_WORKSPACE;
+    }
+    return nn_moments(nvox, c, data, sums_host, ws, as_stream(stream));
+}
+
+FSI_API int fsi_nn_unpack(int64_t nvox, int32_t c, const float *out, const double *base,
+                          const fsi_nn_unpack_spec *u, const uint32_t *dir_mask, const double *gD,
+                          double *x, void *stream)
+{
+    clear_error();
+    FSI_CHECK_ARG(nvox >= 1 && c >= 4 && out && base && u && x, "bad arguments");
+    return nn_unpack(nvox, c, out, base, *u, dir_mask, gD, x, as_stream(stream));
 }
