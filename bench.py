@@ -157,6 +157,14 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--experiment", default=None, choices=["warmstart", "c5", "netspeed"],
+                    help="run a Newton-step experiment instead of the apply benchmark")
+    ap.add_argument("--exp-steps", type=int, default=200)
+    ap.add_argument("--exp-train-end", type=int, default=100)
+    ap.add_argument("--exp-epochs", type=int, default=20)
+    ap.add_argument("--exp-stride", type=int, default=1)
+    ap.add_argument("--exp-save", default=None)
+    ap.add_argument("--exp-load", default=None)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 512 MiB device copy (for counter calibration)")
     args = ap.parse_args(argv)
@@ -170,6 +178,8 @@ def main(argv=None):
     import fsi_workloads as W
     import paper_2601_08266_amd as fsi
 
+    if args.experiment:
+        return run_experiment(args)
     dev = torch.device("cuda:0")
     cfg = W.CONFIGS[args.workload]
     g = cfg.grid
@@ -237,6 +247,47 @@ def main(argv=None):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, case64)
     print(json.dumps(out))
+    return 0
+
+
+def run_experiment(args):
+    import torch
+
+    from paper_2601_08266_amd import experiments as ex
+    from paper_2601_08266_amd import warmstart as wsn
+
+    if args.experiment == "netspeed":
+        dims = (65, 65, 65)
+        net = wsn.WarmStartNet(dims)
+        V = 65 ** 3
+        x = torch.zeros(V * 32, dtype=torch.int16, device="cuda")
+        t = torch.zeros(V * 32, dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            net.forward(x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            net.forward(x)
+        torch.cuda.synchronize()
+        fwd = (time.perf_counter() - t0) / 10 * 1e3
+        t0 = time.perf_counter()
+        for _ in range(5):
+            net.train_sample(x, t, want_loss=False)
+        torch.cuda.synchronize()
+        trn = (time.perf_counter() - t0) / 5 * 1e3
+        flops = 2.0 * 27 * V * sum(l.cin * l.cout for l in net.layers)
+        print(json.dumps({"experiment": "netspeed", "lattice": "65^3", "params": net.n_params,
+                          "forward_ms": round(fwd, 3), "train_sample_ms": round(trn, 3),
+                          "forward_padded_TFLOPs": round(flops / fwd / 1e9, 2)}))
+        return 0
+    if args.experiment == "warmstart":
+        summary, lw = ex.warmstart_c4(steps=args.exp_steps, train_end=args.exp_train_end,
+                                      epochs=args.exp_epochs, eval_stride=args.exp_stride,
+                                      save_path=args.exp_save)
+        print(json.dumps({"experiment": "warmstart_c4", **summary}))
+        return 0
+    summary = ex.large_c5(state_path=args.exp_load)
+    print(json.dumps({"experiment": "large_c5", **summary}))
     return 0
 
 

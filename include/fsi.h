@@ -417,6 +417,16 @@ int fsi_nn_unpack(int64_t nvox, int32_t c, const float *out, const double *base,
                   void *stream);
 
 /*
+ * BLAS-1 helpers used by the drivers (FP64 device vectors):
+ *   fsi_axpby  y = alpha x + beta y (beta = 0: y = alpha x, y's old contents ignored)
+ *   fsi_dot    HOST out = x . y, deterministic fixed-order reduction.  SYNCS.
+ */
+int fsi_axpby(int64_t n, double alpha, const double *x, double beta, double *y, void *stream);
+int fsi_dot(int64_t n, const double *x, const double *y, double *out_host, void *ws,
+            size_t ws_bytes, void *stream);
+size_t fsi_dot_workspace(void);
+
+/*
  * Kernel timing (tracing aid, not part of the method).  fsi_profile_enable(1)
  * resets the totals and brackets each later launch of an instrumented kernel
  * with two hipEvents recorded on that launch's stream; fsi_profile_enable(0)

@@ -418,6 +418,37 @@ def newton_solve(P64: Problem, f: torch.Tensor, x: torch.Tensor, opts: FsiNewton
     return rc, st
 
 
+# --------------------------------------------------------------------------- BLAS-1
+_DOT_WS = {}
+
+
+def axpby(alpha: float, x: torch.Tensor, beta: float, y: torch.Tensor, stream=None):
+    """y = alpha x + beta y on FP64 device vectors (fsi_axpby)."""
+    _need(x, "x", torch.float64)
+    _need(y, "y", torch.float64, x.numel())
+    L.check("fsi_axpby", L.lib().fsi_axpby(x.numel(), float(alpha), _ptr(x), float(beta), _ptr(y),
+                                            _stream(stream)))
+    return y
+
+
+def dot(x: torch.Tensor, y: torch.Tensor, stream=None) -> float:
+    """x . y (fsi_dot, deterministic; synchronises)."""
+    _need(x, "x", torch.float64)
+    _need(y, "y", torch.float64, x.numel())
+    dev = x.device
+    if dev not in _DOT_WS:
+        _DOT_WS[dev] = torch.empty(int(L.lib().fsi_dot_workspace()), dtype=torch.uint8, device=dev)
+    ws = _DOT_WS[dev]
+    out = ctypes.c_double(0.0)
+    L.check("fsi_dot", L.lib().fsi_dot(x.numel(), _ptr(x), _ptr(y), ctypes.byref(out), _ptr(ws),
+                                        ws.numel(), _stream(stream)))
+    return float(out.value)
+
+
+def norm2(x: torch.Tensor, stream=None) -> float:
+    return dot(x, x, stream) ** 0.5
+
+
 # --------------------------------------------------------------------------- timing
 def profile_enable(on: bool = True) -> None:
     """Start (and reset) or stop per-kernel hipEvent timing inside the library."""

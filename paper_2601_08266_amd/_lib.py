@@ -140,6 +140,9 @@ SIGNATURES = {
     "fsi_nn_moments": (ctypes.c_int, [I64, ctypes.c_int32, P, P, P, SZ, P]),
     "fsi_nn_unpack": (ctypes.c_int, [I64, ctypes.c_int32, P, P, ctypes.POINTER(FsiNnUnpackSpec), P,
                                      P, P, P]),
+    "fsi_axpby": (ctypes.c_int, [I64, ctypes.c_double, P, ctypes.c_double, P, P]),
+    "fsi_dot": (ctypes.c_int, [I64, P, P, ctypes.POINTER(ctypes.c_double), P, SZ, P]),
+    "fsi_dot_workspace": (SZ, []),
     "fsi_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "fsi_profile_read": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(I64)]),

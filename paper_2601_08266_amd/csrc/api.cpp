@@ -7,6 +7,7 @@
 #include "dlm.hpp"
 #include "fgmres.hpp"
 #include "kernels.hpp"
+#include "krylov.hpp"
 #include "newton.hpp"
 #include "nn.hpp"
 
@@ -701,4 +702,34 @@ FSI_API int fsi_nn_unpack(int64_t nvox, int32_t c, const float *out, const doubl
     clear_error();
     FSI_CHECK_ARG(nvox >= 1 && c >= 4 && out && base && u && x, "bad arguments");
     return nn_unpack(nvox, c, out, base, *u, dir_mask, gD, x, as_stream(stream));
+}
+
+// ---------------------------------------------------------------- BLAS-1 helpers
+FSI_API int fsi_axpby(int64_t n, double alpha, const double *x, double beta, double *y, void *stream)
+{
+    clear_error();
+    FSI_CHECK_ARG(n >= 0 && (n == 0 || (x && y)), "bad arguments");
+    if (n == 0) return FSI_OK;
+    if (beta == 0.0) return kry_scale(n, alpha, x, y, as_stream(stream));
+    return kry_axpby(n, alpha, x, beta, y, as_stream(stream));
+}
+
+FSI_API size_t fsi_dot_workspace(void) { return align_up((size_t)(KRY_NB + 8) * sizeof(double)); }
+
+FSI_API int fsi_dot(int64_t n, const double *x, const double *y, double *out_host, void *ws,
+                    size_t ws_bytes, void *stream)
+{
+    clear_error();
+    FSI_CHECK_ARG(n >= 1 && x && y && out_host, "bad arguments");
+    if (ws == nullptr || ws_bytes < fsi_dot_workspace()) {
+        set_error("workspace of %zu bytes needed", fsi_dot_workspace());
+        return FSI_ERR_WORKSPACE;
+    }
+    double *part = reinterpret_cast<double *>(ws);
+    hipStream_t st = as_stream(stream);
+    int rc = kry_multidot(n, 1, x, n, y, part, part + KRY_NB, st);
+    if (rc) return rc;
+    FSI_HIP(hipMemcpyAsync(out_host, part + KRY_NB, sizeof(double), hipMemcpyDeviceToHost, st));
+    FSI_HIP(hipStreamSynchronize(st));
+    return FSI_OK;
 }

@@ -1,0 +1,169 @@
+"""Implicit time stepping of the channel-with-rotating-plates problem (argument
+marshalling and orchestration only; every computation runs in libfsi.so).
+
+Per step n -> n+1 (t = (n+1) dt), the order of section 2.4's solution
+algorithm with the stand-ins of this library:
+  1. the immersed points move (rigid rotation of the plates): locate, sort,
+     interface band of s, per-cell DLM blocks, lamg = B^T (kappa g);
+  2. the inflow value and the Dirichlet data g_D;
+  3. the initial guess: the previous state with the Dirichlet values imposed
+     (plain), or a learned prediction kept only if its residual is smaller;
+  4. Newton to ||R|| <= rel_tol ||R(x_plain)|| (the same absolute threshold for
+     any guess, so a guess can change the work, never the answer);
+  5. the multiplier lambda = kappa (g - B u) of the new state, spread to the
+     nodes (B^T lambda), recorded with the state for the learned warm start.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+from typing import Callable, List, Optional
+
+import numpy as np
+import torch
+
+import fsi_workloads as W
+
+from . import (Problem, axpby, dlm_B, dlm_BT, dlm_gram, dlm_locate, make_params, newton_opts,
+               newton_solve, norm2, vms_residual)
+from . import warmstart as ws
+
+
+@dataclass
+class StepRecord:
+    n: int                       # index of the new state (x^{n})
+    t: float
+    x: torch.Tensor              # [4][N] FP64 state
+    btlam: torch.Tensor          # B^T lambda at this state [3][N]
+    lamg: torch.Tensor           # B^T kappa g used by this step [3][N]
+    inflow: float
+    newton_iters: int = 0
+    krylov_iters: int = 0
+    ms_newton: float = 0.0
+    ms_guess: float = 0.0
+    res_plain: float = 0.0
+    res_guess: float = 0.0
+    used_guess: bool = False
+
+
+class ChannelRun:
+    def __init__(self, cfg, device="cuda", inner=torch.float32, eta=1e-3, restart=50,
+                 rel_tol=1e-8, period=0.8, amp_deg=20.0, max_krylov=4000):
+        self.cfg = cfg
+        self.g = cfg.grid
+        self.N = self.g.num_nodes
+        self.dev = torch.device(device)
+        self.inner, self.eta, self.restart, self.rel_tol = inner, eta, restart, rel_tol
+        self.max_krylov = max_krylov
+        self.period, self.amp = period, amp_deg
+        self.prm = make_params(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
+        g = self.g
+        mask = W.channel_dirichlet_mask(g)
+        self.mask = torch.tensor(W.mask_to_bits(mask).view(np.int32), device=self.dev)
+        nx, ny, nz = g.nodes_per_axis
+        k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        inflow = ((i == 0) & (j > 0) & (j < ny - 1) & (k > 0) & (k < nz - 1)).ravel()
+        pat = np.zeros(3 * self.N)
+        pat[: self.N][inflow] = 1.0            # u_x on the inflow face; no-slip wins on edges
+        self.inflow_pattern = torch.tensor(pat, dtype=torch.float64, device=self.dev)
+        self.gD = torch.zeros(3 * self.N, dtype=torch.float64, device=self.dev)
+        self.f = torch.zeros(3 * self.N, dtype=torch.float64, device=self.dev)
+        self.zero_out = torch.zeros(self.N * 32, dtype=torch.float32, device=self.dev)
+        self.x = torch.zeros(4 * self.N, dtype=torch.float64, device=self.dev)
+        self.R = torch.empty_like(self.x)
+        self.n = 0
+        self.kappa = None
+        self.history: List[StepRecord] = []
+        self.newton_ws = None
+        self.m = cfg.m_points
+        vol = W.plate_volume()
+        kap = W.kappa_weights(self.m, vol, cfg.c_m, cfg.alpha)
+        self.kappa64 = torch.tensor(kap, dtype=torch.float64, device=self.dev)
+        self.kappa32 = torch.tensor(kap, dtype=torch.float32, device=self.dev)
+        self.history.append(StepRecord(0, 0.0, self.x.clone(), torch.zeros(3 * self.N, dtype=torch.float64,
+                                                                            device=self.dev),
+                                       torch.zeros(3 * self.N, dtype=torch.float64, device=self.dev), 0.0))
+
+    def inflow_value(self, t):
+        return math.sin(2.0 * math.pi * t / self.period)
+
+    def _points(self, t):
+        X, gp = W.rotating_plate_points(self.m, self.cfg.seed_fields, t, period=self.period,
+                                        amp_deg=self.amp)
+        Xt = torch.tensor(X.ravel(), dtype=torch.float64, device=self.dev)
+        gt = torch.tensor(gp.ravel(), dtype=torch.float64, device=self.dev)
+        tab64 = dlm_locate(self.g, Xt, dtype=torch.float64, s_max=self.cfg.s_max)
+        tab32 = dlm_locate(self.g, Xt, dtype=torch.float32, s_max=self.cfg.s_max)
+        gram64 = dlm_gram(self.g, tab64, self.kappa64)
+        gram32 = dlm_gram(self.g, tab32, self.kappa32)
+        lamg = torch.zeros(3 * self.N, dtype=torch.float64, device=self.dev)
+        dlm_BT(self.g, tab64, gt, lamg, kappa=self.kappa64)
+        P64 = Problem(self.g, self.prm, self.x, tab64, self.kappa64, s=tab64.s, mask=self.mask,
+                      gram=gram64)
+        a32 = torch.zeros(3 * self.N, dtype=torch.float32, device=self.dev)
+        P32 = Problem(self.g, self.prm, a32, tab32, self.kappa32, s=tab32.s, mask=self.mask,
+                      gram=gram32)
+        return P64, P32, lamg, gt, tab64
+
+    def residual_norm(self, P64, x, lamg):
+        vms_residual(P64, self.f, x, gD=self.gD, lamg=lamg, R=self.R)
+        return norm2(self.R)
+
+    def btlam(self, tab64, gt, x):
+        """B^T lambda with lambda = kappa (g - B u) (the paper's lambda = -R^s for the stand-in)."""
+        Bu = dlm_B(self.g, tab64, x[: 3 * self.N])
+        lam = gt.clone()
+        axpby(-1.0, Bu, 1.0, lam)
+        out = torch.zeros(3 * self.N, dtype=torch.float64, device=self.dev)
+        dlm_BT(self.g, tab64, lam, out, kappa=self.kappa64)
+        return out
+
+    def step(self, guess_fn: Optional[Callable] = None, inner=None, record=True):
+        """Advance one step.  guess_fn(run, lamg, inflow) -> FP64 [4][N] guess or None."""
+        cfg = self.cfg
+        n1 = self.n + 1
+        t1 = n1 * cfg.dt
+        P64, P32, lamg, gt, tab64 = self._points(t1)
+        inflow = self.inflow_value(t1)
+        axpby(inflow, self.inflow_pattern, 0.0, self.gD)
+        axpby(cfg.c_m, self.x[: 3 * self.N], 0.0, self.f)
+        torch.cuda.synchronize()
+        t_g0 = time.perf_counter()
+        # plain guess: previous state with the new Dirichlet values
+        x_plain = torch.empty_like(self.x)
+        ws.unpack(self.N, 32, self.zero_out, self.x, [0, 0, 0, 0], [1, 1, 1, 1], x_plain,
+                  mask=self.mask, gD=self.gD)
+        r_plain = self.residual_norm(P64, x_plain, lamg)
+        tol = self.rel_tol * r_plain
+        x0, r_guess, used = x_plain, r_plain, False
+        if guess_fn is not None:
+            xg = guess_fn(self, lamg, inflow)
+            if xg is not None:
+                r_g = self.residual_norm(P64, xg, lamg)
+                if math.isfinite(r_g) and r_g < r_plain:
+                    x0, r_guess, used = xg, r_g, True
+                else:
+                    r_guess = r_g
+        torch.cuda.synchronize()
+        ms_guess = (time.perf_counter() - t_g0) * 1e3
+        inner = inner if inner is not None else self.inner
+        opts = newton_opts(tol_abs=tol, eta=self.eta, restart=self.restart,
+                           max_krylov=self.max_krylov, inner=inner)
+        x_new = x0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = newton_solve(P64, self.f, x_new, opts, P32=P32 if inner == torch.float32 else None,
+                              lamg=lamg, gD=self.gD, check=False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        if rc != 0:
+            raise RuntimeError(f"Newton failed at step {n1} (status {rc}, iters {st.newton_iters}, "
+                               f"hist {list(st.res_hist[:st.newton_iters + 1])})")
+        rec = StepRecord(n1, t1, x_new, self.btlam(tab64, gt, x_new) if record else None, lamg,
+                         inflow, st.newton_iters, st.krylov_iters, ms, ms_guess, r_plain, r_guess, used)
+        self.x = x_new
+        self.n = n1
+        if record:
+            self.history.append(rec)
+        return rec
