@@ -40,7 +40,7 @@ Layout layout(int64_t n, int m, fsi_dtype inner, size_t jws_bytes)
     L.t32a = take((size_t)n * sizeof(float));
     L.t32b = take((size_t)n * sizeof(float));
     L.partial = take((size_t)(m + 2) * KRY_NB * sizeof(double));
-    L.hdev = take((size_t)(2 * (m + 2)) * sizeof(double));
+    L.hdev = take((size_t)(2 * (m + 1) + 2 + m) * sizeof(double));
     L.jws = take(jws_bytes);
     L.total = off;
     return L;
@@ -103,7 +103,8 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
             goto done;
         }
         const double target = o.rtol * bnorm;
-        std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), h1(m + 1), h2(m + 1);
+        std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m),
+            hcopy(2 * (m + 1) + 1);
         double prev_beta = -1.0;
         int stalls = 0;
         for (;;) {
@@ -157,24 +158,23 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
                     else FSI_HIP(hipMemcpyAsync(Zj, Vj, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
                     TRY(J64.apply(Zj, w64, jws, st));
                 }
-                // classical Gram-Schmidt, twice
-                TRY(kry_multidot(n, j + 1, V, n, w64, partial, hdev, st));
-                TRY(kry_multi_axpy(n, j + 1, V, n, hdev, w64, st));
-                TRY(fetch(h1.data(), hdev, j + 1));
-                TRY(kry_multidot(n, j + 1, V, n, w64, partial, hdev, st));
-                TRY(kry_multi_axpy(n, j + 1, V, n, hdev, w64, st));
-                TRY(fetch(h2.data(), hdev, j + 1));
-                double hn = 0.0;
-                TRY(kry_norm(n, w64, partial, hdev, st));
-                TRY(fetch(&hn, hdev, 1));
-                for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h1[i] + h2[i];
+                // classical Gram-Schmidt, twice, in three passes over the basis:
+                //   h1 = V^T w;  w -= V h1 and h2 = V^T w;  w -= V h2 and ||w||
+                // h1, h2 and ||w|| stay on the device until one copy at the end.
+                double *d_h1 = hdev, *d_h2 = hdev + (m + 1), *d_hn = hdev + 2 * (m + 1);
+                TRY(kry_multidot(n, j + 1, V, n, w64, partial, d_h1, st));
+                TRY(kry_axpy_dot(n, j + 1, V, n, d_h1, w64, j + 1, partial, d_h2, st));
+                TRY(kry_axpy_dot(n, j + 1, V, n, d_h2, w64, 0, partial, d_hn, st));
+                TRY(fetch(hcopy.data(), hdev, 2 * (m + 1) + 1));
+                double hn = hcopy[2 * (m + 1)];
+                for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcopy[i] + hcopy[(m + 1) + i];
                 H[(size_t)(j + 1) * m + j] = hn;
                 if (!std::isfinite(hn)) {
                     set_error("Arnoldi vector norm is NaN/Inf");
                     rc = FSI_ERR_NAN;
                     goto done;
                 }
-                if (hn > 0.0) TRY(kry_scale_inv(n, w64, hdev, V + (size_t)(j + 1) * n, st));
+                if (hn > 0.0) TRY(kry_scale_inv(n, w64, d_hn, V + (size_t)(j + 1) * n, st));
                 for (int i = 0; i < j; ++i) {
                     const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
                     H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;

@@ -102,6 +102,53 @@ __global__ __launch_bounds__(KT) void multi_axpy_k(int64_t n, int nk, const doub
     }
 }
 
+// fused CGS2 pass: w[i] -= sum_k h[k] V[k][i], then partial[k][block] of V[k] . w (new w);
+// with nk_dot = 0 it only accumulates partial[0][block] = w . w (the norm pass)
+__global__ __launch_bounds__(KT) void axpy_dot_k(int64_t n, int nk, const double *__restrict__ V, int64_t ldv,
+                                                 const double *__restrict__ h, double *__restrict__ w,
+                                                 int nk_dot, double *__restrict__ partial)
+{
+    __shared__ double red[KG][KT];
+    const int t = threadIdx.x;
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    // update the chunk of w
+    for (int64_t i = lo + t; i < hi; i += KT) {
+        double s = w[i];
+        for (int k = 0; k < nk; ++k) s -= h[k] * V[(int64_t)k * ldv + i];
+        w[i] = s;
+    }
+    // each thread re-reads only the elements it wrote, so no barrier is needed before the dots
+    const int ngroups = nk_dot > 0 ? nk_dot : 1;
+    for (int g0 = 0; g0 < ngroups; g0 += KG) {
+        double acc[KG];
+#pragma unroll
+        for (int k = 0; k < KG; ++k) acc[k] = 0.0;
+        for (int64_t i = lo + t; i < hi; i += KT) {
+            const double wi = w[i];
+            if (nk_dot == 0) {
+                acc[0] += wi * wi;
+            } else {
+#pragma unroll
+                for (int k = 0; k < KG; ++k)
+                    if (g0 + k < nk_dot) acc[k] += V[(int64_t)(g0 + k) * ldv + i] * wi;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KG; ++k) red[k][t] = acc[k];
+        __syncthreads();
+        for (int off = KT / 2; off > 0; off >>= 1) {
+            if (t < off)
+#pragma unroll
+                for (int k = 0; k < KG; ++k) red[k][t] += red[k][t + off];
+            __syncthreads();
+        }
+        if (t < KG && g0 + t < ngroups) partial[(int64_t)(g0 + t) * gridDim.x + blockIdx.x] = red[t][0];
+        __syncthreads();
+    }
+}
+
 // x[i] += sum_k y[k] Z[k][i]   (Z in the inner precision)
 template <typename TZ>
 __global__ __launch_bounds__(KT) void update_k(int64_t n, int nk, const TZ *__restrict__ Z, int64_t ldz,
@@ -181,6 +228,21 @@ int kry_multi_axpy(int64_t n, int nk, const double *V, int64_t ldv, const double
 {
     hipLaunchKernelGGL(multi_axpy_k, dim3(grid_for(n)), dim3(KT), 0, st, n, nk, V, ldv, h, w);
     FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+
+int kry_axpy_dot(int64_t n, int nk, const double *V, int64_t ldv, const double *h, double *w, int nk_dot,
+                 double *partial, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(axpy_dot_k, dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, h, w, nk_dot, partial);
+    FSI_LAUNCH_CHECK();
+    const int nr = nk_dot > 0 ? nk_dot : 1;
+    hipLaunchKernelGGL(reduce_partials_k, dim3((nr + 63) / 64), dim3(64), 0, st, nr, KRY_NB, partial, out);
+    FSI_LAUNCH_CHECK();
+    if (nk_dot == 0) {
+        hipLaunchKernelGGL(sqrt_k, dim3(1), dim3(1), 0, st, out);
+        FSI_LAUNCH_CHECK();
+    }
     return FSI_OK;
 }
 

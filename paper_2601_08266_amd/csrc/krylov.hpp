@@ -17,6 +17,9 @@ int kry_multidot(int64_t n, int nk, const double *V, int64_t ldv, const double *
 int kry_norm(int64_t n, const double *w, double *partial, double *out, hipStream_t st);
 int kry_multi_axpy(int64_t n, int nk, const double *V, int64_t ldv, const double *h, double *w,
                    hipStream_t st);
+// w -= V h (nk vectors); then out[k] = V[k] . w for k < nk_dot, or out[0] = ||w|| if nk_dot == 0
+int kry_axpy_dot(int64_t n, int nk, const double *V, int64_t ldv, const double *h, double *w, int nk_dot,
+                 double *partial, double *out, hipStream_t st);
 int kry_update(int64_t n, int nk, fsi_dtype dz, const void *Z, int64_t ldz, const double *y, double *x,
                hipStream_t st);
 
