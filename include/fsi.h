@@ -371,9 +371,10 @@ int fsi_newton_solve(const fsi_problem *P64, const fsi_problem *P32, const doubl
  *                    as bfloat16 (0 in unused channels).
  * fsi_adam_step      w, m, v float [n]; t >= 1; w_bf16 (optional) gets the
  *                    rounded copy of the updated w.
- * fsi_nn_pack        out[v][c] = (a_c[v] - b_c[v] - shift_c) * scale_c for
- *                    c < nch (a_c NULL: the constant cst_c; b_c NULL: 0), 0 for
- *                    nch <= c < C; a_c, b_c are double [V] device arrays.
+ * fsi_nn_pack        out[v][c] = (ca_c a_c[v] + cb_c b_c[v] + cc_c c_c[v] + cst_c
+ *                    - shift_c) * scale_c for c < nch (a NULL pointer
+ *                    contributes 0), 0 for nch <= c < C; a_c, b_c, c_c are
+ *                    double [V] device arrays.
  * fsi_nn_moments     per channel, sum and sum of squares over V (HOST out
  *                    [C][2] doubles, SYNCS).
  * fsi_nn_unpack      x[f][v] = base[f][v] + out[v][f] / scale_f + shift_f for
@@ -382,6 +383,8 @@ int fsi_newton_solve(const fsi_problem *P64, const fsi_problem *P32, const doubl
 typedef struct {
     const double *a[32];
     const double *b[32];
+    const double *c[32];
+    double ca[32], cb[32], cc[32];
     double cst[32];
     double shift[32];
     double scale[32];

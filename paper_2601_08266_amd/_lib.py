@@ -69,6 +69,8 @@ class FsiNewtonStats(ctypes.Structure):
 
 class FsiNnPackSpec(ctypes.Structure):
     _fields_ = [("a", ctypes.c_void_p * 32), ("b", ctypes.c_void_p * 32),
+                ("c", ctypes.c_void_p * 32), ("ca", ctypes.c_double * 32),
+                ("cb", ctypes.c_double * 32), ("cc", ctypes.c_double * 32),
                 ("cst", ctypes.c_double * 32), ("shift", ctypes.c_double * 32),
                 ("scale", ctypes.c_double * 32), ("nch", ctypes.c_int32)]
 

@@ -76,15 +76,21 @@ __global__ __launch_bounds__(KT) void multidot_k(int64_t n, int nk, const double
     }
 }
 
-// out[k] = sum_b partial[k][b] in block order (one thread per k)
-__global__ void reduce_partials_k(int nk, int nb, const double *__restrict__ partial,
-                                  double *__restrict__ out)
+// out[k] = sum_b partial[k][b]: one block per k, strided per-thread sums then a fixed LDS tree
+__global__ __launch_bounds__(KT) void reduce_partials_k(int nk, int nb, const double *__restrict__ partial,
+                                                        double *__restrict__ out)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nk) return;
+    __shared__ double red[KT];
+    const int k = blockIdx.x, t = threadIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partial[(int64_t)k * nb + b];
-    out[k] = s;
+    for (int b = t; b < nb; b += KT) s += partial[(int64_t)k * nb + b];
+    red[t] = s;
+    __syncthreads();
+    for (int off = KT / 2; off > 0; off >>= 1) {
+        if (t < off) red[t] += red[t + off];
+        __syncthreads();
+    }
+    if (t == 0) out[k] = red[0];
 }
 
 // sqrt of a device scalar, in place
@@ -209,7 +215,7 @@ int kry_multidot(int64_t n, int nk, const double *V, int64_t ldv, const double *
 {
     hipLaunchKernelGGL(multidot_k, dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, w, partial);
     FSI_LAUNCH_CHECK();
-    hipLaunchKernelGGL(reduce_partials_k, dim3((nk + 63) / 64), dim3(64), 0, st, nk, KRY_NB, partial, out);
+    hipLaunchKernelGGL(reduce_partials_k, dim3(nk), dim3(KT), 0, st, nk, KRY_NB, partial, out);
     FSI_LAUNCH_CHECK();
     return FSI_OK;
 }
@@ -237,7 +243,7 @@ int kry_axpy_dot(int64_t n, int nk, const double *V, int64_t ldv, const double *
     hipLaunchKernelGGL(axpy_dot_k, dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, h, w, nk_dot, partial);
     FSI_LAUNCH_CHECK();
     const int nr = nk_dot > 0 ? nk_dot : 1;
-    hipLaunchKernelGGL(reduce_partials_k, dim3((nr + 63) / 64), dim3(64), 0, st, nr, KRY_NB, partial, out);
+    hipLaunchKernelGGL(reduce_partials_k, dim3(nr), dim3(KT), 0, st, nr, KRY_NB, partial, out);
     FSI_LAUNCH_CHECK();
     if (nk_dot == 0) {
         hipLaunchKernelGGL(sqrt_k, dim3(1), dim3(1), 0, st, out);

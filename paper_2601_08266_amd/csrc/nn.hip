@@ -280,8 +280,10 @@ __global__ __launch_bounds__(256) void pack_k(int64_t V, int c, NnPack p, float 
     const int ch = (int)(i % c);
     float r = 0.f;
     if (ch < p.nch) {
-        double val = p.a[ch] ? p.a[ch][v] : p.cst[ch];
-        if (p.b[ch]) val -= p.b[ch][v];
+        double val = p.cst[ch];
+        if (p.a[ch]) val += p.ca[ch] * p.a[ch][v];
+        if (p.b[ch]) val += p.cb[ch] * p.b[ch][v];
+        if (p.c[ch]) val += p.cc[ch] * p.c[ch][v];
         r = (float)((val - p.shift[ch]) * p.scale[ch]);
     }
     out[i] = r;

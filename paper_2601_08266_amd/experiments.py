@@ -38,11 +38,15 @@ def _solve_modes(run, lw, k, modes):
         run.x = run.history[k].x.clone()
         run.n = k
         inner = torch.float64 if mode.endswith("f64") else torch.float32
-        gf = lw.guess if (lw is not None and mode.startswith("nn")) else None
+        gf = None
+        if lw is not None and mode.startswith("nn"):
+            gf = lw.guess
+        elif lw is not None and mode.startswith("extrap"):
+            gf = lw.extrapolation_guess
         rec = run.step(guess_fn=gf, inner=inner, record=False)
         out[mode] = dict(newton=rec.newton_iters, krylov=rec.krylov_iters, ms_newton=rec.ms_newton,
                          ms_guess=rec.ms_guess, res_plain=rec.res_plain, res_guess=rec.res_guess,
-                         used_guess=rec.used_guess)
+                         used_guess=rec.used_guess, hist=rec.res_hist)
         sols[mode] = rec.x
     ref = sols[modes[0]]
     nref = norm2(ref)
@@ -75,7 +79,7 @@ def warmstart_c4(steps=200, train_end=100, epochs=20, lr=1e-3, eval_stride=1, se
         sd["norm"] = dict(in_shift=lw.in_shift, in_scale=lw.in_scale, out_shift=lw.out_shift,
                           out_scale=lw.out_scale)
         torch.save(sd, save_path)
-    modes = ["plain_f64", "plain_mixed", "nn_mixed"]
+    modes = ["plain_f64", "plain_mixed", "extrap_mixed", "nn_mixed"]
     rows = []
     for k in range(train_end, steps, eval_stride):
         r = _solve_modes(run, lw, k, modes)
@@ -103,10 +107,12 @@ def warmstart_c4(steps=200, train_end=100, epochs=20, lr=1e-3, eval_stride=1, se
             "newton_iters": round(agg(m, "newton"), 3),
             "krylov_iters": round(agg(m, "krylov"), 1),
         }
-    summary["nn_mixed"]["guess_used_frac"] = statistics.mean(1.0 if r["nn_mixed"]["used_guess"] else 0.0 for r in rows)
-    summary["nn_mixed"]["res_ratio_mean"] = statistics.mean(r["nn_mixed"]["res_guess"] / r["nn_mixed"]["res_plain"] for r in rows)
-    summary["nn_mixed"]["max_rel_diff_vs_plain_f64"] = max(r["nn_mixed"]["rel_diff_vs_plain_f64"] for r in rows)
-    summary["plain_mixed"]["max_rel_diff_vs_plain_f64"] = max(r["plain_mixed"]["rel_diff_vs_plain_f64"] for r in rows)
+    for m in ("extrap_mixed", "nn_mixed"):
+        summary[m]["guess_used_frac"] = statistics.mean(1.0 if r[m]["used_guess"] else 0.0 for r in rows)
+        summary[m]["res_ratio_median"] = statistics.median(r[m]["res_guess"] / r[m]["res_plain"] for r in rows)
+    for m in modes[1:]:
+        summary[m]["max_rel_diff_vs_plain_f64"] = max(r[m]["rel_diff_vs_plain_f64"] for r in rows)
+    summary["newton_hist_example"] = {m: ["%.2e" % h for h in rows[len(rows) // 2][m]["hist"]] for m in modes}
     summary["speedup_nn_mixed_vs_plain_f64"] = round(summary["plain_f64"]["ms_per_step"] / summary["nn_mixed"]["ms_per_step"], 3)
     summary["speedup_plain_mixed_vs_plain_f64"] = round(summary["plain_f64"]["ms_per_step"] / summary["plain_mixed"]["ms_per_step"], 3)
     return summary, lw
@@ -132,7 +138,7 @@ def large_c5(lw_c4=None, warmup_steps=3, state_path=None):
         lw.in_shift, lw.in_scale = list(nm["in_shift"]), list(nm["in_scale"])
         lw.out_shift, lw.out_scale = list(nm["out_shift"]), list(nm["out_scale"])
     k = run.n
-    modes = ["plain_f64", "plain_mixed"] + (["nn_mixed"] if lw is not None else [])
+    modes = ["plain_f64", "plain_mixed"] + (["extrap_mixed", "nn_mixed"] if lw is not None else [])
     r = _solve_modes(run, lw, k, modes)
     for m in modes:
         _log(f"c5 step {k + 1} {m}: {r[m]['newton']}N/{r[m]['krylov']}K "

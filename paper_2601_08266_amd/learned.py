@@ -2,9 +2,11 @@
 
 Sample k (predicting state k+1) uses 19 input channels: u, v, w, p of states
 k, k-1, k-2; B^T lambda of state k; B^T kappa g of the new step; the new inflow
-value.  Target: the increment x^{k+1} - x^k (4 channels).  Channels are
+value.  The prediction is a correction to the second-order extrapolation
+2 x^k - x^{k-1}: the target is x^{k+1} - 2 x^k + x^{k-1} (4 channels), so a
+network that has learned nothing returns the extrapolation.  Channels are
 normalised with the training set's mean and standard deviation (computed by
-the library's moment kernel).  The prediction is base + increment with the
+the library's moment kernel).  The guess is extrapolation + correction with the
 Dirichlet values imposed; the stepper keeps it only if its residual beats the
 plain guess.
 """
@@ -17,6 +19,7 @@ from typing import List, Optional
 import numpy as np
 import torch
 
+from . import axpby
 from . import warmstart as ws
 from .stepper import ChannelRun, StepRecord
 
@@ -48,23 +51,34 @@ class LearnedWarmStart:
         for lag in range(3):
             st = hist[max(k - lag, 0)].x
             for f in range(4):
-                srcs.append((self._field(st, f), None, 0.0))
+                srcs.append(([(1.0, self._field(st, f))], 0.0))
         for f in range(3):
-            srcs.append((self._field(hist[k].btlam, f), None, 0.0))
+            srcs.append(([(1.0, self._field(hist[k].btlam, f))], 0.0))
         for f in range(3):
-            srcs.append((self._field(lamg, f), None, 0.0))
-        srcs.append((None, None, float(inflow)))
+            srcs.append(([(1.0, self._field(lamg, f))], 0.0))
+        srcs.append(([], float(inflow)))
         out = []
-        for c, (a, b, cst) in enumerate(srcs):
+        for c, (terms, cst) in enumerate(srcs):
             sh, sc = (self.in_shift[c], self.in_scale[c]) if normed else (0.0, 1.0)
-            out.append((a, b, cst, sh, sc))
+            out.append((terms, cst, sh, sc))
         return out
 
     def target_sources(self, hist, k, normed=True):
         out = []
+        prev = hist[max(k - 1, 0)].x
         for f in range(4):
             sh, sc = (self.out_shift[f], self.out_scale[f]) if normed else (0.0, 1.0)
-            out.append((self._field(hist[k + 1].x, f), self._field(hist[k].x, f), 0.0, sh, sc))
+            terms = [(1.0, self._field(hist[k + 1].x, f)), (-2.0, self._field(hist[k].x, f)),
+                     (1.0, self._field(prev, f))]
+            out.append((terms, 0.0, sh, sc))
+        return out
+
+    def extrapolation(self, run: ChannelRun, out: torch.Tensor):
+        """out = 2 x^k - x^{k-1} (FP64 [4][N]) for the run's current state k."""
+        k = run.n
+        hist = run.history
+        axpby(2.0, hist[k].x, 0.0, out)
+        axpby(-1.0, hist[max(k - 1, 0)].x, 1.0, out)
         return out
 
     # ---------------------------------------------------------------- data
@@ -130,6 +144,16 @@ class LearnedWarmStart:
         ws.pack(N, 32, self.input_sources(hist, k, lamg, inflow), self.buf32)
         ws.to_bf16(self.buf32, self.buf_bf)
         out = self.net.forward(self.buf_bf)
+        base = self.extrapolation(run, torch.empty(4 * N, dtype=torch.float64, device=run.dev))
         x = torch.empty(4 * N, dtype=torch.float64, device=run.dev)
-        ws.unpack(N, 32, out, hist[k].x, self.out_shift, self.out_scale, x, mask=run.mask, gD=run.gD)
+        ws.unpack(N, 32, out, base, self.out_shift, self.out_scale, x, mask=run.mask, gD=run.gD)
+        return x
+
+    def extrapolation_guess(self, run: ChannelRun, lamg, inflow):
+        """The network's backbone alone: 2 x^k - x^{k-1} with the Dirichlet values imposed."""
+        N = self.N
+        base = self.extrapolation(run, torch.empty(4 * N, dtype=torch.float64, device=run.dev))
+        x = torch.empty(4 * N, dtype=torch.float64, device=run.dev)
+        ws.unpack(N, 32, run.zero_out, base, [0, 0, 0, 0], [1, 1, 1, 1], x, mask=run.mask,
+                  gD=run.gD)
         return x

@@ -45,6 +45,7 @@ class StepRecord:
     res_plain: float = 0.0
     res_guess: float = 0.0
     used_guess: bool = False
+    res_hist: tuple = ()
 
 
 class ChannelRun:
@@ -161,7 +162,8 @@ class ChannelRun:
             raise RuntimeError(f"Newton failed at step {n1} (status {rc}, iters {st.newton_iters}, "
                                f"hist {list(st.res_hist[:st.newton_iters + 1])})")
         rec = StepRecord(n1, t1, x_new, self.btlam(tab64, gt, x_new) if record else None, lamg,
-                         inflow, st.newton_iters, st.krylov_iters, ms, ms_guess, r_plain, r_guess, used)
+                         inflow, st.newton_iters, st.krylov_iters, ms, ms_guess, r_plain, r_guess, used,
+                         tuple(st.res_hist[: min(st.newton_iters + 1, 32)]))
         self.x = x_new
         self.n = n1
         if record:

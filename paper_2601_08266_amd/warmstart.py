@@ -85,12 +85,16 @@ def to_bf16(x, out, stream=None):
 
 
 def pack(nvox, c, sources, out, stream=None):
-    """sources: list of (a, b, cst, shift, scale): channel = ((a or cst) - b - shift) * scale."""
+    """sources: per channel (terms, cst, shift, scale) with terms a list of up to three
+    (coefficient, FP64 field) pairs: channel = (sum coef * field + cst - shift) * scale."""
     spec = FsiNnPackSpec()
     spec.nch = len(sources)
-    for i, (a, b, cst, shift, scale) in enumerate(sources):
-        spec.a[i] = a.data_ptr() if a is not None else None
-        spec.b[i] = b.data_ptr() if b is not None else None
+    for i, (terms, cst, shift, scale) in enumerate(sources):
+        if len(terms) > 3:
+            raise ValueError("at most three fields per channel")
+        for slot, (coef, fld) in zip(("a", "b", "c"), terms):
+            getattr(spec, slot)[i] = fld.data_ptr()
+            getattr(spec, "c" + slot)[i] = float(coef)
         spec.cst[i] = float(cst)
         spec.shift[i] = float(shift)
         spec.scale[i] = float(scale)

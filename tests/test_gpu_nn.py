@@ -115,12 +115,14 @@ def test_mse_adam_pack_moments_unpack():
     a = torch.tensor(rng.standard_normal(N), device="cuda", dtype=torch.float64)
     b = torch.tensor(rng.standard_normal(N), device="cuda", dtype=torch.float64)
     out = torch.empty(N * 32, device="cuda")
-    ws.pack(N, 32, [(a, None, 0.0, 0.5, 2.0), (a, b, 0.0, 0.0, 1.0), (None, None, 3.0, 1.0, 1.0)], out)
+    ws.pack(N, 32, [([(1.0, a)], 0.0, 0.5, 2.0), ([(1.0, a), (-1.0, b)], 0.0, 0.0, 1.0),
+                    ([], 3.0, 1.0, 1.0), ([(2.0, a), (-1.0, b), (0.5, a)], 0.25, 0.0, 1.0)], out)
     o = out.cpu().numpy().reshape(N, 32)
     an, bn = a.cpu().numpy(), b.cpu().numpy()
     assert np.allclose(o[:, 0], (an - 0.5) * 2.0, atol=1e-6)
     assert np.allclose(o[:, 1], an - bn, atol=1e-6)
-    assert np.allclose(o[:, 2], 2.0) and np.all(o[:, 3:] == 0)
+    assert np.allclose(o[:, 2], 2.0) and np.all(o[:, 4:] == 0)
+    assert np.allclose(o[:, 3], 2.5 * an - bn + 0.25, atol=1e-6)
     mom = ws.moments(N, 32, out)
     assert abs(mom[1][0] - float(np.sum(o[:, 1].astype(np.float64)))) <= 1e-9
     assert abs(mom[1][1] - float(np.sum(o[:, 1].astype(np.float64) ** 2))) <= 1e-9
