@@ -22,7 +22,7 @@ namespace fsi {
 namespace {
 
 struct Layout {
-    size_t V, Z, w64, t32a, t32b, partial, hdev, jws, total;
+    size_t V, Z, w64, t32a, t32b, partial, hdev, gram, jws, total;
 };
 
 Layout layout(int64_t n, int m, fsi_dtype inner, size_t jws_bytes)
@@ -39,8 +39,9 @@ Layout layout(int64_t n, int m, fsi_dtype inner, size_t jws_bytes)
     L.w64 = take((size_t)n * sizeof(double));
     L.t32a = take((size_t)n * sizeof(float));
     L.t32b = take((size_t)n * sizeof(float));
-    L.partial = take((size_t)(m + 2) * KRY_NB * sizeof(double));
-    L.hdev = take((size_t)(2 * (m + 1) + 2 + m) * sizeof(double));
+    L.partial = take((size_t)(2 * (m + 2)) * KRY_NB * sizeof(double));
+    L.hdev = take((size_t)(4 * (m + 1) + 2) * sizeof(double));
+    L.gram = take((size_t)(m + 1) * (m + 1) * sizeof(double));
     L.jws = take(jws_bytes);
     L.total = off;
     return L;
@@ -71,6 +72,7 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
     float *t32b = reinterpret_cast<float *>(base + L.t32b);
     double *partial = reinterpret_cast<double *>(base + L.partial);
     double *hdev = reinterpret_cast<double *>(base + L.hdev);
+    double *Gdev = reinterpret_cast<double *>(base + L.gram);
     void *jws = base + L.jws;
     const size_t zel = inner == FSI_F64 ? sizeof(double) : sizeof(float);
 
@@ -105,6 +107,7 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
         const double target = o.rtol * bnorm;
         std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m),
             hcopy(2 * (m + 1) + 1);
+        (void)0;
         double prev_beta = -1.0;
         int stalls = 0;
         for (;;) {
@@ -158,16 +161,17 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
                     else FSI_HIP(hipMemcpyAsync(Zj, Vj, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
                     TRY(J64.apply(Zj, w64, jws, st));
                 }
-                // classical Gram-Schmidt, twice, in three passes over the basis:
-                //   h1 = V^T w;  w -= V h1 and h2 = V^T w;  w -= V h2 and ||w||
-                // h1, h2 and ||w|| stay on the device until one copy at the end.
-                double *d_h1 = hdev, *d_h2 = hdev + (m + 1), *d_hn = hdev + 2 * (m + 1);
-                TRY(kry_multidot(n, j + 1, V, n, w64, partial, d_h1, st));
-                TRY(kry_axpy_dot(n, j + 1, V, n, d_h1, w64, j + 1, partial, d_h2, st));
-                TRY(kry_axpy_dot(n, j + 1, V, n, d_h2, w64, 0, partial, d_hn, st));
-                TRY(fetch(hcopy.data(), hdev, 2 * (m + 1) + 1));
-                double hn = hcopy[2 * (m + 1)];
-                for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcopy[i] + hcopy[(m + 1) + i];
+                // classical Gram-Schmidt with re-orthogonalisation through the Gram matrix
+                // G = V^T V of the basis: one pass gives a = V^T w and the new Gram column
+                // V^T V_j; the second projection V^T (w - V a) = a - G a needs no further pass,
+                // so w -= V (a + (a - G a)) and ||w|| complete the step in a second pass.
+                double *d_ab = hdev, *d_h = hdev + 2 * (m + 1), *d_hn = hdev + 3 * (m + 1);
+                TRY(kry_multidot2(n, j + 1, V, n, w64, Vj, partial, d_ab, st));
+                TRY(kry_gram_coeffs(j + 1, d_ab, Gdev, m + 1, d_h, st));
+                TRY(kry_axpy_dot(n, j + 1, V, n, d_h, w64, 0, partial, d_hn, st));
+                TRY(fetch(hcopy.data(), d_h, (m + 1) + 1));
+                double hn = hcopy[m + 1];
+                for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcopy[i];
                 H[(size_t)(j + 1) * m + j] = hn;
                 if (!std::isfinite(hn)) {
                     set_error("Arnoldi vector norm is NaN/Inf");

@@ -155,6 +155,72 @@ __global__ __launch_bounds__(KT) void axpy_dot_k(int64_t n, int nk, const double
     }
 }
 
+// partial[k][block] = V[k] . w and partial[nk + k][block] = V[k] . u for k < nk (one read of V)
+__global__ __launch_bounds__(KT) void multidot2_k(int64_t n, int nk, const double *__restrict__ V,
+                                                  int64_t ldv, const double *__restrict__ w,
+                                                  const double *__restrict__ u,
+                                                  double *__restrict__ partial)
+{
+    __shared__ double red[2 * KG][KT];
+    const int t = threadIdx.x;
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    for (int g0 = 0; g0 < nk; g0 += KG) {
+        double aw[KG], au[KG];
+#pragma unroll
+        for (int k = 0; k < KG; ++k) aw[k] = au[k] = 0.0;
+        for (int64_t i = lo + t; i < hi; i += KT) {
+            const double wi = w[i], ui = u[i];
+#pragma unroll
+            for (int k = 0; k < KG; ++k)
+                if (g0 + k < nk) {
+                    const double v = V[(int64_t)(g0 + k) * ldv + i];
+                    aw[k] += v * wi;
+                    au[k] += v * ui;
+                }
+        }
+#pragma unroll
+        for (int k = 0; k < KG; ++k) {
+            red[k][t] = aw[k];
+            red[KG + k][t] = au[k];
+        }
+        __syncthreads();
+        for (int off = KT / 2; off > 0; off >>= 1) {
+            if (t < off)
+#pragma unroll
+                for (int k = 0; k < 2 * KG; ++k) red[k][t] += red[k][t + off];
+            __syncthreads();
+        }
+        if (t < KG && g0 + t < nk) {
+            partial[(int64_t)(g0 + t) * gridDim.x + blockIdx.x] = red[t][0];
+            partial[(int64_t)(nk + g0 + t) * gridDim.x + blockIdx.x] = red[KG + t][0];
+        }
+        __syncthreads();
+    }
+}
+
+// Gram correction of classical Gram-Schmidt: with a = V^T w and b = V^T V_j (the new Gram
+// column), store G[:, j] = G[j, :] = b and the twice-projected coefficients
+// h = a + (a - G a) in h (one block, nk = j + 1 <= ldg).
+__global__ __launch_bounds__(64) void gram_coeffs_k(int nk, const double *__restrict__ ab,
+                                                    double *__restrict__ G, int ldg,
+                                                    double *__restrict__ h)
+{
+    const int t = threadIdx.x;
+    const int j = nk - 1;
+    for (int k = t; k < nk; k += 64) {
+        G[(int64_t)k * ldg + j] = ab[nk + k];
+        G[(int64_t)j * ldg + k] = ab[nk + k];
+    }
+    __syncthreads();
+    for (int k = t; k < nk; k += 64) {
+        double ga = 0.0;
+        for (int m = 0; m < nk; ++m) ga += G[(int64_t)k * ldg + m] * ab[m];
+        h[k] = ab[k] + (ab[k] - ga);
+    }
+}
+
 // x[i] += sum_k y[k] Z[k][i]   (Z in the inner precision)
 template <typename TZ>
 __global__ __launch_bounds__(KT) void update_k(int64_t n, int nk, const TZ *__restrict__ Z, int64_t ldz,
@@ -249,6 +315,23 @@ int kry_axpy_dot(int64_t n, int nk, const double *V, int64_t ldv, const double *
         hipLaunchKernelGGL(sqrt_k, dim3(1), dim3(1), 0, st, out);
         FSI_LAUNCH_CHECK();
     }
+    return FSI_OK;
+}
+
+int kry_multidot2(int64_t n, int nk, const double *V, int64_t ldv, const double *w, const double *u,
+                  double *partial, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(multidot2_k, dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, w, u, partial);
+    FSI_LAUNCH_CHECK();
+    hipLaunchKernelGGL(reduce_partials_k, dim3(2 * nk), dim3(KT), 0, st, 2 * nk, KRY_NB, partial, out);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+
+int kry_gram_coeffs(int nk, const double *ab, double *G, int ldg, double *h, hipStream_t st)
+{
+    hipLaunchKernelGGL(gram_coeffs_k, dim3(1), dim3(64), 0, st, nk, ab, G, ldg, h);
+    FSI_LAUNCH_CHECK();
     return FSI_OK;
 }
 

@@ -20,6 +20,11 @@ int kry_multi_axpy(int64_t n, int nk, const double *V, int64_t ldv, const double
 // w -= V h (nk vectors); then out[k] = V[k] . w for k < nk_dot, or out[0] = ||w|| if nk_dot == 0
 int kry_axpy_dot(int64_t n, int nk, const double *V, int64_t ldv, const double *h, double *w, int nk_dot,
                  double *partial, double *out, hipStream_t st);
+// out[k] = V[k] . w, out[nk + k] = V[k] . u  (k < nk), one pass over V
+int kry_multidot2(int64_t n, int nk, const double *V, int64_t ldv, const double *w, const double *u,
+                  double *partial, double *out, hipStream_t st);
+// Gram column update and twice-projected coefficients (see krylov.hip)
+int kry_gram_coeffs(int nk, const double *ab, double *G, int ldg, double *h, hipStream_t st);
 int kry_update(int64_t n, int nk, fsi_dtype dz, const void *Z, int64_t ldz, const double *y, double *x,
                hipStream_t st);
 

@@ -61,6 +61,7 @@ def warmstart_c4(steps=200, train_end=100, epochs=20, lr=1e-3, eval_stride=1, se
                  save_path=None):
     cfg = W.CONFIGS["c4"]
     run = ChannelRun(cfg)
+    run.record_extrap = True
     t0 = time.perf_counter()
     for n in range(steps):
         rec = run.step()
@@ -69,15 +70,17 @@ def warmstart_c4(steps=200, train_end=100, epochs=20, lr=1e-3, eval_stride=1, se
                  f"krylov={rec.krylov_iters} {rec.ms_newton:.1f} ms")
     sim_s = time.perf_counter() - t0
     lw = LearnedWarmStart(run, seed=seed)
-    ks = list(range(2, train_end))
+    ks = list(range(1, train_end))
     lw.fit_normalisation(run.history, ks)
     lw.build_dataset(run.history, ks)
     _log(f"training on {len(ks)} samples, {lw.net.n_params} parameters")
     lw.train(epochs=epochs, lr=lr, seed=seed, log=_log)
     if save_path:
         sd = lw.net.state_dict()
-        sd["norm"] = dict(in_shift=lw.in_shift, in_scale=lw.in_scale, out_shift=lw.out_shift,
-                          out_scale=lw.out_scale)
+        sd["norm"] = dict(in_shift=[float(v) for v in lw.in_shift],
+                          in_scale=[float(v) for v in lw.in_scale],
+                          out_shift=[float(v) for v in lw.out_shift],
+                          out_scale=[float(v) for v in lw.out_scale])
         torch.save(sd, save_path)
     modes = ["plain_f64", "plain_mixed", "extrap_mixed", "nn_mixed"]
     rows = []

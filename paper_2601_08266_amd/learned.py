@@ -1,14 +1,17 @@
 """Learned warm start for the Newton iterations of ChannelRun (orchestration only).
 
-Sample k (predicting state k+1) uses 19 input channels: u, v, w, p of states
-k, k-1, k-2; B^T lambda of state k; B^T kappa g of the new step; the new inflow
-value.  The prediction is a correction to the second-order extrapolation
-2 x^k - x^{k-1}: the target is x^{k+1} - 2 x^k + x^{k-1} (4 channels), so a
-network that has learned nothing returns the extrapolation.  Channels are
-normalised with the training set's mean and standard deviation (computed by
-the library's moment kernel).  The guess is extrapolation + correction with the
-Dirichlet values imposed; the stepper keeps it only if its residual beats the
-plain guess.
+The guess is the second-order extrapolation x_ex = 2 x^n - x^{n-1} plus a learned
+correction: the network maps the residual of the extrapolation, R_ex = R(x_ex),
+together with the velocity field the step starts from and the interface band s,
+to the correction e = x^{n+1} - x_ex.  Near the solution e ~ J^{-1} R_ex, a linear
+map, so R_ex and e are both divided by ||R_ex|| per sample (the network then
+learns a fixed, scale-free local approximation of the inverse operator); the
+channels are further normalised with training-set statistics.  A network that
+has learned nothing returns the extrapolation; the stepper keeps the guess only
+if its residual beats the plain one.
+
+Inputs (8 channels): R_ex / ||R_ex|| (u, v, w, p rows), u, v, w of the previous
+state, s.  Target (4): e / ||R_ex||.
 """
 from __future__ import annotations
 
@@ -19,7 +22,6 @@ from typing import List, Optional
 import numpy as np
 import torch
 
-from . import axpby
 from . import warmstart as ws
 from .stepper import ChannelRun, StepRecord
 
@@ -29,10 +31,10 @@ class LearnedWarmStart:
         self.run = run
         self.N = run.N
         self.dims = run.g.nodes_per_axis
-        self.net = ws.WarmStartNet(self.dims, in_ch=ws.IN_CH, hidden=hidden, n_hidden=n_hidden,
+        self.net = ws.WarmStartNet(self.dims, in_ch=ws.IN_CH_RES, hidden=hidden, n_hidden=n_hidden,
                                    out_ch=ws.OUT_CH, seed=seed, device=run.dev)
-        self.in_shift = [0.0] * ws.IN_CH
-        self.in_scale = [1.0] * ws.IN_CH
+        self.in_shift = [0.0] * ws.IN_CH_RES
+        self.in_scale = [1.0] * ws.IN_CH_RES
         self.out_shift = [0.0] * 4
         self.out_scale = [1.0] * 4
         self.buf32 = torch.empty(self.N * 32, dtype=torch.float32, device=run.dev)
@@ -46,76 +48,68 @@ class LearnedWarmStart:
     def _field(self, t, f):
         return t[f * self.N:(f + 1) * self.N]
 
-    def input_sources(self, hist: List[StepRecord], k: int, lamg, inflow, normed=True):
+    def input_sources(self, R_ex, rn_ex, u_prev, s_field, normed=True):
         srcs = []
-        for lag in range(3):
-            st = hist[max(k - lag, 0)].x
-            for f in range(4):
-                srcs.append(([(1.0, self._field(st, f))], 0.0))
+        for f in range(4):
+            srcs.append(([(1.0 / rn_ex, self._field(R_ex, f))], 0.0))
         for f in range(3):
-            srcs.append(([(1.0, self._field(hist[k].btlam, f))], 0.0))
-        for f in range(3):
-            srcs.append(([(1.0, self._field(lamg, f))], 0.0))
-        srcs.append(([], float(inflow)))
+            srcs.append(([(1.0, self._field(u_prev, f))], 0.0))
+        srcs.append(([(1.0, s_field)], 0.0))
         out = []
         for c, (terms, cst) in enumerate(srcs):
             sh, sc = (self.in_shift[c], self.in_scale[c]) if normed else (0.0, 1.0)
             out.append((terms, cst, sh, sc))
         return out
 
-    def target_sources(self, hist, k, normed=True):
+    def target_sources(self, rec_next, normed=True):
         out = []
-        prev = hist[max(k - 1, 0)].x
         for f in range(4):
-            sh, sc = (self.out_shift[f], self.out_scale[f]) if normed else (0.0, 1.0)
-            terms = [(1.0, self._field(hist[k + 1].x, f)), (-2.0, self._field(hist[k].x, f)),
-                     (1.0, self._field(prev, f))]
-            out.append((terms, 0.0, sh, sc))
-        return out
-
-    def extrapolation(self, run: ChannelRun, out: torch.Tensor):
-        """out = 2 x^k - x^{k-1} (FP64 [4][N]) for the run's current state k."""
-        k = run.n
-        hist = run.history
-        axpby(2.0, hist[k].x, 0.0, out)
-        axpby(-1.0, hist[max(k - 1, 0)].x, 1.0, out)
+            sc = self.out_scale[f] if normed else 1.0
+            terms = [(1.0 / rec_next.rn_ex, self._field(rec_next.x, f)),
+                     (-1.0 / rec_next.rn_ex, self._field(rec_next.x_ex, f))]
+            out.append((terms, 0.0, 0.0, sc))
         return out
 
     # ---------------------------------------------------------------- data
+    def _samples(self, hist, ks):
+        return [hist[k + 1] for k in ks if hist[k + 1].x_ex is not None and hist[k + 1].rn_ex > 0]
+
     def fit_normalisation(self, hist, ks):
         N = self.N
-        sin = np.zeros((ws.IN_CH, 2))
+        sin = np.zeros((ws.IN_CH_RES, 2))
         sout = np.zeros((4, 2))
-        for k in ks:
-            ws.pack(N, 32, self.input_sources(hist, k, hist[k + 1].lamg, hist[k + 1].inflow, False),
-                    self.buf32)
-            m = ws.moments(N, 32, self.buf32)
-            sin += np.array(m[:ws.IN_CH])
-            ws.pack(N, 32, self.target_sources(hist, k, False), self.buf32)
-            m = ws.moments(N, 32, self.buf32)
-            sout += np.array(m[:4])
-        cnt = float(N * len(ks))
-
-        def ms(s):
-            mean = s[:, 0] / cnt
-            var = np.maximum(s[:, 1] / cnt - mean ** 2, 0.0)
-            std = np.sqrt(var)
-            return mean, np.where(std > 1e-12 * max(1.0, np.abs(mean).max()), std, 1.0)
-
-        mi, si = ms(sin)
-        mo, so = ms(sout)
-        self.in_shift, self.in_scale = list(mi), list(1.0 / si)
-        self.out_shift, self.out_scale = list(mo), list(1.0 / so)
+        recs = self._samples(hist, ks)
+        for r in recs:
+            ws.pack(N, 32, self.input_sources(r.R_ex, r.rn_ex, r.u_prev, r.s, False), self.buf32)
+            sin += np.array(ws.moments(N, 32, self.buf32)[:ws.IN_CH_RES])
+            ws.pack(N, 32, self.target_sources(r, False), self.buf32)
+            sout += np.array(ws.moments(N, 32, self.buf32)[:4])
+        cnt = float(N * len(recs))
+        mean = sin[:, 0] / cnt
+        rms = np.sqrt(np.maximum(sin[:, 1] / cnt, 0.0))
+        std = np.sqrt(np.maximum(sin[:, 1] / cnt - mean ** 2, 0.0))
+        shift, scale = np.zeros(ws.IN_CH_RES), np.ones(ws.IN_CH_RES)
+        # residual channels: scale only (keeps the map linear); fields: mean and std
+        for c in range(ws.IN_CH_RES):
+            if c < 4:
+                scale[c] = 1.0 / rms[c] if rms[c] > 0 else 1.0
+            else:
+                shift[c] = mean[c]
+                scale[c] = 1.0 / std[c] if std[c] > 1e-12 * max(1.0, abs(mean[c])) else 1.0
+        trms = np.sqrt(np.maximum(sout[:, 1] / cnt, 0.0))
+        self.in_shift, self.in_scale = list(shift), list(scale)
+        self.out_shift = [0.0] * 4
+        self.out_scale = list(np.where(trms > 0, 1.0 / trms, 1.0))
 
     def build_dataset(self, hist, ks):
         N = self.N
         self.X, self.T = [], []
-        for k in ks:
-            ws.pack(N, 32, self.input_sources(hist, k, hist[k + 1].lamg, hist[k + 1].inflow), self.buf32)
+        for r in self._samples(hist, ks):
+            ws.pack(N, 32, self.input_sources(r.R_ex, r.rn_ex, r.u_prev, r.s), self.buf32)
             xb = torch.empty(N * 32, dtype=torch.int16, device=self.run.dev)
             ws.to_bf16(self.buf32, xb)
             tt = torch.empty(N * 32, dtype=torch.float32, device=self.run.dev)
-            ws.pack(N, 32, self.target_sources(hist, k), tt)
+            ws.pack(N, 32, self.target_sources(r), tt)
             self.X.append(xb)
             self.T.append(tt)
 
@@ -137,23 +131,19 @@ class LearnedWarmStart:
         self.train_ms = (time.perf_counter() - t0) * 1e3
 
     # ---------------------------------------------------------------- inference
-    def guess(self, run: ChannelRun, lamg, inflow):
-        hist = run.history
-        k = run.n
+    def guess(self, run: ChannelRun, ctx):
+        if ctx["x_ex"] is None or not ctx["rn_ex"] > 0:
+            return None
         N = self.N
-        ws.pack(N, 32, self.input_sources(hist, k, lamg, inflow), self.buf32)
+        u_prev = run.history[run.n].x[: 3 * N]
+        ws.pack(N, 32, self.input_sources(ctx["R_ex"], ctx["rn_ex"], u_prev, ctx["s"]), self.buf32)
         ws.to_bf16(self.buf32, self.buf_bf)
         out = self.net.forward(self.buf_bf)
-        base = self.extrapolation(run, torch.empty(4 * N, dtype=torch.float64, device=run.dev))
         x = torch.empty(4 * N, dtype=torch.float64, device=run.dev)
-        ws.unpack(N, 32, out, base, self.out_shift, self.out_scale, x, mask=run.mask, gD=run.gD)
+        scale = [sc / ctx["rn_ex"] for sc in self.out_scale]
+        ws.unpack(N, 32, out, ctx["x_ex"], [0.0] * 4, scale, x, mask=run.mask, gD=run.gD)
         return x
 
-    def extrapolation_guess(self, run: ChannelRun, lamg, inflow):
-        """The network's backbone alone: 2 x^k - x^{k-1} with the Dirichlet values imposed."""
-        N = self.N
-        base = self.extrapolation(run, torch.empty(4 * N, dtype=torch.float64, device=run.dev))
-        x = torch.empty(4 * N, dtype=torch.float64, device=run.dev)
-        ws.unpack(N, 32, run.zero_out, base, [0, 0, 0, 0], [1, 1, 1, 1], x, mask=run.mask,
-                  gD=run.gD)
-        return x
+    def extrapolation_guess(self, run: ChannelRun, ctx):
+        """The network's backbone alone: 2 x^n - x^{n-1} with the Dirichlet values imposed."""
+        return ctx["x_ex"]

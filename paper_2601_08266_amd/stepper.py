@@ -46,6 +46,11 @@ class StepRecord:
     res_guess: float = 0.0
     used_guess: bool = False
     res_hist: tuple = ()
+    x_ex: Optional[torch.Tensor] = None     # extrapolated guess 2 x^{n-1} - x^{n-2} of this step
+    R_ex: Optional[torch.Tensor] = None     # its residual
+    rn_ex: float = 0.0
+    s: Optional[torch.Tensor] = None        # interface scaling field of this step
+    u_prev: Optional[torch.Tensor] = None   # velocity the step started from
 
 
 class ChannelRun:
@@ -74,6 +79,7 @@ class ChannelRun:
         self.x = torch.zeros(4 * self.N, dtype=torch.float64, device=self.dev)
         self.R = torch.empty_like(self.x)
         self.n = 0
+        self.record_extrap = False
         self.kappa = None
         self.history: List[StepRecord] = []
         self.newton_ws = None
@@ -121,7 +127,9 @@ class ChannelRun:
         return out
 
     def step(self, guess_fn: Optional[Callable] = None, inner=None, record=True):
-        """Advance one step.  guess_fn(run, lamg, inflow) -> FP64 [4][N] guess or None."""
+        """Advance one step.  guess_fn(run, ctx) -> FP64 [4][N] guess or None; ctx holds the
+        step's FP64 problem, lamg, the inflow value, s and the extrapolated guess with its
+        residual (x_ex, R_ex, rn_ex; None before two states exist)."""
         cfg = self.cfg
         n1 = self.n + 1
         t1 = n1 * cfg.dt
@@ -138,8 +146,19 @@ class ChannelRun:
         r_plain = self.residual_norm(P64, x_plain, lamg)
         tol = self.rel_tol * r_plain
         x0, r_guess, used = x_plain, r_plain, False
+        # second-order extrapolation 2 x^n - x^{n-1} and its residual (backbone of the learned guess)
+        ctx = {"P64": P64, "lamg": lamg, "inflow": inflow, "s": P64.s, "x_ex": None, "R_ex": None,
+               "rn_ex": 0.0}
+        if self.n >= 1 and (guess_fn is not None or self.record_extrap):
+            x_ex = torch.empty_like(self.x)
+            axpby(2.0, self.history[self.n].x, 0.0, x_ex)
+            axpby(-1.0, self.history[self.n - 1].x, 1.0, x_ex)
+            ws.unpack(self.N, 32, self.zero_out, x_ex.clone(), [0, 0, 0, 0], [1, 1, 1, 1], x_ex,
+                      mask=self.mask, gD=self.gD)
+            ctx["rn_ex"] = self.residual_norm(P64, x_ex, lamg)
+            ctx["x_ex"], ctx["R_ex"] = x_ex, self.R.clone()
         if guess_fn is not None:
-            xg = guess_fn(self, lamg, inflow)
+            xg = guess_fn(self, ctx)
             if xg is not None:
                 r_g = self.residual_norm(P64, xg, lamg)
                 if math.isfinite(r_g) and r_g < r_plain:
@@ -164,6 +183,10 @@ class ChannelRun:
         rec = StepRecord(n1, t1, x_new, self.btlam(tab64, gt, x_new) if record else None, lamg,
                          inflow, st.newton_iters, st.krylov_iters, ms, ms_guess, r_plain, r_guess, used,
                          tuple(st.res_hist[: min(st.newton_iters + 1, 32)]))
+        if record and self.record_extrap:
+            rec.x_ex, rec.R_ex, rec.rn_ex = ctx["x_ex"], ctx["R_ex"], ctx["rn_ex"]
+            rec.s = P64.s.clone()
+            rec.u_prev = self.history[self.n].x[: 3 * self.N].clone()
         self.x = x_new
         self.n = n1
         if record:
