@@ -121,6 +121,38 @@ def time_applies(fsi, torch, case, steps, warmup, profile):
     return ms, wall / steps * 1e3, kern
 
 
+def newton_step_probe(warm_steps=4, measure_steps=2):
+    """Short Newton-step comparison on the 64^3 rotating-plates channel: after a few plain steps,
+    the next steps are re-solved from the same state with plain FP64, mixed precision, and mixed
+    precision + extrapolated warm start; all stop at the same absolute residual."""
+    import torch
+
+    import fsi_workloads as W
+    from paper_2601_08266_amd.learned import LearnedWarmStart
+    from paper_2601_08266_amd import experiments as ex
+    from paper_2601_08266_amd.stepper import ChannelRun
+
+    run = ChannelRun(W.CONFIGS["c4"])
+    for _ in range(warm_steps):
+        run.step()
+    lw = LearnedWarmStart.__new__(LearnedWarmStart)   # only its extrapolation guess is used here
+    rows = []
+    for k in range(warm_steps, warm_steps + measure_steps):
+        run.x = run.history[k].x.clone()
+        run.n = k
+        rows.append(ex._solve_modes(run, lw, k, ["plain_f64", "plain_mixed", "extrap_mixed"]))
+        run.x = run.history[k].x.clone()
+        run.n = k
+        run.step()
+    out = {"workload": "64^3 Q1 channel, 200k rotating-plate points, steps "
+                       f"{warm_steps + 1}-{warm_steps + measure_steps}, tol 1e-8*||R(x_plain)||"}
+    for m in ["plain_f64", "plain_mixed", "extrap_mixed"]:
+        out[m + "_ms"] = round(sum(r[m]["ms_newton"] + r[m]["ms_guess"] for r in rows) / len(rows), 2)
+        out[m + "_krylov"] = round(sum(r[m]["krylov"] for r in rows) / len(rows), 1)
+    out["speedup_mixed_extrap_vs_plain_f64"] = round(out["plain_f64_ms"] / out["extrap_mixed_ms"], 3)
+    return out
+
+
 def cpu_baseline(cfg, case):
     """The FP64 oracle's Jacobian apply (dense element matrices, point-by-point DLM) on
     the full workload, once, on the host cores."""
@@ -157,6 +189,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-newton", action="store_true", help="skip the short Newton-step probe")
     ap.add_argument("--experiment", default=None, choices=["warmstart", "c5", "netspeed"],
                     help="run a Newton-step experiment instead of the apply benchmark")
     ap.add_argument("--exp-steps", type=int, default=200)
@@ -244,6 +277,8 @@ def main(argv=None):
             "n_occupied_cells": case64["tab"].n_occ,
         },
     }
+    if not args.no_newton and args.workload == "c2":
+        out["newton_step"] = newton_step_probe()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, case64)
     print(json.dumps(out))
