@@ -30,6 +30,27 @@ if ROOT not in sys.path:
 PEAK_FP64_VALU_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (fma) x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 
+# HBM traffic of vms_q1_cells<double> on the 64^3 workload from two rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads
+# for a plain 512 MiB device copy (FETCH_SIZE reads half the copied bytes, WRITE_SIZE all).
+# Valid only for the kernel sources it was taken on: the hash covers them.
+CELL_TRAFFIC = {"sources_sha256_16": "5b93270ddb8bc94b", "fetch_kib": 29039.7, "write_kib": 12960.0,
+                "fetch_scale": 524288.0 / 262159.6, "write_scale": 1.0}
+CELL_SOURCES = ("vms_q1.hip", "kernels.hpp", "common.hpp")
+
+
+def cell_traffic_bytes():
+    """Scaled FETCH+WRITE bytes per launch, or None if the kernel changed since the counters."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in CELL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2601_08266_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != CELL_TRAFFIC["sources_sha256_16"]:
+        return None
+    t = CELL_TRAFFIC
+    return round(1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
+
 
 def q1_cell_flops(has_s=True, visc_strong=True):
     """FP64/FP32 flops one vms_q1_cells lane spends on one Q1 cell (fma = 2, sqrt = div = 1).
@@ -121,7 +142,7 @@ def time_applies(fsi, torch, case, steps, warmup, profile):
     return ms, wall / steps * 1e3, kern
 
 
-def newton_step_probe(warm_steps=4, measure_steps=2):
+def newton_step_probe(warm_steps=60, measure_steps=3):
     """Short Newton-step comparison on the 64^3 rotating-plates channel: after a few plain steps,
     the next steps are re-solved from the same state with plain FP64, mixed precision, and mixed
     precision + extrapolated warm start; all stop at the same absolute residual."""
@@ -261,7 +282,7 @@ def main(argv=None):
             "bound": "alu", "kernel": "vms_q1_cells<double>",
             "achieved": round(achieved_tf, 3), "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved_tf / PEAK_FP64_VALU_TFLOPS, 4),
-            "traffic": None,
+            "traffic": cell_traffic_bytes(), "traffic_unit": "bytes/launch",
             "flops_per_launch": flops, "kernel_ms_avg": round(cell_ms, 6),
             "launches": launches,
             "hbm_algorithmic_GBs": round(hbm_gbs, 1),
