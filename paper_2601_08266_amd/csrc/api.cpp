@@ -70,6 +70,8 @@ VmsConst<T> make_vms_const(const Geo &g, const fsi_vms_params &prm, bool has_s)
     k.K1 = (T)(prm.C_T / (prm.dt * prm.dt) + prm.C_I * prm.nu * prm.nu * GG);
     k.inv_trG = (T)(1.0 / trG);
     k.detJ = (T)(g.h[0] * g.h[1] * g.h[2]);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) k.nu_hh[i][j] = (T)(prm.nu / (g.h[i] * g.h[j]));
     k.visc_strong = prm.visc_strong ? 1 : 0;
     k.has_s = has_s ? 1 : 0;
     return k;
@@ -94,8 +96,8 @@ BrickLayout brick_layout(const Geo &g)
 
 size_t vms_workspace_bytes(const Geo &g, fsi_dtype dt)
 {
-    const BrickLayout b = brick_layout(g);
-    return align_up((size_t)b.nb * 4 * b.nl * (dt == FSI_F64 ? 8 : 4));
+    // brick partial sums: one grid-shaped [4][N] array per brick parity class (8)
+    return align_up((size_t)8 * 4 * (size_t)g.N * (dt == FSI_F64 ? 8 : 4));
 }
 
 template <typename T>

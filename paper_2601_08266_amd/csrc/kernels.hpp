@@ -13,6 +13,7 @@ struct VmsConst {
     T ih2[3];          // 1/h^2
     T inv_trG;         // 1/tr G
     T detJ;            // hx hy hz
+    T nu_hh[3][3];     // nu / (h_i h_k): viscous fluxes from reference-cell derivatives
     int32_t visc_strong;
     int32_t has_s;
 };
@@ -21,7 +22,9 @@ template <typename T>
 VmsConst<T> make_vms_const(const Geo &g, const fsi_vms_params &prm, bool has_s);
 
 // ---- Q1 operator: brick partials + node gather ----
+// one workgroup (4 wavefronts) per brick of 8x8x4 cells (one cell per lane)
 constexpr int Q1_BX = 8, Q1_BY = 8, Q1_BZ = 4;
+constexpr int Q1_NT = Q1_BX * Q1_BY * Q1_BZ;
 constexpr int Q1_NL = (Q1_BX + 1) * (Q1_BY + 1) * (Q1_BZ + 1);
 
 // ---- Q2 operator ----

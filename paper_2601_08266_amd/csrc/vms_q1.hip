@@ -2,20 +2,30 @@
 // form + residual-based SUPG/PSPG/LSIC with the paper's tau_m, tau_c, G).
 //
 // Design
-//  * One workgroup = a brick of 8x8x4 cells, one cell per lane (4 waves).
-//  * Per cell, each nodal field is turned into the 8 coefficients of its
-//    trilinear monomial expansion c_m xi^a eta^b zeta^c (three rounds of
-//    differences); values and derivatives at the 2x2x2 Gauss points are
-//    then short polynomials in compile-time constants.
-//  * The test side accumulates the same 8 monomial moments per output field
-//    and maps them back to the 8 nodes with the transposed difference rounds.
-//  * Element -> node accumulation inside the brick goes through LDS in 8
-//    ordered passes (one per cell corner: no two lanes hit the same node in a
-//    pass), so the result is deterministic without atomics.  Brick-face
-//    nodes are completed by a second, node-parallel gather kernel that sums
-//    the partials of the (up to 8) bricks holding each node in a fixed order,
-//    adds the DLM corner sums of occupied neighbour cells if requested, and
-//    applies the Dirichlet rows.
+//  * One workgroup = a brick of 8x8x4 cells, one cell per lane (4 waves).  Bricks
+//    are dealt to the XCDs in contiguous ranges so neighbouring bricks share L2.
+//  * The brick's 9x9x5 nodes of every field (x, a or f, s) are staged in LDS
+//    with one batch of buffer loads (two nodes per lane per field); the
+//    Dirichlet mask is applied while staging.
+//  * Per cell, the velocity/pressure fields are turned into the 8 coefficients
+//    of their trilinear monomial expansion (three rounds of differences).
+//  * Phase 1 evaluates what depends only on the advection field and s at the 8
+//    Gauss points (a/h, tau_m, tau_c) by one interpolation pass per axis into a
+//    per-lane LDS table.  Phase 2 walks the points in x-pairs (not unrolled: the
+//    live set is the coefficients and the moment accumulators, which keeps FP64
+//    at two waves per SIMD); along a pair a field is E + x O with O its
+//    x-derivative.  Derivatives stay on the reference cell, the 1/h factors sit
+//    in the table and the constants, and the equal Gauss weight is applied once
+//    at the end.
+//  * The test side accumulates 8 monomial moments per output field and maps
+//    them back to the 8 nodes with the transposed difference rounds.
+//  * Element -> node accumulation: each lane parks its 32 nodal outputs in LDS
+//    and each brick node sums the corners of its (up to 8) cells in a fixed
+//    order, so the result is deterministic without atomics.  Bricks of one
+//    parity class (bx, by, bz mod 2) share no node, so each class writes a
+//    grid-shaped partial array; a node-parallel gather kernel sums the classes
+//    holding each node in a fixed order, adds the DLM corner sums of occupied
+//    neighbour cells if requested, and applies the Dirichlet rows.
 #include "kernels.hpp"
 #include "profile.hpp"
 
@@ -34,6 +44,15 @@ __device__ __forceinline__ void to_monomial(T v[8])
     v[1] -= v[0]; v[3] -= v[2]; v[5] -= v[4]; v[7] -= v[6];
     v[2] -= v[0]; v[3] -= v[1]; v[6] -= v[4]; v[7] -= v[5];
     v[4] -= v[0]; v[5] -= v[1]; v[6] -= v[2]; v[7] -= v[3];
+}
+
+// inverse of to_monomial
+template <typename T>
+__device__ __forceinline__ void from_monomial(T v[8])
+{
+    v[4] += v[0]; v[5] += v[1]; v[6] += v[2]; v[7] += v[3];
+    v[2] += v[0]; v[3] += v[1]; v[6] += v[4]; v[7] += v[5];
+    v[1] += v[0]; v[3] += v[2]; v[5] += v[4]; v[7] += v[6];
 }
 
 // transpose of to_monomial: monomial moments -> nodal values
@@ -95,147 +114,300 @@ __device__ __forceinline__ void moments(T m[8], T F0, T G0, T G1, T G2, const QP
     m[7] += F0 * q.xyz + G0 * q.yz + G1 * q.xz + G2 * q.xy;
 }
 
-// Full element computation for one Q1 cell: in[f][A] nodal x (masked), a, s; out[f][A].
-// If dlm != nullptr, the cell's 8x8 block of B^T diag(kappa) B is applied to the
-// velocity and added to the momentum outputs.
-// RESID = true: nonlinear residual of a time step instead of the linear apply: the
-// advection field is the velocity itself (a = u) and ca holds the nodal source
-// f = c_m u_old + body force, whose Galerkin/SUPG/PSPG weighting is subtracted.
+// Buffer loads: one resource per field and block (base = the brick's first node), the
+// lane's node offset in a VGPR and the cell-corner offset, uniform, in an SGPR.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t field_rsrc(const void *base, int64_t bytes)
+{
+    const int32_t n = bytes > (int64_t)0x7fffffff ? 0x7fffffff : (int32_t)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, n, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+// 1/sqrt(x) for x > 0: hardware estimate refined by Newton steps y <- y + y (1 - x y^2) / 2
+// (two in FP64, one in FP32: both end within a few ulp of the correctly rounded value).
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double e = fma(-(x * y), y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+__device__ __forceinline__ float rsqrt_nr(float x)
+{
+    float y = __builtin_amdgcn_rsqf(x);
+    const float e = fmaf(-(x * y), y, 1.0f);
+    return fmaf(0.5f * y, e, y);
+}
+
+// Values at the 8 Gauss points (index ix + 2 iy + 4 iz) of a trilinear field given by its
+// nodal values (index a + 2 b + 4 c): one linear-interpolation pass per axis.
+template <typename T>
+__device__ __forceinline__ void gauss_values(const T v[8], T q[8])
+{
+#pragma unroll
+    for (int i = 0; i < 8; ++i) q[i] = v[i];
+#pragma unroll
+    for (int st = 1; st < 8; st <<= 1) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (i & st) continue;
+            const T v0 = q[i], d = q[i + st] - v0;
+            q[i] = v0 + T(GQ0) * d;
+            q[i + st] = v0 + T(GQ1) * d;
+        }
+    }
+}
+
+// Per-Gauss-point quantities that depend only on the advection field and s, computed
+// before the element loop and kept in LDS (slot j of point q at lq[(5 q + j) * Q1_NT]).
+// Apply: the advection velocity scaled by 1/h (a_k / h_k); residual: the source f.
+// Then tau_m and tau_c.
+constexpr int Q1_NQV = 5;
+
+// Phase 1.  cu: nodal x (Dirichlet-masked in apply mode), turned into monomial form in
+// place; ca: nodal advection field (apply) or source (residual); cs: nodal s.
+// tau_m = (s (C_T/dt^2 + a.Ga + C_I nu^2 G:G))^{-1/2},  tau_c = (tau_m tr G)^{-1}.
 template <typename T, bool RESID>
-__device__ __forceinline__ void q1_cell(const VmsConst<T> &k, T cu[4][8], T ca[3][8], T cs[8],
-                                        T smin, const T *__restrict__ dlm, T out[4][8])
+__device__ __forceinline__ void q1_point_table(const VmsConst<T> &k, T cu[4][8], T ca[3][8], T cs[8],
+                                               T *lq)
+{
+    T Sq[8];
+    if (k.has_s) {
+        T smin = cs[0];
+#pragma unroll
+        for (int A = 1; A < 8; ++A) smin = cs[A] < smin ? cs[A] : smin;
+        gauss_values(cs, Sq);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Sq[q] = Sq[q] < smin ? smin : Sq[q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Sq[q] = T(1);
+    }
+    // a.G a at the points (advection by the velocity itself in the residual)
+    T aGa[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) aGa[q] = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        T vq[8], aq[8];
+        gauss_values(ca[d], vq);
+        if constexpr (RESID) {
+            gauss_values(cu[d], aq);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) lq[(Q1_NQV * q + d) * Q1_NT] = vq[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                aq[q] = vq[q] * k.ih[d];
+                lq[(Q1_NQV * q + d) * Q1_NT] = aq[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const T ah = RESID ? aq[q] * k.ih[d] : aq[q];
+            aGa[q] += ah * ah;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const T tb = Sq[q] * (k.K1 + aGa[q]);
+        const T tau_m = rsqrt_nr(tb);
+        lq[(Q1_NQV * q + 3) * Q1_NT] = tau_m;
+        lq[(Q1_NQV * q + 4) * Q1_NT] = (tb * tau_m) * k.inv_trG;
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) to_monomial(cu[f]);
+}
+
+// Gauss point coordinates on [0,1]^3 and their products, point q = ix + 2 iy + 4 iz
+template <typename T>
+struct Q1Points {
+    T v[8][8];   // x, y, z, xy, xz, yz, xyz, 0
+};
+#define FSI_QP_ROW(q)                                                                              \
+    {(q & 1) ? GQ1 : GQ0, (q & 2) ? GQ1 : GQ0, (q & 4) ? GQ1 : GQ0,                               \
+     ((q & 1) ? GQ1 : GQ0) * ((q & 2) ? GQ1 : GQ0), ((q & 1) ? GQ1 : GQ0) * ((q & 4) ? GQ1 : GQ0), \
+     ((q & 2) ? GQ1 : GQ0) * ((q & 4) ? GQ1 : GQ0),                                              \
+     ((q & 1) ? GQ1 : GQ0) * ((q & 2) ? GQ1 : GQ0) * ((q & 4) ? GQ1 : GQ0), 0.0}
+__constant__ Q1Points<double> q1_points_f64 = {{FSI_QP_ROW(0), FSI_QP_ROW(1), FSI_QP_ROW(2),
+                                                FSI_QP_ROW(3), FSI_QP_ROW(4), FSI_QP_ROW(5),
+                                                FSI_QP_ROW(6), FSI_QP_ROW(7)}};
+#undef FSI_QP_ROW
+#define FSI_QP_ROW(q)                                                                              \
+    {(float)((q & 1) ? GQ1 : GQ0), (float)((q & 2) ? GQ1 : GQ0), (float)((q & 4) ? GQ1 : GQ0),    \
+     (float)(((q & 1) ? GQ1 : GQ0) * ((q & 2) ? GQ1 : GQ0)),                                      \
+     (float)(((q & 1) ? GQ1 : GQ0) * ((q & 4) ? GQ1 : GQ0)),                                      \
+     (float)(((q & 2) ? GQ1 : GQ0) * ((q & 4) ? GQ1 : GQ0)),                                      \
+     (float)(((q & 1) ? GQ1 : GQ0) * ((q & 2) ? GQ1 : GQ0) * ((q & 4) ? GQ1 : GQ0)), 0.0f}
+__constant__ Q1Points<float> q1_points_f32 = {{FSI_QP_ROW(0), FSI_QP_ROW(1), FSI_QP_ROW(2),
+                                               FSI_QP_ROW(3), FSI_QP_ROW(4), FSI_QP_ROW(5),
+                                               FSI_QP_ROW(6), FSI_QP_ROW(7)}};
+#undef FSI_QP_ROW
+template <typename T>
+__device__ __forceinline__ QP<T> q1_point(int q)
+{
+    const T *r;
+    if constexpr (sizeof(T) == 8)
+        r = q1_points_f64.v[q];
+    else
+        r = q1_points_f32.v[q];
+    QP<T> o;
+    o.x = r[0]; o.y = r[1]; o.z = r[2]; o.xy = r[3]; o.xz = r[4]; o.yz = r[5]; o.xyz = r[6];
+    return o;
+}
+
+// Phase 2: Galerkin + SUPG/PSPG/LSIC weighting at the 8 Gauss points from the monomial
+// coefficients cu and the point table lq; output out[f][A] (nodal).  Derivatives are
+// taken on the reference cell and the 1/h factors folded into the table and the
+// constants.  The points are visited in x-pairs sharing (y, z): a field's value along the
+// pair is E + x O with O its x-derivative, so E and O are formed once per pair.
+// If dlm != nullptr, the cell's 8x8 block of B^T diag(kappa) B is applied to the nodal
+// velocity and added to the momentum rows.  RESID = true: nonlinear residual of a time
+// step instead of the linear apply: the advection field is the velocity itself (a = u)
+// and the table holds the source f = c_m u_old + body force, whose Galerkin/SUPG/PSPG
+// weighting is subtracted.
+template <typename T, bool RESID>
+__device__ __forceinline__ void q1_cell(const VmsConst<T> &k, T cu[4][8], const T *lq,
+                                        const T *__restrict__ dlm, T out[4][8])
 {
     T mom[4][8];
 #pragma unroll
     for (int f = 0; f < 4; ++f)
 #pragma unroll
         for (int i = 0; i < 8; ++i) mom[f][i] = T(0);
-    if (dlm != nullptr) {
-        // DLM block on the nodal (Dirichlet-masked) velocity, carried in moment form
+
+#pragma unroll 1
+    for (int pr = 0; pr < 4; ++pr) {
+        const QP<T> q0 = q1_point<T>(2 * pr);
+        T E[4], O[4];
 #pragma unroll
-        for (int A = 0; A < 8; ++A) {
-            T r0 = T(0), r1 = T(0), r2 = T(0);
-#pragma unroll
-            for (int C = 0; C < 8; ++C) {
-                const T gAC = dlm[A * 8 + C];
-                r0 += gAC * cu[0][C];
-                r1 += gAC * cu[1][C];
-                r2 += gAC * cu[2][C];
-            }
-            mom[0][A] = r0;
-            mom[1][A] = r1;
-            mom[2][A] = r2;
+        for (int f = 0; f < 4; ++f) {
+            const T *c = cu[f];
+            E[f] = c[0] + c[2] * q0.y + c[4] * q0.z + c[6] * q0.yz;
+            O[f] = c[1] + c[3] * q0.y + c[5] * q0.z + c[7] * q0.yz;
         }
 #pragma unroll
-        for (int f = 0; f < 3; ++f) to_moments(mom[f]);
-    }
-#pragma unroll
-    for (int f = 0; f < 4; ++f) to_monomial(cu[f]);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) to_monomial(ca[d]);
-    if (k.has_s) to_monomial(cs);
+        for (int ix = 0; ix < 2; ++ix) {
+            const int qi = 2 * pr + ix;
+            const QP<T> q = q1_point<T>(qi);
+            const T *lp = lq + Q1_NQV * qi * Q1_NT;
+            T Ah[3] = {lp[0], lp[Q1_NT], lp[2 * Q1_NT]};
+            const T tau_m = lp[3 * Q1_NT], tau_c = lp[4 * Q1_NT];
 
+            // values and reference derivatives (d/dxi_k)
+            T U[3], dU[3][3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                U[i] = E[i] + q.x * O[i];
+                dU[i][0] = O[i];
+                dU[i][1] = mdy(cu[i], q);
+                dU[i][2] = mdz(cu[i], q);
+            }
+            const T P = E[3] + q.x * O[3];
+            const T dP[3] = {O[3], mdy(cu[3], q), mdz(cu[3], q)};
+            T Fs[3] = {T(0), T(0), T(0)};
+            if constexpr (RESID) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    Fs[d] = Ah[d];
+                    Ah[d] = U[d] * k.ih[d];
+                }
+            }
+            const T div = dU[0][0] * k.ih[0] + dU[1][1] * k.ih[1] + dU[2][2] * k.ih[2];
+            // nu grad(div u) for trilinear fields on Cartesian cells (only mixed second
+            // derivatives survive)
+            T ngd[3] = {T(0), T(0), T(0)};
+            if (k.visc_strong) {
+                const T u1xy = (cu[1][3] + cu[1][7] * q.z) * k.nu_hh[0][1];
+                const T u2xz = (cu[2][5] + cu[2][7] * q.y) * k.nu_hh[0][2];
+                const T u0xy = (cu[0][3] + cu[0][7] * q.z) * k.nu_hh[0][1];
+                const T u2yz = (cu[2][6] + cu[2][7] * q.x) * k.nu_hh[1][2];
+                const T u0xz = (cu[0][5] + cu[0][7] * q.y) * k.nu_hh[0][2];
+                const T u1yz = (cu[1][6] + cu[1][7] * q.x) * k.nu_hh[1][2];
+                ngd[0] = u1xy + u2xz;
+                ngd[1] = u0xy + u2yz;
+                ngd[2] = u0xz + u1yz;
+            }
+            T tr[3], F0[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                T gm = k.c_m * U[i] + (Ah[0] * dU[i][0] + Ah[1] * dU[i][1] + Ah[2] * dU[i][2]);
+                if constexpr (RESID) gm -= Fs[i];
+                F0[i] = gm;
+                const T r = (gm + dP[i] * k.ih[i]) - ngd[i];
+                tr[i] = tau_m * r;
+            }
+            const T diag = tau_c * div - P;
+            // test-side fluxes, already multiplied by 1/h_k:
+            //   nu (d_k u_i + d_i u_k) + a_k tau_m r_i + delta_ik (tau_c div u - p)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                T G[3];
+#pragma unroll
+                for (int kk = 0; kk < 3; ++kk) {
+                    T fl;
+                    if (kk == i)
+                        fl = T(2) * k.nu_hh[i][i] * dU[i][i] + diag * k.ih[i];
+                    else
+                        fl = k.nu_hh[kk][kk] * dU[i][kk] + k.nu_hh[kk][i] * dU[kk][i];
+                    G[kk] = fl + Ah[kk] * tr[i];
+                }
+                moments(mom[i], F0[i], G[0], G[1], G[2], q);
+            }
+            moments(mom[3], div, tr[0] * k.ih[0], tr[1] * k.ih[1], tr[2] * k.ih[2], q);
+        }
+    }
     const T W = k.detJ * T(0.125);
-    const T Wh0 = W * k.ih[0], Wh1 = W * k.ih[1], Wh2 = W * k.ih[2];
-    const T h01 = k.ih[0] * k.ih[1], h02 = k.ih[0] * k.ih[2], h12 = k.ih[1] * k.ih[2];
-
-#pragma unroll
-    for (int qi = 0; qi < 8; ++qi) {
-        QP<T> q;
-        q.x = (qi & 1) ? T(GQ1) : T(GQ0);
-        q.y = (qi & 2) ? T(GQ1) : T(GQ0);
-        q.z = (qi & 4) ? T(GQ1) : T(GQ0);
-        q.xy = q.x * q.y;
-        q.xz = q.x * q.z;
-        q.yz = q.y * q.z;
-        q.xyz = q.xy * q.z;
-
-        T U[3], dU[3][3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            U[i] = mval(cu[i], q);
-            dU[i][0] = mdx(cu[i], q) * k.ih[0];
-            dU[i][1] = mdy(cu[i], q) * k.ih[1];
-            dU[i][2] = mdz(cu[i], q) * k.ih[2];
-        }
-        const T P = mval(cu[3], q);
-        const T dP0 = mdx(cu[3], q) * k.ih[0];
-        const T dP1 = mdy(cu[3], q) * k.ih[1];
-        const T dP2 = mdz(cu[3], q) * k.ih[2];
-        T A0, A1, A2, Fs[3] = {T(0), T(0), T(0)};
-        if constexpr (RESID) {
-            A0 = U[0];
-            A1 = U[1];
-            A2 = U[2];
-            Fs[0] = mval(ca[0], q);
-            Fs[1] = mval(ca[1], q);
-            Fs[2] = mval(ca[2], q);
-        } else {
-            A0 = mval(ca[0], q);
-            A1 = mval(ca[1], q);
-            A2 = mval(ca[2], q);
-        }
-        T S = T(1);
-        if (k.has_s) {
-            S = mval(cs, q);
-            S = S < smin ? smin : S;
-        }
-        // tau_m = (s (C_T/dt^2 + a.Ga + C_I nu^2 G:G))^{-1/2},  tau_c = (tau_m tr G)^{-1}
-        const T tb = S * (k.K1 + A0 * A0 * k.ih2[0] + A1 * A1 * k.ih2[1] + A2 * A2 * k.ih2[2]);
-        const T sq = sqrt(tb);
-        const T tau_m = T(1) / sq;
-        const T tau_c = sq * k.inv_trG;
-
-        const T div = dU[0][0] + dU[1][1] + dU[2][2];
-        // grad(div u) for trilinear fields on Cartesian cells (pure second derivatives vanish)
-        T gd[3] = {T(0), T(0), T(0)};
-        if (k.visc_strong) {
-            const T u1xy = (cu[1][3] + cu[1][7] * q.z) * h01;
-            const T u2xz = (cu[2][5] + cu[2][7] * q.y) * h02;
-            const T u0xy = (cu[0][3] + cu[0][7] * q.z) * h01;
-            const T u2yz = (cu[2][6] + cu[2][7] * q.x) * h12;
-            const T u0xz = (cu[0][5] + cu[0][7] * q.y) * h02;
-            const T u1yz = (cu[1][6] + cu[1][7] * q.x) * h12;
-            gd[0] = u1xy + u2xz;
-            gd[1] = u0xy + u2yz;
-            gd[2] = u0xz + u1yz;
-        }
-        const T dP[3] = {dP0, dP1, dP2};
-        const T Aq[3] = {A0, A1, A2};
-        T tr[3];
-        T F0[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            T g = k.c_m * U[i] + (A0 * dU[i][0] + A1 * dU[i][1] + A2 * dU[i][2]);
-            if constexpr (RESID) g -= Fs[i];
-            F0[i] = g;
-            const T r = g + dP[i] - k.nu * gd[i];
-            tr[i] = tau_m * r;
-        }
-        const T diag = tau_c * div - P;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            T G[3];
-#pragma unroll
-            for (int kk = 0; kk < 3; ++kk) {
-                T fl = k.nu * (dU[i][kk] + dU[kk][i]) + Aq[kk] * tr[i];
-                if (kk == i) fl += diag;
-                G[kk] = fl;
-            }
-            moments(mom[i], W * F0[i], Wh0 * G[0], Wh1 * G[1], Wh2 * G[2], q);
-        }
-        moments(mom[3], W * div, Wh0 * tr[0], Wh1 * tr[1], Wh2 * tr[2], q);
-    }
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) mom[f][i] *= W;
         from_moments(mom[f]);
 #pragma unroll
         for (int i = 0; i < 8; ++i) out[f][i] = mom[f][i];
     }
+    if (dlm != nullptr) {
+        // DLM block on the nodal (Dirichlet-masked) velocity
+#pragma unroll
+        for (int f = 0; f < 3; ++f) from_monomial(cu[f]);
+#pragma unroll
+        for (int A = 0; A < 8; ++A) {
+#pragma unroll
+            for (int C = 0; C < 8; ++C) {
+                const T gAC = dlm[A * 8 + C];
+                out[0][A] += gAC * cu[0][C];
+                out[1][A] += gAC * cu[1][C];
+                out[2][A] += gAC * cu[2][C];
+            }
+        }
+    }
+}
+
+// Brick handled by block bid.  Blocks are dealt to the 8 XCDs round-robin; each XCD is
+// given a contiguous range of bricks (x fastest), so bricks that share face nodes (and
+// the cache lines holding them) mostly run under the same L2.
+__device__ __forceinline__ int64_t xcd_brick(int64_t bid, int64_t nb)
+{
+    const int64_t q = nb / 8, r = nb % 8, xcd = bid % 8, idx = bid / 8;
+    return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
 template <typename T, bool RESID>
-__global__ __launch_bounds__(256) void vms_q1_cells(Geo g, VmsConst<T> k, const T *__restrict__ x,
+__global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, const T *__restrict__ x,
                                                     const T *__restrict__ a,
                                                     const T *__restrict__ s,
                                                     const uint32_t *__restrict__ mask,
@@ -243,70 +415,139 @@ __global__ __launch_bounds__(256) void vms_q1_cells(Geo g, VmsConst<T> k, const 
                                                     const int32_t *__restrict__ occ_index,
                                                     T *__restrict__ part, int nbx, int nby)
 {
-    __shared__ T acc[4 * Q1_NL];
+    // LDS, one region used three ways: the brick's nodal fields (staged with coalesced
+    // loads), then the lanes' Gauss-point tables, then the lanes' nodal outputs.
+    constexpr int NF = 8;   // x (4), a or f (3), s
+    constexpr int NJ = (Q1_NL + Q1_NT - 1) / Q1_NT;   // staged nodes per lane
+    static_assert(8 * Q1_NQV >= 32 && 8 * Q1_NQV * Q1_NT >= NF * Q1_NL, "LDS too small");
+    __shared__ T lds[8 * Q1_NQV * Q1_NT];
     const int t = threadIdx.x;
-    const int64_t bid = blockIdx.x;
+    const int64_t bid = xcd_brick(blockIdx.x, gridDim.x);
     const int bx = (int)(bid % nbx), by = (int)((bid / nbx) % nby), bz = (int)(bid / ((int64_t)nbx * nby));
-    const int tx = t & 7, ty = (t >> 3) & 7, tz = t >> 6;
+    const int tx = t % Q1_BX, ty = (t / Q1_BX) % Q1_BY, tz = t / (Q1_BX * Q1_BY);
     const int cx = bx * Q1_BX + tx, cy = by * Q1_BY + ty, cz = bz * Q1_BZ + tz;
     const bool valid = cx < g.n[0] && cy < g.n[1] && cz < g.n[2];
-    for (int i = t; i < 4 * Q1_NL; i += 256) acc[i] = T(0);
+    const int64_t N = g.N;
+    const int64_t nn01 = (int64_t)g.nn[0] * g.nn[1];
+    constexpr int LX = Q1_BX + 1, LY = Q1_BY + 1;
 
-    T out[4][8];
+    // stage the brick's (LX x LY x (BZ+1)) nodes of every field: 2 nodes per lane
+    {
+        const int64_t base = (int64_t)bx * Q1_BX + (int64_t)g.nn[0] * (by * Q1_BY) + nn01 * (bz * Q1_BZ);
+        const int64_t rem = (N - base) * (int64_t)sizeof(T);
+        uint32_t voff[NJ];
+        bool inb[NJ];
+        int64_t node[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int l = t + Q1_NT * j;
+            const int lx = l % LX, ly = (l / LX) % LY, lz = l / (LX * LY);
+            inb[j] = l < Q1_NL && bx * Q1_BX + lx < g.nn[0] && by * Q1_BY + ly < g.nn[1] &&
+                     bz * Q1_BZ + lz < g.nn[2];
+            const int64_t o = lx + (int64_t)g.nn[0] * ly + nn01 * lz;
+            voff[j] = (uint32_t)(o * (int64_t)sizeof(T));
+            node[j] = base + o;
+        }
+        // all loads first (one batch in flight; the buffer range check makes the ones past
+        // the grid harmless), then the Dirichlet mask, then the LDS stores
+        T v[NF][NJ];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if (f == 7 && !k.has_s) {
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) v[f][j] = T(1);
+                continue;
+            }
+            const T *src = f < 4 ? x + f * N : (f < 7 ? a + (f - 4) * N : s);
+            const __amdgpu_buffer_rsrc_t r = field_rsrc(src + base, rem);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) v[f][j] = buf_load<T>(r, voff[j], 0u);
+        }
+        if (!RESID && mask != nullptr) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+                    if (inb[j] && mask_bit(mask, f * N + node[j])) v[f][j] = T(0);
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+                if (t + Q1_NT * j < Q1_NL) lds[f * Q1_NL + t + Q1_NT * j] = inb[j] ? v[f][j] : T(0);
+    }
+    __syncthreads();
+
+    T cu[4][8];
+    T ca[3][8], cs[8];
     if (valid) {
-        T cu[4][8], ca[3][8], cs[8];
-        T smin = T(1);
-        const int64_t N = g.N;
 #pragma unroll
         for (int A = 0; A < 8; ++A) {
-            const int64_t node = (int64_t)(cx + (A & 1)) +
-                                 (int64_t)g.nn[0] * ((cy + ((A >> 1) & 1)) + (int64_t)g.nn[1] * (cz + (A >> 2)));
+            const int l = (tx + (A & 1)) + LX * ((ty + ((A >> 1) & 1)) + LY * (tz + (A >> 2)));
 #pragma unroll
-            for (int f = 0; f < 3; ++f) {
-                T v = x[f * N + node];
-                if (!RESID && mask_bit(mask, f * N + node)) v = T(0);
-                cu[f][A] = v;
-                ca[f][A] = a[f * N + node];
-            }
-            cu[3][A] = x[3 * N + node];
-            cs[A] = k.has_s ? s[node] : T(1);
-        }
-        if (k.has_s) {
-            smin = cs[0];
+            for (int f = 0; f < 4; ++f) cu[f][A] = lds[f * Q1_NL + l];
 #pragma unroll
-            for (int A = 1; A < 8; ++A) smin = cs[A] < smin ? cs[A] : smin;
+            for (int d = 0; d < 3; ++d) ca[d][A] = lds[(4 + d) * Q1_NL + l];
+            cs[A] = k.has_s ? lds[7 * Q1_NL + l] : T(1);
         }
+    }
+    __syncthreads();
+    T out[4][8];
+    if (valid) {
+        q1_point_table<T, RESID>(k, cu, ca, cs, lds + t);
         const T *dlm = nullptr;
         if (gram != nullptr) {
             const int32_t ko = occ_index[cx + (int64_t)g.n[0] * (cy + (int64_t)g.n[1] * cz)];
             if (ko >= 0) dlm = gram + (int64_t)ko * 64;
         }
-        q1_cell<T, RESID>(k, cu, ca, cs, smin, dlm, out);
+        q1_cell<T, RESID>(k, cu, lds + t, dlm, out);
     }
+    // element -> node accumulation: every lane parks its 32 nodal outputs in LDS, then each
+    // brick node sums the corners of the (up to 8) cells around it in a fixed order
     __syncthreads();
 #pragma unroll
-    for (int A = 0; A < 8; ++A) {
-        if (valid) {
-            const int l = (tx + (A & 1)) + (Q1_BX + 1) * ((ty + ((A >> 1) & 1)) + (Q1_BY + 1) * (tz + (A >> 2)));
+    for (int f = 0; f < 4; ++f)
 #pragma unroll
-            for (int f = 0; f < 4; ++f) acc[f * Q1_NL + l] += out[f][A];
-        }
-        __syncthreads();
-    }
-    for (int l = t; l < Q1_NL; l += 256) {
-        const int lx = l % (Q1_BX + 1), ly = (l / (Q1_BX + 1)) % (Q1_BY + 1), lz = l / ((Q1_BX + 1) * (Q1_BY + 1));
+        for (int A = 0; A < 8; ++A) lds[(f * 8 + A) * Q1_NT + t] = valid ? out[f][A] : T(0);
+    __syncthreads();
+    for (int l = t; l < Q1_NL; l += Q1_NT) {
+        const int lx = l % LX, ly = (l / LX) % LY, lz = l / (LX * LY);
         const int gx = bx * Q1_BX + lx, gy = by * Q1_BY + ly, gz = bz * Q1_BZ + lz;
         if (gx < g.nn[0] && gy < g.nn[1] && gz < g.nn[2]) {
+            T sum[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-            for (int f = 0; f < 4; ++f) part[(bid * 4 + f) * Q1_NL + l] = acc[f * Q1_NL + l];
+            for (int kk = 0; kk < 2; ++kk) {
+                const int czl = lz - 1 + kk;
+                if (czl < 0 || czl >= Q1_BZ) continue;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int cyl = ly - 1 + j;
+                    if (cyl < 0 || cyl >= Q1_BY) continue;
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        const int cxl = lx - 1 + i;
+                        if (cxl < 0 || cxl >= Q1_BX) continue;
+                        const int A = (1 - i) + 2 * (1 - j) + 4 * (1 - kk);
+                        const int lane = cxl + Q1_BX * (cyl + Q1_BY * czl);
+#pragma unroll
+                        for (int f = 0; f < 4; ++f) sum[f] += lds[(f * 8 + A) * Q1_NT + lane];
+                    }
+                }
+            }
+            // bricks of one parity class never share a node: one grid-shaped array per class
+            T *pc = part + (int64_t)((bx & 1) + 2 * (by & 1) + 4 * (bz & 1)) * 4 * N;
+            const int64_t node = gx + (int64_t)g.nn[0] * gy + nn01 * gz;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) pc[f * N + node] = sum[f];
         }
     }
 }
 
 }  // namespace
 
-// Node gather shared by all orders: sums brick partials (bricks of BXxBYxBZ cells, order P)
-// and, optionally, DLM corner sums of occupied neighbour cells; then Dirichlet rows.
+// Node gather shared by all orders: sums the brick partials (bricks of BXxBYxBZ cells of
+// order P; part holds one grid-shaped [4][N] array per brick parity class, so the reads are
+// coalesced) and, optionally, DLM corner sums of occupied neighbour cells; then Dirichlet rows.
 template <typename T, int P, int BX, int BY, int BZ>
 __global__ __launch_bounds__(256) void vms_gather(Geo g, const T *__restrict__ part, int nbx,
                                                   int nby, int nbz, const T *__restrict__ x,
@@ -315,37 +556,37 @@ __global__ __launch_bounds__(256) void vms_gather(Geo g, const T *__restrict__ p
 {
     const T *__restrict__ csum = o.csum;
     const int32_t *__restrict__ occ_index = o.occ_index;
-    constexpr int LX = P * BX + 1, LY = P * BY + 1, LZ = P * BZ + 1, NL = LX * LY * LZ;
     constexpr int NEN = (P + 1) * (P + 1) * (P + 1);
-    const int64_t node = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (node >= g.N) return;
-    const int gx = (int)(node % g.nn[0]);
-    const int gy = (int)((node / g.nn[0]) % g.nn[1]);
-    const int gz = (int)(node / ((int64_t)g.nn[0] * g.nn[1]));
+    // grid: x over the nodes of one z-plane, y over the planes (32-bit index math)
+    const uint32_t plane = (uint32_t)g.nn[0] * (uint32_t)g.nn[1];
+    const uint32_t pidx = blockIdx.x * 256u + threadIdx.x;
+    if (pidx >= plane) return;
+    const int gy = (int)(pidx / (uint32_t)g.nn[0]);
+    const int gx = (int)pidx - gy * g.nn[0];
+    const int gz = (int)blockIdx.y;
+    const int64_t node = (int64_t)gz * plane + pidx;
     // bricks holding the node along each axis (lower brick first)
-    int bxs[2], lxs[2], nxb = 0;
-    int bys[2], lys[2], nyb = 0;
-    int bzs[2], lzs[2], nzb = 0;
+    int bxs[2], nxb = 0, bys[2], nyb = 0, bzs[2], nzb = 0;
     {
-        const int sx = P * BX, sy = P * BY, sz = P * BZ;
-        int b = gx / sx, l = gx % sx;
-        if (l == 0 && b > 0) { bxs[nxb] = b - 1; lxs[nxb++] = sx; }
-        if (b < nbx) { bxs[nxb] = b; lxs[nxb++] = l; }
-        b = gy / sy; l = gy % sy;
-        if (l == 0 && b > 0) { bys[nyb] = b - 1; lys[nyb++] = sy; }
-        if (b < nby) { bys[nyb] = b; lys[nyb++] = l; }
-        b = gz / sz; l = gz % sz;
-        if (l == 0 && b > 0) { bzs[nzb] = b - 1; lzs[nzb++] = sz; }
-        if (b < nbz) { bzs[nzb] = b; lzs[nzb++] = l; }
+        constexpr int sx = P * BX, sy = P * BY, sz = P * BZ;
+        int b = gx / sx;
+        if (gx % sx == 0 && b > 0) bxs[nxb++] = b - 1;
+        if (b < nbx) bxs[nxb++] = b;
+        b = gy / sy;
+        if (gy % sy == 0 && b > 0) bys[nyb++] = b - 1;
+        if (b < nby) bys[nyb++] = b;
+        b = gz / sz;
+        if (gz % sz == 0 && b > 0) bzs[nzb++] = b - 1;
+        if (b < nbz) bzs[nzb++] = b;
     }
     T acc[4] = {T(0), T(0), T(0), T(0)};
     for (int iz = 0; iz < nzb; ++iz)
         for (int iy = 0; iy < nyb; ++iy)
             for (int ix = 0; ix < nxb; ++ix) {
-                const int64_t bid = bxs[ix] + (int64_t)nbx * (bys[iy] + (int64_t)nby * bzs[iz]);
-                const int l = lxs[ix] + LX * (lys[iy] + LY * lzs[iz]);
+                const int cls = (bxs[ix] & 1) + 2 * (bys[iy] & 1) + 4 * (bzs[iz] & 1);
+                const T *pc = part + (int64_t)cls * 4 * g.N + node;
 #pragma unroll
-                for (int f = 0; f < 4; ++f) acc[f] += part[(bid * 4 + f) * NL + l];
+                for (int f = 0; f < 4; ++f) acc[f] += pc[f * g.N];
             }
     if (csum != nullptr) {
         // cells containing the node along each axis: c with P c <= g <= P c + P
@@ -391,12 +632,15 @@ int launch_q1_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, 
                     const uint32_t *mask, const T *gram, const int32_t *occ_index, T *part,
                     const BrickLayout &bl, hipStream_t st, bool resid)
 {
+    // buffer offsets of a brick's nodes are 32-bit: (nodes per plane) x (brick height + 1)
+    FSI_CHECK_ARG((int64_t)g.nn[0] * g.nn[1] * (Q1_BZ + 1) * (int64_t)sizeof(T) < ((int64_t)1 << 31),
+                  "Q1 grid planes too large (%d x %d nodes)", g.nn[0], g.nn[1]);
     ProfileScope prof(resid ? "vms_q1_residual" : "vms_q1_cells", st);
     if (resid)
-        hipLaunchKernelGGL((vms_q1_cells<T, true>), dim3((unsigned)bl.nb), dim3(256), 0, st, g, k, x, a,
+        hipLaunchKernelGGL((vms_q1_cells<T, true>), dim3((unsigned)bl.nb), dim3(Q1_NT), 0, st, g, k, x, a,
                            s, mask, gram, occ_index, part, bl.nbx, bl.nby);
     else
-        hipLaunchKernelGGL((vms_q1_cells<T, false>), dim3((unsigned)bl.nb), dim3(256), 0, st, g, k, x,
+        hipLaunchKernelGGL((vms_q1_cells<T, false>), dim3((unsigned)bl.nb), dim3(Q1_NT), 0, st, g, k, x,
                            a, s, mask, gram, occ_index, part, bl.nbx, bl.nby);
     FSI_LAUNCH_CHECK();
     return FSI_OK;
@@ -406,9 +650,11 @@ template <typename T, int P, int BX, int BY, int BZ>
 int launch_gather(const Geo &g, const T *part, const BrickLayout &bl, const T *x,
                   const uint32_t *mask, T *y, const GatherOpts<T> &o, hipStream_t st)
 {
-    const unsigned blocks = (unsigned)((g.N + 255) / 256);
+    FSI_CHECK_ARG(g.nn[2] <= 65535 && (int64_t)g.nn[0] * g.nn[1] < ((int64_t)1 << 31),
+                  "grid too large for the node gather (%d x %d x %d nodes)", g.nn[0], g.nn[1], g.nn[2]);
+    const unsigned blocks = (unsigned)(((int64_t)g.nn[0] * g.nn[1] + 255) / 256);
     ProfileScope prof("vms_gather", st);
-    hipLaunchKernelGGL((vms_gather<T, P, BX, BY, BZ>), dim3(blocks), dim3(256), 0, st, g, part,
+    hipLaunchKernelGGL((vms_gather<T, P, BX, BY, BZ>), dim3(blocks, (unsigned)g.nn[2]), dim3(256), 0, st, g, part,
                        bl.nbx, bl.nby, bl.nbz, x, mask, y, o);
     FSI_LAUNCH_CHECK();
     return FSI_OK;
