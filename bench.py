@@ -222,9 +222,10 @@ def main(argv=None):
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-newton", action="store_true", help="skip the short Newton-step probe")
-    ap.add_argument("--experiment", default=None, choices=["warmstart", "c5", "netspeed"],
+    ap.add_argument("--experiment", default=None, choices=["warmstart", "c5", "netspeed", "c3"],
                     help="run a Newton-step experiment instead of the apply benchmark")
     ap.add_argument("--exp-steps", type=int, default=200)
+    ap.add_argument("--exp-modes", default="mixed,f64")
     ap.add_argument("--exp-train-end", type=int, default=100)
     ap.add_argument("--exp-epochs", type=int, default=20)
     ap.add_argument("--exp-stride", type=int, default=1)
@@ -346,6 +347,10 @@ def run_experiment(args):
         print(json.dumps({"experiment": "netspeed", "lattice": "65^3", "params": net.n_params,
                           "forward_ms": round(fwd, 3), "train_sample_ms": round(trn, 3),
                           "forward_padded_TFLOPs": round(flops / fwd / 1e9, 2)}))
+        return 0
+    if args.experiment == "c3":
+        print(json.dumps({"experiment": "solve_c3",
+                          **ex.solve_c3(max_iters=args.exp_steps, modes=tuple(args.exp_modes.split(",")))}))
         return 0
     if args.experiment == "warmstart":
         summary, lw = ex.warmstart_c4(steps=args.exp_steps, train_end=args.exp_train_end,

@@ -112,9 +112,12 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
         int stalls = 0;
         for (;;) {
             // true residual r = b - J64 x in FP64 (stored in V[0])
-            TRY(J64.apply(x, w64, jws, st));
-            FSI_HIP(hipMemcpyAsync(V, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
-            TRY(kry_axpby(n, -1.0, w64, 1.0, V, st));
+            {
+                ProfileScope pr("fgmres_residual", st);
+                TRY(J64.apply(x, w64, jws, st));
+                FSI_HIP(hipMemcpyAsync(V, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+                TRY(kry_axpby(n, -1.0, w64, 1.0, V, st));
+            }
             double beta = 0.0;
             TRY(kry_norm(n, V, partial, hdev, st));
             TRY(fetch(&beta, hdev, 1));
@@ -151,14 +154,22 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
                 double *Vj = V + (size_t)j * n;
                 char *Zj = reinterpret_cast<char *>(Z) + (size_t)j * n * zel;
                 if (inner == FSI_F32) {
-                    TRY(kry_cast_f64_f32(n, Vj, t32a, st));
-                    if (pinv) TRY(launch_bjacobi_apply(N, FSI_F32, pinv, t32a, Zj, st));
-                    else FSI_HIP(hipMemcpyAsync(Zj, t32a, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
+                    {
+                        ProfileScope pp("fgmres_precond", st);
+                        TRY(kry_cast_f64_f32(n, Vj, t32a, st));
+                        if (pinv) TRY(launch_bjacobi_apply(N, FSI_F32, pinv, t32a, Zj, st));
+                        else FSI_HIP(hipMemcpyAsync(Zj, t32a, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
+                    }
+                    ProfileScope pa("fgmres_apply", st);
                     TRY(J32->apply(Zj, t32b, jws, st));
                     TRY(kry_cast_f32_f64(n, t32b, w64, st));
                 } else {
-                    if (pinv) TRY(launch_bjacobi_apply(N, FSI_F64, pinv, Vj, Zj, st));
-                    else FSI_HIP(hipMemcpyAsync(Zj, Vj, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+                    {
+                        ProfileScope pp("fgmres_precond", st);
+                        if (pinv) TRY(launch_bjacobi_apply(N, FSI_F64, pinv, Vj, Zj, st));
+                        else FSI_HIP(hipMemcpyAsync(Zj, Vj, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+                    }
+                    ProfileScope pa("fgmres_apply", st);
                     TRY(J64.apply(Zj, w64, jws, st));
                 }
                 // classical Gram-Schmidt with re-orthogonalisation through the Gram matrix
@@ -166,9 +177,12 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
                 // V^T V_j; the second projection V^T (w - V a) = a - G a needs no further pass,
                 // so w -= V (a + (a - G a)) and ||w|| complete the step in a second pass.
                 double *d_ab = hdev, *d_h = hdev + 2 * (m + 1), *d_hn = hdev + 3 * (m + 1);
-                TRY(kry_multidot2(n, j + 1, V, n, w64, Vj, partial, d_ab, st));
-                TRY(kry_gram_coeffs(j + 1, d_ab, Gdev, m + 1, d_h, st));
-                TRY(kry_axpy_dot(n, j + 1, V, n, d_h, w64, 0, partial, d_hn, st));
+                {
+                    ProfileScope po("fgmres_orth", st);
+                    TRY(kry_multidot2(n, j + 1, V, n, w64, Vj, partial, d_ab, st));
+                    TRY(kry_gram_coeffs(j + 1, d_ab, Gdev, m + 1, d_h, st));
+                    TRY(kry_axpy_dot(n, j + 1, V, n, d_h, w64, 0, partial, d_hn, st));
+                }
                 TRY(fetch(hcopy.data(), d_h, (m + 1) + 1));
                 double hn = hcopy[m + 1];
                 for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcopy[i];
