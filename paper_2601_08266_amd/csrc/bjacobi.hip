@@ -243,21 +243,21 @@ __global__ __launch_bounds__(256) void bj_node(Geo g, VmsConst<double> k, const 
     }
 }
 
-template <typename T>
+template <typename T, typename TV, typename TZ>
 __global__ __launch_bounds__(256) void bj_apply(int64_t N, const T *__restrict__ pinv,
-                                                const T *__restrict__ v, T *__restrict__ z)
+                                                const TV *__restrict__ v, TZ *__restrict__ z)
 {
     const int64_t node = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (node >= N) return;
     T vin[4];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) vin[f] = v[f * N + node];
+    for (int f = 0; f < 4; ++f) vin[f] = (T)v[f * N + node];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         T acc = T(0);
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc += pinv[(int64_t)(i * 4 + j) * N + node] * vin[j];
-        z[i * N + node] = acc;
+        z[i * N + node] = (TZ)acc;
     }
 }
 
@@ -309,11 +309,20 @@ int launch_bjacobi_apply(int64_t N, fsi_dtype dt, const void *pinv, const void *
 {
     const unsigned b = (unsigned)((N + 255) / 256);
     if (dt == FSI_F64)
-        hipLaunchKernelGGL(bj_apply<double>, dim3(b), dim3(256), 0, st, N, (const double *)pinv,
-                           (const double *)v, (double *)z);
+        hipLaunchKernelGGL((bj_apply<double, double, double>), dim3(b), dim3(256), 0, st, N,
+                           (const double *)pinv, (const double *)v, (double *)z);
     else
-        hipLaunchKernelGGL(bj_apply<float>, dim3(b), dim3(256), 0, st, N, (const float *)pinv,
-                           (const float *)v, (float *)z);
+        hipLaunchKernelGGL((bj_apply<float, float, float>), dim3(b), dim3(256), 0, st, N,
+                           (const float *)pinv, (const float *)v, (float *)z);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+
+int launch_bjacobi_apply_f64_to_f32(int64_t N, const float *pinv32, const double *v, float *z,
+                                    hipStream_t st)
+{
+    const unsigned b = (unsigned)((N + 255) / 256);
+    hipLaunchKernelGGL((bj_apply<float, double, float>), dim3(b), dim3(256), 0, st, N, pinv32, v, z);
     FSI_LAUNCH_CHECK();
     return FSI_OK;
 }

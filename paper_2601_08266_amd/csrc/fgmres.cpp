@@ -22,7 +22,7 @@ namespace fsi {
 namespace {
 
 struct Layout {
-    size_t V, Z, w64, t32a, t32b, partial, hdev, gram, jws, total;
+    size_t V, Z, w64, t32b, partial, hdev, gram, counter, jws, total;
 };
 
 Layout layout(int64_t n, int m, fsi_dtype inner, size_t jws_bytes)
@@ -37,11 +37,11 @@ Layout layout(int64_t n, int m, fsi_dtype inner, size_t jws_bytes)
     L.V = take((size_t)(m + 1) * n * sizeof(double));
     L.Z = take((size_t)m * n * (inner == FSI_F64 ? sizeof(double) : sizeof(float)));
     L.w64 = take((size_t)n * sizeof(double));
-    L.t32a = take((size_t)n * sizeof(float));
     L.t32b = take((size_t)n * sizeof(float));
     L.partial = take((size_t)(2 * (m + 2)) * KRY_NB * sizeof(double));
     L.hdev = take((size_t)(4 * (m + 1) + 2) * sizeof(double));
     L.gram = take((size_t)(m + 1) * (m + 1) * sizeof(double));
+    L.counter = take(sizeof(int));
     L.jws = take(jws_bytes);
     L.total = off;
     return L;
@@ -68,11 +68,11 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
     double *V = reinterpret_cast<double *>(base + L.V);
     void *Z = base + L.Z;
     double *w64 = reinterpret_cast<double *>(base + L.w64);
-    float *t32a = reinterpret_cast<float *>(base + L.t32a);
     float *t32b = reinterpret_cast<float *>(base + L.t32b);
     double *partial = reinterpret_cast<double *>(base + L.partial);
     double *hdev = reinterpret_cast<double *>(base + L.hdev);
     double *Gdev = reinterpret_cast<double *>(base + L.gram);
+    int *counter = reinterpret_cast<int *>(base + L.counter);
     void *jws = base + L.jws;
     const size_t zel = inner == FSI_F64 ? sizeof(double) : sizeof(float);
 
@@ -89,6 +89,7 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
         if (rc) goto done;   \
     } while (0)
 
+    FSI_HIP(hipMemsetAsync(counter, 0, sizeof(int), st));
     {
         double bnorm = 0.0;
         TRY(kry_norm(n, b, partial, hdev, st));
@@ -156,9 +157,12 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
                 if (inner == FSI_F32) {
                     {
                         ProfileScope pp("fgmres_precond", st);
-                        TRY(kry_cast_f64_f32(n, Vj, t32a, st));
-                        if (pinv) TRY(launch_bjacobi_apply(N, FSI_F32, pinv, t32a, Zj, st));
-                        else FSI_HIP(hipMemcpyAsync(Zj, t32a, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
+                        if (pinv) {
+                            TRY(launch_bjacobi_apply_f64_to_f32(N, reinterpret_cast<const float *>(pinv), Vj,
+                                                                reinterpret_cast<float *>(Zj), st));
+                        } else {
+                            TRY(kry_cast_f64_f32(n, Vj, reinterpret_cast<float *>(Zj), st));
+                        }
                     }
                     ProfileScope pa("fgmres_apply", st);
                     TRY(J32->apply(Zj, t32b, jws, st));
@@ -179,9 +183,15 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
                 double *d_ab = hdev, *d_h = hdev + 2 * (m + 1), *d_hn = hdev + 3 * (m + 1);
                 {
                     ProfileScope po("fgmres_orth", st);
-                    TRY(kry_multidot2(n, j + 1, V, n, w64, Vj, partial, d_ab, st));
-                    TRY(kry_gram_coeffs(j + 1, d_ab, Gdev, m + 1, d_h, st));
-                    TRY(kry_axpy_dot(n, j + 1, V, n, d_h, w64, 0, partial, d_hn, st));
+                    if (j + 1 <= KRY_FUSED_MAXK) {
+                        TRY(kry_cgs_project(n, j + 1, V, n, w64, Vj, partial, d_ab, Gdev, m + 1, d_h,
+                                            counter, st));
+                        TRY(kry_axpy_norm(n, j + 1, V, n, d_h, w64, partial, d_hn, counter, st));
+                    } else {
+                        TRY(kry_multidot2(n, j + 1, V, n, w64, Vj, partial, d_ab, st));
+                        TRY(kry_gram_coeffs(j + 1, d_ab, Gdev, m + 1, d_h, st));
+                        TRY(kry_axpy_dot(n, j + 1, V, n, d_h, w64, 0, partial, d_hn, st));
+                    }
                 }
                 TRY(fetch(hcopy.data(), d_h, (m + 1) + 1));
                 double hn = hcopy[m + 1];

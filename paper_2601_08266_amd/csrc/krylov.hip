@@ -233,6 +233,170 @@ __global__ __launch_bounds__(KT) void update_k(int64_t n, int nk, const TZ *__re
     }
 }
 
+// ---- fused CGS2 step kernels: per-block partials, and the last block to finish reduces them
+// in a fixed order (deterministic), so one launch replaces kernel + reduction + coefficients.
+
+constexpr int CG_WAVES = KT / 64;           // waves per block
+constexpr int CG_MAXK = 13;                 // vectors per wave: nk <= CG_WAVES * CG_MAXK
+static_assert(CG_WAVES * CG_MAXK == KRY_FUSED_MAXK, "fused CGS size");
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum of partial[r][0..nb) for r < nr into out[r]: one wave per row, lane-strided then a fixed
+// butterfly (same order on every run).
+__device__ __forceinline__ void reduce_rows(int nr, int nb, const double *partial, double *out)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int r = wv; r < nr; r += CG_WAVES) {
+        double s = 0.0;
+        for (int b = lane; b < nb; b += 64) s += partial[(int64_t)r * nb + b];
+        s = wave_sum(s);
+        if (lane == 0) out[r] = s;
+    }
+}
+
+// Returns true in the block that finished last (all blocks' partials are then visible).
+__device__ __forceinline__ bool last_block(int *counter)
+{
+    __shared__ bool last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(counter, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
+}
+
+// Projection pass of classical Gram-Schmidt with re-orthogonalisation through the Gram matrix:
+// ab[k] = V[k] . w, ab[nk + k] = V[k] . u (u = V[nk-1], the newest basis vector), k < nk, in one
+// read of V: wave wv of a block takes the vectors k = wv + 4q, q < KQ = ceil(nk / 4), and issues
+// their loads together (past nk the last vector is re-read and not accumulated); then, in the
+// last block, G[:, j] = G[j, :] = ab[nk:] (j = nk - 1) and h = a + (a - G a).
+template <int KQ>
+__global__ __launch_bounds__(KT) void cgs_project_k(int64_t n, int nk, const double *__restrict__ V,
+                                                    int64_t ldv, const double *__restrict__ w,
+                                                    const double *__restrict__ u,
+                                                    double *__restrict__ partial, double *__restrict__ ab,
+                                                    double *__restrict__ G, int ldg,
+                                                    double *__restrict__ h, int *__restrict__ counter)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // chunks of an even number of elements: the loop moves pairs (16-byte loads; n, ldv and
+    // the vector bases are even / 16-byte aligned)
+    const int64_t chunk = ((n + gridDim.x - 1) / gridDim.x + 1) & ~(int64_t)1;
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    const double *vk[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+        const int k = wv + CG_WAVES * q;
+        vk[q] = V + (int64_t)(k < nk ? k : nk - 1) * ldv;
+    }
+    double aw[KQ], au[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) aw[q] = au[q] = 0.0;
+    for (int64_t i = lo + 2 * lane; i < hi; i += 128) {
+        const double2 wi = *reinterpret_cast<const double2 *>(w + i);
+        const double2 ui = *reinterpret_cast<const double2 *>(u + i);
+        double2 v[KQ];
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) v[q] = *reinterpret_cast<const double2 *>(vk[q] + i);
+        __builtin_amdgcn_sched_barrier(0);   // keep the loads in flight together
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            aw[q] += v[q].x * wi.x;
+            au[q] += v[q].x * ui.x;
+            aw[q] += v[q].y * wi.y;
+            au[q] += v[q].y * ui.y;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+        const int k = wv + CG_WAVES * q;
+        const double sw = wave_sum(aw[q]), su = wave_sum(au[q]);
+        if (k < nk && lane == 0) {
+            partial[(int64_t)k * gridDim.x + blockIdx.x] = sw;
+            partial[(int64_t)(nk + k) * gridDim.x + blockIdx.x] = su;
+        }
+    }
+    if (!last_block(counter)) return;
+    reduce_rows(2 * nk, gridDim.x, partial, ab);
+    __syncthreads();
+    const int j = nk - 1, t = threadIdx.x;
+    for (int k = t; k < nk; k += KT) {
+        G[(int64_t)k * ldg + j] = ab[nk + k];
+        G[(int64_t)j * ldg + k] = ab[nk + k];
+    }
+    __syncthreads();
+    for (int k = t; k < nk; k += KT) {
+        double ga = 0.0;
+        for (int m = 0; m < nk; ++m) ga += G[(int64_t)k * ldg + m] * ab[m];
+        h[k] = ab[k] + (ab[k] - ga);
+    }
+    if (t == 0) *counter = 0;
+}
+
+// w -= V h (nk vectors, in groups of 8 whose loads are issued together) and out[0] = ||w||
+// (new w), reduced in the last block.
+__global__ __launch_bounds__(KT) void axpy_norm_k(int64_t n, int nk, const double *__restrict__ V,
+                                                  int64_t ldv, const double *__restrict__ h,
+                                                  double *__restrict__ w, double *__restrict__ partial,
+                                                  double *__restrict__ out, int *__restrict__ counter)
+{
+    constexpr int KB = 8;
+    __shared__ double red[CG_WAVES];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t chunk = ((n + gridDim.x - 1) / gridDim.x + 1) & ~(int64_t)1;
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    double acc = 0.0;
+    for (int64_t i = lo + 2 * threadIdx.x; i < hi; i += 2 * KT) {
+        double2 s = *reinterpret_cast<const double2 *>(w + i);
+        for (int k0 = 0; k0 < nk; k0 += KB) {
+            double2 v[KB];
+            double hk[KB];
+#pragma unroll
+            for (int q = 0; q < KB; ++q) {
+                const int k = k0 + q;
+                v[q] = *reinterpret_cast<const double2 *>(V + (int64_t)(k < nk ? k : nk - 1) * ldv + i);
+                hk[q] = k < nk ? h[k] : 0.0;
+            }
+            __builtin_amdgcn_sched_barrier(0);   // keep the loads in flight together
+#pragma unroll
+            for (int q = 0; q < KB; ++q) {
+                s.x -= hk[q] * v[q].x;
+                s.y -= hk[q] * v[q].y;
+            }
+        }
+        *reinterpret_cast<double2 *>(w + i) = s;
+        acc += s.x * s.x;
+        acc += s.y * s.y;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) red[wv] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int q = 0; q < CG_WAVES; ++q) sum += red[q];
+        partial[blockIdx.x] = sum;
+    }
+    if (!last_block(counter)) return;
+    if (wv == 0) {
+        double sum = 0.0;
+        for (int b = lane; b < (int)gridDim.x; b += 64) sum += partial[b];
+        sum = wave_sum(sum);
+        if (lane == 0) {
+            out[0] = sqrt(sum);
+            *counter = 0;
+        }
+    }
+}
+
 inline unsigned grid_for(int64_t n)
 {
     int64_t b = (n + KT - 1) / KT;
@@ -324,6 +488,49 @@ int kry_multidot2(int64_t n, int nk, const double *V, int64_t ldv, const double 
     hipLaunchKernelGGL(multidot2_k, dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, w, u, partial);
     FSI_LAUNCH_CHECK();
     hipLaunchKernelGGL(reduce_partials_k, dim3(2 * nk), dim3(KT), 0, st, 2 * nk, KRY_NB, partial, out);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+
+int kry_cgs_project(int64_t n, int nk, const double *V, int64_t ldv, const double *w, const double *u,
+                    double *partial, double *ab, double *G, int ldg, double *h, int *counter,
+                    hipStream_t st)
+{
+    if ((n | ldv) & 1 || ((uintptr_t)V | (uintptr_t)w | (uintptr_t)u) & 15) {
+        set_error("CGS projection needs even lengths and 16-byte aligned vectors");
+        return FSI_ERR_ARG;
+    }
+    if (nk > KRY_FUSED_MAXK) {
+        set_error("CGS projection supports at most %d basis vectors (got %d)", CG_WAVES * CG_MAXK, nk);
+        return FSI_ERR_ARG;
+    }
+    switch ((nk + CG_WAVES - 1) / CG_WAVES) {
+#define FSI_CGS_CASE(KQ)                                                                           \
+    case KQ:                                                                                       \
+        hipLaunchKernelGGL(cgs_project_k<KQ>, dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, w, u,   \
+                           partial, ab, G, ldg, h, counter);                                       \
+        break;
+        FSI_CGS_CASE(1) FSI_CGS_CASE(2) FSI_CGS_CASE(3) FSI_CGS_CASE(4) FSI_CGS_CASE(5)
+        FSI_CGS_CASE(6) FSI_CGS_CASE(7) FSI_CGS_CASE(8) FSI_CGS_CASE(9) FSI_CGS_CASE(10)
+        FSI_CGS_CASE(11) FSI_CGS_CASE(12) FSI_CGS_CASE(13)
+#undef FSI_CGS_CASE
+    default:
+        set_error("CGS projection: bad basis size %d", nk);
+        return FSI_ERR_ARG;
+    }
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+
+int kry_axpy_norm(int64_t n, int nk, const double *V, int64_t ldv, const double *h, double *w,
+                  double *partial, double *out, int *counter, hipStream_t st)
+{
+    if ((n | ldv) & 1 || ((uintptr_t)V | (uintptr_t)w) & 15) {
+        set_error("CGS update needs even lengths and 16-byte aligned vectors");
+        return FSI_ERR_ARG;
+    }
+    hipLaunchKernelGGL(axpy_norm_k, dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, h, w, partial, out,
+                       counter);
     FSI_LAUNCH_CHECK();
     return FSI_OK;
 }

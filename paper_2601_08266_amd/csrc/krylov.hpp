@@ -6,6 +6,7 @@
 namespace fsi {
 
 constexpr int KRY_NB = 1024;   // blocks of the multi-dot (partials per vector)
+constexpr int KRY_FUSED_MAXK = 52;   // basis size the fused CGS kernels support
 
 int kry_cast_f64_f32(int64_t n, const double *in, float *out, hipStream_t st);
 int kry_cast_f32_f64(int64_t n, const float *in, double *out, hipStream_t st);
@@ -25,6 +26,15 @@ int kry_multidot2(int64_t n, int nk, const double *V, int64_t ldv, const double 
                   double *partial, double *out, hipStream_t st);
 // Gram column update and twice-projected coefficients (see krylov.hip)
 int kry_gram_coeffs(int nk, const double *ab, double *G, int ldg, double *h, hipStream_t st);
+// One launch each (the last block reduces the per-block partials in a fixed order; counter is a
+// zeroed device int that the kernel leaves at zero):
+// ab = [V^T w; V^T u], Gram column j = nk - 1 from V^T u, h = a + (a - G a)  (nk <= 52)
+int kry_cgs_project(int64_t n, int nk, const double *V, int64_t ldv, const double *w, const double *u,
+                    double *partial, double *ab, double *G, int ldg, double *h, int *counter,
+                    hipStream_t st);
+// w -= V h and out[0] = ||w||
+int kry_axpy_norm(int64_t n, int nk, const double *V, int64_t ldv, const double *h, double *w,
+                  double *partial, double *out, int *counter, hipStream_t st);
 int kry_update(int64_t n, int nk, fsi_dtype dz, const void *Z, int64_t ldz, const double *y, double *x,
                hipStream_t st);
 
