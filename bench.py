@@ -160,19 +160,17 @@ def newton_step_probe(warm_steps=60, measure_steps=3):
     import torch
 
     import fsi_workloads as W
-    from paper_2601_08266_amd.learned import LearnedWarmStart
     from paper_2601_08266_amd import experiments as ex
     from paper_2601_08266_amd.stepper import ChannelRun
 
     run = ChannelRun(W.CONFIGS["c4"])
     for _ in range(warm_steps):
         run.step()
-    lw = LearnedWarmStart.__new__(LearnedWarmStart)   # only its extrapolation guess is used here
     rows = []
     for k in range(warm_steps, warm_steps + measure_steps):
         run.x = run.history[k].x.clone()
         run.n = k
-        rows.append(ex._solve_modes(run, lw, k, ["plain_f64", "plain_mixed", "extrap_mixed"]))
+        rows.append(ex._solve_modes(run, None, k, ["plain_f64", "plain_mixed", "extrap_mixed"]))
         run.x = run.history[k].x.clone()
         run.n = k
         run.step()

@@ -22,7 +22,7 @@ namespace fsi {
 namespace {
 
 struct Layout {
-    size_t V, Z, w64, t32b, partial, hdev, gram, counter, jws, total;
+    size_t V, Z, w64, t32b, partial, hdev, gram, jws, total;
 };
 
 Layout layout(int64_t n, int m, fsi_dtype inner, size_t jws_bytes)
@@ -41,10 +41,44 @@ Layout layout(int64_t n, int m, fsi_dtype inner, size_t jws_bytes)
     L.partial = take((size_t)(2 * (m + 2)) * KRY_NB * sizeof(double));
     L.hdev = take((size_t)(4 * (m + 1) + 2) * sizeof(double));
     L.gram = take((size_t)(m + 1) * (m + 1) * sizeof(double));
-    L.counter = take(sizeof(int));
     L.jws = take(jws_bytes);
     L.total = off;
     return L;
+}
+
+// Pinned host memory for the per-step coefficient copies and the per-step events: allocated on
+// first use, grown as needed, kept for the life of the process (per host thread).
+double *pinned_ring(size_t doubles)
+{
+    thread_local double *buf = nullptr;
+    thread_local size_t cap = 0;
+    if (cap < doubles) {
+        if (buf) (void)hipHostFree(buf);
+        buf = nullptr;
+        cap = 0;
+        if (hipHostMalloc(reinterpret_cast<void **>(&buf), doubles * sizeof(double), hipHostMallocDefault) !=
+            hipSuccess) {
+            set_error("hipHostMalloc of %zu bytes failed", doubles * sizeof(double));
+            buf = nullptr;
+            return nullptr;
+        }
+        cap = doubles;
+    }
+    return buf;
+}
+
+std::vector<hipEvent_t> &step_events(int m)
+{
+    thread_local std::vector<hipEvent_t> ev;
+    while ((int)ev.size() < m) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            set_error("hipEventCreate failed");
+            break;
+        }
+        ev.push_back(e);
+    }
+    return ev;
 }
 
 }  // namespace
@@ -72,7 +106,6 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
     double *partial = reinterpret_cast<double *>(base + L.partial);
     double *hdev = reinterpret_cast<double *>(base + L.hdev);
     double *Gdev = reinterpret_cast<double *>(base + L.gram);
-    int *counter = reinterpret_cast<int *>(base + L.counter);
     void *jws = base + L.jws;
     const size_t zel = inner == FSI_F64 ? sizeof(double) : sizeof(float);
 
@@ -89,7 +122,6 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
         if (rc) goto done;   \
     } while (0)
 
-    FSI_HIP(hipMemsetAsync(counter, 0, sizeof(int), st));
     {
         double bnorm = 0.0;
         TRY(kry_norm(n, b, partial, hdev, st));
@@ -150,8 +182,57 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
             // an FP32 inner cycle cannot resolve much below its own rounding level
             double cycle_target = target;
             if (inner == FSI_F32) cycle_target = std::max(target, o.inner_reduction * beta);
-            int kk = 0;
-            for (int j = 0; j < m && S.iters < o.max_iters; ++j) {
+            // The Arnoldi steps are enqueued without waiting for the host: the coefficients stay
+            // on the device, and each step's (h, ||w||) is copied to pinned host memory behind
+            // it.  The host applies the Givens rotations one step behind the device, so the
+            // convergence test lags by one step (at most one extra step per cycle is computed
+            // and then ignored).
+            double *hring = pinned_ring((size_t)m * (m + 2));
+            if (hring == nullptr) {
+                rc = FSI_ERR_HIP;
+                goto done;
+            }
+            std::vector<hipEvent_t> &ev = step_events(m);
+            if ((int)ev.size() < m) {
+                rc = FSI_ERR_HIP;
+                goto done;
+            }
+            int kk = 0, enq = 0;
+            bool stop = false;
+            auto process = [&](int j) -> int {
+                // Givens update of Hessenberg column j from the host copy of its coefficients
+                FSI_HIP(hipEventSynchronize(ev[j]));
+                const double *hc = hring + (size_t)j * (m + 2);
+                const double hn = hc[m + 1];
+                for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hc[i];
+                H[(size_t)(j + 1) * m + j] = hn;
+                if (!std::isfinite(hn)) {
+                    set_error("Arnoldi vector norm is NaN/Inf");
+                    return FSI_ERR_NAN;
+                }
+                for (int i = 0; i < j; ++i) {
+                    const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
+                    H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
+                    H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+                }
+                const double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
+                const double den = std::hypot(a, c);
+                if (den == 0.0) {
+                    set_error("Krylov breakdown (zero Hessenberg column)");
+                    return FSI_ERR_BREAKDOWN;
+                }
+                cs[j] = a / den;
+                sn[j] = c / den;
+                H[(size_t)j * m + j] = den;
+                H[(size_t)(j + 1) * m + j] = 0.0;
+                gv[j + 1] = -sn[j] * gv[j];
+                gv[j] = cs[j] * gv[j];
+                ++S.iters;
+                kk = j + 1;
+                if (std::fabs(gv[j + 1]) <= cycle_target || hn == 0.0) stop = true;
+                return FSI_OK;
+            };
+            for (int j = 0; j < m && !stop && S.iters + (enq - kk) < o.max_iters; ++j) {
                 double *Vj = V + (size_t)j * n;
                 char *Zj = reinterpret_cast<char *>(Z) + (size_t)j * n * zel;
                 if (inner == FSI_F32) {
@@ -184,47 +265,23 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
                 {
                     ProfileScope po("fgmres_orth", st);
                     if (j + 1 <= KRY_FUSED_MAXK) {
-                        TRY(kry_cgs_project(n, j + 1, V, n, w64, Vj, partial, d_ab, Gdev, m + 1, d_h,
-                                            counter, st));
-                        TRY(kry_axpy_norm(n, j + 1, V, n, d_h, w64, partial, d_hn, counter, st));
+                        TRY(kry_cgs_project(n, j + 1, V, n, w64, Vj, partial, d_ab, Gdev, m + 1, d_h, st));
+                        TRY(kry_axpy_norm(n, j + 1, V, n, d_h, w64, partial, d_hn, st));
                     } else {
                         TRY(kry_multidot2(n, j + 1, V, n, w64, Vj, partial, d_ab, st));
                         TRY(kry_gram_coeffs(j + 1, d_ab, Gdev, m + 1, d_h, st));
                         TRY(kry_axpy_dot(n, j + 1, V, n, d_h, w64, 0, partial, d_hn, st));
                     }
                 }
-                TRY(fetch(hcopy.data(), d_h, (m + 1) + 1));
-                double hn = hcopy[m + 1];
-                for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcopy[i];
-                H[(size_t)(j + 1) * m + j] = hn;
-                if (!std::isfinite(hn)) {
-                    set_error("Arnoldi vector norm is NaN/Inf");
-                    rc = FSI_ERR_NAN;
-                    goto done;
-                }
-                if (hn > 0.0) TRY(kry_scale_inv(n, w64, d_hn, V + (size_t)(j + 1) * n, st));
-                for (int i = 0; i < j; ++i) {
-                    const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
-                    H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
-                    H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
-                }
-                const double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
-                const double den = std::hypot(a, c);
-                if (den == 0.0) {
-                    set_error("Krylov breakdown (zero Hessenberg column)");
-                    rc = FSI_ERR_BREAKDOWN;
-                    goto done;
-                }
-                cs[j] = a / den;
-                sn[j] = c / den;
-                H[(size_t)j * m + j] = den;
-                H[(size_t)(j + 1) * m + j] = 0.0;
-                gv[j + 1] = -sn[j] * gv[j];
-                gv[j] = cs[j] * gv[j];
-                ++S.iters;
-                kk = j + 1;
-                if (std::fabs(gv[j + 1]) <= cycle_target || hn == 0.0) break;
+                FSI_HIP(hipMemcpyAsync(hring + (size_t)j * (m + 2), d_h, (size_t)(m + 2) * sizeof(double),
+                                       hipMemcpyDeviceToHost, st));
+                FSI_HIP(hipEventRecord(ev[j], st));
+                // next basis vector (if ||w|| = 0 the step ends the cycle and this vector is unused)
+                TRY(kry_scale_inv(n, w64, d_hn, V + (size_t)(j + 1) * n, st));
+                ++enq;
+                if (j >= 1) TRY(process(j - 1));
             }
+            if (!stop && enq > kk) TRY(process(enq - 1));
             // y = H^{-1} g (upper triangular), x += Z y
             for (int i = kk - 1; i >= 0; --i) {
                 double s = gv[i];

@@ -76,21 +76,32 @@ __global__ __launch_bounds__(KT) void multidot_k(int64_t n, int nk, const double
     }
 }
 
-// out[k] = sum_b partial[k][b]: one block per k, strided per-thread sums then a fixed LDS tree
+// out[k] = sum_b partial[k][b] (sqrt of it if take_sqrt): one block per k; each thread sums a
+// fixed set of partials (loads issued in groups of 4), then a fixed LDS tree
 __global__ __launch_bounds__(KT) void reduce_partials_k(int nk, int nb, const double *__restrict__ partial,
-                                                        double *__restrict__ out)
+                                                        double *__restrict__ out, int take_sqrt = 0)
 {
     __shared__ double red[KT];
     const int k = blockIdx.x, t = threadIdx.x;
+    const double *p = partial + (int64_t)k * nb;
     double s = 0.0;
-    for (int b = t; b < nb; b += KT) s += partial[(int64_t)k * nb + b];
+    for (int b0 = 0; b0 < nb; b0 += 4 * KT) {
+        double v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int b = b0 + q * KT + t;
+            v[q] = b < nb ? p[b] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s += v[q];
+    }
     red[t] = s;
     __syncthreads();
     for (int off = KT / 2; off > 0; off >>= 1) {
         if (t < off) red[t] += red[t + off];
         __syncthreads();
     }
-    if (t == 0) out[k] = red[0];
+    if (t == 0) out[k] = take_sqrt ? sqrt(red[0]) : red[0];
 }
 
 // sqrt of a device scalar, in place
@@ -247,43 +258,15 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Sum of partial[r][0..nb) for r < nr into out[r]: one wave per row, lane-strided then a fixed
-// butterfly (same order on every run).
-__device__ __forceinline__ void reduce_rows(int nr, int nb, const double *partial, double *out)
-{
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int r = wv; r < nr; r += CG_WAVES) {
-        double s = 0.0;
-        for (int b = lane; b < nb; b += 64) s += partial[(int64_t)r * nb + b];
-        s = wave_sum(s);
-        if (lane == 0) out[r] = s;
-    }
-}
-
-// Returns true in the block that finished last (all blocks' partials are then visible).
-__device__ __forceinline__ bool last_block(int *counter)
-{
-    __shared__ bool last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(counter, 1) == (int)gridDim.x - 1;
-    __syncthreads();
-    if (last) __threadfence();
-    return last;
-}
-
 // Projection pass of classical Gram-Schmidt with re-orthogonalisation through the Gram matrix:
-// ab[k] = V[k] . w, ab[nk + k] = V[k] . u (u = V[nk-1], the newest basis vector), k < nk, in one
-// read of V: wave wv of a block takes the vectors k = wv + 4q, q < KQ = ceil(nk / 4), and issues
-// their loads together (past nk the last vector is re-read and not accumulated); then, in the
-// last block, G[:, j] = G[j, :] = ab[nk:] (j = nk - 1) and h = a + (a - G a).
+// per-block partials of V[k] . w and V[k] . u (u = V[nk-1], the newest basis vector), k < nk, in
+// one read of V: wave wv of a block takes the vectors k = wv + 4q, q < KQ = ceil(nk / 4), and
+// issues their loads together (past nk the last vector is re-read and not accumulated).
 template <int KQ>
 __global__ __launch_bounds__(KT) void cgs_project_k(int64_t n, int nk, const double *__restrict__ V,
                                                     int64_t ldv, const double *__restrict__ w,
                                                     const double *__restrict__ u,
-                                                    double *__restrict__ partial, double *__restrict__ ab,
-                                                    double *__restrict__ G, int ldg,
-                                                    double *__restrict__ h, int *__restrict__ counter)
+                                                    double *__restrict__ partial)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     // chunks of an even number of elements: the loop moves pairs (16-byte loads; n, ldv and
@@ -324,29 +307,13 @@ __global__ __launch_bounds__(KT) void cgs_project_k(int64_t n, int nk, const dou
             partial[(int64_t)(nk + k) * gridDim.x + blockIdx.x] = su;
         }
     }
-    if (!last_block(counter)) return;
-    reduce_rows(2 * nk, gridDim.x, partial, ab);
-    __syncthreads();
-    const int j = nk - 1, t = threadIdx.x;
-    for (int k = t; k < nk; k += KT) {
-        G[(int64_t)k * ldg + j] = ab[nk + k];
-        G[(int64_t)j * ldg + k] = ab[nk + k];
-    }
-    __syncthreads();
-    for (int k = t; k < nk; k += KT) {
-        double ga = 0.0;
-        for (int m = 0; m < nk; ++m) ga += G[(int64_t)k * ldg + m] * ab[m];
-        h[k] = ab[k] + (ab[k] - ga);
-    }
-    if (t == 0) *counter = 0;
 }
 
-// w -= V h (nk vectors, in groups of 8 whose loads are issued together) and out[0] = ||w||
-// (new w), reduced in the last block.
+// w -= V h (nk vectors, in groups of 8 whose loads are issued together) and per-block partials
+// of ||w||^2 (new w).
 __global__ __launch_bounds__(KT) void axpy_norm_k(int64_t n, int nk, const double *__restrict__ V,
                                                   int64_t ldv, const double *__restrict__ h,
-                                                  double *__restrict__ w, double *__restrict__ partial,
-                                                  double *__restrict__ out, int *__restrict__ counter)
+                                                  double *__restrict__ w, double *__restrict__ partial)
 {
     constexpr int KB = 8;
     __shared__ double red[CG_WAVES];
@@ -384,16 +351,6 @@ __global__ __launch_bounds__(KT) void axpy_norm_k(int64_t n, int nk, const doubl
         double sum = 0.0;
         for (int q = 0; q < CG_WAVES; ++q) sum += red[q];
         partial[blockIdx.x] = sum;
-    }
-    if (!last_block(counter)) return;
-    if (wv == 0) {
-        double sum = 0.0;
-        for (int b = lane; b < (int)gridDim.x; b += 64) sum += partial[b];
-        sum = wave_sum(sum);
-        if (lane == 0) {
-            out[0] = sqrt(sum);
-            *counter = 0;
-        }
     }
 }
 
@@ -493,44 +450,44 @@ int kry_multidot2(int64_t n, int nk, const double *V, int64_t ldv, const double 
 }
 
 int kry_cgs_project(int64_t n, int nk, const double *V, int64_t ldv, const double *w, const double *u,
-                    double *partial, double *ab, double *G, int ldg, double *h, int *counter,
-                    hipStream_t st)
+                    double *partial, double *ab, double *G, int ldg, double *h, hipStream_t st)
 {
     if ((n | ldv) & 1 || ((uintptr_t)V | (uintptr_t)w | (uintptr_t)u) & 15) {
         set_error("CGS projection needs even lengths and 16-byte aligned vectors");
-        return FSI_ERR_ARG;
-    }
-    if (nk > KRY_FUSED_MAXK) {
-        set_error("CGS projection supports at most %d basis vectors (got %d)", CG_WAVES * CG_MAXK, nk);
         return FSI_ERR_ARG;
     }
     switch ((nk + CG_WAVES - 1) / CG_WAVES) {
 #define FSI_CGS_CASE(KQ)                                                                           \
     case KQ:                                                                                       \
         hipLaunchKernelGGL(cgs_project_k<KQ>, dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, w, u,   \
-                           partial, ab, G, ldg, h, counter);                                       \
+                           partial);                                                               \
         break;
         FSI_CGS_CASE(1) FSI_CGS_CASE(2) FSI_CGS_CASE(3) FSI_CGS_CASE(4) FSI_CGS_CASE(5)
         FSI_CGS_CASE(6) FSI_CGS_CASE(7) FSI_CGS_CASE(8) FSI_CGS_CASE(9) FSI_CGS_CASE(10)
         FSI_CGS_CASE(11) FSI_CGS_CASE(12) FSI_CGS_CASE(13)
 #undef FSI_CGS_CASE
     default:
-        set_error("CGS projection: bad basis size %d", nk);
+        set_error("CGS projection supports at most %d basis vectors (got %d)", KRY_FUSED_MAXK, nk);
         return FSI_ERR_ARG;
     }
+    FSI_LAUNCH_CHECK();
+    hipLaunchKernelGGL(reduce_partials_k, dim3(2 * nk), dim3(KT), 0, st, 2 * nk, KRY_NB, partial, ab, 0);
+    FSI_LAUNCH_CHECK();
+    hipLaunchKernelGGL(gram_coeffs_k, dim3(1), dim3(64), 0, st, nk, ab, G, ldg, h);
     FSI_LAUNCH_CHECK();
     return FSI_OK;
 }
 
 int kry_axpy_norm(int64_t n, int nk, const double *V, int64_t ldv, const double *h, double *w,
-                  double *partial, double *out, int *counter, hipStream_t st)
+                  double *partial, double *out, hipStream_t st)
 {
     if ((n | ldv) & 1 || ((uintptr_t)V | (uintptr_t)w) & 15) {
         set_error("CGS update needs even lengths and 16-byte aligned vectors");
         return FSI_ERR_ARG;
     }
-    hipLaunchKernelGGL(axpy_norm_k, dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, h, w, partial, out,
-                       counter);
+    hipLaunchKernelGGL(axpy_norm_k, dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, h, w, partial);
+    FSI_LAUNCH_CHECK();
+    hipLaunchKernelGGL(reduce_partials_k, dim3(1), dim3(KT), 0, st, 1, KRY_NB, partial, out, 1);
     FSI_LAUNCH_CHECK();
     return FSI_OK;
 }

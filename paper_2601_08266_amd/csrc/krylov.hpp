@@ -26,15 +26,13 @@ int kry_multidot2(int64_t n, int nk, const double *V, int64_t ldv, const double 
                   double *partial, double *out, hipStream_t st);
 // Gram column update and twice-projected coefficients (see krylov.hip)
 int kry_gram_coeffs(int nk, const double *ab, double *G, int ldg, double *h, hipStream_t st);
-// One launch each (the last block reduces the per-block partials in a fixed order; counter is a
-// zeroed device int that the kernel leaves at zero):
+// CGS2 step kernels (16-byte loads, per-block partials reduced in a fixed order):
 // ab = [V^T w; V^T u], Gram column j = nk - 1 from V^T u, h = a + (a - G a)  (nk <= 52)
 int kry_cgs_project(int64_t n, int nk, const double *V, int64_t ldv, const double *w, const double *u,
-                    double *partial, double *ab, double *G, int ldg, double *h, int *counter,
-                    hipStream_t st);
+                    double *partial, double *ab, double *G, int ldg, double *h, hipStream_t st);
 // w -= V h and out[0] = ||w||
 int kry_axpy_norm(int64_t n, int nk, const double *V, int64_t ldv, const double *h, double *w,
-                  double *partial, double *out, int *counter, hipStream_t st);
+                  double *partial, double *out, hipStream_t st);
 int kry_update(int64_t n, int nk, fsi_dtype dz, const void *Z, int64_t ldz, const double *y, double *x,
                hipStream_t st);
 

@@ -23,7 +23,7 @@ import torch
 import fsi_workloads as W
 
 from . import axpby, norm2
-from .learned import LearnedWarmStart
+from .learned import LearnedWarmStart, linear_extrapolation_guess, quadratic_extrapolation_guess
 from .stepper import ChannelRun
 
 
@@ -41,8 +41,10 @@ def _solve_modes(run, lw, k, modes):
         gf = None
         if lw is not None and mode.startswith("nn"):
             gf = lw.guess
-        elif lw is not None and mode.startswith("extrap"):
-            gf = lw.extrapolation_guess
+        elif mode.startswith("extrap3"):
+            gf = quadratic_extrapolation_guess
+        elif mode.startswith("extrap"):
+            gf = linear_extrapolation_guess
         rec = run.step(guess_fn=gf, inner=inner, record=False)
         out[mode] = dict(newton=rec.newton_iters, krylov=rec.krylov_iters, ms_newton=rec.ms_newton,
                          ms_guess=rec.ms_guess, res_plain=rec.res_plain, res_guess=rec.res_guess,
@@ -82,7 +84,7 @@ def warmstart_c4(steps=200, train_end=100, epochs=20, lr=1e-3, eval_stride=1, se
                           out_shift=[float(v) for v in lw.out_shift],
                           out_scale=[float(v) for v in lw.out_scale])
         torch.save(sd, save_path)
-    modes = ["plain_f64", "plain_mixed", "extrap_mixed", "nn_mixed"]
+    modes = ["plain_f64", "plain_mixed", "extrap_mixed", "extrap3_mixed", "nn_mixed"]
     rows = []
     for k in range(train_end, steps, eval_stride):
         r = _solve_modes(run, lw, k, modes)
@@ -110,8 +112,10 @@ def warmstart_c4(steps=200, train_end=100, epochs=20, lr=1e-3, eval_stride=1, se
             "newton_iters": round(agg(m, "newton"), 3),
             "krylov_iters": round(agg(m, "krylov"), 1),
         }
-    for m in ("extrap_mixed", "nn_mixed"):
-        summary[m]["guess_used_frac"] = statistics.mean(1.0 if r[m]["used_guess"] else 0.0 for r in rows)
+    for m in ("extrap_mixed", "extrap3_mixed", "nn_mixed"):
+        summary[m]["guess_used_frac"] = statistics.mean(1.0 if r[m]["used_guess"] is True else 0.0 for r in rows)
+        summary[m]["extrapolation_fallback_frac"] = statistics.mean(
+            1.0 if r[m]["used_guess"] == "extrapolation" else 0.0 for r in rows)
         summary[m]["res_ratio_median"] = statistics.median(r[m]["res_guess"] / r[m]["res_plain"] for r in rows)
     for m in modes[1:]:
         summary[m]["max_rel_diff_vs_plain_f64"] = max(r[m]["rel_diff_vs_plain_f64"] for r in rows)
@@ -141,7 +145,7 @@ def large_c5(lw_c4=None, warmup_steps=3, state_path=None):
         lw.in_shift, lw.in_scale = list(nm["in_shift"]), list(nm["in_scale"])
         lw.out_shift, lw.out_scale = list(nm["out_shift"]), list(nm["out_scale"])
     k = run.n
-    modes = ["plain_f64", "plain_mixed"] + (["extrap_mixed", "nn_mixed"] if lw is not None else [])
+    modes = ["plain_f64", "plain_mixed", "extrap_mixed", "extrap3_mixed"] + (["nn_mixed"] if lw is not None else [])
     r = _solve_modes(run, lw, k, modes)
     for m in modes:
         _log(f"c5 step {k + 1} {m}: {r[m]['newton']}N/{r[m]['krylov']}K "

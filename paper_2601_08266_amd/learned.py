@@ -22,8 +22,11 @@ from typing import List, Optional
 import numpy as np
 import torch
 
+from . import axpby
 from . import warmstart as ws
 from .stepper import ChannelRun, StepRecord
+
+IN_CH = 8
 
 
 class LearnedWarmStart:
@@ -31,10 +34,10 @@ class LearnedWarmStart:
         self.run = run
         self.N = run.N
         self.dims = run.g.nodes_per_axis
-        self.net = ws.WarmStartNet(self.dims, in_ch=ws.IN_CH_RES, hidden=hidden, n_hidden=n_hidden,
+        self.net = ws.WarmStartNet(self.dims, in_ch=IN_CH, hidden=hidden, n_hidden=n_hidden,
                                    out_ch=ws.OUT_CH, seed=seed, device=run.dev)
-        self.in_shift = [0.0] * ws.IN_CH_RES
-        self.in_scale = [1.0] * ws.IN_CH_RES
+        self.in_shift = [0.0] * IN_CH
+        self.in_scale = [1.0] * IN_CH
         self.out_shift = [0.0] * 4
         self.out_scale = [1.0] * 4
         self.buf32 = torch.empty(self.N * 32, dtype=torch.float32, device=run.dev)
@@ -76,21 +79,21 @@ class LearnedWarmStart:
 
     def fit_normalisation(self, hist, ks):
         N = self.N
-        sin = np.zeros((ws.IN_CH_RES, 2))
+        sin = np.zeros((IN_CH, 2))
         sout = np.zeros((4, 2))
         recs = self._samples(hist, ks)
         for r in recs:
             ws.pack(N, 32, self.input_sources(r.R_ex, r.rn_ex, r.u_prev, r.s, False), self.buf32)
-            sin += np.array(ws.moments(N, 32, self.buf32)[:ws.IN_CH_RES])
+            sin += np.array(ws.moments(N, 32, self.buf32)[:IN_CH])
             ws.pack(N, 32, self.target_sources(r, False), self.buf32)
             sout += np.array(ws.moments(N, 32, self.buf32)[:4])
         cnt = float(N * len(recs))
         mean = sin[:, 0] / cnt
         rms = np.sqrt(np.maximum(sin[:, 1] / cnt, 0.0))
         std = np.sqrt(np.maximum(sin[:, 1] / cnt - mean ** 2, 0.0))
-        shift, scale = np.zeros(ws.IN_CH_RES), np.ones(ws.IN_CH_RES)
+        shift, scale = np.zeros(IN_CH), np.ones(IN_CH)
         # residual channels: scale only (keeps the map linear); fields: mean and std
-        for c in range(ws.IN_CH_RES):
+        for c in range(IN_CH):
             if c < 4:
                 scale[c] = 1.0 / rms[c] if rms[c] > 0 else 1.0
             else:
@@ -144,6 +147,21 @@ class LearnedWarmStart:
         ws.unpack(N, 32, out, ctx["x_ex"], [0.0] * 4, scale, x, mask=run.mask, gD=run.gD)
         return x
 
-    def extrapolation_guess(self, run: ChannelRun, ctx):
-        """The network's backbone alone: 2 x^n - x^{n-1} with the Dirichlet values imposed."""
-        return ctx["x_ex"]
+
+
+def linear_extrapolation_guess(run: ChannelRun, ctx):
+    """The network's backbone alone: 2 x^n - x^{n-1} with the Dirichlet values imposed."""
+    return ctx["x_ex"]
+
+
+def quadratic_extrapolation_guess(run: ChannelRun, ctx):
+    """3 x^n - 3 x^{n-1} + x^{n-2} with the new Dirichlet values (a comparison guess)."""
+    if run.n < 2:
+        return None
+    x = torch.empty_like(run.x)
+    axpby(3.0, run.history[run.n].x, 0.0, x)
+    axpby(-3.0, run.history[run.n - 1].x, 1.0, x)
+    axpby(1.0, run.history[run.n - 2].x, 1.0, x)
+    out = torch.empty_like(x)
+    ws.unpack(run.N, 32, run.zero_out, x, [0, 0, 0, 0], [1, 1, 1, 1], out, mask=run.mask, gD=run.gD)
+    return out

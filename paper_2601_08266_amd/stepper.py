@@ -7,7 +7,8 @@ algorithm with the stand-ins of this library:
      interface band of s, per-cell DLM blocks, lamg = B^T (kappa g);
   2. the inflow value and the Dirichlet data g_D;
   3. the initial guess: the previous state with the Dirichlet values imposed
-     (plain), or a learned prediction kept only if its residual is smaller;
+     (plain), or a proposed (e.g. learned) guess kept only if its residual is the
+     smallest among the plain guess, the extrapolation 2x^n - x^{n-1} and itself;
   4. Newton to ||R|| <= rel_tol ||R(x_plain)|| (the same absolute threshold for
      any guess, so a guess can change the work, never the answer);
   5. the multiplier lambda = kappa (g - B u) of the new state, spread to the
@@ -44,7 +45,7 @@ class StepRecord:
     ms_guess: float = 0.0
     res_plain: float = 0.0
     res_guess: float = 0.0
-    used_guess: bool = False
+    used_guess: object = False    # True (the proposed guess), "extrapolation" or False (plain)
     res_hist: tuple = ()
     x_ex: Optional[torch.Tensor] = None     # extrapolated guess 2 x^{n-1} - x^{n-2} of this step
     R_ex: Optional[torch.Tensor] = None     # its residual
@@ -160,11 +161,14 @@ class ChannelRun:
         if guess_fn is not None:
             xg = guess_fn(self, ctx)
             if xg is not None:
-                r_g = self.residual_norm(P64, xg, lamg)
-                if math.isfinite(r_g) and r_g < r_plain:
-                    x0, r_guess, used = xg, r_g, True
-                else:
-                    r_guess = r_g
+                # safeguard: keep the candidate with the smallest residual among the plain guess,
+                # the extrapolation (its residual is already known) and the proposed guess
+                r_g = r_guess = self.residual_norm(P64, xg, lamg)
+                if ctx["x_ex"] is not None and xg is not ctx["x_ex"] and ctx["rn_ex"] < r_plain and \
+                        not (math.isfinite(r_g) and r_g <= ctx["rn_ex"]):
+                    x0, r_guess, used = ctx["x_ex"], ctx["rn_ex"], "extrapolation"
+                elif math.isfinite(r_g) and r_g < r_plain:
+                    x0, used = xg, True
         torch.cuda.synchronize()
         ms_guess = (time.perf_counter() - t_g0) * 1e3
         inner = inner if inner is not None else self.inner

@@ -22,7 +22,6 @@ from . import _lib as L
 from ._lib import FsiNnPackSpec, FsiNnUnpackSpec
 
 IN_CH = 19        # history-based input set (states n, n-1, n-2, forcing, inflow)
-IN_CH_RES = 8     # residual-based input set (extrapolation residual, velocity, s)
 OUT_CH = 4
 
 
