@@ -7,13 +7,14 @@
 // i + nx (j + ny k)); weights [27][Cout][Cin] with tap = dx + 3 (dy + 3 dz)
 // reading the neighbour at offset (dx - 1, dy - 1, dz - 1); zero padding.
 //
-// Forward / data gradient (implicit GEMM): a block owns 64 voxels x 64 output
-// channels, each wave 16 voxels x 64 channels (4 accumulator tiles).  The K
-// loop runs over the 27 taps x Cin/32 chunks; per step a lane loads 8
-// consecutive input channels of its (shifted) voxel and 8 consecutive input
-// channels of 4 output channels' weights.  The data gradient is the same
-// kernel on flipped, transposed weights, with the ReLU mask of the previous
-// layer applied in the epilogue.
+// Forward / data gradient (implicit GEMM): a block owns 256 voxels x 64 output
+// channels, each wave 64 voxels x 64 channels (16 accumulator tiles).  The K
+// loop runs over the 27 taps x Cin/32 chunks; per step the block stages the
+// chunk's 64 x 32 weights in LDS (double buffered, one barrier per step), and
+// each lane loads 8 consecutive input channels of its 4 (shifted) voxels, so a
+// weight fragment feeds 4 MFMAs and an input fragment 4.  The data gradient is
+// the same kernel on flipped, transposed weights, with the ReLU mask of the
+// previous layer applied in the epilogue.
 // Weight gradient (split K): block (voxel range, tap) stages 32 voxels of dY
 // and of the shifted input in LDS and accumulates the 64x64 tap block with 16
 // MFMA tiles; ranges are summed in a fixed order afterwards (deterministic).
@@ -49,6 +50,14 @@ __device__ __forceinline__ bf8 zero8()
 }
 
 // ---------------------------------------------------------------- forward / dgrad
+constexpr int CF_MT = 4;                 // 16-voxel M tiles per wave
+constexpr int CF_VB = 64 * CF_MT;        // voxels per block (4 waves)
+constexpr int CF_WS = 40;                // LDS row stride (bf16) of a staged weight chunk: 32 + 8 pad
+
+// 16 zero bytes that out-of-range fragment loads read instead (a pointer choice before the
+// load, so the loads can stay in flight: no select on the loaded value)
+__device__ __attribute__((aligned(16))) uint16_t cf_zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
 __global__ __launch_bounds__(256) void conv_fwd_k(int nx, int ny, int nz, int cin, int cout,
                                                   const uint16_t *__restrict__ X,
                                                   const uint16_t *__restrict__ W,
@@ -57,52 +66,101 @@ __global__ __launch_bounds__(256) void conv_fwd_k(int nx, int ny, int nz, int ci
                                                   uint16_t *__restrict__ Ybf,
                                                   float *__restrict__ Yf)
 {
+    // weights of one (tap, 32-channel chunk) for the block's 64 output channels, double buffered
+    __shared__ __attribute__((aligned(16))) uint16_t sW[2][64 * CF_WS];
     const int64_t V = (int64_t)nx * ny * nz;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t v0 = (int64_t)blockIdx.x * 64 + 16 * w;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t vw = (int64_t)blockIdx.x * CF_VB + 64 * w;     // first voxel of this wave
     const int co0 = blockIdx.y * 64;
     const int ntiles = (cout - co0) >= 64 ? 4 : (cout - co0) / 16;
-    const int64_t va = v0 + (lane & 15);
-    const bool vin = va < V;
-    const int ax = (int)(va % nx), ay = (int)((va / nx) % ny), az = (int)(va / ((int64_t)nx * ny));
     const int kq = 8 * (lane >> 4);
-    f4 acc[4];
+    int ax[CF_MT], ay[CF_MT], az[CF_MT];
+    bool vin[CF_MT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = (f4){0.f, 0.f, 0.f, 0.f};
-    for (int tap = 0; tap < 27; ++tap) {
+    for (int m = 0; m < CF_MT; ++m) {
+        const int64_t va = vw + 16 * m + (lane & 15);
+        vin[m] = va < V;
+        ax[m] = (int)(va % nx);
+        ay[m] = (int)((va / nx) % ny);
+        az[m] = (int)(va / ((int64_t)nx * ny));
+    }
+    f4 acc[CF_MT][4];
+#pragma unroll
+    for (int m = 0; m < CF_MT; ++m)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[m][q] = (f4){0.f, 0.f, 0.f, 0.f};
+    const int nchunks = cin / 32, nsteps = 27 * nchunks;
+    // software pipeline: the weights of step s+1 and the input fragments of step s+1 are in
+    // flight while step s runs its MFMAs; the weights go to the other LDS buffer at the end
+    // thread t stages 8 channels of output channel co0 + t/4
+    const int sco = t >> 2, sci = (t & 3) * 8;
+    auto load_w = [&](int step) -> bf8 {
+        const int tap = step / nchunks, c0 = (step % nchunks) * 32;
+        const uint16_t *p = co0 + sco < cout ? W + ((int64_t)tap * cout + co0 + sco) * cin + c0 + sci : cf_zero;
+        return load8(p);
+    };
+    auto load_a = [&](int step, bf8 *a) {
+        const int tap = step / nchunks, c0 = (step % nchunks) * 32;
         const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
-        const int xs = ax + dx, ys = ay + dy, zs = az + dz;
-        const bool inb = vin && xs >= 0 && xs < nx && ys >= 0 && ys < ny && zs >= 0 && zs < nz;
-        const int64_t vs = xs + (int64_t)nx * (ys + (int64_t)ny * zs);
-        const uint16_t *wt = W + (int64_t)tap * cout * cin;
-        for (int c0 = 0; c0 < cin; c0 += 32) {
-            const bf8 a = inb ? load8(X + vs * cin + c0 + kq) : zero8();
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                if (t < ntiles) {
-                    const int co = co0 + 16 * t + (lane & 15);
-                    const bf8 b = load8(wt + (int64_t)co * cin + c0 + kq);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
-                }
+        for (int m = 0; m < CF_MT; ++m) {
+            const int xs = ax[m] + dx, ys = ay[m] + dy, zs = az[m] + dz;
+            const bool inb = vin[m] && xs >= 0 && xs < nx && ys >= 0 && ys < ny && zs >= 0 && zs < nz;
+            const int64_t vs = xs + (int64_t)nx * (ys + (int64_t)ny * zs);
+            a[m] = load8(inb ? X + vs * cin + c0 + kq : cf_zero);
+        }
+    };
+    *reinterpret_cast<bf8 *>(&sW[0][sco * CF_WS + sci]) = load_w(0);
+    bf8 a0[CF_MT], a1[CF_MT];
+    load_a(0, a0);
+    bf8 w_nxt = nsteps > 1 ? load_w(1) : zero8();
+    __syncthreads();
+    // one step: MFMAs on `a_use` (this step's input fragments) while `a_fill` receives the next
+    // step's; the two register sets swap roles every step (the loop below is unrolled by two)
+    auto run_step = [&](int step, bf8 *a_use, bf8 *a_fill) {
+        const int buf = step & 1;
+        const bool more = step + 1 < nsteps;
+        if (more) load_a(step + 1, a_fill);
+        bf8 bq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            bq[q] = *reinterpret_cast<const bf8 *>(&sW[buf][(16 * q + (lane & 15)) * CF_WS + kq]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q < ntiles) {
+#pragma unroll
+                for (int m = 0; m < CF_MT; ++m)
+                    acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_use[m], bq[q], acc[m][q], 0, 0, 0);
             }
         }
+        if (more) {
+            *reinterpret_cast<bf8 *>(&sW[buf ^ 1][sco * CF_WS + sci]) = w_nxt;
+            if (step + 2 < nsteps) w_nxt = load_w(step + 2);
+        }
+        __syncthreads();
+    };
+    for (int step = 0; step < nsteps; step += 2) {
+        run_step(step, a0, a1);
+        if (step + 1 < nsteps) run_step(step + 1, a1, a0);
     }
     // D layout: lane holds rows 4*(lane/16) + e (voxels), column lane%16 (channel)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        if (t >= ntiles) continue;
-        const int co = co0 + 16 * t + (lane & 15);
+    for (int q = 0; q < 4; ++q) {
+        if (q >= ntiles) continue;
+        const int co = co0 + 16 * q + (lane & 15);
         const float bv = bias ? bias[co] : 0.f;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int64_t vo = v0 + 4 * (lane >> 4) + e;
-            if (vo >= V) continue;
-            float val = acc[t][e] + bv;
-            if (gate && !(bf2f(gate[vo * cout + co]) > 0.f)) val = 0.f;
-            if (relu) val = val > 0.f ? val : 0.f;
-            if (Yf) Yf[vo * cout + co] = val;
-            if (Ybf) Ybf[vo * cout + co] = f2bf(val);
-        }
+        for (int m = 0; m < CF_MT; ++m)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t vo = vw + 16 * m + 4 * (lane >> 4) + e;
+                if (vo >= V) continue;
+                float val = acc[m][q][e] + bv;
+                if (gate && !(bf2f(gate[vo * cout + co]) > 0.f)) val = 0.f;
+                if (relu) val = val > 0.f ? val : 0.f;
+                if (Yf) Yf[vo * cout + co] = val;
+                if (Ybf) Ybf[vo * cout + co] = f2bf(val);
+            }
     }
 }
 
@@ -344,7 +402,7 @@ int nn_conv_fwd(const int32_t *dims, int cin, int cout, const uint16_t *X, const
 {
     ProfileScope prof("conv3d_fwd", st);
     const int64_t V = (int64_t)dims[0] * dims[1] * dims[2];
-    dim3 grid((unsigned)((V + 63) / 64), (unsigned)((cout + 63) / 64));
+    dim3 grid((unsigned)((V + CF_VB - 1) / CF_VB), (unsigned)((cout + 63) / 64));
     hipLaunchKernelGGL(conv_fwd_k, grid, dim3(256), 0, st, dims[0], dims[1], dims[2], cin, cout, X, W,
                        bias, relu, gate, Ybf, Yf);
     FSI_LAUNCH_CHECK();
