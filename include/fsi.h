@@ -283,7 +283,13 @@ int fsi_bjacobi_apply(const fsi_grid *grid, fsi_dtype dtype, const void *pinv, c
  *   J32   FP32 problem (same data rounded to FP32) when inner = F32, else NULL
  *   pinv  [16][N] inverse blocks in the inner precision, or NULL (no preconditioner)
  *   b     double [4][N];  x  double [4][N] in: initial guess, out: solution
- *   stats HOST out (may be NULL).  SYNCS (once per Arnoldi step).
+ *   stats HOST out (may be NULL).  SYNCS: the Arnoldi steps are enqueued
+ *         back to back; the host reads each step's coefficients from pinned
+ *         memory one step behind the device (so a cycle may compute one step
+ *         past its stopping point; that step is not used), and it waits for
+ *         the stream at every restart.  The library keeps one pinned host
+ *         buffer and one set of events per host thread for this, allocated
+ *         on first use and kept until the process ends.
  * Returns FSI_OK when ||b - J x||_2 <= rtol ||b||_2 (FP64 residual),
  * FSI_ERR_NOT_CONVERGED (x = last iterate) on the iteration cap or stagnation,
  * FSI_ERR_NAN, FSI_ERR_BREAKDOWN.
