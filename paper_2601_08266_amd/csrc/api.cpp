@@ -96,8 +96,10 @@ BrickLayout brick_layout(const Geo &g)
 
 size_t vms_workspace_bytes(const Geo &g, fsi_dtype dt)
 {
-    // brick partial sums: one grid-shaped [4][N] array per brick parity class (8)
-    return align_up((size_t)8 * 4 * (size_t)g.N * (dt == FSI_F64 ? 8 : 4));
+    // brick partial sums: one [4][nn2][nn1][lx] array per brick parity class (8)
+    const BrickLayout b = brick_layout(g);
+    const PartIndex pi(g.nn, b.nbx, g.p * b.bx);
+    return align_up((size_t)8 * (size_t)pi.cls * (dt == FSI_F64 ? 8 : 4));
 }
 
 template <typename T>

@@ -40,6 +40,28 @@ struct GatherOpts {
     const T *gD = nullptr;            // [3][N]: Dirichlet rows become x - gD instead of x
 };
 
+// Brick partial sums: bricks whose indices have equal parities (mod 2 per axis) share no
+// node, so each of the 8 classes owns one [4][nn2][nn1][lx] array.  Along x a class only
+// holds its own bricks' nodes, packed: brick b (span S = P * bricks cells) keeps its S + 1
+// nodes at slot (b / 2) (S + 1) + (node x - S b), so the rows carry no holes.
+struct PartIndex {
+    int64_t lx, plane, field, cls;
+    int span;   // nodes per brick along x minus one (P * BX)
+    __host__ __device__ PartIndex(const int32_t nn[3], int nbx, int span_) : span(span_)
+    {
+        lx = (int64_t)(span_ + 1) * ((nbx + 1) / 2);
+        plane = lx * nn[1];
+        field = plane * nn[2];
+        cls = 4 * field;
+    }
+    // offset of field 0 of node (gx, gy, gz) in the array of x-brick bxb's class (bxb holds gx)
+    __host__ __device__ int64_t at(int cls_id, int bxb, int gx, int gy, int gz) const
+    {
+        return cls_id * cls + (int64_t)gz * plane + (int64_t)gy * lx + (int64_t)(bxb >> 1) * (span + 1) +
+               (gx - span * bxb);
+    }
+};
+
 struct BrickLayout {
     int bx, by, bz;   // cells per brick
     int nbx, nby, nbz;

@@ -534,11 +534,11 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
                     }
                 }
             }
-            // bricks of one parity class never share a node: one grid-shaped array per class
-            T *pc = part + (int64_t)((bx & 1) + 2 * (by & 1) + 4 * (bz & 1)) * 4 * N;
-            const int64_t node = gx + (int64_t)g.nn[0] * gy + nn01 * gz;
+            // bricks of one parity class never share a node: one array per class
+            const PartIndex pi(g.nn, nbx, Q1_BX);
+            T *pc = part + pi.at((bx & 1) + 2 * (by & 1) + 4 * (bz & 1), bx, gx, gy, gz);
 #pragma unroll
-            for (int f = 0; f < 4; ++f) pc[f * N + node] = sum[f];
+            for (int f = 0; f < 4; ++f) pc[f * pi.field] = sum[f];
         }
     }
 }
@@ -546,8 +546,9 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
 }  // namespace
 
 // Node gather shared by all orders: sums the brick partials (bricks of BXxBYxBZ cells of
-// order P; part holds one grid-shaped [4][N] array per brick parity class, so the reads are
-// coalesced) and, optionally, DLM corner sums of occupied neighbour cells; then Dirichlet rows.
+// order P; part holds one x-packed [4][nn2][nn1][lx] array per brick parity class, so the
+// reads are coalesced and dense) and, optionally, DLM corner sums of occupied neighbour
+// cells; then Dirichlet rows.
 template <typename T, int P, int BX, int BY, int BZ>
 __global__ __launch_bounds__(256) void vms_gather(Geo g, const T *__restrict__ part, int nbx,
                                                   int nby, int nbz, const T *__restrict__ x,
@@ -580,13 +581,14 @@ __global__ __launch_bounds__(256) void vms_gather(Geo g, const T *__restrict__ p
         if (b < nbz) bzs[nzb++] = b;
     }
     T acc[4] = {T(0), T(0), T(0), T(0)};
+    const PartIndex pi(g.nn, nbx, P * BX);
     for (int iz = 0; iz < nzb; ++iz)
         for (int iy = 0; iy < nyb; ++iy)
             for (int ix = 0; ix < nxb; ++ix) {
                 const int cls = (bxs[ix] & 1) + 2 * (bys[iy] & 1) + 4 * (bzs[iz] & 1);
-                const T *pc = part + (int64_t)cls * 4 * g.N + node;
+                const T *pc = part + pi.at(cls, bxs[ix], gx, gy, gz);
 #pragma unroll
-                for (int f = 0; f < 4; ++f) acc[f] += pc[f * g.N];
+                for (int f = 0; f < 4; ++f) acc[f] += pc[f * pi.field];
             }
     if (csum != nullptr) {
         // cells containing the node along each axis: c with P c <= g <= P c + P

@@ -375,11 +375,11 @@ __global__ __launch_bounds__(256) void vms_q2_cells(Geo g, VmsConst<T> k, const 
         const int lx = l % BN, ly = (l / BN) % BN, lz = l / (BN * BN);
         const int gx = 2 * bxi * Q2_BX + lx, gy = 2 * byi * Q2_BY + ly, gz = 2 * bzi * Q2_BZ + lz;
         if (gx < g.nn[0] && gy < g.nn[1] && gz < g.nn[2]) {
-            // bricks of one parity class never share a node: one grid-shaped array per class
-            T *pc = part + (int64_t)((bxi & 1) + 2 * (byi & 1) + 4 * (bzi & 1)) * 4 * g.N;
-            const int64_t node = gx + (int64_t)g.nn[0] * (gy + (int64_t)g.nn[1] * gz);
+            // bricks of one parity class never share a node: one array per class
+            const PartIndex pi(g.nn, nbx, 2 * Q2_BX);
+            T *pc = part + pi.at((bxi & 1) + 2 * (byi & 1) + 4 * (bzi & 1), bxi, gx, gy, gz);
 #pragma unroll
-            for (int f = 0; f < 4; ++f) pc[f * g.N + node] = acc[f * Q2_NL + l];
+            for (int f = 0; f < 4; ++f) pc[f * pi.field] = acc[f * Q2_NL + l];
         }
     }
 }

@@ -9,6 +9,9 @@ learns a fixed, scale-free local approximation of the inverse operator); the
 channels are further normalised with training-set statistics.  A network that
 has learned nothing returns the extrapolation; the stepper keeps the guess only
 if its residual beats the plain one.
+The network's correction c is applied with the step length a that minimises the
+linearised residual ||R_ex + a (R(x_ex + c) - R_ex)|| (one extra residual
+evaluation), so a correction that points the right way is never overshot.
 
 Inputs (8 channels): R_ex / ||R_ex|| (u, v, w, p rows), u, v, w of the previous
 state, s.  Target (4): e / ||R_ex||.
@@ -22,7 +25,7 @@ from typing import List, Optional
 import numpy as np
 import torch
 
-from . import axpby
+from . import axpby, dot
 from . import warmstart as ws
 from .stepper import ChannelRun, StepRecord
 
@@ -30,8 +33,10 @@ IN_CH = 8
 
 
 class LearnedWarmStart:
-    def __init__(self, run: ChannelRun, hidden=64, n_hidden=8, seed=0):
+    def __init__(self, run: ChannelRun, hidden=64, n_hidden=8, seed=0, line_search=True):
         self.run = run
+        self.line_search = line_search
+        self.last_step = 1.0
         self.N = run.N
         self.dims = run.g.nodes_per_axis
         self.net = ws.WarmStartNet(self.dims, in_ch=IN_CH, hidden=hidden, n_hidden=n_hidden,
@@ -142,9 +147,23 @@ class LearnedWarmStart:
         ws.pack(N, 32, self.input_sources(ctx["R_ex"], ctx["rn_ex"], u_prev, ctx["s"]), self.buf32)
         ws.to_bf16(self.buf32, self.buf_bf)
         out = self.net.forward(self.buf_bf)
-        x = torch.empty(4 * N, dtype=torch.float64, device=run.dev)
+        x1 = torch.empty(4 * N, dtype=torch.float64, device=run.dev)
         scale = [sc / ctx["rn_ex"] for sc in self.out_scale]
-        ws.unpack(N, 32, out, ctx["x_ex"], [0.0] * 4, scale, x, mask=run.mask, gD=run.gD)
+        ws.unpack(N, 32, out, ctx["x_ex"], [0.0] * 4, scale, x1, mask=run.mask, gD=run.gD)
+        if not self.line_search:
+            return x1
+        # step length along the correction c = x1 - x_ex: near the solution R is affine in x, so
+        # R(x_ex + a c) ~ R_ex + a D with D = R(x1) - R_ex, minimised by a = -<R_ex, D> / <D, D>
+        run.residual_norm(ctx["P64"], x1, ctx["lamg"])
+        D = run.R.clone()
+        axpby(-1.0, ctx["R_ex"], 1.0, D)
+        dd = dot(D, D)
+        if not dd > 0.0:
+            return x1
+        a = -dot(ctx["R_ex"], D) / dd
+        self.last_step = a
+        x = ctx["x_ex"].clone()
+        axpby(a, x1, 1.0 - a, x)          # x_ex + a (x1 - x_ex); Dirichlet values are kept
         return x
 
 
