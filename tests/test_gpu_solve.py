@@ -82,8 +82,8 @@ def test_bjacobi_blocks_and_inverse(case):
     assert np.abs(z - zr).max() <= 1e-12 * np.abs(zr).max()
 
 
-@pytest.mark.parametrize("inner", ["f64", "f32"])
-def test_fgmres_c1_matches_dense_lu(inner):
+@pytest.mark.parametrize("inner,restart", [("f64", 50), ("f32", 50), ("f64", 80), ("f32", 64)])
+def test_fgmres_c1_matches_dense_lu(inner, restart):
     import torch
     import paper_2601_08266_amd as fsi
     cfg = W.CONFIGS["c1"]
@@ -97,13 +97,15 @@ def test_fgmres_c1_matches_dense_lu(inner):
     pinv64, pinv32, _, _ = fsi.bjacobi_setup(P["J64"])
     x = torch.zeros(4 * N, dtype=torch.float64, device="cuda")
     tdt = torch.float64 if inner == "f64" else torch.float32
-    opts = fsi.solve_opts(restart=50, max_iters=3000, rtol=1e-10, inner=tdt)
+    # restarts of 64 and 80 take the unfused CGS kernels past 52 basis vectors (restarts below
+    # about 45 stagnate on this problem, in the oracle's textbook FGMRES as well)
+    opts = fsi.solve_opts(restart=restart, max_iters=6000, rtol=1e-10, inner=tdt)
     rc, st = fsi.fgmres_solve(P["J64"], _t(b), x, opts, J32=P["J32"] if inner == "f32" else None,
                               pinv=pinv32 if inner == "f32" else pinv64)
     xs = x.cpu().numpy()
     res = np.linalg.norm(b - J @ xs) / np.linalg.norm(b)
     err = np.linalg.norm(xs - x_ref) / np.linalg.norm(x_ref)
-    print(f"fgmres c1 inner={inner}: iters {st.iters} cycles {st.cycles} oracle residual {res:.3e} "
+    print(f"fgmres c1 inner={inner} restart={restart}: iters {st.iters} cycles {st.cycles} oracle residual {res:.3e} "
           f"x err {err:.3e}")
     assert res <= 1.5e-10
     assert err <= 1e-6
