@@ -17,6 +17,9 @@ Contents (each function cites the passage of the paper it follows):
 * ``jacobian`` - the reduced 2x2 block system of section 2.4 with the
                  per-point solid stand-in, plus nodal 4x4 block-Jacobi blocks.
 * ``krylov``   - textbook flexible GMRES (right preconditioned, restarted).
+* ``schur``    - a block preconditioner from the 2x2 sub-matrices of section
+                 2.4's reduced system: nodal velocity blocks and a pressure
+                 Schur-complement Laplacian with one multigrid V-cycle.
 * ``newton``   - the nonlinear residual of one implicit step and Newton.
 * ``conv3d``   - 3x3x3 convolution layers for the learned warm start.
 """
