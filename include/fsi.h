@@ -270,9 +270,58 @@ int fsi_bjacobi_apply(const fsi_grid *grid, fsi_dtype dtype, const void *pinv, c
                       void *z, void *stream);
 
 /*
+ * Schur-complement block preconditioner (section 2.4: the reduced 2x2 block
+ * system J = [[F, G], [D, C]] is solved with block preconditioners built from
+ * its sub-matrices).  This member uses
+ *   F_hat = the nodal 3x3 velocity blocks of J (from fsi_bjacobi_setup's raw
+ *           blocks), inverted per node;
+ *   S_hat = a variable-coefficient pressure Laplacian -div(alpha grad p) on the
+ *           node lattice (trilinear elements of side h/p), standing in for
+ *           S = C - D F^{-1} G: the PSPG block C is tau_m times a Laplacian and
+ *           G^T F^{-1} G acts like one scaled by 1/(c_m + DLM density), so
+ *           alpha = tau_m + mean over the lattice cell's corners of
+ *           1/(c_m + max(d_A, 0)/v_A), d_A = (B^T kappa)_A, v_A the node's
+ *           lumped lattice volume; tau_m from the stabilisation-parameter
+ *           equation with the corner means of a and s.  Dirichlet rows of the
+ *           Laplacian: boundary nodes whose velocity is not fully prescribed
+ *           (node 0 if there is none).  S_hat^{-1} is one multigrid V(2,2)
+ *           cycle: Jacobi smoothing (weight 8/9), trilinear prolongation,
+ *           restriction = its transpose, alpha averaged 2x2x2 per coarser
+ *           level while all cell counts are even and the level has more than
+ *           512 nodes, the coarsest level (at most 1000 nodes) solved with a
+ *           dense inverse.
+ *   FSI_PC_SCHUR_DIAG: z_p = S_hat^{-1} v_p, z_u = F_hat^{-1} v_u.
+ *   FSI_PC_SCHUR_TRI:  z_p as above, z_u = F_hat^{-1} (v_u - [J (0, z_p)]_u)
+ *                      (the upper factor [[F_hat, G], [0, S_hat]]; one extra
+ *                      Jacobian apply per preconditioner apply).
+ * fsi_schur_size: bytes of the preconditioner object for a grid (0 if the
+ *   lattice cannot be coarsened to at most 1000 nodes).  The object holds the
+ *   coefficients, the inverses and the V-cycle's vectors: an apply writes into
+ *   it, so applies that share one object must not overlap.
+ * fsi_schur_setup: builds the object from the FP64 problem (a, s, dir_mask,
+ *   dlm_gram needed when n_occ > 0) and blocks = double [16][N], the raw nodal
+ *   blocks of fsi_bjacobi_setup for the same problem.  SYNCS (the coarsest
+ *   operator is factorised on the host).
+ * fsi_schur_apply: z = P^{-1} v ([4][N] device, precision J->dtype, not
+ *   overlapping); J is only applied in FSI_PC_SCHUR_TRI, with ws of at least
+ *   fsi_jacobian_workspace(J) bytes (ws may be NULL for FSI_PC_SCHUR_DIAG).
+ * fsi_schur_info: levels of the hierarchy, their lattice-cell counts
+ *   (ncell[3 l + d], up to 16 levels) and the byte offsets of each level's
+ *   FP64 alpha array inside the object (for inspection).
+ */
+typedef enum { FSI_PC_BJACOBI = 0, FSI_PC_SCHUR_DIAG = 1, FSI_PC_SCHUR_TRI = 2 } fsi_precond;
+size_t fsi_schur_size(const fsi_grid *grid);
+int fsi_schur_info(const fsi_grid *grid, int32_t *n_levels, int32_t *ncell, int64_t *alpha_offset);
+int fsi_schur_setup(const fsi_problem *P64, const double *blocks, void *pc, size_t pc_bytes,
+                    void *stream);
+int fsi_schur_apply(const fsi_problem *J, int32_t mode, void *pc, const void *v, void *z, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/*
  * fsi_fgmres_solve - solve J x = b with restarted flexible GMRES, right
- * preconditioned by the nodal block-Jacobi blocks (section 2.4: the reduced
- * system is solved iteratively with block preconditioners).
+ * preconditioned by the nodal block-Jacobi blocks or the Schur-complement block
+ * preconditioner (section 2.4: the reduced system is solved iteratively with
+ * block preconditioners).
  * FP64: Krylov basis, classical Gram-Schmidt with re-orthogonalisation, Givens
  * rotations, x, and the residual b - J x recomputed at every restart.
  * Inner precision (opts->inner): the preconditioner and Jacobian applies of
@@ -281,7 +330,9 @@ int fsi_bjacobi_apply(const fsi_grid *grid, fsi_dtype dtype, const void *pinv, c
  * fell by opts->inner_reduction or reached the target).
  *   J64   FP64 problem (true residuals; also the inner applies if inner = F64)
  *   J32   FP32 problem (same data rounded to FP32) when inner = F32, else NULL
- *   pinv  [16][N] inverse blocks in the inner precision, or NULL (no preconditioner)
+ *   pinv  opts->precond = FSI_PC_BJACOBI: [16][N] inverse blocks in the inner
+ *         precision, or NULL (no preconditioner); FSI_PC_SCHUR_*: the object of
+ *         fsi_schur_setup (its scratch vectors are written during the solve)
  *   b     double [4][N];  x  double [4][N] in: initial guess, out: solution
  *   stats HOST out (may be NULL).  SYNCS: the Arnoldi steps are enqueued
  *         back to back; the host reads each step's coefficients from pinned
@@ -300,6 +351,7 @@ typedef struct {
     double rtol;              /* relative FP64 residual target */
     fsi_dtype inner;          /* FSI_F32 (mixed precision) or FSI_F64 */
     double inner_reduction;   /* FP32 cycles stop at this relative reduction (e.g. 1e-5) */
+    int32_t precond;          /* fsi_precond (0: block-Jacobi) */
 } fsi_solve_opts;
 
 typedef struct {
@@ -317,9 +369,9 @@ int fsi_fgmres_solve(const fsi_problem *J64, const fsi_problem *J32, const void 
 /*
  * fsi_newton_solve - one implicit time step: Newton's method on
  * R(x) = 0 (fsi_vms_residual), each correction from J(u_k) dx = -R(x_k)
- * solved by fsi_fgmres_solve with the nodal block-Jacobi preconditioner of
- * J(u_k) (section 2.4: Newton iterations on the monolithic system, each solving
- * the reduced block system).  J(u_k) is the Picard/Oseen linearisation: the
+ * solved by fsi_fgmres_solve with the preconditioner opts->precond of J(u_k)
+ * (section 2.4: Newton iterations on the monolithic system, each solving the
+ * reduced block system).  J(u_k) is the Picard/Oseen linearisation: the
  * operator of fsi_vms_apply with advection field u_k plus the DLM block.
  *   P64   FP64 problem: s, dir_mask, point tables, kappa, dlm_gram (a ignored)
  *   P32   FP32 copy of the same data when opts->inner = FSI_F32, else NULL
@@ -335,6 +387,7 @@ typedef struct {
     int32_t restart, max_krylov;
     fsi_dtype inner;          /* inner precision of the Krylov cycles */
     double inner_reduction;
+    int32_t precond;          /* fsi_precond: block-Jacobi (0) or a Schur form, rebuilt per iteration */
 } fsi_newton_opts;
 
 typedef struct {

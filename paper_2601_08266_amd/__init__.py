@@ -24,6 +24,7 @@ __all__ = [
     "vms_apply_workspace", "vms_apply", "PointTables", "dlm_locate", "dlm_B", "dlm_BT",
     "Problem", "jacobian_apply", "jacobian_workspace", "dlm_gram", "profile_enable",
     "profile_read", "vms_residual", "bjacobi_setup", "bjacobi_apply", "fgmres_solve",
+    "schur_size", "schur_info", "schur_setup", "schur_apply", "PRECONDS",
     "newton_solve", "solve_opts", "newton_opts",
 ]
 
@@ -359,12 +360,64 @@ def bjacobi_apply(grid, pinv: torch.Tensor, v: torch.Tensor, z: Optional[torch.T
     return z
 
 
+PRECONDS = {"bjacobi": L.FSI_PC_BJACOBI, "schur_diag": L.FSI_PC_SCHUR_DIAG, "schur_tri": L.FSI_PC_SCHUR_TRI}
+
+
+def _precond_code(precond) -> int:
+    return PRECONDS[precond] if isinstance(precond, str) else int(precond)
+
+
+def schur_size(grid) -> int:
+    """Bytes of the Schur-complement preconditioner object (fsi_schur_size); 0 if unsupported."""
+    return int(L.lib().fsi_schur_size(ctypes.byref(grid_from(grid))))
+
+
+def schur_info(grid):
+    """(levels, [(cells x, y, z) per level], [byte offset of each level's FP64 alpha])."""
+    g = grid_from(grid)
+    n = ctypes.c_int32(0)
+    cells = (ctypes.c_int32 * 48)()
+    offs = (ctypes.c_int64 * 16)()
+    L.check("fsi_schur_info", L.lib().fsi_schur_info(ctypes.byref(g), ctypes.byref(n), cells, offs))
+    k = int(n.value)
+    return k, [tuple(cells[3 * i:3 * i + 3]) for i in range(k)], [int(offs[i]) for i in range(k)]
+
+
+def schur_setup(problem: Problem, blocks: torch.Tensor, pc: Optional[torch.Tensor] = None, stream=None):
+    """Schur-complement block preconditioner of J (fsi_schur_setup) from the raw nodal blocks of
+    bjacobi_setup(want_blocks=True); returns the object (a uint8 device tensor)."""
+    if problem.dtype != torch.float64:
+        raise TypeError("the Schur preconditioner setup takes the FP64 problem")
+    _need(blocks, "blocks", torch.float64, 16 * problem.N)
+    nbytes = schur_size(problem.grid)
+    if nbytes == 0:
+        raise ValueError("Schur preconditioner unsupported: " + L.lib().fsi_last_error().decode())
+    pc = _workspace(nbytes, blocks.device, pc)
+    L.check("fsi_schur_setup", L.lib().fsi_schur_setup(
+        ctypes.byref(problem.struct), _ptr(blocks), _ptr(pc), pc.numel(), _stream(stream)))
+    return pc
+
+
+def schur_apply(problem: Problem, precond, pc: torch.Tensor, v: torch.Tensor,
+                z: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None):
+    """z = P^{-1} v (fsi_schur_apply) in the problem's precision."""
+    _need(v, "v", problem.dtype, 4 * problem.N)
+    if z is None:
+        z = torch.empty_like(v)
+    ws = _workspace(problem.workspace_bytes(), v.device, ws)
+    L.check("fsi_schur_apply", L.lib().fsi_schur_apply(
+        ctypes.byref(problem.struct), _precond_code(precond), _ptr(pc), _ptr(v), _ptr(z), _ptr(ws),
+        ws.numel(), _stream(stream)))
+    return z
+
+
 def solve_opts(restart=50, max_iters=2000, rtol=1e-10, inner=torch.float32,
-               inner_reduction=1e-5) -> FsiSolveOpts:
+               inner_reduction=1e-5, precond="bjacobi") -> FsiSolveOpts:
     o = FsiSolveOpts()
     o.restart, o.max_iters, o.rtol = int(restart), int(max_iters), float(rtol)
     o.inner = dtype_code(inner)
     o.inner_reduction = float(inner_reduction)
+    o.precond = _precond_code(precond)
     return o
 
 
@@ -389,12 +442,13 @@ def fgmres_solve(J64: Problem, b: torch.Tensor, x: torch.Tensor, opts: FsiSolveO
 
 
 def newton_opts(tol_abs, max_newton=20, eta=1e-3, restart=50, max_krylov=2000,
-                inner=torch.float32, inner_reduction=1e-5) -> FsiNewtonOpts:
+                inner=torch.float32, inner_reduction=1e-5, precond="bjacobi") -> FsiNewtonOpts:
     o = FsiNewtonOpts()
     o.max_newton, o.tol_abs, o.eta = int(max_newton), float(tol_abs), float(eta)
     o.restart, o.max_krylov = int(restart), int(max_krylov)
     o.inner = dtype_code(inner)
     o.inner_reduction = float(inner_reduction)
+    o.precond = _precond_code(precond)
     return o
 
 

@@ -19,6 +19,10 @@ FSI_ERR_UNSUPPORTED = -7
 FSI_F64 = 0
 FSI_F32 = 1
 
+FSI_PC_BJACOBI = 0
+FSI_PC_SCHUR_DIAG = 1
+FSI_PC_SCHUR_TRI = 2
+
 
 class FsiGrid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("order", ctypes.c_int32),
@@ -44,7 +48,7 @@ class FsiProblem(ctypes.Structure):
 class FsiSolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_iters", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("inner", ctypes.c_int),
-                ("inner_reduction", ctypes.c_double)]
+                ("inner_reduction", ctypes.c_double), ("precond", ctypes.c_int32)]
 
 
 class FsiSolveStats(ctypes.Structure):
@@ -57,7 +61,7 @@ class FsiNewtonOpts(ctypes.Structure):
     _fields_ = [("max_newton", ctypes.c_int32), ("tol_abs", ctypes.c_double),
                 ("eta", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_krylov", ctypes.c_int32), ("inner", ctypes.c_int),
-                ("inner_reduction", ctypes.c_double)]
+                ("inner_reduction", ctypes.c_double), ("precond", ctypes.c_int32)]
 
 
 class FsiNewtonStats(ctypes.Structure):
@@ -116,6 +120,11 @@ SIGNATURES = {
     "fsi_bjacobi_setup": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, P, ctypes.POINTER(I64),
                                          P, SZ, P]),
     "fsi_bjacobi_apply": (ctypes.c_int, [ctypes.POINTER(FsiGrid), ctypes.c_int, P, P, P, P]),
+    "fsi_schur_size": (SZ, [ctypes.POINTER(FsiGrid)]),
+    "fsi_schur_info": (ctypes.c_int, [ctypes.POINTER(FsiGrid), ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(I64)]),
+    "fsi_schur_setup": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, SZ, P]),
+    "fsi_schur_apply": (ctypes.c_int, [ctypes.POINTER(FsiProblem), ctypes.c_int32, P, P, P, P, SZ, P]),
     "fsi_fgmres_workspace": (SZ, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiProblem),
                                   ctypes.POINTER(FsiSolveOpts)]),
     "fsi_fgmres_solve": (ctypes.c_int, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiProblem), P,

@@ -4,6 +4,7 @@
 #include <cstring>
 
 #include "bjacobi.hpp"
+#include "schur.hpp"
 #include "dlm.hpp"
 #include "fgmres.hpp"
 #include "kernels.hpp"
@@ -465,6 +466,9 @@ static int check_solve(const fsi_problem *J64, const fsi_problem *J32, const fsi
     FSI_CHECK_ARG(o->max_iters >= 1, "max_iters must be >= 1");
     FSI_CHECK_ARG(std::isfinite(o->rtol) && o->rtol > 0.0 && o->rtol < 1.0, "rtol must be in (0,1)");
     FSI_CHECK_ARG(dtype_ok(o->inner), "bad inner dtype");
+    FSI_CHECK_ARG(o->precond == FSI_PC_BJACOBI || o->precond == FSI_PC_SCHUR_DIAG ||
+                      o->precond == FSI_PC_SCHUR_TRI,
+                  "unknown preconditioner %d", (int)o->precond);
     if (o->inner == FSI_F32) {
         FSI_CHECK_ARG(J32 != nullptr, "inner FP32 needs the FP32 problem");
         rc = check_problem(J32);
@@ -524,8 +528,101 @@ FSI_API int fsi_fgmres_solve(const fsi_problem *J64, const fsi_problem *J32, con
                                     J32->n_occ > 0 ? &v32 : nullptr, w, jw, s);
         };
     }
-    return fgmres_solve(g, c64, o->inner == FSI_F32 ? &c32 : nullptr, pinv, b, x, *o, stats, ws, jw,
-                        as_stream(stream));
+    Precond pc;
+    const JacobianCall *Jin = o->inner == FSI_F32 ? &c32 : &c64;
+    if (o->precond != FSI_PC_BJACOBI) {
+        FSI_CHECK_ARG(pinv != nullptr, "the Schur preconditioner object (fsi_schur_setup) is required");
+        void *obj = const_cast<void *>(pinv);
+        const int mode = o->precond == FSI_PC_SCHUR_DIAG ? 1 : 2;
+        pc.apply = [&, obj, mode](const double *v, void *z, void *w, hipStream_t s) {
+            return schur_apply(g, o->inner, true, mode, obj, v, z, Jin, w, s);
+        };
+    } else if (pinv != nullptr) {
+        pc.apply = [&](const double *v, void *z, void *, hipStream_t s) {
+            if (o->inner == FSI_F32)
+                return launch_bjacobi_apply_f64_to_f32(g.N, (const float *)pinv, v, (float *)z, s);
+            return launch_bjacobi_apply(g.N, FSI_F64, pinv, v, z, s);
+        };
+    }
+    return fgmres_solve(g, c64, o->inner == FSI_F32 ? &c32 : nullptr, pc.apply ? &pc : nullptr, b, x, *o,
+                        stats, ws, jw, as_stream(stream));
+}
+
+FSI_API size_t fsi_schur_size(const fsi_grid *grid)
+{
+    clear_error();
+    if (check_grid(grid) != FSI_OK) return 0;
+    ScPlan p;
+    if (sc_plan(make_geo(*grid), p) != FSI_OK) return 0;
+    return p.total;
+}
+
+FSI_API int fsi_schur_info(const fsi_grid *grid, int32_t *n_levels, int32_t *ncell, int64_t *alpha_offset)
+{
+    clear_error();
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    ScPlan p;
+    rc = sc_plan(make_geo(*grid), p);
+    if (rc) return rc;
+    if (n_levels) *n_levels = p.L;
+    for (int l = 0; l < p.L; ++l) {
+        if (ncell)
+            for (int d = 0; d < 3; ++d) ncell[3 * l + d] = p.lv[l].nc[d];
+        if (alpha_offset) alpha_offset[l] = (int64_t)p.lv[l].a64;
+    }
+    return FSI_OK;
+}
+
+FSI_API int fsi_schur_setup(const fsi_problem *p, const double *blocks, void *pc, size_t pc_bytes,
+                            void *stream)
+{
+    clear_error();
+    int rc = check_problem(p);
+    if (rc) return rc;
+    FSI_CHECK_ARG(p->dtype == FSI_F64, "the Schur preconditioner setup takes the FP64 problem");
+    FSI_CHECK_ARG(blocks != nullptr && pc != nullptr, "blocks and pc must be non-NULL");
+    if (p->n_occ > 0 && p->dlm_gram == nullptr) {
+        set_error("the Schur preconditioner setup needs the per-cell DLM blocks (fsi_dlm_gram) when n_occ > 0");
+        return FSI_ERR_UNSUPPORTED;
+    }
+    const Geo g = make_geo(p->grid);
+    ScPlan plan;
+    rc = sc_plan(g, plan);
+    if (rc) return rc;
+    if (pc_bytes < plan.total) {
+        set_error("preconditioner object of %zu bytes needed (got %zu)", plan.total, pc_bytes);
+        return FSI_ERR_WORKSPACE;
+    }
+    return schur_setup(g, p->prm, (const double *)p->a, (const double *)p->s, p->dir_mask,
+                       p->n_occ > 0 ? (const double *)p->dlm_gram : nullptr, p->occ_index, blocks, pc,
+                       as_stream(stream));
+}
+
+FSI_API int fsi_schur_apply(const fsi_problem *J, int32_t mode, void *pc, const void *v, void *z, void *ws,
+                            size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_problem(J);
+    if (rc) return rc;
+    FSI_CHECK_ARG(mode == FSI_PC_SCHUR_DIAG || mode == FSI_PC_SCHUR_TRI, "mode must be a Schur form");
+    FSI_CHECK_ARG(pc && v && z && v != z, "pc, v and z must be non-NULL, v and z distinct");
+    const Geo g = make_geo(J->grid);
+    ScPlan plan;
+    rc = sc_plan(g, plan);
+    if (rc) return rc;
+    const size_t jw = jac_ws(J);
+    if (mode == FSI_PC_SCHUR_TRI && (ws == nullptr || ws_bytes < jw)) {
+        set_error("workspace of %zu bytes needed (got %zu)", jw, ws_bytes);
+        return FSI_ERR_WORKSPACE;
+    }
+    const DlmView dv = view_of(J);
+    JacobianCall c{[&](const void *xx, void *yy, void *w, hipStream_t s) {
+        return launch_vms_apply(g, J->prm, J->dtype, J->a, J->s, J->dir_mask, xx, yy,
+                                J->n_occ > 0 ? &dv : nullptr, w, jw, s);
+    }};
+    return schur_apply(g, J->dtype, false, mode == FSI_PC_SCHUR_DIAG ? 1 : 2, pc, v, z, &c, ws,
+                       as_stream(stream));
 }
 
 static int check_newton(const fsi_problem *P64, const fsi_problem *P32, const fsi_newton_opts *o)
@@ -540,6 +637,14 @@ static int check_newton(const fsi_problem *P64, const fsi_problem *P32, const fs
     FSI_CHECK_ARG(o->restart >= 1 && o->restart <= 400, "restart must be in [1, 400]");
     FSI_CHECK_ARG(o->max_krylov >= 1, "max_krylov must be >= 1");
     FSI_CHECK_ARG(dtype_ok(o->inner), "bad inner dtype");
+    FSI_CHECK_ARG(o->precond == FSI_PC_BJACOBI || o->precond == FSI_PC_SCHUR_DIAG ||
+                      o->precond == FSI_PC_SCHUR_TRI,
+                  "unknown preconditioner %d", (int)o->precond);
+    if (o->precond != FSI_PC_BJACOBI) {
+        ScPlan sp;
+        rc = sc_plan(make_geo(P64->grid), sp);
+        if (rc) return rc;
+    }
     if (P64->grid.order != 1) {
         set_error("Newton steps are implemented for Q1 grids");
         return FSI_ERR_UNSUPPORTED;

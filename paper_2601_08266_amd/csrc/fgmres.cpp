@@ -7,12 +7,12 @@
 // are stored in that precision.  Every restart begins from the true FP64
 // residual, so the FP32 inner cycles act as iterative refinement steps.
 // Section 2.4 solves the reduced block system with block-preconditioned
-// Krylov iterations; this is that loop for the nodal block-Jacobi choice.
+// Krylov iterations; this is that loop, with the preconditioner passed in as a callable
+// (nodal block-Jacobi or the Schur-complement block preconditioner).
 #include <chrono>
 #include <cmath>
 #include <vector>
 
-#include "bjacobi.hpp"
 #include "fgmres.hpp"
 #include "krylov.hpp"
 #include "profile.hpp"
@@ -88,13 +88,13 @@ size_t fgmres_workspace_bytes(int64_t ndof, int restart, fsi_dtype inner, size_t
     return layout(ndof, restart, inner, jws_bytes).total;
 }
 
-int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32, const void *pinv,
+int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32, const Precond *pc,
                  const double *b, double *x, const fsi_solve_opts &o, fsi_solve_stats *stats,
                  void *ws, size_t jws_bytes, hipStream_t st)
 {
     ProfileScope prof("fgmres_solve", st);
     const auto t_start = std::chrono::steady_clock::now();
-    const int64_t N = g.N, n = 4 * N;
+    const int64_t n = 4 * g.N;
     const int m = o.restart;
     const fsi_dtype inner = o.inner;
     const Layout L = layout(n, m, inner, jws_bytes);
@@ -238,12 +238,8 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
                 if (inner == FSI_F32) {
                     {
                         ProfileScope pp("fgmres_precond", st);
-                        if (pinv) {
-                            TRY(launch_bjacobi_apply_f64_to_f32(N, reinterpret_cast<const float *>(pinv), Vj,
-                                                                reinterpret_cast<float *>(Zj), st));
-                        } else {
-                            TRY(kry_cast_f64_f32(n, Vj, reinterpret_cast<float *>(Zj), st));
-                        }
+                        if (pc) TRY(pc->apply(Vj, Zj, jws, st));
+                        else TRY(kry_cast_f64_f32(n, Vj, reinterpret_cast<float *>(Zj), st));
                     }
                     ProfileScope pa("fgmres_apply", st);
                     TRY(J32->apply(Zj, t32b, jws, st));
@@ -251,7 +247,7 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
                 } else {
                     {
                         ProfileScope pp("fgmres_precond", st);
-                        if (pinv) TRY(launch_bjacobi_apply(N, FSI_F64, pinv, Vj, Zj, st));
+                        if (pc) TRY(pc->apply(Vj, Zj, jws, st));
                         else FSI_HIP(hipMemcpyAsync(Zj, Vj, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
                     }
                     ProfileScope pa("fgmres_apply", st);

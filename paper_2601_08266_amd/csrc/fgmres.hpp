@@ -12,8 +12,14 @@ struct JacobianCall {
     std::function<int(const void *x, void *y, void *ws, hipStream_t st)> apply;
 };
 
+// A bound preconditioner z = P^{-1} v: v is an FP64 [4][N] basis vector, z is written in the
+// inner precision; jws is the Jacobian workspace (free while the preconditioner runs).
+struct Precond {
+    std::function<int(const double *v, void *z, void *jws, hipStream_t st)> apply;
+};
+
 size_t fgmres_workspace_bytes(int64_t ndof, int restart, fsi_dtype inner, size_t jws_bytes);
-int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32, const void *pinv,
+int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32, const Precond *pc,
                  const double *b, double *x, const fsi_solve_opts &o, fsi_solve_stats *stats,
                  void *ws, size_t jws_bytes, hipStream_t st);
 

@@ -1,6 +1,7 @@
 // Newton's method for one implicit step (section 2.4), host-driven:
 //   R_k = R(x_k)                      (residual kernel, FP64)
-//   P_k = nodal blocks of J(u_k)^-1   (block-Jacobi setup, FP64, FP32 copy)
+//   P_k = preconditioner of J(u_k)    (nodal block-Jacobi inverses, or the Schur-complement
+//                                      block preconditioner built from the nodal blocks)
 //   J(u_k) dx = -R_k                  (flexible GMRES, FP64 outer / inner precision)
 //   x_{k+1} = x_k + dx
 #include <chrono>
@@ -11,13 +12,14 @@
 #include "krylov.hpp"
 #include "newton.hpp"
 #include "profile.hpp"
+#include "schur.hpp"
 
 namespace fsi {
 
 namespace {
 
 struct NLayout {
-    size_t R, dx, pinv64, pinv32, a32, scratch, bjws, kws, total;
+    size_t R, dx, pinv64, pinv32, blocks, pc, a32, scratch, bjws, kws, total;
 };
 
 NLayout nlayout(const Geo &g, const fsi_newton_opts &o, size_t jws)
@@ -31,8 +33,15 @@ NLayout nlayout(const Geo &g, const fsi_newton_opts &o, size_t jws)
     };
     L.R = take((size_t)4 * g.N * sizeof(double));
     L.dx = take((size_t)4 * g.N * sizeof(double));
-    L.pinv64 = take((size_t)16 * g.N * sizeof(double));
-    L.pinv32 = take((size_t)16 * g.N * sizeof(float));
+    if (o.precond == FSI_PC_BJACOBI) {
+        L.pinv64 = take((size_t)16 * g.N * sizeof(double));
+        L.pinv32 = take((size_t)16 * g.N * sizeof(float));
+    } else {
+        ScPlan sp;
+        const size_t pcb = sc_plan(g, sp) == FSI_OK ? sp.total : 0;
+        L.blocks = take((size_t)16 * g.N * sizeof(double));
+        L.pc = take(pcb);
+    }
     L.a32 = take((size_t)3 * g.N * sizeof(float));
     L.scratch = take((size_t)(KRY_NB + 16) * sizeof(double));
     L.bjws = take(bjacobi_workspace_bytes(g));
@@ -65,6 +74,9 @@ int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, c
     double *dx = reinterpret_cast<double *>(base + L.dx);
     double *pinv64 = reinterpret_cast<double *>(base + L.pinv64);
     float *pinv32 = reinterpret_cast<float *>(base + L.pinv32);
+    double *blocks = reinterpret_cast<double *>(base + L.blocks);
+    void *pcobj = base + L.pc;
+    const bool schur = o.precond != FSI_PC_BJACOBI;
     float *a32 = reinterpret_cast<float *>(base + L.a32);
     void *bjws = base + L.bjws;
     void *kws = base + L.kws;
@@ -111,10 +123,18 @@ int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, c
         auto ts = std::chrono::steady_clock::now();
         fsi_problem J64 = P64;
         J64.a = x;
-        rc = launch_bjacobi_setup(g, J64.prm, x, (const double *)J64.s, J64.dir_mask,
-                                  J64.n_occ > 0 ? (const double *)J64.dlm_gram : nullptr, J64.occ_index,
-                                  nullptr, pinv64, o.inner == FSI_F32 ? pinv32 : nullptr, nullptr, bjws,
-                                  st);
+        const double *gram64 = J64.n_occ > 0 ? (const double *)J64.dlm_gram : nullptr;
+        if (schur) {
+            rc = launch_bjacobi_setup(g, J64.prm, x, (const double *)J64.s, J64.dir_mask, gram64, J64.occ_index,
+                                      blocks, nullptr, nullptr, nullptr, bjws, st);
+            if (rc) break;
+            rc = schur_setup(g, J64.prm, x, (const double *)J64.s, J64.dir_mask, gram64, J64.occ_index, blocks,
+                             pcobj, st);
+        } else {
+            rc = launch_bjacobi_setup(g, J64.prm, x, (const double *)J64.s, J64.dir_mask, gram64, J64.occ_index,
+                                      nullptr, pinv64, o.inner == FSI_F32 ? pinv32 : nullptr, nullptr, bjws,
+                                      st);
+        }
         if (rc) break;
         fsi_problem J32{};
         if (o.inner == FSI_F32) {
@@ -144,10 +164,21 @@ int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, c
             return launch_vms_apply(g, J32.prm, FSI_F32, J32.a, J32.s, J32.dir_mask, xx, yy,
                                     J32.n_occ > 0 ? &v32 : nullptr, w, jws, s2);
         }};
+        const JacobianCall *Jin = o.inner == FSI_F32 ? &c32 : &c64;
+        const int mode = o.precond == FSI_PC_SCHUR_DIAG ? 1 : 2;
+        Precond pc;
+        if (schur)
+            pc.apply = [&](const double *v, void *z, void *w, hipStream_t s2) {
+                return schur_apply(g, o.inner, true, mode, pcobj, v, z, Jin, w, s2);
+            };
+        else
+            pc.apply = [&](const double *v, void *z, void *, hipStream_t s2) {
+                if (o.inner == FSI_F32) return launch_bjacobi_apply_f64_to_f32(g.N, pinv32, v, (float *)z, s2);
+                return launch_bjacobi_apply(g.N, FSI_F64, pinv64, v, z, s2);
+            };
+        so.precond = o.precond;
         fsi_solve_stats ks{};
-        rc = fgmres_solve(g, c64, o.inner == FSI_F32 ? &c32 : nullptr,
-                          o.inner == FSI_F32 ? (const void *)pinv32 : (const void *)pinv64, R, dx, so,
-                          &ks, kws, jws, st);
+        rc = fgmres_solve(g, c64, o.inner == FSI_F32 ? &c32 : nullptr, &pc, R, dx, so, &ks, kws, jws, st);
         S.krylov_iters += ks.iters;
         S.t_krylov_ms += ms_since(tk);
         if (rc == FSI_ERR_NOT_CONVERGED) rc = FSI_OK;   // inexact Newton: take the step anyway

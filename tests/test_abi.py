@@ -52,3 +52,21 @@ def test_status_strings_and_argument_errors_without_gpu():
                            None, 0, None)
     assert rc == L.FSI_ERR_ARG
     assert b"order" in lib.fsi_last_error()
+
+
+@pytest.mark.parametrize("n,order", [((192, 192, 192), 1), ((96, 96, 96), 2), ((64, 64, 64), 1),
+                                     ((8, 8, 8), 1), ((10, 12, 14), 1), ((5, 6, 7), 2)])
+def test_schur_levels_follow_the_coarsening_rule(n, order):
+    # host-only: the library's multigrid levels equal the oracle's rule (no device work)
+    import paper_2601_08266_amd as fsi
+    from oracle import schur
+    k, cells, offs = fsi.schur_info(fsi.make_grid(n, order))
+    want = schur.level_shapes(tuple(order * c for c in n))
+    assert k == len(want) and cells == want
+    assert offs == sorted(offs) and fsi.schur_size(fsi.make_grid(n, order)) > offs[-1]
+
+
+def test_schur_rejects_lattices_without_a_small_coarse_level():
+    import paper_2601_08266_amd as fsi
+    assert fsi.schur_size(fsi.make_grid((13, 13, 13), 1)) == 0
+    assert b"coarsened" in fsi._lib.lib().fsi_last_error()
