@@ -153,7 +153,10 @@ def time_applies(fsi, torch, case, steps, warmup, profile):
     return ms, wall / steps * 1e3, kern
 
 
-def newton_step_probe(warm_steps=60, measure_steps=3):
+PROBE_MODES = ["plain_f64", "plain_mixed", "extrap_mixed"]
+
+
+def newton_step_probe(warm_steps=60, measure_steps=3, modes=None):
     """Short Newton-step comparison on the 64^3 rotating-plates channel: after a few plain steps,
     the next steps are re-solved from the same state with plain FP64, mixed precision, and mixed
     precision + extrapolated warm start; all stop at the same absolute residual."""
@@ -170,16 +173,17 @@ def newton_step_probe(warm_steps=60, measure_steps=3):
     for k in range(warm_steps, warm_steps + measure_steps):
         run.x = run.history[k].x.clone()
         run.n = k
-        rows.append(ex._solve_modes(run, None, k, ["plain_f64", "plain_mixed", "extrap_mixed"]))
+        rows.append(ex._solve_modes(run, None, k, modes or PROBE_MODES))
         run.x = run.history[k].x.clone()
         run.n = k
         run.step()
     out = {"workload": "64^3 Q1 channel, 200k rotating-plate points, steps "
                        f"{warm_steps + 1}-{warm_steps + measure_steps}, tol 1e-8*||R(x_plain)||"}
-    for m in ["plain_f64", "plain_mixed", "extrap_mixed"]:
+    for m in modes or PROBE_MODES:
         out[m + "_ms"] = round(sum(r[m]["ms_newton"] + r[m]["ms_guess"] for r in rows) / len(rows), 2)
         out[m + "_krylov"] = round(sum(r[m]["krylov"] for r in rows) / len(rows), 1)
-    out["speedup_mixed_extrap_vs_plain_f64"] = round(out["plain_f64_ms"] / out["extrap_mixed_ms"], 3)
+    if "plain_f64_ms" in out and "extrap_mixed_ms" in out:
+        out["speedup_mixed_extrap_vs_plain_f64"] = round(out["plain_f64_ms"] / out["extrap_mixed_ms"], 3)
     return out
 
 
@@ -220,10 +224,14 @@ def main(argv=None):
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-newton", action="store_true", help="skip the short Newton-step probe")
-    ap.add_argument("--experiment", default=None, choices=["warmstart", "c5", "netspeed", "c3"],
+    ap.add_argument("--experiment", default=None, choices=["warmstart", "c5", "netspeed", "c3", "probe"],
                     help="run a Newton-step experiment instead of the apply benchmark")
     ap.add_argument("--exp-steps", type=int, default=200)
-    ap.add_argument("--exp-modes", default="mixed,f64")
+    ap.add_argument("--exp-modes", default=None,
+                    help="comma list: c3 inner precisions (mixed,f64); c5/probe Newton modes "
+                         "(plain|extrap|nn _ mixed|f64, suffix _st / _sd for the Schur preconditioner)")
+    ap.add_argument("--exp-precond", default="bjacobi", choices=["bjacobi", "schur_diag", "schur_tri"],
+                    help="c3 preconditioner")
     ap.add_argument("--exp-train-end", type=int, default=100)
     ap.add_argument("--exp-epochs", type=int, default=20)
     ap.add_argument("--exp-stride", type=int, default=1)
@@ -346,9 +354,14 @@ def run_experiment(args):
                           "forward_ms": round(fwd, 3), "train_sample_ms": round(trn, 3),
                           "forward_padded_TFLOPs": round(flops / fwd / 1e9, 2)}))
         return 0
+    modes = args.exp_modes.split(",") if args.exp_modes else None
     if args.experiment == "c3":
         print(json.dumps({"experiment": "solve_c3",
-                          **ex.solve_c3(max_iters=args.exp_steps, modes=tuple(args.exp_modes.split(",")))}))
+                          **ex.solve_c3(max_iters=args.exp_steps, modes=tuple(modes or ("mixed", "f64")),
+                                        precond=args.exp_precond)}))
+        return 0
+    if args.experiment == "probe":
+        print(json.dumps({"experiment": "newton_probe", **newton_step_probe(modes=modes)}))
         return 0
     if args.experiment == "warmstart":
         summary, lw = ex.warmstart_c4(steps=args.exp_steps, train_end=args.exp_train_end,
@@ -356,7 +369,7 @@ def run_experiment(args):
                                       save_path=args.exp_save)
         print(json.dumps({"experiment": "warmstart_c4", **summary}))
         return 0
-    summary = ex.large_c5(state_path=args.exp_load)
+    summary = ex.large_c5(state_path=args.exp_load, modes=modes)
     print(json.dumps({"experiment": "large_c5", **summary}))
     return 0
 

@@ -31,13 +31,23 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def mode_precond(mode):
+    """Preconditioner named by a mode's suffix: _st Schur block-triangular, _sd Schur block-diagonal,
+    none: the run's default."""
+    if mode.endswith("_st"):
+        return "schur_tri"
+    if mode.endswith("_sd"):
+        return "schur_diag"
+    return None
+
+
 def _solve_modes(run, lw, k, modes):
     out = {}
     sols = {}
     for mode in modes:
         run.x = run.history[k].x.clone()
         run.n = k
-        inner = torch.float64 if mode.endswith("f64") else torch.float32
+        inner = torch.float64 if "f64" in mode else torch.float32
         gf = None
         if lw is not None and mode.startswith("nn"):
             gf = lw.guess
@@ -45,7 +55,7 @@ def _solve_modes(run, lw, k, modes):
             gf = quadratic_extrapolation_guess
         elif mode.startswith("extrap"):
             gf = linear_extrapolation_guess
-        rec = run.step(guess_fn=gf, inner=inner, record=False)
+        rec = run.step(guess_fn=gf, inner=inner, record=False, precond=mode_precond(mode))
         out[mode] = dict(newton=rec.newton_iters, krylov=rec.krylov_iters, ms_newton=rec.ms_newton,
                          ms_guess=rec.ms_guess, res_plain=rec.res_plain, res_guess=rec.res_guess,
                          used_guess=rec.used_guess, hist=rec.res_hist)
@@ -125,11 +135,11 @@ def warmstart_c4(steps=200, train_end=100, epochs=20, lr=1e-3, eval_stride=1, se
     return summary, lw
 
 
-def large_c5(lw_c4=None, warmup_steps=3, state_path=None):
+def large_c5(lw_c4=None, warmup_steps=3, state_path=None, modes=None, warmup_precond="schur_tri"):
     cfg = W.CONFIGS["c5"]
     run = ChannelRun(cfg)
     for n in range(warmup_steps):
-        rec = run.step()
+        rec = run.step(precond=warmup_precond)
         _log(f"c5 warm-up step {rec.n}: newton={rec.newton_iters} krylov={rec.krylov_iters} "
              f"{rec.ms_newton:.0f} ms")
     lw = None
@@ -145,21 +155,24 @@ def large_c5(lw_c4=None, warmup_steps=3, state_path=None):
         lw.in_shift, lw.in_scale = list(nm["in_shift"]), list(nm["in_scale"])
         lw.out_shift, lw.out_scale = list(nm["out_shift"]), list(nm["out_scale"])
     k = run.n
-    modes = ["plain_f64", "plain_mixed", "extrap_mixed", "extrap3_mixed"] + (["nn_mixed"] if lw is not None else [])
+    if modes is None:
+        modes = ["plain_f64", "plain_mixed", "extrap_mixed", "extrap3_mixed"] + (["nn_mixed"] if lw is not None else [])
+    modes = list(modes)
     r = _solve_modes(run, lw, k, modes)
     for m in modes:
         _log(f"c5 step {k + 1} {m}: {r[m]['newton']}N/{r[m]['krylov']}K "
              f"{r[m]['ms_newton'] + r[m]['ms_guess']:.0f} ms")
-    best = "nn_mixed" if lw is not None else "plain_mixed"
     summary = {"workload": "192^3 Q1 channel, 2M points on three rotating plates",
-               "step": k + 1, "dof": 4 * run.N, "modes": r,
-               "speedup_" + best + "_vs_plain_f64":
-                   round((r["plain_f64"]["ms_newton"] + r["plain_f64"]["ms_guess"]) /
-                         (r[best]["ms_newton"] + r[best]["ms_guess"]), 3)}
+               "step": k + 1, "dof": 4 * run.N, "warmup_precond": warmup_precond, "modes": r}
+    if "plain_f64" in r:
+        base = r["plain_f64"]["ms_newton"] + r["plain_f64"]["ms_guess"]
+        for m in modes[1:]:
+            summary["speedup_" + m + "_vs_plain_f64"] = round(base / (r[m]["ms_newton"] + r[m]["ms_guess"]), 3)
     return summary
 
 
-def solve_c3(rtol=1e-10, restart=50, max_iters=6000, profile=True, chunk=1000, modes=("mixed", "f64")):
+def solve_c3(rtol=1e-10, restart=50, max_iters=6000, profile=True, chunk=1000, modes=("mixed", "f64"),
+             precond="bjacobi"):
     """96^3 Q2-Q2 channel (28.8M DOF), 500k plate points, seeded smooth right-hand side zeroed
     on the Dirichlet rows: FGMRES(50) with nodal block-Jacobi to rtol, FP32 inner applies
     (FP64 residual, orthogonalisation and restarts) and, for comparison, FP64 inner applies.
@@ -167,7 +180,7 @@ def solve_c3(rtol=1e-10, restart=50, max_iters=6000, profile=True, chunk=1000, m
     import numpy as np
 
     from . import (Problem, bjacobi_setup, dlm_gram, dlm_locate, fgmres_solve, jacobian_apply,
-                   make_params, profile_enable, profile_read, solve_opts)
+                   make_params, profile_enable, profile_read, schur_setup, solve_opts)
 
     cfg = W.CONFIGS["c3"]
     g = cfg.grid
@@ -187,7 +200,7 @@ def solve_c3(rtol=1e-10, restart=50, max_iters=6000, profile=True, chunk=1000, m
     prm = make_params(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
     Xt = t(X)
     out = {"workload": f"96^3 Q2-Q2 channel, {cfg.m_points} plate points", "dof": 4 * N,
-           "cells": g.num_cells, "rtol": rtol, "restart": restart}
+           "cells": g.num_cells, "rtol": rtol, "restart": restart, "precond": precond}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tab64 = dlm_locate(g, Xt, dtype=torch.float64, s_max=cfg.s_max)
@@ -196,7 +209,12 @@ def solve_c3(rtol=1e-10, restart=50, max_iters=6000, profile=True, chunk=1000, m
     P64 = Problem(g, prm, t(a), tab64, k64, s=tab64.s, mask=mt, gram=dlm_gram(g, tab64, k64))
     P32 = Problem(g, prm, t(a, torch.float32), tab32, k32, s=tab32.s, mask=mt,
                   gram=dlm_gram(g, tab32, k32))
-    pinv64, pinv32, _, nsing = bjacobi_setup(P64)
+    if precond == "bjacobi":
+        pinv64, pinv32, _, nsing = bjacobi_setup(P64)
+    else:
+        _, _, blocks, nsing = bjacobi_setup(P64, want32=False, want_blocks=True)
+        pinv64 = pinv32 = schur_setup(P64, blocks)
+        del blocks
     torch.cuda.synchronize()
     out["setup_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
     out["n_occupied_cells"] = tab64.n_occ
@@ -217,7 +235,7 @@ def solve_c3(rtol=1e-10, restart=50, max_iters=6000, profile=True, chunk=1000, m
         rc = -4
         while iters < max_iters:
             opts = solve_opts(restart=restart, max_iters=min(chunk, max_iters - iters), rtol=rtol,
-                              inner=inner)
+                              inner=inner, precond=precond)
             rc, st = fgmres_solve(P64, bt, x, opts, J32=P32 if inner == torch.float32 else None,
                                   pinv=pinv, check=False)
             iters += st.iters
@@ -248,11 +266,12 @@ def solve_c3(rtol=1e-10, restart=50, max_iters=6000, profile=True, chunk=1000, m
         x = torch.zeros(4 * N, dtype=torch.float64, device=dev)
         profile_enable(True)
         fgmres_solve(P64, bt, x, solve_opts(restart=restart, max_iters=500, rtol=rtol,
-                                            inner=torch.float32), J32=P32, pinv=pinv32, check=False)
+                                            inner=torch.float32, precond=precond), J32=P32, pinv=pinv32,
+                     check=False)
         torch.cuda.synchronize()
         ph = {}
         for name in ("fgmres_apply", "fgmres_precond", "fgmres_orth", "fgmres_residual",
-                     "vms_q2_cells", "vms_gather"):
+                     "vms_q2_cells", "vms_gather", "schur_apply"):
             tot, n = profile_read(name)
             ph[name] = {"ms_total": round(tot, 2), "calls": n}
         profile_enable(False)

@@ -56,8 +56,9 @@ class StepRecord:
 
 class ChannelRun:
     def __init__(self, cfg, device="cuda", inner=torch.float32, eta=1e-3, restart=50,
-                 rel_tol=1e-8, period=0.8, amp_deg=20.0, max_krylov=4000):
+                 rel_tol=1e-8, period=0.8, amp_deg=20.0, max_krylov=4000, precond="bjacobi"):
         self.cfg = cfg
+        self.precond = precond
         self.g = cfg.grid
         self.N = self.g.num_nodes
         self.dev = torch.device(device)
@@ -127,7 +128,7 @@ class ChannelRun:
         dlm_BT(self.g, tab64, lam, out, kappa=self.kappa64)
         return out
 
-    def step(self, guess_fn: Optional[Callable] = None, inner=None, record=True):
+    def step(self, guess_fn: Optional[Callable] = None, inner=None, record=True, precond=None):
         """Advance one step.  guess_fn(run, ctx) -> FP64 [4][N] guess or None; ctx holds the
         step's FP64 problem, lamg, the inflow value, s and the extrapolated guess with its
         residual (x_ex, R_ex, rn_ex; None before two states exist)."""
@@ -173,7 +174,8 @@ class ChannelRun:
         ms_guess = (time.perf_counter() - t_g0) * 1e3
         inner = inner if inner is not None else self.inner
         opts = newton_opts(tol_abs=tol, eta=self.eta, restart=self.restart,
-                           max_krylov=self.max_krylov, inner=inner)
+                           max_krylov=self.max_krylov, inner=inner,
+                           precond=precond if precond is not None else self.precond)
         x_new = x0.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
