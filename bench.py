@@ -153,13 +153,14 @@ def time_applies(fsi, torch, case, steps, warmup, profile):
     return ms, wall / steps * 1e3, kern
 
 
-PROBE_MODES = ["plain_f64", "plain_mixed", "extrap_mixed"]
+PROBE_MODES = ["plain_f64", "plain_mixed", "extrap_mixed", "plain_f64_st", "plain_mixed_st", "extrap_mixed_st"]
 
 
 def newton_step_probe(warm_steps=60, measure_steps=3, modes=None):
     """Short Newton-step comparison on the 64^3 rotating-plates channel: after a few plain steps,
     the next steps are re-solved from the same state with plain FP64, mixed precision, and mixed
-    precision + extrapolated warm start; all stop at the same absolute residual."""
+    precision + extrapolated warm start, each with the block-Jacobi and (suffix _st) the
+    Schur-complement block-triangular preconditioner; all stop at the same absolute residual."""
     import torch
 
     import fsi_workloads as W
@@ -184,6 +185,12 @@ def newton_step_probe(warm_steps=60, measure_steps=3, modes=None):
         out[m + "_krylov"] = round(sum(r[m]["krylov"] for r in rows) / len(rows), 1)
     if "plain_f64_ms" in out and "extrap_mixed_ms" in out:
         out["speedup_mixed_extrap_vs_plain_f64"] = round(out["plain_f64_ms"] / out["extrap_mixed_ms"], 3)
+    if "plain_f64_ms" in out and "extrap_mixed_st_ms" in out:
+        # the fastest form (mixed precision, extrapolated guess, Schur-complement preconditioner)
+        # against plain FP64 Newton with block-Jacobi and against plain FP64 with the same preconditioner
+        out["speedup_extrap_mixed_st_vs_plain_f64"] = round(out["plain_f64_ms"] / out["extrap_mixed_st_ms"], 3)
+    if "plain_f64_st_ms" in out and "extrap_mixed_st_ms" in out:
+        out["speedup_extrap_mixed_st_vs_plain_f64_st"] = round(out["plain_f64_st_ms"] / out["extrap_mixed_st_ms"], 3)
     return out
 
 
@@ -232,6 +239,7 @@ def main(argv=None):
                          "(plain|extrap|nn _ mixed|f64, suffix _st / _sd for the Schur preconditioner)")
     ap.add_argument("--exp-precond", default="bjacobi", choices=["bjacobi", "schur_diag", "schur_tri"],
                     help="c3 preconditioner")
+    ap.add_argument("--exp-restart", type=int, default=50, help="c3 FGMRES restart length")
     ap.add_argument("--exp-train-end", type=int, default=100)
     ap.add_argument("--exp-epochs", type=int, default=20)
     ap.add_argument("--exp-stride", type=int, default=1)
@@ -358,7 +366,7 @@ def run_experiment(args):
     if args.experiment == "c3":
         print(json.dumps({"experiment": "solve_c3",
                           **ex.solve_c3(max_iters=args.exp_steps, modes=tuple(modes or ("mixed", "f64")),
-                                        precond=args.exp_precond)}))
+                                        precond=args.exp_precond, restart=args.exp_restart)}))
         return 0
     if args.experiment == "probe":
         print(json.dumps({"experiment": "newton_probe", **newton_step_probe(modes=modes)}))

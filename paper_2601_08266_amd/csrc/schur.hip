@@ -22,7 +22,8 @@
 //   sc_dmask0      Dirichlet flags of the Laplacian (level 0)
 //   sc_coarsen_*   coarse alpha (mean of 8 children), coarse flags by injection
 //   sc_vel_inverse 3x3 velocity block inverses (FP64, FP32 copy)
-//   sc_first/sc_jacobi/sc_resid/sc_restrict/sc_prolong/sc_coarse: the V-cycle
+//   sc_first/sc_sweep/sc_restrict/sc_prolong/sc_coarse: the V-cycle (sc_sweep: Jacobi sweep or
+//                  residual with the 27-point variable-coefficient stencil)
 //   sc_vel_apply   z_u = F_hat^{-1} (v_u - [J (0, z_p)]_u)
 // Every vector of the V-cycle keeps zeros at Dirichlet nodes, so the 27-point stencil
 // needs no mask on its neighbours.
@@ -37,7 +38,7 @@ namespace fsi {
 
 namespace {
 
-constexpr int SC_TX = 64, SC_TY = 4;
+constexpr int SC_TX = 32, SC_TY = 8;
 
 template <typename T>
 struct Lv {
@@ -78,60 +79,9 @@ __device__ __forceinline__ void cell_alphas(const Lv<T> &L, const T *__restrict_
                 const int cx = i - 1 + ox, cy = j - 1 + oy, cz = k - 1 + oz;
                 const bool ok = cx >= 0 && cx < L.nc[0] && cy >= 0 && cy < L.nc[1] && cz >= 0 && cz < L.nc[2];
                 const int qx = ok ? cx : 0, qy = ok ? cy : 0, qz = ok ? cz : 0;
-                const T v = alpha[qx + (int64_t)L.nc[0] * (qy + (int64_t)L.nc[1] * qz)];
+                const T v = alpha[qx + L.nc[0] * (qy + L.nc[1] * qz)];
                 al[oz][oy][ox] = ok ? v : T(0);
             }
-}
-
-// (K x)_A for node (i, j, k) and the assembled diagonal K_AA.  The coefficient of
-// neighbour A + delta is kc[pattern(delta)] times the sum of alpha over the cells holding
-// both nodes: along an axis with delta = -1 only the lower cell (o = 0), +1 the upper
-// (o = 1), 0 both.
-template <typename T>
-__device__ __forceinline__ T stencil(const Lv<T> &L, const T *__restrict__ alpha, const T *__restrict__ x,
-                                     int i, int j, int k, T &diag)
-{
-    T al[2][2][2];
-    cell_alphas(L, alpha, i, j, k, al);
-    // sx[oz][oy][dx + 1]
-    T sx[2][2][3];
-#pragma unroll
-    for (int oz = 0; oz < 2; ++oz)
-#pragma unroll
-        for (int oy = 0; oy < 2; ++oy) {
-            sx[oz][oy][0] = al[oz][oy][0];
-            sx[oz][oy][2] = al[oz][oy][1];
-            sx[oz][oy][1] = al[oz][oy][0] + al[oz][oy][1];
-        }
-    T sy[2][3][3];
-#pragma unroll
-    for (int oz = 0; oz < 2; ++oz)
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-            sy[oz][0][dx] = sx[oz][0][dx];
-            sy[oz][2][dx] = sx[oz][1][dx];
-            sy[oz][1][dx] = sx[oz][0][dx] + sx[oz][1][dx];
-        }
-    const int64_t nx = L.nn[0], nxy = (int64_t)L.nn[0] * L.nn[1];
-    T y = T(0);
-#pragma unroll
-    for (int dz = 0; dz < 3; ++dz) {
-        const int kk = min(max(k + dz - 1, 0), L.nn[2] - 1);
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy) {
-            const int jj = min(max(j + dy - 1, 0), L.nn[1] - 1);
-            const int64_t row = jj * nx + kk * nxy;
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const int ii = min(max(i + dx - 1, 0), L.nn[0] - 1);
-                const T S = dz == 0 ? sy[0][dy][dx] : (dz == 2 ? sy[1][dy][dx] : sy[0][dy][dx] + sy[1][dy][dx]);
-                const int pat = (dx != 1) + 2 * (dy != 1) + 4 * (dz != 1);
-                y += (L.kc[pat] * S) * x[row + ii];
-                if (pat == 0) diag = L.kc[0] * S;
-            }
-        }
-    }
-    return y;
 }
 
 template <typename T>
@@ -154,7 +104,7 @@ __device__ __forceinline__ T diag_only(const Lv<T> &L, const T *__restrict__ alp
     const int j = blockIdx.y * SC_TY + threadIdx.y;                        \
     const int k = blockIdx.z;                                              \
     if (i >= (L).nn[0] || j >= (L).nn[1]) return;                          \
-    const int64_t id = i + (int64_t)(L).nn[0] * (j + (int64_t)(L).nn[1] * k)
+    const int id = i + (L).nn[0] * (j + (L).nn[1] * k)
 
 // level 0, first sweep from a zero guess: b = v_p (all nodes), x = w b / diag (0 at Dirichlet)
 template <typename T, typename TV>
@@ -168,33 +118,85 @@ __global__ __launch_bounds__(256) void sc_first(Lv<T> L, const T *__restrict__ a
     x[id] = dm[id] ? T(0) : omega * bv / diag_only(L, alpha, i, j, k);
 }
 
-// x_out = x + w (b - K x) / diag; Dirichlet nodes 0, or b / diag in the final sweep (FINAL
-// writes the result to zp in the output precision)
-template <typename T, typename TZ, bool FINAL>
-__global__ __launch_bounds__(256) void sc_jacobi(Lv<T> L, const T *__restrict__ alpha,
-                                                 const uint8_t *__restrict__ dm, const T *__restrict__ b,
-                                                 const T *__restrict__ x, T *__restrict__ xo,
-                                                 TZ *__restrict__ zp, T omega)
+// One stencil sweep over a level, one lane per node (32 x 8 nodes per block, one plane per
+// block, 32-bit offsets: every level holds fewer than 2^31 nodes).  The coefficient of
+// neighbour A + delta is kc[pattern(delta)] times the sum of alpha over the cells holding both
+// nodes: along an axis with delta = -1 only the lower cell, +1 the upper one, 0 both.
+//   MODE 0: xo = x + w (b - K x) / diag     (0 at Dirichlet nodes)
+//   MODE 1: xo = b - K x                    (0 at Dirichlet nodes)
+//   MODE 2: zp = x + w (b - K x) / diag, b / diag at Dirichlet nodes (output precision TZ)
+constexpr int SW_TX = 32, SW_TY = 8;
+
+template <typename T, typename TZ, int MODE>
+__global__ __launch_bounds__(256) void sc_sweep(Lv<T> L, const T *__restrict__ alpha,
+                                                const uint8_t *__restrict__ dm, const T *__restrict__ b,
+                                                const T *__restrict__ x, T *__restrict__ xo,
+                                                TZ *__restrict__ zp, T omega)
 {
-    SC_NODE_INDEX(L);
-    T d = T(1);
-    const T kx = stencil(L, alpha, x, i, j, k, d);
-    if (FINAL) {
-        zp[id] = (TZ)(dm[id] ? b[id] / d : x[id] + omega * (b[id] - kx) / d);
-    } else {
-        xo[id] = dm[id] ? T(0) : x[id] + omega * (b[id] - kx) / d;
+    const int i = blockIdx.x * SW_TX + threadIdx.x, j = blockIdx.y * SW_TY + threadIdx.y, k = blockIdx.z;
+    const int nx = L.nn[0], ny = L.nn[1], nz = L.nn[2];
+    if (i >= nx || j >= ny) return;
+    const int cnx = L.nc[0], cnxy = L.nc[0] * L.nc[1];
+    T al[2][2][2];
+#pragma unroll
+    for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+            for (int ox = 0; ox < 2; ++ox) {
+                const int cx = i - 1 + ox, cy = j - 1 + oy, cz = k - 1 + oz;
+                const bool ok = cx >= 0 && cx < L.nc[0] && cy >= 0 && cy < L.nc[1] && cz >= 0 && cz < L.nc[2];
+                const T v = alpha[ok ? cx + cnx * cy + cnxy * cz : 0];
+                al[oz][oy][ox] = ok ? v : T(0);
+            }
+    T sx[2][2][3];
+#pragma unroll
+    for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 2; ++oy) {
+            sx[oz][oy][0] = al[oz][oy][0];
+            sx[oz][oy][2] = al[oz][oy][1];
+            sx[oz][oy][1] = al[oz][oy][0] + al[oz][oy][1];
+        }
+    T sy[2][3][3];
+#pragma unroll
+    for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            sy[oz][0][dx] = sx[oz][0][dx];
+            sy[oz][2][dx] = sx[oz][1][dx];
+            sy[oz][1][dx] = sx[oz][0][dx] + sx[oz][1][dx];
+        }
+    const int nxy = nx * ny;
+    T y = T(0), d = T(1);
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz) {
+        const int kk = min(max(k + dz - 1, 0), nz - 1);
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const int row = min(max(j + dy - 1, 0), ny - 1) * nx + kk * nxy;
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int ii = min(max(i + dx - 1, 0), nx - 1);
+                const T S = dz == 0 ? sy[0][dy][dx] : (dz == 2 ? sy[1][dy][dx] : sy[0][dy][dx] + sy[1][dy][dx]);
+                const int pat = (dx != 1) + 2 * (dy != 1) + 4 * (dz != 1);
+                y += (L.kc[pat] * S) * x[row + ii];
+                if (pat == 0) d = L.kc[0] * S;
+            }
+        }
     }
+    const int id = i + nx * j + nxy * k;
+    const bool dir = dm[id] != 0;
+    const T bv = b[id];
+    if (MODE == 0) xo[id] = dir ? T(0) : x[id] + omega * (bv - y) / d;
+    if (MODE == 1) xo[id] = dir ? T(0) : bv - y;
+    if (MODE == 2) zp[id] = (TZ)(dir ? bv / d : x[id] + omega * (bv - y) / d);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void sc_resid(Lv<T> L, const T *__restrict__ alpha,
-                                                const uint8_t *__restrict__ dm, const T *__restrict__ b,
-                                                const T *__restrict__ x, T *__restrict__ r)
+dim3 sweep_grid(const ScLevel &L)
 {
-    SC_NODE_INDEX(L);
-    T d = T(1);
-    const T kx = stencil(L, alpha, x, i, j, k, d);
-    r[id] = dm[id] ? T(0) : b[id] - kx;
+    return dim3((unsigned)((L.nn[0] + SW_TX - 1) / SW_TX), (unsigned)((L.nn[1] + SW_TY - 1) / SW_TY),
+                (unsigned)L.nn[2]);
 }
 
 // coarse node (i, j, k): b_c = sum of fine residuals at (2i + di, ...) with weights 1 (di = 0)
@@ -210,7 +212,7 @@ __global__ __launch_bounds__(256) void sc_restrict(Lv<T> L, Lv<T> F, const T *__
         x[id] = T(0);
         return;
     }
-    const int64_t fnx = F.nn[0], fnxy = (int64_t)F.nn[0] * F.nn[1];
+    const int fnx = F.nn[0], fnxy = F.nn[0] * F.nn[1];
     T s = T(0);
 #pragma unroll
     for (int dz = -1; dz <= 1; ++dz) {
@@ -250,7 +252,7 @@ __global__ __launch_bounds__(256) void sc_prolong(Lv<T> L, Lv<T> C, const uint8_
     for (int c = 0; c < nz; ++c) {
         T sy = T(0);
         for (int bb = 0; bb < ny; ++bb) {
-            const T *row = xc + cj[bb] * (int64_t)C.nn[0] + ck[c] * (int64_t)C.nn[0] * C.nn[1];
+            const T *row = xc + cj[bb] * C.nn[0] + ck[c] * C.nn[0] * C.nn[1];
             T sx = T(0);
             for (int a = 0; a < nx; ++a) sx += row[ci[a]];
             sy += wx * sx;
@@ -260,16 +262,19 @@ __global__ __launch_bounds__(256) void sc_prolong(Lv<T> L, Lv<T> C, const uint8_
     x[id] += wz * s;
 }
 
-// coarsest level: x = Kinv b (Kinv symmetric, zero rows/columns at Dirichlet nodes)
+// coarsest level: x = Kinv b (Kinv symmetric, zero rows/columns at Dirichlet nodes); one
+// wavefront per row, lanes stride the row, then a butterfly sum across the wavefront
 template <typename T>
-__global__ __launch_bounds__(256) void sc_coarse(int n, const T *__restrict__ kinv, const T *__restrict__ b,
-                                                 T *__restrict__ x)
+__global__ __launch_bounds__(64) void sc_coarse(int n, const T *__restrict__ kinv, const T *__restrict__ b,
+                                                T *__restrict__ x)
 {
-    const int r = blockIdx.x * 256 + threadIdx.x;
-    if (r >= n) return;
+    const int r = blockIdx.x, lane = threadIdx.x;
+    const T *row = kinv + (int64_t)r * n;
     T s = T(0);
-    for (int c = 0; c < n; ++c) s += kinv[(int64_t)c * n + r] * b[c];
-    x[r] = s;
+    for (int c = lane; c < n; c += 64) s += row[c] * b[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) x[r] = s;
 }
 
 // single-level case: z_p = b / diag at Dirichlet nodes, the coarse solution elsewhere
@@ -510,7 +515,7 @@ int vcycle(const ScPlan &p, char *base, const TV *vp, TZ *zp, hipStream_t st)
     auto A = [&](int l) { return reinterpret_cast<const T *>(base + (sizeof(T) == 8 ? p.lv[l].a64 : p.lv[l].a32)); };
     auto D = [&](int l) { return reinterpret_cast<const uint8_t *>(base + p.lv[l].dm); };
     auto V = [&](int l, size_t off) { return reinterpret_cast<T *>(base + off); };
-    const dim3 blk(SC_TX, SC_TY, 1);
+    const dim3 blk(SC_TX, SC_TY, 1), sblk(SW_TX, SW_TY, 1);
     const int Lc = p.L - 1;
     const ScLevel &L0 = p.lv[0];
     hipLaunchKernelGGL((sc_first<T, TV>), node_grid(L0), blk, 0, st, lv_of<T>(L0), A(0), D(0), vp,
@@ -518,11 +523,11 @@ int vcycle(const ScPlan &p, char *base, const TV *vp, TZ *zp, hipStream_t st)
     FSI_LAUNCH_CHECK();
     for (int l = 0; l < Lc; ++l) {
         const ScLevel &F = p.lv[l], &C = p.lv[l + 1];
-        hipLaunchKernelGGL((sc_jacobi<T, T, false>), node_grid(F), blk, 0, st, lv_of<T>(F), A(l), D(l),
+        hipLaunchKernelGGL((sc_sweep<T, T, 0>), sweep_grid(F), sblk, 0, st, lv_of<T>(F), A(l), D(l),
                            V(l, F.b), V(l, F.x0), V(l, F.x1), (T *)nullptr, omega);
         FSI_LAUNCH_CHECK();
-        hipLaunchKernelGGL((sc_resid<T>), node_grid(F), blk, 0, st, lv_of<T>(F), A(l), D(l), V(l, F.b),
-                           V(l, F.x1), V(l, F.r));
+        hipLaunchKernelGGL((sc_sweep<T, T, 1>), sweep_grid(F), sblk, 0, st, lv_of<T>(F), A(l), D(l),
+                           V(l, F.b), V(l, F.x1), V(l, F.r), (T *)nullptr, omega);
         FSI_LAUNCH_CHECK();
         hipLaunchKernelGGL((sc_restrict<T>), node_grid(C), blk, 0, st, lv_of<T>(C), lv_of<T>(F), A(l + 1),
                            D(l + 1), V(l, F.r), V(l + 1, C.b), V(l + 1, C.x0), omega);
@@ -531,7 +536,7 @@ int vcycle(const ScPlan &p, char *base, const TV *vp, TZ *zp, hipStream_t st)
     {
         const ScLevel &C = p.lv[Lc];
         const T *kinv = reinterpret_cast<const T *>(base + (sizeof(T) == 8 ? p.kinv64 : p.kinv32));
-        hipLaunchKernelGGL((sc_coarse<T>), dim3(blocks_for(C.N)), dim3(256), 0, st, (int)C.N, kinv,
+        hipLaunchKernelGGL((sc_coarse<T>), dim3((unsigned)C.N), dim3(64), 0, st, (int)C.N, kinv,
                            V(Lc, C.b), V(Lc, C.x1));
         FSI_LAUNCH_CHECK();
         if (Lc == 0) {
@@ -546,14 +551,14 @@ int vcycle(const ScPlan &p, char *base, const TV *vp, TZ *zp, hipStream_t st)
         hipLaunchKernelGGL((sc_prolong<T>), node_grid(F), blk, 0, st, lv_of<T>(F), lv_of<T>(C), D(l),
                            V(l + 1, C.x1), V(l, F.x1));
         FSI_LAUNCH_CHECK();
-        hipLaunchKernelGGL((sc_jacobi<T, T, false>), node_grid(F), blk, 0, st, lv_of<T>(F), A(l), D(l),
+        hipLaunchKernelGGL((sc_sweep<T, T, 0>), sweep_grid(F), sblk, 0, st, lv_of<T>(F), A(l), D(l),
                            V(l, F.b), V(l, F.x1), V(l, F.x0), (T *)nullptr, omega);
         FSI_LAUNCH_CHECK();
         if (l == 0)
-            hipLaunchKernelGGL((sc_jacobi<T, TZ, true>), node_grid(F), blk, 0, st, lv_of<T>(F), A(l), D(l),
+            hipLaunchKernelGGL((sc_sweep<T, TZ, 2>), sweep_grid(F), sblk, 0, st, lv_of<T>(F), A(l), D(l),
                                V(l, F.b), V(l, F.x0), (T *)nullptr, zp, omega);
         else
-            hipLaunchKernelGGL((sc_jacobi<T, T, false>), node_grid(F), blk, 0, st, lv_of<T>(F), A(l), D(l),
+            hipLaunchKernelGGL((sc_sweep<T, T, 0>), sweep_grid(F), sblk, 0, st, lv_of<T>(F), A(l), D(l),
                                V(l, F.b), V(l, F.x0), V(l, F.x1), (T *)nullptr, omega);
         FSI_LAUNCH_CHECK();
     }
@@ -634,6 +639,11 @@ int sc_plan(const Geo &g, ScPlan &p)
             nc[d] /= 2;
             l[d] *= 2.0;
         }
+    }
+    if (p.lv[0].N >= ((int64_t)1 << 31)) {
+        set_error("the pressure lattice has %lld nodes; at most 2^31 - 1 are supported",
+                  (long long)p.lv[0].N);
+        return FSI_ERR_ARG;
     }
     const int64_t nco = p.lv[p.L - 1].N;
     if (nco > SC_DIRECT_MAX_NODES) {

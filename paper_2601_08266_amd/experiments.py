@@ -58,7 +58,7 @@ def _solve_modes(run, lw, k, modes):
         rec = run.step(guess_fn=gf, inner=inner, record=False, precond=mode_precond(mode))
         out[mode] = dict(newton=rec.newton_iters, krylov=rec.krylov_iters, ms_newton=rec.ms_newton,
                          ms_guess=rec.ms_guess, res_plain=rec.res_plain, res_guess=rec.res_guess,
-                         used_guess=rec.used_guess, hist=rec.res_hist)
+                         used_guess=rec.used_guess, hist=rec.res_hist, phases_ms=rec.phases_ms)
         sols[mode] = rec.x
     ref = sols[modes[0]]
     nref = norm2(ref)

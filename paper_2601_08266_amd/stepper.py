@@ -52,6 +52,7 @@ class StepRecord:
     rn_ex: float = 0.0
     s: Optional[torch.Tensor] = None        # interface scaling field of this step
     u_prev: Optional[torch.Tensor] = None   # velocity the step started from
+    phases_ms: tuple = ()                   # Newton call: (residuals, preconditioner setups, Krylov solves)
 
 
 class ChannelRun:
@@ -188,7 +189,8 @@ class ChannelRun:
                                f"hist {list(st.res_hist[:st.newton_iters + 1])})")
         rec = StepRecord(n1, t1, x_new, self.btlam(tab64, gt, x_new) if record else None, lamg,
                          inflow, st.newton_iters, st.krylov_iters, ms, ms_guess, r_plain, r_guess, used,
-                         tuple(st.res_hist[: min(st.newton_iters + 1, 32)]))
+                         tuple(st.res_hist[: min(st.newton_iters + 1, 32)]),
+                         phases_ms=(round(st.t_residual_ms, 2), round(st.t_setup_ms, 2), round(st.t_krylov_ms, 2)))
         if record and self.record_extrap:
             rec.x_ex, rec.R_ex, rec.rn_ex = ctx["x_ex"], ctx["R_ex"], ctx["rn_ex"]
             rec.s = P64.s.clone()
