@@ -288,7 +288,7 @@ int fsi_bjacobi_apply(const fsi_grid *grid, fsi_dtype dtype, const void *pinv, c
  *           cycle: Jacobi smoothing (weight 8/9), trilinear prolongation,
  *           restriction = its transpose, alpha averaged 2x2x2 per coarser
  *           level while all cell counts are even and the level has more than
- *           512 nodes, the coarsest level (at most 1000 nodes) solved with a
+ *           64 nodes, the coarsest level (at most 1000 nodes) solved with a
  *           dense inverse.
  *   FSI_PC_SCHUR_DIAG: z_p = S_hat^{-1} v_p, z_u = F_hat^{-1} v_u.
  *   FSI_PC_SCHUR_TRI:  z_p as above, z_u = F_hat^{-1} (v_u - [J (0, z_p)]_u)

@@ -39,7 +39,7 @@ Definitions (the GPU path computes the same quantities its own way):
 * level 0 operator K_0 = sum_c alpha_c k(l), k the trilinear stiffness of a box,
   rows and columns of the Dirichlet set removed;
 * coarse levels: lattice cells merged 2x2x2 while every axis has an even count
-  and the level holds more than 512 nodes; alpha of a coarse cell = mean of its
+  and the level holds more than 64 nodes; alpha of a coarse cell = mean of its
   8 children; coarse node (I,J,K) = fine node (2I,2J,2K), Dirichlet when that
   fine node is; K_{l+1} rediscretised the same way;
 * prolongation P_l: trilinear interpolation between non-Dirichlet nodes (rows of
@@ -60,7 +60,7 @@ import scipy.sparse as sp
 from . import dlm
 
 OMEGA = 8.0 / 9.0
-COARSE_MAX_NODES = 512
+COARSE_MAX_NODES = 64
 DIRECT_MAX_NODES = 1000
 
 # 1D trilinear building blocks on the unit interval: int N_a' N_b' and int N_a N_b

@@ -450,61 +450,76 @@ __global__ __launch_bounds__(256) void sc_vel_inverse(int64_t N, const double *_
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-// dense Cholesky inverse of the coarsest operator on its non-Dirichlet nodes (host, FP64)
+// dense inverse of the coarsest operator on its non-Dirichlet nodes (host, FP64): Cholesky
+// A = L L^T row by row, U = L^{-T} (upper), A^{-1} = U U^T; every inner loop is a contiguous
+// dot product
 int coarse_inverse(const ScLevel &L, const std::vector<double> &alpha, const std::vector<uint8_t> &dm,
                    std::vector<double> &kinv)
 {
     const int64_t n = L.N;
-    std::vector<double> K((size_t)(n * n), 0.0);
+    std::vector<int64_t> pos((size_t)n, -1), keep;
+    for (int64_t i = 0; i < n; ++i)
+        if (!dm[(size_t)i]) {
+            pos[(size_t)i] = (int64_t)keep.size();
+            keep.push_back(i);
+        }
+    const int64_t m = (int64_t)keep.size();
+    std::vector<double> A((size_t)(m * m), 0.0);
     for (int cz = 0; cz < L.nc[2]; ++cz)
         for (int cy = 0; cy < L.nc[1]; ++cy)
             for (int cx = 0; cx < L.nc[0]; ++cx) {
                 const double al = alpha[(size_t)(cx + L.nc[0] * (cy + L.nc[1] * cz))];
                 int64_t ids[8];
                 for (int o = 0; o < 8; ++o)
-                    ids[o] = (cx + (o & 1)) + (int64_t)L.nn[0] * ((cy + ((o >> 1) & 1)) + (int64_t)L.nn[1] * (cz + (o >> 2)));
+                    ids[o] = pos[(size_t)((cx + (o & 1)) +
+                                          (int64_t)L.nn[0] * ((cy + ((o >> 1) & 1)) + (int64_t)L.nn[1] * (cz + (o >> 2))))];
                 for (int a = 0; a < 8; ++a)
-                    for (int b = 0; b < 8; ++b) K[(size_t)(ids[a] * n + ids[b])] += al * L.kc[a ^ b];
+                    for (int b = 0; b < 8; ++b)
+                        if (ids[a] >= 0 && ids[b] >= 0) A[(size_t)(ids[a] * m + ids[b])] += al * L.kc[a ^ b];
             }
-    std::vector<int64_t> keep;
-    for (int64_t i = 0; i < n; ++i)
-        if (!dm[(size_t)i]) keep.push_back(i);
-    const int64_t m = (int64_t)keep.size();
-    std::vector<double> A((size_t)(m * m));
-    for (int64_t i = 0; i < m; ++i)
-        for (int64_t j = 0; j < m; ++j) A[(size_t)(i * m + j)] = K[(size_t)(keep[i] * n + keep[j])];
-    // A = R^T R (upper R stored in A's upper triangle)
-    for (int64_t j = 0; j < m; ++j) {
-        double d = A[(size_t)(j * m + j)];
-        for (int64_t k = 0; k < j; ++k) d -= A[(size_t)(k * m + j)] * A[(size_t)(k * m + j)];
-        if (!(d > 0.0)) {
-            set_error("coarsest pressure Laplacian is not positive definite");
-            return FSI_ERR_BREAKDOWN;
-        }
-        const double rjj = std::sqrt(d);
-        A[(size_t)(j * m + j)] = rjj;
-        for (int64_t i = j + 1; i < m; ++i) {
-            double s = A[(size_t)(j * m + i)];
-            for (int64_t k = 0; k < j; ++k) s -= A[(size_t)(k * m + j)] * A[(size_t)(k * m + i)];
-            A[(size_t)(j * m + i)] = s / rjj;
+    // Cholesky-Banachiewicz: row i of L from rows j < i
+    std::vector<double> Lm((size_t)(m * m), 0.0);
+    for (int64_t i = 0; i < m; ++i) {
+        double *li = &Lm[(size_t)(i * m)];
+        for (int64_t j = 0; j <= i; ++j) {
+            const double *lj = &Lm[(size_t)(j * m)];
+            double s = A[(size_t)(i * m + j)];
+            for (int64_t k = 0; k < j; ++k) s -= li[k] * lj[k];
+            if (j == i) {
+                if (!(s > 0.0)) {
+                    set_error("coarsest pressure Laplacian is not positive definite");
+                    return FSI_ERR_BREAKDOWN;
+                }
+                li[i] = std::sqrt(s);
+            } else {
+                li[j] = s / lj[j];
+            }
         }
     }
-    // columns of A^{-1} = R^{-1} R^{-T} e_c
-    kinv.assign((size_t)(n * n), 0.0);
+    // U = L^{-T}: row r of U^T = L^{-1}; solve L y = e_c for each column c, store U[c][.] = y
+    // transposed as U^T rows so that A^{-1}[i][j] = sum_k W[i][k] W[j][k] with W = L^{-T} rows
+    std::vector<double> W((size_t)(m * m), 0.0);   // W[c][k] = (L^{-1})[k][c], k >= c
     std::vector<double> y((size_t)m);
     for (int64_t c = 0; c < m; ++c) {
-        for (int64_t i = 0; i < m; ++i) {   // R^T y = e_c
-            double s = (i == c) ? 1.0 : 0.0;
-            for (int64_t k = 0; k < i; ++k) s -= A[(size_t)(k * m + i)] * y[(size_t)k];
-            y[(size_t)i] = s / A[(size_t)(i * m + i)];
+        for (int64_t k = 0; k < c; ++k) y[(size_t)k] = 0.0;
+        for (int64_t k = c; k < m; ++k) {
+            const double *lk = &Lm[(size_t)(k * m)];
+            double s = (k == c) ? 1.0 : 0.0;
+            for (int64_t t = c; t < k; ++t) s -= lk[t] * y[(size_t)t];
+            y[(size_t)k] = s / lk[k];
         }
-        for (int64_t i = m - 1; i >= 0; --i) {   // R x = y
-            double s = y[(size_t)i];
-            for (int64_t k = i + 1; k < m; ++k) s -= A[(size_t)(i * m + k)] * y[(size_t)k];
-            y[(size_t)i] = s / A[(size_t)(i * m + i)];
-        }
-        for (int64_t i = 0; i < m; ++i) kinv[(size_t)(keep[c] * n + keep[i])] = y[(size_t)i];
+        for (int64_t k = 0; k < m; ++k) W[(size_t)(c * m + k)] = y[(size_t)k];
     }
+    // A^{-1} = L^{-T} L^{-1}: entry (i, j) = sum_k (L^{-1})[k][i] (L^{-1})[k][j] = W[i] . W[j]
+    kinv.assign((size_t)(n * n), 0.0);
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j <= i; ++j) {
+            const double *wi = &W[(size_t)(i * m)], *wj = &W[(size_t)(j * m)];
+            double s = 0.0;
+            for (int64_t k = i; k < m; ++k) s += wi[k] * wj[k];
+            kinv[(size_t)(keep[i] * n + keep[j])] = s;
+            kinv[(size_t)(keep[j] * n + keep[i])] = s;
+        }
     return FSI_OK;
 }
 

@@ -6,7 +6,7 @@
 namespace fsi {
 
 constexpr int SC_MAX_LEVELS = 16;
-constexpr int64_t SC_COARSE_MAX_NODES = 512;   // coarsen while a level holds more nodes
+constexpr int64_t SC_COARSE_MAX_NODES = 64;    // coarsen while a level holds more nodes
 constexpr int64_t SC_DIRECT_MAX_NODES = 1000;  // largest coarsest level (dense inverse)
 
 struct ScLevel {

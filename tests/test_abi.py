@@ -55,7 +55,7 @@ def test_status_strings_and_argument_errors_without_gpu():
 
 
 @pytest.mark.parametrize("n,order", [((192, 192, 192), 1), ((96, 96, 96), 2), ((64, 64, 64), 1),
-                                     ((8, 8, 8), 1), ((10, 12, 14), 1), ((5, 6, 7), 2)])
+                                     ((8, 8, 8), 1), ((10, 12, 14), 1), ((5, 6, 7), 2), ((3, 3, 3), 1)])
 def test_schur_levels_follow_the_coarsening_rule(n, order):
     # host-only: the library's multigrid levels equal the oracle's rule (no device work)
     import paper_2601_08266_amd as fsi

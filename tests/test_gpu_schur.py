@@ -37,7 +37,7 @@ def _case(name):
         c2 = W.CONFIGS["c2"]
         return build(c2, W.advection_field(c2.grid, c2.seed_fields))
     grids = {"ragged": W.Grid((10, 12, 14), 1), "q2": W.Grid((6, 6, 6), 2), "three": W.Grid((16, 16, 16), 1),
-             "single": W.Grid((4, 4, 4), 1), "cavity": W.Grid((8, 8, 8), 1)}
+             "single": W.Grid((3, 3, 3), 1), "cavity": W.Grid((8, 8, 8), 1)}
     g = grids[name]
     X = rng.uniform(0.15, 0.85, (3, 3000))
     kappa = rng.uniform(1.0, 50.0, 3000)

@@ -111,9 +111,9 @@ def test_prolongation_reproduces_trilinear_fields():
 
 def test_level_shapes_rule():
     assert schur.level_shapes((192, 192, 192)) == [(192,) * 3, (96,) * 3, (48,) * 3, (24,) * 3, (12,) * 3,
-                                                   (6,) * 3]
-    assert schur.level_shapes((64, 64, 64))[-1] == (4, 4, 4)
-    assert schur.level_shapes((8, 8, 8)) == [(8, 8, 8), (4, 4, 4)]
+                                                   (6,) * 3, (3,) * 3]
+    assert schur.level_shapes((64, 64, 64))[-1] == (2, 2, 2)
+    assert schur.level_shapes((8, 8, 8)) == [(8, 8, 8), (4, 4, 4), (2, 2, 2)]
     assert schur.level_shapes((10, 12, 14)) == [(10, 12, 14), (5, 6, 7)]
 
 
@@ -154,7 +154,7 @@ def test_vcycle_contraction(jump, bound):
 
 
 def test_single_level_solves_exactly_and_dirichlet_rows():
-    g = W.Grid((4, 4, 4), 1)
+    g = W.Grid((3, 3, 3), 1)
     N = g.num_nodes
     rng = np.random.default_rng(2)
     a = rng.standard_normal((3, N))
