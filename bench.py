@@ -238,7 +238,7 @@ def main(argv=None):
                     help="comma list: c3 inner precisions (mixed,f64); c5/probe Newton modes "
                          "(plain|extrap|nn _ mixed|f64, suffix _st / _sd for the Schur preconditioner)")
     ap.add_argument("--exp-precond", default="bjacobi", choices=["bjacobi", "schur_diag", "schur_tri"],
-                    help="c3 preconditioner")
+                    help="preconditioner of the c3 solve and of the warmstart run's Newton steps")
     ap.add_argument("--exp-restart", type=int, default=50, help="c3 FGMRES restart length")
     ap.add_argument("--exp-train-end", type=int, default=100)
     ap.add_argument("--exp-epochs", type=int, default=20)
@@ -374,7 +374,7 @@ def run_experiment(args):
     if args.experiment == "warmstart":
         summary, lw = ex.warmstart_c4(steps=args.exp_steps, train_end=args.exp_train_end,
                                       epochs=args.exp_epochs, eval_stride=args.exp_stride,
-                                      save_path=args.exp_save)
+                                      save_path=args.exp_save, precond=args.exp_precond)
         print(json.dumps({"experiment": "warmstart_c4", **summary}))
         return 0
     summary = ex.large_c5(state_path=args.exp_load, modes=modes)
