@@ -21,5 +21,7 @@ Contents (each function cites the passage of the paper it follows):
                  2.4's reduced system: nodal velocity blocks and a pressure
                  Schur-complement Laplacian with one multigrid V-cycle.
 * ``newton``   - the nonlinear residual of one implicit step and Newton.
+* ``genalpha`` - generalized-alpha time stepping (section 2.4) in stage
+                 variables on top of ``newton``.
 * ``conv3d``   - 3x3x3 convolution layers for the learned warm start.
 """

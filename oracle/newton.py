@@ -46,13 +46,14 @@ def multiplier(grid, x, cell, xi, kappa, g):
 
 def solve_step(grid, prm, x0, u_old, cell, xi, kappa, g, s=None, mask=None, gD=None,
                tol_abs=None, rel=1e-8, max_newton=20, linear="dense", eta=1e-3,
-               visc_strong=True, restart=50):
-    """Newton from x0 until ||R||_2 <= tol_abs (default rel * ||R(x0)||_2)."""
+               visc_strong=True, restart=50, body=None):
+    """Newton from x0 until ||R||_2 <= tol_abs (default rel * ||R(x0)||_2); body: an optional
+    nodal source added to c_m u_old."""
     N = grid.num_nodes
     x = np.asarray(x0, dtype=np.float64).reshape(4, N).copy()
     hist = []
     lin_iters = []
-    R = residual(grid, prm, x, u_old, cell, xi, kappa, g, s, mask, gD, visc_strong=visc_strong)
+    R = residual(grid, prm, x, u_old, cell, xi, kappa, g, s, mask, gD, body=body, visc_strong=visc_strong)
     r0 = np.linalg.norm(R)
     if tol_abs is None:
         tol_abs = rel * r0
@@ -82,7 +83,7 @@ def solve_step(grid, prm, x0, u_old, cell, xi, kappa, g, s=None, mask=None, gD=N
                                      max_iters=2000)
             lin_iters.append(info["iters"])
         x = x + dx.reshape(4, N)
-        R = residual(grid, prm, x, u_old, cell, xi, kappa, g, s, mask, gD, visc_strong=visc_strong)
+        R = residual(grid, prm, x, u_old, cell, xi, kappa, g, s, mask, gD, body=body, visc_strong=visc_strong)
         hist.append(np.linalg.norm(R))
     return x, {"history": hist, "tol_abs": tol_abs, "linear_iters": lin_iters,
                "converged": hist[-1] <= tol_abs}
