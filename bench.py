@@ -156,7 +156,7 @@ def time_applies(fsi, torch, case, steps, warmup, profile):
 PROBE_MODES = ["plain_f64", "plain_mixed", "extrap_mixed", "plain_f64_st", "plain_mixed_st", "extrap_mixed_st"]
 
 
-def newton_step_probe(warm_steps=60, measure_steps=3, modes=None):
+def newton_step_probe(warm_steps=60, measure_steps=3, modes=None, integrator="be", rho_inf=0.5):
     """Short Newton-step comparison on the 64^3 rotating-plates channel: after a few plain steps,
     the next steps are re-solved from the same state with plain FP64, mixed precision, and mixed
     precision + extrapolated warm start, each with the block-Jacobi and (suffix _st) the
@@ -167,19 +167,17 @@ def newton_step_probe(warm_steps=60, measure_steps=3, modes=None):
     from paper_2601_08266_amd import experiments as ex
     from paper_2601_08266_amd.stepper import ChannelRun
 
-    run = ChannelRun(W.CONFIGS["c4"])
+    run = ChannelRun(W.CONFIGS["c4"], integrator=integrator, rho_inf=rho_inf)
     for _ in range(warm_steps):
         run.step()
     rows = []
     for k in range(warm_steps, warm_steps + measure_steps):
-        run.x = run.history[k].x.clone()
-        run.n = k
         rows.append(ex._solve_modes(run, None, k, modes or PROBE_MODES))
-        run.x = run.history[k].x.clone()
-        run.n = k
+        run.restore(k)
         run.step()
     out = {"workload": "64^3 Q1 channel, 200k rotating-plate points, steps "
-                       f"{warm_steps + 1}-{warm_steps + measure_steps}, tol 1e-8*||R(x_plain)||"}
+                       f"{warm_steps + 1}-{warm_steps + measure_steps}, tol 1e-8*||R(x_plain)||",
+           "integrator": integrator if integrator == "be" else f"{integrator} rho_inf={rho_inf}"}
     for m in modes or PROBE_MODES:
         out[m + "_ms"] = round(sum(r[m]["ms_newton"] + r[m]["ms_guess"] for r in rows) / len(rows), 2)
         out[m + "_krylov"] = round(sum(r[m]["krylov"] for r in rows) / len(rows), 1)
@@ -240,6 +238,9 @@ def main(argv=None):
     ap.add_argument("--exp-precond", default="bjacobi", choices=["bjacobi", "schur_diag", "schur_tri"],
                     help="preconditioner of the c3 solve and of the warmstart run's Newton steps")
     ap.add_argument("--exp-restart", type=int, default=50, help="c3 FGMRES restart length")
+    ap.add_argument("--exp-integrator", default="be", choices=["be", "genalpha"],
+                    help="time integrator of the probe / warmstart / c5 runs")
+    ap.add_argument("--exp-rho-inf", type=float, default=0.5, help="generalized-alpha rho_inf")
     ap.add_argument("--exp-train-end", type=int, default=100)
     ap.add_argument("--exp-epochs", type=int, default=20)
     ap.add_argument("--exp-stride", type=int, default=1)
@@ -369,15 +370,19 @@ def run_experiment(args):
                                         precond=args.exp_precond, restart=args.exp_restart)}))
         return 0
     if args.experiment == "probe":
-        print(json.dumps({"experiment": "newton_probe", **newton_step_probe(modes=modes)}))
+        print(json.dumps({"experiment": "newton_probe",
+                          **newton_step_probe(modes=modes, integrator=args.exp_integrator,
+                                              rho_inf=args.exp_rho_inf)}))
         return 0
     if args.experiment == "warmstart":
         summary, lw = ex.warmstart_c4(steps=args.exp_steps, train_end=args.exp_train_end,
                                       epochs=args.exp_epochs, eval_stride=args.exp_stride,
-                                      save_path=args.exp_save, precond=args.exp_precond)
+                                      save_path=args.exp_save, precond=args.exp_precond,
+                                      integrator=args.exp_integrator, rho_inf=args.exp_rho_inf)
         print(json.dumps({"experiment": "warmstart_c4", **summary}))
         return 0
-    summary = ex.large_c5(state_path=args.exp_load, modes=modes)
+    summary = ex.large_c5(state_path=args.exp_load, modes=modes, integrator=args.exp_integrator,
+                          rho_inf=args.exp_rho_inf)
     print(json.dumps({"experiment": "large_c5", **summary}))
     return 0
 

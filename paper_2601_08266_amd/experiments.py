@@ -45,8 +45,7 @@ def _solve_modes(run, lw, k, modes):
     out = {}
     sols = {}
     for mode in modes:
-        run.x = run.history[k].x.clone()
-        run.n = k
+        run.restore(k)
         inner = torch.float64 if "f64" in mode else torch.float32
         gf = None
         if lw is not None and mode.startswith("nn"):
@@ -70,9 +69,9 @@ def _solve_modes(run, lw, k, modes):
 
 
 def warmstart_c4(steps=200, train_end=100, epochs=20, lr=1e-3, eval_stride=1, seed=0,
-                 save_path=None, precond="bjacobi"):
+                 save_path=None, precond="bjacobi", integrator="be", rho_inf=0.5):
     cfg = W.CONFIGS["c4"]
-    run = ChannelRun(cfg, precond=precond)
+    run = ChannelRun(cfg, precond=precond, integrator=integrator, rho_inf=rho_inf)
     run.record_extrap = True
     t0 = time.perf_counter()
     for n in range(steps):
@@ -109,7 +108,7 @@ def warmstart_c4(steps=200, train_end=100, epochs=20, lr=1e-3, eval_stride=1, se
 
     summary = {
         "workload": "64^3 Q1 channel, 200k points on three rotating plates, dt=1e-3",
-        "precond": precond,
+        "precond": precond, "integrator": integrator,
         "steps": steps, "train_steps": [2, train_end], "eval_steps": [train_end + 1, steps],
         "epochs": epochs, "params": lw.net.n_params, "train_ms": round(lw.train_ms, 1),
         "final_train_loss": lw.losses[-1] if lw.losses else None,
@@ -136,9 +135,10 @@ def warmstart_c4(steps=200, train_end=100, epochs=20, lr=1e-3, eval_stride=1, se
     return summary, lw
 
 
-def large_c5(lw_c4=None, warmup_steps=3, state_path=None, modes=None, warmup_precond="schur_tri"):
+def large_c5(lw_c4=None, warmup_steps=3, state_path=None, modes=None, warmup_precond="schur_tri",
+             integrator="be", rho_inf=0.5):
     cfg = W.CONFIGS["c5"]
-    run = ChannelRun(cfg)
+    run = ChannelRun(cfg, integrator=integrator, rho_inf=rho_inf)
     for n in range(warmup_steps):
         rec = run.step(precond=warmup_precond)
         _log(f"c5 warm-up step {rec.n}: newton={rec.newton_iters} krylov={rec.krylov_iters} "
@@ -164,7 +164,8 @@ def large_c5(lw_c4=None, warmup_steps=3, state_path=None, modes=None, warmup_pre
         _log(f"c5 step {k + 1} {m}: {r[m]['newton']}N/{r[m]['krylov']}K "
              f"{r[m]['ms_newton'] + r[m]['ms_guess']:.0f} ms")
     summary = {"workload": "192^3 Q1 channel, 2M points on three rotating plates",
-               "step": k + 1, "dof": 4 * run.N, "warmup_precond": warmup_precond, "modes": r}
+               "step": k + 1, "dof": 4 * run.N, "warmup_precond": warmup_precond, "integrator": integrator,
+               "modes": r}
     if "plain_f64" in r:
         base = r["plain_f64"]["ms_newton"] + r["plain_f64"]["ms_guess"]
         for m in modes[1:]:

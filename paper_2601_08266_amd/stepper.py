@@ -53,13 +53,28 @@ class StepRecord:
     s: Optional[torch.Tensor] = None        # interface scaling field of this step
     u_prev: Optional[torch.Tensor] = None   # velocity the step started from
     phases_ms: tuple = ()                   # Newton call: (residuals, preconditioner setups, Krylov solves)
+    xdot: Optional[torch.Tensor] = None     # rates at this state (generalized-alpha)
 
 
 class ChannelRun:
     def __init__(self, cfg, device="cuda", inner=torch.float32, eta=1e-3, restart=50,
-                 rel_tol=1e-8, period=0.8, amp_deg=20.0, max_krylov=4000, precond="bjacobi"):
+                 rel_tol=1e-8, period=0.8, amp_deg=20.0, max_krylov=4000, precond="bjacobi",
+                 integrator="be", rho_inf=0.5):
         self.cfg = cfg
         self.precond = precond
+        # time integrator: backward Euler, or generalized-alpha (section 2.4) in stage variables:
+        # the stage residual at t_n + alpha_f dt is the backward-Euler-form residual with mass
+        # coefficient alpha_m / (gamma dt alpha_f) and source c V_n - (1 - alpha_m/gamma) Vdot_n;
+        # velocity and pressure are then advanced through their rates
+        if integrator == "be":
+            self.coefs = (1.0, 1.0, 1.0)
+        elif integrator == "genalpha":
+            am = 0.5 * (3.0 - rho_inf) / (1.0 + rho_inf)
+            af = 1.0 / (1.0 + rho_inf)
+            self.coefs = (am, af, 0.5 + am - af)
+        else:
+            raise ValueError(f"unknown integrator {integrator!r}")
+        self.integrator = integrator
         self.g = cfg.grid
         self.N = self.g.num_nodes
         self.dev = torch.device(device)
@@ -67,6 +82,9 @@ class ChannelRun:
         self.max_krylov = max_krylov
         self.period, self.amp = period, amp_deg
         self.prm = make_params(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
+        am, af, gm = self.coefs
+        self.c_stage = cfg.c_m if integrator == "be" else am / (gm * cfg.dt * af)
+        self.prm_stage = make_params(cfg.nu, self.c_stage, cfg.dt, cfg.C_T, cfg.C_I)
         g = self.g
         mask = W.channel_dirichlet_mask(g)
         self.mask = torch.tensor(W.mask_to_bits(mask).view(np.int32), device=self.dev)
@@ -80,6 +98,7 @@ class ChannelRun:
         self.f = torch.zeros(3 * self.N, dtype=torch.float64, device=self.dev)
         self.zero_out = torch.zeros(self.N * 32, dtype=torch.float32, device=self.dev)
         self.x = torch.zeros(4 * self.N, dtype=torch.float64, device=self.dev)
+        self.xdot = torch.zeros(4 * self.N, dtype=torch.float64, device=self.dev)   # rates (generalized-alpha)
         self.R = torch.empty_like(self.x)
         self.n = 0
         self.record_extrap = False
@@ -95,6 +114,15 @@ class ChannelRun:
                                                                             device=self.dev),
                                        torch.zeros(3 * self.N, dtype=torch.float64, device=self.dev), 0.0))
 
+    def restore(self, k):
+        """Go back to the recorded state k (to re-solve the next step another way)."""
+        self.x = self.history[k].x.clone()
+        if self.history[k].xdot is not None:
+            self.xdot = self.history[k].xdot.clone()
+        elif k == 0:
+            self.xdot.zero_()
+        self.n = k
+
     def inflow_value(self, t):
         return math.sin(2.0 * math.pi * t / self.period)
 
@@ -109,10 +137,10 @@ class ChannelRun:
         gram32 = dlm_gram(self.g, tab32, self.kappa32)
         lamg = torch.zeros(3 * self.N, dtype=torch.float64, device=self.dev)
         dlm_BT(self.g, tab64, gt, lamg, kappa=self.kappa64)
-        P64 = Problem(self.g, self.prm, self.x, tab64, self.kappa64, s=tab64.s, mask=self.mask,
+        P64 = Problem(self.g, self.prm_stage, self.x, tab64, self.kappa64, s=tab64.s, mask=self.mask,
                       gram=gram64)
         a32 = torch.zeros(3 * self.N, dtype=torch.float32, device=self.dev)
-        P32 = Problem(self.g, self.prm, a32, tab32, self.kappa32, s=tab32.s, mask=self.mask,
+        P32 = Problem(self.g, self.prm_stage, a32, tab32, self.kappa32, s=tab32.s, mask=self.mask,
                       gram=gram32)
         return P64, P32, lamg, gt, tab64
 
@@ -136,10 +164,17 @@ class ChannelRun:
         cfg = self.cfg
         n1 = self.n + 1
         t1 = n1 * cfg.dt
-        P64, P32, lamg, gt, tab64 = self._points(t1)
-        inflow = self.inflow_value(t1)
+        am, af, gm = self.coefs
+        be = self.integrator == "be"
+        # stage time, solid kinematics and Dirichlet data (t_{n+1} for backward Euler)
+        t_s = t1 if be else self.n * cfg.dt + af * cfg.dt
+        P64, P32, lamg, gt, tab64 = self._points(t_s)
+        inflow = self.inflow_value(t1) if be else \
+            (1.0 - af) * self.inflow_value(self.n * cfg.dt) + af * self.inflow_value(t1)
         axpby(inflow, self.inflow_pattern, 0.0, self.gD)
-        axpby(cfg.c_m, self.x[: 3 * self.N], 0.0, self.f)
+        axpby(self.c_stage, self.x[: 3 * self.N], 0.0, self.f)
+        if not be:
+            axpby(-(1.0 - am / gm), self.xdot[: 3 * self.N], 1.0, self.f)
         torch.cuda.synchronize()
         t_g0 = time.perf_counter()
         # plain guess: previous state with the new Dirichlet values
@@ -153,9 +188,10 @@ class ChannelRun:
         ctx = {"P64": P64, "lamg": lamg, "inflow": inflow, "s": P64.s, "x_ex": None, "R_ex": None,
                "rn_ex": 0.0}
         if self.n >= 1 and (guess_fn is not None or self.record_extrap):
+            # linear extrapolation of the state to the stage time: x^n + alpha_f (x^n - x^{n-1})
             x_ex = torch.empty_like(self.x)
-            axpby(2.0, self.history[self.n].x, 0.0, x_ex)
-            axpby(-1.0, self.history[self.n - 1].x, 1.0, x_ex)
+            axpby(1.0 + af, self.history[self.n].x, 0.0, x_ex)
+            axpby(-af, self.history[self.n - 1].x, 1.0, x_ex)
             ws.unpack(self.N, 32, self.zero_out, x_ex.clone(), [0, 0, 0, 0], [1, 1, 1, 1], x_ex,
                       mask=self.mask, gD=self.gD)
             ctx["rn_ex"] = self.residual_norm(P64, x_ex, lamg)
@@ -187,7 +223,16 @@ class ChannelRun:
         if rc != 0:
             raise RuntimeError(f"Newton failed at step {n1} (status {rc}, iters {st.newton_iters}, "
                                f"hist {list(st.res_hist[:st.newton_iters + 1])})")
-        rec = StepRecord(n1, t1, x_new, self.btlam(tab64, gt, x_new) if record else None, lamg,
+        x_stage = x_new
+        if not be:
+            # X_{n+1} = X_n + (X_stage - X_n) / alpha_f; Xdot_{n+1} = Xdot_n + (X_{n+1} - X_n - dt Xdot_n) / (gamma dt)
+            x_new = self.x.clone()
+            axpby(1.0 / af, x_stage, 1.0 - 1.0 / af, x_new)
+            xd = self.xdot.clone()
+            axpby(1.0 / (gm * cfg.dt), x_new, 1.0 - 1.0 / gm, xd)
+            axpby(-1.0 / (gm * cfg.dt), self.x, 1.0, xd)
+            self.xdot = xd
+        rec = StepRecord(n1, t1, x_new, self.btlam(tab64, gt, x_stage) if record else None, lamg,
                          inflow, st.newton_iters, st.krylov_iters, ms, ms_guess, r_plain, r_guess, used,
                          tuple(st.res_hist[: min(st.newton_iters + 1, 32)]),
                          phases_ms=(round(st.t_residual_ms, 2), round(st.t_setup_ms, 2), round(st.t_krylov_ms, 2)))
@@ -195,6 +240,7 @@ class ChannelRun:
             rec.x_ex, rec.R_ex, rec.rn_ex = ctx["x_ex"], ctx["R_ex"], ctx["rn_ex"]
             rec.s = P64.s.clone()
             rec.u_prev = self.history[self.n].x[: 3 * self.N].clone()
+        rec.xdot = self.xdot.clone() if not be else None
         self.x = x_new
         self.n = n1
         if record:
