@@ -158,3 +158,65 @@ def test_newton_with_schur_c1_matches_dense_newton(mode):
           f"oracle ||R|| {np.linalg.norm(R):.3e} (tol {tol:.3e})")
     assert np.linalg.norm(R) <= tol * 1.01
     assert np.linalg.norm(xs - x_ref.ravel()) <= 1e-6 * np.linalg.norm(x_ref)
+
+
+@pytest.mark.parametrize("name", ["c5", "c3"])
+def test_schur_full_size_properties(name):
+    """Full-size workloads (192^3 Q1 + 2M points; 96^3 Q2 + 500k points), where the oracle
+    cannot run whole V-cycles: level-0 alpha at sampled lattice cells against the oracle's
+    formula, coarse alpha = mean of the 8 children, linearity of P^{-1}, and symmetry of the
+    pressure V(2,2) cycle (Jacobi smoothing, R = P^T, exact coarse solve) in FP64 and FP32."""
+    import torch
+    import paper_2601_08266_amd as fsi
+    cfg = W.CONFIGS[name]
+    print(f"schur full size {name}", flush=True)
+    P = build(cfg, W.advection_field(cfg.grid, cfg.seed_fields))
+    g = P["g"]
+    N = g.num_nodes
+    _, _, blocks, nsing = fsi.bjacobi_setup(P["J64"], want32=False, want_blocks=True)
+    assert nsing == 0
+    pc = fsi.schur_setup(P["J64"], blocks)
+    del blocks
+    k, cells, offs = fsi.schur_info(g)
+    alphas = [pc[off:off + 8 * c[0] * c[1] * c[2]].view(torch.float64) for off, c in zip(offs, cells)]
+    # sampled level-0 cells against the oracle's definition
+    rng = np.random.default_rng(7)
+    nc0 = cells[0]
+    sel = rng.choice(nc0[0] * nc0[1] * nc0[2], 4000, replace=False)
+    d = oschur.dlm_row_sums(g, P["cell"], P["xi"], P["kappa"])
+    beta = oschur.node_beta(g, P["prm_o"], d)
+    nn = g.nodes_per_axis
+    cx, cy, cz = sel % nc0[0], (sel // nc0[0]) % nc0[1], sel // (nc0[0] * nc0[1])
+    ids = np.stack([(cx + (o & 1)) + nn[0] * ((cy + ((o >> 1) & 1)) + nn[1] * (cz + (o >> 2))) for o in range(8)])
+    nu, c_m, dt, C_T, C_I = P["prm_o"]
+    a = P["a"].reshape(3, N)
+    am = a[:, ids].mean(axis=1)
+    sm = P["s"][ids].mean(axis=0)
+    h = g.h
+    tau = 1.0 / np.sqrt(sm * (C_T / dt ** 2 + sum(am[q] ** 2 / h[q] ** 2 for q in range(3))
+                              + C_I * nu * nu * sum(1.0 / h[q] ** 4 for q in range(3))))
+    ref = tau + beta[ids].mean(axis=0)
+    got = alphas[0][torch.tensor(sel, device="cuda")].cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"  level-0 alpha at 4000 cells: {err:.3e}", flush=True)
+    assert err <= 1e-13
+    for l in range(1, k):
+        f = alphas[l - 1].view(cells[l - 1][2], cells[l - 1][1], cells[l - 1][0])
+        mean = 0.125 * sum(f[dz::2, dy::2, dx::2] for dz in (0, 1) for dy in (0, 1) for dx in (0, 1))
+        e = (mean.reshape(-1) - alphas[l]).abs().max().item() / alphas[l].abs().max().item()
+        assert e <= 1e-15, (l, e)
+    # linearity and symmetry
+    for dt_, J, tol_lin, tol_sym in ((torch.float64, P["J64"], 1e-13, 1e-11), (torch.float32, P["J32"], 2e-6, 1e-4)):
+        gen = torch.Generator(device="cuda").manual_seed(3)
+        u = torch.randn(4 * N, dtype=dt_, device="cuda", generator=gen)
+        w = torch.randn(4 * N, dtype=dt_, device="cuda", generator=gen)
+        zu = fsi.schur_apply(J, "schur_diag", pc, u)
+        zw = fsi.schur_apply(J, "schur_diag", pc, w)
+        zc = fsi.schur_apply(J, "schur_diag", pc, 2.0 * u - 3.0 * w)
+        lin = ((zc - (2.0 * zu - 3.0 * zw)).norm() / zc.norm()).item()
+        up, wp, zup, zwp = u[3 * N:].double(), w[3 * N:].double(), zu[3 * N:].double(), zw[3 * N:].double()
+        a1, a2 = torch.dot(zup, wp).item(), torch.dot(up, zwp).item()
+        sym = abs(a1 - a2) / max(abs(a1), abs(a2))
+        print(f"  {dt_}: linearity {lin:.3e}, pressure V-cycle symmetry {sym:.3e}", flush=True)
+        assert lin <= tol_lin
+        assert sym <= tol_sym
