@@ -42,11 +42,11 @@ def special_cloud(grid, rng, m):
     return np.ascontiguousarray(X)
 
 
-@pytest.mark.parametrize("case", ["c1", "c2", "special8", "special_q2", "empty"])
+@pytest.mark.parametrize("case", ["c1", "c2", "c3", "c5", "special8", "special_q2", "empty"])
 def test_locate_bitwise(case):
     import paper_2601_08266_amd as fsi
     rng = np.random.default_rng(4)
-    if case in ("c1", "c2"):
+    if case in ("c1", "c2", "c3", "c5"):
         cfg = W.CONFIGS[case]
         g = cfg.grid
         X, _ = points_for(cfg)
@@ -83,7 +83,7 @@ def test_locate_bitwise(case):
     print(f"{case}: m={m} n_occ={tab.n_occ} outside={tab.n_outside}")
 
 
-@pytest.mark.parametrize("case", ["c1", "c2", "q2"])
+@pytest.mark.parametrize("case", ["c1", "c2", "q2", "c3", "c5"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_B_BT_parity_and_adjoint(case, dtype):
     import paper_2601_08266_amd as fsi
@@ -205,16 +205,18 @@ def test_jacobian_c1_full(dtype, mask_on, use_gram):
     assert err <= TOL[dtype]
 
 
+@pytest.mark.parametrize("case", ["c2", "c5", "c3"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("use_gram", [True, False])
-def test_jacobian_c2_sampled(dtype, use_gram):
-    """Full 64^3 / 200k-point size in the benchmark's launch configuration: VMS rows from
-    the oracle's per-row recomputation, DLM term from the oracle's point-by-point B and
-    B^T over all points."""
-    cfg = W.CONFIGS["c2"]
+def test_jacobian_sampled_full_size(case, dtype, use_gram):
+    """Full sizes in the benchmark's launch configuration (64^3 Q1 + 200k points, 192^3 Q1 +
+    2M points, 96^3 Q2 + 500k points): VMS rows from the oracle's per-row recomputation, DLM
+    term from the oracle's point-by-point B and B^T over all points."""
+    cfg = W.CONFIGS[case]
+    print(f"J {case} {dtype} gram={use_gram}", flush=True)
     g, a, x, s, mask, cell, xi, kappa, prm_o, y = _jacobian_case(cfg, dtype, False, use_gram)
     N = g.num_nodes
-    rows = sample_rows(g, 3000, seed=2)
+    rows = sample_rows(g, 3000, seed=2, brick=(8, 8, 4) if g.order == 1 else (4, 4, 4))
     ref = ovms.apply_rows(g, prm_o, a, x, rows, s=s)
     dlm_full = np.zeros(4 * N)
     dlm_full[:3 * N] = odlm.apply_BT(g, cell, xi, odlm.apply_B(g, cell, xi, x.reshape(4, N)[:3]),
@@ -226,5 +228,5 @@ def test_jacobian_c2_sampled(dtype, use_gram):
     near = np.random.default_rng(3).choice(near, min(2000, near.size), replace=False)
     ref2 = ovms.apply_rows(g, prm_o, a, x, near, s=s) + dlm_full[near]
     err2 = rows_rel_err(y[near], ref2)
-    print(f"J c2 {dtype}: sampled {err:.3e}, near-solid {err2:.3e}")
+    print(f"J {case} {dtype}: sampled {err:.3e}, near-solid {err2:.3e}")
     assert err <= TOL[dtype] and err2 <= TOL[dtype]

@@ -27,8 +27,12 @@ def rel(a, b):
     return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
 
 
+# (65, 65, 65): the 64^3 workload's node lattice, with the network's padded layer shapes
+# (input 32 -> 64, hidden 64 -> 64, output 64 -> 32), as the warm start runs them
 @pytest.mark.parametrize("dims,cin,cout", [((7, 5, 6), 32, 64), ((9, 4, 3), 64, 32),
-                                           ((5, 5, 5), 64, 96), ((3, 2, 2), 32, 32)])
+                                           ((5, 5, 5), 64, 96), ((3, 2, 2), 32, 32),
+                                           ((65, 65, 65), 32, 64), ((65, 65, 65), 64, 64),
+                                           ((65, 65, 65), 64, 32)])
 def test_conv_forward_and_data_gradient(dims, cin, cout):
     import torch
     import paper_2601_08266_amd.warmstart as ws
@@ -64,7 +68,7 @@ def test_conv_forward_and_data_gradient(dims, cin, cout):
 
 
 @pytest.mark.parametrize("dims,cin,cout", [((7, 5, 6), 32, 64), ((13, 11, 17), 64, 64),
-                                           ((4, 4, 3), 64, 32)])
+                                           ((4, 4, 3), 64, 32), ((65, 65, 65), 64, 64)])
 def test_conv_weight_gradient(dims, cin, cout):
     import torch
     import paper_2601_08266_amd.warmstart as ws
