@@ -18,6 +18,7 @@ over the timed region.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -120,6 +121,36 @@ def build_problem(cfg, dtype, dev):
     ws = torch.empty(prob.workspace_bytes(), dtype=torch.uint8, device=dev)
     return dict(prob=prob, x=xt, y=y, ws=ws, tab=tab, locate_ms=locate_ms, gram_ms=gram_ms, Xt=Xt, N=N,
                 a_np=a, x_np=x, X_np=X, kappa_np=kappa)
+
+
+def time_dlm(fsi, torch, case, reps=50):
+    """Standalone B u and y += B^T (kappa lam) (fsi_dlm_B / fsi_dlm_BT, FP64) on the workload's
+    point set, timed with events on the launch stream over `reps` calls each."""
+    g, tab, N = case["prob"].grid, case["tab"], case["N"]
+    m = tab.m
+    u = case["x"][: 3 * N]
+    Bu = torch.empty(3 * m, dtype=torch.float64, device="cuda")
+    lam = torch.ones(3 * m, dtype=torch.float64, device="cuda")
+    y = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
+    kap = case["prob"].kappa
+    ws = torch.empty(int(fsi._lib.lib().fsi_dlm_BT_workspace(ctypes.byref(g), tab.n_occ, 0)) or 1,
+                     dtype=torch.uint8, device="cuda")
+    out = {}
+    for name, fn in (("B", lambda: fsi.dlm_B(g, tab, u, Bu)),
+                     ("BT", lambda: fsi.dlm_BT(g, tab, lam, y, kappa=kap, ws=ws))):
+        for _ in range(5):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        out[f"dlm_{name}_us"] = round(us, 2)
+        out[f"dlm_{name}_Gpoints_per_s"] = round(m / us * 1e-3, 3)
+    return out
 
 
 def time_applies(fsi, torch, case, steps, warmup, profile):
@@ -323,6 +354,7 @@ def main(argv=None):
             "locate_ms": round(case64["locate_ms"], 3),
             "dlm_gram_ms": round(case64["gram_ms"], 3),
             "n_occupied_cells": case64["tab"].n_occ,
+            **time_dlm(fsi, torch, case64),
         },
     }
     if not args.no_newton and args.workload == "c2":

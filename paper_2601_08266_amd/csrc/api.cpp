@@ -315,7 +315,7 @@ FSI_API int fsi_dlm_BT(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const i
     rc = launch_dlm_cell_reduce(g, dtype, false, m, n_occ, occ_cell, occ_start, perm, xi, kappa, lam,
                                 nullptr, ws, st);
     if (rc) return rc;
-    return launch_dlm_node_gather(g, dtype, ws, occ_index, y, st);
+    return launch_dlm_node_gather(g, dtype, n_occ, occ_cell, ws, occ_index, y, st);
 }
 
 FSI_API int fsi_dlm_gram(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const void *xi,

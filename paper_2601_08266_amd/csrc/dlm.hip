@@ -10,12 +10,13 @@
 //  CSR      occupied cells from the sorted keys (flag + scan), the inverse map
 //           cell -> occupied index, and the interface band of s.
 //  B        one lane per point: (p+1)^3 shape values, gather of the cell nodes.
-//  B^T      one wave per occupied cell reduces its points' N_A kappa lambda
+//  B^T      8 lanes (Q1) or a wavefront (Q2) per occupied cell reduce its points' N_A kappa lambda
 //           (or N_A kappa (B u) when fused into the Jacobian) into per-cell
-//           corner sums with a fixed butterfly order; a node-parallel gather
-//           adds the corner sums of the occupied neighbour cells in a fixed
-//           order.  No floating-point atomics anywhere, so results are
-//           bitwise reproducible.
+//           corner sums with a fixed butterfly order; a gather over the
+//           occupied cells' corners (the corner of a node's first occupied
+//           cell owns the node) adds the corner sums of the occupied cells
+//           around each node in a fixed order.  No floating-point atomics
+//           anywhere, so results are bitwise reproducible.
 #include <utility>
 
 #include "dlm.hpp"
@@ -341,17 +342,12 @@ __global__ __launch_bounds__(256) void dlm_B_kernel(Geo g, int64_t m, const int3
     for (int f = 0; f < 3; ++f) Bu[f * m + b] = acc[f];
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum_to_lane0(T v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
-
-// One wave per occupied cell: corner sums  csum[o][A][f] = sum_{B in cell} N_A(xi_B) kappa_B mu_B,f
-// with mu = lam (FROM_U = false) or mu = B u restricted to the cell, Dirichlet-masked (FROM_U = true).
-template <typename T, int P, bool FROM_U>
+// Corner sums  csum[o][A][f] = sum_{B in cell} N_A(xi_B) kappa_B mu_B,f  with mu = lam (FROM_U =
+// false) or mu = B u restricted to the cell, Dirichlet-masked (FROM_U = true).  LPC lanes per
+// occupied cell (64 / LPC cells per wavefront): lane r takes the cell's points r, r + LPC, ...
+// in sorted order, then an xor butterfly over the LPC lanes gives every lane the sums and lane
+// r stores the entries e = r, r + LPC, ... (fixed order: deterministic).
+template <typename T, int P, bool FROM_U, int LPC>
 __global__ __launch_bounds__(256) void dlm_cell_reduce(Geo g, int64_t m, int64_t n_occ,
                                                        const int32_t *__restrict__ occ_cell,
                                                        const int32_t *__restrict__ occ_start,
@@ -363,9 +359,10 @@ __global__ __launch_bounds__(256) void dlm_cell_reduce(Geo g, int64_t m, int64_t
                                                        T *__restrict__ csum)
 {
     constexpr int Q = P + 1, NEN = Q * Q * Q;
-    const int64_t o = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (o >= n_occ) return;   // whole wave leaves together
+    static_assert(LPC == 8 || LPC == 64, "lanes per cell");
+    const int64_t o = ((int64_t)blockIdx.x * 256 + threadIdx.x) / LPC;
+    const int lane = threadIdx.x % LPC;
+    if (o >= n_occ) return;   // the LPC lanes of a cell leave together
     const int32_t c = occ_cell[o];
     const int cx = c % g.n[0], cy = (c / g.n[0]) % g.n[1], cz = c / (g.n[0] * g.n[1]);
     T un[FROM_U ? 3 : 1][FROM_U ? NEN : 1];
@@ -389,7 +386,7 @@ __global__ __launch_bounds__(256) void dlm_cell_reduce(Geo g, int64_t m, int64_t
 #pragma unroll
         for (int f = 0; f < 3; ++f) acc[A][f] = T(0);
     const int32_t j0 = occ_start[o], j1 = occ_start[o + 1];
-    for (int32_t j = j0 + lane; j < j1; j += 64) {
+    for (int32_t j = j0 + lane; j < j1; j += LPC) {
         const int32_t b = perm[j];
         T Nx[Q], Ny[Q], Nz[Q];
         lagrange<T, P>(xi[b], Nx);
@@ -422,8 +419,10 @@ __global__ __launch_bounds__(256) void dlm_cell_reduce(Geo g, int64_t m, int64_t
     for (int A = 0; A < NEN; ++A)
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            const T v = wave_sum_to_lane0(acc[A][f]);
-            if (lane == 0) csum[(o * NEN + A) * 3 + f] = v;
+            T v = acc[A][f];
+#pragma unroll
+            for (int off = 1; off < LPC; off <<= 1) v += __shfl_xor(v, off, 64);
+            if ((A * 3 + f) % LPC == lane) csum[(o * NEN + A) * 3 + f] = v;
         }
 }
 
@@ -487,16 +486,25 @@ __global__ __launch_bounds__(64) void dlm_gram_kernel(int64_t m, const int32_t *
 }
 
 // y[3][N] += corner sums of the occupied neighbour cells (standalone B^T)
+// y += (B^T kappa lam) at the nodes of occupied cells.  One lane per (occupied cell, corner):
+// the lane whose cell is the node's first occupied cell in the fixed loop order below sums the
+// corner sums of every occupied cell holding the node, in that order, and writes the node once
+// (no atomics, deterministic; nodes away from the solid are not visited)
 template <typename T, int P>
-__global__ __launch_bounds__(256) void dlm_node_gather(Geo g, const T *__restrict__ csum,
+__global__ __launch_bounds__(256) void dlm_node_gather(Geo g, int64_t n_occ, const int32_t *__restrict__ occ_cell,
+                                                       const T *__restrict__ csum,
                                                        const int32_t *__restrict__ occ_index,
                                                        T *__restrict__ y)
 {
-    constexpr int NEN = (P + 1) * (P + 1) * (P + 1);
-    const int64_t node = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (node >= g.N) return;
-    const int gv[3] = {(int)(node % g.nn[0]), (int)((node / g.nn[0]) % g.nn[1]),
-                       (int)(node / ((int64_t)g.nn[0] * g.nn[1]))};
+    constexpr int Q = P + 1, NEN = Q * Q * Q;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_occ * NEN) return;
+    const int64_t o = t / NEN;
+    const int corner = (int)(t - o * NEN);
+    const int32_t c0 = occ_cell[o];
+    const int gv[3] = {P * (c0 % g.n[0]) + corner % Q, P * ((c0 / g.n[0]) % g.n[1]) + (corner / Q) % Q,
+                       P * (c0 / (g.n[0] * g.n[1])) + corner / (Q * Q)};
+    const int64_t node = gv[0] + (int64_t)g.nn[0] * (gv[1] + (int64_t)g.nn[1] * gv[2]);
     int cs[3][2], as[3][2], nc[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -506,23 +514,22 @@ __global__ __launch_bounds__(256) void dlm_node_gather(Geo g, const T *__restric
         if (c < g.n[d]) { cs[d][nc[d]] = c; as[d][nc[d]++] = gv[d] - P * c; }
     }
     T acc[3] = {T(0), T(0), T(0)};
-    bool any = false;
+    bool first = true;
     for (int iz = 0; iz < nc[2]; ++iz)
         for (int iy = 0; iy < nc[1]; ++iy)
             for (int ix = 0; ix < nc[0]; ++ix) {
                 const int64_t c = cs[0][ix] + (int64_t)g.n[0] * (cs[1][iy] + (int64_t)g.n[1] * cs[2][iz]);
                 const int32_t ko = occ_index[c];
                 if (ko >= 0) {
-                    const int A = as[0][ix] + (P + 1) * (as[1][iy] + (P + 1) * as[2][iz]);
+                    if (first && ko != o) return;   // another lane owns this node
+                    first = false;
+                    const int A = as[0][ix] + Q * (as[1][iy] + Q * as[2][iz]);
 #pragma unroll
                     for (int f = 0; f < 3; ++f) acc[f] += csum[((int64_t)ko * NEN + A) * 3 + f];
-                    any = true;
                 }
             }
-    if (any) {
 #pragma unroll
-        for (int f = 0; f < 3; ++f) y[f * g.N + node] += acc[f];
-    }
+    for (int f = 0; f < 3; ++f) y[f * g.N + node] += acc[f];
 }
 
 inline unsigned nblk(int64_t n, int per = 256) { return (unsigned)((n + per - 1) / per); }
@@ -693,21 +700,24 @@ static int launch_reduce_t(const Geo &g, bool from_u, int64_t m, int64_t n_occ, 
                            const T *src, const uint32_t *mask, T *csum, hipStream_t st)
 {
     if (n_occ == 0) return FSI_OK;
-    const unsigned blocks = (unsigned)((n_occ + 3) / 4);
     ProfileScope prof("dlm_cell_reduce", st);
     if (g.p == 1) {
+        // Q1: 8 lanes per cell (24 corner sums, ~tens of points per cell)
+        const unsigned blocks = (unsigned)((n_occ + 31) / 32);
         if (from_u)
-            hipLaunchKernelGGL((dlm_cell_reduce<T, 1, true>), dim3(blocks), dim3(256), 0, st, g, m, n_occ,
+            hipLaunchKernelGGL((dlm_cell_reduce<T, 1, true, 8>), dim3(blocks), dim3(256), 0, st, g, m, n_occ,
                                occ_cell, occ_start, perm, xi, kappa, src, mask, csum);
         else
-            hipLaunchKernelGGL((dlm_cell_reduce<T, 1, false>), dim3(blocks), dim3(256), 0, st, g, m, n_occ,
+            hipLaunchKernelGGL((dlm_cell_reduce<T, 1, false, 8>), dim3(blocks), dim3(256), 0, st, g, m, n_occ,
                                occ_cell, occ_start, perm, xi, kappa, src, mask, csum);
     } else {
+        // Q2: a wavefront per cell (81 corner sums)
+        const unsigned blocks = (unsigned)((n_occ + 3) / 4);
         if (from_u)
-            hipLaunchKernelGGL((dlm_cell_reduce<T, 2, true>), dim3(blocks), dim3(256), 0, st, g, m, n_occ,
+            hipLaunchKernelGGL((dlm_cell_reduce<T, 2, true, 64>), dim3(blocks), dim3(256), 0, st, g, m, n_occ,
                                occ_cell, occ_start, perm, xi, kappa, src, mask, csum);
         else
-            hipLaunchKernelGGL((dlm_cell_reduce<T, 2, false>), dim3(blocks), dim3(256), 0, st, g, m, n_occ,
+            hipLaunchKernelGGL((dlm_cell_reduce<T, 2, false, 64>), dim3(blocks), dim3(256), 0, st, g, m, n_occ,
                                occ_cell, occ_start, perm, xi, kappa, src, mask, csum);
     }
     FSI_LAUNCH_CHECK();
@@ -750,22 +760,24 @@ int launch_dlm_gram(const Geo &g, fsi_dtype dt, int64_t m, int64_t n_occ, const 
     return FSI_OK;
 }
 
-int launch_dlm_node_gather(const Geo &g, fsi_dtype dt, const void *csum, const int32_t *occ_index,
-                           void *y, hipStream_t st)
+int launch_dlm_node_gather(const Geo &g, fsi_dtype dt, int64_t n_occ, const int32_t *occ_cell, const void *csum,
+                           const int32_t *occ_index, void *y, hipStream_t st)
 {
+    if (n_occ == 0) return FSI_OK;
+    const unsigned blocks = nblk(n_occ * (g.p == 1 ? 8 : 27));
     if (dt == FSI_F64) {
         if (g.p == 1)
-            hipLaunchKernelGGL((dlm_node_gather<double, 1>), dim3(nblk(g.N)), dim3(256), 0, st, g,
+            hipLaunchKernelGGL((dlm_node_gather<double, 1>), dim3(blocks), dim3(256), 0, st, g, n_occ, occ_cell,
                                (const double *)csum, occ_index, (double *)y);
         else
-            hipLaunchKernelGGL((dlm_node_gather<double, 2>), dim3(nblk(g.N)), dim3(256), 0, st, g,
+            hipLaunchKernelGGL((dlm_node_gather<double, 2>), dim3(blocks), dim3(256), 0, st, g, n_occ, occ_cell,
                                (const double *)csum, occ_index, (double *)y);
     } else {
         if (g.p == 1)
-            hipLaunchKernelGGL((dlm_node_gather<float, 1>), dim3(nblk(g.N)), dim3(256), 0, st, g,
+            hipLaunchKernelGGL((dlm_node_gather<float, 1>), dim3(blocks), dim3(256), 0, st, g, n_occ, occ_cell,
                                (const float *)csum, occ_index, (float *)y);
         else
-            hipLaunchKernelGGL((dlm_node_gather<float, 2>), dim3(nblk(g.N)), dim3(256), 0, st, g,
+            hipLaunchKernelGGL((dlm_node_gather<float, 2>), dim3(blocks), dim3(256), 0, st, g, n_occ, occ_cell,
                                (const float *)csum, occ_index, (float *)y);
     }
     FSI_LAUNCH_CHECK();

@@ -18,7 +18,7 @@ int launch_dlm_cell_reduce(const Geo &g, fsi_dtype dt, bool from_u, int64_t m, i
                            void *csum, hipStream_t st);
 int launch_dlm_gram(const Geo &g, fsi_dtype dt, int64_t m, int64_t n_occ, const int32_t *occ_start,
                     const int32_t *perm, const void *xi, const void *kappa, void *gram, hipStream_t st);
-int launch_dlm_node_gather(const Geo &g, fsi_dtype dt, const void *csum, const int32_t *occ_index,
-                           void *y, hipStream_t st);
+int launch_dlm_node_gather(const Geo &g, fsi_dtype dt, int64_t n_occ, const int32_t *occ_cell, const void *csum,
+                           const int32_t *occ_index, void *y, hipStream_t st);
 
 }  // namespace fsi
