@@ -13,7 +13,8 @@ here is the block factorisation's upper factor
 or its block diagonal, with
 
 * F_hat: the nodal 3x3 velocity blocks of J (the velocity part of the nodal
-  4x4 diagonal blocks), inverted per node;
+  4x4 diagonal blocks), inverted per node, optionally followed by k
+  minimal-residual steps on F preconditioned by them (velocity_solve);
 * S_hat ~ S = C - D F^{-1} G: because D = -G^T for the Galerkin terms, C is
   tau_m times a pressure Laplacian (PSPG) and F ~ c_m M + the DLM block, S acts
   like the variable-coefficient Laplacian  -div(alpha grad p)  with
@@ -299,9 +300,33 @@ def velocity_inverses(blocks):
     return np.linalg.inv(np.asarray(blocks, dtype=np.float64)[:, :3, :3])
 
 
-def precond_apply(levels, finv, v, mode="diag", jac=None):
+def velocity_solve(finv, t, vel_steps=0, jac=None):
+    """F_hat^{-1} t for the velocity block ([3][N]).  vel_steps = 0: the nodal block inverses;
+    k > 0: k minimal-residual steps on F (the velocity rows of J [u; 0]) preconditioned by them:
+    r = t, z = 0; each step p = blocks^{-1} r, q = F p, alpha = (q.r)/(q.q), z += alpha p,
+    r -= alpha q."""
+    N = finv.shape[0]
+    t = np.asarray(t, dtype=np.float64).reshape(3, N)
+    if vel_steps == 0:
+        return np.einsum("nij,jn->in", finv, t)
+    z = np.zeros((3, N))
+    r = t.copy()
+    for _ in range(vel_steps):
+        p = np.einsum("nij,jn->in", finv, r)
+        xp = np.zeros((4, N))
+        xp[:3] = p
+        q = np.asarray(jac(xp)).reshape(4, N)[:3]
+        qq = float(np.sum(q * q))
+        alpha = float(np.sum(q * r)) / qq if qq > 0.0 else 0.0
+        z += alpha * p
+        r -= alpha * q
+    return z
+
+
+def precond_apply(levels, finv, v, mode="diag", jac=None, vel_steps=0):
     """z = P^{-1} v ([4][N]); mode 'diag' (block diagonal) or 'tri' (upper block triangular, needs
-    jac(x) = J x for the velocity rows of J [0; z_p])."""
+    jac(x) = J x for the velocity rows of J [0; z_p]); vel_steps: minimal-residual steps of the
+    velocity solve (velocity_solve, also needs jac)."""
     N = finv.shape[0]
     v = np.asarray(v, dtype=np.float64).reshape(4, N)
     z = np.zeros((4, N))
@@ -313,5 +338,5 @@ def precond_apply(levels, finv, v, mode="diag", jac=None):
         t -= np.asarray(jac(xp)).reshape(4, N)[:3]
     elif mode != "diag":
         raise ValueError(mode)
-    z[:3] = np.einsum("nij,jn->in", finv, t)
+    z[:3] = velocity_solve(finv, t, vel_steps, jac)
     return z
