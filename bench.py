@@ -184,14 +184,16 @@ def time_applies(fsi, torch, case, steps, warmup, profile):
     return ms, wall / steps * 1e3, kern
 
 
-PROBE_MODES = ["plain_f64", "plain_mixed", "extrap_mixed", "plain_f64_st", "plain_mixed_st", "extrap_mixed_st"]
+PROBE_MODES = ["plain_f64", "plain_mixed", "extrap_mixed", "plain_f64_st", "plain_mixed_st", "extrap_mixed_st",
+               "plain_f64_st2", "plain_mixed_st2", "extrap_mixed_st2"]
 
 
 def newton_step_probe(warm_steps=60, measure_steps=3, modes=None, integrator="be", rho_inf=0.5):
     """Short Newton-step comparison on the 64^3 rotating-plates channel: after a few plain steps,
     the next steps are re-solved from the same state with plain FP64, mixed precision, and mixed
     precision + extrapolated warm start, each with the block-Jacobi and (suffix _st) the
-    Schur-complement block-triangular preconditioner; all stop at the same absolute residual."""
+    Schur-complement block-triangular preconditioner, the latter also with two minimal-residual
+    steps on its velocity block (_st2); all stop at the same absolute residual."""
     import torch
 
     import fsi_workloads as W
@@ -220,6 +222,11 @@ def newton_step_probe(warm_steps=60, measure_steps=3, modes=None, integrator="be
         out["speedup_extrap_mixed_st_vs_plain_f64"] = round(out["plain_f64_ms"] / out["extrap_mixed_st_ms"], 3)
     if "plain_f64_st_ms" in out and "extrap_mixed_st_ms" in out:
         out["speedup_extrap_mixed_st_vs_plain_f64_st"] = round(out["plain_f64_st_ms"] / out["extrap_mixed_st_ms"], 3)
+    if "plain_f64_ms" in out and "extrap_mixed_st2_ms" in out:
+        # with two minimal-residual velocity steps in the Schur preconditioner (the fastest form)
+        out["speedup_extrap_mixed_st2_vs_plain_f64"] = round(out["plain_f64_ms"] / out["extrap_mixed_st2_ms"], 3)
+    if "plain_f64_st2_ms" in out and "extrap_mixed_st2_ms" in out:
+        out["speedup_extrap_mixed_st2_vs_plain_f64_st2"] = round(out["plain_f64_st2_ms"] / out["extrap_mixed_st2_ms"], 3)
     return out
 
 
@@ -269,6 +276,8 @@ def main(argv=None):
     ap.add_argument("--exp-precond", default="bjacobi", choices=["bjacobi", "schur_diag", "schur_tri"],
                     help="preconditioner of the c3 solve and of the warmstart run's Newton steps")
     ap.add_argument("--exp-restart", type=int, default=50, help="c3 FGMRES restart length")
+    ap.add_argument("--exp-vel-steps", type=int, default=0,
+                    help="c3: minimal-residual steps on the velocity block of the Schur preconditioner")
     ap.add_argument("--exp-integrator", default="be", choices=["be", "genalpha"],
                     help="time integrator of the probe / warmstart / c5 runs")
     ap.add_argument("--exp-rho-inf", type=float, default=0.5, help="generalized-alpha rho_inf")
@@ -399,7 +408,8 @@ def run_experiment(args):
     if args.experiment == "c3":
         print(json.dumps({"experiment": "solve_c3",
                           **ex.solve_c3(max_iters=args.exp_steps, modes=tuple(modes or ("mixed", "f64")),
-                                        precond=args.exp_precond, restart=args.exp_restart)}))
+                                        precond=args.exp_precond, restart=args.exp_restart,
+                                        vel_steps=args.exp_vel_steps)}))
         return 0
     if args.experiment == "probe":
         print(json.dumps({"experiment": "newton_probe",

@@ -294,6 +294,12 @@ int fsi_bjacobi_apply(const fsi_grid *grid, fsi_dtype dtype, const void *pinv, c
  *   FSI_PC_SCHUR_TRI:  z_p as above, z_u = F_hat^{-1} (v_u - [J (0, z_p)]_u)
  *                      (the upper factor [[F_hat, G], [0, S_hat]]; one extra
  *                      Jacobian apply per preconditioner apply).
+ *   vel_steps = k > 0: F_hat^{-1} t becomes k minimal-residual steps on F (the
+ *                      velocity rows of J [u; 0]) preconditioned by the nodal
+ *                      blocks: r = t, z = 0; p = blocks^{-1} r, q = F p,
+ *                      alpha = (q.r)/(q.q), z += alpha p, r -= alpha q (one
+ *                      Jacobian apply per step; the step lengths stay on the
+ *                      device).  0 <= k <= 16.
  * fsi_schur_size: bytes of the preconditioner object for a grid (0 if the
  *   lattice cannot be coarsened to at most 1000 nodes).  The object holds the
  *   coefficients, the inverses and the V-cycle's vectors: an apply writes into
@@ -303,8 +309,9 @@ int fsi_bjacobi_apply(const fsi_grid *grid, fsi_dtype dtype, const void *pinv, c
  *   blocks of fsi_bjacobi_setup for the same problem.  SYNCS (the coarsest
  *   operator is factorised on the host).
  * fsi_schur_apply: z = P^{-1} v ([4][N] device, precision J->dtype, not
- *   overlapping); J is only applied in FSI_PC_SCHUR_TRI, with ws of at least
- *   fsi_jacobian_workspace(J) bytes (ws may be NULL for FSI_PC_SCHUR_DIAG).
+ *   overlapping); J is only applied in FSI_PC_SCHUR_TRI or with vel_steps > 0,
+ *   with ws of at least fsi_jacobian_workspace(J) bytes (ws may be NULL
+ *   otherwise).
  * fsi_schur_info: levels of the hierarchy, their lattice-cell counts
  *   (ncell[3 l + d], up to 16 levels) and the byte offsets of each level's
  *   FP64 alpha array inside the object (for inspection).
@@ -314,8 +321,8 @@ size_t fsi_schur_size(const fsi_grid *grid);
 int fsi_schur_info(const fsi_grid *grid, int32_t *n_levels, int32_t *ncell, int64_t *alpha_offset);
 int fsi_schur_setup(const fsi_problem *P64, const double *blocks, void *pc, size_t pc_bytes,
                     void *stream);
-int fsi_schur_apply(const fsi_problem *J, int32_t mode, void *pc, const void *v, void *z, void *ws,
-                    size_t ws_bytes, void *stream);
+int fsi_schur_apply(const fsi_problem *J, int32_t mode, int32_t vel_steps, void *pc, const void *v,
+                    void *z, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * fsi_fgmres_solve - solve J x = b with restarted flexible GMRES, right
@@ -352,6 +359,7 @@ typedef struct {
     fsi_dtype inner;          /* FSI_F32 (mixed precision) or FSI_F64 */
     double inner_reduction;   /* FP32 cycles stop at this relative reduction (e.g. 1e-5) */
     int32_t precond;          /* fsi_precond (0: block-Jacobi) */
+    int32_t vel_steps;        /* Schur forms: minimal-residual steps on the velocity block */
 } fsi_solve_opts;
 
 typedef struct {
@@ -388,6 +396,7 @@ typedef struct {
     fsi_dtype inner;          /* inner precision of the Krylov cycles */
     double inner_reduction;
     int32_t precond;          /* fsi_precond: block-Jacobi (0) or a Schur form, rebuilt per iteration */
+    int32_t vel_steps;        /* Schur forms: minimal-residual steps on the velocity block */
 } fsi_newton_opts;
 
 typedef struct {

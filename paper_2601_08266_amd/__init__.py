@@ -399,25 +399,27 @@ def schur_setup(problem: Problem, blocks: torch.Tensor, pc: Optional[torch.Tenso
 
 
 def schur_apply(problem: Problem, precond, pc: torch.Tensor, v: torch.Tensor,
-                z: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None):
+                z: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None,
+                vel_steps: int = 0):
     """z = P^{-1} v (fsi_schur_apply) in the problem's precision."""
     _need(v, "v", problem.dtype, 4 * problem.N)
     if z is None:
         z = torch.empty_like(v)
     ws = _workspace(problem.workspace_bytes(), v.device, ws)
     L.check("fsi_schur_apply", L.lib().fsi_schur_apply(
-        ctypes.byref(problem.struct), _precond_code(precond), _ptr(pc), _ptr(v), _ptr(z), _ptr(ws),
+        ctypes.byref(problem.struct), _precond_code(precond), int(vel_steps), _ptr(pc), _ptr(v), _ptr(z), _ptr(ws),
         ws.numel(), _stream(stream)))
     return z
 
 
 def solve_opts(restart=50, max_iters=2000, rtol=1e-10, inner=torch.float32,
-               inner_reduction=1e-5, precond="bjacobi") -> FsiSolveOpts:
+               inner_reduction=1e-5, precond="bjacobi", vel_steps=0) -> FsiSolveOpts:
     o = FsiSolveOpts()
     o.restart, o.max_iters, o.rtol = int(restart), int(max_iters), float(rtol)
     o.inner = dtype_code(inner)
     o.inner_reduction = float(inner_reduction)
     o.precond = _precond_code(precond)
+    o.vel_steps = int(vel_steps)
     return o
 
 
@@ -442,13 +444,14 @@ def fgmres_solve(J64: Problem, b: torch.Tensor, x: torch.Tensor, opts: FsiSolveO
 
 
 def newton_opts(tol_abs, max_newton=20, eta=1e-3, restart=50, max_krylov=2000,
-                inner=torch.float32, inner_reduction=1e-5, precond="bjacobi") -> FsiNewtonOpts:
+                inner=torch.float32, inner_reduction=1e-5, precond="bjacobi", vel_steps=0) -> FsiNewtonOpts:
     o = FsiNewtonOpts()
     o.max_newton, o.tol_abs, o.eta = int(max_newton), float(tol_abs), float(eta)
     o.restart, o.max_krylov = int(restart), int(max_krylov)
     o.inner = dtype_code(inner)
     o.inner_reduction = float(inner_reduction)
     o.precond = _precond_code(precond)
+    o.vel_steps = int(vel_steps)
     return o
 
 

@@ -48,7 +48,8 @@ class FsiProblem(ctypes.Structure):
 class FsiSolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_iters", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("inner", ctypes.c_int),
-                ("inner_reduction", ctypes.c_double), ("precond", ctypes.c_int32)]
+                ("inner_reduction", ctypes.c_double), ("precond", ctypes.c_int32),
+                ("vel_steps", ctypes.c_int32)]
 
 
 class FsiSolveStats(ctypes.Structure):
@@ -61,7 +62,8 @@ class FsiNewtonOpts(ctypes.Structure):
     _fields_ = [("max_newton", ctypes.c_int32), ("tol_abs", ctypes.c_double),
                 ("eta", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_krylov", ctypes.c_int32), ("inner", ctypes.c_int),
-                ("inner_reduction", ctypes.c_double), ("precond", ctypes.c_int32)]
+                ("inner_reduction", ctypes.c_double), ("precond", ctypes.c_int32),
+                ("vel_steps", ctypes.c_int32)]
 
 
 class FsiNewtonStats(ctypes.Structure):
@@ -124,7 +126,8 @@ SIGNATURES = {
     "fsi_schur_info": (ctypes.c_int, [ctypes.POINTER(FsiGrid), ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(I64)]),
     "fsi_schur_setup": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, SZ, P]),
-    "fsi_schur_apply": (ctypes.c_int, [ctypes.POINTER(FsiProblem), ctypes.c_int32, P, P, P, P, SZ, P]),
+    "fsi_schur_apply": (ctypes.c_int, [ctypes.POINTER(FsiProblem), ctypes.c_int32, ctypes.c_int32, P, P, P, P,
+                                       SZ, P]),
     "fsi_fgmres_workspace": (SZ, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiProblem),
                                   ctypes.POINTER(FsiSolveOpts)]),
     "fsi_fgmres_solve": (ctypes.c_int, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiProblem), P,

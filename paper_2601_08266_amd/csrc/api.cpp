@@ -469,6 +469,7 @@ static int check_solve(const fsi_problem *J64, const fsi_problem *J32, const fsi
     FSI_CHECK_ARG(o->precond == FSI_PC_BJACOBI || o->precond == FSI_PC_SCHUR_DIAG ||
                       o->precond == FSI_PC_SCHUR_TRI,
                   "unknown preconditioner %d", (int)o->precond);
+    FSI_CHECK_ARG(o->vel_steps >= 0 && o->vel_steps <= 16, "vel_steps must be in [0, 16]");
     if (o->inner == FSI_F32) {
         FSI_CHECK_ARG(J32 != nullptr, "inner FP32 needs the FP32 problem");
         rc = check_problem(J32);
@@ -535,7 +536,7 @@ FSI_API int fsi_fgmres_solve(const fsi_problem *J64, const fsi_problem *J32, con
         void *obj = const_cast<void *>(pinv);
         const int mode = o->precond == FSI_PC_SCHUR_DIAG ? 1 : 2;
         pc.apply = [&, obj, mode](const double *v, void *z, void *w, hipStream_t s) {
-            return schur_apply(g, o->inner, true, mode, obj, v, z, Jin, w, s);
+            return schur_apply(g, o->inner, true, mode, o->vel_steps, obj, v, z, Jin, w, s);
         };
     } else if (pinv != nullptr) {
         pc.apply = [&](const double *v, void *z, void *, hipStream_t s) {
@@ -599,8 +600,8 @@ FSI_API int fsi_schur_setup(const fsi_problem *p, const double *blocks, void *pc
                        as_stream(stream));
 }
 
-FSI_API int fsi_schur_apply(const fsi_problem *J, int32_t mode, void *pc, const void *v, void *z, void *ws,
-                            size_t ws_bytes, void *stream)
+FSI_API int fsi_schur_apply(const fsi_problem *J, int32_t mode, int32_t vel_steps, void *pc, const void *v,
+                            void *z, void *ws, size_t ws_bytes, void *stream)
 {
     clear_error();
     int rc = check_problem(J);
@@ -612,7 +613,7 @@ FSI_API int fsi_schur_apply(const fsi_problem *J, int32_t mode, void *pc, const 
     rc = sc_plan(g, plan);
     if (rc) return rc;
     const size_t jw = jac_ws(J);
-    if (mode == FSI_PC_SCHUR_TRI && (ws == nullptr || ws_bytes < jw)) {
+    if ((mode == FSI_PC_SCHUR_TRI || vel_steps > 0) && (ws == nullptr || ws_bytes < jw)) {
         set_error("workspace of %zu bytes needed (got %zu)", jw, ws_bytes);
         return FSI_ERR_WORKSPACE;
     }
@@ -621,7 +622,7 @@ FSI_API int fsi_schur_apply(const fsi_problem *J, int32_t mode, void *pc, const 
         return launch_vms_apply(g, J->prm, J->dtype, J->a, J->s, J->dir_mask, xx, yy,
                                 J->n_occ > 0 ? &dv : nullptr, w, jw, s);
     }};
-    return schur_apply(g, J->dtype, false, mode == FSI_PC_SCHUR_DIAG ? 1 : 2, pc, v, z, &c, ws,
+    return schur_apply(g, J->dtype, false, mode == FSI_PC_SCHUR_DIAG ? 1 : 2, vel_steps, pc, v, z, &c, ws,
                        as_stream(stream));
 }
 
@@ -640,6 +641,7 @@ static int check_newton(const fsi_problem *P64, const fsi_problem *P32, const fs
     FSI_CHECK_ARG(o->precond == FSI_PC_BJACOBI || o->precond == FSI_PC_SCHUR_DIAG ||
                       o->precond == FSI_PC_SCHUR_TRI,
                   "unknown preconditioner %d", (int)o->precond);
+    FSI_CHECK_ARG(o->vel_steps >= 0 && o->vel_steps <= 16, "vel_steps must be in [0, 16]");
     if (o->precond != FSI_PC_BJACOBI) {
         ScPlan sp;
         rc = sc_plan(make_geo(P64->grid), sp);

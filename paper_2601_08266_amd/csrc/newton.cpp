@@ -169,7 +169,7 @@ int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, c
         Precond pc;
         if (schur)
             pc.apply = [&](const double *v, void *z, void *w, hipStream_t s2) {
-                return schur_apply(g, o.inner, true, mode, pcobj, v, z, Jin, w, s2);
+                return schur_apply(g, o.inner, true, mode, o.vel_steps, pcobj, v, z, Jin, w, s2);
             };
         else
             pc.apply = [&](const double *v, void *z, void *, hipStream_t s2) {
@@ -177,6 +177,7 @@ int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, c
                 return launch_bjacobi_apply(g.N, FSI_F64, pinv64, v, z, s2);
             };
         so.precond = o.precond;
+        so.vel_steps = o.vel_steps;
         fsi_solve_stats ks{};
         rc = fgmres_solve(g, c64, o.inner == FSI_F32 ? &c32 : nullptr, &pc, R, dx, so, &ks, kws, jws, st);
         S.krylov_iters += ks.iters;

@@ -24,9 +24,12 @@
 //   sc_vel_inverse 3x3 velocity block inverses (FP64, FP32 copy)
 //   sc_first/sc_sweep/sc_restrict/sc_prolong/sc_coarse: the V-cycle (sc_sweep: Jacobi sweep or
 //                  residual with the 27-point variable-coefficient stencil)
-//   sc_vel_apply   z_u = F_hat^{-1} (v_u - [J (0, z_p)]_u)
+//   sc_vel_apply   z_u = F_hat^{-1} (v_u - [J (0, z_p)]_u) with the nodal block inverses, or
+//   sc_vel_resid, sc_mr_dots, sc_mr_alpha, sc_mr_update: minimal-residual steps on F (the velocity
+//                  rows of J [u; 0]) preconditioned by them; the step length stays on the device
 // Every vector of the V-cycle keeps zeros at Dirichlet nodes, so the 27-point stencil
 // needs no mask on its neighbours.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -310,6 +313,84 @@ __global__ __launch_bounds__(256) void sc_vel_apply(int64_t N, const T *__restri
     }
 }
 
+// ---- minimal-residual steps on the velocity block ----
+constexpr int MR_NB = 512;   // blocks of the dot-product pass
+
+// r = v_u - yt_u (yt = J (0, z_p) in the block-triangular form, or nullptr)
+template <typename T, typename TV>
+__global__ __launch_bounds__(256) void sc_vel_resid(int64_t n3, const TV *__restrict__ v, const T *__restrict__ yt,
+                                                    T *__restrict__ r)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (int64_t)gridDim.x * 256) {
+        T t = (T)v[i];
+        if (yt != nullptr) t -= yt[i];
+        r[i] = t;
+    }
+}
+
+// per-block partial sums of q.r and q.q (FP64 accumulation, fixed tree order)
+template <typename T>
+__global__ __launch_bounds__(256) void sc_mr_dots(int64_t n3, const T *__restrict__ q, const T *__restrict__ r,
+                                                  double *__restrict__ part)
+{
+    __shared__ double sh[2][256];
+    double qr = 0.0, qq = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (int64_t)gridDim.x * 256) {
+        const double a = (double)q[i];
+        qr += a * (double)r[i];
+        qq += a * a;
+    }
+    sh[0][threadIdx.x] = qr;
+    sh[1][threadIdx.x] = qq;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sh[0][0];
+        part[2 * blockIdx.x + 1] = sh[1][0];
+    }
+}
+
+// alpha = (q.r) / (q.q) from the partials (0 if q = 0), kept on the device
+__global__ __launch_bounds__(256) void sc_mr_alpha(int nb, const double *__restrict__ part, double *__restrict__ alpha)
+{
+    __shared__ double sh[2][256];
+    double qr = 0.0, qq = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        qr += part[2 * b];
+        qq += part[2 * b + 1];
+    }
+    sh[0][threadIdx.x] = qr;
+    sh[1][threadIdx.x] = qq;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) alpha[0] = sh[1][0] > 0.0 ? sh[0][0] / sh[1][0] : 0.0;
+}
+
+// z = (first ? 0 : z) + alpha p;  r -= alpha q
+template <typename T>
+__global__ __launch_bounds__(256) void sc_mr_update(int64_t n3, const double *__restrict__ alpha,
+                                                    const T *__restrict__ p, const T *__restrict__ q,
+                                                    T *__restrict__ z, T *__restrict__ r, int first)
+{
+    const T a = (T)alpha[0];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (int64_t)gridDim.x * 256) {
+        z[i] = (first ? T(0) : z[i]) + a * p[i];
+        r[i] -= a * q[i];
+    }
+}
+
 // ---- setup kernels (FP64) ----
 
 // node weight beta_A; the DLM row sum of node A is the sum over the occupied grid cells that
@@ -581,9 +662,10 @@ int vcycle(const ScPlan &p, char *base, const TV *vp, TZ *zp, hipStream_t st)
 }
 
 template <typename T, typename TV, typename TZ>
-int apply_t(const Geo &g, const ScPlan &p, int mode, char *base, const TV *v, TZ *z, const JacobianCall *J,
-            void *jws, hipStream_t st)
+int apply_t(const Geo &g, const ScPlan &p, int mode, int vel_steps, char *base, const TV *v, TZ *z,
+            const JacobianCall *J, void *jws, hipStream_t st)
 {
+    static_assert(sizeof(T) == sizeof(TZ), "the preconditioned vector is in the compute precision");
     const int64_t N = g.N;
     int rc = vcycle<T, TV, TZ>(p, base, v + 3 * N, z + 3 * N, st);
     if (rc) return rc;
@@ -596,8 +678,37 @@ int apply_t(const Geo &g, const ScPlan &p, int mode, char *base, const TV *v, TZ
         yt = y;
     }
     const T *finv = reinterpret_cast<const T *>(base + (sizeof(T) == 8 ? p.finv64 : p.finv32));
-    hipLaunchKernelGGL((sc_vel_apply<T, TV, TZ>), dim3(blocks_for(N)), dim3(256), 0, st, N, finv, v, yt, z);
+    if (vel_steps == 0) {
+        hipLaunchKernelGGL((sc_vel_apply<T, TV, TZ>), dim3(blocks_for(N)), dim3(256), 0, st, N, finv, v, yt, z);
+        FSI_LAUNCH_CHECK();
+        return FSI_OK;
+    }
+    // minimal-residual steps on F = velocity rows of J [u; 0], preconditioned by the block inverses
+    T *r = reinterpret_cast<T *>(base + p.mr_r);
+    T *xin = reinterpret_cast<T *>(base + p.mr_x);
+    T *q = reinterpret_cast<T *>(base + p.mr_q);
+    double *part = reinterpret_cast<double *>(base + p.mr_part);
+    double *alpha = part + 2 * MR_NB;
+    TZ *zu = z;   // the velocity part of z accumulates the steps (TZ = T)
+    const int64_t n3 = 3 * N;
+    const unsigned ub = (unsigned)std::min<int64_t>(blocks_for(n3), 4096);
+    hipLaunchKernelGGL((sc_vel_resid<T, TV>), dim3(ub), dim3(256), 0, st, n3, v, yt, r);
     FSI_LAUNCH_CHECK();
+    FSI_HIP(hipMemsetAsync(xin + n3, 0, (size_t)N * sizeof(T), st));
+    for (int it = 0; it < vel_steps; ++it) {
+        hipLaunchKernelGGL((sc_vel_apply<T, T, T>), dim3(blocks_for(N)), dim3(256), 0, st, N, finv, r, (const T *)nullptr,
+                           xin);
+        FSI_LAUNCH_CHECK();
+        rc = J->apply(xin, q, jws, st);
+        if (rc) return rc;
+        hipLaunchKernelGGL((sc_mr_dots<T>), dim3(MR_NB), dim3(256), 0, st, n3, q, r, part);
+        FSI_LAUNCH_CHECK();
+        hipLaunchKernelGGL(sc_mr_alpha, dim3(1), dim3(256), 0, st, MR_NB, part, alpha);
+        FSI_LAUNCH_CHECK();
+        hipLaunchKernelGGL((sc_mr_update<T>), dim3(ub), dim3(256), 0, st, n3, alpha, xin, q,
+                           reinterpret_cast<T *>(zu), r, it == 0 ? 1 : 0);
+        FSI_LAUNCH_CHECK();
+    }
     return FSI_OK;
 }
 
@@ -672,6 +783,10 @@ int sc_plan(const Geo &g, ScPlan &p)
     p.kinv64 = take((size_t)(nco * nco) * sizeof(double));
     p.kinv32 = take((size_t)(nco * nco) * sizeof(float));
     p.yt = take((size_t)4 * g.N * sizeof(double));
+    p.mr_r = take((size_t)3 * g.N * sizeof(double));
+    p.mr_x = take((size_t)4 * g.N * sizeof(double));
+    p.mr_q = take((size_t)4 * g.N * sizeof(double));
+    p.mr_part = take((size_t)(2 * MR_NB + 8) * sizeof(double));
     p.cnt = take(256);
     p.total = off;
     return FSI_OK;
@@ -747,7 +862,7 @@ int schur_setup(const Geo &g, const fsi_vms_params &prm, const double *a, const 
     return FSI_OK;
 }
 
-int schur_apply(const Geo &g, fsi_dtype inner, bool v_f64, int mode, void *pc, const void *v,
+int schur_apply(const Geo &g, fsi_dtype inner, bool v_f64, int mode, int vel_steps, void *pc, const void *v,
                 void *z, const JacobianCall *J, void *jws, hipStream_t st)
 {
     ProfileScope prof("schur_apply", st);
@@ -758,16 +873,21 @@ int schur_apply(const Geo &g, fsi_dtype inner, bool v_f64, int mode, void *pc, c
         set_error("unknown Schur preconditioner mode %d", mode);
         return FSI_ERR_ARG;
     }
-    if (mode == 2 && J == nullptr) {
-        set_error("the block-triangular form needs the Jacobian");
+    if ((mode == 2 || vel_steps > 0) && J == nullptr) {
+        set_error("the block-triangular form and the velocity steps need the Jacobian");
+        return FSI_ERR_ARG;
+    }
+    if (vel_steps < 0 || vel_steps > 16) {
+        set_error("velocity minimal-residual steps must be in [0, 16] (got %d)", vel_steps);
         return FSI_ERR_ARG;
     }
     char *base = reinterpret_cast<char *>(pc);
     if (inner == FSI_F64)
-        return apply_t<double, double, double>(g, p, mode, base, (const double *)v, (double *)z, J, jws, st);
+        return apply_t<double, double, double>(g, p, mode, vel_steps, base, (const double *)v, (double *)z, J, jws,
+                                               st);
     if (v_f64)
-        return apply_t<float, double, float>(g, p, mode, base, (const double *)v, (float *)z, J, jws, st);
-    return apply_t<float, float, float>(g, p, mode, base, (const float *)v, (float *)z, J, jws, st);
+        return apply_t<float, double, float>(g, p, mode, vel_steps, base, (const double *)v, (float *)z, J, jws, st);
+    return apply_t<float, float, float>(g, p, mode, vel_steps, base, (const float *)v, (float *)z, J, jws, st);
 }
 
 }  // namespace fsi

@@ -21,7 +21,7 @@ struct ScLevel {
 struct ScPlan {
     int L;
     ScLevel lv[SC_MAX_LEVELS];
-    size_t finv64, finv32, kinv64, kinv32, yt, cnt, total;
+    size_t finv64, finv32, kinv64, kinv32, yt, mr_r, mr_x, mr_q, mr_part, cnt, total;
 };
 
 // Levels and layout of the preconditioner object for a grid (a pure function of the grid).
@@ -34,9 +34,10 @@ int schur_setup(const Geo &g, const fsi_vms_params &prm, const double *a, const 
                 const double *blocks, void *pc, hipStream_t st);
 
 // z = P^{-1} v ([4][N]); mode 1: block diagonal, 2: upper block triangular (uses J, in the
-// precision `inner`, with workspace jws).  z is in the precision `inner`; v is FP64 when v_f64,
-// else in `inner`.
-int schur_apply(const Geo &g, fsi_dtype inner, bool v_f64, int mode, void *pc, const void *v,
+// precision `inner`, with workspace jws); vel_steps minimal-residual steps on the velocity block
+// (0: the nodal block inverses alone; > 0 uses J).  z is in the precision `inner`; v is FP64
+// when v_f64, else in `inner`.
+int schur_apply(const Geo &g, fsi_dtype inner, bool v_f64, int mode, int vel_steps, void *pc, const void *v,
                 void *z, const JacobianCall *J, void *jws, hipStream_t st);
 
 }  // namespace fsi

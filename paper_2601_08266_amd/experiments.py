@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import json
 import math
+import re
 import statistics
 import sys
 import time
@@ -32,13 +33,13 @@ def _log(msg):
 
 
 def mode_precond(mode):
-    """Preconditioner named by a mode's suffix: _st Schur block-triangular, _sd Schur block-diagonal,
-    none: the run's default."""
-    if mode.endswith("_st"):
-        return "schur_tri"
-    if mode.endswith("_sd"):
-        return "schur_diag"
-    return None
+    """(preconditioner, velocity steps) named by a mode's suffix: _st / _sd the Schur
+    block-triangular / block-diagonal form, followed by an optional number of minimal-residual
+    steps on the velocity block (_st2); none: the run's defaults."""
+    m = re.search(r"_(st|sd)(\d*)$", mode)
+    if m is None:
+        return None, None
+    return ("schur_tri" if m.group(1) == "st" else "schur_diag"), int(m.group(2) or 0)
 
 
 def _solve_modes(run, lw, k, modes):
@@ -54,7 +55,8 @@ def _solve_modes(run, lw, k, modes):
             gf = quadratic_extrapolation_guess
         elif mode.startswith("extrap"):
             gf = linear_extrapolation_guess
-        rec = run.step(guess_fn=gf, inner=inner, record=False, precond=mode_precond(mode))
+        pc, vs = mode_precond(mode)
+        rec = run.step(guess_fn=gf, inner=inner, record=False, precond=pc, vel_steps=vs)
         out[mode] = dict(newton=rec.newton_iters, krylov=rec.krylov_iters, ms_newton=rec.ms_newton,
                          ms_guess=rec.ms_guess, res_plain=rec.res_plain, res_guess=rec.res_guess,
                          used_guess=rec.used_guess, hist=rec.res_hist, phases_ms=rec.phases_ms)
@@ -174,7 +176,7 @@ def large_c5(lw_c4=None, warmup_steps=3, state_path=None, modes=None, warmup_pre
 
 
 def solve_c3(rtol=1e-10, restart=50, max_iters=6000, profile=True, chunk=1000, modes=("mixed", "f64"),
-             precond="bjacobi"):
+             precond="bjacobi", vel_steps=0):
     """96^3 Q2-Q2 channel (28.8M DOF), 500k plate points, seeded smooth right-hand side zeroed
     on the Dirichlet rows: FGMRES(50) with nodal block-Jacobi to rtol, FP32 inner applies
     (FP64 residual, orthogonalisation and restarts) and, for comparison, FP64 inner applies.
@@ -202,7 +204,7 @@ def solve_c3(rtol=1e-10, restart=50, max_iters=6000, profile=True, chunk=1000, m
     prm = make_params(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
     Xt = t(X)
     out = {"workload": f"96^3 Q2-Q2 channel, {cfg.m_points} plate points", "dof": 4 * N,
-           "cells": g.num_cells, "rtol": rtol, "restart": restart, "precond": precond}
+           "cells": g.num_cells, "rtol": rtol, "restart": restart, "precond": precond, "vel_steps": vel_steps}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tab64 = dlm_locate(g, Xt, dtype=torch.float64, s_max=cfg.s_max)
@@ -237,7 +239,7 @@ def solve_c3(rtol=1e-10, restart=50, max_iters=6000, profile=True, chunk=1000, m
         rc = -4
         while iters < max_iters:
             opts = solve_opts(restart=restart, max_iters=min(chunk, max_iters - iters), rtol=rtol,
-                              inner=inner, precond=precond)
+                              inner=inner, precond=precond, vel_steps=vel_steps)
             rc, st = fgmres_solve(P64, bt, x, opts, J32=P32 if inner == torch.float32 else None,
                                   pinv=pinv, check=False)
             iters += st.iters
@@ -268,7 +270,8 @@ def solve_c3(rtol=1e-10, restart=50, max_iters=6000, profile=True, chunk=1000, m
         x = torch.zeros(4 * N, dtype=torch.float64, device=dev)
         profile_enable(True)
         fgmres_solve(P64, bt, x, solve_opts(restart=restart, max_iters=500, rtol=rtol,
-                                            inner=torch.float32, precond=precond), J32=P32, pinv=pinv32,
+                                            inner=torch.float32, precond=precond, vel_steps=vel_steps),
+                     J32=P32, pinv=pinv32,
                      check=False)
         torch.cuda.synchronize()
         ph = {}

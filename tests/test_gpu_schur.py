@@ -220,3 +220,65 @@ def test_schur_full_size_properties(name):
         print(f"  {dt_}: linearity {lin:.3e}, pressure V-cycle symmetry {sym:.3e}", flush=True)
         assert lin <= tol_lin
         assert sym <= tol_sym
+
+
+@pytest.mark.parametrize("name", ["c1", "ragged", "q2", "c2"])
+def test_schur_velocity_steps_match_oracle(name):
+    """Minimal-residual steps on the velocity block (the step lengths on the device) against
+    oracle/schur.velocity_solve: block-diagonal and block-triangular forms, 1 and 3 steps."""
+    import torch
+    import paper_2601_08266_amd as fsi
+    P = _case(name)
+    g = P["g"]
+    N = g.num_nodes
+    print(f"schur velocity steps {name}", flush=True)
+    lv, finv = _oracle(P)
+    _, _, blocks, _ = fsi.bjacobi_setup(P["J64"], want32=False, want_blocks=True)
+    pc = fsi.schur_setup(P["J64"], blocks)
+    v = np.random.default_rng(6).standard_normal(4 * N)
+    v32 = v.astype(np.float32).astype(np.float64)
+
+    def jac(x):
+        return ojac.apply(g, P["prm_o"], P["a"], x, P["cell"], P["xi"], P["kappa"], s=P["s"], mask=P["mask"])
+
+    for mode, form in (("schur_diag", "diag"), ("schur_tri", "tri")):
+        for k in (1, 3):
+            ref = oschur.precond_apply(lv, finv, v, form, jac=jac, vel_steps=k)
+            z = fsi.schur_apply(P["J64"], mode, pc, _t(v), vel_steps=k).cpu().numpy()
+            e64 = field_rel_err(z, ref, 4)
+            ref32 = oschur.precond_apply(lv, finv, v32, form, jac=jac, vel_steps=k)
+            z32 = fsi.schur_apply(P["J32"], mode, pc, _t(v32, "f32"), vel_steps=k).cpu().numpy()
+            e32 = field_rel_err(z32, ref32, 4)
+            print(f"  {mode} k={k}: FP64 {e64:.3e}  FP32 {e32:.3e}", flush=True)
+            assert e64 <= 1e-12
+            assert e32 <= 1e-5
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_fgmres_with_schur_velocity_steps_c1(inner):
+    import torch
+    import paper_2601_08266_amd as fsi
+    cfg = W.CONFIGS["c1"]
+    P = build(cfg, W.advection_field(cfg.grid, cfg.seed_fields))
+    g = P["g"]
+    N = g.num_nodes
+    b = W.smooth_fourier_field(g, cfg.seed_vectors).ravel()
+    b[:3 * N][P["mask"].ravel()] = 0.0
+    J = ojac.dense(g, P["prm_o"], P["a"], P["cell"], P["xi"], P["kappa"], s=P["s"], mask=P["mask"])
+    x_ref = np.linalg.solve(J, b)
+    _, _, blocks, _ = fsi.bjacobi_setup(P["J64"], want32=False, want_blocks=True)
+    pc = fsi.schur_setup(P["J64"], blocks)
+    its = {}
+    for k in (0, 2):
+        x = torch.zeros(4 * N, dtype=torch.float64, device="cuda")
+        tdt = torch.float64 if inner == "f64" else torch.float32
+        opts = fsi.solve_opts(restart=50, max_iters=3000, rtol=1e-10, inner=tdt, precond="schur_tri", vel_steps=k)
+        rc, st = fsi.fgmres_solve(P["J64"], _t(b), x, opts, J32=P["J32"] if inner == "f32" else None, pinv=pc)
+        xs = x.cpu().numpy()
+        res = np.linalg.norm(b - J @ xs) / np.linalg.norm(b)
+        err = np.linalg.norm(xs - x_ref) / np.linalg.norm(x_ref)
+        its[k] = st.iters
+        print(f"fgmres c1 schur_tri vel_steps={k} inner={inner}: iters {st.iters} residual {res:.3e} x err {err:.3e}")
+        assert res <= 1.5e-10
+        assert err <= 1e-6
+    assert its[2] < its[0], its
