@@ -12,6 +12,11 @@ Euler, c_m = 1/dt):
   Dirichlet rows identity, columns zero.
   Multiplier reported afterwards: lambda_B = kappa_B (g_B - (B u)_B), the
   paper's lambda = -R^s (eq. nodal_lagrange) for the stand-in solid residual.
+  Full Newton tangent (tangent="fd"): the derivative of R itself, including the
+  reactive convection, the linearised SUPG test functions and tau, taken as a
+  directional forward difference J v = (R(x + e v~) - R(x)) / e with v~ = v with
+  its Dirichlet entries zeroed, e = sqrt(2^-52) (1 + ||x||) / ||v~||; Dirichlet
+  rows are the identity.
 """
 from __future__ import annotations
 
@@ -44,9 +49,35 @@ def multiplier(grid, x, cell, xi, kappa, g):
     return np.asarray(kappa)[None, :] * (np.asarray(g).reshape(3, -1) - Bu)
 
 
+FD_DELTA = 2.0 ** -26   # sqrt of the FP64 unit roundoff
+
+
+def tangent_fd_apply(grid, prm, x, R0, v, u_old, cell, xi, kappa, g, s=None, mask=None, gD=None,
+                     body=None, visc_strong=True):
+    """Full Newton tangent times v by a directional forward difference (see the header)."""
+    N = grid.num_nodes
+    x = np.asarray(x, dtype=np.float64).reshape(4, N)
+    v = np.asarray(v, dtype=np.float64).reshape(4, N)
+    vm = v.copy()
+    m = None
+    if mask is not None:
+        m = np.asarray(mask, dtype=bool).reshape(3, N)
+        vm[:3][m] = 0.0
+    nv = np.linalg.norm(vm)
+    y = np.zeros((4, N))
+    if nv > 0.0:
+        e = FD_DELTA * (1.0 + np.linalg.norm(x)) / nv
+        Rp = residual(grid, prm, x + e * vm, u_old, cell, xi, kappa, g, s, mask, gD, body=body,
+                      visc_strong=visc_strong)
+        y = (Rp - np.asarray(R0).reshape(4, N)) / e
+    if m is not None:
+        y[:3][m] = v[:3][m]
+    return y
+
+
 def solve_step(grid, prm, x0, u_old, cell, xi, kappa, g, s=None, mask=None, gD=None,
                tol_abs=None, rel=1e-8, max_newton=20, linear="dense", eta=1e-3,
-               visc_strong=True, restart=50, body=None):
+               visc_strong=True, restart=50, body=None, tangent="picard"):
     """Newton from x0 until ||R||_2 <= tol_abs (default rel * ||R(x0)||_2); body: an optional
     nodal source added to c_m u_old."""
     N = grid.num_nodes
@@ -62,7 +93,18 @@ def solve_step(grid, prm, x0, u_old, cell, xi, kappa, g, s=None, mask=None, gD=N
         if hist[-1] <= tol_abs:
             break
         a = x[:3].copy()
-        if linear == "dense":
+        if tangent == "fd":
+            # full tangent: dense by columns of the directional differences (small grids only)
+            n = 4 * N
+            J = np.empty((n, n))
+            for j in range(n):
+                e_j = np.zeros(n)
+                e_j[j] = 1.0
+                J[:, j] = tangent_fd_apply(grid, prm, x, R, e_j, u_old, cell, xi, kappa, g, s, mask, gD,
+                                           body=body, visc_strong=visc_strong).ravel()
+            dx = np.linalg.solve(J, -R.ravel())
+            lin_iters.append(0)
+        elif linear == "dense":
             J = jacobian.dense(grid, prm, a, cell, xi, kappa, s=s, mask=mask, visc_strong=visc_strong)
             dx = np.linalg.solve(J, -R.ravel())
             lin_iters.append(0)

@@ -78,3 +78,59 @@ def test_newton_step_converges_dense_and_fgmres_agree():
     assert np.linalg.norm(x1 - x2) <= 1e-6 * np.linalg.norm(x1)
     R = newton.residual(g, prm, x1, u_old, cell, xi, kappa, g_pts, s=s, mask=m, gD=gD)
     assert np.linalg.norm(R) <= info1["tol_abs"]
+
+
+def _small_newton_case():
+    g = W.Grid((3, 3, 3), 1)
+    N = g.num_nodes
+    cfg = W.CONFIGS["c1"]
+    prm = vms.params_array(cfg.nu, cfg.c_m, cfg.dt)
+    rng = np.random.default_rng(1)
+    u_old = 0.5 * W.advection_field(g, 3)
+    X = rng.uniform(0.3, 0.7, (3, 40))
+    cell, xi = dlm.locate(g, X)
+    kap = np.full(40, 50.0)
+    gp = np.zeros((3, 40))
+    m = W.channel_dirichlet_mask(g)
+    gD = np.zeros((3, N))
+    x0 = np.concatenate([u_old, np.zeros((1, N))])
+    x0[:3][m] = 0.0
+    return g, N, prm, u_old, cell, xi, kap, gp, m, gD, x0
+
+
+def test_fd_tangent_is_the_derivative_of_the_residual():
+    # the forward difference at e ~ 1e-8 agrees with a central difference at h = 1e-4 (error O(h^2))
+    g, N, prm, u_old, cell, xi, kap, gp, m, gD, x0 = _small_newton_case()
+    rng = np.random.default_rng(2)
+    x = x0 + 0.05 * rng.standard_normal(x0.shape)
+    x[:3][m] = 0.0
+    R0 = newton.residual(g, prm, x, u_old, cell, xi, kap, gp, mask=m, gD=gD)
+    v = rng.standard_normal((4, N))
+    y = newton.tangent_fd_apply(g, prm, x, R0, v, u_old, cell, xi, kap, gp, mask=m, gD=gD)
+    vm = v.copy()
+    vm[:3][m] = 0.0
+    h = 1e-4
+    Rp = newton.residual(g, prm, x + h * vm, u_old, cell, xi, kap, gp, mask=m, gD=gD)
+    Rm = newton.residual(g, prm, x - h * vm, u_old, cell, xi, kap, gp, mask=m, gD=gD)
+    yc = (Rp - Rm) / (2 * h)
+    yc[:3][m] = v[:3][m]
+    assert np.linalg.norm(y - yc) <= 1e-6 * np.linalg.norm(yc)
+    # it differs from the Picard/Oseen matrix by the dropped derivatives (reactive convection,
+    # SUPG test function, tau), which are not small relative to rounding
+    yp = jacobian.apply(g, prm, x[:3], v, cell, xi, kap, mask=m)
+    assert np.linalg.norm(y - yp) > 1e-6 * np.linalg.norm(yp)
+
+
+def test_full_tangent_newton_converges_quadratically():
+    g, N, prm, u_old, cell, xi, kap, gp, m, gD, x0 = _small_newton_case()
+    R0 = newton.residual(g, prm, x0, u_old, cell, xi, kap, gp, mask=m, gD=gD)
+    tol = 1e-13 * np.linalg.norm(R0)
+    hist = {}
+    for tg in ("picard", "fd"):
+        x, info = newton.solve_step(g, prm, x0, u_old, cell, xi, kap, gp, mask=m, gD=gD, tol_abs=tol, tangent=tg)
+        assert info["converged"]
+        hist[tg] = info["history"]
+    # second step: linear contraction for Picard, quadratic for the full tangent
+    rp, rf = hist["picard"], hist["fd"]
+    assert rf[2] <= 1e-2 * rp[2], (rp, rf)
+    assert rf[2] / rf[1] <= 1e-2 * (rp[2] / rp[1]), (rp, rf)
