@@ -397,6 +397,7 @@ typedef struct {
     double inner_reduction;
     int32_t precond;          /* fsi_precond: block-Jacobi (0) or a Schur form, rebuilt per iteration */
     int32_t vel_steps;        /* Schur forms: minimal-residual steps on the velocity block */
+    int32_t tangent;          /* 0: Picard/Oseen J(u_k); 1: full Newton tangent (fsi_tangent_apply) */
 } fsi_newton_opts;
 
 typedef struct {
@@ -407,6 +408,25 @@ typedef struct {
 
 size_t fsi_newton_workspace(const fsi_problem *P64, const fsi_problem *P32,
                             const fsi_newton_opts *opts);
+
+/*
+ * fsi_tangent_apply - the full Newton tangent of the step residual (section 2.4:
+ * Newton's method on the monolithic system), i.e. the derivative of
+ * fsi_vms_residual with respect to x including what the Picard/Oseen J drops
+ * (the reactive convection, the linearised SUPG test functions and tau),
+ * applied by a directional forward difference of the FP64 residual:
+ *   y = (R(x + e v~) - R0) / e,  v~ = v with its velocity Dirichlet entries
+ *   zeroed, e = 2^-26 (1 + ||x||) / ||v~||;  velocity Dirichlet rows y = v.
+ * P64, f, lamg, gD as in fsi_vms_residual (FP64, Q1); x double [4][N];
+ * R0 = R(x) double [4][N]; v, y [4][N] in precision dtype (not overlapping).
+ * ws: at least fsi_tangent_workspace(P64) bytes.  fsi_newton_solve uses it as
+ * the Krylov operator when opts->tangent = 1 (the preconditioner keeps the
+ * Picard operator).
+ */
+size_t fsi_tangent_workspace(const fsi_problem *P64);
+int fsi_tangent_apply(const fsi_problem *P64, const double *f, const double *lamg, const double *gD,
+                      const double *x, const double *R0, fsi_dtype dtype, const void *v, void *y,
+                      void *ws, size_t ws_bytes, void *stream);
 int fsi_newton_solve(const fsi_problem *P64, const fsi_problem *P32, const double *f,
                      const double *lamg, const double *gD, double *x,
                      const fsi_newton_opts *opts, fsi_newton_stats *stats, void *ws,

@@ -24,7 +24,7 @@ __all__ = [
     "vms_apply_workspace", "vms_apply", "PointTables", "dlm_locate", "dlm_B", "dlm_BT",
     "Problem", "jacobian_apply", "jacobian_workspace", "dlm_gram", "profile_enable",
     "profile_read", "vms_residual", "bjacobi_setup", "bjacobi_apply", "fgmres_solve",
-    "schur_size", "schur_info", "schur_setup", "schur_apply", "PRECONDS",
+    "schur_size", "schur_info", "schur_setup", "schur_apply", "PRECONDS", "tangent_apply",
     "newton_solve", "solve_opts", "newton_opts",
 ]
 
@@ -444,7 +444,8 @@ def fgmres_solve(J64: Problem, b: torch.Tensor, x: torch.Tensor, opts: FsiSolveO
 
 
 def newton_opts(tol_abs, max_newton=20, eta=1e-3, restart=50, max_krylov=2000,
-                inner=torch.float32, inner_reduction=1e-5, precond="bjacobi", vel_steps=0) -> FsiNewtonOpts:
+                inner=torch.float32, inner_reduction=1e-5, precond="bjacobi", vel_steps=0,
+                tangent="picard") -> FsiNewtonOpts:
     o = FsiNewtonOpts()
     o.max_newton, o.tol_abs, o.eta = int(max_newton), float(tol_abs), float(eta)
     o.restart, o.max_krylov = int(restart), int(max_krylov)
@@ -452,7 +453,23 @@ def newton_opts(tol_abs, max_newton=20, eta=1e-3, restart=50, max_krylov=2000,
     o.inner_reduction = float(inner_reduction)
     o.precond = _precond_code(precond)
     o.vel_steps = int(vel_steps)
+    o.tangent = {"picard": 0, "full": 1}[tangent] if isinstance(tangent, str) else int(tangent)
     return o
+
+
+def tangent_apply(P64: Problem, f: torch.Tensor, x: torch.Tensor, R0: torch.Tensor, v: torch.Tensor,
+                  lamg=None, gD=None, y: Optional[torch.Tensor] = None, stream=None):
+    """Full Newton tangent times v by a directional difference of the residual (fsi_tangent_apply)."""
+    _need(x, "x", torch.float64, 4 * P64.N)
+    _need(R0, "R0", torch.float64, 4 * P64.N)
+    if y is None:
+        y = torch.empty_like(v)
+    nbytes = int(L.lib().fsi_tangent_workspace(ctypes.byref(P64.struct)))
+    ws = _workspace(nbytes, x.device, None)
+    L.check("fsi_tangent_apply", L.lib().fsi_tangent_apply(
+        ctypes.byref(P64.struct), _ptr(f), _ptr(lamg), _ptr(gD), _ptr(x), _ptr(R0), dtype_code(v.dtype),
+        _ptr(v), _ptr(y), _ptr(ws), ws.numel(), _stream(stream)))
+    return y
 
 
 def newton_solve(P64: Problem, f: torch.Tensor, x: torch.Tensor, opts: FsiNewtonOpts,

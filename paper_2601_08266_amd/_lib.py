@@ -63,7 +63,7 @@ class FsiNewtonOpts(ctypes.Structure):
                 ("eta", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_krylov", ctypes.c_int32), ("inner", ctypes.c_int),
                 ("inner_reduction", ctypes.c_double), ("precond", ctypes.c_int32),
-                ("vel_steps", ctypes.c_int32)]
+                ("vel_steps", ctypes.c_int32), ("tangent", ctypes.c_int32)]
 
 
 class FsiNewtonStats(ctypes.Structure):
@@ -135,6 +135,8 @@ SIGNATURES = {
                                         ctypes.POINTER(FsiSolveStats), P, SZ, P]),
     "fsi_newton_workspace": (SZ, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiProblem),
                                   ctypes.POINTER(FsiNewtonOpts)]),
+    "fsi_tangent_workspace": (SZ, [ctypes.POINTER(FsiProblem)]),
+    "fsi_tangent_apply": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, P, P, P, ctypes.c_int, P, P, P, SZ, P]),
     "fsi_newton_solve": (ctypes.c_int, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiProblem), P, P,
                                         P, P, ctypes.POINTER(FsiNewtonOpts),
                                         ctypes.POINTER(FsiNewtonStats), P, SZ, P]),

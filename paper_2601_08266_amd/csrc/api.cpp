@@ -642,6 +642,7 @@ static int check_newton(const fsi_problem *P64, const fsi_problem *P32, const fs
                       o->precond == FSI_PC_SCHUR_TRI,
                   "unknown preconditioner %d", (int)o->precond);
     FSI_CHECK_ARG(o->vel_steps >= 0 && o->vel_steps <= 16, "vel_steps must be in [0, 16]");
+    FSI_CHECK_ARG(o->tangent == 0 || o->tangent == 1, "tangent must be 0 (Picard) or 1 (full)");
     if (o->precond != FSI_PC_BJACOBI) {
         ScPlan sp;
         rc = sc_plan(make_geo(P64->grid), sp);
@@ -673,6 +674,52 @@ FSI_API size_t fsi_newton_workspace(const fsi_problem *P64, const fsi_problem *P
     size_t jw = jac_ws(P64);
     if (o->inner == FSI_F32) jw = std::max(jw, jac_ws(P32));
     return newton_workspace_bytes(make_geo(P64->grid), *o, jw);
+}
+
+FSI_API size_t fsi_tangent_workspace(const fsi_problem *P64)
+{
+    clear_error();
+    if (check_problem(P64) != FSI_OK) return 0;
+    const Geo g = make_geo(P64->grid);
+    return align_up(tangent_workspace_bytes(g)) + jac_ws(P64);
+}
+
+FSI_API int fsi_tangent_apply(const fsi_problem *P64, const double *f, const double *lamg, const double *gD,
+                              const double *x, const double *R0, fsi_dtype dtype, const void *v, void *y,
+                              void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_problem(P64);
+    if (rc) return rc;
+    FSI_CHECK_ARG(P64->dtype == FSI_F64, "the tangent takes the FP64 problem");
+    FSI_CHECK_ARG(dtype_ok(dtype), "bad dtype");
+    if (P64->grid.order != 1) {
+        set_error("the residual kernel is implemented for Q1 grids");
+        return FSI_ERR_UNSUPPORTED;
+    }
+    FSI_CHECK_ARG(f && x && R0 && v && y && v != y, "f, x, R0, v, y must be non-NULL and v != y");
+    FSI_CHECK_ARG(P64->dir_mask == nullptr || gD != nullptr, "gD required with a Dirichlet mask");
+    if (P64->n_occ > 0 && P64->dlm_gram == nullptr) {
+        set_error("the tangent needs the per-cell DLM blocks (fsi_dlm_gram) when n_occ > 0");
+        return FSI_ERR_UNSUPPORTED;
+    }
+    const Geo g = make_geo(P64->grid);
+    const size_t a = align_up(tangent_workspace_bytes(g));
+    if (ws == nullptr || ws_bytes < a + jac_ws(P64)) {
+        set_error("workspace of %zu bytes needed (got %zu)", a + jac_ws(P64), ws_bytes);
+        return FSI_ERR_WORKSPACE;
+    }
+    // the difference step of fsi_newton_solve: 2^-26 (1 + ||x||), ||x|| from the device (SYNCS)
+    hipStream_t st = as_stream(stream);
+    double *scr = reinterpret_cast<double *>(reinterpret_cast<char *>(ws) + a);
+    rc = kry_norm(4 * g.N, x, scr, scr + KRY_NB, st);
+    if (rc) return rc;
+    double xn = 0.0;
+    FSI_HIP(hipMemcpyAsync(&xn, scr + KRY_NB, sizeof(double), hipMemcpyDeviceToHost, st));
+    FSI_HIP(hipStreamSynchronize(st));
+    const DlmView dv = view_of(P64);
+    return tangent_apply(g, *P64, P64->n_occ > 0 ? &dv : nullptr, f, lamg, gD, x, R0, std::ldexp(1.0, -26) * (1.0 + xn),
+                         dtype, v, y, ws, reinterpret_cast<char *>(ws) + a, st);
 }
 
 FSI_API int fsi_newton_solve(const fsi_problem *P64, const fsi_problem *P32, const double *f,

@@ -33,13 +33,17 @@ def _log(msg):
 
 
 def mode_precond(mode):
-    """(preconditioner, velocity steps) named by a mode's suffix: _st / _sd the Schur
+    """(preconditioner, velocity steps, tangent) named by a mode's suffixes: _st / _sd the Schur
     block-triangular / block-diagonal form, followed by an optional number of minimal-residual
-    steps on the velocity block (_st2); none: the run's defaults."""
+    steps on the velocity block (_st2), then an optional _ft for the full Newton tangent;
+    None: the run's defaults."""
+    tangent = None
+    if mode.endswith("_ft"):
+        mode, tangent = mode[:-3], "full"
     m = re.search(r"_(st|sd)(\d*)$", mode)
     if m is None:
-        return None, None
-    return ("schur_tri" if m.group(1) == "st" else "schur_diag"), int(m.group(2) or 0)
+        return None, None, tangent
+    return ("schur_tri" if m.group(1) == "st" else "schur_diag"), int(m.group(2) or 0), tangent
 
 
 def _solve_modes(run, lw, k, modes):
@@ -55,8 +59,8 @@ def _solve_modes(run, lw, k, modes):
             gf = quadratic_extrapolation_guess
         elif mode.startswith("extrap"):
             gf = linear_extrapolation_guess
-        pc, vs = mode_precond(mode)
-        rec = run.step(guess_fn=gf, inner=inner, record=False, precond=pc, vel_steps=vs)
+        pc, vs, tg = mode_precond(mode)
+        rec = run.step(guess_fn=gf, inner=inner, record=False, precond=pc, vel_steps=vs, tangent=tg)
         out[mode] = dict(newton=rec.newton_iters, krylov=rec.krylov_iters, ms_newton=rec.ms_newton,
                          ms_guess=rec.ms_guess, res_plain=rec.res_plain, res_guess=rec.res_guess,
                          used_guess=rec.used_guess, hist=rec.res_hist, phases_ms=rec.phases_ms)

@@ -59,10 +59,11 @@ class StepRecord:
 class ChannelRun:
     def __init__(self, cfg, device="cuda", inner=torch.float32, eta=1e-3, restart=50,
                  rel_tol=1e-8, period=0.8, amp_deg=20.0, max_krylov=4000, precond="bjacobi",
-                 integrator="be", rho_inf=0.5, vel_steps=0):
+                 integrator="be", rho_inf=0.5, vel_steps=0, tangent="picard"):
         self.cfg = cfg
         self.precond = precond
         self.vel_steps = vel_steps
+        self.tangent = tangent
         # time integrator: backward Euler, or generalized-alpha (section 2.4) in stage variables:
         # the stage residual at t_n + alpha_f dt is the backward-Euler-form residual with mass
         # coefficient alpha_m / (gamma dt alpha_f) and source c V_n - (1 - alpha_m/gamma) Vdot_n;
@@ -158,7 +159,8 @@ class ChannelRun:
         dlm_BT(self.g, tab64, lam, out, kappa=self.kappa64)
         return out
 
-    def step(self, guess_fn: Optional[Callable] = None, inner=None, record=True, precond=None, vel_steps=None):
+    def step(self, guess_fn: Optional[Callable] = None, inner=None, record=True, precond=None, vel_steps=None,
+             tangent=None):
         """Advance one step.  guess_fn(run, ctx) -> FP64 [4][N] guess or None; ctx holds the
         step's FP64 problem, lamg, the inflow value, s and the extrapolated guess with its
         residual (x_ex, R_ex, rn_ex; None before two states exist)."""
@@ -214,7 +216,8 @@ class ChannelRun:
         opts = newton_opts(tol_abs=tol, eta=self.eta, restart=self.restart,
                            max_krylov=self.max_krylov, inner=inner,
                            precond=precond if precond is not None else self.precond,
-                           vel_steps=vel_steps if vel_steps is not None else self.vel_steps)
+                           vel_steps=vel_steps if vel_steps is not None else self.vel_steps,
+                           tangent=tangent if tangent is not None else self.tangent)
         x_new = x0.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -211,3 +211,70 @@ def test_newton_c1_matches_dense_newton(inner):
           f"{np.linalg.norm(R):.3e} (tol {tol:.3e})")
     assert np.linalg.norm(R) <= tol * 1.01
     assert np.linalg.norm(xs - x_ref.ravel()) <= 1e-6 * np.linalg.norm(x_ref)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_tangent_apply_c1_matches_oracle(dt):
+    """Full Newton tangent by a directional difference of the residual (fsi_tangent_apply)
+    against oracle.newton.tangent_fd_apply with the same step rule.  Each side differences its
+    own residual, whose 1e-16 rounding the quotient amplifies by 1/e ~ 1e8, so the two agree
+    to about 1e-7 relative; the bound is 1e-5."""
+    import torch
+    import paper_2601_08266_amd as fsi
+    cfg = W.CONFIGS["c1"]
+    X, g_pts, kappa, u_old, mask, gD, x0 = newton_case(cfg)
+    g = cfg.grid
+    N = g.num_nodes
+    P = build(cfg, u_old, X=X, kappa=kappa)
+    kappa = P["kappa"]
+    rng = np.random.default_rng(12)
+    x = x0 + 0.01 * rng.standard_normal(x0.shape)
+    x[:3][mask] = gD[mask]
+    f = cfg.c_m * u_old
+    lamg = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
+    fsi.dlm_BT(g, P["J64"].tables, _t(g_pts), lamg, kappa=_t(kappa))
+    R0 = fsi.vms_residual(P["J64"], _t(f), _t(x), gD=_t(gD), lamg=lamg)
+    R0_o = onewton.residual(g, P["prm_o"], x, u_old, P["cell"], P["xi"], kappa, g_pts, s=P["s"], mask=mask, gD=gD)
+    v = rng.standard_normal(4 * N)
+    if dt == "f32":
+        v = v.astype(np.float32).astype(np.float64)
+    y = fsi.tangent_apply(P["J64"], _t(f), _t(x), R0, _t(v, dt), lamg=lamg, gD=_t(gD)).cpu().numpy()
+    ref = onewton.tangent_fd_apply(g, P["prm_o"], x, R0_o, v, u_old, P["cell"], P["xi"], kappa, g_pts,
+                                   s=P["s"], mask=mask, gD=gD)
+    err = field_rel_err(y, ref, 4)
+    print(f"tangent c1 {dt}: {err:.3e}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("precond", ["schur_tri", "bjacobi"])
+def test_newton_full_tangent_c1_matches_dense_newton(precond):
+    import torch
+    import paper_2601_08266_amd as fsi
+    cfg = W.CONFIGS["c1"]
+    X, g_pts, kappa, u_old, mask, gD, x0 = newton_case(cfg)
+    g = cfg.grid
+    N = g.num_nodes
+    P = build(cfg, u_old, X=X, kappa=kappa)
+    kappa = P["kappa"]
+    R0 = onewton.residual(g, P["prm_o"], x0, u_old, P["cell"], P["xi"], kappa, g_pts, s=P["s"],
+                          mask=mask, gD=gD)
+    tol = 1e-8 * np.linalg.norm(R0)
+    x_ref, info = onewton.solve_step(g, P["prm_o"], x0, u_old, P["cell"], P["xi"], kappa, g_pts,
+                                     s=P["s"], mask=mask, gD=gD, tol_abs=tol, linear="dense")
+    lamg = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
+    fsi.dlm_BT(g, P["J64"].tables, _t(g_pts), lamg, kappa=_t(kappa))
+    its = {}
+    for tangent in ("picard", "full"):
+        x = _t(x0)
+        opts = fsi.newton_opts(tol_abs=tol, inner=torch.float32, precond=precond, tangent=tangent)
+        rc, st = fsi.newton_solve(P["J64"], _t(cfg.c_m * u_old), x, opts, P32=P["J32"], lamg=lamg, gD=_t(gD))
+        xs = x.cpu().numpy()
+        R = onewton.residual(g, P["prm_o"], xs, u_old, P["cell"], P["xi"], kappa, g_pts, s=P["s"],
+                             mask=mask, gD=gD)
+        hist = list(st.res_hist[:st.newton_iters + 1])
+        print(f"newton c1 {precond} tangent={tangent}: {st.newton_iters} Newton / {st.krylov_iters} Krylov, "
+              f"hist {['%.2e' % h for h in hist]}, oracle ||R|| {np.linalg.norm(R):.3e} (tol {tol:.3e})")
+        assert np.linalg.norm(R) <= tol * 1.01
+        assert np.linalg.norm(xs - x_ref.ravel()) <= 1e-6 * np.linalg.norm(x_ref)
+        its[tangent] = st.newton_iters
+    assert its["full"] <= its["picard"]
