@@ -277,7 +277,7 @@ def main(argv=None):
                     help="preconditioner of the c3 solve and of the warmstart run's Newton steps")
     ap.add_argument("--exp-restart", type=int, default=50, help="c3 FGMRES restart length")
     ap.add_argument("--exp-vel-steps", type=int, default=0,
-                    help="c3: minimal-residual steps on the velocity block of the Schur preconditioner")
+                    help="c3 / warmstart: minimal-residual steps on the velocity block of the Schur preconditioner")
     ap.add_argument("--exp-integrator", default="be", choices=["be", "genalpha"],
                     help="time integrator of the probe / warmstart / c5 runs")
     ap.add_argument("--exp-rho-inf", type=float, default=0.5, help="generalized-alpha rho_inf")
@@ -420,7 +420,8 @@ def run_experiment(args):
         summary, lw = ex.warmstart_c4(steps=args.exp_steps, train_end=args.exp_train_end,
                                       epochs=args.exp_epochs, eval_stride=args.exp_stride,
                                       save_path=args.exp_save, precond=args.exp_precond,
-                                      integrator=args.exp_integrator, rho_inf=args.exp_rho_inf)
+                                      integrator=args.exp_integrator, rho_inf=args.exp_rho_inf,
+                                      vel_steps=args.exp_vel_steps)
         print(json.dumps({"experiment": "warmstart_c4", **summary}))
         return 0
     summary = ex.large_c5(state_path=args.exp_load, modes=modes, integrator=args.exp_integrator,

@@ -75,9 +75,9 @@ def _solve_modes(run, lw, k, modes):
 
 
 def warmstart_c4(steps=200, train_end=100, epochs=20, lr=1e-3, eval_stride=1, seed=0,
-                 save_path=None, precond="bjacobi", integrator="be", rho_inf=0.5):
+                 save_path=None, precond="bjacobi", integrator="be", rho_inf=0.5, vel_steps=0):
     cfg = W.CONFIGS["c4"]
-    run = ChannelRun(cfg, precond=precond, integrator=integrator, rho_inf=rho_inf)
+    run = ChannelRun(cfg, precond=precond, integrator=integrator, rho_inf=rho_inf, vel_steps=vel_steps)
     run.record_extrap = True
     t0 = time.perf_counter()
     for n in range(steps):
@@ -114,7 +114,7 @@ def warmstart_c4(steps=200, train_end=100, epochs=20, lr=1e-3, eval_stride=1, se
 
     summary = {
         "workload": "64^3 Q1 channel, 200k points on three rotating plates, dt=1e-3",
-        "precond": precond, "integrator": integrator,
+        "precond": precond, "vel_steps": vel_steps, "integrator": integrator,
         "steps": steps, "train_steps": [2, train_end], "eval_steps": [train_end + 1, steps],
         "epochs": epochs, "params": lw.net.n_params, "train_ms": round(lw.train_ms, 1),
         "final_train_loss": lw.losses[-1] if lw.losses else None,
