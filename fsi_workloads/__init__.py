@@ -21,6 +21,10 @@ Workload recipe (stated once here, repeated in the design notes):
 * Per-point weight kappa_B = alpha * c_m * V_B with alpha = 100 and
   V_B = solid volume / M (stand-in for the solid block of the reduced system,
   section 2.4).
+* Solid mesh (for the hyperelastic solid block): the same three plates meshed by
+  structured trilinear hexahedra, two node layers through the thickness, polar
+  angle 10-90 degrees; its nodes are the solid points.  Solid state: a finite
+  rigid rotation plus a small smooth displacement field (seeded).
 * Seeds: configuration k uses 1000 + k for fields and geometry and 2000 + k for
   random vectors.
 """
@@ -221,6 +225,79 @@ def rotating_plate_points(m: int, seed: int, t: float, period: float = 0.8,
     rel = X - np.asarray(center)[:, None]
     g = np.stack([np.zeros_like(rel[0]), -thdot * rel[2], thdot * rel[1]])
     return X, np.ascontiguousarray(g)
+
+
+PLATE_T_DEG = (10.0, 90.0)
+
+
+def plate_solid_mesh(n_t: int, n_f: int, n_r: int = 2, center=(0.5, 0.5, 0.5),
+                     rotation_deg: float = 0.0):
+    """Structured trilinear-hex mesh of the three plates; its nodes are the solid points.
+
+    Plate k spans r in [0.29, 0.31] (n_r nodes), polar angle t in [10, 90] degrees (n_t
+    nodes; the pole is left out so no element degenerates) and azimuth f in
+    [120k + 2, 120(k+1) - 2] degrees (n_f nodes), all uniformly spaced:
+    X = c + r (cos t, sin t cos f, sin t sin f), then an optional rigid rotation about the
+    x axis through c.  Node (k, i_r, j_t, l_f) has index ((k n_f + l_f) n_t + j_t) n_r + i_r.
+    Element corner a + 2b + 4c sits at offsets (a, b, c) along (r, t, f), a right-handed
+    order (positive volume).
+
+    Returns (X [3][M] float64, conn [E][8] int32).
+    """
+    assert n_r >= 2 and n_t >= 2 and n_f >= 2
+    out, conns = [], []
+    r = np.linspace(PLATE_R[0], PLATE_R[1], n_r)
+    t = np.radians(np.linspace(PLATE_T_DEG[0], PLATE_T_DEG[1], n_t))
+    for k in range(3):
+        f = np.radians(np.linspace(120.0 * k + PLATE_MARGIN_DEG, 120.0 * (k + 1) - PLATE_MARGIN_DEG, n_f))
+        F, T, R = np.meshgrid(f, t, r, indexing="ij")          # [n_f][n_t][n_r]
+        out.append(np.stack([R * np.cos(T), R * np.sin(T) * np.cos(F), R * np.sin(T) * np.sin(F)]).reshape(3, -1))
+        base = k * n_f * n_t * n_r
+        lf, jt, ir = np.meshgrid(np.arange(n_f - 1), np.arange(n_t - 1), np.arange(n_r - 1), indexing="ij")
+        lf, jt, ir = lf.ravel(), jt.ravel(), ir.ravel()
+        corners = []
+        for cidx in range(8):
+            a, b, c = cidx & 1, (cidx >> 1) & 1, cidx >> 2
+            corners.append(base + ((lf + c) * n_t + (jt + b)) * n_r + (ir + a))
+        conns.append(np.stack(corners, axis=1))
+    rel = np.concatenate(out, axis=1)
+    if rotation_deg != 0.0:
+        th = math.radians(rotation_deg)
+        cs, sn = math.cos(th), math.sin(th)
+        rel = np.stack([rel[0], cs * rel[1] - sn * rel[2], sn * rel[1] + cs * rel[2]])
+    X = np.ascontiguousarray(np.asarray(center, dtype=np.float64)[:, None] + rel)
+    return X, np.ascontiguousarray(np.concatenate(conns).astype(np.int32))
+
+
+def solid_mesh_size(m_target: int):
+    """(n_t, n_f) of a two-layer plate mesh with about m_target nodes (3 plates x 2 x n_t x n_f)."""
+    per = max(m_target / 6.0, 4.0)
+    n_t = max(2, int(round(math.sqrt(per / 1.48))))
+    n_f = max(2, int(round(per / n_t)))
+    return n_t, n_f
+
+
+def solid_displacement(X, seed: int, rotation_deg: float = 10.0, amp: float = 0.002,
+                       center=(0.5, 0.5, 0.5)):
+    """Synthetic solid state: U = (R - I)(X - c) + amp * d(X), [3][M].
+
+    R is a rigid rotation about the x axis by rotation_deg (a finite rotation) and d a
+    smooth field sum_{m=1..3} A_m sin(2 pi k_m . X + phi_m) with integer k_m in {-3..3}^3,
+    A_m ~ N(0, I) and phases uniform in [0, 2 pi) (small strains on top of the rotation).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rel = X - np.asarray(center, dtype=np.float64)[:, None]
+    th = math.radians(rotation_deg)
+    cs, sn = math.cos(th), math.sin(th)
+    U = np.stack([np.zeros_like(rel[0]), (cs - 1.0) * rel[1] - sn * rel[2], sn * rel[1] + (cs - 1.0) * rel[2]])
+    for _ in range(3):
+        kv = rng.integers(-3, 4, size=3)
+        while not kv.any():
+            kv = rng.integers(-3, 4, size=3)
+        A = rng.standard_normal(3)
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        U += amp * A[:, None] * np.sin(2.0 * math.pi * (kv @ X) + ph)[None, :]
+    return np.ascontiguousarray(U)
 
 
 def kappa_weights(m: int, solid_volume: float, c_m: float, alpha: float = 100.0):

@@ -23,5 +23,8 @@ Contents (each function cites the passage of the paper it follows):
 * ``newton``   - the nonlinear residual of one implicit step and Newton.
 * ``genalpha`` - generalized-alpha time stepping (section 2.4) in stage
                  variables on top of ``newton``.
+* ``solid``    - the hyperelastic solid block of section 2.4's reduced system
+                 (neo-Hookean energy of eq. inc_neoHk on trilinear hexahedra whose
+                 nodes are the solid points), replacing the per-point stand-in.
 * ``conv3d``   - 3x3x3 convolution layers for the learned warm start.
 """

@@ -1,0 +1,218 @@
+"""Hyperelastic solid block of the reduced system (test infrastructure only).
+
+Section 2.4's momentum-momentum block is dR^{f,m}/dV + C^lambda dR^s/dU (C^lambda)^T.
+This module replaces the per-point stand-in kappa_B I of ``jacobian`` with the solid's
+own tangent, from the solid weak form of section 2.2 (eq. solid_weak_form) and the
+nearly-incompressible neo-Hookean energy of section 4.2 (eq. inc_neoHk):
+
+    psi(F) = C0/2 (tr Cbar - 3) + kappa_s/2 ((J^2 - 1)/2 - ln J),
+    Cbar = Fbar^T Fbar,  Fbar = J^{-1/3} F,  J = det F.
+
+The solid is discretised by trilinear hexahedra on the reference configuration (2x2x2
+Gauss points on [0,1]^3); its nodes are the multiplier points (section 2.3: delta
+functions at the solid nodes), so C^lambda couples them to the fluid through the same
+B / B^T as the point stand-in.  Readings (where the paper is silent or garbled):
+
+* the isochoric split is Fbar = J^{-1/3} F (the printed exponent +1/3 would not give
+  det Fbar = 1);
+* the inertia term of eq. solid_weak_form uses rho^s dOmega_t = rho^s_0 dOmega_0 (mass
+  conservation) and rho^f dOmega_t = rho^f J dOmega_0, so its mass matrix is
+  int (rho^s_0 - rho^f J) N_A N_B dOmega_0;
+* the subtracted viscous work -int 2 mu^f eps(w):eps(v) is taken with the solid
+  velocity interpolant (the velocities agree at the solid nodes by eq.
+  nodal_solid_velo) on the current configuration (grad_x N = F^{-T} grad_X N,
+  dOmega_t = J dOmega_0);
+* within one linear solve the configuration is frozen for the mass and viscous terms
+  (their geometric derivatives are dropped, as the Picard linearisation of the fluid
+  does); the stress term enters with its full material tangent dP/dF.
+
+In velocity form (the unknowns of the linear solves here), the block applied to the
+solid-node velocities is
+
+    K_s = c_M M + c_K K(U) - c_V K_v(U)
+
+with c_M, c_K, c_V the time integrator's derivatives of (acceleration, displacement,
+velocity) with respect to the new velocity (backward Euler: 1/dt, dt, 1).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# 2-point Gauss-Legendre on [0, 1]: points and the equal weight 1/8 per 3D point
+_G = (0.5 - 0.5 / np.sqrt(3.0), 0.5 + 0.5 / np.sqrt(3.0))
+GAUSS = np.array([[_G[i & 1], _G[(i >> 1) & 1], _G[i >> 2]] for i in range(8)])
+GAUSS_W = 0.125
+
+
+def shape(xi):
+    """Trilinear shape functions on [0,1]^3 and their xi-derivatives at one point.
+
+    Corner c = a + 2b + 4c' sits at (a, b, c').  Returns (N [8], dN [8][3]).
+    """
+    N = np.empty(8)
+    dN = np.empty((8, 3))
+    for c in range(8):
+        o = (c & 1, (c >> 1) & 1, c >> 2)
+        f = [xi[d] if o[d] else 1.0 - xi[d] for d in range(3)]
+        df = [1.0 if o[d] else -1.0 for d in range(3)]
+        N[c] = f[0] * f[1] * f[2]
+        dN[c] = (df[0] * f[1] * f[2], f[0] * df[1] * f[2], f[0] * f[1] * df[2])
+    return N, dN
+
+
+# ---- constitutive law (eq. inc_neoHk) ----
+
+def energy(F, C0, kap):
+    """psi(F) of eq. inc_neoHk with Fbar = J^{-1/3} F."""
+    J = np.linalg.det(F)
+    I1bar = J ** (-2.0 / 3.0) * np.sum(F * F)
+    return 0.5 * C0 * (I1bar - 3.0) + 0.5 * kap * (0.5 * (J * J - 1.0) - np.log(J))
+
+
+def piola(F, C0, kap):
+    """First Piola-Kirchhoff stress P = dpsi/dF:
+    C0 J^{-2/3} (F - I1/3 F^{-T}) + kap/2 (J^2 - 1) F^{-T}."""
+    J = np.linalg.det(F)
+    Fit = np.linalg.inv(F).T
+    I1 = np.sum(F * F)
+    return C0 * J ** (-2.0 / 3.0) * (F - I1 / 3.0 * Fit) + 0.5 * kap * (J * J - 1.0) * Fit
+
+
+def piola_tangent(F, dF, C0, kap):
+    """dP = (dP/dF) : dF, differentiating piola() term by term:
+    d(J^{-2/3}) = -2/3 J^{-2/3} (F^{-T}:dF),  d(I1) = 2 F:dF,
+    d(F^{-T}) = -F^{-T} dF^T F^{-T},  d(J^2) = 2 J^2 (F^{-T}:dF)."""
+    J = np.linalg.det(F)
+    Fit = np.linalg.inv(F).T
+    I1 = np.sum(F * F)
+    tr = np.sum(Fit * dF)
+    a = J ** (-2.0 / 3.0)
+    dFit = -Fit @ dF.T @ Fit
+    d_iso = C0 * a * (-2.0 / 3.0 * tr * (F - I1 / 3.0 * Fit) + dF - 2.0 / 3.0 * np.sum(F * dF) * Fit
+                      - I1 / 3.0 * dFit)
+    d_vol = kap * J * J * tr * Fit + 0.5 * kap * (J * J - 1.0) * dFit
+    return d_iso + d_vol
+
+
+def elasticity_tensor(F, C0, kap):
+    """A[i,K,j,L] = dP_iK / dF_jL, column by column from piola_tangent."""
+    A = np.empty((3, 3, 3, 3))
+    for j in range(3):
+        for L in range(3):
+            E = np.zeros((3, 3))
+            E[j, L] = 1.0
+            A[:, :, j, L] = piola_tangent(F, E, C0, kap)
+    return A
+
+
+# ---- one element ----
+
+def _kinematics(Xe, Ue, q):
+    """Gauss point q: shape values, reference gradients G [8][3], det of dX/dxi, F."""
+    N, dN = shape(GAUSS[q])
+    J0 = Xe.T @ dN                       # J0[i][k] = dX_i / dxi_k
+    det0 = np.linalg.det(J0)
+    G = dN @ np.linalg.inv(J0)           # G[A][K] = dN_A / dX_K
+    F = np.eye(3) + Ue.T @ G             # F[i][K] = delta_iK + dU_i / dX_K
+    return N, G, det0, F
+
+
+def element_energy(Xe, Ue, prm):
+    """Stored energy sum_q w det0 psi(F_q) of one element (Xe, Ue: [8][3])."""
+    return sum(GAUSS_W * d * energy(F, prm["C0"], prm["kappa_s"])
+               for _, _, d, F in (_kinematics(Xe, Ue, q) for q in range(8)))
+
+
+def element_force(Xe, Ue, prm):
+    """Internal force f[A][i] = sum_q w det0 P(F_q)_iK G_AK (the weak form's grad w : sigma
+    term, pulled back to the reference configuration)."""
+    f = np.zeros((8, 3))
+    for q in range(8):
+        _, G, d, F = _kinematics(Xe, Ue, q)
+        f += GAUSS_W * d * G @ piola(F, prm["C0"], prm["kappa_s"]).T
+    return f
+
+
+def element_matrices(Xe, Ue, prm):
+    """(M, K, Kv), each [24][24] with DOF 3A + i: the mass matrix with density
+    rho_s0 - rho_f J, the material tangent of the stress term and the viscous matrix
+    2 mu_f int eps(N_A e_i) : eps(N_B e_j) dOmega_t."""
+    M = np.zeros((24, 24))
+    K = np.zeros((24, 24))
+    Kv = np.zeros((24, 24))
+    for q in range(8):
+        N, G, d, F = _kinematics(Xe, Ue, q)
+        J = np.linalg.det(F)
+        w = GAUSS_W * d
+        rho = prm["rho_s0"] - prm["rho_f"] * J
+        A = elasticity_tensor(F, prm["C0"], prm["kappa_s"])
+        g = G @ np.linalg.inv(F)            # g[A][k] = dN_A / dx_k (current configuration)
+        I3 = np.eye(3)
+        # blocks [a][i][b][j] for every node pair (a, b)
+        M += (w * rho * np.einsum("a,b,ij->aibj", N, N, I3)).reshape(24, 24)
+        K += (w * np.einsum("aK,iKjL,bL->aibj", G, A, G)).reshape(24, 24)
+        Kv += (w * J * prm["mu_f"] * (np.einsum("ak,bk,ij->aibj", g, g, I3)
+                                      + np.einsum("bi,aj->aibj", g, g))).reshape(24, 24)
+    return M, K, Kv
+
+
+def element_block(Xe, Ue, prm, cM, cK, cV):
+    M, K, Kv = element_matrices(Xe, Ue, prm)
+    return cM * M + cK * K - cV * Kv
+
+
+# ---- whole mesh ----
+
+def apply(X0, conn, U, v, prm, cM, cK, cV):
+    """y = K_s v at the solid nodes ([3][M] in and out): sum over elements of the dense
+    element block applied to the element's nodal values."""
+    X0 = np.asarray(X0, dtype=np.float64)
+    U = np.asarray(U, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    y = np.zeros_like(v)
+    for e in range(conn.shape[0]):
+        nodes = conn[e]
+        Ke = element_block(X0[:, nodes].T, U[:, nodes].T, prm, cM, cK, cV)
+        ye = Ke @ v[:, nodes].T.reshape(24)
+        np.add.at(y.T, nodes, ye.reshape(8, 3))
+    return y
+
+
+def apply_rows(X0, conn, U, v, prm, cM, cK, cV, nodes):
+    """Rows of K_s v at the listed solid nodes only ([3][len(nodes)]): the elements that
+    touch each node, summed."""
+    nodes = np.asarray(nodes)
+    touch = {}
+    for e in range(conn.shape[0]):
+        for c, n in enumerate(conn[e]):
+            touch.setdefault(int(n), []).append((e, c))
+    out = np.zeros((3, nodes.size))
+    X0 = np.asarray(X0, dtype=np.float64)
+    U = np.asarray(U, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    for k, n in enumerate(nodes):
+        for e, c in touch.get(int(n), []):
+            el = conn[e]
+            Ke = element_block(X0[:, el].T, U[:, el].T, prm, cM, cK, cV)
+            out[:, k] += Ke[3 * c:3 * c + 3] @ v[:, el].T.reshape(24)
+    return out
+
+
+def jacobian_apply(grid, prm_f, a, x, cell, xi, X0, conn, U, prm_s, cM, cK, cV, s=None, mask=None,
+                   visc_strong=True):
+    """J x of section 2.4's reduced system with the solid tangent:
+    J = A_VMS + [[C^lambda K_s (C^lambda)^T, 0], [0, 0]], C^lambda = B^T over the solid nodes
+    (located by (cell, xi)); Dirichlet velocity DOFs have zero columns and identity rows."""
+    from . import dlm, vms
+    N = grid.num_nodes
+    x = np.asarray(x, dtype=np.float64).reshape(4, N)
+    xm = x.copy()
+    if mask is not None:
+        m = np.asarray(mask, dtype=bool).reshape(3, N)
+        xm[:3][m] = 0.0
+    y = vms.apply(grid, prm_f, a, xm, s=s, mask=None, visc_strong=visc_strong)
+    us = dlm.apply_B(grid, cell, xi, xm[:3])
+    y[:3] += dlm.apply_BT(grid, cell, xi, apply(X0, conn, U, us, prm_s, cM, cK, cV))
+    if mask is not None:
+        y[:3][m] = x[:3][m]
+    return y
