@@ -230,6 +230,13 @@ def rotating_plate_points(m: int, seed: int, t: float, period: float = 0.8,
 PLATE_T_DEG = (10.0, 90.0)
 
 
+# Solid material of the hyperelastic block: shear modulus C0 with the bulk-to-shear
+# ratio kappa_s = C0 / 10 of the paper's oscillating-leaflet case (section 4.3), the
+# falling sphere's density ratio rho_s0 / rho_f = 1.5 (section 4.4), and mu_f = nu rho_f
+# of the fluid settings (nu = 1e-2).
+SOLID_MATERIAL = dict(C0=1.0e5, kappa_s=1.0e4, rho_s0=1.5, rho_f=1.0, mu_f=0.01)
+
+
 def plate_solid_mesh(n_t: int, n_f: int, n_r: int = 2, center=(0.5, 0.5, 0.5),
                      rotation_deg: float = 0.0):
     """Structured trilinear-hex mesh of the three plates; its nodes are the solid points.

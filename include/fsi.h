@@ -229,6 +229,73 @@ int fsi_jacobian_apply(const fsi_problem *problem, const void *x, void *y, void 
                        size_t ws_bytes, void *stream);
 
 /*
+ * Hyperelastic solid block (section 2.4's C^lambda dR^s/dU (C^lambda)^T with the
+ * solid's own tangent in place of the per-point stand-in kappa_B I).  The solid
+ * weak form is section 2.2's eq. solid_weak_form, the material the nearly-
+ * incompressible neo-Hookean energy of eq. inc_neoHk,
+ *   psi = C0/2 (tr Cbar - 3) + kappa_s/2 ((J^2 - 1)/2 - ln J),  Cbar = Fbar^T Fbar,
+ *   Fbar = J^{-1/3} F (the isochoric part; the printed exponent +1/3 is read as -1/3),
+ * discretised by trilinear hexahedra (2x2x2 Gauss points) whose nodes are the
+ * multiplier points (section 2.3: delta functions at the solid nodes).  Applied to
+ * solid-node velocities v:
+ *   y = c_M M v + c_K K(U) v - c_V K_v(U) v,
+ *   M   = int (rho_s0 - rho_f J) N_A N_B dOmega_0  (the inertia term with
+ *         rho^s dOmega_t = rho_s0 dOmega_0 and rho^f dOmega_t = rho^f J dOmega_0),
+ *   K   = int grad_0 N_A . dP/dF . grad_0 N_B dOmega_0  (P = dpsi/dF, F = I + grad_0 U),
+ *   K_v = 2 mu_f int eps(N_A) : eps(N_B) dOmega_t  (the subtracted work of the
+ *         artificial fluid, with the solid velocity interpolant, on the current
+ *         configuration); the configuration is frozen within a linear solve for M
+ *         and K_v.  c_M, c_K, c_V are the integrator's derivatives of the solid
+ *         acceleration, displacement and velocity with respect to the new velocity
+ *         (backward Euler: 1/dt, dt, 1).
+ * Deterministic: element forces are summed per node in ascending element order.
+ */
+typedef struct {
+    int64_t n_nodes;            /* M: solid nodes (= the DLM points) */
+    int64_t n_elem;             /* hexahedra */
+    const double *X0;           /* [3][M] reference positions (device) */
+    const int32_t *conn;        /* [n_elem][8] corner node indices (device); corner
+                                   a + 2b + 4c sits at reference (a, b, c) in [0,1]^3 */
+    const int32_t *node_start;  /* [M + 1] from fsi_solid_setup (device) */
+    const int32_t *node_slot;   /* [8 n_elem] from fsi_solid_setup (device) */
+    double C0, kappa_s;         /* eq. inc_neoHk */
+    double rho_s0, rho_f, mu_f; /* solid reference density, fluid density and viscosity */
+} fsi_solid;
+
+/*
+ * fsi_solid_setup - per-mesh table of the element corners around every node
+ * (node_start [M+1], node_slot [8 n_elem] = e*8 + c in ascending order), built on
+ * the host from conn.  Rejects (FSI_ERR_ARG) any conn entry outside [0, M).
+ * SYNCS the stream.
+ */
+int fsi_solid_setup(int64_t n_nodes, int64_t n_elem, const int32_t *conn, int32_t *node_start,
+                    int32_t *node_slot, void *stream);
+
+/*
+ * fsi_solid_apply - y = (c_M M + c_K K(U) - c_V K_v(U)) v at the solid nodes.
+ *   U        double [3][M] solid displacement (current = X0 + U; device)
+ *   v, y     T [3][M] (device, not overlapping); y is overwritten
+ *   ws       at least fsi_solid_workspace(n_elem, dtype) bytes
+ */
+size_t fsi_solid_workspace(int64_t n_elem, fsi_dtype dtype);
+int fsi_solid_apply(const fsi_solid *solid, fsi_dtype dtype, const double *U, double cM, double cK,
+                    double cV, const void *v, void *y, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * fsi_jacobian_solid_apply - y = J x for the reduced system with the solid block:
+ *   J = A_VMS(a, s) + [[B^T K_s B, 0], [0, 0]],  K_s = c_M M + c_K K(U) - c_V K_v(U),
+ * with B = (C^lambda)^T over the solid nodes (problem->m == solid->n_nodes; the
+ * point tables come from fsi_dlm_locate on the current positions X0 + U;
+ * problem->kappa and problem->dlm_gram are ignored).  Dirichlet velocity DOFs
+ * (dir_mask) have identity rows and zero columns.  x, y: T [4][N] (device, not
+ * overlapping).  ws: at least fsi_jacobian_solid_workspace(problem, solid) bytes.
+ */
+size_t fsi_jacobian_solid_workspace(const fsi_problem *problem, const fsi_solid *solid);
+int fsi_jacobian_solid_apply(const fsi_problem *problem, const fsi_solid *solid, const double *U,
+                             double cM, double cK, double cV, const void *x, void *y, void *ws,
+                             size_t ws_bytes, void *stream);
+
+/*
  * fsi_vms_residual - nonlinear residual of one implicit step (Q1 grids), the
  * right-hand side of the Newton corrections of section 2.4:
  *   R = A(a = u, tau(u)) x - F(f) + [B^T diag(kappa) (B u - g); 0]

@@ -3,7 +3,7 @@
 Section 2.4's momentum-momentum block is dR^{f,m}/dV + C^lambda dR^s/dU (C^lambda)^T.
 This module replaces the per-point stand-in kappa_B I of ``jacobian`` with the solid's
 own tangent, from the solid weak form of section 2.2 (eq. solid_weak_form) and the
-nearly-incompressible neo-Hookean energy of section 4.2 (eq. inc_neoHk):
+nearly-incompressible neo-Hookean energy of section 4.3 (eq. inc_neoHk):
 
     psi(F) = C0/2 (tr Cbar - 3) + kappa_s/2 ((J^2 - 1)/2 - ln J),
     Cbar = Fbar^T Fbar,  Fbar = J^{-1/3} F,  J = det F.

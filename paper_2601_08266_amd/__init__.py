@@ -25,7 +25,8 @@ __all__ = [
     "Problem", "jacobian_apply", "jacobian_workspace", "dlm_gram", "profile_enable",
     "profile_read", "vms_residual", "bjacobi_setup", "bjacobi_apply", "fgmres_solve",
     "schur_size", "schur_info", "schur_setup", "schur_apply", "PRECONDS", "tangent_apply",
-    "newton_solve", "solve_opts", "newton_opts",
+    "newton_solve", "solve_opts", "newton_opts", "Solid", "solid_apply", "jacobian_solid_workspace",
+    "jacobian_solid_apply",
 ]
 
 _TORCH_OF = {FSI_F64: torch.float64, FSI_F32: torch.float32}
@@ -308,6 +309,70 @@ def jacobian_apply(problem: Problem, x: torch.Tensor, y: Optional[torch.Tensor] 
     ws = _workspace(problem.workspace_bytes(), x.device, ws)
     L.check("fsi_jacobian_apply", L.lib().fsi_jacobian_apply(
         ctypes.byref(problem.struct), _ptr(x), _ptr(y), _ptr(ws), ws.numel(), _stream(stream)))
+    return y
+
+
+# --------------------------------------------------------------------------- solid block
+class Solid:
+    """fsi_solid: a trilinear-hex solid mesh whose nodes are the DLM points, with the
+    neo-Hookean material of eq. inc_neoHk; the node -> element-corner table is built by
+    fsi_solid_setup (which validates the connectivity)."""
+
+    def __init__(self, X0: torch.Tensor, conn: torch.Tensor, C0: float, kappa_s: float, rho_s0: float,
+                 rho_f: float, mu_f: float, stream=None):
+        _need(X0, "X0", torch.float64)
+        _need(conn, "conn", torch.int32)
+        m = X0.numel() // 3
+        ne = conn.numel() // 8
+        if X0.numel() != 3 * m or conn.numel() != 8 * ne:
+            raise ValueError("X0 must be [3][M] and conn [n_elem][8]")
+        self.X0, self.conn, self.m, self.n_elem = X0, conn, m, ne
+        self.node_start = torch.empty(m + 1, dtype=torch.int32, device=X0.device)
+        self.node_slot = torch.empty(max(8 * ne, 1), dtype=torch.int32, device=X0.device)
+        L.check("fsi_solid_setup", L.lib().fsi_solid_setup(
+            m, ne, _ptr(conn), _ptr(self.node_start), _ptr(self.node_slot), _stream(stream)))
+        st = L.FsiSolid()
+        st.n_nodes, st.n_elem = m, ne
+        st.X0, st.conn = X0.data_ptr(), conn.data_ptr()
+        st.node_start, st.node_slot = self.node_start.data_ptr(), self.node_slot.data_ptr()
+        st.C0, st.kappa_s, st.rho_s0, st.rho_f, st.mu_f = C0, kappa_s, rho_s0, rho_f, mu_f
+        self.struct = st
+
+
+def solid_apply(solid: Solid, U: torch.Tensor, v: torch.Tensor, cM: float, cK: float, cV: float,
+                y: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None):
+    """y = (c_M M + c_K K(U) - c_V K_v(U)) v at the solid nodes (fsi_solid_apply)."""
+    dt = v.dtype
+    _need(U, "U", torch.float64, 3 * solid.m)
+    _need(v, "v", dt, 3 * solid.m)
+    if y is None:
+        y = torch.empty_like(v)
+    _need(y, "y", dt, 3 * solid.m)
+    ws = _workspace(int(L.lib().fsi_solid_workspace(solid.n_elem, dtype_code(dt))), v.device, ws)
+    L.check("fsi_solid_apply", L.lib().fsi_solid_apply(
+        ctypes.byref(solid.struct), dtype_code(dt), _ptr(U), cM, cK, cV, _ptr(v), _ptr(y), _ptr(ws),
+        ws.numel() * ws.element_size(), _stream(stream)))
+    return y
+
+
+def jacobian_solid_workspace(problem: Problem, solid: Solid) -> int:
+    return int(L.lib().fsi_jacobian_solid_workspace(ctypes.byref(problem.struct), ctypes.byref(solid.struct)))
+
+
+def jacobian_solid_apply(problem: Problem, solid: Solid, U: torch.Tensor, x: torch.Tensor, cM: float,
+                         cK: float, cV: float, y: Optional[torch.Tensor] = None,
+                         ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """y = J x with the solid block B^T K_s B in place of the point stand-in
+    (fsi_jacobian_solid_apply); the problem's points are the solid's nodes."""
+    _need(x, "x", problem.dtype, 4 * problem.N)
+    _need(U, "U", torch.float64, 3 * solid.m)
+    if y is None:
+        y = torch.empty_like(x)
+    _need(y, "y", problem.dtype, 4 * problem.N)
+    ws = _workspace(jacobian_solid_workspace(problem, solid), x.device, ws)
+    L.check("fsi_jacobian_solid_apply", L.lib().fsi_jacobian_solid_apply(
+        ctypes.byref(problem.struct), ctypes.byref(solid.struct), _ptr(U), cM, cK, cV, _ptr(x), _ptr(y),
+        _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
     return y
 
 

@@ -45,6 +45,13 @@ class FsiProblem(ctypes.Structure):
                 ("dlm_gram", ctypes.c_void_p)]
 
 
+class FsiSolid(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_elem", ctypes.c_int64), ("X0", ctypes.c_void_p),
+                ("conn", ctypes.c_void_p), ("node_start", ctypes.c_void_p),
+                ("node_slot", ctypes.c_void_p), ("C0", ctypes.c_double), ("kappa_s", ctypes.c_double),
+                ("rho_s0", ctypes.c_double), ("rho_f", ctypes.c_double), ("mu_f", ctypes.c_double)]
+
+
 class FsiSolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_iters", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("inner", ctypes.c_int),
@@ -118,6 +125,14 @@ SIGNATURES = {
     "fsi_jacobian_workspace": (SZ, [ctypes.POINTER(FsiProblem)]),
     "fsi_jacobian_apply": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, P, SZ, P]),
     "fsi_vms_residual": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, P, P, P, P, SZ, P]),
+    "fsi_solid_setup": (ctypes.c_int, [I64, I64, P, P, P, P]),
+    "fsi_solid_workspace": (SZ, [I64, ctypes.c_int]),
+    "fsi_solid_apply": (ctypes.c_int, [ctypes.POINTER(FsiSolid), ctypes.c_int, P, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, P, P, P, SZ, P]),
+    "fsi_jacobian_solid_workspace": (SZ, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiSolid)]),
+    "fsi_jacobian_solid_apply": (ctypes.c_int, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiSolid), P,
+                                                ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P,
+                                                P, SZ, P]),
     "fsi_bjacobi_workspace": (SZ, [ctypes.POINTER(FsiGrid)]),
     "fsi_bjacobi_setup": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, P, ctypes.POINTER(I64),
                                          P, SZ, P]),

@@ -114,7 +114,7 @@ static int vms_apply_t(const Geo &g, const fsi_vms_params &prm, const T *a, cons
     const size_t vbytes = vms_workspace_bytes(g, sizeof(T) == 8 ? FSI_F64 : FSI_F32);
     T *csum = nullptr;
     // DLM block: per-cell blocks folded into the cell kernel when available
-    const bool use_gram = dlm != nullptr && dlm->n_occ > 0 && dlm->gram != nullptr;
+    const bool use_gram = dlm != nullptr && dlm->n_occ > 0 && dlm->gram != nullptr && dlm->solid == nullptr;
     const T *gram = use_gram ? reinterpret_cast<const T *>(dlm->gram) : nullptr;
     const int32_t *gidx = use_gram ? dlm->occ_index : nullptr;
     int rc;
@@ -123,9 +123,27 @@ static int vms_apply_t(const Geo &g, const fsi_vms_params &prm, const T *a, cons
     else
         rc = launch_q2_cells<T>(g, k, x, a, s, mask, gram, gidx, part, bl, st);
     if (rc) return rc;
-    if (dlm != nullptr && dlm->n_occ > 0 && !use_gram) {
+    const fsi_dtype dt = sizeof(T) == 8 ? FSI_F64 : FSI_F32;
+    if (dlm != nullptr && dlm->n_occ > 0 && dlm->solid != nullptr) {
+        // solid block: u_s = B x (Dirichlet-masked), l_s = K_s u_s at the solid nodes, then the
+        // corner sums of B^T l_s, added by the node gather before the Dirichlet rows
+        char *w = reinterpret_cast<char *>(ws) + vbytes;
+        csum = reinterpret_cast<T *>(w);
+        w += dlm_csum_bytes(g, dlm->n_occ, dt);
+        T *us = reinterpret_cast<T *>(w);
+        w += align_up((size_t)3 * dlm->m * sizeof(T));
+        T *ls = reinterpret_cast<T *>(w);
+        w += align_up((size_t)3 * dlm->m * sizeof(T));
+        rc = launch_dlm_B(g, dt, dlm->m, dlm->cell, dlm->xi, x, mask, us, st);
+        if (rc) return rc;
+        rc = launch_solid_apply(*dlm->solid, dt, dlm->solid_U, dlm->solid_c, us, ls, w, st);
+        if (rc) return rc;
+        rc = launch_dlm_cell_reduce(g, dt, false, dlm->m, dlm->n_occ, dlm->occ_cell, dlm->occ_start,
+                                    dlm->perm, dlm->xi, nullptr, ls, nullptr, csum, st);
+        if (rc) return rc;
+    } else if (dlm != nullptr && dlm->n_occ > 0 && !use_gram) {
         csum = reinterpret_cast<T *>(reinterpret_cast<char *>(ws) + vbytes);
-        rc = launch_dlm_cell_reduce(g, sizeof(T) == 8 ? FSI_F64 : FSI_F32, true, dlm->m, dlm->n_occ,
+        rc = launch_dlm_cell_reduce(g, dt, true, dlm->m, dlm->n_occ,
                                     dlm->occ_cell, dlm->occ_start, dlm->perm, dlm->xi, dlm->kappa, x,
                                     mask, csum, st);
         if (rc) return rc;
@@ -279,7 +297,7 @@ FSI_API int fsi_dlm_B(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const in
     FSI_CHECK_ARG(dtype_ok(dtype), "bad dtype %d", (int)dtype);
     FSI_CHECK_ARG(m >= 0 && m < ((int64_t)1 << 31) - 1, "m out of range");
     FSI_CHECK_ARG(m == 0 || (cell && xi && u && Bu), "cell, xi, u and Bu must be non-NULL");
-    return launch_dlm_B(make_geo(*grid), dtype, m, cell, xi, u, Bu, as_stream(stream));
+    return launch_dlm_B(make_geo(*grid), dtype, m, cell, xi, u, nullptr, Bu, as_stream(stream));
 }
 
 FSI_API size_t fsi_dlm_BT_workspace(const fsi_grid *grid, int64_t n_occ, fsi_dtype dtype)
@@ -376,6 +394,107 @@ FSI_API int fsi_jacobian_apply(const fsi_problem *p, const void *x, void *y, voi
     DlmView v{p->m,     p->cell,  p->xi,        p->perm,  p->occ_cell, p->occ_start,
               p->n_occ, p->occ_index, p->kappa, p->dlm_gram};
     return launch_vms_apply(g, p->prm, p->dtype, p->a, p->s, p->dir_mask, x, y,
+                            p->n_occ > 0 ? &v : nullptr, ws, ws_bytes, as_stream(stream));
+}
+
+// ---- hyperelastic solid block ----
+
+static int check_solid(const fsi_solid *S)
+{
+    FSI_CHECK_ARG(S != nullptr, "solid is NULL");
+    FSI_CHECK_ARG(S->n_nodes >= 0 && S->n_nodes < ((int64_t)1 << 31) - 1, "solid n_nodes out of range");
+    FSI_CHECK_ARG(S->n_elem >= 0 && S->n_elem < ((int64_t)1 << 28), "solid n_elem out of range");
+    FSI_CHECK_ARG(S->n_nodes == 0 || (S->X0 && S->node_start), "solid X0 and node_start must be non-NULL");
+    FSI_CHECK_ARG(S->n_elem == 0 || (S->conn && S->node_slot), "solid conn and node_slot must be non-NULL");
+    FSI_CHECK_ARG(std::isfinite(S->C0) && std::isfinite(S->kappa_s) && std::isfinite(S->rho_s0) &&
+                      std::isfinite(S->rho_f) && std::isfinite(S->mu_f),
+                  "solid material parameters must be finite");
+    return FSI_OK;
+}
+
+static SolidView solid_view(const fsi_solid *S)
+{
+    return SolidView{S->n_nodes,    S->n_elem, S->X0,     S->conn,  S->node_start, S->node_slot,
+                     S->C0,         S->kappa_s, S->rho_s0, S->rho_f, S->mu_f};
+}
+
+FSI_API int fsi_solid_setup(int64_t n_nodes, int64_t n_elem, const int32_t *conn, int32_t *node_start,
+                            int32_t *node_slot, void *stream)
+{
+    clear_error();
+    FSI_CHECK_ARG(n_nodes >= 0 && n_nodes < ((int64_t)1 << 31) - 1, "n_nodes out of range");
+    FSI_CHECK_ARG(n_elem >= 0 && n_elem < ((int64_t)1 << 28), "n_elem out of range");
+    FSI_CHECK_ARG(node_start != nullptr, "node_start must be non-NULL");
+    FSI_CHECK_ARG(n_elem == 0 || (conn && node_slot), "conn and node_slot must be non-NULL");
+    return solid_build_csr(n_nodes, n_elem, conn, node_start, node_slot, as_stream(stream));
+}
+
+FSI_API size_t fsi_solid_workspace(int64_t n_elem, fsi_dtype dtype)
+{
+    return solid_workspace_bytes(n_elem, dtype);
+}
+
+FSI_API int fsi_solid_apply(const fsi_solid *S, fsi_dtype dtype, const double *U, double cM, double cK,
+                            double cV, const void *v, void *y, void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_solid(S);
+    if (rc) return rc;
+    FSI_CHECK_ARG(dtype_ok(dtype), "bad dtype %d", (int)dtype);
+    FSI_CHECK_ARG(std::isfinite(cM) && std::isfinite(cK) && std::isfinite(cV), "coefficients must be finite");
+    FSI_CHECK_ARG(S->n_nodes == 0 || (U && v && y), "U, v and y must be non-NULL");
+    FSI_CHECK_ARG(v != y, "v and y must not alias");
+    const size_t need = solid_workspace_bytes(S->n_elem, dtype);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+        return FSI_ERR_WORKSPACE;
+    }
+    return launch_solid_apply(solid_view(S), dtype, U, SolidCoefs{cM, cK, cV}, v, y, ws, as_stream(stream));
+}
+
+static size_t jacobian_solid_bytes(const fsi_problem *p, const fsi_solid *S)
+{
+    const Geo g = make_geo(p->grid);
+    const size_t es = p->dtype == FSI_F64 ? 8 : 4;
+    return vms_workspace_bytes(g, p->dtype) + dlm_csum_bytes(g, p->n_occ, p->dtype) +
+           2 * align_up((size_t)3 * p->m * es) + solid_workspace_bytes(S->n_elem, p->dtype);
+}
+
+FSI_API size_t fsi_jacobian_solid_workspace(const fsi_problem *p, const fsi_solid *S)
+{
+    if (check_problem(p) != FSI_OK || check_solid(S) != FSI_OK) return 0;
+    return jacobian_solid_bytes(p, S);
+}
+
+FSI_API int fsi_jacobian_solid_apply(const fsi_problem *p, const fsi_solid *S, const double *U, double cM,
+                                     double cK, double cV, const void *x, void *y, void *ws,
+                                     size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_problem(p);
+    if (rc) return rc;
+    rc = check_solid(S);
+    if (rc) return rc;
+    FSI_CHECK_ARG(p->m == S->n_nodes, "the problem's points (%lld) must be the solid's nodes (%lld)",
+                  (long long)p->m, (long long)S->n_nodes);
+    FSI_CHECK_ARG(std::isfinite(cM) && std::isfinite(cK) && std::isfinite(cV), "coefficients must be finite");
+    FSI_CHECK_ARG(x && y, "x and y must be non-NULL");
+    FSI_CHECK_ARG(x != y, "x and y must not alias");
+    FSI_CHECK_ARG(S->n_nodes == 0 || U != nullptr, "U must be non-NULL");
+    if (p->n_occ > 0)
+        FSI_CHECK_ARG(p->cell != nullptr, "point cells must be non-NULL when n_occ > 0");
+    const size_t need = jacobian_solid_bytes(p, S);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+        return FSI_ERR_WORKSPACE;
+    }
+    const SolidView sv = solid_view(S);
+    DlmView v{p->m,     p->cell,      p->xi,   p->perm, p->occ_cell, p->occ_start,
+              p->n_occ, p->occ_index, nullptr, nullptr};
+    v.solid = &sv;
+    v.solid_U = U;
+    v.solid_c = SolidCoefs{cM, cK, cV};
+    return launch_vms_apply(make_geo(p->grid), p->prm, p->dtype, p->a, p->s, p->dir_mask, x, y,
                             p->n_occ > 0 ? &v : nullptr, ws, ws_bytes, as_stream(stream));
 }
 

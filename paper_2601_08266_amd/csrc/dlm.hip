@@ -312,6 +312,7 @@ __device__ __forceinline__ void lagrange(T t, T N[P + 1])
 template <typename T, int P>
 __global__ __launch_bounds__(256) void dlm_B_kernel(Geo g, int64_t m, const int32_t *__restrict__ cell,
                                                     const T *__restrict__ xi, const T *__restrict__ u,
+                                                    const uint32_t *__restrict__ mask,
                                                     T *__restrict__ Bu)
 {
     constexpr int Q = P + 1;
@@ -335,7 +336,8 @@ __global__ __launch_bounds__(256) void dlm_B_kernel(Geo g, int64_t m, const int3
                                          (int64_t)g.nn[0] * ((P * cy + ay) + (int64_t)g.nn[1] * (P * cz + az));
                     const T w = Nx[ax] * Ny[ay] * Nz[az];
 #pragma unroll
-                    for (int f = 0; f < 3; ++f) acc[f] += w * u[f * g.N + node];
+                    for (int f = 0; f < 3; ++f)
+                        acc[f] += w * (mask_bit(mask, f * g.N + node) ? T(0) : u[f * g.N + node]);
                 }
     }
 #pragma unroll
@@ -667,24 +669,25 @@ int launch_locate(const Geo &g, int64_t m, const double *X, fsi_dtype dt, int32_
 }
 
 template <typename T>
-static int launch_B_t(const Geo &g, int64_t m, const int32_t *cell, const T *xi, const T *u, T *Bu,
-                      hipStream_t st)
+static int launch_B_t(const Geo &g, int64_t m, const int32_t *cell, const T *xi, const T *u,
+                      const uint32_t *mask, T *Bu, hipStream_t st)
 {
     if (m == 0) return FSI_OK;
+    ProfileScope prof("dlm_B", st);
     if (g.p == 1)
-        hipLaunchKernelGGL((dlm_B_kernel<T, 1>), dim3(nblk(m)), dim3(256), 0, st, g, m, cell, xi, u, Bu);
+        hipLaunchKernelGGL((dlm_B_kernel<T, 1>), dim3(nblk(m)), dim3(256), 0, st, g, m, cell, xi, u, mask, Bu);
     else
-        hipLaunchKernelGGL((dlm_B_kernel<T, 2>), dim3(nblk(m)), dim3(256), 0, st, g, m, cell, xi, u, Bu);
+        hipLaunchKernelGGL((dlm_B_kernel<T, 2>), dim3(nblk(m)), dim3(256), 0, st, g, m, cell, xi, u, mask, Bu);
     FSI_LAUNCH_CHECK();
     return FSI_OK;
 }
 
 int launch_dlm_B(const Geo &g, fsi_dtype dt, int64_t m, const int32_t *cell, const void *xi,
-                 const void *u, void *Bu, hipStream_t st)
+                 const void *u, const uint32_t *mask, void *Bu, hipStream_t st)
 {
     if (dt == FSI_F64)
-        return launch_B_t<double>(g, m, cell, (const double *)xi, (const double *)u, (double *)Bu, st);
-    return launch_B_t<float>(g, m, cell, (const float *)xi, (const float *)u, (float *)Bu, st);
+        return launch_B_t<double>(g, m, cell, (const double *)xi, (const double *)u, mask, (double *)Bu, st);
+    return launch_B_t<float>(g, m, cell, (const float *)xi, (const float *)u, mask, (float *)Bu, st);
 }
 
 size_t dlm_csum_bytes(const Geo &g, int64_t n_occ, fsi_dtype dt)

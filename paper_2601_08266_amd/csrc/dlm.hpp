@@ -10,8 +10,9 @@ int launch_locate(const Geo &g, int64_t m, const double *X, fsi_dtype dt, int32_
                   int32_t *perm, int32_t *occ_cell, int32_t *occ_start, int32_t *occ_index,
                   void *s_out, double s_max, int64_t *n_occ_host, int64_t *n_outside_host, void *ws,
                   hipStream_t st);
+// Bu = B u; Dirichlet velocity entries of u (mask bits, or NULL) read as zero
 int launch_dlm_B(const Geo &g, fsi_dtype dt, int64_t m, const int32_t *cell, const void *xi,
-                 const void *u, void *Bu, hipStream_t st);
+                 const void *u, const uint32_t *mask, void *Bu, hipStream_t st);
 int launch_dlm_cell_reduce(const Geo &g, fsi_dtype dt, bool from_u, int64_t m, int64_t n_occ,
                            const int32_t *occ_cell, const int32_t *occ_start, const int32_t *perm,
                            const void *xi, const void *kappa, const void *src, const uint32_t *mask,

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "solid.hpp"
 
 namespace fsi {
 
@@ -84,6 +85,11 @@ struct DlmView {
     const int32_t *occ_index;   // [E] occupied index per cell or -1
     const void *kappa;
     const void *gram;           // [n_occ][nen][nen] or nullptr
+    // hyperelastic solid block in place of the per-point kappa (kappa and gram unused):
+    // the points are the solid's nodes, y += B^T (c_M M + c_K K(U) - c_V K_v(U)) B x_u
+    const SolidView *solid = nullptr;
+    const double *solid_U = nullptr;
+    SolidCoefs solid_c{};
 };
 
 // y = A x (+ B^T kappa B x_u if dlm != nullptr), Dirichlet rows -> x.

@@ -1,0 +1,30 @@
+// Internal declarations of the hyperelastic solid block.
+#pragma once
+
+#include "common.hpp"
+
+namespace fsi {
+
+// Material and mesh of the immersed solid (all device pointers).
+struct SolidView {
+    int64_t n_nodes, n_elem;
+    const double *X0;            // [3][n_nodes] reference positions
+    const int32_t *conn;         // [n_elem][8]
+    const int32_t *node_start;   // [n_nodes + 1]
+    const int32_t *node_slot;    // [8 n_elem]: element corners e*8 + c around each node, ascending
+    double C0, kappa_s, rho_s0, rho_f, mu_f;
+};
+
+// Time-integration coefficients of the block c_M M + c_K K(U) - c_V K_v(U).
+struct SolidCoefs {
+    double cM, cK, cV;
+};
+
+size_t solid_workspace_bytes(int64_t n_elem, fsi_dtype dt);
+int solid_build_csr(int64_t n_nodes, int64_t n_elem, const int32_t *conn, int32_t *node_start,
+                    int32_t *node_slot, hipStream_t st);
+// y [3][n_nodes] = (c_M M + c_K K(U) - c_V K_v(U)) v, v [3][n_nodes] in precision dt
+int launch_solid_apply(const SolidView &s, fsi_dtype dt, const double *U, const SolidCoefs &k,
+                       const void *v, void *y, void *ws, hipStream_t st);
+
+}  // namespace fsi

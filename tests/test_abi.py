@@ -70,3 +70,19 @@ def test_schur_rejects_lattices_without_a_small_coarse_level():
     import paper_2601_08266_amd as fsi
     assert fsi.schur_size(fsi.make_grid((13, 13, 13), 1)) == 0
     assert b"coarsened" in fsi._lib.lib().fsi_last_error()
+
+
+def test_solid_entry_points_reject_bad_arguments_without_gpu():
+    import paper_2601_08266_amd._lib as L
+    lib = L.lib()
+    assert lib.fsi_solid_setup(-1, 0, None, None, None, None) == L.FSI_ERR_ARG
+    assert lib.fsi_solid_setup(8, 1, None, None, None, None) == L.FSI_ERR_ARG
+    assert lib.fsi_solid_workspace(10, 0) >= 10 * 24 * 8
+    s = L.FsiSolid()
+    s.n_nodes, s.n_elem = 8, 1          # tables missing
+    rc = lib.fsi_solid_apply(ctypes.byref(s), 0, None, 1.0, 1.0, 1.0, None, None, None, 0, None)
+    assert rc == L.FSI_ERR_ARG
+    s.n_nodes, s.n_elem = 0, 0
+    s.C0 = float("nan")
+    rc = lib.fsi_solid_apply(ctypes.byref(s), 0, None, 1.0, 1.0, 1.0, None, None, None, 0, None)
+    assert rc == L.FSI_ERR_ARG and b"finite" in lib.fsi_last_error()

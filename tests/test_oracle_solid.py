@@ -1,5 +1,5 @@
 """Pins of the oracle's hyperelastic solid block (oracle/solid.py; section 2.2's solid weak
-form with section 4.2's nearly-incompressible neo-Hookean energy, eq. inc_neoHk).
+form with section 4.3's nearly-incompressible neo-Hookean energy, eq. inc_neoHk).
 
 * The reference state is stress free; a pure dilation stores only the volumetric energy.
 * P is the gradient of psi, and dP the derivative of P (central differences).
