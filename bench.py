@@ -79,6 +79,92 @@ def dlm_cell_flops():
     return 2 * 192 + 36
 
 
+def solid_elem_flops():
+    """Flops solid_elem_k spends on one hexahedron (8 lanes, one per Gauss point; fma = 2,
+    add/mul/div/cbrt = 1), counted from the kernel's arithmetic, per lane:
+    23 trilinear shape evaluations (10 each); dX/dxi from 7 corner differences (7 x 21);
+    its determinant, cofactors and inverse (51); reference gradients, displacement
+    differences, v at the point, F and dF over 8 corners (8 x 60); F + I (3); det,
+    cofactors and F^{-T} (51); I1, F^{-T}:dF, F:dF (54); d(F^{-T}) (99); J^{-2/3} and the
+    scalar factors (13); grad_x v (45); the stress increment Q with the viscous term
+    (9 x 26 + 2); inertia factor and weight (4); nodal forces of 8 corners (8 x 15
+    gradients + 8 x 27) and their 8-lane sums (8 x 9)."""
+    per_lane = (23 * 10 + 7 * 21 + 51 + 8 * 60 + 3 + 51 + 54 + 99 + 13 + 45 + 9 * 26 + 2 + 4 +
+                8 * (15 + 27 + 9))
+    return 8 * per_lane
+
+
+def time_solid(fsi, torch, cfg, reps=50):
+    """Hyperelastic solid block on the workload's plate mesh (nodes = the DLM points, about
+    cfg.m_points of them): fsi_solid_apply and the reduced-system Jacobian with the solid
+    block (fsi_jacobian_solid_apply), FP64 and FP32, timed with events on the launch stream;
+    the element kernel's average duration from the library's per-kernel events."""
+    import numpy as np
+
+    import fsi_workloads as W
+
+    g = cfg.grid
+    N = g.num_nodes
+    n_t, n_f = W.solid_mesh_size(cfg.m_points)
+    X0, conn = W.plate_solid_mesh(n_t, n_f)
+    U = W.solid_displacement(X0, cfg.seed_fields)
+    M, ne = X0.shape[1], conn.shape[0]
+
+    def t(v, dt=torch.float64):
+        return torch.tensor(np.ascontiguousarray(v).ravel(), dtype=dt, device="cuda")
+
+    S = fsi.Solid(t(X0), torch.tensor(conn.ravel(), dtype=torch.int32, device="cuda"), **W.SOLID_MATERIAL)
+    Ut = t(U)
+    cM, cK, cV = cfg.c_m, cfg.dt, 1.0
+    prm = fsi.make_params(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
+    a = W.advection_field(g, cfg.seed_fields)
+    x = W.random_vector(4 * N, cfg.seed_vectors)
+    v = W.random_vector(3 * M, cfg.seed_vectors + 1)
+    out = {"mesh_nodes": M, "mesh_elements": ne}
+
+    def timed(fn):
+        for _ in range(5):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        vt, yt = t(v, dt), torch.empty(3 * M, dtype=dt, device="cuda")
+        sws = torch.empty(int(fsi._lib.lib().fsi_solid_workspace(ne, fsi.dtype_code(dt))), dtype=torch.uint8,
+                          device="cuda")
+        ms = timed(lambda: fsi.solid_apply(S, Ut, vt, cM, cK, cV, y=yt, ws=sws))
+        fsi.profile_enable(True)
+        for _ in range(reps):
+            fsi.solid_apply(S, Ut, vt, cM, cK, cV, y=yt, ws=sws)
+        torch.cuda.synchronize()
+        kern = {}
+        for kname in ("solid_elem", "solid_gather"):
+            tot, n = fsi.profile_read(kname)
+            kern[kname] = round(tot / n, 6) if n else 0.0
+        fsi.profile_enable(False)
+        tab = fsi.dlm_locate(g, t(X0 + U), dtype=dt, s_max=cfg.s_max)
+        prob = fsi.Problem(g, prm, t(a, dt), tab, None, s=tab.s)
+        xt, jy = t(x, dt), torch.empty(4 * N, dtype=dt, device="cuda")
+        jws = torch.empty(fsi.jacobian_solid_workspace(prob, S), dtype=torch.uint8, device="cuda")
+        jms = timed(lambda: fsi.jacobian_solid_apply(prob, S, Ut, xt, cM, cK, cV, y=jy, ws=jws))
+        elem_ms = kern["solid_elem"]
+        out[name] = {
+            "solid_apply_us": round(ms * 1e3, 2),
+            "kernels_ms": kern,
+            "solid_elem_TFLOPs": round(solid_elem_flops() * ne / (elem_ms * 1e-3) / 1e12, 3) if elem_ms else None,
+            "jacobian_with_solid_us": round(jms * 1e3, 2),
+            "jacobian_with_solid_gdofs": round(4 * N / (jms * 1e-3) / 1e9, 4),
+        }
+    out["solid_elem_flops_per_element"] = solid_elem_flops()
+    return out
+
+
 def build_problem(cfg, dtype, dev):
     import numpy as np
     import torch
@@ -366,6 +452,8 @@ def main(argv=None):
             **time_dlm(fsi, torch, case64),
         },
     }
+    if args.workload != "c1":
+        out["solid_block"] = time_solid(fsi, torch, cfg)
     if not args.no_newton and args.workload == "c2":
         out["newton_step"] = newton_step_probe()
     if not args.no_cpu_baseline:

@@ -13,13 +13,15 @@
 // with F = I + grad_0 U on the reference mesh X0 and 2x2x2 Gauss points on [0,1]^3.
 //
 // Design
-//  * Eight lanes per element, one per Gauss point (a wavefront holds 8 elements).  A
-//    lane forms dX/dxi, F and dF = grad_0 v at its point by a loop over the 8 corners
-//    (corner positions and displacements relative to corner 0, differenced in FP64,
-//    so the FP32 variant keeps its accuracy on small elements far from the origin),
-//    then the stress increment Q = c_K dP - c_V J sigma_v F^{-T} and the inertia
-//    c_M (rho_s0 - rho_f J) v(x_q), and finally its weighted share of the 24 nodal
-//    forces, summed over the 8 lanes by an xor butterfly (the same bits in every lane,
+//  * Eight lanes per element, one per Gauss point (a wavefront holds 8 elements).
+//    Corner positions and displacements are taken relative to corner 0 and differenced
+//    in FP64, so the FP32 variant keeps its accuracy on small elements far from the
+//    origin; in FP32 lane q loads corner q's values and the 8 lanes exchange them by
+//    cross-lane permutes (fewer memory instructions), in FP64 each lane loads all 8
+//    corners (a permute per FP64 value costs two, on a VALU-bound kernel).  A lane forms dX/dxi, F and dF = grad_0 v at its point by a loop over
+//    the 8 corners, then the stress increment Q = c_K dP - c_V J sigma_v F^{-T} and the
+//    inertia c_M (rho_s0 - rho_f J) v(x_q), and finally its weighted share of the 24
+//    nodal forces, summed over the 8 lanes by an xor butterfly (the same bits in every lane,
 //    independent of scheduling).  Lane c stores corner c's 3 sums.
 //  * Element -> node: a node-parallel gather sums the corner slots of the elements
 //    around each node in ascending order (CSR built once per mesh), so the result
@@ -112,18 +114,51 @@ __global__ __launch_bounds__(256) void solid_elem_k(int64_t ne, int64_t m, const
     const int64_t e = valid ? (gid >> 3) : ne - 1;
     const int q = (int)(gid & 7);
     const int lane0 = (int)(threadIdx.x & 63) & ~7;
+    // FP32: lane q loads corner q's position, displacement and v (relative to corner 0, in
+    // FP64) and the element's 8 lanes exchange them by cross-lane permutes.  FP64 (two
+    // permutes per value on a VALU-bound kernel): every lane loads the corners itself.
+    constexpr bool XCH = sizeof(T) == 4;
     const int32_t mine = conn[e * 8 + q];
+    T dxm[3], dum[3], vm[3];
     int32_t nd[8];
+    double xr[3], ur[3];
+    if constexpr (XCH) {
+        double xm[3], um[3];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) nd[c] = __shfl(mine, lane0 + c, 64);
+        for (int d = 0; d < 3; ++d) {
+            xm[d] = X0[d * m + mine];
+            um[d] = U[d * m + mine];
+            vm[d] = v[d * m + mine];
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            dxm[d] = (T)(xm[d] - __shfl(xm[d], lane0, 64));
+            dum[d] = (T)(um[d] - __shfl(um[d], lane0, 64));
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) nd[c] = __shfl(mine, lane0 + c, 64);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            xr[d] = X0[d * m + nd[0]];
+            ur[d] = U[d * m + nd[0]];
+        }
+    }
+    // corner c's position / displacement relative to corner 0, and its v
+    auto dx_at = [&](int c, int i) -> T {
+        if constexpr (XCH) return __shfl(dxm[i], lane0 + c, 64);
+        else return (T)(X0[i * m + nd[c]] - xr[i]);
+    };
+    auto du_at = [&](int c, int i) -> T {
+        if constexpr (XCH) return __shfl(dum[i], lane0 + c, 64);
+        else return (T)(U[i * m + nd[c]] - ur[i]);
+    };
+    auto v_at = [&](int c, int i) -> T {
+        if constexpr (XCH) return __shfl(vm[i], lane0 + c, 64);
+        else return v[i * m + nd[c]];
+    };
 
     const T xi[3] = {T((q & 1) ? SQ1 : SQ0), T((q & 2) ? SQ1 : SQ0), T((q & 4) ? SQ1 : SQ0)};
-    double xr[3], ur[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        xr[d] = X0[d * m + nd[0]];
-        ur[d] = U[d * m + nd[0]];
-    }
     // dX/dxi at the point
     T J0[3][3] = {};
 #pragma unroll
@@ -132,7 +167,7 @@ __global__ __launch_bounds__(256) void solid_elem_k(int64_t ne, int64_t m, const
         corner_shape<T>(c, xi, Nc, dN);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            const T dx = (T)(X0[i * m + nd[c]] - xr[i]);
+            const T dx = dx_at(c, i);
 #pragma unroll
             for (int kk = 0; kk < 3; ++kk) J0[i][kk] += dx * dN[kk];
         }
@@ -158,8 +193,8 @@ __global__ __launch_bounds__(256) void solid_elem_k(int64_t ne, int64_t m, const
         for (int K = 0; K < 3; ++K) G[K] = dN[0] * Ji[0][K] + dN[1] * Ji[1][K] + dN[2] * Ji[2][K];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            const T du = (T)(U[i * m + nd[c]] - ur[i]);
-            const T vc = v[i * m + nd[c]];
+            const T du = du_at(c, i);
+            const T vc = v_at(c, i);
             vq[i] += Nc * vc;
 #pragma unroll
             for (int K = 0; K < 3; ++K) {
