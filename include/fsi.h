@@ -191,13 +191,30 @@ int fsi_dlm_gram(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const void *x
                  const void *kappa, void *gram, void *stream);
 
 /*
+ * Mesh and material of the immersed solid for the hyperelastic solid block
+ * (fsi_solid_setup / fsi_solid_apply below, which state the operator).
+ */
+typedef struct fsi_solid {
+    int64_t n_nodes;            /* M: solid nodes (= the DLM points) */
+    int64_t n_elem;             /* hexahedra */
+    const double *X0;           /* [3][M] reference positions (device) */
+    const int32_t *conn;        /* [n_elem][8] corner node indices (device); corner
+                                   a + 2b + 4c sits at reference (a, b, c) in [0,1]^3 */
+    const int32_t *node_start;  /* [M + 1] from fsi_solid_setup (device) */
+    const int32_t *node_slot;   /* [8 n_elem] from fsi_solid_setup (device) */
+    double C0, kappa_s;         /* eq. inc_neoHk */
+    double rho_s0, rho_f, mu_f; /* solid reference density, fluid density and viscosity */
+} fsi_solid;
+
+/*
  * Everything the Jacobian of the reduced system needs (section 2.4):
  *   J = A_VMS(a, s) + [[B^T diag(kappa) B, 0], [0, 0]],
  * i.e. the paper's dR^{f,m}/dV + C^lambda dR^s/dU (C^lambda)^T block with the
  * solid tangent replaced by the per-point diagonal stand-in kappa_B I.
  * Dirichlet velocity DOFs (dir_mask) have identity rows and zero columns.
  * All arrays are device pointers in precision `dtype`, except the integer
- * point tables.  m = 0 (no solid) is allowed.
+ * point tables.  m = 0 (no solid) is allowed.  With `solid` set, the solid's own
+ * tangent block replaces the per-point stand-in (see the field).
  */
 typedef struct {
     fsi_grid grid;
@@ -217,6 +234,15 @@ typedef struct {
     const void *kappa;         /* T [M] */
     const void *dlm_gram;      /* T [n_occ][nen][nen] from fsi_dlm_gram, or NULL: then the
                                   DLM block is applied point by point (B, kappa, B^T) */
+    const fsi_solid *solid;    /* or NULL.  Set: every apply of this problem (fsi_jacobian_apply,
+                                  fsi_fgmres_solve) uses the solid block B^T K_s B of
+                                  fsi_jacobian_solid_apply (the points must be the solid's
+                                  nodes) instead of B^T diag(kappa) B; kappa and dlm_gram then
+                                  only describe the preconditioners' per-point approximation
+                                  of that block.  fsi_vms_residual and fsi_newton_solve reject
+                                  it (the solid's nonlinear residual is not part of the library). */
+    const double *solid_U;     /* double [3][M] solid displacement when solid != NULL */
+    double solid_cM, solid_cK, solid_cV;  /* coefficients of K_s (fsi_solid_apply) */
 } fsi_problem;
 
 /*
@@ -250,17 +276,7 @@ int fsi_jacobian_apply(const fsi_problem *problem, const void *x, void *y, void 
  *         (backward Euler: 1/dt, dt, 1).
  * Deterministic: element forces are summed per node in ascending element order.
  */
-typedef struct {
-    int64_t n_nodes;            /* M: solid nodes (= the DLM points) */
-    int64_t n_elem;             /* hexahedra */
-    const double *X0;           /* [3][M] reference positions (device) */
-    const int32_t *conn;        /* [n_elem][8] corner node indices (device); corner
-                                   a + 2b + 4c sits at reference (a, b, c) in [0,1]^3 */
-    const int32_t *node_start;  /* [M + 1] from fsi_solid_setup (device) */
-    const int32_t *node_slot;   /* [8 n_elem] from fsi_solid_setup (device) */
-    double C0, kappa_s;         /* eq. inc_neoHk */
-    double rho_s0, rho_f, mu_f; /* solid reference density, fluid density and viscosity */
-} fsi_solid;
+
 
 /*
  * fsi_solid_setup - per-mesh table of the element corners around every node

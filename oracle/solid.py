@@ -216,3 +216,35 @@ def jacobian_apply(grid, prm_f, a, x, cell, xi, X0, conn, U, prm_s, cM, cK, cV, 
     if mask is not None:
         y[:3][m] = x[:3][m]
     return y
+
+
+def dense(X0, conn, U, prm, cM, cK, cV):
+    """K_s assembled densely ([3M][3M], DOF i*M + node, matching [3][M] vectors); small meshes."""
+    M = X0.shape[1]
+    K = np.zeros((3 * M, 3 * M))
+    for e in range(conn.shape[0]):
+        nodes = conn[e]
+        Ke = element_block(X0[:, nodes].T, U[:, nodes].T, prm, cM, cK, cV)
+        idx = np.array([[i * M + n for i in range(3)] for n in nodes]).reshape(24)  # 3A + i -> i*M + node
+        K[np.ix_(idx, idx)] += Ke
+    return K
+
+
+def jacobian_dense(grid, prm_f, a, cell, xi, X0, conn, U, prm_s, cM, cK, cV, s=None, mask=None,
+                   visc_strong=True):
+    """Dense J = A_VMS + [[B^T K_s B, 0], [0, 0]] with Dirichlet rows/columns (small cases)."""
+    from . import dlm, vms
+    N = grid.num_nodes
+    M = X0.shape[1]
+    A = vms.assemble_dense(grid, prm_f, a, s=s, visc_strong=visc_strong)
+    Bs = dlm.dense_B(grid, cell, xi)
+    Ks = dense(X0, conn, U, prm_s, cM, cK, cV)
+    for i in range(3):
+        for j in range(3):
+            A[i * N:(i + 1) * N, j * N:(j + 1) * N] += Bs.T @ Ks[i * M:(i + 1) * M, j * M:(j + 1) * M] @ Bs
+    if mask is not None:
+        m = np.concatenate([np.asarray(mask, dtype=bool).reshape(-1), np.zeros(N, dtype=bool)])
+        A[:, m] = 0.0
+        A[m, :] = 0.0
+        A[m, m] = 1.0
+    return A

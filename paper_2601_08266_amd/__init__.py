@@ -245,7 +245,11 @@ class Problem:
 
     def __init__(self, grid, prm: FsiVmsParams, a: torch.Tensor, tables: Optional[PointTables],
                  kappa: Optional[torch.Tensor], s: Optional[torch.Tensor] = None,
-                 mask: Optional[torch.Tensor] = None, gram: Optional[torch.Tensor] = None):
+                 mask: Optional[torch.Tensor] = None, gram: Optional[torch.Tensor] = None,
+                 solid: Optional["Solid"] = None, solid_U: Optional[torch.Tensor] = None,
+                 solid_coefs=(0.0, 0.0, 0.0)):
+        """With `solid` (and its displacement `solid_U`, coefficients (c_M, c_K, c_V)) every
+        apply uses the solid block B^T K_s B; kappa / gram then only feed the preconditioners."""
         g = grid_from(grid)
         dt = a.dtype
         self.grid, self.prm, self.dtype = g, prm, dt
@@ -271,6 +275,12 @@ class Problem:
             st.n_occ = tables.n_occ
             st.kappa = kappa.data_ptr() if kappa is not None else None
             st.dlm_gram = gram.data_ptr() if gram is not None else None
+        self.solid, self.solid_U = solid, solid_U
+        if solid is not None:
+            _need(solid_U, "solid_U", torch.float64, 3 * solid.m)
+            st.solid = ctypes.addressof(solid.struct)
+            st.solid_U = solid_U.data_ptr()
+            st.solid_cM, st.solid_cK, st.solid_cV = (float(c) for c in solid_coefs)
         self.struct = st
         self.N = num_nodes(g)
 

@@ -42,7 +42,8 @@ class FsiProblem(ctypes.Structure):
                 ("perm", ctypes.c_void_p), ("occ_cell", ctypes.c_void_p),
                 ("occ_start", ctypes.c_void_p), ("occ_index", ctypes.c_void_p),
                 ("n_occ", ctypes.c_int64), ("kappa", ctypes.c_void_p),
-                ("dlm_gram", ctypes.c_void_p)]
+                ("dlm_gram", ctypes.c_void_p), ("solid", ctypes.c_void_p), ("solid_U", ctypes.c_void_p),
+                ("solid_cM", ctypes.c_double), ("solid_cK", ctypes.c_double), ("solid_cV", ctypes.c_double)]
 
 
 class FsiSolid(ctypes.Structure):

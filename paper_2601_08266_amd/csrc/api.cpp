@@ -136,7 +136,7 @@ static int vms_apply_t(const Geo &g, const fsi_vms_params &prm, const T *a, cons
         w += align_up((size_t)3 * dlm->m * sizeof(T));
         rc = launch_dlm_B(g, dt, dlm->m, dlm->cell, dlm->xi, x, mask, us, st);
         if (rc) return rc;
-        rc = launch_solid_apply(*dlm->solid, dt, dlm->solid_U, dlm->solid_c, us, ls, w, st);
+        rc = launch_solid_apply(solid_view(*dlm->solid), dt, dlm->solid_U, dlm->solid_c, us, ls, w, st);
         if (rc) return rc;
         rc = launch_dlm_cell_reduce(g, dt, false, dlm->m, dlm->n_occ, dlm->occ_cell, dlm->occ_start,
                                     dlm->perm, dlm->xi, nullptr, ls, nullptr, csum, st);
@@ -352,6 +352,9 @@ FSI_API int fsi_dlm_gram(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const
     return launch_dlm_gram(g, dtype, m, n_occ, occ_start, perm, xi, kappa, gram, as_stream(stream));
 }
 
+static int check_solid(const fsi_solid *S);
+static DlmView view_of(const fsi_problem *p);
+
 static int check_problem(const fsi_problem *p)
 {
     FSI_CHECK_ARG(p != nullptr, "problem is NULL");
@@ -367,14 +370,35 @@ static int check_problem(const fsi_problem *p)
     if (p->n_occ > 0)
         FSI_CHECK_ARG(p->xi && p->perm && p->occ_cell && p->occ_start && p->occ_index,
                       "point tables must be non-NULL when n_occ > 0");
+    if (p->solid != nullptr) {
+        rc = check_solid(p->solid);
+        if (rc) return rc;
+        FSI_CHECK_ARG(p->m == p->solid->n_nodes, "the problem's points (%lld) must be the solid's nodes (%lld)",
+                      (long long)p->m, (long long)p->solid->n_nodes);
+        FSI_CHECK_ARG(p->m == 0 || p->solid_U != nullptr, "solid_U must be non-NULL");
+        FSI_CHECK_ARG(std::isfinite(p->solid_cM) && std::isfinite(p->solid_cK) && std::isfinite(p->solid_cV),
+                      "solid coefficients must be finite");
+        if (p->n_occ > 0) FSI_CHECK_ARG(p->cell != nullptr, "point cells must be non-NULL with a solid");
+    }
     return FSI_OK;
+}
+
+// workspace of one Jacobian apply of problem p (with solid S in place of p->solid if given)
+static size_t problem_ws(const fsi_problem *p, const fsi_solid *S = nullptr)
+{
+    const Geo g = make_geo(p->grid);
+    if (S == nullptr) S = p->solid;
+    size_t b = vms_workspace_bytes(g, p->dtype) + dlm_csum_bytes(g, p->n_occ, p->dtype);
+    if (S != nullptr)
+        b += 2 * align_up((size_t)3 * p->m * (p->dtype == FSI_F64 ? 8 : 4)) +
+             solid_workspace_bytes(S->n_elem, p->dtype);
+    return b;
 }
 
 FSI_API size_t fsi_jacobian_workspace(const fsi_problem *p)
 {
     if (check_problem(p) != FSI_OK) return 0;
-    const Geo g = make_geo(p->grid);
-    return vms_workspace_bytes(g, p->dtype) + dlm_csum_bytes(g, p->n_occ, p->dtype);
+    return problem_ws(p);
 }
 
 FSI_API int fsi_jacobian_apply(const fsi_problem *p, const void *x, void *y, void *ws,
@@ -386,13 +410,12 @@ FSI_API int fsi_jacobian_apply(const fsi_problem *p, const void *x, void *y, voi
     FSI_CHECK_ARG(x && y, "x and y must be non-NULL");
     FSI_CHECK_ARG(x != y, "x and y must not alias");
     const Geo g = make_geo(p->grid);
-    const size_t need = vms_workspace_bytes(g, p->dtype) + dlm_csum_bytes(g, p->n_occ, p->dtype);
+    const size_t need = problem_ws(p);
     if (ws == nullptr || ws_bytes < need) {
         set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
         return FSI_ERR_WORKSPACE;
     }
-    DlmView v{p->m,     p->cell,  p->xi,        p->perm,  p->occ_cell, p->occ_start,
-              p->n_occ, p->occ_index, p->kappa, p->dlm_gram};
+    const DlmView v = view_of(p);
     return launch_vms_apply(g, p->prm, p->dtype, p->a, p->s, p->dir_mask, x, y,
                             p->n_occ > 0 ? &v : nullptr, ws, ws_bytes, as_stream(stream));
 }
@@ -410,12 +433,6 @@ static int check_solid(const fsi_solid *S)
                       std::isfinite(S->rho_f) && std::isfinite(S->mu_f),
                   "solid material parameters must be finite");
     return FSI_OK;
-}
-
-static SolidView solid_view(const fsi_solid *S)
-{
-    return SolidView{S->n_nodes,    S->n_elem, S->X0,     S->conn,  S->node_start, S->node_slot,
-                     S->C0,         S->kappa_s, S->rho_s0, S->rho_f, S->mu_f};
 }
 
 FSI_API int fsi_solid_setup(int64_t n_nodes, int64_t n_elem, const int32_t *conn, int32_t *node_start,
@@ -449,16 +466,10 @@ FSI_API int fsi_solid_apply(const fsi_solid *S, fsi_dtype dtype, const double *U
         set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
         return FSI_ERR_WORKSPACE;
     }
-    return launch_solid_apply(solid_view(S), dtype, U, SolidCoefs{cM, cK, cV}, v, y, ws, as_stream(stream));
+    return launch_solid_apply(solid_view(*S), dtype, U, SolidCoefs{cM, cK, cV}, v, y, ws, as_stream(stream));
 }
 
-static size_t jacobian_solid_bytes(const fsi_problem *p, const fsi_solid *S)
-{
-    const Geo g = make_geo(p->grid);
-    const size_t es = p->dtype == FSI_F64 ? 8 : 4;
-    return vms_workspace_bytes(g, p->dtype) + dlm_csum_bytes(g, p->n_occ, p->dtype) +
-           2 * align_up((size_t)3 * p->m * es) + solid_workspace_bytes(S->n_elem, p->dtype);
-}
+static size_t jacobian_solid_bytes(const fsi_problem *p, const fsi_solid *S) { return problem_ws(p, S); }
 
 FSI_API size_t fsi_jacobian_solid_workspace(const fsi_problem *p, const fsi_solid *S)
 {
@@ -488,10 +499,9 @@ FSI_API int fsi_jacobian_solid_apply(const fsi_problem *p, const fsi_solid *S, c
         set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
         return FSI_ERR_WORKSPACE;
     }
-    const SolidView sv = solid_view(S);
     DlmView v{p->m,     p->cell,      p->xi,   p->perm, p->occ_cell, p->occ_start,
               p->n_occ, p->occ_index, nullptr, nullptr};
-    v.solid = &sv;
+    v.solid = S;
     v.solid_U = U;
     v.solid_c = SolidCoefs{cM, cK, cV};
     return launch_vms_apply(make_geo(p->grid), p->prm, p->dtype, p->a, p->s, p->dir_mask, x, y,
@@ -500,8 +510,14 @@ FSI_API int fsi_jacobian_solid_apply(const fsi_problem *p, const fsi_solid *S, c
 
 static DlmView view_of(const fsi_problem *p)
 {
-    return DlmView{p->m,     p->cell,      p->xi,    p->perm,     p->occ_cell, p->occ_start,
-                   p->n_occ, p->occ_index, p->kappa, p->dlm_gram};
+    DlmView v{p->m,     p->cell,      p->xi,    p->perm,     p->occ_cell, p->occ_start,
+              p->n_occ, p->occ_index, p->kappa, p->dlm_gram};
+    if (p->solid != nullptr) {
+        v.solid = p->solid;
+        v.solid_U = p->solid_U;
+        v.solid_c = SolidCoefs{p->solid_cM, p->solid_cK, p->solid_cV};
+    }
+    return v;
 }
 
 FSI_API int fsi_vms_residual(const fsi_problem *p, const void *f, const void *lamg, const void *gD,
@@ -522,6 +538,10 @@ FSI_API int fsi_vms_residual(const fsi_problem *p, const void *f, const void *la
     FSI_CHECK_ARG(p->dir_mask == nullptr || gD != nullptr, "gD required with a Dirichlet mask");
     if (p->n_occ > 0 && p->dlm_gram == nullptr) {
         set_error("the residual needs the per-cell DLM blocks (fsi_dlm_gram) when n_occ > 0");
+        return FSI_ERR_UNSUPPORTED;
+    }
+    if (p->solid != nullptr) {
+        set_error("the residual of a problem with a solid block is not part of the library");
         return FSI_ERR_UNSUPPORTED;
     }
     const Geo g = make_geo(p->grid);
@@ -603,11 +623,7 @@ static int check_solve(const fsi_problem *J64, const fsi_problem *J32, const fsi
     return FSI_OK;
 }
 
-static size_t jac_ws(const fsi_problem *p)
-{
-    const Geo g = make_geo(p->grid);
-    return vms_workspace_bytes(g, p->dtype) + dlm_csum_bytes(g, p->n_occ, p->dtype);
-}
+static size_t jac_ws(const fsi_problem *p) { return problem_ws(p); }
 
 FSI_API size_t fsi_fgmres_workspace(const fsi_problem *J64, const fsi_problem *J32,
                                     const fsi_solve_opts *o)
@@ -771,6 +787,10 @@ static int check_newton(const fsi_problem *P64, const fsi_problem *P32, const fs
         set_error("Newton steps are implemented for Q1 grids");
         return FSI_ERR_UNSUPPORTED;
     }
+    if (P64->solid != nullptr || (P32 != nullptr && P32->solid != nullptr)) {
+        set_error("Newton steps with a solid block need the solid's residual, which is not part of the library");
+        return FSI_ERR_UNSUPPORTED;
+    }
     if (P64->n_occ > 0) FSI_CHECK_ARG(P64->dlm_gram != nullptr, "P64->dlm_gram required");
     if (o->inner == FSI_F32) {
         FSI_CHECK_ARG(P32 != nullptr, "inner FP32 needs the FP32 problem");
@@ -814,6 +834,10 @@ FSI_API int fsi_tangent_apply(const fsi_problem *P64, const double *f, const dou
     FSI_CHECK_ARG(dtype_ok(dtype), "bad dtype");
     if (P64->grid.order != 1) {
         set_error("the residual kernel is implemented for Q1 grids");
+        return FSI_ERR_UNSUPPORTED;
+    }
+    if (P64->solid != nullptr) {
+        set_error("the residual of a problem with a solid block is not part of the library");
         return FSI_ERR_UNSUPPORTED;
     }
     FSI_CHECK_ARG(f && x && R0 && v && y && v != y, "f, x, R0, v, y must be non-NULL and v != y");

@@ -87,7 +87,7 @@ struct DlmView {
     const void *gram;           // [n_occ][nen][nen] or nullptr
     // hyperelastic solid block in place of the per-point kappa (kappa and gram unused):
     // the points are the solid's nodes, y += B^T (c_M M + c_K K(U) - c_V K_v(U)) B x_u
-    const SolidView *solid = nullptr;
+    const fsi_solid *solid = nullptr;
     const double *solid_U = nullptr;
     SolidCoefs solid_c{};
 };

@@ -20,6 +20,12 @@ struct SolidCoefs {
     double cM, cK, cV;
 };
 
+inline SolidView solid_view(const fsi_solid &S)
+{
+    return SolidView{S.n_nodes, S.n_elem,  S.X0,     S.conn,  S.node_start, S.node_slot,
+                     S.C0,      S.kappa_s, S.rho_s0, S.rho_f, S.mu_f};
+}
+
 size_t solid_workspace_bytes(int64_t n_elem, fsi_dtype dt);
 int solid_build_csr(int64_t n_nodes, int64_t n_elem, const int32_t *conn, int32_t *node_start,
                     int32_t *node_slot, hipStream_t st);

@@ -252,3 +252,24 @@ def test_mass_total_is_solid_minus_displaced_fluid():
         tv = t.reshape(24)
         expect = PRM["rho_s0"] * V0 - PRM["rho_f"] * Vt
         assert tv @ M @ tv == pytest.approx(expect, rel=1e-12)
+
+
+def test_dense_assemblies_match_the_applies():
+    from oracle import dlm, vms
+    X, conn = W.plate_solid_mesh(3, 4)
+    U = W.solid_displacement(X, 5)
+    M = X.shape[1]
+    v = np.random.default_rng(1).standard_normal((3, M))
+    K = solid.dense(X, conn, U, PRM, 1e3, 1e-3, 1.0)
+    y = solid.apply(X, conn, U, v, PRM, 1e3, 1e-3, 1.0)
+    assert np.abs(K @ v.reshape(-1) - y.reshape(-1)).max() <= 1e-12 * np.abs(y).max()
+    g = W.Grid((4, 4, 4), 1)
+    N = g.num_nodes
+    cell, xi = dlm.locate(g, X + U)
+    a = W.advection_field(g, 1001)
+    prm_f = vms.params_array(0.01, 1000.0, 1e-3)
+    mask = W.channel_dirichlet_mask(g)
+    x = np.random.default_rng(2).standard_normal(4 * N)
+    J = solid.jacobian_dense(g, prm_f, a, cell, xi, X, conn, U, PRM, 1e3, 1e-3, 1.0, mask=mask)
+    yj = solid.jacobian_apply(g, prm_f, a, x, cell, xi, X, conn, U, PRM, 1e3, 1e-3, 1.0, mask=mask)
+    assert np.abs(J @ x - yj.reshape(-1)).max() <= 1e-12 * np.abs(yj).max()
