@@ -353,7 +353,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-newton", action="store_true", help="skip the short Newton-step probe")
-    ap.add_argument("--experiment", default=None, choices=["warmstart", "c5", "netspeed", "c3", "probe"],
+    ap.add_argument("--experiment", default=None, choices=["warmstart", "c5", "netspeed", "c3", "probe", "solid"],
                     help="run a Newton-step experiment instead of the apply benchmark")
     ap.add_argument("--exp-steps", type=int, default=200)
     ap.add_argument("--exp-modes", default=None,
@@ -498,6 +498,12 @@ def run_experiment(args):
                           **ex.solve_c3(max_iters=args.exp_steps, modes=tuple(modes or ("mixed", "f64")),
                                         precond=args.exp_precond, restart=args.exp_restart,
                                         vel_steps=args.exp_vel_steps)}))
+        return 0
+    if args.experiment == "solid":
+        print(json.dumps({"experiment": "solid_solve",
+                          **ex.solid_solve(max_iters=args.exp_steps, precond=args.exp_precond,
+                                           restart=args.exp_restart, vel_steps=args.exp_vel_steps,
+                                           workload=args.workload)}))
         return 0
     if args.experiment == "probe":
         print(json.dumps({"experiment": "newton_probe",
