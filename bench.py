@@ -35,7 +35,7 @@ PEAK_HBM_GBS = 8000.0
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads
 # for a plain 512 MiB device copy (FETCH_SIZE reads half the copied bytes, WRITE_SIZE all).
 # Valid only for the kernel sources it was taken on: the hash covers them.
-CELL_TRAFFIC = {"sources_sha256_16": "7787a1935b5a88b4", "fetch_kib": 12860.9, "write_kib": 12986.7,
+CELL_TRAFFIC = {"sources_sha256_16": "94afbe3dcf8c95f4", "fetch_kib": 12861.3, "write_kib": 12985.6,
                 "fetch_scale": 524288.0 / 262159.8, "write_scale": 1.0}
 CELL_SOURCES = ("vms_q1.hip", "kernels.hpp", "common.hpp")
 
@@ -353,6 +353,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-newton", action="store_true", help="skip the short Newton-step probe")
+    ap.add_argument("--no-solid", action="store_true", help="skip the solid-block timings")
     ap.add_argument("--experiment", default=None, choices=["warmstart", "c5", "netspeed", "c3", "probe", "solid"],
                     help="run a Newton-step experiment instead of the apply benchmark")
     ap.add_argument("--exp-steps", type=int, default=200)
@@ -452,7 +453,7 @@ def main(argv=None):
             **time_dlm(fsi, torch, case64),
         },
     }
-    if args.workload != "c1":
+    if args.workload != "c1" and not args.no_solid:
         out["solid_block"] = time_solid(fsi, torch, cfg)
     if not args.no_newton and args.workload == "c2":
         out["newton_step"] = newton_step_probe()

@@ -309,7 +309,9 @@ __device__ __forceinline__ void lagrange(T t, T N[P + 1])
     }
 }
 
-template <typename T, int P>
+// MASKED: Dirichlet velocity entries of u (mask bits) read as zero; the unmasked variant keeps
+// its loads unconditional, so they issue as one batch
+template <typename T, int P, bool MASKED>
 __global__ __launch_bounds__(256) void dlm_B_kernel(Geo g, int64_t m, const int32_t *__restrict__ cell,
                                                     const T *__restrict__ xi, const T *__restrict__ u,
                                                     const uint32_t *__restrict__ mask,
@@ -336,8 +338,13 @@ __global__ __launch_bounds__(256) void dlm_B_kernel(Geo g, int64_t m, const int3
                                          (int64_t)g.nn[0] * ((P * cy + ay) + (int64_t)g.nn[1] * (P * cz + az));
                     const T w = Nx[ax] * Ny[ay] * Nz[az];
 #pragma unroll
-                    for (int f = 0; f < 3; ++f)
-                        acc[f] += w * (mask_bit(mask, f * g.N + node) ? T(0) : u[f * g.N + node]);
+                    for (int f = 0; f < 3; ++f) {
+                        const T uf = u[f * g.N + node];
+                        if constexpr (MASKED)
+                            acc[f] += ((mask[(f * g.N + node) >> 5] >> ((f * g.N + node) & 31)) & 1u) ? T(0) : w * uf;
+                        else
+                            acc[f] += w * uf;
+                    }
                 }
     }
 #pragma unroll
@@ -673,11 +680,17 @@ static int launch_B_t(const Geo &g, int64_t m, const int32_t *cell, const T *xi,
                       const uint32_t *mask, T *Bu, hipStream_t st)
 {
     if (m == 0) return FSI_OK;
-    ProfileScope prof("dlm_B", st);
-    if (g.p == 1)
-        hipLaunchKernelGGL((dlm_B_kernel<T, 1>), dim3(nblk(m)), dim3(256), 0, st, g, m, cell, xi, u, mask, Bu);
-    else
-        hipLaunchKernelGGL((dlm_B_kernel<T, 2>), dim3(nblk(m)), dim3(256), 0, st, g, m, cell, xi, u, mask, Bu);
+    if (g.p == 1) {
+        if (mask != nullptr)
+            hipLaunchKernelGGL((dlm_B_kernel<T, 1, true>), dim3(nblk(m)), dim3(256), 0, st, g, m, cell, xi, u, mask, Bu);
+        else
+            hipLaunchKernelGGL((dlm_B_kernel<T, 1, false>), dim3(nblk(m)), dim3(256), 0, st, g, m, cell, xi, u, mask, Bu);
+    } else {
+        if (mask != nullptr)
+            hipLaunchKernelGGL((dlm_B_kernel<T, 2, true>), dim3(nblk(m)), dim3(256), 0, st, g, m, cell, xi, u, mask, Bu);
+        else
+            hipLaunchKernelGGL((dlm_B_kernel<T, 2, false>), dim3(nblk(m)), dim3(256), 0, st, g, m, cell, xi, u, mask, Bu);
+    }
     FSI_LAUNCH_CHECK();
     return FSI_OK;
 }
