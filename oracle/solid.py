@@ -248,3 +248,81 @@ def jacobian_dense(grid, prm_f, a, cell, xi, X0, conn, U, prm_s, cM, cK, cV, s=N
         A[m, :] = 0.0
         A[m, m] = 1.0
     return A
+
+
+# ---- the solid's nonlinear residual and one coupled time step ----
+#
+# Solid residual at the nodes (eq. solid_weak_form tested with each nodal shape function; no
+# body force or traction on the solid), with the readings above:
+#   R^s(U, V, A) = M_rho(U) A + f_int(U) - K_v(U) V.
+# Backward Euler in velocity form, the solid velocity being the fluid's at the solid nodes
+# (eq. nodal_solid_velo): V = B u, U = U_n + dt V, A = (V - V_n) / dt.  The fluid momentum
+# residual gains C^lambda R^s = B^T R^s (the multiplier eliminated by eq. nodal_lagrange,
+# lambda = -R^s), and after the step the solid moves by dt V (Delta U = (C^lambda)^T Delta V
+# integrated).  Its derivative with respect to u is B^T (c_M M + c_K K - c_V K_v) B with
+# (1/dt, dt, 1) up to the geometric derivatives of M_rho and K_v, which the Newton matrix drops.
+
+
+def residual(X0, conn, U, V, A, prm):
+    """R^s(U, V, A) at the solid nodes ([3][M] arrays)."""
+    X0 = np.asarray(X0, dtype=np.float64)
+    U = np.asarray(U, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    A = np.asarray(A, dtype=np.float64)
+    R = np.zeros_like(U)
+    for e in range(conn.shape[0]):
+        nodes = conn[e]
+        Xe, Ue = X0[:, nodes].T, U[:, nodes].T
+        M, _, Kv = element_matrices(Xe, Ue, prm)
+        re = M @ A[:, nodes].T.reshape(24) - Kv @ V[:, nodes].T.reshape(24) + element_force(Xe, Ue, prm).reshape(24)
+        np.add.at(R.T, nodes, re.reshape(8, 3))
+    return R
+
+
+def step_state(grid, cell, xi, x, U_n, V_n, dt):
+    """(V, U, A) of the solid for the fluid state x: V = B u, U = U_n + dt V, A = (V - V_n)/dt."""
+    from . import dlm
+    N = grid.num_nodes
+    V = dlm.apply_B(grid, cell, xi, np.asarray(x, dtype=np.float64).reshape(4, N)[:3])
+    return V, U_n + dt * V, (V - V_n) / dt
+
+
+def step_residual(grid, prm_f, x, f, cell, xi, X0, conn, U_n, V_n, dt, prm_s, s=None, mask=None, gD=None,
+                  visc_strong=True):
+    """R(x) = R_fluid(x; f) + [B^T R^s(U_n + dt B u, B u, (B u - V_n)/dt); 0], Dirichlet rows u - gD
+    (R_fluid: the VMS step residual with nodal source f = c_m u_old + body force)."""
+    from . import dlm, vms
+    N = grid.num_nodes
+    x = np.asarray(x, dtype=np.float64).reshape(4, N)
+    R = vms.residual_fluid(grid, prm_f, x, np.asarray(f, dtype=np.float64).reshape(3, N), s=s,
+                           visc_strong=visc_strong)
+    V, U, A = step_state(grid, cell, xi, x, U_n, V_n, dt)
+    R[:3] += dlm.apply_BT(grid, cell, xi, residual(X0, conn, U, V, A, prm_s))
+    if mask is not None:
+        m = np.asarray(mask, dtype=bool).reshape(3, N)
+        gd = np.zeros((3, N)) if gD is None else np.asarray(gD).reshape(3, N)
+        R[:3][m] = x[:3][m] - gd[m]
+    return R
+
+
+def newton_step(grid, prm_f, x0, f, cell, xi, X0, conn, U_n, V_n, dt, prm_s, s=None, mask=None, gD=None,
+                tol_abs=None, rel=1e-8, max_newton=30, visc_strong=True):
+    """Newton on step_residual from x0 with the matrix A(a = u_k) + B^T K_s(U_k) B (dense solves);
+    returns (x, U_{n+1}, V_{n+1}, info)."""
+    N = grid.num_nodes
+    x = np.asarray(x0, dtype=np.float64).reshape(4, N).copy()
+    R = step_residual(grid, prm_f, x, f, cell, xi, X0, conn, U_n, V_n, dt, prm_s, s, mask, gD, visc_strong)
+    hist = [np.linalg.norm(R)]
+    if tol_abs is None:
+        tol_abs = rel * hist[0]
+    for _ in range(max_newton):
+        if hist[-1] <= tol_abs:
+            break
+        _, U, _ = step_state(grid, cell, xi, x, U_n, V_n, dt)
+        J = jacobian_dense(grid, prm_f, x[:3].copy(), cell, xi, X0, conn, U, prm_s, 1.0 / dt, dt, 1.0, s=s,
+                           mask=mask, visc_strong=visc_strong)
+        x = x + np.linalg.solve(J, -R.ravel()).reshape(4, N)
+        R = step_residual(grid, prm_f, x, f, cell, xi, X0, conn, U_n, V_n, dt, prm_s, s, mask, gD, visc_strong)
+        hist.append(np.linalg.norm(R))
+    V, U, _ = step_state(grid, cell, xi, x, U_n, V_n, dt)
+    return x, U, V, {"history": hist, "tol_abs": tol_abs, "converged": hist[-1] <= tol_abs}
