@@ -26,7 +26,7 @@ __all__ = [
     "profile_read", "vms_residual", "bjacobi_setup", "bjacobi_apply", "fgmres_solve",
     "schur_size", "schur_info", "schur_setup", "schur_apply", "PRECONDS", "tangent_apply",
     "newton_solve", "solve_opts", "newton_opts", "Solid", "solid_apply", "jacobian_solid_workspace",
-    "jacobian_solid_apply",
+    "jacobian_solid_apply", "solid_residual", "solid_step_residual", "newton_solid_solve",
 ]
 
 _TORCH_OF = {FSI_F64: torch.float64, FSI_F32: torch.float32}
@@ -564,6 +564,63 @@ def newton_solve(P64: Problem, f: torch.Tensor, x: torch.Tensor, opts: FsiNewton
                                   ws.numel(), _stream(stream))
     if check:
         L.check("fsi_newton_solve", rc)
+    return rc, st
+
+
+def solid_residual(solid: "Solid", U: torch.Tensor, V: torch.Tensor, A: torch.Tensor,
+                   R: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None):
+    """R^s = M_rho(U) A + f_int(U) - K_v(U) V at the solid nodes (fsi_solid_residual, FP64)."""
+    for t, n in ((U, "U"), (V, "V"), (A, "A")):
+        _need(t, n, torch.float64, 3 * solid.m)
+    if R is None:
+        R = torch.empty_like(U)
+    _need(R, "R", torch.float64, 3 * solid.m)
+    ws = _workspace(int(L.lib().fsi_solid_workspace(solid.n_elem, FSI_F64)), U.device, ws)
+    L.check("fsi_solid_residual", L.lib().fsi_solid_residual(
+        ctypes.byref(solid.struct), _ptr(U), _ptr(V), _ptr(A), _ptr(R), _ptr(ws), ws.numel(), _stream(stream)))
+    return R
+
+
+def solid_step_residual(problem: Problem, solid: "Solid", U_n: torch.Tensor, V_n: torch.Tensor, dt: float,
+                        f: torch.Tensor, x: torch.Tensor, gD=None, R=None, U=None, V=None, ws=None, stream=None):
+    """Step residual with the solid (fsi_solid_step_residual); returns (R, U, V)."""
+    N, M = problem.N, solid.m
+    _need(x, "x", torch.float64, 4 * N)
+    _need(f, "f", torch.float64, 3 * N)
+    R = torch.empty_like(x) if R is None else R
+    U = torch.empty_like(U_n) if U is None else U
+    V = torch.empty_like(V_n) if V is None else V
+    for t, n in ((U_n, "U_n"), (V_n, "V_n"), (U, "U"), (V, "V")):
+        _need(t, n, torch.float64, 3 * M)
+    ws = _workspace(int(L.lib().fsi_solid_step_workspace(ctypes.byref(problem.struct), ctypes.byref(solid.struct))),
+                    x.device, ws)
+    L.check("fsi_solid_step_residual", L.lib().fsi_solid_step_residual(
+        ctypes.byref(problem.struct), ctypes.byref(solid.struct), _ptr(U_n), _ptr(V_n), float(dt), _ptr(f),
+        _ptr(gD), _ptr(x), _ptr(R), _ptr(U), _ptr(V), _ptr(ws), ws.numel(), _stream(stream)))
+    return R, U, V
+
+
+def newton_solid_solve(P64: Problem, solid: "Solid", U_n: torch.Tensor, V_n: torch.Tensor, dt: float,
+                       f: torch.Tensor, x: torch.Tensor, U: torch.Tensor, V: torch.Tensor, opts: FsiNewtonOpts,
+                       P32: Optional[Problem] = None, gD=None, ws: Optional[torch.Tensor] = None, stream=None,
+                       check: bool = True):
+    """One backward-Euler step with the solid (fsi_newton_solid_solve); x, U, V updated in place.
+    Returns (status, stats)."""
+    _need(x, "x", torch.float64, 4 * P64.N)
+    _need(f, "f", torch.float64, 3 * P64.N)
+    p32 = ctypes.byref(P32.struct) if P32 is not None else None
+    nbytes = int(L.lib().fsi_newton_solid_workspace(ctypes.byref(P64.struct), p32, ctypes.byref(solid.struct),
+                                                     ctypes.byref(opts)))
+    if nbytes == 0:
+        raise ValueError("invalid Newton arguments: " + L.lib().fsi_last_error().decode())
+    ws = _workspace(nbytes, x.device, ws)
+    st = FsiNewtonStats()
+    rc = L.lib().fsi_newton_solid_solve(ctypes.byref(P64.struct), p32, ctypes.byref(solid.struct), _ptr(U_n),
+                                        _ptr(V_n), float(dt), _ptr(f), _ptr(gD), _ptr(x), _ptr(U), _ptr(V),
+                                        ctypes.byref(opts), ctypes.byref(st), _ptr(ws), ws.numel(),
+                                        _stream(stream))
+    if check:
+        L.check("fsi_newton_solid_solve", rc)
     return rc, st
 
 

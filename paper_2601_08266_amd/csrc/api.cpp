@@ -508,6 +508,112 @@ FSI_API int fsi_jacobian_solid_apply(const fsi_problem *p, const fsi_solid *S, c
                             p->n_occ > 0 ? &v : nullptr, ws, ws_bytes, as_stream(stream));
 }
 
+// ---- the solid's nonlinear residual and the coupled step ----
+
+FSI_API int fsi_solid_residual(const fsi_solid *S, const double *U, const double *V, const double *A, double *R,
+                               void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_solid(S);
+    if (rc) return rc;
+    FSI_CHECK_ARG(S->n_nodes == 0 || (U && V && A && R), "U, V, A and R must be non-NULL");
+    FSI_CHECK_ARG(R != U && R != V && R != A, "R must not alias the inputs");
+    const size_t need = solid_workspace_bytes(S->n_elem, FSI_F64);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+        return FSI_ERR_WORKSPACE;
+    }
+    return launch_solid_residual(solid_view(*S), U, V, A, R, ws, as_stream(stream));
+}
+
+int fsi::solid_step_residual(const Geo &g, const fsi_problem &P, const SolidStep &ss, const double *f,
+                             const double *gD, const double *x, double *R, void *ws, hipStream_t st)
+{
+    // V = B u (the solid moves with the fluid), U = U_n + dt V, A = (V - V_n)/dt, R^s at the
+    // solid nodes, its B^T corner sums, then the fluid step residual whose node gather adds them
+    // before the Dirichlet rows (u - gD)
+    const int64_t m = P.m;
+    const VmsConst<double> k = make_vms_const<double>(g, P.prm, P.s != nullptr);
+    const BrickLayout bl = brick_layout(g);
+    char *w = reinterpret_cast<char *>(ws);
+    double *part = reinterpret_cast<double *>(w);
+    w += vms_workspace_bytes(g, FSI_F64);
+    double *csum = reinterpret_cast<double *>(w);
+    w += dlm_csum_bytes(g, P.n_occ, FSI_F64);
+    double *A = reinterpret_cast<double *>(w);
+    w += align_up((size_t)3 * m * sizeof(double));
+    double *Rs = reinterpret_cast<double *>(w);
+    w += align_up((size_t)3 * m * sizeof(double));
+    int rc = FSI_OK;
+    const bool solid_on = P.n_occ > 0 && m > 0;
+    if (m > 0) {
+        rc = launch_dlm_B(g, FSI_F64, m, P.cell, P.xi, x, nullptr, ss.V, st);
+        if (rc) return rc;
+        rc = launch_solid_state(m, ss.dt, ss.U_n, ss.V_n, ss.V, ss.U, A, st);
+        if (rc) return rc;
+    }
+    if (solid_on) {
+        rc = launch_solid_residual(solid_view(*ss.S), ss.U, ss.V, A, Rs, w, st);
+        if (rc) return rc;
+        rc = launch_dlm_cell_reduce(g, FSI_F64, false, m, P.n_occ, P.occ_cell, P.occ_start, P.perm, P.xi, nullptr,
+                                    Rs, nullptr, csum, st);
+        if (rc) return rc;
+    }
+    rc = launch_q1_cells<double>(g, k, (const double *)x, f, (const double *)P.s, P.dir_mask, nullptr, nullptr,
+                                 part, bl, st, true);
+    if (rc) return rc;
+    GatherOpts<double> o;
+    o.csum = solid_on ? csum : nullptr;
+    o.occ_index = solid_on ? P.occ_index : nullptr;
+    o.gD = gD;
+    return launch_gather<double, 1, Q1_BX, Q1_BY, Q1_BZ>(g, part, bl, x, P.dir_mask, R, o, st);
+}
+
+static int check_solid_step(const fsi_problem *p, const fsi_solid *S, const double *U_n, const double *V_n,
+                            double dt, const double *U, const double *V)
+{
+    int rc = check_problem(p);
+    if (rc) return rc;
+    rc = check_solid(S);
+    if (rc) return rc;
+    FSI_CHECK_ARG(p->dtype == FSI_F64, "the step residual takes the FP64 problem");
+    FSI_CHECK_ARG(p->solid == nullptr, "pass the solid as the argument, not in the problem");
+    FSI_CHECK_ARG(p->m == S->n_nodes, "the problem's points (%lld) must be the solid's nodes (%lld)",
+                  (long long)p->m, (long long)S->n_nodes);
+    FSI_CHECK_ARG(std::isfinite(dt) && dt > 0.0, "dt must be finite and > 0");
+    FSI_CHECK_ARG(p->m == 0 || (U_n && V_n && U && V && p->cell && p->xi), "solid state arrays must be non-NULL");
+    FSI_CHECK_ARG(U != U_n && V != V_n && U != V, "U, V must be distinct from U_n, V_n and each other");
+    if (p->grid.order != 1) {
+        set_error("the residual kernel is implemented for Q1 grids");
+        return FSI_ERR_UNSUPPORTED;
+    }
+    return FSI_OK;
+}
+
+FSI_API size_t fsi_solid_step_workspace(const fsi_problem *p, const fsi_solid *S)
+{
+    if (check_problem(p) != FSI_OK || check_solid(S) != FSI_OK) return 0;
+    return problem_ws(p, S);
+}
+
+FSI_API int fsi_solid_step_residual(const fsi_problem *p, const fsi_solid *S, const double *U_n, const double *V_n,
+                                    double dt, const double *f, const double *gD, const double *x, double *R,
+                                    double *U, double *V, void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_solid_step(p, S, U_n, V_n, dt, U, V);
+    if (rc) return rc;
+    FSI_CHECK_ARG(f && x && R && x != R, "f, x, R must be non-NULL and x != R");
+    FSI_CHECK_ARG(p->dir_mask == nullptr || gD != nullptr, "gD required with a Dirichlet mask");
+    const size_t need = problem_ws(p, S);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+        return FSI_ERR_WORKSPACE;
+    }
+    const SolidStep ss{S, U_n, V_n, dt, U, V};
+    return solid_step_residual(make_geo(p->grid), *p, ss, f, gD, x, R, ws, as_stream(stream));
+}
+
 static DlmView view_of(const fsi_problem *p)
 {
     DlmView v{p->m,     p->cell,      p->xi,    p->perm,     p->occ_cell, p->occ_start,
@@ -885,6 +991,42 @@ FSI_API int fsi_newton_solve(const fsi_problem *P64, const fsi_problem *P32, con
     }
     return newton_solve(g, *P64, o->inner == FSI_F32 ? P32 : nullptr, f, lamg, gD, x, *o, stats, ws, jw,
                         as_stream(stream));
+}
+
+FSI_API size_t fsi_newton_solid_workspace(const fsi_problem *P64, const fsi_problem *P32, const fsi_solid *S,
+                                          const fsi_newton_opts *o)
+{
+    if (check_newton(P64, P32, o) != FSI_OK || check_solid(S) != FSI_OK) return 0;
+    size_t jw = problem_ws(P64, S);
+    if (o->inner == FSI_F32) jw = std::max(jw, problem_ws(P32, S));
+    return newton_workspace_bytes(make_geo(P64->grid), *o, jw);
+}
+
+FSI_API int fsi_newton_solid_solve(const fsi_problem *P64, const fsi_problem *P32, const fsi_solid *S,
+                                   const double *U_n, const double *V_n, double dt, const double *f,
+                                   const double *gD, double *x, double *U, double *V, const fsi_newton_opts *o,
+                                   fsi_newton_stats *stats, void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_newton(P64, P32, o);
+    if (rc) return rc;
+    rc = check_solid_step(P64, S, U_n, V_n, dt, U, V);
+    if (rc) return rc;
+    if (o->inner == FSI_F32) FSI_CHECK_ARG(P32->m == S->n_nodes, "P32's points must be the solid's nodes");
+    FSI_CHECK_ARG(o->tangent == 0, "the full tangent is not available with the solid block");
+    FSI_CHECK_ARG(f && x, "f and x must be non-NULL");
+    FSI_CHECK_ARG(P64->dir_mask == nullptr || gD != nullptr, "gD required with a Dirichlet mask");
+    size_t jw = problem_ws(P64, S);
+    if (o->inner == FSI_F32) jw = std::max(jw, problem_ws(P32, S));
+    const Geo g = make_geo(P64->grid);
+    const size_t need = newton_workspace_bytes(g, *o, jw);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+        return FSI_ERR_WORKSPACE;
+    }
+    const SolidStep ss{S, U_n, V_n, dt, U, V};
+    return newton_solve(g, *P64, o->inner == FSI_F32 ? P32 : nullptr, f, nullptr, gD, x, *o, stats, ws, jw,
+                        as_stream(stream), &ss);
 }
 
 // ---------------------------------------------------------------- warm-start network

@@ -139,7 +139,7 @@ size_t newton_workspace_bytes(const Geo &g, const fsi_newton_opts &o, size_t jws
 
 int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, const double *f,
                  const double *lamg, const double *gD, double *x, const fsi_newton_opts &o,
-                 fsi_newton_stats *stats, void *ws, size_t jws, hipStream_t st)
+                 fsi_newton_stats *stats, void *ws, size_t jws, hipStream_t st, const SolidStep *ss)
 {
     ProfileScope prof("newton_solve", st);
     const auto t0 = std::chrono::steady_clock::now();
@@ -162,11 +162,20 @@ int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, c
 
     fsi_newton_stats S{};
     int rc = FSI_OK;
-    const DlmView v64{P64.m,     P64.cell,      P64.xi,    P64.perm,     P64.occ_cell, P64.occ_start,
-                      P64.n_occ, P64.occ_index, P64.kappa, P64.dlm_gram};
+    DlmView v64{P64.m,     P64.cell,      P64.xi,    P64.perm,     P64.occ_cell, P64.occ_start,
+                P64.n_occ, P64.occ_index, P64.kappa, P64.dlm_gram};
     DlmView v32{};
     if (P32) v32 = DlmView{P32->m,     P32->cell,      P32->xi,    P32->perm,     P32->occ_cell,
                            P32->occ_start, P32->n_occ, P32->occ_index, P32->kappa, P32->dlm_gram};
+    if (ss != nullptr) {
+        // the operator's solid block at the current iterate (U is refreshed by every residual);
+        // kappa and the per-cell blocks stay for the preconditioners
+        for (DlmView *dv : {&v64, &v32}) {
+            dv->solid = ss->S;
+            dv->solid_U = ss->U;
+            dv->solid_c = SolidCoefs{1.0 / ss->dt, ss->dt, 1.0};
+        }
+    }
     double *scratch = reinterpret_cast<double *>(base + L.scratch);
     auto rnorm = [&](double &out) -> int {
         int r = kry_norm(n, R, scratch, scratch + KRY_NB, st);
@@ -177,8 +186,11 @@ int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, c
     };
     for (int it = 0;; ++it) {
         auto tr = std::chrono::steady_clock::now();
-        rc = launch_vms_residual(g, P64.prm, FSI_F64, P64.s, P64.dir_mask, gD, x, f,
-                                 P64.n_occ > 0 ? &v64 : nullptr, lamg, R, kws, st);
+        if (ss != nullptr)
+            rc = solid_step_residual(g, P64, *ss, f, gD, x, R, kws, st);
+        else
+            rc = launch_vms_residual(g, P64.prm, FSI_F64, P64.s, P64.dir_mask, gD, x, f,
+                                     P64.n_occ > 0 ? &v64 : nullptr, lamg, R, kws, st);
         if (rc) break;
         double rn = 0.0;
         rc = rnorm(rn);

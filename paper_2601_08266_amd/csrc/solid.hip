@@ -101,13 +101,17 @@ __device__ __forceinline__ double cbrt_t<double>(double x) { return cbrt(x); }
 template <>
 __device__ __forceinline__ float cbrt_t<float>(float x) { return cbrtf(x); }
 
-template <typename T>
+// RESID = false: the tangent block applied to v.  RESID = true (FP64): the solid's nonlinear
+// residual R^s = M_rho(U) A + f_int(U) - K_v(U) V with v = V and acc = A; the same element walk
+// with P(F) in place of c_K dP, c_V = 1 and the inertia of A instead of c_M v.
+template <typename T, bool RESID>
 __global__ __launch_bounds__(256) void solid_elem_k(int64_t ne, int64_t m, const int32_t *__restrict__ conn,
                                                     const double *__restrict__ X0,
                                                     const double *__restrict__ U,
-                                                    const T *__restrict__ v, SolidK<T> k,
-                                                    T *__restrict__ ef)
+                                                    const T *__restrict__ v, const T *__restrict__ acc,
+                                                    SolidK<T> k, T *__restrict__ ef)
 {
+    static_assert(!RESID || sizeof(T) == 8, "the residual is FP64");
     const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool valid = (gid >> 3) < ne;
     // lanes past the last element repeat it (their sums are not stored)
@@ -183,8 +187,8 @@ __global__ __launch_bounds__(256) void solid_elem_k(int64_t ne, int64_t m, const
 #pragma unroll
             for (int b = 0; b < 3; ++b) Ji[a][b] = C[b][a] * r;
     }
-    // F - I, dF = grad_0 v and v at the point
-    T F[3][3] = {}, dF[3][3] = {}, vq[3] = {};
+    // F - I, dF = grad_0 v and v at the point (and A at the point for the residual)
+    T F[3][3] = {}, dF[3][3] = {}, vq[3] = {}, aq[3] = {};
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         T Nc, dN[3], G[3];
@@ -196,6 +200,7 @@ __global__ __launch_bounds__(256) void solid_elem_k(int64_t ne, int64_t m, const
             const T du = du_at(c, i);
             const T vc = v_at(c, i);
             vq[i] += Nc * vc;
+            if constexpr (RESID) aq[i] += Nc * acc[i * m + nd[c]];
 #pragma unroll
             for (int K = 0; K < 3; ++K) {
                 F[i][K] += du * G[K];
@@ -239,13 +244,14 @@ __global__ __launch_bounds__(256) void solid_elem_k(int64_t ne, int64_t m, const
             for (int K = 0; K < 3; ++K)
                 dFit[i][K] = -(t[i][0] * Fit[0][K] + t[i][1] * Fit[1][K] + t[i][2] * Fit[2][K]);
     }
-    // stress increment of eq. inc_neoHk: isochoric and volumetric parts of dP
+    // stress increment of eq. inc_neoHk: isochoric and volumetric parts of dP (the residual:
+    // P = C0 J^{-2/3} (F - I1/3 F^{-T}) + kap/2 (J^2 - 1) F^{-T})
     const T cb = cbrt_t<T>(J);
     const T a23 = T(1) / (cb * cb);           // J^{-2/3}
     const T J2 = J * J;
-    const T ci = k.cK * k.C0 * a23;
-    const T vol_t = k.cK * k.kap * J2 * tr;
-    const T vol_d = k.cK * T(0.5) * k.kap * (J2 - T(1));
+    const T ci = (RESID ? T(1) : k.cK) * k.C0 * a23;
+    const T vol_t = RESID ? T(0) : k.cK * k.kap * J2 * tr;
+    const T vol_d = (RESID ? T(1) : k.cK) * T(0.5) * k.kap * (J2 - T(1));
     // viscous stress of the velocity gradient on the current configuration:
     // grad_x v = dF F^{-1}, sigma = mu_f (grad_x v + grad_x v^T), pulled back: J sigma F^{-T}
     T L[3][3];
@@ -255,19 +261,27 @@ __global__ __launch_bounds__(256) void solid_elem_k(int64_t ne, int64_t m, const
         for (int kk = 0; kk < 3; ++kk)
             L[i][kk] = dF[i][0] * Fit[kk][0] + dF[i][1] * Fit[kk][1] + dF[i][2] * Fit[kk][2];
     T Q[3][3];
-    const T cvJ = k.cV * k.mu_f * J;
+    const T cvJ = (RESID ? T(1) : k.cV) * k.mu_f * J;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int K = 0; K < 3; ++K) {
-            const T iso = T(-2.0 / 3.0) * tr * (F[i][K] - I1 * T(1.0 / 3.0) * Fit[i][K]) + dF[i][K] -
-                          T(2.0 / 3.0) * FdF * Fit[i][K] - I1 * T(1.0 / 3.0) * dFit[i][K];
             T sv = T(0);
 #pragma unroll
             for (int kk = 0; kk < 3; ++kk) sv += (L[i][kk] + L[kk][i]) * Fit[kk][K];
-            Q[i][K] = ci * iso + vol_t * Fit[i][K] + vol_d * dFit[i][K] - cvJ * sv;
+            if constexpr (RESID) {
+                Q[i][K] = ci * (F[i][K] - I1 * T(1.0 / 3.0) * Fit[i][K]) + vol_d * Fit[i][K] - cvJ * sv;
+            } else {
+                const T iso = T(-2.0 / 3.0) * tr * (F[i][K] - I1 * T(1.0 / 3.0) * Fit[i][K]) + dF[i][K] -
+                              T(2.0 / 3.0) * FdF * Fit[i][K] - I1 * T(1.0 / 3.0) * dFit[i][K];
+                Q[i][K] = ci * iso + vol_t * Fit[i][K] + vol_d * dFit[i][K] - cvJ * sv;
+            }
         }
-    const T mq = k.cM * (k.rho_s0 - k.rho_f * J);
+    const T mq = (RESID ? T(1) : k.cM) * (k.rho_s0 - k.rho_f * J);
+    if constexpr (RESID) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) vq[i] = aq[i];   // the inertia acts on A
+    }
     const T w = det0 * T(0.125);
     // nodal forces: f_c = w (Q grad_0 N_c + mq v(x_q) N_c), summed over the 8 points
 #pragma unroll
@@ -318,7 +332,8 @@ int solid_apply_t(const SolidView &s, const double *U, const SolidCoefs &c, cons
         k.mu_f = (T)s.mu_f;
         ProfileScope prof("solid_elem", st);
         const unsigned blocks = (unsigned)((ne * 8 + 255) / 256);
-        hipLaunchKernelGGL(solid_elem_k<T>, dim3(blocks), dim3(256), 0, st, ne, m, s.conn, s.X0, U, v, k, ef);
+        hipLaunchKernelGGL((solid_elem_k<T, false>), dim3(blocks), dim3(256), 0, st, ne, m, s.conn, s.X0, U, v,
+                           (const T *)nullptr, k, ef);
         FSI_LAUNCH_CHECK();
     }
     ProfileScope prof("solid_gather", st);
@@ -328,7 +343,50 @@ int solid_apply_t(const SolidView &s, const double *U, const SolidCoefs &c, cons
     return FSI_OK;
 }
 
+// backward-Euler solid state from the solid velocity V: U = U_n + dt V, A = (V - V_n) / dt
+__global__ __launch_bounds__(256) void solid_state_k(int64_t n, double dt, const double *__restrict__ Un,
+                                                     const double *__restrict__ Vn, const double *__restrict__ V,
+                                                     double *__restrict__ U, double *__restrict__ A)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double vi = V[i];
+    U[i] = Un[i] + dt * vi;
+    A[i] = (vi - Vn[i]) / dt;
+}
+
 }  // namespace
+
+int launch_solid_residual(const SolidView &s, const double *U, const double *V, const double *A, double *R,
+                          void *ws, hipStream_t st)
+{
+    const int64_t m = s.n_nodes, ne = s.n_elem;
+    if (m == 0) return FSI_OK;
+    double *ef = reinterpret_cast<double *>(ws);
+    if (ne > 0) {
+        SolidK<double> k{};
+        k.C0 = s.C0; k.kap = s.kappa_s; k.rho_s0 = s.rho_s0; k.rho_f = s.rho_f; k.mu_f = s.mu_f;
+        ProfileScope prof("solid_resid", st);
+        const unsigned blocks = (unsigned)((ne * 8 + 255) / 256);
+        hipLaunchKernelGGL((solid_elem_k<double, true>), dim3(blocks), dim3(256), 0, st, ne, m, s.conn, s.X0, U, V,
+                           A, k, ef);
+        FSI_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(solid_gather_k<double>, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, m,
+                       s.node_start, s.node_slot, (const double *)ef, R);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+
+int launch_solid_state(int64_t m, double dt, const double *Un, const double *Vn, const double *V, double *U,
+                       double *A, hipStream_t st)
+{
+    if (m == 0) return FSI_OK;
+    const int64_t n = 3 * m;
+    hipLaunchKernelGGL(solid_state_k, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, dt, Un, Vn, V, U, A);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
 
 size_t solid_workspace_bytes(int64_t n_elem, fsi_dtype dt)
 {

@@ -214,3 +214,136 @@ def test_fgmres_with_solid_block_matches_dense_solve(inner, precond):
     print(f"fgmres+solid inner={inner} {precond}: {st.iters} it, oracle residual {res:.3e}, x err {err:.3e}")
     assert res <= 1.5e-10
     assert err <= 1e-6
+
+
+# ---- the solid's residual and one coupled time step ----
+
+def test_solid_residual_matches_oracle():
+    import paper_2601_08266_amd as fsi
+    for size in ((6, 8), (12, 16)):
+        X0, conn, U = _mesh(*size)
+        M = X0.shape[1]
+        rng = np.random.default_rng(11)
+        V = 0.1 * rng.standard_normal((3, M))
+        A = 10.0 * rng.standard_normal((3, M))
+        print(f"solid residual {size}", flush=True)
+        R = fsi.solid_residual(_solid(X0, conn), _t(U), _t(V), _t(A)).cpu().numpy()
+        ref = osolid.residual(X0, conn, U, V, A, MAT)
+        err = field_rel_err(R, ref, 3)
+        print(f"  rel err {err:.3e}")
+        assert err <= TOL["f64"]
+
+
+def _channel_solid(n=8, size=(6, 8), seed=3):
+    cfg = dataclasses.replace(W.CONFIGS["c2"], grid=W.Grid((n, n, n), 1))
+    g = cfg.grid
+    N = g.num_nodes
+    X0, conn, U_n = _mesh(*size)
+    M = X0.shape[1]
+    rng = np.random.default_rng(seed)
+    V_n = 0.05 * rng.standard_normal((3, M))
+    mask = W.channel_dirichlet_mask(g)
+    nx = g.nodes_per_axis[0]
+    gD = np.zeros((3, N))
+    gD[0][(np.arange(N) % nx == 0) & mask[0]] = 1.0
+    gD[:, ~mask[0]] = 0.0
+    u_old = 0.1 * W.smooth_fourier_field(g, cfg.seed_vectors)[:3]
+    x0 = np.concatenate([u_old, np.zeros((1, N))])
+    x0[:3][mask] = gD[mask]
+    return cfg, g, X0, conn, U_n, V_n, mask, gD, u_old, x0
+
+
+def _gpu_problems(cfg, g, X0, conn, U_n, mask, inner):
+    """FP64 (and FP32) problems on the solid's nodes located at the step's configuration, with the
+    lumped-inertia kappa for the preconditioners."""
+    import paper_2601_08266_amd as fsi
+    import torch
+    M = X0.shape[1]
+    kappa = np.full(M, cfg.c_m * (MAT["rho_s0"] - MAT["rho_f"]) * W.plate_volume() / M)
+    mt = torch.tensor(W.mask_to_bits(mask).view(np.int32), device="cuda")
+    out = []
+    for dt in ([torch.float64] + ([torch.float32] if inner == "f32" else [])):
+        tab = fsi.dlm_locate(g, _t(X0 + U_n), dtype=dt, s_max=cfg.s_max)
+        kt = _t(kappa, "f64" if dt == torch.float64 else "f32")
+        a = torch.zeros(3 * g.num_nodes, dtype=dt, device="cuda")
+        out.append(fsi.Problem(g, fsi.make_params(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I), a, tab, kt,
+                               s=tab.s, mask=mt, gram=fsi.dlm_gram(g, tab, kt)))
+    return out
+
+
+def test_step_residual_matches_oracle():
+    import paper_2601_08266_amd as fsi
+    cfg, g, X0, conn, U_n, V_n, mask, gD, u_old, x0 = _channel_solid()
+    N = g.num_nodes
+    rng = np.random.default_rng(5)
+    x = x0 + 0.1 * rng.standard_normal((4, N))
+    x[:3][mask] = gD[mask] + 0.01
+    f = cfg.c_m * u_old
+    (P64,) = _gpu_problems(cfg, g, X0, conn, U_n, mask, "f64")
+    R, U, V = fsi.solid_step_residual(P64, _solid(X0, conn), _t(U_n), _t(V_n), cfg.dt, _t(f), _t(x), gD=_t(gD))
+    cell, xi = odlm.locate(g, X0 + U_n)
+    s = odlm.s_field(g, cell, cfg.s_max)
+    prm_o = ovms.params_array(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
+    ref = osolid.step_residual(g, prm_o, x, f, cell, xi, X0, conn, U_n, V_n, cfg.dt, MAT, s=s, mask=mask, gD=gD)
+    Vr, Ur, _ = osolid.step_state(g, cell, xi, x, U_n, V_n, cfg.dt)
+    err = field_rel_err(R.cpu().numpy(), ref, 4)
+    eu = field_rel_err(U.cpu().numpy(), Ur, 3)
+    ev = field_rel_err(V.cpu().numpy(), Vr, 3)
+    print(f"step residual rel err {err:.3e}, U {eu:.3e}, V {ev:.3e}")
+    assert err <= TOL["f64"] and eu <= TOL["f64"] and ev <= TOL["f64"]
+
+
+@pytest.mark.parametrize("inner,precond,vel_steps", [("f64", "schur_tri", 4), ("f32", "schur_tri", 4),
+                                                     ("f32", "bjacobi", 0)])
+def test_newton_with_solid_matches_oracle(inner, precond, vel_steps):
+    """Two backward-Euler steps of the 8^3 channel with the 288-node elastic plates, the solid
+    moving with the fluid: the library's Newton (FGMRES inner solves) against the oracle's Newton
+    with dense solves, both to 1e-8 of the same initial residual per step.  The library's state
+    must solve the oracle's step equations (the oracle's residual evaluated at it, from the
+    library's own step-start state) to that tolerance; the two states agree to the accuracy the
+    tolerance allows on this stiff system (1e-5)."""
+    import paper_2601_08266_amd as fsi
+    import torch
+    cfg, g, X0, conn, U_n, V_n, mask, gD, u_old, x0 = _channel_solid()
+    N = g.num_nodes
+    prm_o = ovms.params_array(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
+    S = _solid(X0, conn)
+    x_gpu = _t(x0)
+    Ug, Vg = _t(U_n), _t(V_n)
+    x_ref, U_ref, V_ref = x0.copy(), U_n.copy(), V_n.copy()
+    for step in range(2):
+        # oracle step (the configuration of step n locates the points)
+        cell, xi = odlm.locate(g, X0 + U_ref)
+        s = odlm.s_field(g, cell, cfg.s_max)
+        f_ref = cfg.c_m * x_ref[:3]
+        R0 = osolid.step_residual(g, prm_o, x_ref, f_ref, cell, xi, X0, conn, U_ref, V_ref, cfg.dt, MAT, s=s,
+                                  mask=mask, gD=gD)
+        tol = 1e-8 * np.linalg.norm(R0)
+        x_ref, U_ref, V_ref, info = osolid.newton_step(g, prm_o, x_ref, f_ref, cell, xi, X0, conn, U_ref, V_ref,
+                                                       cfg.dt, MAT, s=s, mask=mask, gD=gD, tol_abs=tol)
+        assert info["converged"]
+        # library step from its own state
+        x_prev = x_gpu.cpu().numpy().reshape(4, N).copy()
+        Un_g, Vn_g = Ug.clone(), Vg.clone()
+        Un_np, Vn_np = Un_g.cpu().numpy().reshape(3, -1), Vn_g.cpu().numpy().reshape(3, -1)
+        probs = _gpu_problems(cfg, g, X0, conn, Un_np, mask, inner)
+        f_g = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+        fsi.axpby(cfg.c_m, x_gpu[:3 * N], 0.0, f_g)
+        opts = fsi.newton_opts(tol, max_newton=30, inner=torch.float64 if inner == "f64" else torch.float32,
+                               precond=precond, vel_steps=vel_steps, max_krylov=4000)
+        rc, st = fsi.newton_solid_solve(probs[0], S, Un_g, Vn_g, cfg.dt, f_g, x_gpu, Ug, Vg, opts,
+                                        P32=probs[1] if inner == "f32" else None, gD=_t(gD))
+        xg = x_gpu.cpu().numpy().reshape(4, N)
+        cg, xig = odlm.locate(g, X0 + Un_np)
+        Rg = osolid.step_residual(g, prm_o, xg, cfg.c_m * x_prev[:3], cg, xig, X0, conn, Un_np, Vn_np, cfg.dt, MAT,
+                                  s=odlm.s_field(g, cg, cfg.s_max), mask=mask, gD=gD)
+        Vo, Uo, _ = osolid.step_state(g, cg, xig, xg, Un_np, Vn_np, cfg.dt)
+        ex = np.linalg.norm(xg - x_ref) / np.linalg.norm(x_ref)
+        eu = np.linalg.norm(Ug.cpu().numpy() - U_ref.ravel()) / np.linalg.norm(U_ref)
+        print(f"step {step} {inner} {precond}: {st.newton_iters} Newton / {st.krylov_iters} Krylov, "
+              f"oracle {len(info['history']) - 1} Newton; oracle residual at the library's state "
+              f"{np.linalg.norm(Rg):.3e} (tol {tol:.3e}); x rel diff {ex:.3e}, U rel diff {eu:.3e}", flush=True)
+        assert np.linalg.norm(Rg) <= 1.05 * tol
+        assert field_rel_err(Ug.cpu().numpy(), Uo, 3) <= TOL["f64"]
+        assert field_rel_err(Vg.cpu().numpy(), Vo, 3) <= TOL["f64"]
+        assert ex <= 1e-5 and eu <= 1e-7
