@@ -378,7 +378,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-newton", action="store_true", help="skip the short Newton-step probe")
     ap.add_argument("--no-solid", action="store_true", help="skip the solid-block timings")
-    ap.add_argument("--experiment", default=None, choices=["warmstart", "c5", "netspeed", "c3", "probe", "solid"],
+    ap.add_argument("--experiment", default=None,
+                    choices=["warmstart", "c5", "netspeed", "c3", "probe", "solid", "solid_steps"],
                     help="run a Newton-step experiment instead of the apply benchmark")
     ap.add_argument("--exp-steps", type=int, default=200)
     ap.add_argument("--exp-modes", default=None,
@@ -535,6 +536,11 @@ def run_experiment(args):
                           **ex.solid_solve(max_iters=args.exp_steps, precond=args.exp_precond,
                                            restart=args.exp_restart, vel_steps=args.exp_vel_steps,
                                            workload=args.workload)}))
+        return 0
+    if args.experiment == "solid_steps":
+        print(json.dumps({"experiment": "solid_steps",
+                          **ex.solid_steps(steps=args.exp_steps, precond=args.exp_precond,
+                                           vel_steps=args.exp_vel_steps, workload=args.workload)}))
         return 0
     if args.experiment == "probe":
         print(json.dumps({"experiment": "newton_probe",
