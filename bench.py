@@ -393,6 +393,8 @@ def main(argv=None):
     ap.add_argument("--exp-integrator", default="be", choices=["be", "genalpha"],
                     help="time integrator of the probe / warmstart / c5 runs")
     ap.add_argument("--exp-rho-inf", type=float, default=0.5, help="generalized-alpha rho_inf")
+    ap.add_argument("--exp-c-stiff", type=float, default=0.0,
+                    help="solid / solid_steps: stiffness share of the preconditioners' per-point kappa")
     ap.add_argument("--exp-train-end", type=int, default=100)
     ap.add_argument("--exp-epochs", type=int, default=20)
     ap.add_argument("--exp-stride", type=int, default=1)
@@ -535,12 +537,13 @@ def run_experiment(args):
         print(json.dumps({"experiment": "solid_solve",
                           **ex.solid_solve(max_iters=args.exp_steps, precond=args.exp_precond,
                                            restart=args.exp_restart, vel_steps=args.exp_vel_steps,
-                                           workload=args.workload)}))
+                                           workload=args.workload, c_stiff=args.exp_c_stiff)}))
         return 0
     if args.experiment == "solid_steps":
         print(json.dumps({"experiment": "solid_steps",
                           **ex.solid_steps(steps=args.exp_steps, precond=args.exp_precond,
-                                           vel_steps=args.exp_vel_steps, workload=args.workload)}))
+                                           vel_steps=args.exp_vel_steps, workload=args.workload,
+                                           c_stiff=args.exp_c_stiff)}))
         return 0
     if args.experiment == "probe":
         print(json.dumps({"experiment": "newton_probe",

@@ -290,7 +290,20 @@ def solve_c3(rtol=1e-10, restart=50, max_iters=6000, profile=True, chunk=1000, m
     return out
 
 
-def solid_solve(rtol=1e-8, restart=50, max_iters=3000, precond="schur_tri", vel_steps=2, workload="c2"):
+def solid_kappa(cfg, M, c_stiff=0.0):
+    """Per-point weight through which the preconditioners see the solid block: its lumped inertia
+    c_M (rho_s0 - rho_f) V / M plus, with c_stiff > 0, a stiffness share c_stiff dt C0 (V / M) / h^2
+    (h the fluid cell size: the block's diagonal at a fluid node is the strain energy of the
+    node's shape function over the solid, about dt C0 V_support / h^2)."""
+    import numpy as np
+    vb = W.plate_volume() / M
+    h = cfg.grid.h[0]
+    mat = W.SOLID_MATERIAL
+    return np.full(M, cfg.c_m * (mat["rho_s0"] - mat["rho_f"]) * vb + c_stiff * cfg.dt * mat["C0"] * vb / (h * h))
+
+
+def solid_solve(rtol=1e-8, restart=50, max_iters=3000, precond="schur_tri", vel_steps=2, workload="c2",
+                c_stiff=0.0):
     """One linear solve of the reduced system with the hyperelastic solid block (64^3 channel,
     the plates meshed by ~200k-node hexahedra at a deformed state), FP32 inner applies and
     FP64 outer FGMRES to rtol, against the same solve with the per-point stand-in kappa on the
@@ -328,10 +341,10 @@ def solid_solve(rtol=1e-8, restart=50, max_iters=3000, precond="schur_tri", vel_
     tab64 = dlm_locate(g, Xt, dtype=torch.float64, s_max=cfg.s_max)
     tab32 = dlm_locate(g, Xt, dtype=torch.float32, s_max=cfg.s_max)
     out = {"workload": f"{g.n[0]}^3 Q1 channel, plates meshed by {conn.shape[0]} hexahedra ({M} nodes)",
-           "rtol": rtol, "restart": restart, "precond": precond, "vel_steps": vel_steps,
+           "rtol": rtol, "restart": restart, "precond": precond, "vel_steps": vel_steps, "c_stiff": c_stiff,
            "n_occupied_cells": tab64.n_occ}
     kap_standin = W.kappa_weights(M, W.plate_volume(), cfg.c_m, cfg.alpha)
-    kap_inertia = np.full(M, cM * (W.SOLID_MATERIAL["rho_s0"] - W.SOLID_MATERIAL["rho_f"]) * W.plate_volume() / M)
+    kap_inertia = solid_kappa(cfg, M, c_stiff)
     y = torch.empty_like(bt)
     for name, kap, solid in (("standin", kap_standin, False), ("solid", kap_inertia, True)):
         k64, k32 = t(kap), t(kap, torch.float32)
@@ -366,7 +379,7 @@ def solid_solve(rtol=1e-8, restart=50, max_iters=3000, precond="schur_tri", vel_
     return out
 
 
-def solid_steps(steps=3, precond="schur_tri", vel_steps=8, inner="f32", workload="c2", inflow=1.0):
+def solid_steps(steps=3, precond="schur_tri", vel_steps=8, inner="f32", workload="c2", inflow=1.0, c_stiff=0.0):
     """Coupled time steps with the elastic plates moving with the fluid (64^3 channel, the plates
     meshed by ~200k-node hexahedra, stress free at rest; inflow u_x = `inflow` on x = 0 from a
     fluid at rest): per step, locate the solid nodes at X0 + U_n, then Newton on the step
@@ -404,7 +417,7 @@ def solid_steps(steps=3, precond="schur_tri", vel_steps=8, inner="f32", workload
     U = torch.zeros(3 * M, dtype=torch.float64, device=dev)
     V = torch.zeros(3 * M, dtype=torch.float64, device=dev)
     prm = make_params(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
-    kap = np.full(M, cfg.c_m * (W.SOLID_MATERIAL["rho_s0"] - W.SOLID_MATERIAL["rho_f"]) * W.plate_volume() / M)
+    kap = solid_kappa(cfg, M, c_stiff)
     idt = torch.float32 if inner == "f32" else torch.float64
     rows = []
     for n in range(steps):
@@ -438,4 +451,5 @@ def solid_steps(steps=3, precond="schur_tri", vel_steps=8, inner="f32", workload
         _log(f"solid step {n + 1}: rc {rc}, {st.newton_iters} Newton / {st.krylov_iters} Krylov, {ms:.0f} ms")
     return {"workload": f"{g.n[0]}^3 Q1 channel, elastic plates meshed by {conn.shape[0]} hexahedra ({M} nodes), "
                         f"inflow {inflow}, dt {cfg.dt}", "precond": precond, "vel_steps": vel_steps, "inner": inner,
+            "c_stiff": c_stiff,
             "steps": rows}
