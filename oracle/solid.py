@@ -190,11 +190,13 @@ def apply_rows(X0, conn, U, v, prm, cM, cK, cV, nodes):
     X0 = np.asarray(X0, dtype=np.float64)
     U = np.asarray(U, dtype=np.float64)
     v = np.asarray(v, dtype=np.float64)
+    blocks = {}     # each element's block computed once
     for k, n in enumerate(nodes):
         for e, c in touch.get(int(n), []):
             el = conn[e]
-            Ke = element_block(X0[:, el].T, U[:, el].T, prm, cM, cK, cV)
-            out[:, k] += Ke[3 * c:3 * c + 3] @ v[:, el].T.reshape(24)
+            if e not in blocks:
+                blocks[e] = element_block(X0[:, el].T, U[:, el].T, prm, cM, cK, cV)
+            out[:, k] += blocks[e][3 * c:3 * c + 3] @ v[:, el].T.reshape(24)
     return out
 
 

@@ -347,3 +347,54 @@ def test_newton_with_solid_matches_oracle(inner, precond, vel_steps):
         assert field_rel_err(Ug.cpu().numpy(), Uo, 3) <= TOL["f64"]
         assert field_rel_err(Vg.cpu().numpy(), Vo, 3) <= TOL["f64"]
         assert ex <= 1e-5 and eu <= 1e-7
+
+
+def test_jacobian_with_solid_block_sampled_full_size():
+    """The benchmark's configuration (64^3 Q1, the plates meshed by 98,787 hexahedra, FP64, no
+    Dirichlet rows): sampled rows of J x with the solid block.  VMS rows from the oracle's
+    per-row recomputation; the solid term at a fluid node A is sum_B N_A(X_B) (K_s B x)_B over the
+    solid nodes B in the cells around A, with K_s B x from the oracle's rows of the solid block."""
+    import paper_2601_08266_amd as fsi
+    import torch
+    cfg = W.CONFIGS["c2"]
+    g = cfg.grid
+    N = g.num_nodes
+    n_t, n_f = W.solid_mesh_size(cfg.m_points)
+    X0, conn, U = _mesh(n_t, n_f)
+    Xc = X0 + U
+    print(f"J+solid full size: {X0.shape[1]} solid nodes, {conn.shape[0]} elements", flush=True)
+    tab = fsi.dlm_locate(g, _t(Xc), dtype=torch.float64, s_max=cfg.s_max)
+    a = W.advection_field(g, cfg.seed_fields)
+    x = W.random_vector(4 * N, cfg.seed_vectors)
+    prob = fsi.Problem(g, fsi.make_params(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I), _t(a), tab, None, s=tab.s)
+    cM, cK, cV = cfg.c_m, cfg.dt, 1.0
+    y = fsi.jacobian_solid_apply(prob, _solid(X0, conn), _t(U), _t(x), cM, cK, cV).cpu().numpy()
+    cell, xi = odlm.locate(g, Xc)
+    s = odlm.s_field(g, cell, cfg.s_max)
+    prm_o = ovms.params_array(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
+    vals, ids = odlm.point_shapes(g, cell, xi)
+    rng = np.random.default_rng(9)
+    # two fluid nodes of occupied cells (their rows carry the solid term) and random rows
+    occ_nodes = np.unique(ids[:, cell >= 0])
+    near = rng.choice(occ_nodes, 2, replace=False)
+    nodes_all = np.concatenate([near, rng.choice(N, 200, replace=False)])
+    rows = np.concatenate([f * N + nodes_all for f in range(4)])
+    ref = ovms.apply_rows(g, prm_o, a, x, rows, s=s)
+    us = odlm.apply_B(g, cell, xi, x.reshape(4, N)[:3])
+    pts = np.nonzero(np.isin(ids, nodes_all).any(axis=0) & (cell >= 0))[0]
+    ksu = osolid.apply_rows(X0, conn, U, us, MAT, cM, cK, cV, pts)
+    solid_term = np.zeros((3, nodes_all.size))
+    pos = {int(n): i for i, n in enumerate(nodes_all)}
+    for j, b in enumerate(pts):
+        for c in range(ids.shape[0]):
+            i = pos.get(int(ids[c, b]))
+            if i is not None:
+                solid_term[:, i] += vals[c, b] * ksu[:, j]
+    ref = ref.reshape(4, -1)
+    ref[:3] += solid_term
+    got = y.reshape(4, N)[:, nodes_all]
+    err = rows_rel_err(got, ref)
+    err_near = rows_rel_err(got[:, :2], ref[:, :2])
+    print(f"  sampled rows {err:.3e}, rows with the solid term {err_near:.3e} ({pts.size} solid nodes)")
+    assert np.abs(solid_term[:, :2]).max() > 0
+    assert err <= TOL["f64"] and err_near <= TOL["f64"]
