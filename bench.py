@@ -97,7 +97,25 @@ def solid_elem_flops():
     return 8 * per_lane
 
 
-def time_solid(fsi, torch, cfg, reps=50):
+def solid_cpu_baseline(X0, conn, U, cM, cK, cV, n_elem=300):
+    """The oracle's solid apply (dense 24x24 element blocks, numpy, one core) on the first
+    n_elem elements of the same mesh: elements per second."""
+    import numpy as np
+
+    import fsi_workloads as W
+    from oracle import solid as osolid
+
+    sub = conn[:n_elem]
+    v = np.ones_like(U)
+    t0 = time.perf_counter()
+    y = osolid.apply(X0, sub, U, v, W.SOLID_MATERIAL, cM, cK, cV)
+    dt = time.perf_counter() - t0
+    assert np.all(np.isfinite(y))
+    return {"value": round(n_elem / dt, 1), "unit": "elements/s", "cores": 1, "kind": "oracle",
+            "sample": f"the oracle's FP64 solid apply on the first {n_elem} of the mesh's elements, {dt:.2f} s"}
+
+
+def time_solid(fsi, torch, cfg, reps=50, cpu=True):
     """Hyperelastic solid block on the workload's plate mesh (nodes = the DLM points, about
     cfg.m_points of them): fsi_solid_apply and the reduced-system Jacobian with the solid
     block (fsi_jacobian_solid_apply), FP64 and FP32, timed with events on the launch stream;
@@ -165,6 +183,9 @@ def time_solid(fsi, torch, cfg, reps=50):
             "jacobian_with_solid_gdofs": round(4 * N / (jms * 1e-3) / 1e9, 4),
         }
     out["solid_elem_flops_per_element"] = solid_elem_flops()
+    out["gpu_elements_per_s_f64"] = round(ne / (out["f64"]["solid_apply_us"] * 1e-6), 1)
+    if cpu:
+        out["cpu_baseline"] = solid_cpu_baseline(X0, conn, U, cM, cK, cV)
     return out
 
 
@@ -487,7 +508,7 @@ def main(argv=None):
         },
     }
     if args.workload != "c1" and not args.no_solid:
-        out["solid_block"] = time_solid(fsi, torch, cfg)
+        out["solid_block"] = time_solid(fsi, torch, cfg, cpu=not args.no_cpu_baseline)
     if not args.no_newton and args.workload == "c2":
         out["newton_step"] = newton_step_probe()
     if not args.no_cpu_baseline:
