@@ -398,3 +398,43 @@ def test_jacobian_with_solid_block_sampled_full_size():
     print(f"  sampled rows {err:.3e}, rows with the solid term {err_near:.3e} ({pts.size} solid nodes)")
     assert np.abs(solid_term[:, :2]).max() > 0
     assert err <= TOL["f64"] and err_near <= TOL["f64"]
+
+
+def test_solid_degenerate_cases():
+    """Edge cases of the solid block: a mesh with nodes and no elements (K_s = 0), a single
+    element, and plates sticking out of the fluid grid (solid nodes outside every cell: B gives
+    them zero velocity and B^T drops their forces, but they still couple to the nodes inside)."""
+    import paper_2601_08266_amd as fsi
+    import torch
+    X0, conn, U = _mesh(6, 8)
+    M = X0.shape[1]
+    v = W.random_vector(3 * M, 21).reshape(3, M)
+    cM, cK, cV = COEFS["all"]
+    # no elements
+    S0 = fsi.Solid(_t(X0), torch.zeros(0, dtype=torch.int32, device="cuda"), **MAT)
+    y0 = fsi.solid_apply(S0, _t(U), _t(v), cM, cK, cV)
+    assert torch.count_nonzero(y0).item() == 0
+    # one element
+    y1 = fsi.solid_apply(_solid(X0, conn[:1]), _t(U), _t(v), cM, cK, cV).cpu().numpy().reshape(3, M)
+    ref1 = osolid.apply(X0, conn[:1], U, v, MAT, cM, cK, cV)
+    assert np.linalg.norm(y1 - ref1) <= 1e-12 * np.linalg.norm(ref1)
+    assert np.count_nonzero(np.abs(ref1).sum(axis=0)) == 8
+    # plates shifted by 0.3 in x: part of the solid lies outside [0, 1]^3
+    cfg = dataclasses.replace(W.CONFIGS["c2"], grid=W.Grid((8, 8, 8), 1))
+    g = cfg.grid
+    N = g.num_nodes
+    Xs = X0 + np.array([[0.3], [0.0], [0.0]])
+    Xc = Xs + U
+    tab = fsi.dlm_locate(g, _t(Xc), dtype=torch.float64, s_max=cfg.s_max)
+    assert 0 < tab.n_outside < M
+    a = W.advection_field(g, cfg.seed_fields)
+    x = W.random_vector(4 * N, cfg.seed_vectors)
+    prob = fsi.Problem(g, fsi.make_params(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I), _t(a), tab, None, s=tab.s)
+    y = fsi.jacobian_solid_apply(prob, _solid(Xs, conn), _t(U), _t(x), cM, cK, cV).cpu().numpy()
+    cell, xi = odlm.locate(g, Xc)
+    s = odlm.s_field(g, cell, cfg.s_max)
+    prm_o = ovms.params_array(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
+    ref = osolid.jacobian_apply(g, prm_o, a, x, cell, xi, Xs, conn, U, MAT, cM, cK, cV, s=s)
+    err = field_rel_err(y, ref, 4)
+    print(f"solid partly outside ({tab.n_outside} of {M} nodes outside): rel err {err:.3e}")
+    assert err <= TOL["f64"]
