@@ -239,8 +239,9 @@ typedef struct {
                                   fsi_jacobian_solid_apply (the points must be the solid's
                                   nodes) instead of B^T diag(kappa) B; kappa and dlm_gram then
                                   only describe the preconditioners' per-point approximation
-                                  of that block.  fsi_vms_residual and fsi_newton_solve reject
-                                  it (the solid's nonlinear residual is not part of the library). */
+                                  of that block.  fsi_vms_residual, fsi_tangent_apply and
+                                  fsi_newton_solve reject it: the step with the solid's own
+                                  residual is fsi_solid_step_residual / fsi_newton_solid_solve. */
     const double *solid_U;     /* double [3][M] solid displacement when solid != NULL */
     double solid_cM, solid_cK, solid_cV;  /* coefficients of K_s (fsi_solid_apply) */
 } fsi_problem;

@@ -647,7 +647,7 @@ FSI_API int fsi_vms_residual(const fsi_problem *p, const void *f, const void *la
         return FSI_ERR_UNSUPPORTED;
     }
     if (p->solid != nullptr) {
-        set_error("the residual of a problem with a solid block is not part of the library");
+        set_error("a problem carrying the solid block: its step residual is fsi_solid_step_residual");
         return FSI_ERR_UNSUPPORTED;
     }
     const Geo g = make_geo(p->grid);
@@ -894,7 +894,8 @@ static int check_newton(const fsi_problem *P64, const fsi_problem *P32, const fs
         return FSI_ERR_UNSUPPORTED;
     }
     if (P64->solid != nullptr || (P32 != nullptr && P32->solid != nullptr)) {
-        set_error("Newton steps with a solid block need the solid's residual, which is not part of the library");
+        set_error("a problem carrying the solid block: its Newton step is fsi_newton_solid_solve (the solid passed "
+                  "as its argument)");
         return FSI_ERR_UNSUPPORTED;
     }
     if (P64->n_occ > 0) FSI_CHECK_ARG(P64->dlm_gram != nullptr, "P64->dlm_gram required");
@@ -943,7 +944,7 @@ FSI_API int fsi_tangent_apply(const fsi_problem *P64, const double *f, const dou
         return FSI_ERR_UNSUPPORTED;
     }
     if (P64->solid != nullptr) {
-        set_error("the residual of a problem with a solid block is not part of the library");
+        set_error("a problem carrying the solid block: its step residual is fsi_solid_step_residual");
         return FSI_ERR_UNSUPPORTED;
     }
     FSI_CHECK_ARG(f && x && R0 && v && y && v != y, "f, x, R0, v, y must be non-NULL and v != y");
