@@ -564,7 +564,8 @@ def run_experiment(args):
         print(json.dumps({"experiment": "solid_steps",
                           **ex.solid_steps(steps=args.exp_steps, precond=args.exp_precond,
                                            vel_steps=args.exp_vel_steps, workload=args.workload,
-                                           c_stiff=args.exp_c_stiff)}))
+                                           c_stiff=args.exp_c_stiff, integrator=args.exp_integrator,
+                                           rho_inf=args.exp_rho_inf)}))
         return 0
     if args.experiment == "probe":
         print(json.dumps({"experiment": "newton_probe",

@@ -327,22 +327,27 @@ int fsi_solid_residual(const fsi_solid *solid, const double *U, const double *V,
 
 /*
  * fsi_solid_step_residual - the step residual of section 2.4 with the solid in
- * place of the per-point stand-in, backward Euler in velocity form: the solid
- * velocity is the fluid's at the solid nodes (eq. nodal_solid_velo), V = B u,
- * U = U_n + dt V, A = (V - V_n)/dt, and the multiplier is eliminated by eq.
- * nodal_lagrange (lambda = -R^s), so
+ * place of the per-point stand-in: the solid velocity is the fluid's at the
+ * solid nodes (eq. nodal_solid_velo), V = B u, the solid displacement and
+ * acceleration are affine in it, U = U_base + cU V, A = cA V - A_base, and the
+ * multiplier is eliminated by eq. nodal_lagrange (lambda = -R^s), so
  *   R = R_fluid(x; f) + [B^T R^s(U, V, A); 0],  Dirichlet rows u - gD,
  * with R_fluid as in fsi_vms_residual (problem->a, kappa, dlm_gram unused).
+ * Backward Euler in velocity form: U_base = U_n, cU = dt, A_base = V_n / dt,
+ * cA = 1 / dt.  Generalized-alpha in stage unknowns (the displacement advancing
+ * through its rate V with the fluid's gamma): cU = gamma dt, U_base = U_n +
+ * (alpha_f - gamma) dt V_n, cA = alpha_m / (gamma dt alpha_f), A_base = cA V_n -
+ * (1 - alpha_m / gamma) Vdot_n.
  * problem: FP64, Q1, problem->solid NULL, its points (located at the step's
  * configuration) the solid's nodes.
- *   U_n, V_n  double [3][M] solid state at t_n;  f, gD  double [3][N]
+ *   U_base, A_base  double [3][M];  f, gD  double [3][N]
  *   x         double [4][N];  R  double [4][N] out
  *   U, V      double [3][M] out: the solid state of x
  *   ws        at least fsi_solid_step_workspace(problem, solid) bytes
  */
 size_t fsi_solid_step_workspace(const fsi_problem *problem, const fsi_solid *solid);
-int fsi_solid_step_residual(const fsi_problem *problem, const fsi_solid *solid, const double *U_n,
-                            const double *V_n, double dt, const double *f, const double *gD,
+int fsi_solid_step_residual(const fsi_problem *problem, const fsi_solid *solid, const double *U_base,
+                            const double *A_base, double cU, double cA, const double *f, const double *gD,
                             const double *x, double *R, double *U, double *V, void *ws, size_t ws_bytes,
                             void *stream);
 
@@ -551,24 +556,26 @@ int fsi_newton_solve(const fsi_problem *P64, const fsi_problem *P32, const doubl
                      size_t ws_bytes, void *stream);
 
 /*
- * fsi_newton_solid_solve - one backward-Euler step with the hyperelastic solid:
- * Newton on fsi_solid_step_residual from x, each iteration solving with the
- * matrix A(a = u_k) + B^T (c_M M + c_K K(U_k) - c_V K_v(U_k)) B, (c_M, c_K, c_V)
- * = (1/dt, dt, 1) (the configuration frozen for M and K_v, as the Picard
+ * fsi_newton_solid_solve - one time step with the hyperelastic solid: Newton on
+ * fsi_solid_step_residual from x, each iteration solving with the matrix
+ * A(a = u_k) + B^T (c_M M + c_K K(U_k) - c_V K_v(U_k)) B, (c_M, c_K, c_V)
+ * = (cA, cU, 1) (the configuration frozen for M and K_v, as the Picard
  * linearisation of the fluid), by FGMRES with the options' preconditioner built
  * from the problems' per-point kappa and per-cell blocks (an approximation of
  * the solid block that the caller chooses; dlm_gram is required).  After the
- * step, U and V hold the solid state of the converged x: U_{n+1} = U_n + dt V_{n+1},
- * the solid update Delta U = (C^lambda)^T Delta V of section 2.4 integrated.
+ * step, U and V hold the solid state of the converged x (backward Euler:
+ * U_{n+1} = U_n + dt V_{n+1}, the solid update Delta U = (C^lambda)^T Delta V of
+ * section 2.4 integrated).
  * opts->tangent must be 0.  Other arguments as fsi_newton_solve and
  * fsi_solid_step_residual; ws: fsi_newton_solid_workspace(P64, P32, solid, opts).
  */
 size_t fsi_newton_solid_workspace(const fsi_problem *P64, const fsi_problem *P32, const fsi_solid *solid,
                                   const fsi_newton_opts *opts);
 int fsi_newton_solid_solve(const fsi_problem *P64, const fsi_problem *P32, const fsi_solid *solid,
-                           const double *U_n, const double *V_n, double dt, const double *f,
-                           const double *gD, double *x, double *U, double *V, const fsi_newton_opts *opts,
-                           fsi_newton_stats *stats, void *ws, size_t ws_bytes, void *stream);
+                           const double *U_base, const double *A_base, double cU, double cA,
+                           const double *f, const double *gD, double *x, double *U, double *V,
+                           const fsi_newton_opts *opts, fsi_newton_stats *stats, void *ws, size_t ws_bytes,
+                           void *stream);
 
 /*
  * Learned warm start (an addition to the method: a better Newton initial

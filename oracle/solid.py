@@ -257,12 +257,16 @@ def jacobian_dense(grid, prm_f, a, cell, xi, X0, conn, U, prm_s, cM, cK, cV, s=N
 # Solid residual at the nodes (eq. solid_weak_form tested with each nodal shape function; no
 # body force or traction on the solid), with the readings above:
 #   R^s(U, V, A) = M_rho(U) A + f_int(U) - K_v(U) V.
-# Backward Euler in velocity form, the solid velocity being the fluid's at the solid nodes
-# (eq. nodal_solid_velo): V = B u, U = U_n + dt V, A = (V - V_n) / dt.  The fluid momentum
-# residual gains C^lambda R^s = B^T R^s (the multiplier eliminated by eq. nodal_lagrange,
-# lambda = -R^s), and after the step the solid moves by dt V (Delta U = (C^lambda)^T Delta V
-# integrated).  Its derivative with respect to u is B^T (c_M M + c_K K - c_V K_v) B with
-# (1/dt, dt, 1) up to the geometric derivatives of M_rho and K_v, which the Newton matrix drops.
+# The solid velocity is the fluid's at the solid nodes (eq. nodal_solid_velo): V = B u, and the
+# displacement and acceleration are affine in it, U = U_base + c_U V, A = c_A V - A_base:
+# backward Euler in velocity form has U_base = U_n, c_U = dt, A_base = V_n / dt, c_A = 1 / dt;
+# generalized-alpha in stage unknowns (the solid displacement advancing through its rate V with
+# the fluid's gamma) has c_U = gamma dt, U_base = U_n + (alpha_f - gamma) dt V_n,
+# c_A = alpha_m / (gamma dt alpha_f), A_base = c_A V_n - (1 - alpha_m / gamma) Vdot_n.  The fluid
+# momentum residual gains C^lambda R^s = B^T R^s (the multiplier eliminated by eq.
+# nodal_lagrange, lambda = -R^s), and the solid moves with the fluid (Delta U = (C^lambda)^T
+# Delta V integrated).  Its derivative with respect to u is B^T (c_M M + c_K K - c_V K_v) B with
+# (c_A, c_U, 1) up to the geometric derivatives of M_rho and K_v, which the Newton matrix drops.
 
 
 def residual(X0, conn, U, V, A, prm):
@@ -281,24 +285,29 @@ def residual(X0, conn, U, V, A, prm):
     return R
 
 
-def step_state(grid, cell, xi, x, U_n, V_n, dt):
-    """(V, U, A) of the solid for the fluid state x: V = B u, U = U_n + dt V, A = (V - V_n)/dt."""
+def be_state(U_n, V_n, dt):
+    """(U_base, A_base, c_U, c_A) of a backward-Euler step."""
+    return U_n, V_n / dt, dt, 1.0 / dt
+
+
+def step_state(grid, cell, xi, x, Ub, Ab, cU, cA):
+    """(V, U, A) of the solid for the fluid state x: V = B u, U = Ub + cU V, A = cA V - Ab."""
     from . import dlm
     N = grid.num_nodes
     V = dlm.apply_B(grid, cell, xi, np.asarray(x, dtype=np.float64).reshape(4, N)[:3])
-    return V, U_n + dt * V, (V - V_n) / dt
+    return V, Ub + cU * V, cA * V - Ab
 
 
-def step_residual(grid, prm_f, x, f, cell, xi, X0, conn, U_n, V_n, dt, prm_s, s=None, mask=None, gD=None,
+def step_residual(grid, prm_f, x, f, cell, xi, X0, conn, state, prm_s, s=None, mask=None, gD=None,
                   visc_strong=True):
-    """R(x) = R_fluid(x; f) + [B^T R^s(U_n + dt B u, B u, (B u - V_n)/dt); 0], Dirichlet rows u - gD
-    (R_fluid: the VMS step residual with nodal source f = c_m u_old + body force)."""
+    """R(x) = R_fluid(x; f) + [B^T R^s(Ub + cU B u, B u, cA B u - Ab); 0], Dirichlet rows u - gD
+    (state = (Ub, Ab, cU, cA); R_fluid: the VMS step residual with nodal source f)."""
     from . import dlm, vms
     N = grid.num_nodes
     x = np.asarray(x, dtype=np.float64).reshape(4, N)
     R = vms.residual_fluid(grid, prm_f, x, np.asarray(f, dtype=np.float64).reshape(3, N), s=s,
                            visc_strong=visc_strong)
-    V, U, A = step_state(grid, cell, xi, x, U_n, V_n, dt)
+    V, U, A = step_state(grid, cell, xi, x, *state)
     R[:3] += dlm.apply_BT(grid, cell, xi, residual(X0, conn, U, V, A, prm_s))
     if mask is not None:
         m = np.asarray(mask, dtype=bool).reshape(3, N)
@@ -307,24 +316,53 @@ def step_residual(grid, prm_f, x, f, cell, xi, X0, conn, U_n, V_n, dt, prm_s, s=
     return R
 
 
-def newton_step(grid, prm_f, x0, f, cell, xi, X0, conn, U_n, V_n, dt, prm_s, s=None, mask=None, gD=None,
+def newton_step(grid, prm_f, x0, f, cell, xi, X0, conn, state, prm_s, s=None, mask=None, gD=None,
                 tol_abs=None, rel=1e-8, max_newton=30, visc_strong=True):
-    """Newton on step_residual from x0 with the matrix A(a = u_k) + B^T K_s(U_k) B (dense solves);
-    returns (x, U_{n+1}, V_{n+1}, info)."""
+    """Newton on step_residual from x0 with the matrix A(a = u_k) + B^T K_s(U_k) B, K_s with
+    (c_A, c_U, 1) (dense solves); returns (x, U, V, info) at the converged x."""
     N = grid.num_nodes
+    Ub, Ab, cU, cA = state
     x = np.asarray(x0, dtype=np.float64).reshape(4, N).copy()
-    R = step_residual(grid, prm_f, x, f, cell, xi, X0, conn, U_n, V_n, dt, prm_s, s, mask, gD, visc_strong)
+    R = step_residual(grid, prm_f, x, f, cell, xi, X0, conn, state, prm_s, s, mask, gD, visc_strong)
     hist = [np.linalg.norm(R)]
     if tol_abs is None:
         tol_abs = rel * hist[0]
     for _ in range(max_newton):
         if hist[-1] <= tol_abs:
             break
-        _, U, _ = step_state(grid, cell, xi, x, U_n, V_n, dt)
-        J = jacobian_dense(grid, prm_f, x[:3].copy(), cell, xi, X0, conn, U, prm_s, 1.0 / dt, dt, 1.0, s=s,
+        _, U, _ = step_state(grid, cell, xi, x, *state)
+        J = jacobian_dense(grid, prm_f, x[:3].copy(), cell, xi, X0, conn, U, prm_s, cA, cU, 1.0, s=s,
                            mask=mask, visc_strong=visc_strong)
         x = x + np.linalg.solve(J, -R.ravel()).reshape(4, N)
-        R = step_residual(grid, prm_f, x, f, cell, xi, X0, conn, U_n, V_n, dt, prm_s, s, mask, gD, visc_strong)
+        R = step_residual(grid, prm_f, x, f, cell, xi, X0, conn, state, prm_s, s, mask, gD, visc_strong)
         hist.append(np.linalg.norm(R))
-    V, U, _ = step_state(grid, cell, xi, x, U_n, V_n, dt)
+    V, U, _ = step_state(grid, cell, xi, x, *state)
     return x, U, V, {"history": hist, "tol_abs": tol_abs, "converged": hist[-1] <= tol_abs}
+
+
+def genalpha_step(grid, prm_stage, coefs, dt, x_n, xdot_n, Vs_n, Vsdot_n, U_n, cell, xi, X0, conn, prm_s,
+                  s=None, mask=None, gD_stage=None, tol_abs=None, rel=1e-8):
+    """One generalized-alpha step of the coupled system in stage unknowns (the fluid as in
+    oracle.genalpha: mass coefficient c = alpha_m / (gamma dt alpha_f) in prm_stage, source
+    c V_n - (1 - alpha_m/gamma) Vdot_n; the solid velocity Vs = B u, its rate Vsdot and its
+    displacement U advancing through Vs with the same gamma).  Returns the new fluid state and
+    rates, the new solid velocity, rate and displacement, the stage state and Newton's info."""
+    am, af, gm = coefs
+    c = am / (gm * dt * af)
+    N = grid.num_nodes
+    x_n = np.asarray(x_n, dtype=np.float64).reshape(4, N)
+    xdot_n = np.asarray(xdot_n, dtype=np.float64).reshape(4, N)
+    f = c * x_n[:3] - (1.0 - am / gm) * xdot_n[:3]
+    state = (U_n + (af - gm) * dt * Vs_n, c * Vs_n - (1.0 - am / gm) * Vsdot_n, gm * dt, c)
+    x0 = x_n.copy()
+    if mask is not None:
+        m = np.asarray(mask, dtype=bool).reshape(3, N)
+        x0[:3][m] = np.asarray(gD_stage).reshape(3, N)[m]
+    x_st, _, Vs_st, info = newton_step(grid, prm_stage, x0, f, cell, xi, X0, conn, state, prm_s, s=s, mask=mask,
+                                       gD=gD_stage, tol_abs=tol_abs, rel=rel)
+    x1 = x_n + (x_st - x_n) / af
+    xdot1 = xdot_n + (x1 - x_n - dt * xdot_n) / (gm * dt)
+    Vs1 = Vs_n + (Vs_st - Vs_n) / af
+    Vsdot1 = Vsdot_n + (Vs1 - Vs_n - dt * Vsdot_n) / (gm * dt)
+    U1 = U_n + dt * Vs_n + gm * dt * (Vs1 - Vs_n)
+    return x1, xdot1, Vs1, Vsdot1, U1, x_st, info

@@ -26,7 +26,7 @@ __all__ = [
     "profile_read", "vms_residual", "bjacobi_setup", "bjacobi_apply", "fgmres_solve",
     "schur_size", "schur_info", "schur_setup", "schur_apply", "PRECONDS", "tangent_apply",
     "newton_solve", "solve_opts", "newton_opts", "Solid", "solid_apply", "jacobian_solid_workspace",
-    "jacobian_solid_apply", "solid_residual", "solid_step_residual", "newton_solid_solve",
+    "jacobian_solid_apply", "solid_residual", "solid_step_residual", "solid_be_state", "newton_solid_solve",
 ]
 
 _TORCH_OF = {FSI_F64: torch.float64, FSI_F32: torch.float32}
@@ -581,31 +581,40 @@ def solid_residual(solid: "Solid", U: torch.Tensor, V: torch.Tensor, A: torch.Te
     return R
 
 
-def solid_step_residual(problem: Problem, solid: "Solid", U_n: torch.Tensor, V_n: torch.Tensor, dt: float,
-                        f: torch.Tensor, x: torch.Tensor, gD=None, R=None, U=None, V=None, ws=None, stream=None):
-    """Step residual with the solid (fsi_solid_step_residual); returns (R, U, V)."""
+def solid_step_residual(problem: Problem, solid: "Solid", state, f: torch.Tensor, x: torch.Tensor, gD=None,
+                        R=None, U=None, V=None, ws=None, stream=None):
+    """Step residual with the solid (fsi_solid_step_residual); state = (U_base, A_base, cU, cA).
+    Returns (R, U, V)."""
+    Ub, Ab, cU, cA = state
     N, M = problem.N, solid.m
     _need(x, "x", torch.float64, 4 * N)
     _need(f, "f", torch.float64, 3 * N)
     R = torch.empty_like(x) if R is None else R
-    U = torch.empty_like(U_n) if U is None else U
-    V = torch.empty_like(V_n) if V is None else V
-    for t, n in ((U_n, "U_n"), (V_n, "V_n"), (U, "U"), (V, "V")):
+    U = torch.empty_like(Ub) if U is None else U
+    V = torch.empty_like(Ub) if V is None else V
+    for t, n in ((Ub, "U_base"), (Ab, "A_base"), (U, "U"), (V, "V")):
         _need(t, n, torch.float64, 3 * M)
     ws = _workspace(int(L.lib().fsi_solid_step_workspace(ctypes.byref(problem.struct), ctypes.byref(solid.struct))),
                     x.device, ws)
     L.check("fsi_solid_step_residual", L.lib().fsi_solid_step_residual(
-        ctypes.byref(problem.struct), ctypes.byref(solid.struct), _ptr(U_n), _ptr(V_n), float(dt), _ptr(f),
-        _ptr(gD), _ptr(x), _ptr(R), _ptr(U), _ptr(V), _ptr(ws), ws.numel(), _stream(stream)))
+        ctypes.byref(problem.struct), ctypes.byref(solid.struct), _ptr(Ub), _ptr(Ab), float(cU), float(cA),
+        _ptr(f), _ptr(gD), _ptr(x), _ptr(R), _ptr(U), _ptr(V), _ptr(ws), ws.numel(), _stream(stream)))
     return R, U, V
 
 
-def newton_solid_solve(P64: Problem, solid: "Solid", U_n: torch.Tensor, V_n: torch.Tensor, dt: float,
-                       f: torch.Tensor, x: torch.Tensor, U: torch.Tensor, V: torch.Tensor, opts: FsiNewtonOpts,
-                       P32: Optional[Problem] = None, gD=None, ws: Optional[torch.Tensor] = None, stream=None,
-                       check: bool = True):
-    """One backward-Euler step with the solid (fsi_newton_solid_solve); x, U, V updated in place.
-    Returns (status, stats)."""
+def solid_be_state(U_n: torch.Tensor, V_n: torch.Tensor, dt: float):
+    """(U_base, A_base, cU, cA) of a backward-Euler step: (U_n, V_n / dt, dt, 1 / dt)."""
+    Ab = torch.empty_like(V_n)
+    axpby(1.0 / dt, V_n, 0.0, Ab)
+    return U_n, Ab, dt, 1.0 / dt
+
+
+def newton_solid_solve(P64: Problem, solid: "Solid", state, f: torch.Tensor, x: torch.Tensor, U: torch.Tensor,
+                       V: torch.Tensor, opts: FsiNewtonOpts, P32: Optional[Problem] = None, gD=None,
+                       ws: Optional[torch.Tensor] = None, stream=None, check: bool = True):
+    """One time step with the solid (fsi_newton_solid_solve); state = (U_base, A_base, cU, cA);
+    x, U, V updated in place.  Returns (status, stats)."""
+    Ub, Ab, cU, cA = state
     _need(x, "x", torch.float64, 4 * P64.N)
     _need(f, "f", torch.float64, 3 * P64.N)
     p32 = ctypes.byref(P32.struct) if P32 is not None else None
@@ -615,8 +624,8 @@ def newton_solid_solve(P64: Problem, solid: "Solid", U_n: torch.Tensor, V_n: tor
         raise ValueError("invalid Newton arguments: " + L.lib().fsi_last_error().decode())
     ws = _workspace(nbytes, x.device, ws)
     st = FsiNewtonStats()
-    rc = L.lib().fsi_newton_solid_solve(ctypes.byref(P64.struct), p32, ctypes.byref(solid.struct), _ptr(U_n),
-                                        _ptr(V_n), float(dt), _ptr(f), _ptr(gD), _ptr(x), _ptr(U), _ptr(V),
+    rc = L.lib().fsi_newton_solid_solve(ctypes.byref(P64.struct), p32, ctypes.byref(solid.struct), _ptr(Ub),
+                                        _ptr(Ab), float(cU), float(cA), _ptr(f), _ptr(gD), _ptr(x), _ptr(U), _ptr(V),
                                         ctypes.byref(opts), ctypes.byref(st), _ptr(ws), ws.numel(),
                                         _stream(stream))
     if check:

@@ -134,7 +134,7 @@ SIGNATURES = {
     "fsi_solid_residual": (ctypes.c_int, [ctypes.POINTER(FsiSolid), P, P, P, P, P, SZ, P]),
     "fsi_solid_step_workspace": (SZ, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiSolid)]),
     "fsi_solid_step_residual": (ctypes.c_int, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiSolid), P, P,
-                                               ctypes.c_double, P, P, P, P, P, P, P, SZ, P]),
+                                               ctypes.c_double, ctypes.c_double, P, P, P, P, P, P, P, SZ, P]),
     "fsi_jacobian_solid_apply": (ctypes.c_int, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiSolid), P,
                                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P,
                                                 P, SZ, P]),
@@ -163,7 +163,8 @@ SIGNATURES = {
     "fsi_newton_solid_workspace": (SZ, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiProblem),
                                         ctypes.POINTER(FsiSolid), ctypes.POINTER(FsiNewtonOpts)]),
     "fsi_newton_solid_solve": (ctypes.c_int, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiProblem),
-                                              ctypes.POINTER(FsiSolid), P, P, ctypes.c_double, P, P, P, P, P,
+                                              ctypes.POINTER(FsiSolid), P, P, ctypes.c_double, ctypes.c_double,
+                                              P, P, P, P, P,
                                               ctypes.POINTER(FsiNewtonOpts), ctypes.POINTER(FsiNewtonStats), P,
                                               SZ, P]),
     "fsi_conv3d_fwd": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int32, P,

@@ -529,9 +529,9 @@ FSI_API int fsi_solid_residual(const fsi_solid *S, const double *U, const double
 int fsi::solid_step_residual(const Geo &g, const fsi_problem &P, const SolidStep &ss, const double *f,
                              const double *gD, const double *x, double *R, void *ws, hipStream_t st)
 {
-    // V = B u (the solid moves with the fluid), U = U_n + dt V, A = (V - V_n)/dt, R^s at the
-    // solid nodes, its B^T corner sums, then the fluid step residual whose node gather adds them
-    // before the Dirichlet rows (u - gD)
+    // V = B u (the solid moves with the fluid), U = Ub + cU V, A = cA V - Ab, R^s at the solid
+    // nodes, its B^T corner sums, then the fluid step residual whose node gather adds them before
+    // the Dirichlet rows (u - gD)
     const int64_t m = P.m;
     const VmsConst<double> k = make_vms_const<double>(g, P.prm, P.s != nullptr);
     const BrickLayout bl = brick_layout(g);
@@ -549,7 +549,7 @@ int fsi::solid_step_residual(const Geo &g, const fsi_problem &P, const SolidStep
     if (m > 0) {
         rc = launch_dlm_B(g, FSI_F64, m, P.cell, P.xi, x, nullptr, ss.V, st);
         if (rc) return rc;
-        rc = launch_solid_state(m, ss.dt, ss.U_n, ss.V_n, ss.V, ss.U, A, st);
+        rc = launch_solid_state(m, ss.cU, ss.cA, ss.Ub, ss.Ab, ss.V, ss.U, A, st);
         if (rc) return rc;
     }
     if (solid_on) {
@@ -569,8 +569,8 @@ int fsi::solid_step_residual(const Geo &g, const fsi_problem &P, const SolidStep
     return launch_gather<double, 1, Q1_BX, Q1_BY, Q1_BZ>(g, part, bl, x, P.dir_mask, R, o, st);
 }
 
-static int check_solid_step(const fsi_problem *p, const fsi_solid *S, const double *U_n, const double *V_n,
-                            double dt, const double *U, const double *V)
+static int check_solid_step(const fsi_problem *p, const fsi_solid *S, const double *Ub, const double *Ab,
+                            double cU, double cA, const double *U, const double *V)
 {
     int rc = check_problem(p);
     if (rc) return rc;
@@ -580,9 +580,10 @@ static int check_solid_step(const fsi_problem *p, const fsi_solid *S, const doub
     FSI_CHECK_ARG(p->solid == nullptr, "pass the solid as the argument, not in the problem");
     FSI_CHECK_ARG(p->m == S->n_nodes, "the problem's points (%lld) must be the solid's nodes (%lld)",
                   (long long)p->m, (long long)S->n_nodes);
-    FSI_CHECK_ARG(std::isfinite(dt) && dt > 0.0, "dt must be finite and > 0");
-    FSI_CHECK_ARG(p->m == 0 || (U_n && V_n && U && V && p->cell && p->xi), "solid state arrays must be non-NULL");
-    FSI_CHECK_ARG(U != U_n && V != V_n && U != V, "U, V must be distinct from U_n, V_n and each other");
+    FSI_CHECK_ARG(std::isfinite(cU) && std::isfinite(cA), "cU and cA must be finite");
+    FSI_CHECK_ARG(p->m == 0 || (Ub && Ab && U && V && p->cell && p->xi), "solid state arrays must be non-NULL");
+    FSI_CHECK_ARG(U != Ub && U != Ab && V != Ub && V != Ab && U != V,
+                  "U, V must be distinct from U_base, A_base and each other");
     if (p->grid.order != 1) {
         set_error("the residual kernel is implemented for Q1 grids");
         return FSI_ERR_UNSUPPORTED;
@@ -596,12 +597,13 @@ FSI_API size_t fsi_solid_step_workspace(const fsi_problem *p, const fsi_solid *S
     return problem_ws(p, S);
 }
 
-FSI_API int fsi_solid_step_residual(const fsi_problem *p, const fsi_solid *S, const double *U_n, const double *V_n,
-                                    double dt, const double *f, const double *gD, const double *x, double *R,
-                                    double *U, double *V, void *ws, size_t ws_bytes, void *stream)
+FSI_API int fsi_solid_step_residual(const fsi_problem *p, const fsi_solid *S, const double *U_base,
+                                    const double *A_base, double cU, double cA, const double *f, const double *gD,
+                                    const double *x, double *R, double *U, double *V, void *ws, size_t ws_bytes,
+                                    void *stream)
 {
     clear_error();
-    int rc = check_solid_step(p, S, U_n, V_n, dt, U, V);
+    int rc = check_solid_step(p, S, U_base, A_base, cU, cA, U, V);
     if (rc) return rc;
     FSI_CHECK_ARG(f && x && R && x != R, "f, x, R must be non-NULL and x != R");
     FSI_CHECK_ARG(p->dir_mask == nullptr || gD != nullptr, "gD required with a Dirichlet mask");
@@ -610,7 +612,7 @@ FSI_API int fsi_solid_step_residual(const fsi_problem *p, const fsi_solid *S, co
         set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
         return FSI_ERR_WORKSPACE;
     }
-    const SolidStep ss{S, U_n, V_n, dt, U, V};
+    const SolidStep ss{S, U_base, A_base, cU, cA, U, V};
     return solid_step_residual(make_geo(p->grid), *p, ss, f, gD, x, R, ws, as_stream(stream));
 }
 
@@ -1004,14 +1006,15 @@ FSI_API size_t fsi_newton_solid_workspace(const fsi_problem *P64, const fsi_prob
 }
 
 FSI_API int fsi_newton_solid_solve(const fsi_problem *P64, const fsi_problem *P32, const fsi_solid *S,
-                                   const double *U_n, const double *V_n, double dt, const double *f,
-                                   const double *gD, double *x, double *U, double *V, const fsi_newton_opts *o,
-                                   fsi_newton_stats *stats, void *ws, size_t ws_bytes, void *stream)
+                                   const double *U_base, const double *A_base, double cU, double cA,
+                                   const double *f, const double *gD, double *x, double *U, double *V,
+                                   const fsi_newton_opts *o, fsi_newton_stats *stats, void *ws, size_t ws_bytes,
+                                   void *stream)
 {
     clear_error();
     int rc = check_newton(P64, P32, o);
     if (rc) return rc;
-    rc = check_solid_step(P64, S, U_n, V_n, dt, U, V);
+    rc = check_solid_step(P64, S, U_base, A_base, cU, cA, U, V);
     if (rc) return rc;
     if (o->inner == FSI_F32) FSI_CHECK_ARG(P32->m == S->n_nodes, "P32's points must be the solid's nodes");
     FSI_CHECK_ARG(o->tangent == 0, "the full tangent is not available with the solid block");
@@ -1025,7 +1028,7 @@ FSI_API int fsi_newton_solid_solve(const fsi_problem *P64, const fsi_problem *P3
         set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
         return FSI_ERR_WORKSPACE;
     }
-    const SolidStep ss{S, U_n, V_n, dt, U, V};
+    const SolidStep ss{S, U_base, A_base, cU, cA, U, V};
     return newton_solve(g, *P64, o->inner == FSI_F32 ? P32 : nullptr, f, nullptr, gD, x, *o, stats, ws, jw,
                         as_stream(stream), &ss);
 }

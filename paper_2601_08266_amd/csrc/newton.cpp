@@ -173,7 +173,7 @@ int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, c
         for (DlmView *dv : {&v64, &v32}) {
             dv->solid = ss->S;
             dv->solid_U = ss->U;
-            dv->solid_c = SolidCoefs{1.0 / ss->dt, ss->dt, 1.0};
+            dv->solid_c = SolidCoefs{ss->cA, ss->cU, 1.0};
         }
     }
     double *scratch = reinterpret_cast<double *>(base + L.scratch);

@@ -16,14 +16,14 @@ size_t tangent_workspace_bytes(const Geo &g);
 int tangent_apply(const Geo &g, const fsi_problem &P64, const DlmView *dlm, const double *f, const double *lamg,
                   const double *gD, const double *x, const double *R0, double delta, fsi_dtype dt, const void *v,
                   void *y, void *fdws, void *rws, hipStream_t st);
-// One backward-Euler step with the hyperelastic solid (the problem's points are its nodes):
-// the step residual gains B^T R^s(U_n + dt B u, B u, (B u - V_n)/dt) and the Newton matrix
-// B^T (c_M M + c_K K - c_V K_v) B with (1/dt, dt, 1); U and V receive the solid state of the
-// last residual's iterate.
+// One time step with the hyperelastic solid (the problem's points are its nodes): V = B u,
+// U = Ub + cU V, A = cA V - Ab; the step residual gains B^T R^s(U, V, A) and the Newton matrix
+// B^T (c_M M + c_K K - c_V K_v) B with (cA, cU, 1); U and V receive the solid state of the last
+// residual's iterate.
 struct SolidStep {
     const fsi_solid *S;
-    const double *U_n, *V_n;
-    double dt;
+    const double *Ub, *Ab;
+    double cU, cA;
     double *U, *V;
 };
 // R = the step residual with the solid (FP64, Q1); ws: the Jacobian workspace of P64 with S

@@ -343,16 +343,17 @@ int solid_apply_t(const SolidView &s, const double *U, const SolidCoefs &c, cons
     return FSI_OK;
 }
 
-// backward-Euler solid state from the solid velocity V: U = U_n + dt V, A = (V - V_n) / dt
-__global__ __launch_bounds__(256) void solid_state_k(int64_t n, double dt, const double *__restrict__ Un,
-                                                     const double *__restrict__ Vn, const double *__restrict__ V,
+// solid state from the solid velocity V: U = Ub + cU V, A = cA V - Ab (backward Euler:
+// Ub = U_n, cU = dt, Ab = V_n / dt, cA = 1 / dt)
+__global__ __launch_bounds__(256) void solid_state_k(int64_t n, double cU, double cA, const double *__restrict__ Ub,
+                                                     const double *__restrict__ Ab, const double *__restrict__ V,
                                                      double *__restrict__ U, double *__restrict__ A)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const double vi = V[i];
-    U[i] = Un[i] + dt * vi;
-    A[i] = (vi - Vn[i]) / dt;
+    U[i] = Ub[i] + cU * vi;
+    A[i] = cA * vi - Ab[i];
 }
 
 }  // namespace
@@ -378,12 +379,13 @@ int launch_solid_residual(const SolidView &s, const double *U, const double *V, 
     return FSI_OK;
 }
 
-int launch_solid_state(int64_t m, double dt, const double *Un, const double *Vn, const double *V, double *U,
-                       double *A, hipStream_t st)
+int launch_solid_state(int64_t m, double cU, double cA, const double *Ub, const double *Ab, const double *V,
+                       double *U, double *A, hipStream_t st)
 {
     if (m == 0) return FSI_OK;
     const int64_t n = 3 * m;
-    hipLaunchKernelGGL(solid_state_k, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, dt, Un, Vn, V, U, A);
+    hipLaunchKernelGGL(solid_state_k, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, cU, cA, Ub, Ab, V, U,
+                       A);
     FSI_LAUNCH_CHECK();
     return FSI_OK;
 }

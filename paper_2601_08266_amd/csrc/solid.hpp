@@ -35,8 +35,8 @@ int launch_solid_apply(const SolidView &s, fsi_dtype dt, const double *U, const 
 // R [3][n_nodes] = M_rho(U) A + f_int(U) - K_v(U) V (FP64; ws: solid_workspace_bytes(n_elem, F64))
 int launch_solid_residual(const SolidView &s, const double *U, const double *V, const double *A, double *R,
                           void *ws, hipStream_t st);
-// U = U_n + dt V, A = (V - V_n) / dt over [3][m]
-int launch_solid_state(int64_t m, double dt, const double *Un, const double *Vn, const double *V, double *U,
-                       double *A, hipStream_t st);
+// U = Ub + cU V, A = cA V - Ab over [3][m]
+int launch_solid_state(int64_t m, double cU, double cA, const double *Ub, const double *Ab, const double *V,
+                       double *U, double *A, hipStream_t st);
 
 }  // namespace fsi

@@ -379,77 +379,34 @@ def solid_solve(rtol=1e-8, restart=50, max_iters=3000, precond="schur_tri", vel_
     return out
 
 
-def solid_steps(steps=3, precond="schur_tri", vel_steps=8, inner="f32", workload="c2", inflow=1.0, c_stiff=0.0):
-    """Coupled time steps with the elastic plates moving with the fluid (64^3 channel, the plates
-    meshed by ~200k-node hexahedra, stress free at rest; inflow u_x = `inflow` on x = 0 from a
-    fluid at rest): per step, locate the solid nodes at X0 + U_n, then Newton on the step
-    residual with the solid (fsi_newton_solid_solve) to 1e-8 of the initial residual, FGMRES
-    with `precond` built from the lumped-inertia kappa.  Reports Newton / Krylov iterations and
-    wall time per step, and the solid's motion."""
-    import numpy as np
-
-    from . import (Problem, Solid, dlm_gram, dlm_locate, make_params, newton_opts, newton_solid_solve,
-                   solid_step_residual)
+def solid_steps(steps=3, precond="schur_tri", vel_steps=8, inner="f32", workload="c2", inflow=1.0, c_stiff=0.0,
+                integrator="be", rho_inf=0.5):
+    """Coupled time steps with the elastic plates moving with the fluid (the configuration's
+    channel, the plates meshed by hexahedra with about the configuration's point count, stress
+    free at rest; inflow u_x = `inflow` on x = 0 from a fluid at rest) through
+    solid_stepper.SolidChannel: per step, locate the solid nodes at X0 + U_n, then Newton on the
+    step residual with the solid to 1e-8 of the initial residual, FGMRES with `precond` built from
+    the per-point kappa of solid_kappa.  Reports Newton / Krylov iterations and wall time per
+    step, and the solid's motion."""
+    from .solid_stepper import SolidChannel
 
     cfg = W.CONFIGS[workload]
-    g = cfg.grid
-    N = g.num_nodes
-    dev = torch.device("cuda")
-
-    def t(v, dt=torch.float64):
-        return torch.tensor(np.ascontiguousarray(v).ravel(), dtype=dt, device=dev)
-
     n_t, n_f = W.solid_mesh_size(cfg.m_points)
     X0, conn = W.plate_solid_mesh(n_t, n_f)
-    M = X0.shape[1]
-    S = Solid(t(X0), torch.tensor(conn.ravel(), dtype=torch.int32, device=dev), **W.SOLID_MATERIAL)
-    mask = W.channel_dirichlet_mask(g)
-    nx = g.nodes_per_axis[0]
-    inflow_nodes = (np.arange(N) % nx == 0)
-    wall = mask[0] & ~inflow_nodes
-    gD = np.zeros((3, N))
-    gD[0][inflow_nodes & ~wall] = inflow
-    gDt = t(gD)
-    mt = torch.tensor(W.mask_to_bits(mask).view(np.int32), device=dev)
-    x = np.zeros((4, N))
-    x[:3][mask] = gD[mask]
-    xt = t(x)
-    U = torch.zeros(3 * M, dtype=torch.float64, device=dev)
-    V = torch.zeros(3 * M, dtype=torch.float64, device=dev)
-    prm = make_params(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
-    kap = solid_kappa(cfg, M, c_stiff)
-    idt = torch.float32 if inner == "f32" else torch.float64
+    run = SolidChannel(cfg, X0, conn, integrator=integrator, rho_inf=rho_inf, precond=precond, vel_steps=vel_steps,
+                       inner=inner, inflow=inflow, kappa=solid_kappa(cfg, X0.shape[1], c_stiff))
     rows = []
-    for n in range(steps):
-        t0 = time.perf_counter()
-        Xc = t(X0) + U
-        probs = []
-        for dt in ([torch.float64] + ([torch.float32] if inner == "f32" else [])):
-            tab = dlm_locate(g, Xc, dtype=dt, s_max=cfg.s_max)
-            kt = t(kap, dt)
-            probs.append(Problem(g, prm, torch.zeros(3 * N, dtype=dt, device=dev), tab, kt, s=tab.s, mask=mt,
-                                 gram=dlm_gram(g, tab, kt)))
-        f = torch.empty(3 * N, dtype=torch.float64, device=dev)
-        axpby(cfg.c_m, xt[:3 * N], 0.0, f)
-        Un, Vn = U.clone(), V.clone()
-        R0, _, _ = solid_step_residual(probs[0], S, Un, Vn, cfg.dt, f, xt, gD=gDt)
-        torch.cuda.synchronize()
-        t_setup = (time.perf_counter() - t0) * 1e3
-        tol = 1e-8 * norm2(R0)
-        opts = newton_opts(tol, max_newton=30, inner=idt, precond=precond, vel_steps=vel_steps, max_krylov=6000)
-        t1 = time.perf_counter()
-        rc, st = newton_solid_solve(probs[0], S, Un, Vn, cfg.dt, f, xt, U, V, opts,
-                                    P32=probs[1] if inner == "f32" else None, gD=gDt, check=False)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t1) * 1e3
-        row = {"step": n + 1, "status": rc, "newton": st.newton_iters, "krylov": st.krylov_iters,
-               "ms_newton": round(ms, 1), "ms_locate_setup": round(t_setup, 1),
-               "ms_residuals": round(st.t_residual_ms, 1), "ms_setups": round(st.t_setup_ms, 1),
-               "ms_krylov": round(st.t_krylov_ms, 1), "n_occupied_cells": probs[0].tables.n_occ,
-               "solid_speed_max": float(V.abs().max()), "solid_disp_max": float(U.abs().max())}
-        rows.append(row)
-        _log(f"solid step {n + 1}: rc {rc}, {st.newton_iters} Newton / {st.krylov_iters} Krylov, {ms:.0f} ms")
-    return {"workload": f"{g.n[0]}^3 Q1 channel, elastic plates meshed by {conn.shape[0]} hexahedra ({M} nodes), "
-                        f"inflow {inflow}, dt {cfg.dt}", "precond": precond, "vel_steps": vel_steps, "inner": inner,
-            "c_stiff": c_stiff,
-            "steps": rows}
+    for _ in range(steps):
+        rec = run.step()
+        rec.pop("stage_x")
+        rec.pop("tol")
+        rec["solid_speed_max"] = float(run.Vs.abs().max())
+        rec["solid_disp_max"] = float(run.U.abs().max())
+        rows.append(rec)
+        _log(f"solid step {rec['step']}: rc {rec['status']}, {rec['newton']} Newton / {rec['krylov']} Krylov, "
+             f"{rec['ms_newton']:.0f} ms")
+    g = cfg.grid
+    return {"workload": f"{g.n[0]}^3 Q1 channel, elastic plates meshed by {conn.shape[0]} hexahedra "
+                        f"({X0.shape[1]} nodes), inflow {inflow}, dt {cfg.dt}",
+            "integrator": integrator, "rho_inf": rho_inf if integrator != "be" else None, "precond": precond,
+            "vel_steps": vel_steps, "inner": inner, "c_stiff": c_stiff, "steps": rows}

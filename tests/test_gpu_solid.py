@@ -280,12 +280,14 @@ def test_step_residual_matches_oracle():
     x[:3][mask] = gD[mask] + 0.01
     f = cfg.c_m * u_old
     (P64,) = _gpu_problems(cfg, g, X0, conn, U_n, mask, "f64")
-    R, U, V = fsi.solid_step_residual(P64, _solid(X0, conn), _t(U_n), _t(V_n), cfg.dt, _t(f), _t(x), gD=_t(gD))
+    R, U, V = fsi.solid_step_residual(P64, _solid(X0, conn), (_t(U_n), _t(V_n / cfg.dt), cfg.dt, 1.0 / cfg.dt),
+                                      _t(f), _t(x), gD=_t(gD))
     cell, xi = odlm.locate(g, X0 + U_n)
     s = odlm.s_field(g, cell, cfg.s_max)
     prm_o = ovms.params_array(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
-    ref = osolid.step_residual(g, prm_o, x, f, cell, xi, X0, conn, U_n, V_n, cfg.dt, MAT, s=s, mask=mask, gD=gD)
-    Vr, Ur, _ = osolid.step_state(g, cell, xi, x, U_n, V_n, cfg.dt)
+    be = osolid.be_state(U_n, V_n, cfg.dt)
+    ref = osolid.step_residual(g, prm_o, x, f, cell, xi, X0, conn, be, MAT, s=s, mask=mask, gD=gD)
+    Vr, Ur, _ = osolid.step_state(g, cell, xi, x, *be)
     err = field_rel_err(R.cpu().numpy(), ref, 4)
     eu = field_rel_err(U.cpu().numpy(), Ur, 3)
     ev = field_rel_err(V.cpu().numpy(), Vr, 3)
@@ -316,11 +318,11 @@ def test_newton_with_solid_matches_oracle(inner, precond, vel_steps):
         cell, xi = odlm.locate(g, X0 + U_ref)
         s = odlm.s_field(g, cell, cfg.s_max)
         f_ref = cfg.c_m * x_ref[:3]
-        R0 = osolid.step_residual(g, prm_o, x_ref, f_ref, cell, xi, X0, conn, U_ref, V_ref, cfg.dt, MAT, s=s,
-                                  mask=mask, gD=gD)
+        be = osolid.be_state(U_ref, V_ref, cfg.dt)
+        R0 = osolid.step_residual(g, prm_o, x_ref, f_ref, cell, xi, X0, conn, be, MAT, s=s, mask=mask, gD=gD)
         tol = 1e-8 * np.linalg.norm(R0)
-        x_ref, U_ref, V_ref, info = osolid.newton_step(g, prm_o, x_ref, f_ref, cell, xi, X0, conn, U_ref, V_ref,
-                                                       cfg.dt, MAT, s=s, mask=mask, gD=gD, tol_abs=tol)
+        x_ref, U_ref, V_ref, info = osolid.newton_step(g, prm_o, x_ref, f_ref, cell, xi, X0, conn, be, MAT, s=s,
+                                                       mask=mask, gD=gD, tol_abs=tol)
         assert info["converged"]
         # library step from its own state
         x_prev = x_gpu.cpu().numpy().reshape(4, N).copy()
@@ -331,13 +333,14 @@ def test_newton_with_solid_matches_oracle(inner, precond, vel_steps):
         fsi.axpby(cfg.c_m, x_gpu[:3 * N], 0.0, f_g)
         opts = fsi.newton_opts(tol, max_newton=30, inner=torch.float64 if inner == "f64" else torch.float32,
                                precond=precond, vel_steps=vel_steps, max_krylov=4000)
-        rc, st = fsi.newton_solid_solve(probs[0], S, Un_g, Vn_g, cfg.dt, f_g, x_gpu, Ug, Vg, opts,
-                                        P32=probs[1] if inner == "f32" else None, gD=_t(gD))
+        rc, st = fsi.newton_solid_solve(probs[0], S, fsi.solid_be_state(Un_g, Vn_g, cfg.dt), f_g, x_gpu, Ug, Vg,
+                                        opts, P32=probs[1] if inner == "f32" else None, gD=_t(gD))
         xg = x_gpu.cpu().numpy().reshape(4, N)
         cg, xig = odlm.locate(g, X0 + Un_np)
-        Rg = osolid.step_residual(g, prm_o, xg, cfg.c_m * x_prev[:3], cg, xig, X0, conn, Un_np, Vn_np, cfg.dt, MAT,
+        be_g = osolid.be_state(Un_np, Vn_np, cfg.dt)
+        Rg = osolid.step_residual(g, prm_o, xg, cfg.c_m * x_prev[:3], cg, xig, X0, conn, be_g, MAT,
                                   s=odlm.s_field(g, cg, cfg.s_max), mask=mask, gD=gD)
-        Vo, Uo, _ = osolid.step_state(g, cg, xig, xg, Un_np, Vn_np, cfg.dt)
+        Vo, Uo, _ = osolid.step_state(g, cg, xig, xg, *be_g)
         ex = np.linalg.norm(xg - x_ref) / np.linalg.norm(x_ref)
         eu = np.linalg.norm(Ug.cpu().numpy() - U_ref.ravel()) / np.linalg.norm(U_ref)
         print(f"step {step} {inner} {precond}: {st.newton_iters} Newton / {st.krylov_iters} Krylov, "
@@ -438,3 +441,57 @@ def test_solid_degenerate_cases():
     err = field_rel_err(y, ref, 4)
     print(f"solid partly outside ({tab.n_outside} of {M} nodes outside): rel err {err:.3e}")
     assert err <= TOL["f64"]
+
+
+@pytest.mark.parametrize("integrator", ["be", "genalpha"])
+def test_solid_channel_steps_match_oracle(integrator):
+    """Two coupled steps of the 8^3 channel with the elastic plates through the library's stepper
+    (solid_stepper.SolidChannel: locate, step residual, Newton, rate updates by fsi_axpby) against
+    the oracle's steps (oracle/solid.genalpha_step, dense Newton), backward Euler and
+    generalized-alpha with rho_inf = 0.5.  At every step the library's stage state solves the
+    oracle's stage equations (built from the library's own step-start state) to the step's
+    tolerance, and the states agree to what that tolerance allows on this stiff system."""
+    from paper_2601_08266_amd.solid_stepper import SolidChannel, ga_coefficients
+    cfg = dataclasses.replace(W.CONFIGS["c2"], grid=W.Grid((8, 8, 8), 1))
+    g = cfg.grid
+    N = g.num_nodes
+    X0, conn = W.plate_solid_mesh(6, 8)
+    M = X0.shape[1]
+    run = SolidChannel(cfg, X0, conn, integrator=integrator, rho_inf=0.5, precond="schur_tri", vel_steps=4)
+    coefs = (1.0, 1.0, 1.0) if integrator == "be" else ga_coefficients(0.5)
+    am, af, gm = coefs
+    dt = cfg.dt
+    c = am / (gm * dt * af)
+    prm_stage = ovms.params_array(cfg.nu, c, dt, cfg.C_T, cfg.C_I)
+    mask = W.channel_dirichlet_mask(g)
+    gD = run.gD.cpu().numpy().reshape(3, N)
+    ref = dict(x=run.x.cpu().numpy().reshape(4, N), xd=np.zeros((4, N)), Vs=np.zeros((3, M)), Vsd=np.zeros((3, M)),
+               U=np.zeros((3, M)))
+    for step in range(2):
+        start = dict(x=run.x.cpu().numpy().reshape(4, N), xd=run.xdot.cpu().numpy().reshape(4, N),
+                     Vs=run.Vs.cpu().numpy().reshape(3, M), Vsd=run.Vsdot.cpu().numpy().reshape(3, M),
+                     U=run.U.cpu().numpy().reshape(3, M))
+        rec = run.step()
+        assert rec["status"] == 0
+        # the oracle's stage equations at the library's stage state
+        cg, xig = odlm.locate(g, X0 + start["U"])
+        sg = odlm.s_field(g, cg, cfg.s_max)
+        f = c * start["x"][:3] - (1.0 - am / gm) * start["xd"][:3]
+        state = (start["U"] + (af - gm) * dt * start["Vs"], c * start["Vs"] - (1.0 - am / gm) * start["Vsd"], gm * dt, c)
+        Rg = osolid.step_residual(g, prm_stage, rec["stage_x"].cpu().numpy().reshape(4, N), f, cg, xig, X0, conn, state,
+                                  MAT, s=sg, mask=mask, gD=gD)
+        # the oracle's own step from its own state
+        co, xio = odlm.locate(g, X0 + ref["U"])
+        so = odlm.s_field(g, co, cfg.s_max)
+        x1, xd1, Vs1, Vsd1, U1, _, info = osolid.genalpha_step(g, prm_stage, coefs, dt, ref["x"], ref["xd"], ref["Vs"],
+                                                               ref["Vsd"], ref["U"], co, xio, X0, conn, MAT, s=so,
+                                                               mask=mask, gD_stage=gD, tol_abs=rec["tol"])
+        assert info["converged"]
+        ref = dict(x=x1, xd=xd1, Vs=Vs1, Vsd=Vsd1, U=U1)
+        ex = np.linalg.norm(run.x.cpu().numpy() - x1.ravel()) / np.linalg.norm(x1)
+        eu = np.linalg.norm(run.U.cpu().numpy() - U1.ravel()) / np.linalg.norm(U1)
+        print(f"{integrator} step {step}: {rec['newton']} Newton / {rec['krylov']} Krylov; oracle residual at the "
+              f"library's stage {np.linalg.norm(Rg):.3e} (tol {rec['tol']:.3e}); x rel diff {ex:.3e}, "
+              f"U rel diff {eu:.3e}", flush=True)
+        assert np.linalg.norm(Rg) <= 1.05 * rec["tol"]
+        assert ex <= 1e-5 and eu <= 1e-5

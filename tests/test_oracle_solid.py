@@ -334,7 +334,36 @@ def test_coupled_newton_step_converges():
     x0 = np.zeros((4, N))
     x0[:3][mask] = gD[mask]
     f = (1.0 / dt) * np.zeros((3, N))
-    x, U, V, info = solid.newton_step(g, prm_f, x0, f, cell, xi, X, conn, U_n, V_n, dt, PRM, mask=mask, gD=gD)
+    x, U, V, info = solid.newton_step(g, prm_f, x0, f, cell, xi, X, conn, solid.be_state(U_n, V_n, dt), PRM,
+                                      mask=mask, gD=gD)
     print("coupled step residuals", ["%.2e" % h for h in info["history"]])
     assert info["converged"] and len(info["history"]) <= 8
     np.testing.assert_allclose(U, U_n + dt * V, rtol=1e-14, atol=1e-16)
+
+
+def test_coupled_genalpha_with_unit_coefficients_is_backward_euler():
+    from oracle import dlm, vms
+    g = W.Grid((4, 4, 4), 1)
+    N = g.num_nodes
+    X, conn = W.plate_solid_mesh(3, 4)
+    M = X.shape[1]
+    U_n = W.solid_displacement(X, 5)
+    rng = np.random.default_rng(2)
+    V_n = 0.05 * rng.standard_normal((3, M))
+    dt = 1e-3
+    cell, xi = dlm.locate(g, X + U_n)
+    prm_f = vms.params_array(0.01, 1.0 / dt, dt)
+    mask = W.channel_dirichlet_mask(g)
+    gD = np.zeros((3, N))
+    gD[0][np.arange(N) % g.nodes_per_axis[0] == 0] = 1.0
+    x_n = np.zeros((4, N))
+    x_n[:3][mask] = gD[mask]
+    x1, xdot1, Vs1, _, U1, x_st, info = solid.genalpha_step(g, prm_f, (1.0, 1.0, 1.0), dt, x_n, np.zeros((4, N)),
+                                                            V_n, np.zeros((3, M)), U_n, cell, xi, X, conn, PRM,
+                                                            mask=mask, gD_stage=gD)
+    xb, Ub, Vb, _ = solid.newton_step(g, prm_f, x_n, (1.0 / dt) * x_n[:3], cell, xi, X, conn,
+                                      solid.be_state(U_n, V_n, dt), PRM, mask=mask, gD=gD)
+    assert info["converged"]
+    assert np.abs(x1 - xb).max() <= 1e-12 * np.abs(xb).max()
+    assert np.abs(U1 - Ub).max() <= 1e-12 * np.abs(Ub).max()
+    np.testing.assert_allclose(Vs1, Vb, rtol=1e-10, atol=1e-12 * np.abs(Vb).max())
