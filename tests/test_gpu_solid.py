@@ -495,3 +495,35 @@ def test_solid_channel_steps_match_oracle(integrator):
               f"U rel diff {eu:.3e}", flush=True)
         assert np.linalg.norm(Rg) <= 1.05 * rec["tol"]
         assert ex <= 1e-5 and eu <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_jacobian_with_solid_block_q2(dtype):
+    """The solid block through a Q2-Q2 fluid grid (4^3 cells of order 2): the same B / B^T with
+    quadratic shape functions, against the oracle's composition, with Dirichlet rows."""
+    import paper_2601_08266_amd as fsi
+    import torch
+    cfg = dataclasses.replace(W.CONFIGS["c2"], grid=W.Grid((4, 4, 4), 2))
+    g = cfg.grid
+    N = g.num_nodes
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    npdt = np.float64 if dtype == "f64" else np.float32
+    X0, conn, U = _mesh(6, 8)
+    Xc = X0 + U
+    tab = fsi.dlm_locate(g, _t(Xc), dtype=tdt, s_max=cfg.s_max)
+    a = W.advection_field(g, cfg.seed_fields).astype(npdt).astype(np.float64)
+    x = W.random_vector(4 * N, cfg.seed_vectors).astype(npdt).astype(np.float64)
+    mask = W.channel_dirichlet_mask(g)
+    mt = torch.tensor(W.mask_to_bits(mask).view(np.int32), device="cuda")
+    prob = fsi.Problem(g, fsi.make_params(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I), _t(a, dtype), tab, None,
+                       s=tab.s, mask=mt)
+    cM, cK, cV = COEFS["all"]
+    y = fsi.jacobian_solid_apply(prob, _solid(X0, conn), _t(U), _t(x, dtype), cM, cK, cV).cpu().numpy()
+    cell, xi = odlm.locate(g, Xc)
+    s = odlm.s_field(g, cell, cfg.s_max)
+    prm_o = ovms.params_array(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
+    ref = osolid.jacobian_apply(g, prm_o, a, x, cell, xi.astype(npdt).astype(np.float64), X0, conn, U, MAT, cM, cK,
+                                cV, s=s, mask=mask)
+    err = field_rel_err(y, ref, 4)
+    print(f"J+solid Q2 {dtype}: rel err {err:.3e} ({tab.n_occ} occupied cells)")
+    assert tab.n_occ > 0 and err <= TOL[dtype]
