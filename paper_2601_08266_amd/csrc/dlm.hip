@@ -395,33 +395,59 @@ __global__ __launch_bounds__(256) void dlm_cell_reduce(Geo g, int64_t m, int64_t
 #pragma unroll
         for (int f = 0; f < 3; ++f) acc[A][f] = T(0);
     const int32_t j0 = occ_start[o], j1 = occ_start[o + 1];
-    for (int32_t j = j0 + lane; j < j1; j += LPC) {
-        const int32_t b = perm[j];
-        T Nx[Q], Ny[Q], Nz[Q];
-        lagrange<T, P>(xi[b], Nx);
-        lagrange<T, P>(xi[m + b], Ny);
-        lagrange<T, P>(xi[2 * m + b], Nz);
-        const T kb = kappa ? kappa[b] : T(1);
-        T mu[3];
-        if constexpr (FROM_U) {
-            T bu[3] = {T(0), T(0), T(0)};
+    // FP32: UB points per lane and round, their sorted positions' point indices loaded together,
+    // then their xi / kappa / src, then accumulated in ascending order (the loads of a round in
+    // flight together instead of one dependent chain per point).  FP64 keeps one point per round:
+    // the extra registers cost it a wave per SIMD, which measured slower.
+    constexpr int UB = sizeof(T) == 4 ? (P == 1 ? 4 : 2) : 1;
+    for (int32_t j = j0 + lane; j < j1; j += LPC * UB) {
+        int32_t bs[UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            const int32_t ju = j + u * LPC;
+            bs[u] = perm[ju < j1 ? ju : j];
+        }
+        T xs[UB][3], kbs[UB], ms[UB][3];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            const int32_t b = bs[u];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) xs[u][d] = xi[d * m + b];
+            kbs[u] = kappa ? kappa[b] : T(1);
+            if constexpr (!FROM_U) {
+#pragma unroll
+                for (int f = 0; f < 3; ++f) ms[u][f] = src[f * m + b];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            if (j + u * LPC >= j1) break;
+            T Nx[Q], Ny[Q], Nz[Q];
+            lagrange<T, P>(xs[u][0], Nx);
+            lagrange<T, P>(xs[u][1], Ny);
+            lagrange<T, P>(xs[u][2], Nz);
+            const T kb = kbs[u];
+            T mu[3];
+            if constexpr (FROM_U) {
+                T bu[3] = {T(0), T(0), T(0)};
+#pragma unroll
+                for (int A = 0; A < NEN; ++A) {
+                    const T w = Nx[A % Q] * Ny[(A / Q) % Q] * Nz[A / (Q * Q)];
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) bu[f] += w * un[f][A];
+                }
+#pragma unroll
+                for (int f = 0; f < 3; ++f) mu[f] = kb * bu[f];
+            } else {
+#pragma unroll
+                for (int f = 0; f < 3; ++f) mu[f] = kb * ms[u][f];
+            }
 #pragma unroll
             for (int A = 0; A < NEN; ++A) {
                 const T w = Nx[A % Q] * Ny[(A / Q) % Q] * Nz[A / (Q * Q)];
 #pragma unroll
-                for (int f = 0; f < 3; ++f) bu[f] += w * un[f][A];
+                for (int f = 0; f < 3; ++f) acc[A][f] += w * mu[f];
             }
-#pragma unroll
-            for (int f = 0; f < 3; ++f) mu[f] = kb * bu[f];
-        } else {
-#pragma unroll
-            for (int f = 0; f < 3; ++f) mu[f] = kb * src[f * m + b];
-        }
-#pragma unroll
-        for (int A = 0; A < NEN; ++A) {
-            const T w = Nx[A % Q] * Ny[(A / Q) % Q] * Nz[A / (Q * Q)];
-#pragma unroll
-            for (int f = 0; f < 3; ++f) acc[A][f] += w * mu[f];
         }
     }
 #pragma unroll
