@@ -414,6 +414,9 @@ def main(argv=None):
     ap.add_argument("--exp-integrator", default="be", choices=["be", "genalpha"],
                     help="time integrator of the probe / warmstart / c5 runs")
     ap.add_argument("--exp-rho-inf", type=float, default=0.5, help="generalized-alpha rho_inf")
+    ap.add_argument("--exp-inflow", type=float, default=1.0, help="solid_steps: inflow velocity")
+    ap.add_argument("--exp-gravity", type=float, default=0.0,
+                    help="solid_steps: body force -g e_z per unit mass on the solid (0: none)")
     ap.add_argument("--exp-c-stiff", type=float, default=0.0,
                     help="solid / solid_steps: stiffness share of the preconditioners' per-point kappa")
     ap.add_argument("--exp-train-end", type=int, default=100)
@@ -565,7 +568,8 @@ def run_experiment(args):
                           **ex.solid_steps(steps=args.exp_steps, precond=args.exp_precond,
                                            vel_steps=args.exp_vel_steps, workload=args.workload,
                                            c_stiff=args.exp_c_stiff, integrator=args.exp_integrator,
-                                           rho_inf=args.exp_rho_inf)}))
+                                           rho_inf=args.exp_rho_inf, inflow=args.exp_inflow,
+                                           gravity=(0.0, 0.0, -args.exp_gravity) if args.exp_gravity else None)}))
         return 0
     if args.experiment == "probe":
         print(json.dumps({"experiment": "newton_probe",

@@ -337,7 +337,8 @@ int fsi_solid_residual(const fsi_solid *solid, const double *U, const double *V,
  * cA = 1 / dt.  Generalized-alpha in stage unknowns (the displacement advancing
  * through its rate V with the fluid's gamma): cU = gamma dt, U_base = U_n +
  * (alpha_f - gamma) dt V_n, cA = alpha_m / (gamma dt alpha_f), A_base = cA V_n -
- * (1 - alpha_m / gamma) Vdot_n.
+ * (1 - alpha_m / gamma) Vdot_n.  A body force f per unit mass on the solid (the
+ * (rho_s - rho_f)(A - f) of eq. solid_weak_form) enters as A_base + f.
  * problem: FP64, Q1, problem->solid NULL, its points (located at the step's
  * configuration) the solid's nodes.
  *   U_base, A_base  double [3][M];  f, gD  double [3][N]

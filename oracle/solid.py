@@ -269,12 +269,15 @@ def jacobian_dense(grid, prm_f, a, cell, xi, X0, conn, U, prm_s, cM, cK, cV, s=N
 # (c_A, c_U, 1) up to the geometric derivatives of M_rho and K_v, which the Newton matrix drops.
 
 
-def residual(X0, conn, U, V, A, prm):
-    """R^s(U, V, A) at the solid nodes ([3][M] arrays)."""
+def residual(X0, conn, U, V, A, prm, body=None):
+    """R^s(U, V, A) at the solid nodes ([3][M] arrays); body: an optional body force per unit mass
+    f ([3] or [3][M]) of the inertia term (rho_s - rho_f)(A - f)."""
     X0 = np.asarray(X0, dtype=np.float64)
     U = np.asarray(U, dtype=np.float64)
     V = np.asarray(V, dtype=np.float64)
     A = np.asarray(A, dtype=np.float64)
+    if body is not None:
+        A = A - np.broadcast_to(np.asarray(body, dtype=np.float64).reshape(3, -1), A.shape)
     R = np.zeros_like(U)
     for e in range(conn.shape[0]):
         nodes = conn[e]
@@ -299,7 +302,7 @@ def step_state(grid, cell, xi, x, Ub, Ab, cU, cA):
 
 
 def step_residual(grid, prm_f, x, f, cell, xi, X0, conn, state, prm_s, s=None, mask=None, gD=None,
-                  visc_strong=True):
+                  visc_strong=True, body=None):
     """R(x) = R_fluid(x; f) + [B^T R^s(Ub + cU B u, B u, cA B u - Ab); 0], Dirichlet rows u - gD
     (state = (Ub, Ab, cU, cA); R_fluid: the VMS step residual with nodal source f)."""
     from . import dlm, vms
@@ -308,7 +311,7 @@ def step_residual(grid, prm_f, x, f, cell, xi, X0, conn, state, prm_s, s=None, m
     R = vms.residual_fluid(grid, prm_f, x, np.asarray(f, dtype=np.float64).reshape(3, N), s=s,
                            visc_strong=visc_strong)
     V, U, A = step_state(grid, cell, xi, x, *state)
-    R[:3] += dlm.apply_BT(grid, cell, xi, residual(X0, conn, U, V, A, prm_s))
+    R[:3] += dlm.apply_BT(grid, cell, xi, residual(X0, conn, U, V, A, prm_s, body=body))
     if mask is not None:
         m = np.asarray(mask, dtype=bool).reshape(3, N)
         gd = np.zeros((3, N)) if gD is None else np.asarray(gD).reshape(3, N)
@@ -317,13 +320,13 @@ def step_residual(grid, prm_f, x, f, cell, xi, X0, conn, state, prm_s, s=None, m
 
 
 def newton_step(grid, prm_f, x0, f, cell, xi, X0, conn, state, prm_s, s=None, mask=None, gD=None,
-                tol_abs=None, rel=1e-8, max_newton=30, visc_strong=True):
+                tol_abs=None, rel=1e-8, max_newton=30, visc_strong=True, body=None):
     """Newton on step_residual from x0 with the matrix A(a = u_k) + B^T K_s(U_k) B, K_s with
     (c_A, c_U, 1) (dense solves); returns (x, U, V, info) at the converged x."""
     N = grid.num_nodes
     Ub, Ab, cU, cA = state
     x = np.asarray(x0, dtype=np.float64).reshape(4, N).copy()
-    R = step_residual(grid, prm_f, x, f, cell, xi, X0, conn, state, prm_s, s, mask, gD, visc_strong)
+    R = step_residual(grid, prm_f, x, f, cell, xi, X0, conn, state, prm_s, s, mask, gD, visc_strong, body)
     hist = [np.linalg.norm(R)]
     if tol_abs is None:
         tol_abs = rel * hist[0]
@@ -334,14 +337,14 @@ def newton_step(grid, prm_f, x0, f, cell, xi, X0, conn, state, prm_s, s=None, ma
         J = jacobian_dense(grid, prm_f, x[:3].copy(), cell, xi, X0, conn, U, prm_s, cA, cU, 1.0, s=s,
                            mask=mask, visc_strong=visc_strong)
         x = x + np.linalg.solve(J, -R.ravel()).reshape(4, N)
-        R = step_residual(grid, prm_f, x, f, cell, xi, X0, conn, state, prm_s, s, mask, gD, visc_strong)
+        R = step_residual(grid, prm_f, x, f, cell, xi, X0, conn, state, prm_s, s, mask, gD, visc_strong, body)
         hist.append(np.linalg.norm(R))
     V, U, _ = step_state(grid, cell, xi, x, *state)
     return x, U, V, {"history": hist, "tol_abs": tol_abs, "converged": hist[-1] <= tol_abs}
 
 
 def genalpha_step(grid, prm_stage, coefs, dt, x_n, xdot_n, Vs_n, Vsdot_n, U_n, cell, xi, X0, conn, prm_s,
-                  s=None, mask=None, gD_stage=None, tol_abs=None, rel=1e-8):
+                  s=None, mask=None, gD_stage=None, tol_abs=None, rel=1e-8, body=None):
     """One generalized-alpha step of the coupled system in stage unknowns (the fluid as in
     oracle.genalpha: mass coefficient c = alpha_m / (gamma dt alpha_f) in prm_stage, source
     c V_n - (1 - alpha_m/gamma) Vdot_n; the solid velocity Vs = B u, its rate Vsdot and its
@@ -359,7 +362,7 @@ def genalpha_step(grid, prm_stage, coefs, dt, x_n, xdot_n, Vs_n, Vsdot_n, U_n, c
         m = np.asarray(mask, dtype=bool).reshape(3, N)
         x0[:3][m] = np.asarray(gD_stage).reshape(3, N)[m]
     x_st, _, Vs_st, info = newton_step(grid, prm_stage, x0, f, cell, xi, X0, conn, state, prm_s, s=s, mask=mask,
-                                       gD=gD_stage, tol_abs=tol_abs, rel=rel)
+                                       gD=gD_stage, tol_abs=tol_abs, rel=rel, body=body)
     x1 = x_n + (x_st - x_n) / af
     xdot1 = xdot_n + (x1 - x_n - dt * xdot_n) / (gm * dt)
     Vs1 = Vs_n + (Vs_st - Vs_n) / af

@@ -380,7 +380,7 @@ def solid_solve(rtol=1e-8, restart=50, max_iters=3000, precond="schur_tri", vel_
 
 
 def solid_steps(steps=3, precond="schur_tri", vel_steps=8, inner="f32", workload="c2", inflow=1.0, c_stiff=0.0,
-                integrator="be", rho_inf=0.5):
+                integrator="be", rho_inf=0.5, gravity=None):
     """Coupled time steps with the elastic plates moving with the fluid (the configuration's
     channel, the plates meshed by hexahedra with about the configuration's point count, stress
     free at rest; inflow u_x = `inflow` on x = 0 from a fluid at rest) through
@@ -394,7 +394,7 @@ def solid_steps(steps=3, precond="schur_tri", vel_steps=8, inner="f32", workload
     n_t, n_f = W.solid_mesh_size(cfg.m_points)
     X0, conn = W.plate_solid_mesh(n_t, n_f)
     run = SolidChannel(cfg, X0, conn, integrator=integrator, rho_inf=rho_inf, precond=precond, vel_steps=vel_steps,
-                       inner=inner, inflow=inflow, kappa=solid_kappa(cfg, X0.shape[1], c_stiff))
+                       inner=inner, inflow=inflow, kappa=solid_kappa(cfg, X0.shape[1], c_stiff), gravity=gravity)
     rows = []
     for _ in range(steps):
         rec = run.step()
@@ -409,4 +409,4 @@ def solid_steps(steps=3, precond="schur_tri", vel_steps=8, inner="f32", workload
     return {"workload": f"{g.n[0]}^3 Q1 channel, elastic plates meshed by {conn.shape[0]} hexahedra "
                         f"({X0.shape[1]} nodes), inflow {inflow}, dt {cfg.dt}",
             "integrator": integrator, "rho_inf": rho_inf if integrator != "be" else None, "precond": precond,
-            "vel_steps": vel_steps, "inner": inner, "c_stiff": c_stiff, "steps": rows}
+            "vel_steps": vel_steps, "inner": inner, "c_stiff": c_stiff, "gravity": gravity, "steps": rows}

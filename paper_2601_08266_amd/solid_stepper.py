@@ -36,7 +36,7 @@ class SolidChannel:
     walls) with a solid mesh (X0 [3][M], conn [E][8]) that starts at rest and stress free."""
 
     def __init__(self, cfg, X0, conn, integrator="be", rho_inf=0.5, precond="schur_tri", vel_steps=8,
-                 inner="f32", inflow=1.0, kappa=None, rel_tol=1e-8, max_krylov=6000):
+                 inner="f32", inflow=1.0, kappa=None, rel_tol=1e-8, max_krylov=6000, gravity=None):
         dev = torch.device("cuda")
         self.cfg, self.g = cfg, cfg.grid
         self.dev = dev
@@ -66,6 +66,12 @@ class SolidChannel:
             mat = W.SOLID_MATERIAL
             kappa = np.full(self.M, cfg.c_m * (mat["rho_s0"] - mat["rho_f"]) * W.plate_volume() / self.M)
         self.kappa = np.asarray(kappa, dtype=np.float64)
+        # a body force per unit mass on the solid (eq. solid_weak_form's (rho_s - rho_f)(A - f)):
+        # it shifts the acceleration, A - f = c_A V - (A_base + f); the fluid's own weight is
+        # balanced by the hydrostatic pressure and left out
+        self.body = None
+        if gravity is not None:
+            self.body = torch.tensor(np.repeat(np.asarray(gravity, dtype=np.float64), self.M), device=dev)
         self.n = 0
 
     def _t(self, v, dt=torch.float64):
@@ -97,6 +103,8 @@ class SolidChannel:
         Ab = torch.empty_like(self.Vs)
         axpby(c, self.Vs, 0.0, Ab)
         axpby(-r, self.Vsdot, 1.0, Ab)
+        if self.body is not None:
+            axpby(1.0, self.body, 1.0, Ab)
         state = (Ub, Ab, gm * dt, c)
         x_st = self.x.clone()
         R0, _, _ = solid_step_residual(probs[0], self.solid, state, f, x_st, gD=self.gD)

@@ -527,3 +527,40 @@ def test_jacobian_with_solid_block_q2(dtype):
     err = field_rel_err(y, ref, 4)
     print(f"J+solid Q2 {dtype}: rel err {err:.3e} ({tab.n_occ} occupied cells)")
     assert tab.n_occ > 0 and err <= TOL[dtype]
+
+
+def test_solid_channel_with_gravity_matches_oracle():
+    """Plates released from rest under a body force (no inflow): two generalized-alpha steps of
+    the library's stepper against the oracle's steps with the same body force."""
+    from paper_2601_08266_amd.solid_stepper import SolidChannel, ga_coefficients
+    cfg = dataclasses.replace(W.CONFIGS["c2"], grid=W.Grid((8, 8, 8), 1))
+    g = cfg.grid
+    N = g.num_nodes
+    X0, conn = W.plate_solid_mesh(6, 8)
+    M = X0.shape[1]
+    grav = (0.0, 0.0, -9.81)
+    run = SolidChannel(cfg, X0, conn, integrator="genalpha", rho_inf=0.5, precond="schur_tri", vel_steps=4,
+                       inflow=0.0, gravity=grav)
+    coefs = ga_coefficients(0.5)
+    am, af, gm = coefs
+    dt = cfg.dt
+    prm_stage = ovms.params_array(cfg.nu, am / (gm * dt * af), dt, cfg.C_T, cfg.C_I)
+    mask = W.channel_dirichlet_mask(g)
+    gD = np.zeros((3, N))
+    ref = dict(x=np.zeros((4, N)), xd=np.zeros((4, N)), Vs=np.zeros((3, M)), Vsd=np.zeros((3, M)), U=np.zeros((3, M)))
+    for step in range(2):
+        rec = run.step()
+        assert rec["status"] == 0
+        co, xio = odlm.locate(g, X0 + ref["U"])
+        x1, xd1, Vs1, Vsd1, U1, _, info = osolid.genalpha_step(
+            g, prm_stage, coefs, dt, ref["x"], ref["xd"], ref["Vs"], ref["Vsd"], ref["U"], co, xio, X0, conn, MAT,
+            s=odlm.s_field(g, co, cfg.s_max), mask=mask, gD_stage=gD, tol_abs=rec["tol"], body=np.array(grav))
+        assert info["converged"]
+        ref = dict(x=x1, xd=xd1, Vs=Vs1, Vsd=Vsd1, U=U1)
+        ev = np.linalg.norm(run.Vs.cpu().numpy() - Vs1.ravel()) / np.linalg.norm(Vs1)
+        ex = np.linalg.norm(run.x.cpu().numpy() - x1.ravel()) / np.linalg.norm(x1)
+        print(f"gravity step {step}: {rec['newton']} Newton / {rec['krylov']} Krylov; solid velocity z mean "
+              f"{run.Vs.cpu().numpy().reshape(3, M)[2].mean():.3e} (oracle {Vs1[2].mean():.3e}); "
+              f"x rel diff {ex:.3e}, Vs rel diff {ev:.3e}", flush=True)
+        assert Vs1[2].mean() < 0.0          # the plates start to fall
+        assert ex <= 1e-5 and ev <= 1e-5

@@ -367,3 +367,20 @@ def test_coupled_genalpha_with_unit_coefficients_is_backward_euler():
     assert np.abs(x1 - xb).max() <= 1e-12 * np.abs(xb).max()
     assert np.abs(U1 - Ub).max() <= 1e-12 * np.abs(Ub).max()
     np.testing.assert_allclose(Vs1, Vb, rtol=1e-10, atol=1e-12 * np.abs(Vb).max())
+
+
+def test_body_force_enters_as_a_shift_of_the_acceleration():
+    """R^s(U, V, A; f) = R^s(U, V, A - f): the body force of eq. solid_weak_form's inertia term;
+    a stress-free solid at rest in free fall (A = f) has zero residual."""
+    X, conn = W.plate_solid_mesh(3, 4)
+    M = X.shape[1]
+    U = W.solid_displacement(X, 5)
+    rng = np.random.default_rng(4)
+    V = 0.1 * rng.standard_normal((3, M))
+    A = rng.standard_normal((3, M))
+    fb = np.array([0.0, 0.0, -9.81])
+    np.testing.assert_allclose(solid.residual(X, conn, U, V, A, PRM, body=fb),
+                               solid.residual(X, conn, U, V, A - fb[:, None], PRM), rtol=1e-14, atol=1e-14)
+    zero = np.zeros((3, M))
+    R = solid.residual(X, conn, zero, zero, np.tile(fb[:, None], (1, M)), PRM, body=fb)
+    assert np.abs(R).max() <= 1e-15 * np.abs(solid.residual(X, conn, zero, zero, np.tile(fb[:, None], (1, M)), PRM)).max()
