@@ -246,15 +246,42 @@ __global__ __launch_bounds__(256) void sum_ranges_k(int64_t n, int nranges, cons
 }
 
 // db partials: partial[r][c] = sum_{v in range r} dY[v][c]
+// (c <= 256: the block's 256 / c voxel groups take interleaved voxels of the range, four
+// independent sums per thread, then the groups are added in a fixed order through LDS)
 __global__ __launch_bounds__(256) void bias_grad_k(int64_t V, int c, int range, const uint16_t *__restrict__ dY,
                                                    float *__restrict__ partial)
 {
+    __shared__ float red[256];
     const int r = blockIdx.x;
-    for (int ch = threadIdx.x; ch < c; ch += 256) {
-        float s = 0.f;
-        const int64_t vb = (int64_t)r * range, ve = vb + range < V ? vb + range : V;
-        for (int64_t v = vb; v < ve; ++v) s += bf2f(dY[v * c + ch]);
-        partial[(int64_t)r * c + ch] = s;
+    const int64_t vb = (int64_t)r * range, ve = vb + range < V ? vb + range : V;
+    if (c > 256) {
+        for (int ch = threadIdx.x; ch < c; ch += 256) {
+            float s = 0.f;
+            for (int64_t v = vb; v < ve; ++v) s += bf2f(dY[v * c + ch]);
+            partial[(int64_t)r * c + ch] = s;
+        }
+        return;
+    }
+    const int t = threadIdx.x, groups = 256 / c, ch = t % c, grp = t / c;
+    float s = 0.f;
+    if (grp < groups) {
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        int64_t v = vb + grp;
+        for (; v + 3 * groups < ve; v += 4 * groups) {
+            s0 += bf2f(dY[v * c + ch]);
+            s1 += bf2f(dY[(v + groups) * c + ch]);
+            s2 += bf2f(dY[(v + 2 * groups) * c + ch]);
+            s3 += bf2f(dY[(v + 3 * groups) * c + ch]);
+        }
+        for (; v < ve; v += groups) s0 += bf2f(dY[v * c + ch]);
+        s = (s0 + s1) + (s2 + s3);
+    }
+    red[t] = s;
+    __syncthreads();
+    if (t < c) {
+        float acc = 0.f;
+        for (int gi = 0; gi < groups; ++gi) acc += red[gi * c + t];
+        partial[(int64_t)r * c + t] = acc;
     }
 }
 

@@ -68,7 +68,8 @@ def test_conv_forward_and_data_gradient(dims, cin, cout):
 
 
 @pytest.mark.parametrize("dims,cin,cout", [((7, 5, 6), 32, 64), ((13, 11, 17), 64, 64),
-                                           ((4, 4, 3), 64, 32), ((65, 65, 65), 64, 64)])
+                                           ((4, 4, 3), 64, 32), ((65, 65, 65), 64, 64),
+                                           ((5, 6, 7), 32, 96), ((3, 4, 5), 32, 288)])
 def test_conv_weight_gradient(dims, cin, cout):
     import torch
     import paper_2601_08266_amd.warmstart as ws
