@@ -15,9 +15,10 @@
 // weight fragment feeds 4 MFMAs and an input fragment 4.  The data gradient is
 // the same kernel on flipped, transposed weights, with the ReLU mask of the
 // previous layer applied in the epilogue.
-// Weight gradient (split K): block (voxel range, tap) stages 32 voxels of dY
-// and of the shifted input in LDS and accumulates the 64x64 tap block with 16
-// MFMA tiles; ranges are summed in a fixed order afterwards (deterministic).
+// Weight gradient (split K): block (voxel range, tap) stages 64 voxels of dY
+// and of the shifted input, transposed, in LDS and accumulates the 64x64 tap
+// block with 16 MFMA tiles; ranges are summed in a fixed order afterwards
+// (deterministic).
 #include "nn.hpp"
 #include "profile.hpp"
 
@@ -165,15 +166,22 @@ __global__ __launch_bounds__(256) void conv_fwd_k(int nx, int ny, int nz, int ci
 }
 
 // ---------------------------------------------------------------- weight gradient
-constexpr int WG_K = 32;   // voxels per K step
+constexpr int WG_K = 64;          // voxels per K step
+constexpr int WG_S = WG_K + 8;    // LDS row stride (bf16) of a transposed tile: 144 B, so the 16 rows
+                                  // one 16-lane group reads start on distinct 4-bank groups
 
+// Both MFMA operands need 8 consecutive voxels of one channel per lane, while the activations are
+// channel-contiguous: each step stages 64 voxels x 64 channels of dY and of the shifted input
+// transposed in LDS ([channel][voxel], pairs of voxels packed in one 32-bit write), so a fragment
+// is one 128-bit LDS read.  The tiles are double buffered: the next step's global loads are in
+// flight during this step's MFMAs, one barrier per step.
 __global__ __launch_bounds__(256) void conv_wgrad_k(int nx, int ny, int nz, int cin, int cout,
                                                     int range, const uint16_t *__restrict__ dY,
                                                     const uint16_t *__restrict__ X,
                                                     float *__restrict__ partial)
 {
-    __shared__ uint16_t sdy[WG_K][64];
-    __shared__ uint16_t sx[WG_K][64];
+    __shared__ __attribute__((aligned(16))) uint16_t sdy[2][64 * WG_S];
+    __shared__ __attribute__((aligned(16))) uint16_t sx[2][64 * WG_S];
     const int64_t V = (int64_t)nx * ny * nz;
     const int r = blockIdx.x, tap = blockIdx.y;
     const int co0 = blockIdx.z / ((cin + 63) / 64) * 64;
@@ -182,45 +190,72 @@ __global__ __launch_bounds__(256) void conv_wgrad_k(int nx, int ny, int nz, int 
     const int nci = cin - ci0 < 64 ? cin - ci0 : 64;
     const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // staging role: voxels 2p, 2p + 1 of the step, channels 8g .. 8g + 7
+    const int p = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const bool gy = 8 * g < mco, gx = 8 * g < nci;
+    const int64_t vbeg = (int64_t)r * range;
+    const int64_t vend = vbeg + range < V ? vbeg + range : V;
+    const int nsteps = (int)((vend - vbeg + WG_K - 1) / WG_K);
+    uint4 ry[2], rx[2];
+    auto load = [&](int step) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t v = vbeg + (int64_t)step * WG_K + 2 * p + h;
+            uint4 zy = make_uint4(0, 0, 0, 0), zx = make_uint4(0, 0, 0, 0);
+            if (v < vend) {
+                if (gy) zy = *reinterpret_cast<const uint4 *>(dY + v * cout + co0 + 8 * g);
+                // lattices hold fewer than 2^31 voxels: 32-bit index arithmetic
+                const uint32_t u = (uint32_t)v, uxy = u / (uint32_t)nx;
+                const int x = (int)(u - uxy * (uint32_t)nx), y = (int)(uxy % (uint32_t)ny), z = (int)(uxy / (uint32_t)ny);
+                const int xs = x + dx, ys = y + dy, zs = z + dz;
+                if (gx && xs >= 0 && xs < nx && ys >= 0 && ys < ny && zs >= 0 && zs < nz) {
+                    const int64_t vs = xs + (int64_t)nx * (ys + (int64_t)ny * zs);
+                    zx = *reinterpret_cast<const uint4 *>(X + vs * cin + ci0 + 8 * g);
+                }
+            }
+            ry[h] = zy;
+            rx[h] = zx;
+        }
+    };
+    auto store = [&](int buf) {
+        const uint32_t y0[4] = {ry[0].x, ry[0].y, ry[0].z, ry[0].w}, y1[4] = {ry[1].x, ry[1].y, ry[1].z, ry[1].w};
+        const uint32_t x0[4] = {rx[0].x, rx[0].y, rx[0].z, rx[0].w}, x1[4] = {rx[1].x, rx[1].y, rx[1].z, rx[1].w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            // channel 8g + 2q: low halves of the two voxels' words; channel 8g + 2q + 1: high halves
+            const int c = 8 * g + 2 * q;
+            *reinterpret_cast<uint32_t *>(&sdy[buf][c * WG_S + 2 * p]) = (y0[q] & 0xffffu) | (y1[q] << 16);
+            *reinterpret_cast<uint32_t *>(&sdy[buf][(c + 1) * WG_S + 2 * p]) = (y0[q] >> 16) | (y1[q] & 0xffff0000u);
+            *reinterpret_cast<uint32_t *>(&sx[buf][c * WG_S + 2 * p]) = (x0[q] & 0xffffu) | (x1[q] << 16);
+            *reinterpret_cast<uint32_t *>(&sx[buf][(c + 1) * WG_S + 2 * p]) = (x0[q] >> 16) | (x1[q] & 0xffff0000u);
+        }
+    };
     // this wave's 4 tiles of the 4x4 grid of 16x16 tiles: (mt = w, nt = 0..3)
     f4 acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = (f4){0.f, 0.f, 0.f, 0.f};
-    const int64_t vbeg = (int64_t)r * range;
-    const int64_t vend = vbeg + range < V ? vbeg + range : V;
-    for (int64_t k0 = vbeg; k0 < vend; k0 += WG_K) {
-        // stage 32 voxels x 64 channels of dY and of the shifted input (8 channels per thread)
-        {
-            const int row = threadIdx.x >> 3, cb = (threadIdx.x & 7) * 8;
-            const int64_t v = k0 + row;
-            uint4 zy = make_uint4(0, 0, 0, 0), zx = make_uint4(0, 0, 0, 0);
-            if (v < vend) {
-                if (cb < mco) zy = *reinterpret_cast<const uint4 *>(dY + v * cout + co0 + cb);
-                const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((int64_t)nx * ny));
-                const int xs = x + dx, ys = y + dy, zs = z + dz;
-                if (cb < nci && xs >= 0 && xs < nx && ys >= 0 && ys < ny && zs >= 0 && zs < nz) {
-                    const int64_t vs = xs + (int64_t)nx * (ys + (int64_t)ny * zs);
-                    zx = *reinterpret_cast<const uint4 *>(X + vs * cin + ci0 + cb);
-                }
+    if (nsteps > 0) {
+        load(0);
+        store(0);
+    }
+    __syncthreads();
+    const int kq = 8 * (lane >> 4);
+    for (int step = 0; step < nsteps; ++step) {
+        const int buf = step & 1;
+        const bool more = step + 1 < nsteps;
+        if (more) load(step + 1);
+#pragma unroll
+        for (int kh = 0; kh < WG_K / 32; ++kh) {
+            // A (M = co, K = voxel): row co = 16 w + lane % 16; B (K = voxel, N = ci): column lane % 16
+            const bf8 a = *reinterpret_cast<const bf8 *>(&sdy[buf][(16 * w + (lane & 15)) * WG_S + 32 * kh + kq]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const bf8 b = *reinterpret_cast<const bf8 *>(&sx[buf][(16 * t + (lane & 15)) * WG_S + 32 * kh + kq]);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
             }
-            *reinterpret_cast<uint4 *>(&sdy[row][cb]) = zy;
-            *reinterpret_cast<uint4 *>(&sx[row][cb]) = zx;
         }
-        __syncthreads();
-        const int kq = 8 * (lane >> 4);
-        // A (M = co, K = voxel): rows co = 16 w + lane%16
-        uint16_t av[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) av[e] = sdy[kq + e][16 * w + (lane & 15)];
-        const bf8 a = __builtin_bit_cast(bf8, av);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            uint16_t bv[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) bv[e] = sx[kq + e][16 * t + (lane & 15)];
-            const bf8 b = __builtin_bit_cast(bf8, bv);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
-        }
+        // the other buffer was last read in the previous step, which every wave has finished
+        if (more) store(buf ^ 1);
         __syncthreads();
     }
     // partial[r][tap][co][ci]

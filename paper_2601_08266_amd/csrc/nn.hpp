@@ -7,7 +7,7 @@
 
 namespace fsi {
 
-constexpr int NN_WG_RANGE = 2048;   // voxels per weight-gradient range (multiple of 32)
+constexpr int NN_WG_RANGE = 4096;   // voxels per weight-gradient range (multiple of 64)
 
 typedef fsi_nn_pack_spec NnPack;
 typedef fsi_nn_unpack_spec NnUnpack;
