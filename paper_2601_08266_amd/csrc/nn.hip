@@ -7,12 +7,13 @@
 // i + nx (j + ny k)); weights [27][Cout][Cin] with tap = dx + 3 (dy + 3 dz)
 // reading the neighbour at offset (dx - 1, dy - 1, dz - 1); zero padding.
 //
-// Forward / data gradient (implicit GEMM): a block owns 256 voxels x 64 output
-// channels, each wave 64 voxels x 64 channels (16 accumulator tiles).  The K
-// loop runs over the 27 taps x Cin/32 chunks; per step the block stages the
-// chunk's 64 x 32 weights in LDS (double buffered, one barrier per step), and
-// each lane loads 8 consecutive input channels of its 4 (shifted) voxels, so a
-// weight fragment feeds 4 MFMAs and an input fragment 4.  The data gradient is
+// Forward / data gradient (implicit GEMM): a block owns 128 voxels x 64 output
+// channels, each wave 32 voxels x 64 channels (8 accumulator tiles; 5 waves per
+// SIMD, where 64-voxel waves fit 3 and left the second round of blocks at 65^3
+// mostly empty).  The K loop runs over the 27 taps x Cin/32 chunks; per step the
+// block stages the chunk's 64 x 32 weights in LDS (double buffered, one barrier
+// per step), and each lane loads 8 consecutive input channels of its 2 (shifted)
+// voxels, so a weight fragment feeds 2 MFMAs and an input fragment 4.  The data gradient is
 // the same kernel on flipped, transposed weights, with the ReLU mask of the
 // previous layer applied in the epilogue.
 // Weight gradient (split K): block (voxel range, tap) stages 64 voxels of dY
@@ -51,7 +52,7 @@ __device__ __forceinline__ bf8 zero8()
 }
 
 // ---------------------------------------------------------------- forward / dgrad
-constexpr int CF_MT = 4;                 // 16-voxel M tiles per wave
+constexpr int CF_MT = 2;                 // 16-voxel M tiles per wave
 constexpr int CF_VB = 64 * CF_MT;        // voxels per block (4 waves)
 constexpr int CF_WS = 40;                // LDS row stride (bf16) of a staged weight chunk: 32 + 8 pad
 
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(256) void conv_fwd_k(int nx, int ny, int nz, int ci
     __shared__ __attribute__((aligned(16))) uint16_t sW[2][64 * CF_WS];
     const int64_t V = (int64_t)nx * ny * nz;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int64_t vw = (int64_t)blockIdx.x * CF_VB + 64 * w;     // first voxel of this wave
+    const int64_t vw = (int64_t)blockIdx.x * CF_VB + 16 * CF_MT * w;   // first voxel of this wave
     const int co0 = blockIdx.y * 64;
     const int ntiles = (cout - co0) >= 64 ? 4 : (cout - co0) / 16;
     const int kq = 8 * (lane >> 4);
