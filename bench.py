@@ -577,12 +577,14 @@ def run_experiment(args):
                                               rho_inf=args.exp_rho_inf)}))
         return 0
     if args.experiment == "warmstart":
-        summary, lw = ex.warmstart_c4(steps=args.exp_steps, train_end=args.exp_train_end,
-                                      epochs=args.exp_epochs, eval_stride=args.exp_stride,
-                                      save_path=args.exp_save, precond=args.exp_precond,
-                                      integrator=args.exp_integrator, rho_inf=args.exp_rho_inf,
-                                      vel_steps=args.exp_vel_steps)
-        print(json.dumps({"experiment": "warmstart_c4", **summary}))
+        # --workload c5: the 192^3 run trained on its own first steps
+        key = "c5" if args.workload == "c5" else "c4"
+        summary, lw = ex.warmstart(key, steps=args.exp_steps, train_end=args.exp_train_end,
+                                   epochs=args.exp_epochs, eval_stride=args.exp_stride,
+                                   save_path=args.exp_save, precond=args.exp_precond,
+                                   integrator=args.exp_integrator, rho_inf=args.exp_rho_inf,
+                                   vel_steps=args.exp_vel_steps)
+        print(json.dumps({"experiment": "warmstart_" + key, **summary}))
         return 0
     summary = ex.large_c5(state_path=args.exp_load, modes=modes, integrator=args.exp_integrator,
                           rho_inf=args.exp_rho_inf)

@@ -1,14 +1,15 @@
 """Measurement drivers for the Newton-step workloads (orchestration only).
 
-warmstart_c4: 64^3 Q1 channel, three rotating plates (200k points), 200
-  implicit steps with the plain guess (mixed-precision Newton); the network is
-  trained on samples from steps 1-100 and evaluated on steps 101-200, where
-  every step is re-solved from the recorded state three ways: plain guess with
-  FP64 inner Krylov applies, plain guess with FP32 inner applies, learned guess
-  with FP32 inner applies.  All three stop at the same absolute residual.
+warmstart: a channel run (64^3 Q1 with three rotating plates and 200k points,
+  or 192^3 with 2M points) stepped with the plain guess (mixed-precision Newton);
+  the network is trained on samples from the first steps (1-100 of 200 at 64^3,
+  1-20 of 40 at 192^3) and evaluated on the rest, where every step is re-solved
+  from the recorded state: plain guess with FP64 inner Krylov applies, plain
+  guess with FP32 inner applies, extrapolated and learned guesses with FP32
+  inner applies.  All stop at the same absolute residual.
 large_c5: 192^3 Q1 channel, 2M points: after warm-up steps, one Newton step
-  plain FP64 vs mixed precision + learned warm start (the 64^3 network applied
-  fully convolutionally to the finer lattice).
+  plain FP64 vs mixed precision + learned warm start (a 64^3-trained network
+  applied fully convolutionally to the finer lattice).
 """
 from __future__ import annotations
 
@@ -74,16 +75,22 @@ def _solve_modes(run, lw, k, modes):
     return out
 
 
-def warmstart_c4(steps=200, train_end=100, epochs=20, lr=1e-3, eval_stride=1, seed=0,
-                 save_path=None, precond="bjacobi", integrator="be", rho_inf=0.5, vel_steps=0):
-    cfg = W.CONFIGS["c4"]
+WARMSTART_WORKLOADS = {
+    "c4": "64^3 Q1 channel, 200k points on three rotating plates, dt=1e-3",
+    "c5": "192^3 Q1 channel, 2M points on three rotating plates, dt=1e-3",
+}
+
+
+def warmstart(cfg_key="c4", steps=200, train_end=100, epochs=20, lr=1e-3, eval_stride=1, seed=0,
+              save_path=None, precond="bjacobi", integrator="be", rho_inf=0.5, vel_steps=0):
+    cfg = W.CONFIGS[cfg_key]
     run = ChannelRun(cfg, precond=precond, integrator=integrator, rho_inf=rho_inf, vel_steps=vel_steps)
     run.record_extrap = True
     t0 = time.perf_counter()
     for n in range(steps):
         rec = run.step()
         if (n + 1) % 10 == 0 or n < 3:
-            _log(f"c4 step {rec.n}: t={rec.t:.3f} inflow={rec.inflow:+.3f} newton={rec.newton_iters} "
+            _log(f"{cfg_key} step {rec.n}: t={rec.t:.3f} inflow={rec.inflow:+.3f} newton={rec.newton_iters} "
                  f"krylov={rec.krylov_iters} {rec.ms_newton:.1f} ms")
     sim_s = time.perf_counter() - t0
     lw = LearnedWarmStart(run, seed=seed)
@@ -113,7 +120,7 @@ def warmstart_c4(steps=200, train_end=100, epochs=20, lr=1e-3, eval_stride=1, se
         return statistics.mean(r[mode][key] for r in rows)
 
     summary = {
-        "workload": "64^3 Q1 channel, 200k points on three rotating plates, dt=1e-3",
+        "workload": WARMSTART_WORKLOADS[cfg_key],
         "precond": precond, "vel_steps": vel_steps, "integrator": integrator,
         "steps": steps, "train_steps": [2, train_end], "eval_steps": [train_end + 1, steps],
         "epochs": epochs, "params": lw.net.n_params, "train_ms": round(lw.train_ms, 1),
