@@ -281,6 +281,24 @@ __global__ __launch_bounds__(256) void sum_ranges_k(int64_t n, int nranges, cons
     out[i] = s;
 }
 
+// Few outputs over many ranges (the bias gradient): one block per output, thread t sums ranges
+// t, t + 256, ... in order, then a fixed pairing tree in LDS (deterministic).
+__global__ __launch_bounds__(256) void sum_ranges_wide_k(int64_t n, int nranges, const float *__restrict__ partial,
+                                                         float *__restrict__ out)
+{
+    __shared__ float red[256];
+    const int64_t i = blockIdx.x;
+    float s = 0.f;
+    for (int r = threadIdx.x; r < nranges; r += 256) s += partial[(int64_t)r * n + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = red[0];
+}
+
 // db partials: partial[r][c] = sum_{v in range r} dY[v][c]
 // (c <= 256: the block's 256 / c voxel groups take interleaved voxels of the range, four
 // independent sums per thread, then the groups are added in a fixed order through LDS)
@@ -476,8 +494,9 @@ size_t nn_wgrad_workspace(const int32_t *dims, int cin, int cout)
 {
     const int64_t V = (int64_t)dims[0] * dims[1] * dims[2];
     const int64_t nr = (V + NN_WG_RANGE - 1) / NN_WG_RANGE;
+    const int64_t nrb = (V + NN_BG_RANGE - 1) / NN_BG_RANGE;
     return align_up((size_t)nr * 27 * cin * cout * sizeof(float)) +
-           align_up((size_t)nr * cout * sizeof(float));
+           align_up((size_t)nrb * cout * sizeof(float));
 }
 
 int nn_conv_wgrad(const int32_t *dims, int cin, int cout, const uint16_t *dY, const uint16_t *X, float *dW,
@@ -497,9 +516,10 @@ int nn_conv_wgrad(const int32_t *dims, int cin, int cout, const uint16_t *dY, co
     hipLaunchKernelGGL(sum_ranges_k, dim3(nb(nw)), dim3(256), 0, st, nw, nr, part, dW);
     FSI_LAUNCH_CHECK();
     if (db) {
-        hipLaunchKernelGGL(bias_grad_k, dim3(nr), dim3(256), 0, st, V, cout, NN_WG_RANGE, dY, bpart);
+        const int nrb = (int)((V + NN_BG_RANGE - 1) / NN_BG_RANGE);
+        hipLaunchKernelGGL(bias_grad_k, dim3(nrb), dim3(256), 0, st, V, cout, NN_BG_RANGE, dY, bpart);
         FSI_LAUNCH_CHECK();
-        hipLaunchKernelGGL(sum_ranges_k, dim3(nb(cout)), dim3(256), 0, st, (int64_t)cout, nr, bpart, db);
+        hipLaunchKernelGGL(sum_ranges_wide_k, dim3(cout), dim3(256), 0, st, (int64_t)cout, nrb, bpart, db);
         FSI_LAUNCH_CHECK();
     }
     return FSI_OK;

@@ -8,6 +8,7 @@
 namespace fsi {
 
 constexpr int NN_WG_RANGE = 4096;   // voxels per weight-gradient range (multiple of 64)
+constexpr int NN_BG_RANGE = 512;    // voxels per bias-gradient range
 
 typedef fsi_nn_pack_spec NnPack;
 typedef fsi_nn_unpack_spec NnUnpack;
