@@ -379,13 +379,20 @@ __global__ __launch_bounds__(256) void mse_k(int64_t V, int c, int used, const f
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-__global__ void sum_partials_d(int n, const double *__restrict__ partial, double *__restrict__ out)
+// one block: thread t sums partials t, t + 256, ... in order, then a fixed pairing tree
+__global__ __launch_bounds__(256) void sum_partials_d(int n, const double *__restrict__ partial,
+                                                      double *__restrict__ out)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += partial[i];
-        out[0] = s;
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += partial[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) out[0] = red[0];
 }
 
 __global__ __launch_bounds__(256) void adam_k(int64_t n, float *__restrict__ w, const float *__restrict__ g,
@@ -541,7 +548,7 @@ int nn_mse(int64_t V, int c, int used, const float *pred, const float *target, u
     double *part = reinterpret_cast<double *>(ws);
     hipLaunchKernelGGL(mse_k, dim3(1024), dim3(256), 0, st, V, c, used, pred, target, dpred, part);
     FSI_LAUNCH_CHECK();
-    hipLaunchKernelGGL(sum_partials_d, dim3(1), dim3(64), 0, st, 1024, part, part + 1024);
+    hipLaunchKernelGGL(sum_partials_d, dim3(1), dim3(256), 0, st, 1024, part, part + 1024);
     FSI_LAUNCH_CHECK();
     if (loss_host) {
         double s = 0.0;
