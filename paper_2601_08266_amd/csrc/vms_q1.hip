@@ -582,14 +582,31 @@ __global__ __launch_bounds__(256) void vms_gather(Geo g, const T *__restrict__ p
     }
     T acc[4] = {T(0), T(0), T(0), T(0)};
     const PartIndex pi(g.nn, nbx, P * BX);
-    for (int iz = 0; iz < nzb; ++iz)
-        for (int iy = 0; iy < nyb; ++iy)
-            for (int ix = 0; ix < nxb; ++ix) {
-                const int cls = (bxs[ix] & 1) + 2 * (bys[iy] & 1) + 4 * (bzs[iz] & 1);
-                const T *pc = part + pi.at(cls, bxs[ix], gx, gy, gz);
+    // the up to 8 bricks' partials are all loaded before any is added (a node on a brick face
+    // would otherwise wait for one load round per brick), then summed in the fixed order z, y, x
+    T pv[2][2][2][4];
 #pragma unroll
-                for (int f = 0; f < 4; ++f) acc[f] += pc[f * pi.field];
-            }
+    for (int iz = 0; iz < 2; ++iz)
+#pragma unroll
+        for (int iy = 0; iy < 2; ++iy)
+#pragma unroll
+            for (int ix = 0; ix < 2; ++ix)
+                if (iz < nzb && iy < nyb && ix < nxb) {
+                    const int cls = (bxs[ix] & 1) + 2 * (bys[iy] & 1) + 4 * (bzs[iz] & 1);
+                    const T *pc = part + pi.at(cls, bxs[ix], gx, gy, gz);
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) pv[iz][iy][ix][f] = pc[f * pi.field];
+                }
+#pragma unroll
+    for (int iz = 0; iz < 2; ++iz)
+#pragma unroll
+        for (int iy = 0; iy < 2; ++iy)
+#pragma unroll
+            for (int ix = 0; ix < 2; ++ix)
+                if (iz < nzb && iy < nyb && ix < nxb) {
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) acc[f] += pv[iz][iy][ix][f];
+                }
     if (csum != nullptr) {
         // cells containing the node along each axis: c with P c <= g <= P c + P
         int cxs[2], axs[2], ncx = 0, cys[2], ays[2], ncy = 0, czs[2], azs[2], ncz = 0;
