@@ -428,8 +428,8 @@ def main(argv=None):
                     help="also run one plain 512 MiB device copy (for counter calibration)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(how the apply would shard is described in the design notes)", file=sys.stderr)
         return 2
 
     import torch

@@ -1,6 +1,6 @@
 """Pins of the oracle's Schur-complement block preconditioner (oracle/schur.py).
 
-The preconditioner is a design of this build (section 2.4 names block
+The preconditioner is a design of this library (section 2.4 names block
 preconditioners from the sub-matrices, not a member), so the pins check that
 each piece does what its definition states, by routes that share no code with
 it: the pressure stiffness against the separately pinned VMS element matrices
