@@ -12,11 +12,11 @@ Euler, c_m = 1/dt):
   Dirichlet rows identity, columns zero.
   Multiplier reported afterwards: lambda_B = kappa_B (g_B - (B u)_B), the
   paper's lambda = -R^s (eq. nodal_lagrange) for the stand-in solid residual.
-  Full Newton tangent (tangent="fd"): the derivative of R itself, including the
-  reactive convection, the linearised SUPG test functions and tau, taken as a
-  directional forward difference J v = (R(x + e v~) - R(x)) / e with v~ = v with
-  its Dirichlet entries zeroed, e = sqrt(2^-52) (1 + ||x||) / ||v~||; Dirichlet
-  rows are the identity.
+  Full Newton tangent (tangent="full"): the derivative of R itself, including
+  the reactive convection (du.grad)u, the linearised SUPG test function
+  (du.grad)w and the derivatives of tau_m and tau_c, from the element tangents
+  of vms_ref.c written out term by term; the DLM part is linear, so it keeps
+  B^T kappa B; Dirichlet rows are the identity and Dirichlet columns zero.
 """
 from __future__ import annotations
 
@@ -49,30 +49,40 @@ def multiplier(grid, x, cell, xi, kappa, g):
     return np.asarray(kappa)[None, :] * (np.asarray(g).reshape(3, -1) - Bu)
 
 
-FD_DELTA = 2.0 ** -26   # sqrt of the FP64 unit roundoff
-
-
-def tangent_fd_apply(grid, prm, x, R0, v, u_old, cell, xi, kappa, g, s=None, mask=None, gD=None,
-                     body=None, visc_strong=True):
-    """Full Newton tangent times v by a directional forward difference (see the header)."""
+def tangent_apply(grid, prm, x, v, u_old, cell, xi, kappa, s=None, mask=None, body=None,
+                  visc_strong=True):
+    """Full Newton tangent of residual() at x times v ([4][N]; see the header)."""
     N = grid.num_nodes
     x = np.asarray(x, dtype=np.float64).reshape(4, N)
     v = np.asarray(v, dtype=np.float64).reshape(4, N)
-    vm = v.copy()
+    c_m = float(prm[1])
+    f = c_m * np.asarray(u_old, dtype=np.float64).reshape(3, N)
+    if body is not None:
+        f = f + np.asarray(body).reshape(3, N)
+    y = vms.tangent_apply(grid, prm, x, f, v, s=s, mask=mask, visc_strong=visc_strong)
+    vm = v[:3].copy()
     m = None
     if mask is not None:
         m = np.asarray(mask, dtype=bool).reshape(3, N)
-        vm[:3][m] = 0.0
-    nv = np.linalg.norm(vm)
-    y = np.zeros((4, N))
-    if nv > 0.0:
-        e = FD_DELTA * (1.0 + np.linalg.norm(x)) / nv
-        Rp = residual(grid, prm, x + e * vm, u_old, cell, xi, kappa, g, s, mask, gD, body=body,
-                      visc_strong=visc_strong)
-        y = (Rp - np.asarray(R0).reshape(4, N)) / e
+        vm[m] = 0.0
+    dl = dlm.apply_BT(grid, cell, xi, dlm.apply_B(grid, cell, xi, vm), kappa)
     if m is not None:
-        y[:3][m] = v[:3][m]
+        dl[m] = 0.0
+    y[:3] += dl
     return y
+
+
+def tangent_dense(grid, prm, x, u_old, cell, xi, kappa, s=None, mask=None, body=None,
+                  visc_strong=True):
+    """Dense full tangent (4N x 4N) by columns of tangent_apply (small grids only)."""
+    n = 4 * grid.num_nodes
+    J = np.empty((n, n))
+    for j in range(n):
+        e_j = np.zeros(n)
+        e_j[j] = 1.0
+        J[:, j] = tangent_apply(grid, prm, x, e_j, u_old, cell, xi, kappa, s, mask, body,
+                                visc_strong).ravel()
+    return J
 
 
 def solve_step(grid, prm, x0, u_old, cell, xi, kappa, g, s=None, mask=None, gD=None,
@@ -93,15 +103,8 @@ def solve_step(grid, prm, x0, u_old, cell, xi, kappa, g, s=None, mask=None, gD=N
         if hist[-1] <= tol_abs:
             break
         a = x[:3].copy()
-        if tangent == "fd":
-            # full tangent: dense by columns of the directional differences (small grids only)
-            n = 4 * N
-            J = np.empty((n, n))
-            for j in range(n):
-                e_j = np.zeros(n)
-                e_j[j] = 1.0
-                J[:, j] = tangent_fd_apply(grid, prm, x, R, e_j, u_old, cell, xi, kappa, g, s, mask, gD,
-                                           body=body, visc_strong=visc_strong).ravel()
+        if tangent == "full":
+            J = tangent_dense(grid, prm, x, u_old, cell, xi, kappa, s, mask, body, visc_strong)
             dx = np.linalg.solve(J, -R.ravel())
             lin_iters.append(0)
         elif linear == "dense":

@@ -18,6 +18,9 @@ from . import build as _build
 
 MASS, CONV, VISC, PDIV, CONT, SUPG, PSPG, LSIC = 1, 2, 4, 8, 16, 32, 64, 128
 ALL = 255
+# test functions of the source load (Galerkin, SUPG, PSPG)
+SRC_GAL, SRC_SUPG, SRC_PSPG = 1, 2, 4
+SRC_ALL = 7
 
 _lib = None
 
@@ -33,13 +36,16 @@ def lib():
         P = ctypes.c_void_p
         I = ctypes.c_int
         _lib.oracle_element_matrix.argtypes = [I, P, P, I, I, P, P, ctypes.c_uint, P]
-        _lib.oracle_source_matrix.argtypes = [I, P, P, I, P, P, P]
+        _lib.oracle_source_matrix.argtypes = [I, P, P, I, P, P, ctypes.c_uint, P]
+        _lib.oracle_element_tangent.argtypes = [I, P, P, I, I, P, P, P, P]
+        _lib.oracle_vms_tangent_apply.argtypes = [P, I, P, P, I, P, P, P, P, P, P]
         _lib.oracle_vms_apply.argtypes = [P, I, P, P, I, P, P, P, P, P]
         _lib.oracle_vms_rows.argtypes = [P, I, P, P, I, P, P, P, P, P, ctypes.c_int64, P]
         _lib.oracle_vms_diag_blocks.argtypes = [P, I, P, P, I, P, P, P, P]
         _lib.oracle_vms_residual.argtypes = [P, I, P, P, I, P, P, P, P]
         for f in (_lib.oracle_element_matrix, _lib.oracle_source_matrix, _lib.oracle_vms_apply,
-                  _lib.oracle_vms_rows, _lib.oracle_vms_diag_blocks, _lib.oracle_vms_residual):
+                  _lib.oracle_vms_rows, _lib.oracle_vms_diag_blocks, _lib.oracle_vms_residual,
+                  _lib.oracle_element_tangent, _lib.oracle_vms_tangent_apply):
             f.restype = ctypes.c_int
     return _lib
 
@@ -72,14 +78,28 @@ def element_matrix(p, h, prm, a_e, s_e=None, terms=ALL, visc_strong=True, nq=0):
     return K
 
 
-def source_matrix(p, h, prm, a_e, s_e=None, nq=0):
+def source_matrix(p, h, prm, a_e, s_e=None, nq=0, terms=SRC_ALL):
+    """Load matrix of a nodal source: rows = test DOFs, cols = [3][nen] source values."""
     nen = (p + 1) ** 3
     L = np.zeros((4 * nen, 3 * nen))
     h = _f64(h); prm = _f64(prm); a_e = _f64(a_e); s_e = _f64(s_e)
-    rc = lib().oracle_source_matrix(p, _p(h), _p(prm), nq, _p(a_e), _p(s_e), _p(L))
+    rc = lib().oracle_source_matrix(p, _p(h), _p(prm), nq, _p(a_e), _p(s_e), terms, _p(L))
     if rc:
         raise ValueError(f"oracle_source_matrix failed ({rc})")
     return L
+
+
+def element_tangent(p, h, prm, x_e, f_e, s_e=None, visc_strong=True, nq=0):
+    """Dense (4 nen)^2 full Newton tangent of the element residual K(a=u) x - L(a=u) f at the
+    element state x_e ([4][nen]) with nodal source f_e ([3][nen])."""
+    nen = (p + 1) ** 3
+    T = np.zeros((4 * nen, 4 * nen))
+    h = _f64(h); prm = _f64(prm); x_e = _f64(x_e); f_e = _f64(f_e); s_e = _f64(s_e)
+    rc = lib().oracle_element_tangent(p, _p(h), _p(prm), int(bool(visc_strong)), nq, _p(x_e), _p(f_e),
+                                      _p(s_e), _p(T))
+    if rc:
+        raise ValueError(f"oracle_element_tangent failed ({rc})")
+    return T
 
 
 def _grid_args(grid):
@@ -144,6 +164,22 @@ def residual_fluid(grid, prm, x, f, s=None, visc_strong=True):
     if rc:
         raise ValueError(f"oracle_vms_residual failed ({rc})")
     return R
+
+
+def tangent_apply(grid, prm, x, f, v, s=None, mask=None, visc_strong=True):
+    """Fluid part of the full Newton tangent at state x (source f) times v ([4][N]); Dirichlet
+    columns of v zeroed, Dirichlet rows return v."""
+    n, h = _grid_args(grid)
+    N = grid.num_nodes
+    x = _f64(x).reshape(4, N); f = _f64(f).reshape(3, N); v = _f64(v).reshape(4, N)
+    s = _f64(s); prm = _f64(prm)
+    m = _mask_bytes(mask)
+    y = np.zeros((4, N))
+    rc = lib().oracle_vms_tangent_apply(_p(n), grid.order, _p(h), _p(prm), int(bool(visc_strong)),
+                                        _p(s), _p(m), _p(x), _p(f), _p(v), _p(y))
+    if rc:
+        raise ValueError(f"oracle_vms_tangent_apply failed ({rc})")
+    return y
 
 
 def cell_node_ids(grid, cx, cy, cz):

@@ -252,9 +252,15 @@ int oracle_element_matrix(int p, const double *h, const double *prm, int visc_st
  * SUPG and PSPG test functions applied to a nodal body-force-like field f
  * (f = c_m u_old + body force in a time step), i.e. the load
  *   int w.f + tau_m ((a.grad)w + grad q).f.
+ * terms selects the test functions (OR_SRC_* flags; OR_SRC_ALL for the load
+ * of the method).
  */
+#define OR_SRC_GAL 1u
+#define OR_SRC_SUPG 2u
+#define OR_SRC_PSPG 4u
+#define OR_SRC_ALL 7u
 int oracle_source_matrix(int p, const double *h, const double *prm, int nq,
-                         const double *a_e, const double *s_e, double *L)
+                         const double *a_e, const double *s_e, unsigned terms, double *L)
 {
     if (p != 1 && p != 2) return -1;
     if (nq == 0) nq = p + 1;
@@ -280,13 +286,16 @@ int oracle_source_matrix(int p, const double *h, const double *prm, int nq,
                 stab_params(h, prm, aq, sq, &tau_m, &tau_c);
                 for (int A = 0; A < nen; ++A) {
                     double adNA = aq[0] * S.dN[A][0] + aq[1] * S.dN[A][1] + aq[2] * S.dN[A][2];
+                    const double gal = (terms & OR_SRC_GAL) ? S.N[A] : 0.0;
+                    const double supg = (terms & OR_SRC_SUPG) ? tau_m * adNA : 0.0;
+                    const double pspg = (terms & OR_SRC_PSPG) ? tau_m : 0.0;
                     for (int B = 0; B < nen; ++B) {
                         for (int i = 0; i < 3; ++i)
                             L[(size_t)(i * nen + A) * nc + (i * nen + B)] +=
-                                W * (S.N[A] * S.N[B] + tau_m * adNA * S.N[B]);
+                                W * (gal * S.N[B] + supg * S.N[B]);
                         for (int j = 0; j < 3; ++j)
                             L[(size_t)(3 * nen + A) * nc + (j * nen + B)] +=
-                                W * tau_m * S.dN[A][j] * S.N[B];
+                                W * pspg * S.dN[A][j] * S.N[B];
                     }
                 }
             }
@@ -536,7 +545,7 @@ int oracle_vms_residual(const int *n, int p, const double *h, const double *prm,
                 if (s) s_e[A] = s[g];
             }
             oracle_element_matrix(p, h, prm, visc_strong, 0, a_e, s ? s_e : NULL, OR_ALL, K);
-            oracle_source_matrix(p, h, prm, 0, a_e, s ? s_e : NULL, L);
+            oracle_source_matrix(p, h, prm, 0, a_e, s ? s_e : NULL, OR_SRC_ALL, L);
             for (int r = 0; r < nd; ++r) {
                 double acc = 0.0;
                 for (int c = 0; c < nd; ++c) acc += K[(size_t)r * nd + c] * x_e[c];
@@ -556,5 +565,196 @@ int oracle_vms_residual(const int *n, int p, const double *h, const double *prm,
             for (int A = 0; A < nen; ++A) R[f2 * N + ids[A]] += re[(size_t)e * nd + f2 * nen + A];
     }
     free(re);
+    return 0;
+}
+
+/*
+ * Full Newton tangent of the element residual (section 2.4: Newton's method on
+ * the monolithic system).  The element residual of a time step is
+ *   r_e(x) = K_e(a = u, tau(u)) x - L_e(a = u, tau(u)) f,
+ * i.e. per quadrature point, with rho = r_m(u, p) - f the strong momentum
+ * residual including the source,
+ *   momentum test w:  w.(c_m u + (u.grad)u - f) + 2 nu eps(w):eps(u) - (div w) p
+ *                     + tau_m ((u.grad)w).rho + tau_c (div w)(div u)
+ *   continuity test q: q div u + tau_m grad q . rho.
+ * T = d r_e / d x ((4 nen) x (4 nen), row-major), written out term by term:
+ * besides the Picard/Oseen entries it has the reactive convection
+ * (du.grad)u in the Galerkin, SUPG and PSPG terms, the derivative of the SUPG
+ * test function (du.grad)w . rho, and the derivatives of tau_m and tau_c
+ * with respect to the advecting velocity,
+ *   d tau_m = -tau_m^3 s (u . G du),   d tau_c = -(tau_c / tau_m) d tau_m.
+ * x_e = [4][nen] state (u, p), f_e = [3][nen] nodal source, s_e as above.
+ */
+int oracle_element_tangent(int p, const double *h, const double *prm, int visc_strong, int nq,
+                           const double *x_e, const double *f_e, const double *s_e, double *T)
+{
+    if (p != 1 && p != 2) return -1;
+    if (nq == 0) nq = p + 1;
+    const int q = p + 1, nen = q * q * q, nd = 4 * nen;
+    const double nu = prm[0], c_m = prm[1];
+    const double vs = visc_strong ? nu : 0.0;
+    double pt[4], wt[4];
+    if (gauss01(nq, pt, wt)) return -1;
+    memset(T, 0, sizeof(double) * (size_t)nd * nd);
+    const double detJ = h[0] * h[1] * h[2];
+    double Gd[3];
+    for (int k = 0; k < 3; ++k) Gd[k] = 1.0 / (h[k] * h[k]);
+    shape_t S;
+    for (int qz = 0; qz < nq; ++qz)
+        for (int qy = 0; qy < nq; ++qy)
+            for (int qx = 0; qx < nq; ++qx) {
+                double xi[3] = {pt[qx], pt[qy], pt[qz]};
+                double W = wt[qx] * wt[qy] * wt[qz] * detJ;
+                shape3d(p, h, xi, &S);
+                /* state at the point */
+                double u[3] = {0, 0, 0}, gu[3][3] = {{0}}, gp[3] = {0, 0, 0}, f[3] = {0, 0, 0};
+                double lapu[3] = {0, 0, 0}, gdiv[3] = {0, 0, 0}, sq = 0.0;
+                for (int B = 0; B < nen; ++B) {
+                    for (int i = 0; i < 3; ++i) {
+                        const double ui = x_e[i * nen + B];
+                        u[i] += S.N[B] * ui;
+                        f[i] += S.N[B] * f_e[i * nen + B];
+                        for (int k = 0; k < 3; ++k) gu[i][k] += S.dN[B][k] * ui;
+                        lapu[i] += (S.d2N[B][0][0] + S.d2N[B][1][1] + S.d2N[B][2][2]) * ui;
+                        /* d_k (div u) collects d_k d_i u_i */
+                        for (int k = 0; k < 3; ++k) gdiv[k] += S.d2N[B][k][i] * ui;
+                    }
+                    for (int k = 0; k < 3; ++k) gp[k] += S.dN[B][k] * x_e[3 * nen + B];
+                    sq += S.N[B] * (s_e ? s_e[B] : 1.0);
+                }
+                sq = clamp_s(sq, s_e, nen);
+                double tau_m, tau_c;
+                stab_params(h, prm, u, sq, &tau_m, &tau_c);
+                double divu = gu[0][0] + gu[1][1] + gu[2][2];
+                double rho[3];
+                for (int i = 0; i < 3; ++i) {
+                    double conv = u[0] * gu[i][0] + u[1] * gu[i][1] + u[2] * gu[i][2];
+                    rho[i] = c_m * u[i] + conv + gp[i] - vs * (lapu[i] + gdiv[i]) - f[i];
+                }
+                /* derivatives of tau_m, tau_c along the trial velocity component j (per N_B) */
+                double dtm[3], dtc[3];
+                for (int j = 0; j < 3; ++j) {
+                    dtm[j] = -tau_m * tau_m * tau_m * sq * u[j] * Gd[j];
+                    dtc[j] = -(tau_c / tau_m) * dtm[j];
+                }
+                double adN[27], lapN[27], gNrho[27];
+                for (int A = 0; A < nen; ++A) {
+                    adN[A] = u[0] * S.dN[A][0] + u[1] * S.dN[A][1] + u[2] * S.dN[A][2];
+                    lapN[A] = S.d2N[A][0][0] + S.d2N[A][1][1] + S.d2N[A][2][2];
+                    gNrho[A] = S.dN[A][0] * rho[0] + S.dN[A][1] * rho[1] + S.dN[A][2] * rho[2];
+                }
+                for (int A = 0; A < nen; ++A)
+                    for (int B = 0; B < nen; ++B) {
+                        const double NA = S.N[A], NB = S.N[B];
+                        const double gAgB = S.dN[A][0] * S.dN[B][0] + S.dN[A][1] * S.dN[B][1]
+                                          + S.dN[A][2] * S.dN[B][2];
+                        /* d rho_i / d u_{B,j} */
+                        double drho[3][3];
+                        for (int i = 0; i < 3; ++i)
+                            for (int j = 0; j < 3; ++j)
+                                drho[i][j] = (i == j ? c_m * NB + adN[B] - vs * lapN[B] : 0.0)
+                                           + NB * gu[i][j] - vs * S.d2N[B][i][j];
+                        for (int i = 0; i < 3; ++i)
+                            for (int j = 0; j < 3; ++j) {
+                                double v = 0.0;
+                                /* Galerkin: mass, convection (both factors), viscous */
+                                if (i == j) v += c_m * NA * NB + NA * adN[B] + nu * gAgB;
+                                v += NA * NB * gu[i][j];
+                                v += nu * S.dN[A][j] * S.dN[B][i];
+                                /* SUPG: tau_m (u.grad N_A) rho_i, all three factors varied */
+                                v += tau_m * adN[A] * drho[i][j];
+                                v += tau_m * NB * S.dN[A][j] * rho[i];
+                                v += dtm[j] * NB * adN[A] * rho[i];
+                                /* LSIC: tau_c d_i N_A div u */
+                                v += tau_c * S.dN[A][i] * S.dN[B][j];
+                                v += dtc[j] * NB * S.dN[A][i] * divu;
+                                T[(size_t)(i * nen + A) * nd + (j * nen + B)] += W * v;
+                            }
+                        for (int i = 0; i < 3; ++i) {
+                            double v = -S.dN[A][i] * NB + tau_m * adN[A] * S.dN[B][i];
+                            T[(size_t)(i * nen + A) * nd + (3 * nen + B)] += W * v;
+                        }
+                        for (int j = 0; j < 3; ++j) {
+                            double v = NA * S.dN[B][j];
+                            double t = 0.0;
+                            for (int i = 0; i < 3; ++i) t += S.dN[A][i] * drho[i][j];
+                            v += tau_m * t + dtm[j] * NB * gNrho[A];
+                            T[(size_t)(3 * nen + A) * nd + (j * nen + B)] += W * v;
+                        }
+                        T[(size_t)(3 * nen + A) * nd + (3 * nen + B)] += W * tau_m * gAgB;
+                    }
+            }
+    return 0;
+}
+
+/*
+ * y = T(x) v over the whole grid: the fluid part of the full Newton tangent of
+ * the step residual at the state x ([4][N]) with nodal source f ([3][N]).
+ * dmask (bytes, [3][N]) or NULL: masked entries of v are zeroed before the
+ * apply (Dirichlet columns) and masked rows return v (the derivative of
+ * u_D - g_D).
+ */
+int oracle_vms_tangent_apply(const int *n, int p, const double *h, const double *prm,
+                             int visc_strong, const double *s, const uint8_t *dmask,
+                             const double *x, const double *f, const double *v, double *y)
+{
+    if (p != 1 && p != 2) return -1;
+    const int q = p + 1, nen = q * q * q, nd = 4 * nen;
+    const int64_t Nx = (int64_t)p * n[0] + 1, Ny = (int64_t)p * n[1] + 1, Nz = (int64_t)p * n[2] + 1;
+    const int64_t N = Nx * Ny * Nz;
+    const int64_t E = (int64_t)n[0] * n[1] * n[2];
+    double *ye = (double *)malloc(sizeof(double) * (size_t)E * nd);
+    if (!ye) return -2;
+    int err = 0;
+#pragma omp parallel
+    {
+        double *T = (double *)malloc(sizeof(double) * (size_t)nd * nd);
+        double x_e[108], f_e[81], s_e[27], v_e[108];
+        int64_t ids[27];
+        if (!T) {
+#pragma omp atomic write
+            err = -2;
+        }
+#pragma omp for schedule(static)
+        for (int64_t e = 0; e < E; ++e) {
+            if (!T) continue;
+            int64_t cx = e % n[0], cy = (e / n[0]) % n[1], cz = e / ((int64_t)n[0] * n[1]);
+            cell_nodes(n, p, cx, cy, cz, ids);
+            for (int A = 0; A < nen; ++A) {
+                int64_t g = ids[A];
+                for (int d = 0; d < 4; ++d) {
+                    x_e[d * nen + A] = x[d * N + g];
+                    double vv = v[d * N + g];
+                    if (d < 3 && dmask && dmask[d * N + g]) vv = 0.0;
+                    v_e[d * nen + A] = vv;
+                }
+                for (int d = 0; d < 3; ++d) f_e[d * nen + A] = f[d * N + g];
+                if (s) s_e[A] = s[g];
+            }
+            oracle_element_tangent(p, h, prm, visc_strong, 0, x_e, f_e, s ? s_e : NULL, T);
+            for (int r = 0; r < nd; ++r) {
+                double acc = 0.0;
+                for (int c = 0; c < nd; ++c) acc += T[(size_t)r * nd + c] * v_e[c];
+                ye[(size_t)e * nd + r] = acc;
+            }
+        }
+        free(T);
+    }
+    if (err) {
+        free(ye);
+        return err;
+    }
+    memset(y, 0, sizeof(double) * (size_t)(4 * N));
+    int64_t ids[27];
+    for (int64_t e = 0; e < E; ++e) {
+        int64_t cx = e % n[0], cy = (e / n[0]) % n[1], cz = e / ((int64_t)n[0] * n[1]);
+        cell_nodes(n, p, cx, cy, cz, ids);
+        for (int f2 = 0; f2 < 4; ++f2)
+            for (int A = 0; A < nen; ++A) y[f2 * N + ids[A]] += ye[(size_t)e * nd + f2 * nen + A];
+    }
+    if (dmask)
+        for (int64_t i = 0; i < 3 * N; ++i)
+            if (dmask[i]) y[i] = v[i];
+    free(ye);
     return 0;
 }

@@ -98,27 +98,79 @@ def _small_newton_case():
     return g, N, prm, u_old, cell, xi, kap, gp, m, gD, x0
 
 
-def test_fd_tangent_is_the_derivative_of_the_residual():
-    # the forward difference at e ~ 1e-8 agrees with a central difference at h = 1e-4 (error O(h^2))
-    g, N, prm, u_old, cell, xi, kap, gp, m, gD, x0 = _small_newton_case()
-    rng = np.random.default_rng(2)
-    x = x0 + 0.05 * rng.standard_normal(x0.shape)
-    x[:3][m] = 0.0
-    R0 = newton.residual(g, prm, x, u_old, cell, xi, kap, gp, mask=m, gD=gD)
-    v = rng.standard_normal((4, N))
-    y = newton.tangent_fd_apply(g, prm, x, R0, v, u_old, cell, xi, kap, gp, mask=m, gD=gD)
-    vm = v.copy()
-    vm[:3][m] = 0.0
-    h = 1e-4
-    Rp = newton.residual(g, prm, x + h * vm, u_old, cell, xi, kap, gp, mask=m, gD=gD)
-    Rm = newton.residual(g, prm, x - h * vm, u_old, cell, xi, kap, gp, mask=m, gD=gD)
-    yc = (Rp - Rm) / (2 * h)
-    yc[:3][m] = v[:3][m]
-    assert np.linalg.norm(y - yc) <= 1e-6 * np.linalg.norm(yc)
-    # it differs from the Picard/Oseen matrix by the dropped derivatives (reactive convection,
-    # SUPG test function, tau), which are not small relative to rounding
-    yp = jacobian.apply(g, prm, x[:3], v, cell, xi, kap, mask=m)
-    assert np.linalg.norm(y - yp) > 1e-6 * np.linalg.norm(yp)
+def _central(fun, x, v, h):
+    """Richardson-extrapolated central difference of fun at x along v (error O(h^4))."""
+    d1 = (fun(x + h * v) - fun(x - h * v)) / (2 * h)
+    d2 = (fun(x + 0.5 * h * v) - fun(x - 0.5 * h * v)) / h
+    return (4.0 * d2 - d1) / 3.0
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("c_m", [1000.0, 5.0])
+def test_element_tangent_is_the_derivative_of_the_element_residual(order, c_m):
+    """The analytic element tangent (reactive convection, SUPG test-function and tau derivatives)
+    against central differences of the element residual K(a=u, tau(u)) x - L(a=u, tau(u)) f,
+    which the element-matrix pins fix; a jump in s exercises the Q2 clamp."""
+    nen = (order + 1) ** 3
+    h = np.array([0.3, 0.25, 0.2])
+    prm = vms.params_array(0.05, c_m, 1e-2)
+    rng = np.random.default_rng(40 + order)
+    x_e = rng.standard_normal(4 * nen)
+    f_e = rng.standard_normal(3 * nen)
+    s_e = np.where(rng.uniform(size=nen) < 0.4, 100.0, 1.0)
+
+    def r_e(xx):
+        a_e = xx[:3 * nen]
+        K = vms.element_matrix(order, h, prm, a_e, s_e)
+        L = vms.source_matrix(order, h, prm, a_e, s_e)
+        return K @ xx - L @ f_e
+
+    T = vms.element_tangent(order, h, prm, x_e, f_e, s_e)
+    for k in range(6):
+        v = rng.standard_normal(4 * nen)
+        ref = _central(r_e, x_e, v, 1e-3)
+        got = T @ v
+        for f in range(4):
+            sl = slice(f * nen, (f + 1) * nen)
+            assert np.linalg.norm(got[sl] - ref[sl]) <= 1e-8 * np.linalg.norm(ref[sl]), (k, f)
+    # not vacuous: the full tangent differs from the Picard/Oseen element matrix
+    K = vms.element_matrix(order, h, prm, x_e[:3 * nen], s_e)
+    assert np.linalg.norm(T - K) > 1e-3 * np.linalg.norm(K)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_full_tangent_is_the_derivative_of_the_residual(order):
+    """Global full tangent (with s, the DLM block and Dirichlet rows) against central differences
+    of the step residual along directions with zero Dirichlet entries; Dirichlet rows give v."""
+    g = W.Grid((3, 3, 2), order)
+    N = g.num_nodes
+    prm = vms.params_array(0.01, 1000.0, 1e-3)
+    rng = np.random.default_rng(3 + order)
+    u_old = 0.5 * W.advection_field(g, 3)
+    X = rng.uniform(0.3, 0.7, (3, 40))
+    cell, xi = dlm.locate(g, X)
+    kap = np.full(40, 50.0)
+    gp = rng.standard_normal((3, 40))
+    s = dlm.s_field(g, cell, 100.0)
+    m = W.channel_dirichlet_mask(g)
+    gD = np.zeros((3, N))
+    x = np.concatenate([u_old, np.zeros((1, N))]) + 0.3 * rng.standard_normal((4, N))
+
+    def R(xx):
+        return newton.residual(g, prm, xx, u_old, cell, xi, kap, gp, s=s, mask=m, gD=gD)
+
+    for k in range(3):
+        v = rng.standard_normal((4, N))
+        vm = v.copy()
+        vm[:3][m] = 0.0
+        ref = _central(R, x, vm, 1e-4)
+        got = newton.tangent_apply(g, prm, x, v, u_old, cell, xi, kap, s=s, mask=m)
+        ref[:3][m] = v[:3][m]
+        for f in range(4):
+            assert np.linalg.norm(got[f] - ref[f]) <= 1e-8 * np.linalg.norm(ref[f]), (k, f)
+    # the dropped derivatives are not small relative to rounding
+    yp = jacobian.apply(g, prm, x[:3], v, cell, xi, kap, s=s, mask=m)
+    assert np.linalg.norm(got - yp) > 1e-5 * np.linalg.norm(yp)
 
 
 def test_full_tangent_newton_converges_quadratically():
@@ -126,11 +178,11 @@ def test_full_tangent_newton_converges_quadratically():
     R0 = newton.residual(g, prm, x0, u_old, cell, xi, kap, gp, mask=m, gD=gD)
     tol = 1e-13 * np.linalg.norm(R0)
     hist = {}
-    for tg in ("picard", "fd"):
+    for tg in ("picard", "full"):
         x, info = newton.solve_step(g, prm, x0, u_old, cell, xi, kap, gp, mask=m, gD=gD, tol_abs=tol, tangent=tg)
         assert info["converged"]
         hist[tg] = info["history"]
     # second step: linear contraction for Picard, quadratic for the full tangent
-    rp, rf = hist["picard"], hist["fd"]
+    rp, rf = hist["picard"], hist["full"]
     assert rf[2] <= 1e-2 * rp[2], (rp, rf)
     assert rf[2] / rf[1] <= 1e-2 * (rp[2] / rp[1]), (rp, rf)

@@ -369,3 +369,190 @@ def test_dense_apply_rows_and_mask_consistency():
     rows = rng.choice(4 * N, 200, replace=False)
     yr = vms.apply_rows(g, P, a, x, rows, s=s, mask=mask)
     assert np.abs(yr - y.ravel()[rows]).max() <= 1e-13 * np.abs(ref).max()
+
+
+# ------------------------------------------------ the step residual's source weighting
+def _residual_patch_case(order=2):
+    """Q2 grid and an exact steady state of the nonlinear step residual with a = u:
+    u = M x (M symmetric, trace free: div u = 0, (u.grad)u = M^2 x), p = -x.M^2 x / 2 - phi
+    (phi quadratic), u_old = u - grad(phi) / c_m, so r_m(u, p) - c_m u_old = 0 at every point."""
+    grid = W.Grid((3, 3, 3), order, x0=(0.1, -0.2, 0.3), h=(0.3, 0.25, 0.2))
+    rng = np.random.default_rng(17)
+    A = rng.standard_normal((3, 3))
+    M = A + A.T
+    M -= np.trace(M) / 3.0 * np.eye(3)
+    Q = rng.standard_normal((3, 3))
+    Q = Q + Q.T
+    b = rng.standard_normal(3)
+    c_m = 40.0
+    X, Y, Z = W.node_coords(grid)
+    xs = np.stack([X, Y, Z])
+    u = M @ xs
+    M2 = M @ M
+    phi = 0.5 * np.einsum("in,ij,jn->n", xs, Q, xs) + b @ xs
+    p = -0.5 * np.einsum("in,ij,jn->n", xs, M2, xs) - phi
+    u_old = u - (Q @ xs + b[:, None]) / c_m
+    N = grid.num_nodes
+    s = rng.uniform(1.0, 100.0, size=N)
+    prm_ = prm(nu=0.3, c_m=c_m, dt=0.05)
+    return grid, prm_, np.concatenate([u, p[None]]), c_m * u_old, s
+
+
+def _assemble_residual(grid, prm_, x, f, s, src_terms):
+    """Element-by-element K(a=u) x - L(a=u) f with the chosen source test functions."""
+    N = grid.num_nodes
+    p = grid.order
+    nen = (p + 1) ** 3
+    R = np.zeros(4 * N)
+    for cz in range(grid.n[2]):
+        for cy in range(grid.n[1]):
+            for cx in range(grid.n[0]):
+                ids = vms.cell_node_ids(grid, cx, cy, cz)
+                x_e = np.concatenate([x[f_][ids] for f_ in range(4)])
+                f_e = np.concatenate([f[d][ids] for d in range(3)])
+                K = vms.element_matrix(p, grid.h, prm_, x_e[:3 * nen], s[ids])
+                L = vms.source_matrix(p, grid.h, prm_, x_e[:3 * nen], s[ids], terms=src_terms)
+                dofs = np.concatenate([f_ * N + ids for f_ in range(4)])
+                R[dofs] += K @ x_e - L @ f_e
+    return R
+
+
+def test_residual_patch_exact_steady_state_with_source():
+    """Interior rows of the step residual vanish for any s and tau when the source c_m u_old
+    balances the strong residual: pins the Galerkin + SUPG + PSPG weighting of the source and
+    a = u in the convection and in tau."""
+    grid, prm_, x, f, s = _residual_patch_case()
+    R = vms.residual_fluid(grid, prm_, x, f, s=s).ravel()
+    inner = interior_rows(grid)
+    scale = np.abs(_assemble_residual(grid, prm_, x, f, s, 0)).max()   # K x alone
+    assert np.abs(R[inner]).max() <= 1e-11 * scale, np.abs(R[inner]).max() / scale
+    assert np.abs(R[~inner]).max() > 1e-3 * scale   # boundary rows are not zero
+    # the element-by-element sum with every source term reproduces the oracle's residual
+    R_all = _assemble_residual(grid, prm_, x, f, s, vms.SRC_ALL)
+    assert np.abs(R_all - R).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("variant", ["no_supg", "no_pspg", "supg_sign", "pspg_sign", "no_gal"])
+def test_residual_patch_detects_a_wrong_source_weighting(variant):
+    """A plausible mistake in the source weighting (a dropped or sign-flipped SUPG / PSPG / Galerkin
+    test function) breaks the patch test above."""
+    grid, prm_, x, f, s = _residual_patch_case()
+    terms = {"no_supg": vms.SRC_GAL | vms.SRC_PSPG, "no_pspg": vms.SRC_GAL | vms.SRC_SUPG,
+             "no_gal": vms.SRC_SUPG | vms.SRC_PSPG}
+    if variant in terms:
+        R = _assemble_residual(grid, prm_, x, f, s, terms[variant])
+    else:
+        flip = vms.SRC_SUPG if variant == "supg_sign" else vms.SRC_PSPG
+        R = (_assemble_residual(grid, prm_, x, f, s, vms.SRC_ALL)
+             + 2.0 * (_assemble_residual(grid, prm_, x, f, s, vms.SRC_ALL & ~flip)
+                      - _assemble_residual(grid, prm_, x, f, s, vms.SRC_ALL)))
+    inner = interior_rows(grid)
+    scale = np.abs(_assemble_residual(grid, prm_, x, f, s, 0)).max()
+    assert np.abs(R[inner]).max() > 1e-6 * scale
+
+
+# ------------------------------------------------ s at the quadrature points
+def _lagrange_1d(order, t):
+    """Values and derivatives of the 1D Lagrange polynomials on the nodes k/order at t."""
+    nodes = np.arange(order + 1) / order
+    val = np.ones((order + 1, t.size))
+    der = np.zeros((order + 1, t.size))
+    for k in range(order + 1):
+        others = [m for m in range(order + 1) if m != k]
+        for m in others:
+            val[k] *= (t - nodes[m]) / (nodes[k] - nodes[m])
+        for m in others:
+            term = np.full(t.size, 1.0 / (nodes[k] - nodes[m]))
+            for l in others:
+                if l != m:
+                    term = term * (t - nodes[l]) / (nodes[k] - nodes[l])
+            der[k] += term
+    return val, der
+
+
+def _pspg_block_from_point_s(order, h, a_c, s_at, P):
+    """tau_m(s(x_q)) int grad N_A . grad N_B by (order+1)-point Gauss with s given per point."""
+    nu, dt, C_T, C_I = P[0], P[2], P[3], P[4]
+    t, w = np.polynomial.legendre.leggauss(order + 1)
+    t = 0.5 * (t + 1.0)
+    w = 0.5 * w
+    val, der = _lagrange_1d(order, t)
+    q = order + 1
+    nen = q ** 3
+    G = 1.0 / np.asarray(h) ** 2
+    K = np.zeros((nen, nen))
+    for iz in range(q):
+        for iy in range(q):
+            for ix in range(q):
+                grads = np.zeros((nen, 3))
+                for az in range(q):
+                    for ay in range(q):
+                        for ax in range(q):
+                            A = ax + q * (ay + q * az)
+                            grads[A] = [der[ax, ix] * val[ay, iy] * val[az, iz] / h[0],
+                                        val[ax, ix] * der[ay, iy] * val[az, iz] / h[1],
+                                        val[ax, ix] * val[ay, iy] * der[az, iz] / h[2]]
+                sq = s_at(t[ix], t[iy], t[iz])
+                bracket = C_T / dt ** 2 + np.sum(G * a_c ** 2) + C_I * nu ** 2 * np.sum(G ** 2)
+                tau_m = 1.0 / np.sqrt(sq * bracket)
+                K += w[ix] * w[iy] * w[iz] * np.prod(h) * tau_m * grads @ grads.T
+    return K
+
+
+def _nodal_s(order, fun):
+    q = order + 1
+    s = np.zeros(q ** 3)
+    for az in range(q):
+        for ay in range(q):
+            for ax in range(q):
+                s[ax + q * (ay + q * az)] = fun(ax / order, ay / order, az / order)
+    return s
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_s_is_interpolated_to_the_gauss_points(order):
+    """s linear in x (so the clamp cannot act): the PSPG block equals the closed-form tau_m of
+    the analytic s at each Gauss point times grad N_A . grad N_B (section 2.1 interpolates s
+    with the pressure space)."""
+    h = np.array([0.3, 0.25, 0.2])
+    a_c = np.array([0.7, -1.3, 0.4])
+    P = prm(nu=0.05, dt=2e-3)
+    s_fun = lambda x, y, z: 2.0 + 60.0 * x + 25.0 * y + 9.0 * z
+    nen = (order + 1) ** 3
+    K = vms.element_matrix(order, h, P, np.repeat(a_c, nen), _nodal_s(order, s_fun), terms=vms.PSPG)
+    ref = _pspg_block_from_point_s(order, h, a_c, s_fun, P)
+    got = K[3 * nen:, 3 * nen:]
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    # a constant s equal to the cell mean would be a different block (the pin is not vacuous)
+    ref_mean = _pspg_block_from_point_s(order, h, a_c, lambda x, y, z: s_fun(0.5, 0.5, 0.5), P)
+    assert np.abs(ref_mean - ref).max() > 1e-3 * np.abs(ref).max()
+
+
+def test_q2_s_clamp_keeps_tau_at_most_its_s1_value():
+    """Q2 with a nodal jump of s (1 next to 100): the interpolant dips below 1 at Gauss points,
+    which would give tau_m above its s = 1 value or no real tau_m at all; clamped below by the
+    cell's smallest nodal s (reading of section 2.1's s), every point keeps s >= 1, so the PSPG
+    block stays below the s = 1 block in the Loewner order and equals the block of the clamped
+    pointwise s."""
+    order = 2
+    h = np.array([0.2, 0.2, 0.2])
+    a_c = np.array([0.3, 0.2, -0.5])
+    P = prm()
+    nodal = _nodal_s(order, lambda x, y, z: 100.0 if x == 1.0 else 1.0)
+    nen = 27
+    # the interpolant at the first Gauss abscissa in x: 1 + 99 N_2(t0) < 1
+    t0 = 0.5 * (1.0 - np.sqrt(3.0 / 5.0))
+    val, _ = _lagrange_1d(order, np.array([t0]))
+    assert 1.0 + 99.0 * val[2, 0] < 0.0
+    K = vms.element_matrix(order, h, P, np.repeat(a_c, nen), nodal, terms=vms.PSPG)[3 * nen:, 3 * nen:]
+    K1 = vms.element_matrix(order, h, P, np.repeat(a_c, nen), np.ones(nen), terms=vms.PSPG)[3 * nen:, 3 * nen:]
+    assert np.all(np.isfinite(K))
+    ev = np.linalg.eigvalsh(K1 - K)
+    assert ev.min() >= -1e-12 * np.abs(K1).max()
+
+    def s_clamped(x, y, z):
+        vx, _ = _lagrange_1d(order, np.array([x]))
+        return max(1.0 + 99.0 * vx[2, 0], 1.0)
+
+    ref = _pspg_block_from_point_s(order, h, a_c, s_clamped, P)
+    assert np.abs(K - ref).max() <= 1e-13 * np.abs(ref).max()
