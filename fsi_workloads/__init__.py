@@ -39,7 +39,7 @@ __all__ = [
     "Grid", "Config", "CONFIGS", "get_config", "node_coords", "advection_field",
     "sphere_points", "plate_points", "plate_volume", "sphere_volume",
     "kappa_weights", "random_vector", "channel_dirichlet_mask", "mask_to_bits",
-    "rotating_plate_points", "smooth_fourier_field",
+    "rotating_plate_points", "smooth_fourier_field", "channel_inflow_pattern", "channel_inflow_value",
 ]
 
 
@@ -329,6 +329,22 @@ def channel_dirichlet_mask(grid: Grid):
     i, j, k = i.ravel(), j.ravel(), k.ravel()
     node = (i == 0) | (j == 0) | (j == ny - 1) | (k == 0) | (k == nz - 1)
     return np.stack([node, node, node])
+
+
+def channel_inflow_pattern(grid: Grid):
+    """[3][N] Dirichlet data of the channel's inflow for a unit inflow speed: u_x = 1 on the
+    x = 0 face, zero elsewhere (no-slip wins on the face's edges)."""
+    nx, ny, nz = grid.nodes_per_axis
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    inflow = ((i == 0) & (j > 0) & (j < ny - 1) & (k > 0) & (k < nz - 1)).ravel()
+    pat = np.zeros((3, grid.num_nodes))
+    pat[0][inflow] = 1.0
+    return pat
+
+
+def channel_inflow_value(t: float, period: float = 0.8):
+    """Inflow speed of the channel workloads at time t: sin(2 pi t / period)."""
+    return math.sin(2.0 * math.pi * t / period)
 
 
 def mask_to_bits(mask3):

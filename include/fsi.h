@@ -465,16 +465,20 @@ int fsi_schur_apply(const fsi_problem *J, int32_t mode, int32_t vel_steps, void 
  *         precision, or NULL (no preconditioner); FSI_PC_SCHUR_*: the object of
  *         fsi_schur_setup (its scratch vectors are written during the solve)
  *   b     double [4][N];  x  double [4][N] in: initial guess, out: solution
- *   stats HOST out (may be NULL).  SYNCS: the Arnoldi steps are enqueued
- *         back to back; the host reads each step's coefficients from pinned
- *         memory one step behind the device (so a cycle may compute one step
- *         past its stopping point; that step is not used), and it waits for
- *         the stream at every restart.  The library keeps one pinned host
- *         buffer and one set of events per host thread for this, allocated
- *         on first use and kept until the process ends.
+ *   stats HOST out (may be NULL).  SYNCS: with opts->host_ring (pinned host
+ *         memory of the caller, e.g. from hipHostMalloc, at least
+ *         restart * (restart + 2) doubles) the Arnoldi steps are enqueued back
+ *         to back and the host reads each step's coefficients from the ring
+ *         one step behind the device (so a cycle may compute one step past its
+ *         stopping point; that step is not used); without it (NULL) each step
+ *         waits for its coefficients.  It waits for the stream at every
+ *         restart.  The call creates its per-step events and destroys them
+ *         before it returns; it keeps nothing.
  * Returns FSI_OK when ||b - J x||_2 <= rtol ||b||_2 (FP64 residual),
- * FSI_ERR_NOT_CONVERGED (x = last iterate) on the iteration cap or stagnation,
- * FSI_ERR_NAN, FSI_ERR_BREAKDOWN.
+ * FSI_ERR_NOT_CONVERGED (x = last iterate) on the iteration cap or on
+ * stagnation (three restart cycles in a row without a 0.1 % residual
+ * reduction), FSI_ERR_NAN (NaN/Inf in b, in a residual or in an Arnoldi
+ * vector), FSI_ERR_BREAKDOWN.
  */
 typedef struct {
     int32_t restart;          /* Krylov vectors per cycle (e.g. 50) */
@@ -484,6 +488,8 @@ typedef struct {
     double inner_reduction;   /* FP32 cycles stop at this relative reduction (e.g. 1e-5) */
     int32_t precond;          /* fsi_precond (0: block-Jacobi) */
     int32_t vel_steps;        /* Schur forms: minimal-residual steps on the velocity block */
+    double *host_ring;        /* pinned host ring of the caller, or NULL (see below) */
+    int64_t host_ring_len;    /* doubles in host_ring */
 } fsi_solve_opts;
 
 typedef struct {
@@ -522,6 +528,8 @@ typedef struct {
     int32_t precond;          /* fsi_precond: block-Jacobi (0) or a Schur form, rebuilt per iteration */
     int32_t vel_steps;        /* Schur forms: minimal-residual steps on the velocity block */
     int32_t tangent;          /* 0: Picard/Oseen J(u_k); 1: full Newton tangent (fsi_tangent_apply) */
+    double *host_ring;        /* passed to every FGMRES solve (fsi_solve_opts), or NULL */
+    int64_t host_ring_len;
 } fsi_newton_opts;
 
 typedef struct {
@@ -535,21 +543,28 @@ size_t fsi_newton_workspace(const fsi_problem *P64, const fsi_problem *P32,
 
 /*
  * fsi_tangent_apply - the full Newton tangent of the step residual (section 2.4:
- * Newton's method on the monolithic system), i.e. the derivative of
- * fsi_vms_residual with respect to x including what the Picard/Oseen J drops
- * (the reactive convection, the linearised SUPG test functions and tau),
- * applied by a directional forward difference of the FP64 residual:
- *   y = (R(x + e v~) - R0) / e,  v~ = v with its velocity Dirichlet entries
- *   zeroed, e = 2^-26 (1 + ||x||) / ||v~||;  velocity Dirichlet rows y = v.
- * P64, f, lamg, gD as in fsi_vms_residual (FP64, Q1); x double [4][N];
- * R0 = R(x) double [4][N]; v, y [4][N] in precision dtype (not overlapping).
- * ws: at least fsi_tangent_workspace(P64) bytes.  fsi_newton_solve uses it as
- * the Krylov operator when opts->tangent = 1 (the preconditioner keeps the
- * Picard operator).
+ * Newton's method on the monolithic system; section 2.1 for the terms), i.e.
+ * the derivative of fsi_vms_residual with respect to x, applied to v:
+ *   y = J_full(x) v = A(a = u, tau(u)) v~ + [B^T kappa B v~_u; 0]
+ *       + (reactive convection (dv.grad)u in the Galerkin, SUPG and PSPG terms)
+ *       + (SUPG test-function derivative ((dv.grad)w) . rho)
+ *       + (derivatives of tau_m and tau_c along dv: d tau_m = -tau_m^3 s (u.G dv),
+ *          d tau_c = -(tau_c / tau_m) d tau_m),
+ * where rho = r_m(u, p) - f is the state's strong momentum residual and
+ * v~ = v with its velocity Dirichlet entries zeroed; velocity Dirichlet rows
+ * y = v.  The DLM block is linear, so its derivative is the Picard one.
+ *   P  the problem in the precision of the call (P->dtype): s, dir_mask, point
+ *      tables, kappa, dlm_gram or the pointwise path; P->a is ignored (the
+ *      advection field is the state's velocity); no solid block
+ *   x  state (u, p), T [4][N];  f  source c_m u_old + body force, T [3][N]
+ *      (lamg and gD of the residual are constant and drop out)
+ *   v, y  T [4][N], y must not alias x, f or v
+ * Q1 only.  ws: at least fsi_tangent_workspace(P) bytes.  Deterministic.
+ * fsi_newton_solve uses it as the Krylov operator when opts->tangent = 1 (in
+ * the inner precision; the preconditioner keeps the Picard operator).
  */
-size_t fsi_tangent_workspace(const fsi_problem *P64);
-int fsi_tangent_apply(const fsi_problem *P64, const double *f, const double *lamg, const double *gD,
-                      const double *x, const double *R0, fsi_dtype dtype, const void *v, void *y,
+size_t fsi_tangent_workspace(const fsi_problem *P);
+int fsi_tangent_apply(const fsi_problem *P, const void *x, const void *f, const void *v, void *y,
                       void *ws, size_t ws_bytes, void *stream);
 int fsi_newton_solve(const fsi_problem *P64, const fsi_problem *P32, const double *f,
                      const double *lamg, const double *gD, double *x,
@@ -665,9 +680,12 @@ size_t fsi_dot_workspace(void);
 
 /*
  * Kernel timing (tracing aid, not part of the method).  fsi_profile_enable(1)
- * resets the totals and brackets each later launch of an instrumented kernel
- * with two hipEvents recorded on that launch's stream; fsi_profile_enable(0)
- * stops recording.  fsi_profile_read(name, ...) waits for the recorded events
+ * creates a pool of hipEvents, resets the totals and brackets each later launch
+ * of an instrumented kernel with two events recorded on that launch's stream;
+ * fsi_profile_enable(0) stops recording and destroys the events and the totals
+ * (read them before).  This timing registry is the only state the library keeps
+ * between calls besides the per-thread error text, and it exists only while
+ * profiling is on; do not switch it while another thread is inside a call.  fsi_profile_read(name, ...) waits for the recorded events
  * (SYNCS) and returns the summed elapsed milliseconds and the number of
  * launches of the kernel `name` ("vms_q1_cells", "vms_q2_cells",
  * "vms_gather", "dlm_cell_reduce", "dlm_locate", ...; unknown names read 0).

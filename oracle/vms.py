@@ -39,13 +39,15 @@ def lib():
         _lib.oracle_source_matrix.argtypes = [I, P, P, I, P, P, ctypes.c_uint, P]
         _lib.oracle_element_tangent.argtypes = [I, P, P, I, I, P, P, P, P]
         _lib.oracle_vms_tangent_apply.argtypes = [P, I, P, P, I, P, P, P, P, P, P]
+        _lib.oracle_vms_step_rows.argtypes = [P, I, P, P, I, P, P, P, P, P, I, P, ctypes.c_int64, P]
         _lib.oracle_vms_apply.argtypes = [P, I, P, P, I, P, P, P, P, P]
         _lib.oracle_vms_rows.argtypes = [P, I, P, P, I, P, P, P, P, P, ctypes.c_int64, P]
         _lib.oracle_vms_diag_blocks.argtypes = [P, I, P, P, I, P, P, P, P]
         _lib.oracle_vms_residual.argtypes = [P, I, P, P, I, P, P, P, P]
         for f in (_lib.oracle_element_matrix, _lib.oracle_source_matrix, _lib.oracle_vms_apply,
                   _lib.oracle_vms_rows, _lib.oracle_vms_diag_blocks, _lib.oracle_vms_residual,
-                  _lib.oracle_element_tangent, _lib.oracle_vms_tangent_apply):
+                  _lib.oracle_element_tangent, _lib.oracle_vms_tangent_apply,
+                  _lib.oracle_vms_step_rows):
             f.restype = ctypes.c_int
     return _lib
 
@@ -180,6 +182,23 @@ def tangent_apply(grid, prm, x, f, v, s=None, mask=None, visc_strong=True):
     if rc:
         raise ValueError(f"oracle_vms_tangent_apply failed ({rc})")
     return y
+
+
+def step_rows(grid, prm, x, f, rows, s=None, mask=None, v=None, visc_strong=True):
+    """Rows (flat f*N + node) of residual_fluid (v is None) or of tangent_apply (v given)."""
+    n, h = _grid_args(grid)
+    N = grid.num_nodes
+    x = _f64(x).reshape(4, N); f = _f64(f).reshape(3, N); s = _f64(s); prm = _f64(prm)
+    vv = None if v is None else _f64(v).reshape(4, N)
+    m = _mask_bytes(mask)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.zeros(rows.size)
+    rc = lib().oracle_vms_step_rows(_p(n), grid.order, _p(h), _p(prm), int(bool(visc_strong)), _p(s),
+                                    _p(m), _p(x), _p(f), _p(vv), 1 if v is None else 2, _p(rows),
+                                    rows.size, _p(out))
+    if rc:
+        raise ValueError(f"oracle_vms_step_rows failed ({rc})")
+    return out
 
 
 def cell_node_ids(grid, cx, cy, cz):

@@ -758,3 +758,84 @@ int oracle_vms_tangent_apply(const int *n, int p, const double *h, const double 
     free(ye);
     return 0;
 }
+
+/*
+ * Selected rows (rows[r] = f*N + node) of the step residual's fluid part
+ * (mode 1: sum_e K_e(a=u) x_e - L_e(a=u) f_e, no Dirichlet handling, as
+ * oracle_vms_residual) or of the full tangent times v (mode 2: as
+ * oracle_vms_tangent_apply, Dirichlet columns of v zeroed and rows = v).
+ * Each row sums the contributions of the cells containing the node.
+ */
+int oracle_vms_step_rows(const int *n, int p, const double *h, const double *prm, int visc_strong,
+                         const double *s, const uint8_t *dmask, const double *x, const double *f,
+                         const double *v, int mode, const int64_t *rows, int64_t nrows, double *out)
+{
+    if ((p != 1 && p != 2) || (mode != 1 && mode != 2)) return -1;
+    const int q = p + 1, nen = q * q * q, nd = 4 * nen, nc = 3 * nen;
+    const int64_t Nx = (int64_t)p * n[0] + 1, Ny = (int64_t)p * n[1] + 1, Nz = (int64_t)p * n[2] + 1;
+    const int64_t N = Nx * Ny * Nz;
+    int err = 0;
+#pragma omp parallel
+    {
+        double *K = (double *)malloc(sizeof(double) * (size_t)nd * nd);
+        double *L = (double *)malloc(sizeof(double) * (size_t)nd * nc);
+        double x_e[108], f_e[81], s_e[27], v_e[108];
+        int64_t ids[27];
+        if (!K || !L) {
+#pragma omp atomic write
+            err = -2;
+        }
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t r = 0; r < nrows; ++r) {
+            if (!K || !L) continue;
+            int64_t row = rows[r];
+            int fr = (int)(row / N);
+            int64_t g = row % N;
+            if (mode == 2 && fr < 3 && dmask && dmask[row]) {
+                out[r] = v[row];
+                continue;
+            }
+            int64_t gi[3] = {g % Nx, (g / Nx) % Ny, g / (Nx * Ny)};
+            int64_t lo[3], hi[3];
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = gi[d] - p < 0 ? 0 : (gi[d] - 1) / p;
+                hi[d] = gi[d] / p;
+                if (hi[d] > n[d] - 1) hi[d] = n[d] - 1;
+            }
+            double acc = 0.0;
+            for (int64_t cz = lo[2]; cz <= hi[2]; ++cz)
+                for (int64_t cy = lo[1]; cy <= hi[1]; ++cy)
+                    for (int64_t cx = lo[0]; cx <= hi[0]; ++cx) {
+                        int A = (int)((gi[0] - p * cx) + q * ((gi[1] - p * cy) + q * (gi[2] - p * cz)));
+                        cell_nodes(n, p, cx, cy, cz, ids);
+                        for (int B = 0; B < nen; ++B) {
+                            int64_t gg = ids[B];
+                            for (int d = 0; d < 4; ++d) {
+                                x_e[d * nen + B] = x[d * N + gg];
+                                if (mode == 2) {
+                                    double vv = v[d * N + gg];
+                                    if (d < 3 && dmask && dmask[d * N + gg]) vv = 0.0;
+                                    v_e[d * nen + B] = vv;
+                                }
+                            }
+                            for (int d = 0; d < 3; ++d) f_e[d * nen + B] = f[d * N + gg];
+                            if (s) s_e[B] = s[gg];
+                        }
+                        const int rr = fr * nen + A;
+                        if (mode == 1) {
+                            oracle_element_matrix(p, h, prm, visc_strong, 0, x_e, s ? s_e : NULL, OR_ALL, K);
+                            oracle_source_matrix(p, h, prm, 0, x_e, s ? s_e : NULL, OR_SRC_ALL, L);
+                            for (int c = 0; c < nd; ++c) acc += K[(size_t)rr * nd + c] * x_e[c];
+                            for (int c = 0; c < nc; ++c) acc -= L[(size_t)rr * nc + c] * f_e[c];
+                        } else {
+                            oracle_element_tangent(p, h, prm, visc_strong, 0, x_e, f_e, s ? s_e : NULL, K);
+                            for (int c = 0; c < nd; ++c) acc += K[(size_t)rr * nd + c] * v_e[c];
+                        }
+                    }
+            out[r] = acc;
+        }
+        free(K);
+        free(L);
+    }
+    return err;
+}

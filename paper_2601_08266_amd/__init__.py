@@ -487,14 +487,27 @@ def schur_apply(problem: Problem, precond, pc: torch.Tensor, v: torch.Tensor,
     return z
 
 
+def _attach_host_ring(o, restart, pinned):
+    """Give the options a pinned host ring for the Arnoldi coefficients (the library keeps no
+    host memory of its own); the tensor lives as long as the options object."""
+    n = int(restart) * (int(restart) + 2)
+    if pinned and torch.cuda.is_available():
+        ring = torch.empty(n, dtype=torch.float64, pin_memory=True)
+        o._host_ring = ring
+        o.host_ring, o.host_ring_len = ring.data_ptr(), n
+    else:
+        o.host_ring, o.host_ring_len = None, 0
+
+
 def solve_opts(restart=50, max_iters=2000, rtol=1e-10, inner=torch.float32,
-               inner_reduction=1e-5, precond="bjacobi", vel_steps=0) -> FsiSolveOpts:
+               inner_reduction=1e-5, precond="bjacobi", vel_steps=0, pinned=True) -> FsiSolveOpts:
     o = FsiSolveOpts()
     o.restart, o.max_iters, o.rtol = int(restart), int(max_iters), float(rtol)
     o.inner = dtype_code(inner)
     o.inner_reduction = float(inner_reduction)
     o.precond = _precond_code(precond)
     o.vel_steps = int(vel_steps)
+    _attach_host_ring(o, restart, pinned)
     return o
 
 
@@ -520,7 +533,7 @@ def fgmres_solve(J64: Problem, b: torch.Tensor, x: torch.Tensor, opts: FsiSolveO
 
 def newton_opts(tol_abs, max_newton=20, eta=1e-3, restart=50, max_krylov=2000,
                 inner=torch.float32, inner_reduction=1e-5, precond="bjacobi", vel_steps=0,
-                tangent="picard") -> FsiNewtonOpts:
+                tangent="picard", pinned=True) -> FsiNewtonOpts:
     o = FsiNewtonOpts()
     o.max_newton, o.tol_abs, o.eta = int(max_newton), float(tol_abs), float(eta)
     o.restart, o.max_krylov = int(restart), int(max_krylov)
@@ -529,21 +542,26 @@ def newton_opts(tol_abs, max_newton=20, eta=1e-3, restart=50, max_krylov=2000,
     o.precond = _precond_code(precond)
     o.vel_steps = int(vel_steps)
     o.tangent = {"picard": 0, "full": 1}[tangent] if isinstance(tangent, str) else int(tangent)
+    _attach_host_ring(o, restart, pinned)
     return o
 
 
-def tangent_apply(P64: Problem, f: torch.Tensor, x: torch.Tensor, R0: torch.Tensor, v: torch.Tensor,
-                  lamg=None, gD=None, y: Optional[torch.Tensor] = None, stream=None):
-    """Full Newton tangent times v by a directional difference of the residual (fsi_tangent_apply)."""
-    _need(x, "x", torch.float64, 4 * P64.N)
-    _need(R0, "R0", torch.float64, 4 * P64.N)
+def tangent_apply(P: Problem, x: torch.Tensor, f: torch.Tensor, v: torch.Tensor,
+                  y: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None):
+    """Full Newton tangent of the step residual at state x (source f) times v (fsi_tangent_apply),
+    all in the problem's precision."""
+    dt = P.dtype
+    _need(x, "x", dt, 4 * P.N)
+    _need(f, "f", dt, 3 * P.N)
+    _need(v, "v", dt, 4 * P.N)
     if y is None:
         y = torch.empty_like(v)
-    nbytes = int(L.lib().fsi_tangent_workspace(ctypes.byref(P64.struct)))
-    ws = _workspace(nbytes, x.device, None)
+    nbytes = int(L.lib().fsi_tangent_workspace(ctypes.byref(P.struct)))
+    if nbytes == 0:
+        raise ValueError("invalid tangent arguments: " + L.lib().fsi_last_error().decode())
+    ws = _workspace(nbytes, x.device, ws)
     L.check("fsi_tangent_apply", L.lib().fsi_tangent_apply(
-        ctypes.byref(P64.struct), _ptr(f), _ptr(lamg), _ptr(gD), _ptr(x), _ptr(R0), dtype_code(v.dtype),
-        _ptr(v), _ptr(y), _ptr(ws), ws.numel(), _stream(stream)))
+        ctypes.byref(P.struct), _ptr(x), _ptr(f), _ptr(v), _ptr(y), _ptr(ws), ws.numel(), _stream(stream)))
     return y
 
 

@@ -57,7 +57,8 @@ class FsiSolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_iters", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("inner", ctypes.c_int),
                 ("inner_reduction", ctypes.c_double), ("precond", ctypes.c_int32),
-                ("vel_steps", ctypes.c_int32)]
+                ("vel_steps", ctypes.c_int32), ("host_ring", ctypes.c_void_p),
+                ("host_ring_len", ctypes.c_int64)]
 
 
 class FsiSolveStats(ctypes.Structure):
@@ -71,7 +72,8 @@ class FsiNewtonOpts(ctypes.Structure):
                 ("eta", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_krylov", ctypes.c_int32), ("inner", ctypes.c_int),
                 ("inner_reduction", ctypes.c_double), ("precond", ctypes.c_int32),
-                ("vel_steps", ctypes.c_int32), ("tangent", ctypes.c_int32)]
+                ("vel_steps", ctypes.c_int32), ("tangent", ctypes.c_int32),
+                ("host_ring", ctypes.c_void_p), ("host_ring_len", ctypes.c_int64)]
 
 
 class FsiNewtonStats(ctypes.Structure):
@@ -156,7 +158,7 @@ SIGNATURES = {
     "fsi_newton_workspace": (SZ, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiProblem),
                                   ctypes.POINTER(FsiNewtonOpts)]),
     "fsi_tangent_workspace": (SZ, [ctypes.POINTER(FsiProblem)]),
-    "fsi_tangent_apply": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, P, P, P, ctypes.c_int, P, P, P, SZ, P]),
+    "fsi_tangent_apply": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, P, P, P, SZ, P]),
     "fsi_newton_solve": (ctypes.c_int, [ctypes.POINTER(FsiProblem), ctypes.POINTER(FsiProblem), P, P,
                                         P, P, ctypes.POINTER(FsiNewtonOpts),
                                         ctypes.POINTER(FsiNewtonStats), P, SZ, P]),

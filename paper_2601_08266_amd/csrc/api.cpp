@@ -103,10 +103,13 @@ size_t vms_workspace_bytes(const Geo &g, fsi_dtype dt)
     return align_up((size_t)8 * (size_t)pi.cls * (dt == FSI_F64 ? 8 : 4));
 }
 
+// tstate / tsrc (Q1 only): apply the full Newton tangent at the state tstate = (u, p) with
+// source tsrc instead (a must then be tstate's velocity): the Picard cells, then the tangent
+// correction added to the same brick partials, then the node gather.
 template <typename T>
 static int vms_apply_t(const Geo &g, const fsi_vms_params &prm, const T *a, const T *s,
                        const uint32_t *mask, const T *x, T *y, const DlmView *dlm, void *ws,
-                       hipStream_t st)
+                       hipStream_t st, const T *tstate = nullptr, const T *tsrc = nullptr)
 {
     const BrickLayout bl = brick_layout(g);
     const VmsConst<T> k = make_vms_const<T>(g, prm, s != nullptr);
@@ -123,6 +126,10 @@ static int vms_apply_t(const Geo &g, const fsi_vms_params &prm, const T *a, cons
     else
         rc = launch_q2_cells<T>(g, k, x, a, s, mask, gram, gidx, part, bl, st);
     if (rc) return rc;
+    if (tstate != nullptr) {
+        rc = launch_q1_tangent<T>(g, k, tstate, tsrc, s, mask, x, part, bl, st);
+        if (rc) return rc;
+    }
     const fsi_dtype dt = sizeof(T) == 8 ? FSI_F64 : FSI_F32;
     if (dlm != nullptr && dlm->n_occ > 0 && dlm->solid != nullptr) {
         // solid block: u_s = B x (Dirichlet-masked), l_s = K_s u_s at the solid nodes, then the
@@ -189,6 +196,21 @@ int launch_vms_residual(const Geo &g, const fsi_vms_params &prm, fsi_dtype dt, c
                                       (const double *)lamg, (double *)R, ws, st);
     return vms_residual_t<float>(g, prm, (const float *)s, mask, (const float *)gD, (const float *)x,
                                  (const float *)f, dlm, (const float *)lamg, (float *)R, ws, st);
+}
+
+int launch_tangent_apply(const Geo &g, const fsi_vms_params &prm, fsi_dtype dt, const void *s,
+                         const uint32_t *mask, const void *x, const void *f, const DlmView *dlm,
+                         const void *v, void *y, void *ws, hipStream_t st)
+{
+    if (g.p != 1) {
+        set_error("the full Newton tangent is implemented for Q1 grids");
+        return FSI_ERR_UNSUPPORTED;
+    }
+    if (dt == FSI_F64)
+        return vms_apply_t<double>(g, prm, (const double *)x, (const double *)s, mask, (const double *)v,
+                                   (double *)y, dlm, ws, st, (const double *)x, (const double *)f);
+    return vms_apply_t<float>(g, prm, (const float *)x, (const float *)s, mask, (const float *)v, (float *)y,
+                              dlm, ws, st, (const float *)x, (const float *)f);
 }
 
 int launch_vms_apply(const Geo &g, const fsi_vms_params &prm, fsi_dtype dt, const void *a,
@@ -924,54 +946,38 @@ FSI_API size_t fsi_newton_workspace(const fsi_problem *P64, const fsi_problem *P
     return newton_workspace_bytes(make_geo(P64->grid), *o, jw);
 }
 
-FSI_API size_t fsi_tangent_workspace(const fsi_problem *P64)
+FSI_API size_t fsi_tangent_workspace(const fsi_problem *P)
 {
     clear_error();
-    if (check_problem(P64) != FSI_OK) return 0;
-    const Geo g = make_geo(P64->grid);
-    return align_up(tangent_workspace_bytes(g)) + jac_ws(P64);
+    if (check_problem(P) != FSI_OK) return 0;
+    return jac_ws(P);
 }
 
-FSI_API int fsi_tangent_apply(const fsi_problem *P64, const double *f, const double *lamg, const double *gD,
-                              const double *x, const double *R0, fsi_dtype dtype, const void *v, void *y,
+FSI_API int fsi_tangent_apply(const fsi_problem *P, const void *x, const void *f, const void *v, void *y,
                               void *ws, size_t ws_bytes, void *stream)
 {
     clear_error();
-    int rc = check_problem(P64);
+    int rc = check_problem(P);
     if (rc) return rc;
-    FSI_CHECK_ARG(P64->dtype == FSI_F64, "the tangent takes the FP64 problem");
-    FSI_CHECK_ARG(dtype_ok(dtype), "bad dtype");
-    if (P64->grid.order != 1) {
-        set_error("the residual kernel is implemented for Q1 grids");
+    if (P->grid.order != 1) {
+        set_error("the full Newton tangent is implemented for Q1 grids");
         return FSI_ERR_UNSUPPORTED;
     }
-    if (P64->solid != nullptr) {
-        set_error("a problem carrying the solid block: its step residual is fsi_solid_step_residual");
+    if (P->solid != nullptr) {
+        set_error("a problem carrying the solid block: its step is fsi_newton_solid_solve (Picard only)");
         return FSI_ERR_UNSUPPORTED;
     }
-    FSI_CHECK_ARG(f && x && R0 && v && y && v != y, "f, x, R0, v, y must be non-NULL and v != y");
-    FSI_CHECK_ARG(P64->dir_mask == nullptr || gD != nullptr, "gD required with a Dirichlet mask");
-    if (P64->n_occ > 0 && P64->dlm_gram == nullptr) {
-        set_error("the tangent needs the per-cell DLM blocks (fsi_dlm_gram) when n_occ > 0");
-        return FSI_ERR_UNSUPPORTED;
-    }
-    const Geo g = make_geo(P64->grid);
-    const size_t a = align_up(tangent_workspace_bytes(g));
-    if (ws == nullptr || ws_bytes < a + jac_ws(P64)) {
-        set_error("workspace of %zu bytes needed (got %zu)", a + jac_ws(P64), ws_bytes);
+    FSI_CHECK_ARG(x && f && v && y, "x, f, v and y must be non-NULL");
+    FSI_CHECK_ARG(v != y && x != y && f != y, "y must not alias x, f or v");
+    const Geo g = make_geo(P->grid);
+    const size_t need = jac_ws(P);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
         return FSI_ERR_WORKSPACE;
     }
-    // the difference step of fsi_newton_solve: 2^-26 (1 + ||x||), ||x|| from the device (SYNCS)
-    hipStream_t st = as_stream(stream);
-    double *scr = reinterpret_cast<double *>(reinterpret_cast<char *>(ws) + a);
-    rc = kry_norm(4 * g.N, x, scr, scr + KRY_NB, st);
-    if (rc) return rc;
-    double xn = 0.0;
-    FSI_HIP(hipMemcpyAsync(&xn, scr + KRY_NB, sizeof(double), hipMemcpyDeviceToHost, st));
-    FSI_HIP(hipStreamSynchronize(st));
-    const DlmView dv = view_of(P64);
-    return tangent_apply(g, *P64, P64->n_occ > 0 ? &dv : nullptr, f, lamg, gD, x, R0, std::ldexp(1.0, -26) * (1.0 + xn),
-                         dtype, v, y, ws, reinterpret_cast<char *>(ws) + a, st);
+    const DlmView dv = view_of(P);
+    return launch_tangent_apply(g, P->prm, P->dtype, P->s, P->dir_mask, x, f, P->n_occ > 0 ? &dv : nullptr, v, y,
+                                ws, as_stream(stream));
 }
 
 FSI_API int fsi_newton_solve(const fsi_problem *P64, const fsi_problem *P32, const double *f,

@@ -355,7 +355,9 @@ __global__ __launch_bounds__(256) void dlm_B_kernel(Geo g, int64_t m, const int3
 // false) or mu = B u restricted to the cell, Dirichlet-masked (FROM_U = true).  LPC lanes per
 // occupied cell (64 / LPC cells per wavefront): lane r takes the cell's points r, r + LPC, ...
 // in sorted order, then an xor butterfly over the LPC lanes gives every lane the sums and lane
-// r stores the entries e = r, r + LPC, ... (fixed order: deterministic).
+// r stores the entries e = r, r + LPC, ... (fixed order: deterministic).  The sums run in FP64
+// for both precisions (a cell can hold hundreds of points; an FP32 product is rounded once
+// per term and the total once when stored).
 template <typename T, int P, bool FROM_U, int LPC>
 __global__ __launch_bounds__(256) void dlm_cell_reduce(Geo g, int64_t m, int64_t n_occ,
                                                        const int32_t *__restrict__ occ_cell,
@@ -389,11 +391,11 @@ __global__ __launch_bounds__(256) void dlm_cell_reduce(Geo g, int64_t m, int64_t
             }
         }
     }
-    T acc[NEN][3];
+    double acc[NEN][3];
 #pragma unroll
     for (int A = 0; A < NEN; ++A)
 #pragma unroll
-        for (int f = 0; f < 3; ++f) acc[A][f] = T(0);
+        for (int f = 0; f < 3; ++f) acc[A][f] = 0.0;
     const int32_t j0 = occ_start[o], j1 = occ_start[o + 1];
     // FP32: UB points per lane and round, their sorted positions' point indices loaded together,
     // then their xi / kappa / src, then accumulated in ascending order (the loads of a round in
@@ -446,7 +448,7 @@ __global__ __launch_bounds__(256) void dlm_cell_reduce(Geo g, int64_t m, int64_t
             for (int A = 0; A < NEN; ++A) {
                 const T w = Nx[A % Q] * Ny[(A / Q) % Q] * Nz[A / (Q * Q)];
 #pragma unroll
-                for (int f = 0; f < 3; ++f) acc[A][f] += w * mu[f];
+                for (int f = 0; f < 3; ++f) acc[A][f] += (double)(w * mu[f]);
             }
         }
     }
@@ -454,10 +456,10 @@ __global__ __launch_bounds__(256) void dlm_cell_reduce(Geo g, int64_t m, int64_t
     for (int A = 0; A < NEN; ++A)
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            T v = acc[A][f];
+            double v = acc[A][f];
 #pragma unroll
             for (int off = 1; off < LPC; off <<= 1) v += __shfl_xor(v, off, 64);
-            if ((A * 3 + f) % LPC == lane) csum[(o * NEN + A) * 3 + f] = v;
+            if ((A * 3 + f) % LPC == lane) csum[(o * NEN + A) * 3 + f] = (T)v;
         }
 }
 

@@ -16,6 +16,7 @@
 #include "fgmres.hpp"
 #include "krylov.hpp"
 #include "profile.hpp"
+#include "stall.hpp"
 
 namespace fsi {
 
@@ -46,40 +47,26 @@ Layout layout(int64_t n, int m, fsi_dtype inner, size_t jws_bytes)
     return L;
 }
 
-// Pinned host memory for the per-step coefficient copies and the per-step events: allocated on
-// first use, grown as needed, kept for the life of the process (per host thread).
-double *pinned_ring(size_t doubles)
-{
-    thread_local double *buf = nullptr;
-    thread_local size_t cap = 0;
-    if (cap < doubles) {
-        if (buf) (void)hipHostFree(buf);
-        buf = nullptr;
-        cap = 0;
-        if (hipHostMalloc(reinterpret_cast<void **>(&buf), doubles * sizeof(double), hipHostMallocDefault) !=
-            hipSuccess) {
-            set_error("hipHostMalloc of %zu bytes failed", doubles * sizeof(double));
-            buf = nullptr;
-            return nullptr;
-        }
-        cap = doubles;
+// The per-step events of one solve, created at its start and destroyed when it returns.
+struct StepEvents {
+    std::vector<hipEvent_t> ev;
+    ~StepEvents()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
-    return buf;
-}
-
-std::vector<hipEvent_t> &step_events(int m)
-{
-    thread_local std::vector<hipEvent_t> ev;
-    while ((int)ev.size() < m) {
-        hipEvent_t e = nullptr;
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-            set_error("hipEventCreate failed");
-            break;
+    int create(int m)
+    {
+        while ((int)ev.size() < m) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                set_error("hipEventCreate failed");
+                return FSI_ERR_HIP;
+            }
+            ev.push_back(e);
         }
-        ev.push_back(e);
+        return FSI_OK;
     }
-    return ev;
-}
+};
 
 }  // namespace
 
@@ -143,6 +130,20 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
         (void)0;
         double prev_beta = -1.0;
         int stalls = 0;
+        // host copies of the per-step coefficients: the caller's pinned ring (copies run behind
+        // the device, see below) or, without one, host memory of this call with a wait per step
+        const size_t ring_len = (size_t)m * (m + 2);
+        const bool pinned = o.host_ring != nullptr;
+        if (pinned && o.host_ring_len < (int64_t)ring_len) {
+            set_error("host_ring holds %lld doubles, %zu needed", (long long)o.host_ring_len, ring_len);
+            rc = FSI_ERR_ARG;
+            goto done;
+        }
+        std::vector<double> own_ring(pinned ? 0 : ring_len);
+        double *hring = pinned ? o.host_ring : own_ring.data();
+        StepEvents events;
+        TRY(events.create(m));
+        std::vector<hipEvent_t> &ev = events.ev;
         for (;;) {
             // true residual r = b - J64 x in FP64 (stored in V[0])
             {
@@ -168,12 +169,10 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
                 rc = FSI_ERR_NOT_CONVERGED;
                 goto done;
             }
-            if (prev_beta >= 0.0 && beta > 0.999 * prev_beta) {
-                if (++stalls >= 3) {
-                    set_error("stagnation at residual %.3e (target %.3e)", beta, target);
-                    rc = FSI_ERR_NOT_CONVERGED;
-                    goto done;
-                }
+            if (krylov_stagnated(prev_beta, beta, stalls)) {
+                set_error("stagnation at residual %.3e (target %.3e)", beta, target);
+                rc = FSI_ERR_NOT_CONVERGED;
+                goto done;
             }
             prev_beta = beta;
             TRY(kry_scale_inv(n, V, hdev, V, st));
@@ -187,16 +186,6 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
             // it.  The host applies the Givens rotations one step behind the device, so the
             // convergence test lags by one step (at most one extra step per cycle is computed
             // and then ignored).
-            double *hring = pinned_ring((size_t)m * (m + 2));
-            if (hring == nullptr) {
-                rc = FSI_ERR_HIP;
-                goto done;
-            }
-            std::vector<hipEvent_t> &ev = step_events(m);
-            if ((int)ev.size() < m) {
-                rc = FSI_ERR_HIP;
-                goto done;
-            }
             int kk = 0, enq = 0;
             bool stop = false;
             auto process = [&](int j) -> int {
@@ -272,6 +261,7 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
                 FSI_HIP(hipMemcpyAsync(hring + (size_t)j * (m + 2), d_h, (size_t)(m + 2) * sizeof(double),
                                        hipMemcpyDeviceToHost, st));
                 FSI_HIP(hipEventRecord(ev[j], st));
+                if (!pinned) FSI_HIP(hipEventSynchronize(ev[j]));
                 // next basis vector (if ||w|| = 0 the step ends the cycle and this vector is unused)
                 TRY(kry_scale_inv(n, w64, d_hn, V + (size_t)(j + 1) * n, st));
                 ++enq;

@@ -103,6 +103,12 @@ template <typename T>
 int launch_q1_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, const T *s,
                     const uint32_t *mask, const T *gram, const int32_t *occ_index, T *part,
                     const BrickLayout &bl, hipStream_t st, bool resid);
+// Full-tangent correction (Q1): adds to the brick partials of a Picard apply with a = u the
+// derivative terms that the Picard operator drops, for state x = (u, p), source f and
+// velocity direction dv (Dirichlet entries of dv ignored).
+template <typename T>
+int launch_q1_tangent(const Geo &g, const VmsConst<T> &k, const T *x, const T *f, const T *s,
+                      const uint32_t *mask, const T *dv, T *part, const BrickLayout &bl, hipStream_t st);
 template <typename T>
 int launch_q2_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, const T *s,
                     const uint32_t *mask, const T *gram, const int32_t *occ_index, T *part,
@@ -116,5 +122,11 @@ int launch_gather(const Geo &g, const T *part, const BrickLayout &bl, const T *x
 int launch_vms_residual(const Geo &g, const fsi_vms_params &prm, fsi_dtype dt, const void *s,
                         const uint32_t *mask, const void *gD, const void *x, const void *f,
                         const DlmView *dlm, const void *lamg, void *R, void *ws, hipStream_t st);
+
+// Full Newton tangent of that residual times v (Q1): the Picard apply with a = u plus the
+// correction above; Dirichlet rows y = v.  x: state [4][N], f: source [3][N], precision dt.
+int launch_tangent_apply(const Geo &g, const fsi_vms_params &prm, fsi_dtype dt, const void *s,
+                         const uint32_t *mask, const void *x, const void *f, const DlmView *dlm,
+                         const void *v, void *y, void *ws, hipStream_t st);
 
 }  // namespace fsi

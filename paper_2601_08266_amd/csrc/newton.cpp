@@ -3,8 +3,9 @@
 //   P_k = preconditioner of J(u_k)    (nodal block-Jacobi inverses, or the Schur-complement
 //                                      block preconditioner built from the nodal blocks)
 //   J(u_k) dx = -R_k                  (flexible GMRES, FP64 outer / inner precision); J is the
-//                                      Picard/Oseen operator, or the full Newton tangent applied
-//                                      by directional differences of the residual kernel
+//                                      Picard/Oseen operator, or the full Newton tangent (the
+//                                      Picard cells plus the tangent-correction cells, in the
+//                                      inner precision)
 //   x_{k+1} = x_k + dx
 #include <algorithm>
 #include <chrono>
@@ -21,38 +22,8 @@ namespace fsi {
 
 namespace {
 
-// v64 = v with the velocity Dirichlet entries zeroed (the direction of the difference)
-template <typename T>
-__global__ __launch_bounds__(256) void fd_prepare(int64_t n, int64_t N, const uint32_t *__restrict__ mask,
-                                                  const T *__restrict__ v, double *__restrict__ vm)
-{
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        vm[i] = (i < 3 * N && mask_bit(mask, i)) ? 0.0 : (double)v[i];
-}
-
-// xp = x + (delta / ||vm||) vm   (xp = x when vm = 0)
-__global__ __launch_bounds__(256) void fd_perturb(int64_t n, const double *__restrict__ x, const double *__restrict__ vm,
-                                                  const double *__restrict__ nrm, double delta, double *__restrict__ xp)
-{
-    const double e = nrm[0] > 0.0 ? delta / nrm[0] : 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        xp[i] = x[i] + e * vm[i];
-}
-
-// y = (Rp - R0) ||vm|| / delta; velocity Dirichlet rows y = v
-template <typename T>
-__global__ __launch_bounds__(256) void fd_finish(int64_t n, int64_t N, const uint32_t *__restrict__ mask,
-                                                 const double *__restrict__ Rp, const double *__restrict__ R0,
-                                                 const double *__restrict__ nrm, double delta, const T *__restrict__ v,
-                                                 T *__restrict__ y)
-{
-    const double s = nrm[0] > 0.0 ? nrm[0] / delta : 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        y[i] = (i < 3 * N && mask_bit(mask, i)) ? v[i] : (T)((Rp[i] - R0[i]) * s);
-}
-
 struct NLayout {
-    size_t R, dx, pinv64, pinv32, blocks, pc, a32, scratch, bjws, fd, kws, total;
+    size_t R, dx, pinv64, pinv32, blocks, pc, a32, f32, scratch, bjws, kws, total;
 };
 
 NLayout nlayout(const Geo &g, const fsi_newton_opts &o, size_t jws)
@@ -75,10 +46,12 @@ NLayout nlayout(const Geo &g, const fsi_newton_opts &o, size_t jws)
         L.blocks = take((size_t)16 * g.N * sizeof(double));
         L.pc = take(pcb);
     }
-    L.a32 = take((size_t)3 * g.N * sizeof(float));
+    // FP32 copy of the iterate (its velocity is the Picard advection field; the full tangent
+    // also reads its pressure) and of the source (full tangent)
+    L.a32 = take((size_t)4 * g.N * sizeof(float));
+    L.f32 = o.tangent ? take((size_t)3 * g.N * sizeof(float)) : 0;
     L.scratch = take((size_t)(KRY_NB + 16) * sizeof(double));
     L.bjws = take(bjacobi_workspace_bytes(g));
-    L.fd = o.tangent ? take(tangent_workspace_bytes(g) + (size_t)4 * g.N * sizeof(double)) : 0;
     L.kws = take(fgmres_workspace_bytes(4 * g.N, o.restart, o.inner, jws));
     L.total = off;
     return L;
@@ -90,47 +63,6 @@ double ms_since(std::chrono::steady_clock::time_point t)
 }
 
 }  // namespace
-
-size_t tangent_workspace_bytes(const Geo &g)
-{
-    return 3 * align_up((size_t)4 * g.N * sizeof(double)) + align_up((size_t)(KRY_NB + 16) * sizeof(double));
-}
-
-int tangent_apply(const Geo &g, const fsi_problem &P64, const DlmView *dlm, const double *f, const double *lamg,
-                  const double *gD, const double *x, const double *R0, double delta, fsi_dtype dt, const void *v,
-                  void *y, void *fdws, void *rws, hipStream_t st)
-{
-    const int64_t N = g.N, n = 4 * N;
-    char *base = reinterpret_cast<char *>(fdws);
-    const size_t vb = align_up((size_t)n * sizeof(double));
-    double *vm = reinterpret_cast<double *>(base);
-    double *xp = reinterpret_cast<double *>(base + vb);
-    double *Rp = reinterpret_cast<double *>(base + 2 * vb);
-    double *scr = reinterpret_cast<double *>(base + 3 * vb);
-    double *nrm = scr + KRY_NB;
-    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
-    if (dt == FSI_F64)
-        hipLaunchKernelGGL(fd_prepare<double>, dim3(blocks), dim3(256), 0, st, n, N, P64.dir_mask,
-                           (const double *)v, vm);
-    else
-        hipLaunchKernelGGL(fd_prepare<float>, dim3(blocks), dim3(256), 0, st, n, N, P64.dir_mask,
-                           (const float *)v, vm);
-    FSI_LAUNCH_CHECK();
-    int rc = kry_norm(n, vm, scr, nrm, st);
-    if (rc) return rc;
-    hipLaunchKernelGGL(fd_perturb, dim3(blocks), dim3(256), 0, st, n, x, vm, nrm, delta, xp);
-    FSI_LAUNCH_CHECK();
-    rc = launch_vms_residual(g, P64.prm, FSI_F64, P64.s, P64.dir_mask, gD, xp, f, dlm, lamg, Rp, rws, st);
-    if (rc) return rc;
-    if (dt == FSI_F64)
-        hipLaunchKernelGGL(fd_finish<double>, dim3(blocks), dim3(256), 0, st, n, N, P64.dir_mask, Rp, R0, nrm,
-                           delta, (const double *)v, (double *)y);
-    else
-        hipLaunchKernelGGL(fd_finish<float>, dim3(blocks), dim3(256), 0, st, n, N, P64.dir_mask, Rp, R0, nrm,
-                           delta, (const float *)v, (float *)y);
-    FSI_LAUNCH_CHECK();
-    return FSI_OK;
-}
 
 size_t newton_workspace_bytes(const Geo &g, const fsi_newton_opts &o, size_t jws)
 {
@@ -152,10 +84,8 @@ int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, c
     double *blocks = reinterpret_cast<double *>(base + L.blocks);
     void *pcobj = base + L.pc;
     const bool schur = o.precond != FSI_PC_BJACOBI;
-    void *fdws = base + L.fd;
-    double *R0 = reinterpret_cast<double *>(base + L.fd + 3 * align_up((size_t)4 * g.N * sizeof(double)) +
-                                            align_up((size_t)(KRY_NB + 16) * sizeof(double)));
     float *a32 = reinterpret_cast<float *>(base + L.a32);
+    float *f32 = o.tangent ? reinterpret_cast<float *>(base + L.f32) : nullptr;
     void *bjws = base + L.bjws;
     void *kws = base + L.kws;
     const int64_t n = 4 * g.N;
@@ -184,6 +114,13 @@ int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, c
         FSI_HIP(hipStreamSynchronize(st));
         return FSI_OK;
     };
+    if (o.tangent && o.inner == FSI_F32) {
+        rc = kry_cast_f64_f32(3 * g.N, f, f32, st);
+        if (rc) {
+            if (stats) *stats = S;
+            return rc;
+        }
+    }
     for (int it = 0;; ++it) {
         auto tr = std::chrono::steady_clock::now();
         if (ss != nullptr)
@@ -228,23 +165,12 @@ int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, c
         if (rc) break;
         fsi_problem J32{};
         if (o.inner == FSI_F32) {
-            rc = kry_cast_f64_f32(3 * g.N, x, a32, st);
+            rc = kry_cast_f64_f32((o.tangent ? 4 : 3) * g.N, x, a32, st);
             if (rc) break;
             J32 = *P32;
             J32.a = a32;
         }
         S.t_setup_ms += ms_since(ts);
-        // full tangent: keep R(x_k), and the difference step delta = 2^-26 (1 + ||x_k||)
-        double delta = 0.0;
-        if (o.tangent) {
-            FSI_HIP(hipMemcpyAsync(R0, R, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
-            double xn = 0.0;
-            rc = kry_norm(n, x, scratch, scratch + KRY_NB, st);
-            if (rc) break;
-            FSI_HIP(hipMemcpyAsync(&xn, scratch + KRY_NB, sizeof(double), hipMemcpyDeviceToHost, st));
-            FSI_HIP(hipStreamSynchronize(st));
-            delta = std::ldexp(1.0, -26) * (1.0 + xn);
-        }
         // b = -R, dx = 0
         auto tk = std::chrono::steady_clock::now();
         rc = kry_scale(n, -1.0, R, R, st);
@@ -279,17 +205,18 @@ int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, c
             };
         so.precond = o.precond;
         so.vel_steps = o.vel_steps;
+        so.host_ring = o.host_ring;
+        so.host_ring_len = o.host_ring_len;
         fsi_solve_stats ks{};
-        // operator of the linear solve: the Picard/Oseen J, or the full tangent by differences of
-        // the residual (FP64; the inner-precision vectors are widened and narrowed around it);
-        // the preconditioner keeps the Picard operator
+        // operator of the linear solve: the Picard/Oseen J, or the full Newton tangent at x_k in
+        // the same precision; the preconditioner keeps the Picard operator
         JacobianCall t64{[&](const void *xx, void *yy, void *w, hipStream_t s2) {
-            return tangent_apply(g, P64, P64.n_occ > 0 ? &v64 : nullptr, f, lamg, gD, x, R0, delta, FSI_F64, xx, yy,
-                                 fdws, w, s2);
+            return launch_tangent_apply(g, J64.prm, FSI_F64, J64.s, J64.dir_mask, x, f,
+                                        J64.n_occ > 0 ? &v64 : nullptr, xx, yy, w, s2);
         }};
         JacobianCall t32{[&](const void *xx, void *yy, void *w, hipStream_t s2) {
-            return tangent_apply(g, P64, P64.n_occ > 0 ? &v64 : nullptr, f, lamg, gD, x, R0, delta, FSI_F32, xx, yy,
-                                 fdws, w, s2);
+            return launch_tangent_apply(g, J32.prm, FSI_F32, J32.s, J32.dir_mask, a32, f32,
+                                        J32.n_occ > 0 ? &v32 : nullptr, xx, yy, w, s2);
         }};
         const JacobianCall &op64 = o.tangent ? t64 : c64;
         const JacobianCall &op32 = o.tangent ? t32 : c32;

@@ -7,15 +7,6 @@ namespace fsi {
 
 size_t newton_workspace_bytes(const Geo &g, const fsi_newton_opts &o, size_t jws);
 
-// Full Newton tangent of the step residual applied by a directional forward difference:
-//   y = (R(x + e v~) - R0) / e,  v~ = v with the velocity Dirichlet entries zeroed,
-//   e = delta / ||v~||; velocity Dirichlet rows y = v.  R0 = R(x); v, y in precision dt; the
-//   residual is evaluated in FP64.  fdws: tangent_workspace_bytes(g); rws: the residual's
-//   workspace.
-size_t tangent_workspace_bytes(const Geo &g);
-int tangent_apply(const Geo &g, const fsi_problem &P64, const DlmView *dlm, const double *f, const double *lamg,
-                  const double *gD, const double *x, const double *R0, double delta, fsi_dtype dt, const void *v,
-                  void *y, void *fdws, void *rws, hipStream_t st);
 // One time step with the hyperelastic solid (the problem's points are its nodes): V = B u,
 // U = Ub + cU V, A = cA V - Ab; the step residual gains B^T R^s(U, V, A) and the Newton matrix
 // B^T (c_M M + c_K K - c_V K_v) B with (cA, cU, 1); U and V receive the solid state of the last

@@ -1,6 +1,8 @@
 // Optional per-kernel timing: when enabled, every instrumented launch is
 // bracketed by two hipEvents recorded on the launch stream; reading the
 // totals waits for the events and sums their elapsed times per kernel name.
+// Everything here exists only between fsi_profile_enable(1) and
+// fsi_profile_enable(0): disabling destroys the events and the totals.
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -109,11 +111,20 @@ extern "C" __attribute__((visibility("default"))) int fsi_profile_enable(int on)
     Registry &r = reg();
     std::lock_guard<std::mutex> lk(r.mu);
     int rc = drain(r);
+    if (!on) {
+        for (hipEvent_t e : r.pool) (void)hipEventDestroy(e);
+        std::vector<hipEvent_t>().swap(r.pool);
+        std::vector<std::string>().swap(r.names);
+        std::vector<double>().swap(r.total_ms);
+        std::vector<int64_t>().swap(r.count);
+        r.enabled = false;
+        return rc;
+    }
     for (size_t i = 0; i < r.total_ms.size(); ++i) {
         r.total_ms[i] = 0.0;
         r.count[i] = 0;
     }
-    if (on && r.pool.size() < 512) {
+    if (r.pool.size() < 512) {
         for (int i = 0; i < 512; ++i) {
             hipEvent_t e = nullptr;
             if (hipEventCreate(&e) != hipSuccess) {

@@ -397,6 +397,93 @@ __device__ __forceinline__ void q1_cell(const VmsConst<T> &k, T cu[4][8], const 
     }
 }
 
+// Phase 2 of the full Newton tangent (section 2.4: Newton on the monolithic system): what the
+// Picard/Oseen operator with a = u leaves out of the derivative of the step residual, applied
+// to the velocity direction dv.  With rho = r_m(u, p) - f the strong momentum residual of the
+// state and c = (dv.grad)u, per Gauss point
+//   momentum test w:   w.c + ((u.grad)w).(tau_m c + sigma rho) + tau_m ((dv.grad)w).rho
+//                      + dtau_c (div w)(div u)
+//   continuity test q: grad q.(tau_m c + sigma rho)
+// with sigma = d tau_m = -tau_m^3 s (u.G dv) = -(tau_m / B)(u.G dv), B = K1 + u.G u, and
+// dtau_c = -(tau_c / tau_m) sigma.  cu: state (u, p) in monomial form; cd: dv in monomial form;
+// lq: the residual's point table (f, tau_m, tau_c).
+template <typename T>
+__device__ __forceinline__ void q1_tangent_cell(const VmsConst<T> &k, const T cu[4][8], const T cd[3][8],
+                                                const T *lq, T out[4][8])
+{
+    T mom[4][8];
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) mom[f][i] = T(0);
+
+#pragma unroll 1
+    for (int qi = 0; qi < 8; ++qi) {
+        const QP<T> q = q1_point<T>(qi);
+        const T *lp = lq + Q1_NQV * qi * Q1_NT;
+        const T tau_m = lp[3 * Q1_NT], tau_c = lp[4 * Q1_NT];
+        T U[3], dU[3][3], Ah[3], D[3], Dh[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            U[i] = mval(cu[i], q);
+            dU[i][0] = mdx(cu[i], q);
+            dU[i][1] = mdy(cu[i], q);
+            dU[i][2] = mdz(cu[i], q);
+            Ah[i] = U[i] * k.ih[i];
+            D[i] = mval(cd[i], q);
+            Dh[i] = D[i] * k.ih[i];
+        }
+        const T dP[3] = {mdx(cu[3], q), mdy(cu[3], q), mdz(cu[3], q)};
+        const T div = dU[0][0] * k.ih[0] + dU[1][1] * k.ih[1] + dU[2][2] * k.ih[2];
+        T ngd[3] = {T(0), T(0), T(0)};
+        if (k.visc_strong) {
+            const T u1xy = (cu[1][3] + cu[1][7] * q.z) * k.nu_hh[0][1];
+            const T u2xz = (cu[2][5] + cu[2][7] * q.y) * k.nu_hh[0][2];
+            const T u0xy = (cu[0][3] + cu[0][7] * q.z) * k.nu_hh[0][1];
+            const T u2yz = (cu[2][6] + cu[2][7] * q.x) * k.nu_hh[1][2];
+            const T u0xz = (cu[0][5] + cu[0][7] * q.y) * k.nu_hh[0][2];
+            const T u1yz = (cu[1][6] + cu[1][7] * q.x) * k.nu_hh[1][2];
+            ngd[0] = u1xy + u2xz;
+            ngd[1] = u0xy + u2yz;
+            ngd[2] = u0xz + u1yz;
+        }
+        // rho_i and c_i = dv_j d_j u_i (physical derivatives: reference ones times 1/h)
+        T rho[3], c[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const T conv = Ah[0] * dU[i][0] + Ah[1] * dU[i][1] + Ah[2] * dU[i][2];
+            rho[i] = ((k.c_m * U[i] + conv - lp[i * Q1_NT]) + dP[i] * k.ih[i]) - ngd[i];
+            c[i] = Dh[0] * dU[i][0] + Dh[1] * dU[i][1] + Dh[2] * dU[i][2];
+        }
+        const T B = k.K1 + (Ah[0] * Ah[0] + Ah[1] * Ah[1] + Ah[2] * Ah[2]);
+        const T sigma = -(tau_m / B) * (Ah[0] * Dh[0] + Ah[1] * Dh[1] + Ah[2] * Dh[2]);
+        const T dtc_div = -(tau_c / tau_m) * sigma * div;
+        T e[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) e[i] = tau_m * c[i] + sigma * rho[i];
+        // test-side fluxes multiplied by 1/h_k (reference derivatives of the test functions)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const T tr = tau_m * rho[i];
+            T G[3];
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk) G[kk] = Ah[kk] * e[i] + Dh[kk] * tr;
+            G[i] += dtc_div * k.ih[i];
+            moments(mom[i], c[i], G[0], G[1], G[2], q);
+        }
+        moments(mom[3], T(0), e[0] * k.ih[0], e[1] * k.ih[1], e[2] * k.ih[2], q);
+    }
+    const T W = k.detJ * T(0.125);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) mom[f][i] *= W;
+        from_moments(mom[f]);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) out[f][i] = mom[f][i];
+    }
+}
+
 // Brick handled by block bid.  Blocks are dealt to the 8 XCDs round-robin; each XCD is
 // given a contiguous range of bricks (x fastest), so bricks that share face nodes (and
 // the cache lines holding them) mostly run under the same L2.
@@ -406,18 +493,23 @@ __device__ __forceinline__ int64_t xcd_brick(int64_t bid, int64_t nb)
     return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
-template <typename T, bool RESID>
+// MODE 0: linear apply (advection field a); 1: step residual (a = u, source f in `a`);
+// 2: full-tangent correction: x = state (u, p), `a` = source f, dv = velocity direction; the
+// result is added to the brick partials that the Picard apply (MODE 0 with a = u) wrote.
+template <typename T, int MODE>
 __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, const T *__restrict__ x,
                                                     const T *__restrict__ a,
                                                     const T *__restrict__ s,
                                                     const uint32_t *__restrict__ mask,
                                                     const T *__restrict__ gram,
                                                     const int32_t *__restrict__ occ_index,
-                                                    T *__restrict__ part, int nbx, int nby)
+                                                    T *__restrict__ part, int nbx, int nby,
+                                                    const T *__restrict__ dv)
 {
+    constexpr bool RESID = MODE != 0;
     // LDS, one region used three ways: the brick's nodal fields (staged with coalesced
     // loads), then the lanes' Gauss-point tables, then the lanes' nodal outputs.
-    constexpr int NF = 8;   // x (4), a or f (3), s
+    constexpr int NF = MODE == 2 ? 11 : 8;   // x (4), a or f (3), s (, dv (3))
     constexpr int NJ = (Q1_NL + Q1_NT - 1) / Q1_NT;   // staged nodes per lane
     static_assert(8 * Q1_NQV >= 32 && 8 * Q1_NQV * Q1_NT >= NF * Q1_NL, "LDS too small");
     __shared__ T lds[8 * Q1_NQV * Q1_NT];
@@ -458,17 +550,19 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
                 for (int j = 0; j < NJ; ++j) v[f][j] = T(1);
                 continue;
             }
-            const T *src = f < 4 ? x + f * N : (f < 7 ? a + (f - 4) * N : s);
+            const T *src = f < 4 ? x + f * N : (f < 7 ? a + (f - 4) * N : (f == 7 ? s : dv + (f - 8) * N));
             const __amdgpu_buffer_rsrc_t r = field_rsrc(src + base, rem);
 #pragma unroll
             for (int j = 0; j < NJ; ++j) v[f][j] = buf_load<T>(r, voff[j], 0u);
         }
-        if (!RESID && mask != nullptr) {
+        if (MODE != 1 && mask != nullptr) {
+            // Dirichlet columns: the apply's x, the tangent's direction
+            constexpr int F0 = MODE == 2 ? 8 : 0;
 #pragma unroll
             for (int f = 0; f < 3; ++f)
 #pragma unroll
                 for (int j = 0; j < NJ; ++j)
-                    if (inb[j] && mask_bit(mask, f * N + node[j])) v[f][j] = T(0);
+                    if (inb[j] && mask_bit(mask, f * N + node[j])) v[F0 + f][j] = T(0);
         }
 #pragma unroll
         for (int f = 0; f < NF; ++f)
@@ -480,6 +574,7 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
 
     T cu[4][8];
     T ca[3][8], cs[8];
+    T cd[MODE == 2 ? 3 : 1][8];
     if (valid) {
 #pragma unroll
         for (int A = 0; A < 8; ++A) {
@@ -489,18 +584,28 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
 #pragma unroll
             for (int d = 0; d < 3; ++d) ca[d][A] = lds[(4 + d) * Q1_NL + l];
             cs[A] = k.has_s ? lds[7 * Q1_NL + l] : T(1);
+            if constexpr (MODE == 2) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) cd[d][A] = lds[(8 + d) * Q1_NL + l];
+            }
         }
     }
     __syncthreads();
     T out[4][8];
     if (valid) {
         q1_point_table<T, RESID>(k, cu, ca, cs, lds + t);
-        const T *dlm = nullptr;
-        if (gram != nullptr) {
-            const int32_t ko = occ_index[cx + (int64_t)g.n[0] * (cy + (int64_t)g.n[1] * cz)];
-            if (ko >= 0) dlm = gram + (int64_t)ko * 64;
+        if constexpr (MODE == 2) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) to_monomial(cd[d]);
+            q1_tangent_cell<T>(k, cu, cd, lds + t, out);
+        } else {
+            const T *dlm = nullptr;
+            if (gram != nullptr) {
+                const int32_t ko = occ_index[cx + (int64_t)g.n[0] * (cy + (int64_t)g.n[1] * cz)];
+                if (ko >= 0) dlm = gram + (int64_t)ko * 64;
+            }
+            q1_cell<T, RESID>(k, cu, lds + t, dlm, out);
         }
-        q1_cell<T, RESID>(k, cu, lds + t, dlm, out);
     }
     // element -> node accumulation: every lane parks its 32 nodal outputs in LDS, then each
     // brick node sums the corners of the (up to 8) cells around it in a fixed order
@@ -537,8 +642,14 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
             // bricks of one parity class never share a node: one array per class
             const PartIndex pi(g.nn, nbx, Q1_BX);
             T *pc = part + pi.at((bx & 1) + 2 * (by & 1) + 4 * (bz & 1), bx, gx, gy, gz);
+            if constexpr (MODE == 2) {
+                // added to what the Picard apply of the same brick wrote (stream order)
 #pragma unroll
-            for (int f = 0; f < 4; ++f) pc[f * pi.field] = sum[f];
+                for (int f = 0; f < 4; ++f) pc[f * pi.field] += sum[f];
+            } else {
+#pragma unroll
+                for (int f = 0; f < 4; ++f) pc[f * pi.field] = sum[f];
+            }
         }
     }
 }
@@ -656,14 +767,33 @@ int launch_q1_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, 
                   "Q1 grid planes too large (%d x %d nodes)", g.nn[0], g.nn[1]);
     ProfileScope prof(resid ? "vms_q1_residual" : "vms_q1_cells", st);
     if (resid)
-        hipLaunchKernelGGL((vms_q1_cells<T, true>), dim3((unsigned)bl.nb), dim3(Q1_NT), 0, st, g, k, x, a,
-                           s, mask, gram, occ_index, part, bl.nbx, bl.nby);
+        hipLaunchKernelGGL((vms_q1_cells<T, 1>), dim3((unsigned)bl.nb), dim3(Q1_NT), 0, st, g, k, x, a,
+                           s, mask, gram, occ_index, part, bl.nbx, bl.nby, (const T *)nullptr);
     else
-        hipLaunchKernelGGL((vms_q1_cells<T, false>), dim3((unsigned)bl.nb), dim3(Q1_NT), 0, st, g, k, x,
-                           a, s, mask, gram, occ_index, part, bl.nbx, bl.nby);
+        hipLaunchKernelGGL((vms_q1_cells<T, 0>), dim3((unsigned)bl.nb), dim3(Q1_NT), 0, st, g, k, x,
+                           a, s, mask, gram, occ_index, part, bl.nbx, bl.nby, (const T *)nullptr);
     FSI_LAUNCH_CHECK();
     return FSI_OK;
 }
+
+template <typename T>
+int launch_q1_tangent(const Geo &g, const VmsConst<T> &k, const T *x, const T *f, const T *s,
+                      const uint32_t *mask, const T *dv, T *part, const BrickLayout &bl, hipStream_t st)
+{
+    FSI_CHECK_ARG((int64_t)g.nn[0] * g.nn[1] * (Q1_BZ + 1) * (int64_t)sizeof(T) < ((int64_t)1 << 31),
+                  "Q1 grid planes too large (%d x %d nodes)", g.nn[0], g.nn[1]);
+    ProfileScope prof("vms_q1_tangent", st);
+    hipLaunchKernelGGL((vms_q1_cells<T, 2>), dim3((unsigned)bl.nb), dim3(Q1_NT), 0, st, g, k, x, f, s, mask,
+                       (const T *)nullptr, (const int32_t *)nullptr, part, bl.nbx, bl.nby, dv);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+template int launch_q1_tangent<double>(const Geo &, const VmsConst<double> &, const double *, const double *,
+                                       const double *, const uint32_t *, const double *, double *,
+                                       const BrickLayout &, hipStream_t);
+template int launch_q1_tangent<float>(const Geo &, const VmsConst<float> &, const float *, const float *,
+                                      const float *, const uint32_t *, const float *, float *,
+                                      const BrickLayout &, hipStream_t);
 
 template <typename T, int P, int BX, int BY, int BZ>
 int launch_gather(const Geo &g, const T *part, const BrickLayout &bl, const T *x,

@@ -90,12 +90,8 @@ class ChannelRun:
         g = self.g
         mask = W.channel_dirichlet_mask(g)
         self.mask = torch.tensor(W.mask_to_bits(mask).view(np.int32), device=self.dev)
-        nx, ny, nz = g.nodes_per_axis
-        k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-        inflow = ((i == 0) & (j > 0) & (j < ny - 1) & (k > 0) & (k < nz - 1)).ravel()
-        pat = np.zeros(3 * self.N)
-        pat[: self.N][inflow] = 1.0            # u_x on the inflow face; no-slip wins on edges
-        self.inflow_pattern = torch.tensor(pat, dtype=torch.float64, device=self.dev)
+        self.inflow_pattern = torch.tensor(W.channel_inflow_pattern(g).ravel(), dtype=torch.float64,
+                                           device=self.dev)
         self.gD = torch.zeros(3 * self.N, dtype=torch.float64, device=self.dev)
         self.f = torch.zeros(3 * self.N, dtype=torch.float64, device=self.dev)
         self.zero_out = torch.zeros(self.N * 32, dtype=torch.float32, device=self.dev)
@@ -125,8 +121,39 @@ class ChannelRun:
             self.xdot.zero_()
         self.n = k
 
+    def checkpoint(self, path):
+        """Write the state needed to continue the run (step index, x, the rates and the last
+        states the extrapolated guesses use) to an .npz file (plain arrays, no pickles)."""
+        keep = self.history[-3:]
+        np.savez(path, n=np.int64(self.n), x=self.x.cpu().numpy(), xdot=self.xdot.cpu().numpy(),
+                 hist_n=np.array([r.n for r in keep], dtype=np.int64),
+                 hist_t=np.array([r.t for r in keep], dtype=np.float64),
+                 hist_x=np.stack([r.x.cpu().numpy() for r in keep]),
+                 hist_inflow=np.array([r.inflow for r in keep], dtype=np.float64),
+                 integrator=np.array(self.integrator), coefs=np.array(self.coefs, dtype=np.float64))
+
+    def resume(self, path):
+        """Continue from a checkpoint of the same configuration: the next step is bitwise the
+        one the uninterrupted run takes (the library's kernels are deterministic)."""
+        with np.load(path, allow_pickle=False) as d:
+            if str(d["integrator"]) != self.integrator or not np.array_equal(d["coefs"], np.array(self.coefs)):
+                raise ValueError("checkpoint of another time integrator")
+            if d["x"].size != 4 * self.N:
+                raise ValueError("checkpoint of another grid")
+            self.n = int(d["n"])
+            self.x = torch.tensor(d["x"], dtype=torch.float64, device=self.dev)
+            self.xdot = torch.tensor(d["xdot"], dtype=torch.float64, device=self.dev)
+            self.history = []
+            for k in range(d["hist_n"].size):
+                xk = torch.tensor(d["hist_x"][k], dtype=torch.float64, device=self.dev)
+                self.history.append(StepRecord(int(d["hist_n"][k]), float(d["hist_t"][k]), xk, None, None,
+                                               float(d["hist_inflow"][k])))
+            # history is indexed by step number: pad the steps that were not kept
+            first = int(d["hist_n"][0]) if d["hist_n"].size else self.n
+            self.history = [None] * first + self.history
+
     def inflow_value(self, t):
-        return math.sin(2.0 * math.pi * t / self.period)
+        return W.channel_inflow_value(t, self.period)
 
     def _points(self, t):
         X, gp = W.rotating_plate_points(self.m, self.cfg.seed_fields, t, period=self.period,

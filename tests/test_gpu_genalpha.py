@@ -37,7 +37,7 @@ def test_channel_steps_match_oracle(integrator):
 
     prm = ovms.params_array(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
     mask = W.channel_dirichlet_mask(g)
-    pattern = run.inflow_pattern.cpu().numpy().reshape(3, N)
+    pattern = W.channel_inflow_pattern(g)
     kappa = W.kappa_weights(cfg.m_points, W.plate_volume(), cfg.c_m, cfg.alpha)
     x = np.zeros((4, N))
     xdot = np.zeros((4, N))
@@ -49,7 +49,8 @@ def test_channel_steps_match_oracle(integrator):
                                         amp_deg=run.amp)
         cell, xi = odlm.locate(g, X)
         s = odlm.s_field(g, cell, cfg.s_max)
-        inflow = (1.0 - af) * run.inflow_value(n * dt) + af * run.inflow_value((n + 1) * dt)
+        inflow = ((1.0 - af) * W.channel_inflow_value(n * dt, run.period)
+                  + af * W.channel_inflow_value((n + 1) * dt, run.period))
         x, xdot, _, info = oga.step(g, prm, coefs, dt, x, xdot, cell, xi, kappa, gp, s=s, mask=mask,
                                     gD_stage=pattern * inflow, rel=run.rel_tol)
         assert info["converged"]

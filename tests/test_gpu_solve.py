@@ -14,7 +14,7 @@ from oracle import jacobian as ojac
 from oracle import newton as onewton
 from oracle import vms as ovms
 
-from helpers import field_rel_err, points_for
+from helpers import field_rel_err, points_for, rows_field_rel_err, sample_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -156,26 +156,77 @@ def newton_case(cfg, t_step=0.05):
     return X, g_pts, kappa, u_old, mask, gD, x0
 
 
-def test_residual_c1_matches_oracle():
+def _step_case(case):
+    """State, source and points of one implicit step: the 8^3 sphere, a ragged 11x9x6 grid
+    (several bricks with partial ones in every direction, random points), or 64^3 with the
+    rotating plates (200k points)."""
+    cfg = W.CONFIGS["c2" if case == "c2" else "c1"]
+    if case == "ragged":
+        g = W.Grid((11, 9, 6), 1)
+        rng = np.random.default_rng(21)
+        X = rng.uniform(0.15, 0.85, (3, 2500))
+        kappa = rng.uniform(10.0, 200.0, 2500)
+        N = g.num_nodes
+        Xn, _, _ = W.node_coords(g)
+        u_old = 0.3 * W.advection_field(g, cfg.seed_fields)
+        mask = W.channel_dirichlet_mask(g)
+        gD = np.zeros((3, N))
+        gD[0] = np.where(Xn == 0.0, 0.4, 0.0)
+        gD[:, ~mask[0]] = 0.0
+        x0 = np.concatenate([u_old, np.zeros((1, N))])
+        x0[:3][mask] = gD[mask]
+        g_pts = rng.standard_normal((3, 2500)) * 0.1
+    else:
+        g = cfg.grid
+        X, g_pts, kappa, u_old, mask, gD, x0 = newton_case(cfg)
+    P = build(cfg, u_old, grid=g, X=X, kappa=kappa)
+    return cfg, g, P, X, g_pts, u_old, mask, gD, x0
+
+
+def _residual_ref(g, P, x, u_old, g_pts, mask, gD, c_m, rows=None):
+    """The oracle's step residual: all of it, or the listed rows (fluid rows per row, the DLM
+    term from the point-by-point B and B^T over all points, Dirichlet rows u - gD)."""
+    if rows is None:
+        return onewton.residual(g, P["prm_o"], x, u_old, P["cell"], P["xi"], P["kappa"], g_pts,
+                                s=P["s"], mask=mask, gD=gD).ravel()
+    N = g.num_nodes
+    ref = ovms.step_rows(g, P["prm_o"], x, c_m * u_old, rows, s=P["s"])
+    full = np.zeros(4 * N)
+    Bu = odlm.apply_B(g, P["cell"], P["xi"], x.reshape(4, N)[:3])
+    full[:3 * N] = odlm.apply_BT(g, P["cell"], P["xi"], Bu - g_pts, P["kappa"]).ravel()
+    ref = ref + full[rows]
+    dr = rows < 3 * N
+    md = np.zeros(rows.size, bool)
+    md[dr] = mask.ravel()[rows[dr]]
+    ref[md] = x.ravel()[rows[md]] - gD.ravel()[rows[md]]
+    return ref
+
+
+@pytest.mark.parametrize("case", ["c1", "ragged", "c2"])
+def test_residual_matches_oracle(case):
+    """The nonlinear step residual (FP64) on the 8^3 sphere case and a ragged multi-brick grid
+    (whole vectors), and at 64^3 with 200k points (sampled rows, brick faces and the domain
+    boundary included), per field."""
     import torch
     import paper_2601_08266_amd as fsi
-    cfg = W.CONFIGS["c1"]
-    X, g_pts, kappa, u_old, mask, gD, x0 = newton_case(cfg)
-    g = cfg.grid
+    print(f"residual {case}", flush=True)
+    cfg, g, P, X, g_pts, u_old, mask, gD, x0 = _step_case(case)
     N = g.num_nodes
-    P = build(cfg, u_old, X=X, kappa=kappa)
-    kappa = P["kappa"]
     rng = np.random.default_rng(9)
     x = x0 + 0.01 * rng.standard_normal(x0.shape)
     x[:3][mask] = gD[mask]
     f = cfg.c_m * u_old
     lamg = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
-    fsi.dlm_BT(g, P["J64"].tables, _t(g_pts), lamg, kappa=_t(kappa))
+    fsi.dlm_BT(g, P["J64"].tables, _t(g_pts), lamg, kappa=_t(P["kappa"]))
     R = fsi.vms_residual(P["J64"], _t(f), _t(x), gD=_t(gD), lamg=lamg).cpu().numpy()
-    ref = onewton.residual(g, P["prm_o"], x, u_old, P["cell"], P["xi"], kappa, g_pts, s=P["s"],
-                           mask=mask, gD=gD)
-    err = field_rel_err(R, ref, 4)
-    print(f"residual c1: {err:.3e}")
+    if case == "c2":
+        rows = sample_rows(g, 3000, seed=5)
+        ref = _residual_ref(g, P, x, u_old, g_pts, mask, gD, cfg.c_m, rows)
+        err = rows_field_rel_err(R[rows], ref, rows, N)
+    else:
+        ref = _residual_ref(g, P, x, u_old, g_pts, mask, gD, cfg.c_m)
+        err = field_rel_err(R, ref, 4)
+    print(f"residual {case}: {err:.3e}")
     assert err <= 1e-12
 
 
@@ -213,37 +264,50 @@ def test_newton_c1_matches_dense_newton(inner):
     assert np.linalg.norm(xs - x_ref.ravel()) <= 1e-6 * np.linalg.norm(x_ref)
 
 
+@pytest.mark.parametrize("case", ["c1", "ragged", "c2"])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-def test_tangent_apply_c1_matches_oracle(dt):
-    """Full Newton tangent by a directional difference of the residual (fsi_tangent_apply)
-    against oracle.newton.tangent_fd_apply with the same step rule.  Each side differences its
-    own residual, whose 1e-16 rounding the quotient amplifies by 1/e ~ 1e8, so the two agree
-    to about 1e-7 relative; the bound is 1e-5."""
+def test_tangent_apply_matches_oracle(case, dt):
+    """Full Newton tangent (fsi_tangent_apply: Picard cells + tangent-correction cells + node
+    gather) against the oracle's analytic element tangents (pinned by central differences of the
+    residual), with s, Dirichlet rows/columns and the DLM block; FP32 on FP32-rounded inputs.
+    Whole vectors on the 8^3 and ragged grids, sampled rows per field at 64^3 + 200k points."""
     import torch
     import paper_2601_08266_amd as fsi
-    cfg = W.CONFIGS["c1"]
-    X, g_pts, kappa, u_old, mask, gD, x0 = newton_case(cfg)
-    g = cfg.grid
+    print(f"tangent {case} {dt}", flush=True)
+    cfg, g, P, X, g_pts, u_old, mask, gD, x0 = _step_case(case)
     N = g.num_nodes
-    P = build(cfg, u_old, X=X, kappa=kappa)
-    kappa = P["kappa"]
     rng = np.random.default_rng(12)
-    x = x0 + 0.01 * rng.standard_normal(x0.shape)
+    x = x0 + 0.05 * rng.standard_normal(x0.shape)
     x[:3][mask] = gD[mask]
     f = cfg.c_m * u_old
-    lamg = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
-    fsi.dlm_BT(g, P["J64"].tables, _t(g_pts), lamg, kappa=_t(kappa))
-    R0 = fsi.vms_residual(P["J64"], _t(f), _t(x), gD=_t(gD), lamg=lamg)
-    R0_o = onewton.residual(g, P["prm_o"], x, u_old, P["cell"], P["xi"], kappa, g_pts, s=P["s"], mask=mask, gD=gD)
     v = rng.standard_normal(4 * N)
     if dt == "f32":
-        v = v.astype(np.float32).astype(np.float64)
-    y = fsi.tangent_apply(P["J64"], _t(f), _t(x), R0, _t(v, dt), lamg=lamg, gD=_t(gD)).cpu().numpy()
-    ref = onewton.tangent_fd_apply(g, P["prm_o"], x, R0_o, v, u_old, P["cell"], P["xi"], kappa, g_pts,
-                                   s=P["s"], mask=mask, gD=gD)
-    err = field_rel_err(y, ref, 4)
-    print(f"tangent c1 {dt}: {err:.3e}")
-    assert err <= 1e-5
+        x, f, v = (np.asarray(t_, np.float32).astype(np.float64) for t_ in (x, f, v))
+    J = P["J64"] if dt == "f64" else P["J32"]
+    y = fsi.tangent_apply(J, _t(x, dt), _t(f, dt), _t(v, dt)).cpu().numpy().astype(np.float64)
+    y2 = fsi.tangent_apply(J, _t(x, dt), _t(f, dt), _t(v, dt)).cpu().numpy().astype(np.float64)
+    assert np.array_equal(y, y2)
+    if case == "c2":
+        rows = sample_rows(g, 3000, seed=6)
+        ref = ovms.step_rows(g, P["prm_o"], x, f, rows, s=P["s"], mask=mask, v=v)
+        vm = v.reshape(4, N)[:3].copy()
+        vm[mask] = 0.0
+        dl = odlm.apply_BT(g, P["cell"], P["xi"], odlm.apply_B(g, P["cell"], P["xi"], vm), P["kappa"])
+        dl[mask] = 0.0
+        full = np.concatenate([dl.ravel(), np.zeros(N)])
+        ref = ref + full[rows]
+        err = rows_field_rel_err(y[rows], ref, rows, N)
+    else:
+        ref = onewton.tangent_apply(g, P["prm_o"], x, v, u_old, P["cell"], P["xi"], P["kappa"], s=P["s"],
+                                    mask=mask)
+        err = field_rel_err(y, ref, 4)
+    # the full tangent is not the Picard operator (the test is not vacuous)
+    yp = fsi.jacobian_apply(fsi.Problem(g, J.prm, _t(x[:3], dt), J.tables,
+                                        J.kappa, s=J.s, mask=J.mask, gram=J.gram), _t(v, dt)).cpu().numpy()
+    diff = np.linalg.norm(y - yp) / np.linalg.norm(yp)
+    print(f"tangent {case} {dt}: {err:.3e} (full vs Picard {diff:.2e})")
+    assert err <= (1e-12 if dt == "f64" else 1e-5)
+    assert diff > 1e-6
 
 
 @pytest.mark.parametrize("precond", ["schur_tri", "bjacobi"])
