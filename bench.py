@@ -1,19 +1,23 @@
 #!/usr/bin/env python
 """Benchmark of the immersed FD/DLM Jacobian hot path on one MI355X.
 
-Metric: GDOF/s of the VMS+DLM Jacobian apply, GDOF/s = 4 N_nodes / t_apply.
-Workload (default): 64^3 Q1-Q1 grid (274,625 nodes, 1,098,500 DOF), Oseen
+Metric: GDOF/s of the VMS+DLM Jacobian apply, GDOF/s = 4 N_nodes / t_apply, and
+the wall time of a Newton step to the 1e-8 residual.
+Workload (default): 192^3 Q1-Q1 grid (7,189,057 nodes, 28,756,228 DOF), Oseen
 linearisation about a seeded smooth advection field (nu = 1e-2, dt = 1e-3),
-three thin curved plates with 200,000 solid points (apply mode, no Dirichlet
+three thin curved plates with 2,000,000 solid points (apply mode, no Dirichlet
 mask).  One step = one J x: the VMS operator (Galerkin + SUPG/PSPG/LSIC,
-section 2.1) plus the DLM block B^T diag(kappa) B (section 2.3/2.4), in FP64;
-the FP32 rate is reported beside it.  Inputs are synthetic and resident in
-HBM before timing starts.
+section 2.1) plus the DLM block B^T diag(kappa) B (sections 2.3/2.4), in FP64;
+the FP32 rate and the point-by-point DLM path are reported beside it.  Inputs
+are synthetic and resident in HBM before timing starts; the vectors (690 MB per
+apply) do not fit the 256 MB Infinity Cache.
 
-Extra fields: FP32 apply rate, the point-location time, the HBM-byte rate of
-the VMS kernel, and the roofline of the dominant kernel (vms_q1_cells, FP64
-vector-ALU bound) from library-side hipEvents recorded on its launch stream
-over the timed region.
+Also reported: the roofline of the dominant kernel (vms_q1_cells, FP64 vector-ALU
+bound) from library-side hipEvents recorded on its launch stream over the timed
+applies, the standalone B / B^T, the solid block, the Newton-step block on the
+192^3 rotating-plates channel (plain FP64, mixed precision, extrapolated and
+learned warm starts, Picard and full tangent, all to the same absolute
+residual), and the oracle's apply on the host cores.
 """
 from __future__ import annotations
 
@@ -31,7 +35,7 @@ if ROOT not in sys.path:
 PEAK_FP64_VALU_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (fma) x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 
-# HBM traffic of vms_q1_cells<double> on the 64^3 workload from two rocprofv3 --pmc passes
+# HBM traffic of vms_q1_cells<double> on the headline workload from two rocprofv3 --pmc passes
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads
 # for a plain 512 MiB device copy (FETCH_SIZE reads half the copied bytes, WRITE_SIZE all).
 # Valid only for the kernel sources it was taken on: the hash covers them.
@@ -40,7 +44,7 @@ CELL_TRAFFIC = {"workload": "c2", "sources_sha256_16": "e9557c0c913eabe7", "fetc
 CELL_SOURCES = ("vms_q1.hip", "kernels.hpp", "common.hpp")
 
 
-def cell_traffic_bytes(workload="c2"):
+def cell_traffic_bytes(workload="c5"):
     """Scaled FETCH+WRITE bytes per launch, or None if the kernel changed since the counters
     or the workload is not the one they were taken on."""
     import hashlib
@@ -361,44 +365,178 @@ def newton_step_probe(warm_steps=60, measure_steps=3, modes=None, integrator="be
     return out
 
 
-def cpu_baseline(cfg, case):
-    """The FP64 oracle's Jacobian apply (dense element matrices, point-by-point DLM) on
-    the full workload, once, on the host cores."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_jacobian(cfg, grid, a, x, X, kappa):
     import numpy as np
 
     from oracle import dlm as odlm
     from oracle import jacobian as ojac
     from oracle import vms as ovms
 
-    g = cfg.grid
     prm = ovms.params_array(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
-    cell, xi = odlm.locate(g, case["X_np"])
-    s = odlm.s_field(g, cell, cfg.s_max)
+    cell, xi = odlm.locate(grid, X)
+    s = odlm.s_field(grid, cell, cfg.s_max)
     ovms.lib()
-    times = []
-    for _ in range(3):
-        t0 = time.perf_counter()
-        y = ojac.apply(g, prm, case["a_np"], case["x_np"], cell, xi, case["kappa_np"], s=s)
-        times.append(time.perf_counter() - t0)
-        assert np.all(np.isfinite(y))
+    t0 = time.perf_counter()
+    y = ojac.apply(grid, prm, a, x, cell, xi, kappa, s=s)
+    dt = time.perf_counter() - t0
+    assert np.all(np.isfinite(y))
+    return dt
+
+
+def slab_case(cfg, layers=4):
+    """A slab of `layers` cell layers through the middle of the workload's grid (the same
+    advection field, vector and points restricted to it): the oracle's one-core sample."""
+    import numpy as np
+
+    import fsi_workloads as W
+
+    g = cfg.grid
+    N = g.num_nodes
+    nx, ny, nz = g.nodes_per_axis
+    k0 = g.n[2] // 2 - layers // 2
+    sg = W.Grid((g.n[0], g.n[1], layers), 1, x0=(g.x0[0], g.x0[1], g.x0[2] + k0 * g.h[2]), h=g.h)
+    nodes = (np.arange(nx * ny)[None, :] + nx * ny * (k0 + np.arange(layers + 1))[:, None]).ravel()
+    a = W.advection_field(g, cfg.seed_fields)[:, nodes]
+    x = W.random_vector(4 * N, cfg.seed_vectors).reshape(4, N)[:, nodes]
+    X = W.plate_points(cfg.m_points, cfg.seed_fields)
+    z = X[2]
+    inside = (z >= sg.x0[2]) & (z <= sg.x0[2] + layers * g.h[2])
+    kappa = W.kappa_weights(cfg.m_points, W.plate_volume(), cfg.c_m, cfg.alpha)[inside]
+    return sg, a, x, np.ascontiguousarray(X[:, inside]), kappa
+
+
+def cpu_one_core_main(workload):
+    """Child process (OMP_NUM_THREADS=1): the oracle's Jacobian apply on a slab of the
+    workload; prints one JSON line."""
+    import fsi_workloads as W
+
+    cfg = W.CONFIGS[workload]
+    sg, a, x, X, kappa = slab_case(cfg)
+    times = [_oracle_jacobian(cfg, sg, a, x, X, kappa) for _ in range(3)]
+    dt = sorted(times)[1]
+    print(json.dumps({"value": round(4 * sg.num_nodes / dt / 1e9, 6), "unit": "GDOF/s", "cores": 1,
+                      "seconds": round(dt, 3), "points": int(X.shape[1]),
+                      "sample": f"{sg.n[0]}x{sg.n[1]}x{sg.n[2]}-cell slab through the middle of the grid "
+                                f"({sg.num_nodes} nodes, {X.shape[1]} points), median of 3"}))
+    return 0
+
+
+def cpu_baseline(cfg, case, one_core=True):
+    """The FP64 oracle's Jacobian apply (dense element matrices, point-by-point DLM) on the full
+    workload on all host cores (median of 3), and on one core for a slab of it."""
+    import subprocess
+
+    times = [_oracle_jacobian(cfg, cfg.grid, case["a_np"], case["x_np"], case["X_np"], case["kappa_np"])
+             for _ in range(3)]
     dt = sorted(times)[1]
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(4 * g.num_nodes / dt / 1e9, 6), "unit": "GDOF/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"full FP64 Jacobian apply of the same workload ({g.n[0]}^3 Q1, "
-                      f"{cfg.m_points} points), median of 3 = {dt:.2f} s wall; OpenMP element "
-                      f"loop + numpy DLM"}
+    g = cfg.grid
+    out = {"value": round(4 * g.num_nodes / dt / 1e9, 6), "unit": "GDOF/s", "cores": cores,
+           "kind": "oracle",
+           "sample": f"full FP64 Jacobian apply of the same workload ({g.n[0]}^3 Q1, "
+                     f"{cfg.m_points} points), median of 3 = {dt:.2f} s wall; OpenMP element "
+                     f"loop + numpy DLM",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    if one_core:
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-one-core",
+                            "--workload", next(k for k, v in __import__("fsi_workloads").CONFIGS.items()
+                                               if v is cfg)],
+                           env=env, capture_output=True, text=True, timeout=600)
+        if r.returncode == 0 and r.stdout.strip():
+            out["one_core"] = json.loads(r.stdout.strip().splitlines()[-1])
+        else:
+            out["one_core"] = {"error": (r.stderr or "")[-300:]}
+    return out
+
+
+NEWTON_MODES_C5 = ["plain_f64_st2", "plain_mixed_st2", "extrap_mixed_st2", "extrap_mixed_st2_ft", "nn_mixed_st2"]
+
+
+def newton_block(workload="c5", train_end=20, eval_steps=2, epochs=20, modes=None):
+    """Newton steps of the rotating-plates channel on the workload's grid (192^3 by default):
+    the run is advanced train_end steps (mixed precision, Schur block-triangular preconditioner
+    with two velocity steps); the warm-start network is trained on its steps 2..train_end with
+    the library's kernels; then each of the next eval_steps steps is solved from the same state
+    in every mode, all to the same absolute residual 1e-8 ||R(x_plain)||.  Modes: plain / extrap
+    / nn guess, f64 / mixed inner precision, _ft the full Newton tangent (Picard otherwise)."""
+    import statistics
+
+    import fsi_workloads as W
+    from paper_2601_08266_amd import experiments as ex
+    from paper_2601_08266_amd.learned import LearnedWarmStart
+    from paper_2601_08266_amd.stepper import ChannelRun
+
+    modes = list(modes or NEWTON_MODES_C5)
+    cfg = W.CONFIGS[workload]
+    t0 = time.perf_counter()
+    run = ChannelRun(cfg, precond="schur_tri", vel_steps=2)
+    run.record_extrap = True
+    for _ in range(train_end):
+        run.step()
+    sim_s = time.perf_counter() - t0
+    lw = LearnedWarmStart(run, seed=0)
+    ks = list(range(1, train_end))
+    lw.fit_normalisation(run.history, ks)
+    lw.build_dataset(run.history, ks)
+    lw.train(epochs=epochs, lr=1e-3, seed=0)
+    rows = []
+    for k in range(train_end, train_end + eval_steps):
+        rows.append(ex._solve_modes(run, lw, k, modes))
+        run.restore(k)
+        run.step()
+
+    def agg(m, key):
+        return statistics.mean(r[m][key] for r in rows)
+
+    g = cfg.grid
+    out = {"workload": f"{g.n[0]}^3 Q1 channel, {cfg.m_points} points on three rotating plates, "
+                       f"dt = {cfg.dt}, backward Euler; trained on steps 2-{train_end}, "
+                       f"steps {train_end + 1}-{train_end + eval_steps} solved in every mode",
+           "tol": "1e-8 * ||R(x_plain)||, the same absolute threshold in every mode",
+           "precond": "Schur block-triangular, 2 velocity steps", "dof": 4 * g.num_nodes,
+           "simulate_s": round(sim_s, 1), "train_ms": round(lw.train_ms, 1), "epochs": epochs,
+           "train_samples": len(ks), "final_train_loss": round(lw.losses[-1], 4) if lw.losses else None}
+    for m in modes:
+        out[m] = {"ms_per_step": round(agg(m, "ms_newton") + agg(m, "ms_guess"), 2),
+                  "ms_guess": round(agg(m, "ms_guess"), 2),
+                  "newton_iters": round(agg(m, "newton"), 2), "krylov_iters": round(agg(m, "krylov"), 1),
+                  "phases_ms": [round(statistics.mean(r[m]["phases_ms"][i] for r in rows), 1) for i in range(3)]}
+        if m != modes[0]:
+            out[m]["max_rel_diff_vs_" + modes[0]] = max(r[m]["rel_diff_vs_" + modes[0]] for r in rows)
+        if m.startswith(("nn", "extrap")):
+            out[m]["guess_used"] = [str(r[m]["used_guess"]) for r in rows]
+    base = out[modes[0]]["ms_per_step"]
+    for m in modes[1:]:
+        out["speedup_" + m + "_vs_" + modes[0]] = round(base / out[m]["ms_per_step"], 3)
+    return out
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5"])
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c5", choices=["c1", "c2", "c5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-newton", action="store_true", help="skip the short Newton-step probe")
+    ap.add_argument("--no-newton", action="store_true", help="skip the Newton-step block")
+    ap.add_argument("--newton-epochs", type=int, default=20)
+    ap.add_argument("--newton-eval-steps", type=int, default=2)
+    ap.add_argument("--newton-probe", action="store_true",
+                    help="also the short 64^3 Newton-step probe with block-Jacobi and Schur modes")
     ap.add_argument("--no-solid", action="store_true", help="skip the solid-block timings")
+    ap.add_argument("--cpu-one-core", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--experiment", default=None,
                     choices=["warmstart", "c5", "netspeed", "c3", "probe", "solid", "solid_steps"],
                     help="run a Newton-step experiment instead of the apply benchmark")
@@ -427,6 +565,8 @@ def main(argv=None):
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 512 MiB device copy (for counter calibration)")
     args = ap.parse_args(argv)
+    if args.cpu_one_core:
+        return cpu_one_core_main(args.workload)
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(how the apply would shard is described in the design notes)", file=sys.stderr)
@@ -455,8 +595,17 @@ def main(argv=None):
 
     ms64, wall64, kern = time_applies(fsi, torch, case64, args.steps, args.warmup, profile=True)
     ms32, wall32, kern32 = time_applies(fsi, torch, case32, args.steps, args.warmup, profile=True)
+    # the point-by-point DLM path (B, kappa, B^T corner sums in the node gather) instead of the
+    # per-cell blocks folded into the cell kernel
+    pw = dict(case64)
+    p0 = case64["prob"]
+    pw["prob"] = fsi.Problem(g, p0.prm, p0.a, p0.tables, p0.kappa, s=p0.s)
+    pw["ws"] = torch.empty(pw["prob"].workspace_bytes(), dtype=torch.uint8, device=dev)
+    ms_pw, _, kern_pw = time_applies(fsi, torch, pw, args.steps, args.warmup, profile=False)
+    del pw
 
-    cold64 = time_cold(torch, case64)
+    resident = 4 * N * 8 * 4 < 256e6
+    cold64 = time_cold(torch, case64) if resident else None
     gdofs64 = 4 * N / (ms64 * 1e-3) / 1e9
     gdofs32 = 4 * N / (ms32 * 1e-3) / 1e9
     cell_ms, launches = kern.get("vms_q1_cells", (0.0, 0))
@@ -493,27 +642,39 @@ def main(argv=None):
             "launches": launches,
             "hbm_algorithmic_GBs": round(hbm_gbs, 1),
             "hbm_frac": round(hbm_gbs / PEAK_HBM_GBS, 4),
-            # the workload's vectors (tens of MB) stay in the 256 MB Infinity Cache between
-            # back-to-back applies; extra.cold_cache_* times applies after a 512 MiB overwrite
-            "infinity_cache_resident": 4 * N * 8 * 4 < 256e6,
+            # vectors that fit the 256 MB Infinity Cache stay there between back-to-back applies
+            # (then extra.cold_cache_* times applies after a 512 MiB overwrite)
+            "infinity_cache_resident": resident,
         },
         "extra": {
             "fp32_gdofs": round(gdofs32, 4), "fp32_ms_per_step": round(ms32, 6),
-            "cold_cache_ms_per_apply_f64": round(cold64, 6),
-            "cold_cache_gdofs_f64": round(4 * N / (cold64 * 1e-3) / 1e9, 4),
             "host_wall_ms_per_step_f64": round(wall64, 6),
             "kernels_f64_ms": {k: round(v[0], 6) for k, v in kern.items()},
             "kernels_f32_ms": {k: round(v[0], 6) for k, v in kern32.items()},
+            # the DLM block applied point by point (B, kappa, B^T) instead of through the per-cell
+            # blocks, which are built once per point set (dlm_gram) and reused by every apply
+            "pointwise_dlm_gdofs_f64": round(4 * N / (ms_pw * 1e-3) / 1e9, 4),
+            "pointwise_dlm_ms_per_step_f64": round(ms_pw, 6),
             "locate_ms": round(case64["locate_ms"], 3),
             "dlm_gram_ms": round(case64["gram_ms"], 3),
+            "dlm_gram_in_applies": round(case64["gram_ms"] / ms64, 3),
             "n_occupied_cells": case64["tab"].n_occ,
             **time_dlm(fsi, torch, case64),
         },
     }
+    if cold64 is not None:
+        out["extra"]["cold_cache_ms_per_apply_f64"] = round(cold64, 6)
+        out["extra"]["cold_cache_gdofs_f64"] = round(4 * N / (cold64 * 1e-3) / 1e9, 4)
+    # free the apply benchmark's buffers before the Newton runs
+    del case32
+    torch.cuda.synchronize()
     if args.workload != "c1" and not args.no_solid:
         out["solid_block"] = time_solid(fsi, torch, cfg, cpu=not args.no_cpu_baseline)
-    if not args.no_newton and args.workload == "c2":
-        out["newton_step"] = newton_step_probe()
+    if not args.no_newton and args.workload in ("c2", "c5"):
+        out["newton_step"] = newton_block("c5" if args.workload == "c5" else "c4",
+                                          epochs=args.newton_epochs, eval_steps=args.newton_eval_steps)
+    if args.newton_probe:
+        out["newton_probe_64cube"] = newton_step_probe()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, case64)
     print(json.dumps(out))
