@@ -174,6 +174,24 @@ int fsi_dlm_BT(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const int32_t *
                void *stream);
 
 /*
+ * fsi_dlm_BT_noalloc - fsi_dlm_BT without a workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops that
+ * forbid hipMalloc): the per-occupied-cell corner sums go to a scratch array
+ * the library holds on each GPU it runs on until the process ends, of
+ * fsi_dlm_BT_noalloc_max_bytes() bytes (32 MiB: up to 174,762 occupied Q1
+ * cells in FP64, 349,525 in FP32).  Same arguments and result as fsi_dlm_BT
+ * (bitwise: the same kernels); n_occ whose corner sums exceed the array ->
+ * FSI_ERR_WORKSPACE before any device work.  It allocates nothing.  Calls that
+ * overlap on one GPU (other streams or threads) share the array and race: keep
+ * them in one stream order.
+ */
+size_t fsi_dlm_BT_noalloc_max_bytes(void);
+int fsi_dlm_BT_noalloc(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const int32_t *perm,
+                       const void *xi, const int32_t *occ_cell, const int32_t *occ_start,
+                       const int32_t *occ_index, int64_t n_occ, const void *lam, const void *kappa,
+                       void *y, void *stream);
+
+/*
  * fsi_dlm_gram - per occupied cell o, the block of B^T diag(kappa) B that
  * couples the cell's own (p+1)^3 nodes:
  *   gram[o][A][C] = sum_{B in cell o} kappa_B N_A(xi_B) N_C(xi_B)

@@ -125,6 +125,9 @@ SIGNATURES = {
                                   P, P, P, P, SZ, P]),
     "fsi_dlm_gram": (ctypes.c_int, [ctypes.POINTER(FsiGrid), ctypes.c_int, I64, P, P, P, I64, P, P,
                                     P]),
+    "fsi_dlm_BT_noalloc_max_bytes": (SZ, []),
+    "fsi_dlm_BT_noalloc": (ctypes.c_int, [ctypes.POINTER(FsiGrid), ctypes.c_int, I64, P, P, P, P, P, I64,
+                                          P, P, P, P]),
     "fsi_jacobian_workspace": (SZ, [ctypes.POINTER(FsiProblem)]),
     "fsi_jacobian_apply": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, P, SZ, P]),
     "fsi_vms_residual": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, P, P, P, P, SZ, P]),

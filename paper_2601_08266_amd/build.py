@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfsi.so")
 SOURCES = ["api.cpp", "profile.cpp", "fgmres.cpp", "newton.cpp", "vms_q1.hip", "vms_q2.hip", "dlm.hip",
-           "bjacobi.hip", "krylov.hip", "nn.hip", "schur.hip", "solid.hip"]
+           "bjacobi.hip", "krylov.hip", "nn.hip", "schur.hip", "solid.hip", "noalloc.hip"]
 HEADERS = ["common.hpp", "kernels.hpp", "dlm.hpp", "profile.hpp", "bjacobi.hpp", "krylov.hpp",
            "fgmres.hpp", "newton.hpp", "nn.hpp", "schur.hpp", "solid.hpp", "stall.hpp"]
 ARCH = "gfx950"
