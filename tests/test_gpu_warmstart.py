@@ -1,5 +1,5 @@
 """What the trained warm-start network gains over the method without it (the learned warm
-start is an addition to the predictor of section 2.4's Newton steps).
+start is an addition to the predictor of section 2.4's Newton steps), and over its own backbone.
 
 A 16^3 rotating-plates channel is advanced 30 backward-Euler steps; the network is trained
 with the library's own forward / backward kernels and Adam on steps 2-20, and steps 21-30
@@ -49,5 +49,18 @@ def test_learned_guess_gains_over_the_plain_guess():
         assert r["nn_mixed"]["res_guess"] < r["nn_mixed"]["res_plain"]
         # ... and the converged state is the same to the accuracy the common tolerance allows
         assert r["nn_mixed"]["rel_diff_vs_plain_mixed"] <= 1e-5
-    # the gain over the method without the network: fewer Krylov iterations than the plain guess
+    # the network's own guess (not the safeguard's fallback) is the one used in most steps
+    used = sum(1 for r in rows if r["nn_mixed"]["used_guess"] is True)
+    assert used >= 0.8 * len(rows), used
+    # fewer Krylov iterations than the plain guess
     assert mean("nn_mixed", "krylov") < mean("plain_mixed", "krylov")
+    # what the network adds over its own backbone, the linear extrapolation it corrects: the
+    # measured result is that it does not pay (Krylov counts within a fraction of an iteration,
+    # wall time including the inference larger); recorded, not hidden
+    nn_k, ex_k = mean("nn_mixed", "krylov"), mean("extrap_mixed", "krylov")
+    nn_ms = mean("nn_mixed", "ms_newton") + mean("nn_mixed", "ms_guess")
+    ex_ms = mean("extrap_mixed", "ms_newton") + mean("extrap_mixed", "ms_guess")
+    print(f"network vs extrapolation: krylov {nn_k:.2f} vs {ex_k:.2f}, ms {nn_ms:.1f} vs {ex_ms:.1f}")
+    if not (nn_k < ex_k and nn_ms < ex_ms):
+        pytest.xfail(f"the learned correction does not beat the extrapolation it corrects: "
+                     f"{nn_k:.2f} vs {ex_k:.2f} Krylov iterations, {nn_ms:.1f} vs {ex_ms:.1f} ms per step")
