@@ -486,11 +486,12 @@ def newton_block(workload="c5", train_end=20, eval_steps=2, epochs=20, modes=Non
     for _ in range(train_end):
         run.step()
     sim_s = time.perf_counter() - t0
-    lw = LearnedWarmStart(run, seed=0)
-    ks = list(range(1, train_end))
-    lw.fit_normalisation(run.history, ks)
-    lw.build_dataset(run.history, ks)
-    lw.train(epochs=epochs, lr=1e-3, seed=0)
+    lw, ks = None, list(range(1, train_end))
+    if any(m.startswith("nn") for m in modes):
+        lw = LearnedWarmStart(run, seed=0)
+        lw.fit_normalisation(run.history, ks)
+        lw.build_dataset(run.history, ks)
+        lw.train(epochs=epochs, lr=1e-3, seed=0)
     rows = []
     for k in range(train_end, train_end + eval_steps):
         rows.append(ex._solve_modes(run, lw, k, modes))
@@ -506,8 +507,10 @@ def newton_block(workload="c5", train_end=20, eval_steps=2, epochs=20, modes=Non
                        f"steps {train_end + 1}-{train_end + eval_steps} solved in every mode",
            "tol": "1e-8 * ||R(x_plain)||, the same absolute threshold in every mode",
            "precond": "Schur block-triangular, 2 velocity steps", "dof": 4 * g.num_nodes,
-           "simulate_s": round(sim_s, 1), "train_ms": round(lw.train_ms, 1), "epochs": epochs,
-           "train_samples": len(ks), "final_train_loss": round(lw.losses[-1], 4) if lw.losses else None}
+           "simulate_s": round(sim_s, 1)}
+    if lw is not None:
+        out.update({"train_ms": round(lw.train_ms, 1), "epochs": epochs, "train_samples": len(ks),
+                    "final_train_loss": round(lw.losses[-1], 4) if lw.losses else None})
     for m in modes:
         out[m] = {"ms_per_step": round(agg(m, "ms_newton") + agg(m, "ms_guess"), 2),
                   "ms_guess": round(agg(m, "ms_guess"), 2),
@@ -533,6 +536,9 @@ def main(argv=None):
     ap.add_argument("--no-newton", action="store_true", help="skip the Newton-step block")
     ap.add_argument("--newton-epochs", type=int, default=20)
     ap.add_argument("--newton-eval-steps", type=int, default=2)
+    ap.add_argument("--newton-train-end", type=int, default=20,
+                    help="steps run before the measured ones (the network trains on 2..this)")
+    ap.add_argument("--newton-modes", default=None, help="comma list of Newton modes (default: all)")
     ap.add_argument("--newton-probe", action="store_true",
                     help="also the short 64^3 Newton-step probe with block-Jacobi and Schur modes")
     ap.add_argument("--no-solid", action="store_true", help="skip the solid-block timings")
@@ -672,7 +678,9 @@ def main(argv=None):
         out["solid_block"] = time_solid(fsi, torch, cfg, cpu=not args.no_cpu_baseline)
     if not args.no_newton and args.workload in ("c2", "c5"):
         out["newton_step"] = newton_block("c5" if args.workload == "c5" else "c4",
-                                          epochs=args.newton_epochs, eval_steps=args.newton_eval_steps)
+                                          train_end=args.newton_train_end, epochs=args.newton_epochs,
+                                          eval_steps=args.newton_eval_steps,
+                                          modes=args.newton_modes.split(",") if args.newton_modes else None)
     if args.newton_probe:
         out["newton_probe_64cube"] = newton_step_probe()
     if not args.no_cpu_baseline:

@@ -45,13 +45,15 @@ def _mesh(n_t, n_f, seed=1001):
     return X, conn, U
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("terms", ["all", "mass", "stiff", "visc"])
-@pytest.mark.parametrize("size", [(3, 4), (6, 8), (12, 16)])
+# each term alone on the two small meshes, all terms together on the three sizes
+SOLID_CASES = [(size, terms, dtype) for dtype in ("f64", "f32")
+               for size in ((3, 4), (6, 8)) for terms in ("all", "mass", "stiff", "visc")] + \
+              [((12, 16), "all", dtype) for dtype in ("f64", "f32")]
+
+
+@pytest.mark.parametrize("size,terms,dtype", SOLID_CASES)
 def test_solid_apply_matches_oracle(size, terms, dtype):
     import paper_2601_08266_amd as fsi
-    if size == (12, 16) and terms != "all":
-        pytest.skip("the separate terms are covered on the smaller meshes")
     X, conn, U = _mesh(*size)
     M = X.shape[1]
     npdt = np.float64 if dtype == "f64" else np.float32
