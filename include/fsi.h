@@ -534,7 +534,11 @@ int fsi_fgmres_solve(const fsi_problem *J64, const fsi_problem *J32, const void 
  *   f, lamg, gD  as in fsi_vms_residual (FP64)
  *   x     double [4][N] in: guess (Dirichlet values imposed), out: solution
  * Stops when ||R||_2 <= opts->tol_abs; each linear solve uses the relative
- * tolerance max(eta, 0.5 tol_abs / ||R||).  stats: HOST out.  SYNCS.
+ * tolerance max(eta', 0.5 tol_abs / ||R||) with eta' = eta for the Picard
+ * operator; for the full tangent eta' = min(eta, sqrt(0.5 tol_abs / ||R||)) in
+ * the first iteration and 0.5 tol_abs / ||R|| after it (with quadratic
+ * convergence two iterations then reach the target).
+ * stats: HOST out.  SYNCS.
  */
 typedef struct {
     int32_t max_newton;       /* Newton iterations cap (e.g. 20) */

@@ -179,7 +179,14 @@ int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, c
         fsi_solve_opts so{};
         so.restart = o.restart;
         so.max_iters = o.max_krylov;
-        so.rtol = std::max(o.eta, 0.5 * o.tol_abs / rn);
+        // forcing: eta, or what the last iteration needs (half the remaining reduction).  With
+        // the full tangent (quadratic convergence) the first iteration solves to at most the
+        // square root of that and the next ones to the final target, so that two iterations
+        // reach it when the quadratic term is small
+        const double last = 0.5 * o.tol_abs / rn;
+        double eta = o.eta;
+        if (o.tangent) eta = it == 0 ? std::min(o.eta, std::sqrt(last)) : last;
+        so.rtol = std::max(eta, last);
         if (so.rtol >= 1.0) so.rtol = 0.5;
         so.inner = o.inner;
         so.inner_reduction = o.inner_reduction;

@@ -417,61 +417,75 @@ __device__ __forceinline__ void q1_tangent_cell(const VmsConst<T> &k, const T cu
 #pragma unroll
         for (int i = 0; i < 8; ++i) mom[f][i] = T(0);
 
+    // the points in x-pairs sharing (y, z): along a pair a field is E + x O (O its x-derivative)
 #pragma unroll 1
-    for (int qi = 0; qi < 8; ++qi) {
-        const QP<T> q = q1_point<T>(qi);
-        const T *lp = lq + Q1_NQV * qi * Q1_NT;
-        const T tau_m = lp[3 * Q1_NT], tau_c = lp[4 * Q1_NT];
-        T U[3], dU[3][3], Ah[3], D[3], Dh[3];
+    for (int pr = 0; pr < 4; ++pr) {
+        const QP<T> q0 = q1_point<T>(2 * pr);
+        T Eu[3], Ou[3], Ed[3], Od[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            U[i] = mval(cu[i], q);
-            dU[i][0] = mdx(cu[i], q);
-            dU[i][1] = mdy(cu[i], q);
-            dU[i][2] = mdz(cu[i], q);
-            Ah[i] = U[i] * k.ih[i];
-            D[i] = mval(cd[i], q);
-            Dh[i] = D[i] * k.ih[i];
+            Eu[i] = cu[i][0] + cu[i][2] * q0.y + cu[i][4] * q0.z + cu[i][6] * q0.yz;
+            Ou[i] = cu[i][1] + cu[i][3] * q0.y + cu[i][5] * q0.z + cu[i][7] * q0.yz;
+            Ed[i] = cd[i][0] + cd[i][2] * q0.y + cd[i][4] * q0.z + cd[i][6] * q0.yz;
+            Od[i] = cd[i][1] + cd[i][3] * q0.y + cd[i][5] * q0.z + cd[i][7] * q0.yz;
         }
-        const T dP[3] = {mdx(cu[3], q), mdy(cu[3], q), mdz(cu[3], q)};
-        const T div = dU[0][0] * k.ih[0] + dU[1][1] * k.ih[1] + dU[2][2] * k.ih[2];
-        T ngd[3] = {T(0), T(0), T(0)};
-        if (k.visc_strong) {
-            const T u1xy = (cu[1][3] + cu[1][7] * q.z) * k.nu_hh[0][1];
-            const T u2xz = (cu[2][5] + cu[2][7] * q.y) * k.nu_hh[0][2];
-            const T u0xy = (cu[0][3] + cu[0][7] * q.z) * k.nu_hh[0][1];
-            const T u2yz = (cu[2][6] + cu[2][7] * q.x) * k.nu_hh[1][2];
-            const T u0xz = (cu[0][5] + cu[0][7] * q.y) * k.nu_hh[0][2];
-            const T u1yz = (cu[1][6] + cu[1][7] * q.x) * k.nu_hh[1][2];
-            ngd[0] = u1xy + u2xz;
-            ngd[1] = u0xy + u2yz;
-            ngd[2] = u0xz + u1yz;
+#pragma unroll
+        for (int ix = 0; ix < 2; ++ix) {
+            const int qi = 2 * pr + ix;
+            const QP<T> q = q1_point<T>(qi);
+            const T *lp = lq + Q1_NQV * qi * Q1_NT;
+            const T tau_m = lp[3 * Q1_NT], tau_c = lp[4 * Q1_NT];
+            T U[3], dU[3][3], Ah[3], D[3], Dh[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                U[i] = Eu[i] + q.x * Ou[i];
+                dU[i][0] = Ou[i];
+                dU[i][1] = mdy(cu[i], q);
+                dU[i][2] = mdz(cu[i], q);
+                Ah[i] = U[i] * k.ih[i];
+                D[i] = Ed[i] + q.x * Od[i];
+                Dh[i] = D[i] * k.ih[i];
+            }
+            const T dP[3] = {mdx(cu[3], q), mdy(cu[3], q), mdz(cu[3], q)};
+            const T div = dU[0][0] * k.ih[0] + dU[1][1] * k.ih[1] + dU[2][2] * k.ih[2];
+            T ngd[3] = {T(0), T(0), T(0)};
+            if (k.visc_strong) {
+                const T u1xy = (cu[1][3] + cu[1][7] * q.z) * k.nu_hh[0][1];
+                const T u2xz = (cu[2][5] + cu[2][7] * q.y) * k.nu_hh[0][2];
+                const T u0xy = (cu[0][3] + cu[0][7] * q.z) * k.nu_hh[0][1];
+                const T u2yz = (cu[2][6] + cu[2][7] * q.x) * k.nu_hh[1][2];
+                const T u0xz = (cu[0][5] + cu[0][7] * q.y) * k.nu_hh[0][2];
+                const T u1yz = (cu[1][6] + cu[1][7] * q.x) * k.nu_hh[1][2];
+                ngd[0] = u1xy + u2xz;
+                ngd[1] = u0xy + u2yz;
+                ngd[2] = u0xz + u1yz;
+            }
+            // rho_i and c_i = dv_j d_j u_i (physical derivatives: reference ones times 1/h)
+            T rho[3], c[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const T conv = Ah[0] * dU[i][0] + Ah[1] * dU[i][1] + Ah[2] * dU[i][2];
+                rho[i] = ((k.c_m * U[i] + conv - lp[i * Q1_NT]) + dP[i] * k.ih[i]) - ngd[i];
+                c[i] = Dh[0] * dU[i][0] + Dh[1] * dU[i][1] + Dh[2] * dU[i][2];
+            }
+            const T B = k.K1 + (Ah[0] * Ah[0] + Ah[1] * Ah[1] + Ah[2] * Ah[2]);
+            const T sigma = -(tau_m / B) * (Ah[0] * Dh[0] + Ah[1] * Dh[1] + Ah[2] * Dh[2]);
+            const T dtc_div = -(tau_c / tau_m) * sigma * div;
+            T e[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) e[i] = tau_m * c[i] + sigma * rho[i];
+            // test-side fluxes multiplied by 1/h_k (reference derivatives of the test functions)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const T tr = tau_m * rho[i];
+                T G[3];
+#pragma unroll
+                for (int kk = 0; kk < 3; ++kk) G[kk] = Ah[kk] * e[i] + Dh[kk] * tr;
+                G[i] += dtc_div * k.ih[i];
+                moments(mom[i], c[i], G[0], G[1], G[2], q);
+            }
+            moments(mom[3], T(0), e[0] * k.ih[0], e[1] * k.ih[1], e[2] * k.ih[2], q);
         }
-        // rho_i and c_i = dv_j d_j u_i (physical derivatives: reference ones times 1/h)
-        T rho[3], c[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const T conv = Ah[0] * dU[i][0] + Ah[1] * dU[i][1] + Ah[2] * dU[i][2];
-            rho[i] = ((k.c_m * U[i] + conv - lp[i * Q1_NT]) + dP[i] * k.ih[i]) - ngd[i];
-            c[i] = Dh[0] * dU[i][0] + Dh[1] * dU[i][1] + Dh[2] * dU[i][2];
-        }
-        const T B = k.K1 + (Ah[0] * Ah[0] + Ah[1] * Ah[1] + Ah[2] * Ah[2]);
-        const T sigma = -(tau_m / B) * (Ah[0] * Dh[0] + Ah[1] * Dh[1] + Ah[2] * Dh[2]);
-        const T dtc_div = -(tau_c / tau_m) * sigma * div;
-        T e[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) e[i] = tau_m * c[i] + sigma * rho[i];
-        // test-side fluxes multiplied by 1/h_k (reference derivatives of the test functions)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const T tr = tau_m * rho[i];
-            T G[3];
-#pragma unroll
-            for (int kk = 0; kk < 3; ++kk) G[kk] = Ah[kk] * e[i] + Dh[kk] * tr;
-            G[i] += dtc_div * k.ih[i];
-            moments(mom[i], c[i], G[0], G[1], G[2], q);
-        }
-        moments(mom[3], T(0), e[0] * k.ih[0], e[1] * k.ih[1], e[2] * k.ih[2], q);
     }
     const T W = k.detJ * T(0.125);
 #pragma unroll

@@ -3,10 +3,12 @@
 //
 // Design
 //  * One workgroup = a brick of 4x4x4 cells (9x9x9 nodes), processed in 8
-//    rounds of a 2x2x2 group of cells.  In a round, lane l < 216 owns
-//    (cell l/27, index j = l%27) where j is read as a node (a,b,c), an
-//    intermediate (q,b,c) / (q,q',c) or a quadrature point (q,q',q'')
-//    depending on the pass.
+//    rounds of a 2x2x2 group of cells.  In a round, each half-wavefront (32
+//    lanes) holds one cell: lane j < 27 of it owns index j, read as a node
+//    (a,b,c), an intermediate (q,b,c) / (q,q',c) or a quadrature point
+//    (q,q',q'') depending on the pass.  A cell's passes exchange values only
+//    among its own lanes (per-cell LDS slices, one wavefront), so they are
+//    ordered by wavefront-level fences instead of workgroup barriers.
 //  * Interpolation is sum-factorised through LDS: nodal values -> x-line
 //    values (N, N', N'') -> xy-plane values -> quadrature-point values,
 //    value/gradient/second derivatives as each field needs them (velocity:
@@ -15,9 +17,11 @@
 //  * The test side is the transposed contraction: per quadrature point the
 //    4 weighted flux components (value, d/dx, d/dy, d/dz) of each output
 //    field go through z, y, x passes back to the 27 nodes.
-//  * Nodes of the 8 cells of a round are added into the brick's LDS node
-//    accumulator one cell at a time (ordered, deterministic), brick faces
-//    are finished by the shared node-gather kernel.
+//  * The 8 cells of a round park their nodal outputs in LDS; after one
+//    workgroup barrier each of the round's 5x5x5 nodes adds the outputs of
+//    the cells holding it in a fixed cell order to the brick's LDS node
+//    accumulator (deterministic); brick faces are finished by the shared
+//    node-gather kernel.
 #include "kernels.hpp"
 #include "profile.hpp"
 
@@ -25,9 +29,17 @@ namespace fsi {
 
 namespace {
 
-constexpr int CPR = 8;           // cells per round
-constexpr int LANES = CPR * 27;  // active lanes per round
+constexpr int CPR = 8;           // cells per round (one per 32-lane half-wavefront)
 constexpr int BN = 2 * Q2_BX + 1;
+
+// Orders one wavefront's LDS accesses: the stores before it are seen by the loads after it
+// (lanes of one wavefront; no workgroup barrier).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // 3-point Gauss-Legendre on [0,1]
 constexpr double G3_0 = 0.11270166537925831148;
@@ -77,7 +89,7 @@ __device__ __forceinline__ void interp(const Tab<T> &tb, T (*nod)[27], T (*bx)[3
 {
     const int i0 = j % 3, i1 = (j / 3) % 3, i2 = j / 9;
     if (act) nod[lc][j] = v;
-    __syncthreads();
+    wave_sync();
     // pass x: (q, b, c) <- nodes (a, b, c)
     if (act) {
         T s0 = T(0), s1 = T(0), s2 = T(0);
@@ -92,7 +104,7 @@ __device__ __forceinline__ void interp(const Tab<T> &tb, T (*nod)[27], T (*bx)[3
         if (NDER >= 1) bx[lc][1][j] = s1;
         if (NDER >= 2) bx[lc][2][j] = s2;
     }
-    __syncthreads();
+    wave_sync();
     // pass y: (q, q', c) <- (q, b, c); derivative orders (x, y):
     // 0:(0,0) 1:(1,0) 2:(0,1) 3:(2,0) 4:(1,1) 5:(0,2)
     if (act) {
@@ -126,7 +138,7 @@ __device__ __forceinline__ void interp(const Tab<T> &tb, T (*nod)[27], T (*bx)[3
             by[lc][5][j] = r[5];
         }
     }
-    __syncthreads();
+    wave_sync();
     // pass z: (q, q', q'') <- (q, q', c)
 #pragma unroll
     for (int k = 0; k < 10; ++k) out[k] = T(0);
@@ -152,7 +164,7 @@ __device__ __forceinline__ void interp(const Tab<T> &tb, T (*nod)[27], T (*bx)[3
             }
         }
     }
-    __syncthreads();
+    wave_sync();
 }
 
 // Transposed contraction of one output field: this lane holds the weighted flux
@@ -170,7 +182,7 @@ __device__ __forceinline__ T project(const Tab<T> &tb, T (*fl)[4][27], T (*bx)[3
         fl[lc][2][j] = g1;
         fl[lc][3][j] = g2;
     }
-    __syncthreads();
+    wave_sync();
     // z^T: (q, q', c) <- points (q, q', q'')
     if (act) {
         T p0 = T(0), p1 = T(0), p2 = T(0);
@@ -186,7 +198,7 @@ __device__ __forceinline__ T project(const Tab<T> &tb, T (*fl)[4][27], T (*bx)[3
         bx[lc][1][j] = p1;
         bx[lc][2][j] = p2;
     }
-    __syncthreads();
+    wave_sync();
     // y^T: (q, b, c) <- (q, q', c)
     if (act) {
         T r0 = T(0), r1 = T(0);
@@ -200,7 +212,7 @@ __device__ __forceinline__ T project(const Tab<T> &tb, T (*fl)[4][27], T (*bx)[3
         by[lc][0][j] = r0;
         by[lc][1][j] = r1;
     }
-    __syncthreads();
+    wave_sync();
     // x^T: node (a, b, c) <- (q, b, c)
     T y = T(0);
     if (act) {
@@ -210,7 +222,7 @@ __device__ __forceinline__ T project(const Tab<T> &tb, T (*fl)[4][27], T (*bx)[3
             y += tb.N[i0][qx] * by[lc][0][src] + tb.D[i0][qx] * by[lc][1][src];
         }
     }
-    __syncthreads();
+    wave_sync();
     return y;
 }
 
@@ -229,14 +241,15 @@ __global__ __launch_bounds__(256) void vms_q2_cells(Geo g, VmsConst<T> k, const 
     __shared__ T bx[CPR][3][27];
     __shared__ T by[CPR][6][27];
     __shared__ T fl[CPR][4][27];
+    __shared__ T outs[CPR][4][27];
     __shared__ T smin_s[CPR];
     __shared__ Tab<T> tb;
 
     const int t = threadIdx.x;
     const int64_t bid = blockIdx.x;
     const int bxi = (int)(bid % nbx), byi = (int)((bid / nbx) % nby), bzi = (int)(bid / ((int64_t)nbx * nby));
-    const int lc = t / 27, j = t % 27;
-    const bool lane_on = t < LANES;
+    const int lc = t / 32, j = t % 32;
+    const bool lane_on = j < 27;
     fill_tab(tb, t);
     for (int i = t; i < 4 * Q2_NL; i += 256) acc[i] = T(0);
     __syncthreads();
@@ -276,13 +289,13 @@ __global__ __launch_bounds__(256) void vms_q2_cells(Geo g, VmsConst<T> k, const 
         T S = T(1);
         if (k.has_s) {
             if (act) nod[lc][j] = v[7];
-            __syncthreads();
+            wave_sync();
             if (act && j == 0) {
                 T m = nod[lc][0];
                 for (int i = 1; i < 27; ++i) m = nod[lc][i] < m ? nod[lc][i] : m;
                 smin_s[lc] = m;
             }
-            __syncthreads();
+            wave_sync();
             interp<T, 0>(tb, nod, bx, by, lc, j, act, v[7], qs);
             if (act) S = qs[0] < smin_s[lc] ? smin_s[lc] : qs[0];
         }
@@ -361,15 +374,40 @@ __global__ __launch_bounds__(256) void vms_q2_cells(Geo g, VmsConst<T> k, const 
                 out[2] += r2;
             }
         }
-        // ordered accumulation of the round's 8 cells into the brick's nodes
-        const int l = (2 * cxl + na) + BN * ((2 * cyl + nb) + BN * (2 * czl + nc));
-        for (int pc = 0; pc < CPR; ++pc) {
-            if (act && lc == pc) {
+        // ordered accumulation of the round's 8 cells into the brick's nodes: each node of the
+        // round's 5x5x5 group adds the outputs of the cells holding it in cell order
+        if (lane_on) {
 #pragma unroll
-                for (int f = 0; f < 4; ++f) acc[f * Q2_NL + l] += out[f];
-            }
-            __syncthreads();
+            for (int f = 0; f < 4; ++f) outs[lc][f][j] = act ? out[f] : T(0);
         }
+        __syncthreads();
+        if (t < 125) {
+            const int gx = t % 5, gy = (t / 5) % 5, gz = t / 25;
+            T sum[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int ck = 0; ck < 2; ++ck) {
+                const int lz = gz - 2 * ck;
+                if (lz < 0 || lz > 2) continue;
+#pragma unroll
+                for (int cj = 0; cj < 2; ++cj) {
+                    const int ly = gy - 2 * cj;
+                    if (ly < 0 || ly > 2) continue;
+#pragma unroll
+                    for (int ci = 0; ci < 2; ++ci) {
+                        const int lx = gx - 2 * ci;
+                        if (lx < 0 || lx > 2) continue;
+                        const int cell = ci + 2 * cj + 4 * ck;
+                        const int jn = lx + 3 * ly + 9 * lz;
+#pragma unroll
+                        for (int f = 0; f < 4; ++f) sum[f] += outs[cell][f][jn];
+                    }
+                }
+            }
+            const int l = (4 * (r & 1) + gx) + BN * ((4 * ((r >> 1) & 1) + gy) + BN * (4 * (r >> 2) + gz));
+#pragma unroll
+            for (int f = 0; f < 4; ++f) acc[f * Q2_NL + l] += sum[f];
+        }
+        __syncthreads();
     }
     for (int l = t; l < Q2_NL; l += 256) {
         const int lx = l % BN, ly = (l / BN) % BN, lz = l / (BN * BN);
