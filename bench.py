@@ -80,6 +80,25 @@ def q1_cell_flops(has_s=True, visc_strong=True):
     return table + loop + 32 + 48
 
 
+def q2_cell_flops(has_s=True):
+    """Flops vms_q2_cells spends on one Q2 cell in apply mode (fma = 2, add/mul/sqrt/div = 1),
+    counted from the kernel's arithmetic; a cell is 27 lanes, lane j one node / one Gauss point.
+    Per lane: the sum-factorised interpolation of u, v, w with second derivatives (x pass 9,
+    y pass 18, z pass 30 fma: 114 each), of p with its gradient (6 + 9 + 12 fma: 54), of the 3
+    advection components and s (values only, 3 + 3 + 3 fma: 18 each); the pointwise terms
+    (physical derivatives and Hessians 21 + lap 6, grad p 3, tau 10, div 2, the three momentum
+    residuals times tau_m 45, tau_c div - p 2, the 12 test-side fluxes 39, Gauss weight and
+    scaling 31: 159); the four transposed contractions (12 + 9 + 6 fma: 54 each); the ordered
+    node accumulation (4).  Plus the cell's smallest nodal s (26 compares)."""
+    per_lane = 3 * 114 + 54 + (4 if has_s else 3) * 18 + 159 + 4 * 54 + 4
+    return 27 * per_lane + (26 if has_s else 0)
+
+
+def q2_dlm_cell_flops():
+    """Extra flops of an occupied Q2 cell: its 27x27 block on 3 velocity components."""
+    return 2 * 27 * 27 * 3
+
+
 def dlm_cell_flops():
     """Extra flops of an occupied cell: its 8x8 block on 3 velocity components (192 fma)
     and the velocity back to nodal form (3 x 12)."""
@@ -237,6 +256,31 @@ def build_problem(cfg, dtype, dev):
                 a_np=a, x_np=x, X_np=X, kappa_np=kappa)
 
 
+def time_q2_apply(fsi, torch, steps=20, warmup=5):
+    """The Q2 Jacobian apply of the 96^3 Q2-Q2 grid with 500k plate points (the mixed-precision
+    solve configuration's operator), FP64 and FP32: GDOF/s and the cell kernel's rate against
+    the FP64 vector peak, from the library's per-kernel events."""
+    import fsi_workloads as W
+
+    cfg = W.CONFIGS["c3"]
+    g = cfg.grid
+    out = {"workload": f"{cfg.name}: {g.n[0]}^3 Q2-Q2 VMS+DLM Jacobian apply, {cfg.m_points} points",
+           "dof": 4 * g.num_nodes, "cells": g.num_cells}
+    for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        case = build_problem(cfg, dt, torch.device("cuda:0"))
+        ms, _, kern = time_applies(fsi, torch, case, steps, warmup, profile=True,
+                                   kernels=("vms_q2_cells", "vms_gather"))
+        cell_ms = kern["vms_q2_cells"][0]
+        flops = q2_cell_flops() * g.num_cells + q2_dlm_cell_flops() * case["tab"].n_occ
+        tf = flops / (cell_ms * 1e-3) / 1e12 if cell_ms > 0 else 0.0
+        out[name] = {"ms_per_apply": round(ms, 4), "gdofs": round(4 * case["N"] / (ms * 1e-3) / 1e9, 3),
+                     "kernels_ms": {k: round(v[0], 4) for k, v in kern.items()},
+                     "cell_TFLOPs": round(tf, 2), "cell_frac_of_78.6": round(tf / PEAK_FP64_VALU_TFLOPS, 4)}
+        del case
+    out["flops_per_cell"] = q2_cell_flops()
+    return out
+
+
 def time_dlm(fsi, torch, case, reps=50):
     """Standalone B u and y += B^T (kappa lam) (fsi_dlm_B / fsi_dlm_BT, FP64) on the workload's
     point set, timed with events on the launch stream over `reps` calls each."""
@@ -267,7 +311,7 @@ def time_dlm(fsi, torch, case, reps=50):
     return out
 
 
-def time_applies(fsi, torch, case, steps, warmup, profile):
+def time_applies(fsi, torch, case, steps, warmup, profile, kernels=("vms_q1_cells", "vms_gather")):
     """Time `steps` back-to-back applies (no per-kernel events in this pass); then, if asked,
     the same number again with the library's per-kernel hipEvents for the kernel breakdown."""
     prob, x, y, ws = case["prob"], case["x"], case["y"], case["ws"]
@@ -291,7 +335,7 @@ def time_applies(fsi, torch, case, steps, warmup, profile):
         for _ in range(steps):
             apply()
         torch.cuda.synchronize()
-        for name in ("vms_q1_cells", "vms_gather"):
+        for name in kernels:
             tot, n = fsi.profile_read(name)
             kern[name] = (tot / n if n else 0.0, n)
         fsi.profile_enable(False)
@@ -542,6 +586,7 @@ def main(argv=None):
     ap.add_argument("--newton-probe", action="store_true",
                     help="also the short 64^3 Newton-step probe with block-Jacobi and Schur modes")
     ap.add_argument("--no-solid", action="store_true", help="skip the solid-block timings")
+    ap.add_argument("--no-q2", action="store_true", help="skip the 96^3 Q2 apply row")
     ap.add_argument("--cpu-one-core", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--experiment", default=None,
                     choices=["warmstart", "c5", "netspeed", "c3", "probe", "solid", "solid_steps"],
@@ -676,6 +721,8 @@ def main(argv=None):
     torch.cuda.synchronize()
     if args.workload != "c1" and not args.no_solid:
         out["solid_block"] = time_solid(fsi, torch, cfg, cpu=not args.no_cpu_baseline)
+    if not args.no_q2:
+        out["q2_apply"] = time_q2_apply(fsi, torch)
     if not args.no_newton and args.workload in ("c2", "c5"):
         out["newton_step"] = newton_block("c5" if args.workload == "c5" else "c4",
                                           train_end=args.newton_train_end, epochs=args.newton_epochs,

@@ -357,7 +357,7 @@ int fsi_solid_residual(const fsi_solid *solid, const double *U, const double *V,
  * (alpha_f - gamma) dt V_n, cA = alpha_m / (gamma dt alpha_f), A_base = cA V_n -
  * (1 - alpha_m / gamma) Vdot_n.  A body force f per unit mass on the solid (the
  * (rho_s - rho_f)(A - f) of eq. solid_weak_form) enters as A_base + f.
- * problem: FP64, Q1, problem->solid NULL, its points (located at the step's
+ * problem: FP64, Q1 or Q2, problem->solid NULL, its points (located at the step's
  * configuration) the solid's nodes.
  *   U_base, A_base  double [3][M];  f, gD  double [3][N]
  *   x         double [4][N];  R  double [4][N] out
@@ -371,7 +371,7 @@ int fsi_solid_step_residual(const fsi_problem *problem, const fsi_solid *solid, 
                             void *stream);
 
 /*
- * fsi_vms_residual - nonlinear residual of one implicit step (Q1 grids), the
+ * fsi_vms_residual - nonlinear residual of one implicit step (Q1 and Q2), the
  * right-hand side of the Newton corrections of section 2.4:
  *   R = A(a = u, tau(u)) x - F(f) + [B^T diag(kappa) (B u - g); 0]
  * with A the operator of fsi_vms_apply evaluated with the velocity itself as

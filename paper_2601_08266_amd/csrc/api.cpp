@@ -174,7 +174,8 @@ static int vms_residual_t(const Geo &g, const fsi_vms_params &prm, const T *s, c
     const bool use_gram = dlm != nullptr && dlm->n_occ > 0 && dlm->gram != nullptr;
     const T *gram = use_gram ? reinterpret_cast<const T *>(dlm->gram) : nullptr;
     const int32_t *gidx = use_gram ? dlm->occ_index : nullptr;
-    int rc = launch_q1_cells<T>(g, k, x, f, s, mask, gram, gidx, part, bl, st, true);
+    int rc = g.p == 1 ? launch_q1_cells<T>(g, k, x, f, s, mask, gram, gidx, part, bl, st, true)
+                      : launch_q2_cells<T>(g, k, x, f, s, mask, gram, gidx, part, bl, st, true);
     if (rc) return rc;
     GatherOpts<T> o;
     o.sub3 = lamg;
@@ -183,7 +184,8 @@ static int vms_residual_t(const Geo &g, const fsi_vms_params &prm, const T *s, c
         set_error("residual with a Dirichlet mask needs the Dirichlet values gD");
         return FSI_ERR_ARG;
     }
-    return launch_gather<T, 1, Q1_BX, Q1_BY, Q1_BZ>(g, part, bl, x, mask, R, o, st);
+    if (g.p == 1) return launch_gather<T, 1, Q1_BX, Q1_BY, Q1_BZ>(g, part, bl, x, mask, R, o, st);
+    return launch_gather<T, 2, Q2_BX, Q2_BY, Q2_BZ>(g, part, bl, x, mask, R, o, st);
 }
 
 int launch_vms_residual(const Geo &g, const fsi_vms_params &prm, fsi_dtype dt, const void *s,
@@ -581,14 +583,17 @@ int fsi::solid_step_residual(const Geo &g, const fsi_problem &P, const SolidStep
                                     Rs, nullptr, csum, st);
         if (rc) return rc;
     }
-    rc = launch_q1_cells<double>(g, k, (const double *)x, f, (const double *)P.s, P.dir_mask, nullptr, nullptr,
-                                 part, bl, st, true);
+    rc = g.p == 1 ? launch_q1_cells<double>(g, k, (const double *)x, f, (const double *)P.s, P.dir_mask, nullptr,
+                                            nullptr, part, bl, st, true)
+                  : launch_q2_cells<double>(g, k, (const double *)x, f, (const double *)P.s, P.dir_mask, nullptr,
+                                            nullptr, part, bl, st, true);
     if (rc) return rc;
     GatherOpts<double> o;
     o.csum = solid_on ? csum : nullptr;
     o.occ_index = solid_on ? P.occ_index : nullptr;
     o.gD = gD;
-    return launch_gather<double, 1, Q1_BX, Q1_BY, Q1_BZ>(g, part, bl, x, P.dir_mask, R, o, st);
+    if (g.p == 1) return launch_gather<double, 1, Q1_BX, Q1_BY, Q1_BZ>(g, part, bl, x, P.dir_mask, R, o, st);
+    return launch_gather<double, 2, Q2_BX, Q2_BY, Q2_BZ>(g, part, bl, x, P.dir_mask, R, o, st);
 }
 
 static int check_solid_step(const fsi_problem *p, const fsi_solid *S, const double *Ub, const double *Ab,
@@ -606,10 +611,6 @@ static int check_solid_step(const fsi_problem *p, const fsi_solid *S, const doub
     FSI_CHECK_ARG(p->m == 0 || (Ub && Ab && U && V && p->cell && p->xi), "solid state arrays must be non-NULL");
     FSI_CHECK_ARG(U != Ub && U != Ab && V != Ub && V != Ab && U != V,
                   "U, V must be distinct from U_base, A_base and each other");
-    if (p->grid.order != 1) {
-        set_error("the residual kernel is implemented for Q1 grids");
-        return FSI_ERR_UNSUPPORTED;
-    }
     return FSI_OK;
 }
 
@@ -660,10 +661,6 @@ FSI_API int fsi_vms_residual(const fsi_problem *p, const void *f, const void *la
     rc = check_params(&p->prm);
     if (rc) return rc;
     FSI_CHECK_ARG(dtype_ok(p->dtype), "bad dtype");
-    if (p->grid.order != 1) {
-        set_error("the residual kernel is implemented for Q1 grids");
-        return FSI_ERR_UNSUPPORTED;
-    }
     FSI_CHECK_ARG(f && x && R && x != R, "f, x, R must be non-NULL and x != R");
     FSI_CHECK_ARG(p->dir_mask == nullptr || gD != nullptr, "gD required with a Dirichlet mask");
     if (p->n_occ > 0 && p->dlm_gram == nullptr) {
@@ -913,8 +910,8 @@ static int check_newton(const fsi_problem *P64, const fsi_problem *P32, const fs
         rc = sc_plan(make_geo(P64->grid), sp);
         if (rc) return rc;
     }
-    if (P64->grid.order != 1) {
-        set_error("Newton steps are implemented for Q1 grids");
+    if (P64->grid.order != 1 && o->tangent) {
+        set_error("the full Newton tangent is implemented for Q1 grids");
         return FSI_ERR_UNSUPPORTED;
     }
     if (P64->solid != nullptr || (P32 != nullptr && P32->solid != nullptr)) {

@@ -112,12 +112,12 @@ int launch_q1_tangent(const Geo &g, const VmsConst<T> &k, const T *x, const T *f
 template <typename T>
 int launch_q2_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, const T *s,
                     const uint32_t *mask, const T *gram, const int32_t *occ_index, T *part,
-                    const BrickLayout &bl, hipStream_t st);
+                    const BrickLayout &bl, hipStream_t st, bool resid = false);
 template <typename T, int P, int BX, int BY, int BZ>
 int launch_gather(const Geo &g, const T *part, const BrickLayout &bl, const T *x,
                   const uint32_t *mask, T *y, const GatherOpts<T> &o, hipStream_t st);
 
-// Nonlinear residual of one implicit step (Q1):
+// Nonlinear residual of one implicit step (Q1 or Q2):
 //   R = A(a = u) x - F(f) + B^T kappa B u - lamg,   Dirichlet rows R = u - gD
 int launch_vms_residual(const Geo &g, const fsi_vms_params &prm, fsi_dtype dt, const void *s,
                         const uint32_t *mask, const void *gD, const void *x, const void *f,

@@ -226,8 +226,12 @@ __device__ __forceinline__ T project(const Tab<T> &tb, T (*fl)[4][27], T (*bx)[3
     return y;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void vms_q2_cells(Geo g, VmsConst<T> k, const T *__restrict__ x,
+// RESID = false: the linear apply with advection field a (x Dirichlet-masked); RESID = true:
+// the nonlinear residual of a time step, advection by the velocity itself (a = u), `a` holds
+// the source f = c_m u_old + body force, whose Galerkin/SUPG/PSPG weighting is subtracted
+// (x unmasked: the gather sets the Dirichlet rows to u - g_D).
+template <typename T, bool RESID>
+__global__ __launch_bounds__(256, 3) void vms_q2_cells(Geo g, VmsConst<T> k, const T *__restrict__ x,
                                                     const T *__restrict__ a,
                                                     const T *__restrict__ s,
                                                     const uint32_t *__restrict__ mask,
@@ -240,8 +244,7 @@ __global__ __launch_bounds__(256) void vms_q2_cells(Geo g, VmsConst<T> k, const 
     __shared__ T nodu[CPR][3][27];
     __shared__ T bx[CPR][3][27];
     __shared__ T by[CPR][6][27];
-    __shared__ T fl[CPR][4][27];
-    __shared__ T outs[CPR][4][27];
+    __shared__ T fl[CPR][4][27];   // the projections' fluxes, then the round's nodal outputs
     __shared__ T smin_s[CPR];
     __shared__ Tab<T> tb;
 
@@ -256,26 +259,44 @@ __global__ __launch_bounds__(256) void vms_q2_cells(Geo g, VmsConst<T> k, const 
 
     const int64_t N = g.N;
     const int na = j % 3, nb = (j / 3) % 3, nc = j / 9;   // this lane's node in its cell
+    // this lane's node values of round r (x with the Dirichlet mask applied later, a, s), loaded
+    // one round ahead so their latency hides behind the previous round's arithmetic
+    auto load_round = [&](int r, T v[8]) {
+        const int cxl = 2 * (r & 1) + (lc & 1), cyl = 2 * ((r >> 1) & 1) + ((lc >> 1) & 1),
+                  czl = 2 * (r >> 2) + (lc >> 2);
+        const int cx = bxi * Q2_BX + cxl, cy = byi * Q2_BY + cyl, cz = bzi * Q2_BZ + czl;
+#pragma unroll
+        for (int f = 0; f < 7; ++f) v[f] = T(0);
+        v[7] = T(1);
+        if (lane_on && cx < g.n[0] && cy < g.n[1] && cz < g.n[2]) {
+            const int64_t node = (int64_t)(2 * cx + na) +
+                                 (int64_t)g.nn[0] * ((2 * cy + nb) + (int64_t)g.nn[1] * (2 * cz + nc));
+#pragma unroll
+            for (int f = 0; f < 4; ++f) v[f] = x[f * N + node];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) v[4 + f] = a[f * N + node];
+            if (k.has_s) v[7] = s[node];
+        }
+    };
+    T vnext[8];
+    load_round(0, vnext);
     for (int r = 0; r < 8; ++r) {
         const int cxl = 2 * (r & 1) + (lc & 1), cyl = 2 * ((r >> 1) & 1) + ((lc >> 1) & 1),
                   czl = 2 * (r >> 2) + (lc >> 2);
         const int cx = bxi * Q2_BX + cxl, cy = byi * Q2_BY + cyl, cz = bzi * Q2_BZ + czl;
         const bool act = lane_on && cx < g.n[0] && cy < g.n[1] && cz < g.n[2];
-        // this lane's node values
-        T v[8] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(1)};
+        T v[8];
+#pragma unroll
+        for (int f = 0; f < 8; ++f) v[f] = vnext[f];
+        if (r + 1 < 8) load_round(r + 1, vnext);
         if (act) {
             const int64_t node = (int64_t)(2 * cx + na) +
                                  (int64_t)g.nn[0] * ((2 * cy + nb) + (int64_t)g.nn[1] * (2 * cz + nc));
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
-                T u = x[f * N + node];
-                if (mask_bit(mask, f * N + node)) u = T(0);
-                v[f] = u;
-                v[4 + f] = a[f * N + node];
-                nodu[lc][f][j] = u;
+                if (!RESID && mask_bit(mask, f * N + node)) v[f] = T(0);
+                nodu[lc][f][j] = v[f];
             }
-            v[3] = x[3 * N + node];
-            if (k.has_s) v[7] = s[node];
         }
         // quadrature-point values
         T qu[3][10], qp[10], qa[3][10], qs[10];
@@ -320,7 +341,9 @@ __global__ __launch_bounds__(256) void vms_q2_cells(Geo g, VmsConst<T> k, const 
             }
             const T P = qp[0];
             const T dP[3] = {qp[1] * ih[0], qp[2] * ih[1], qp[3] * ih[2]};
-            const T Aq[3] = {qa[0][0], qa[1][0], qa[2][0]};
+            // advection: the field a, or (residual) the velocity itself with the source f
+            const T Aq[3] = {RESID ? U[0] : qa[0][0], RESID ? U[1] : qa[1][0], RESID ? U[2] : qa[2][0]};
+            const T Fs[3] = {RESID ? qa[0][0] : T(0), RESID ? qa[1][0] : T(0), RESID ? qa[2][0] : T(0)};
             const T tbk = S * (k.K1 + Aq[0] * Aq[0] * k.ih2[0] + Aq[1] * Aq[1] * k.ih2[1] +
                                Aq[2] * Aq[2] * k.ih2[2]);
             const T sq = sqrt(tbk);
@@ -330,7 +353,8 @@ __global__ __launch_bounds__(256) void vms_q2_cells(Geo g, VmsConst<T> k, const 
             T tr[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const T gi = k.c_m * U[i] + (Aq[0] * dU[i][0] + Aq[1] * dU[i][1] + Aq[2] * dU[i][2]);
+                T gi = k.c_m * U[i] + (Aq[0] * dU[i][0] + Aq[1] * dU[i][1] + Aq[2] * dU[i][2]);
+                if constexpr (RESID) gi -= Fs[i];
                 F0[i] = gi;
                 T visc = T(0);
                 if (k.visc_strong) visc = lap[i] + (hes[0][i][0] + hes[1][i][1] + hes[2][i][2]);
@@ -376,9 +400,10 @@ __global__ __launch_bounds__(256) void vms_q2_cells(Geo g, VmsConst<T> k, const 
         }
         // ordered accumulation of the round's 8 cells into the brick's nodes: each node of the
         // round's 5x5x5 group adds the outputs of the cells holding it in cell order
+        // (the last projection ended with this wavefront's fence, so its cell's slice of fl is free)
         if (lane_on) {
 #pragma unroll
-            for (int f = 0; f < 4; ++f) outs[lc][f][j] = act ? out[f] : T(0);
+            for (int f = 0; f < 4; ++f) fl[lc][f][j] = act ? out[f] : T(0);
         }
         __syncthreads();
         if (t < 125) {
@@ -399,7 +424,7 @@ __global__ __launch_bounds__(256) void vms_q2_cells(Geo g, VmsConst<T> k, const 
                         const int cell = ci + 2 * cj + 4 * ck;
                         const int jn = lx + 3 * ly + 9 * lz;
 #pragma unroll
-                        for (int f = 0; f < 4; ++f) sum[f] += outs[cell][f][jn];
+                        for (int f = 0; f < 4; ++f) sum[f] += fl[cell][f][jn];
                     }
                 }
             }
@@ -427,11 +452,15 @@ __global__ __launch_bounds__(256) void vms_q2_cells(Geo g, VmsConst<T> k, const 
 template <typename T>
 int launch_q2_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, const T *s,
                     const uint32_t *mask, const T *gram, const int32_t *occ_index, T *part,
-                    const BrickLayout &bl, hipStream_t st)
+                    const BrickLayout &bl, hipStream_t st, bool resid)
 {
-    ProfileScope prof("vms_q2_cells", st);
-    hipLaunchKernelGGL(vms_q2_cells<T>, dim3((unsigned)bl.nb), dim3(256), 0, st, g, k, x, a, s, mask,
-                       gram, occ_index, part, bl.nbx, bl.nby);
+    ProfileScope prof(resid ? "vms_q2_residual" : "vms_q2_cells", st);
+    if (resid)
+        hipLaunchKernelGGL((vms_q2_cells<T, true>), dim3((unsigned)bl.nb), dim3(256), 0, st, g, k, x, a, s, mask,
+                           gram, occ_index, part, bl.nbx, bl.nby);
+    else
+        hipLaunchKernelGGL((vms_q2_cells<T, false>), dim3((unsigned)bl.nb), dim3(256), 0, st, g, k, x, a, s, mask,
+                           gram, occ_index, part, bl.nbx, bl.nby);
     FSI_LAUNCH_CHECK();
     return FSI_OK;
 }
@@ -439,9 +468,9 @@ int launch_q2_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, 
 template int launch_q2_cells<double>(const Geo &, const VmsConst<double> &, const double *,
                                      const double *, const double *, const uint32_t *,
                                      const double *, const int32_t *, double *,
-                                     const BrickLayout &, hipStream_t);
+                                     const BrickLayout &, hipStream_t, bool);
 template int launch_q2_cells<float>(const Geo &, const VmsConst<float> &, const float *,
                                     const float *, const float *, const uint32_t *, const float *,
-                                    const int32_t *, float *, const BrickLayout &, hipStream_t);
+                                    const int32_t *, float *, const BrickLayout &, hipStream_t, bool);
 
 }  // namespace fsi

@@ -161,8 +161,8 @@ def _step_case(case):
     (several bricks with partial ones in every direction, random points), or 64^3 with the
     rotating plates (200k points)."""
     cfg = W.CONFIGS["c2" if case == "c2" else "c1"]
-    if case == "ragged":
-        g = W.Grid((11, 9, 6), 1)
+    if case in ("ragged", "q2"):
+        g = W.Grid((11, 9, 6), 1) if case == "ragged" else W.Grid((5, 4, 3), 2)
         rng = np.random.default_rng(21)
         X = rng.uniform(0.15, 0.85, (3, 2500))
         kappa = rng.uniform(10.0, 200.0, 2500)
@@ -202,11 +202,11 @@ def _residual_ref(g, P, x, u_old, g_pts, mask, gD, c_m, rows=None):
     return ref
 
 
-@pytest.mark.parametrize("case", ["c1", "ragged", "c2"])
+@pytest.mark.parametrize("case", ["c1", "ragged", "q2", "c2"])
 def test_residual_matches_oracle(case):
-    """The nonlinear step residual (FP64) on the 8^3 sphere case and a ragged multi-brick grid
-    (whole vectors), and at 64^3 with 200k points (sampled rows, brick faces and the domain
-    boundary included), per field."""
+    """The nonlinear step residual (FP64) on the 8^3 sphere case, a ragged multi-brick Q1 grid and
+    a ragged Q2 grid (whole vectors), and at 64^3 with 200k points (sampled rows, brick faces and
+    the domain boundary included), per field."""
     import torch
     import paper_2601_08266_amd as fsi
     print(f"residual {case}", flush=True)
@@ -342,3 +342,47 @@ def test_newton_full_tangent_c1_matches_dense_newton(precond):
         assert np.linalg.norm(xs - x_ref.ravel()) <= 1e-6 * np.linalg.norm(x_ref)
         its[tangent] = st.newton_iters
     assert its["full"] <= its["picard"]
+
+
+@pytest.mark.parametrize("inner,precond", [("f64", "bjacobi"), ("f32", "schur_diag")])
+def test_newton_q2_matches_dense_newton(inner, precond):
+    """One implicit step on a Q2-Q2 grid (3x3x3 cells, 343 nodes, channel boundary conditions,
+    random points): the library's Newton (Picard operator) against the oracle's Newton with dense
+    LU, both to the same absolute residual."""
+    import torch
+    import paper_2601_08266_amd as fsi
+    cfg = W.CONFIGS["c1"]
+    g = W.Grid((3, 3, 3), 2)
+    N = g.num_nodes
+    rng = np.random.default_rng(31)
+    X = rng.uniform(0.2, 0.8, (3, 300))
+    kappa = rng.uniform(10.0, 100.0, 300)
+    g_pts = 0.1 * rng.standard_normal((3, 300))
+    Xn, _, _ = W.node_coords(g)
+    u_old = 0.3 * W.advection_field(g, cfg.seed_fields)
+    mask = W.channel_dirichlet_mask(g)
+    gD = np.zeros((3, N))
+    gD[0] = np.where(Xn == 0.0, 0.5, 0.0)
+    gD[:, ~mask[0]] = 0.0
+    x0 = np.concatenate([u_old, np.zeros((1, N))])
+    x0[:3][mask] = gD[mask]
+    P = build(cfg, u_old, grid=g, X=X, kappa=kappa)
+    kappa = P["kappa"]
+    R0 = onewton.residual(g, P["prm_o"], x0, u_old, P["cell"], P["xi"], kappa, g_pts, s=P["s"], mask=mask, gD=gD)
+    tol = 1e-8 * np.linalg.norm(R0)
+    x_ref, info = onewton.solve_step(g, P["prm_o"], x0, u_old, P["cell"], P["xi"], kappa, g_pts, s=P["s"],
+                                     mask=mask, gD=gD, tol_abs=tol, linear="dense")
+    assert info["converged"]
+    lamg = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
+    fsi.dlm_BT(g, P["J64"].tables, _t(g_pts), lamg, kappa=_t(kappa))
+    x = _t(x0)
+    tdt = torch.float64 if inner == "f64" else torch.float32
+    opts = fsi.newton_opts(tol_abs=tol, inner=tdt, precond=precond)
+    rc, st = fsi.newton_solve(P["J64"], _t(cfg.c_m * u_old), x, opts, P32=P["J32"] if inner == "f32" else None,
+                              lamg=lamg, gD=_t(gD))
+    xs = x.cpu().numpy()
+    R = onewton.residual(g, P["prm_o"], xs, u_old, P["cell"], P["xi"], kappa, g_pts, s=P["s"], mask=mask, gD=gD)
+    print(f"newton q2 {inner} {precond}: {st.newton_iters} Newton / {st.krylov_iters} Krylov, oracle "
+          f"{len(info['history']) - 1} Newton; oracle ||R|| {np.linalg.norm(R):.3e} (tol {tol:.3e})")
+    assert np.linalg.norm(R) <= tol * 1.01
+    assert np.linalg.norm(xs - x_ref.ravel()) <= 1e-6 * np.linalg.norm(x_ref)
