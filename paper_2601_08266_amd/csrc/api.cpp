@@ -104,8 +104,9 @@ size_t vms_workspace_bytes(const Geo &g, fsi_dtype dt)
 }
 
 // tstate / tsrc (Q1 only): apply the full Newton tangent at the state tstate = (u, p) with
-// source tsrc instead (a must then be tstate's velocity): the Picard cells, then the tangent
-// correction added to the same brick partials, then the node gather.
+// source tsrc instead (a must then be tstate's velocity): the Picard cells and the tangent
+// correction (one merged pass in FP32, two passes into the same brick partials in FP64), then
+// the node gather.
 template <typename T>
 static int vms_apply_t(const Geo &g, const fsi_vms_params &prm, const T *a, const T *s,
                        const uint32_t *mask, const T *x, T *y, const DlmView *dlm, void *ws,
@@ -120,16 +121,23 @@ static int vms_apply_t(const Geo &g, const fsi_vms_params &prm, const T *a, cons
     const bool use_gram = dlm != nullptr && dlm->n_occ > 0 && dlm->gram != nullptr && dlm->solid == nullptr;
     const T *gram = use_gram ? reinterpret_cast<const T *>(dlm->gram) : nullptr;
     const int32_t *gidx = use_gram ? dlm->occ_index : nullptr;
-    int rc;
-    if (g.p == 1)
-        rc = launch_q1_cells<T>(g, k, x, a, s, mask, gram, gidx, part, bl, st, false);
-    else
-        rc = launch_q2_cells<T>(g, k, x, a, s, mask, gram, gidx, part, bl, st);
-    if (rc) return rc;
-    if (tstate != nullptr) {
-        rc = launch_q1_tangent<T>(g, k, tstate, tsrc, s, mask, x, part, bl, st);
-        if (rc) return rc;
+    int rc = FSI_OK;
+    if constexpr (sizeof(T) == 4) {
+        // FP32: the Picard operator and the correction in one pass of cells (162 VGPRs, 3 waves
+        // per SIMD); in FP64 the merged cell would need 388 registers (1 wave), so there the
+        // correction is a second pass added to the Picard partials
+        if (tstate != nullptr)
+            rc = launch_q1_tangent_fused<T>(g, k, tstate, tsrc, s, mask, gram, gidx, x, part, bl, st);
     }
+    if (tstate == nullptr || sizeof(T) == 8) {
+        if (g.p == 1)
+            rc = launch_q1_cells<T>(g, k, x, a, s, mask, gram, gidx, part, bl, st, false);
+        else
+            rc = launch_q2_cells<T>(g, k, x, a, s, mask, gram, gidx, part, bl, st);
+        if (rc) return rc;
+        if (tstate != nullptr) rc = launch_q1_tangent<T>(g, k, tstate, tsrc, s, mask, x, part, bl, st);
+    }
+    if (rc) return rc;
     const fsi_dtype dt = sizeof(T) == 8 ? FSI_F64 : FSI_F32;
     if (dlm != nullptr && dlm->n_occ > 0 && dlm->solid != nullptr) {
         // solid block: u_s = B x (Dirichlet-masked), l_s = K_s u_s at the solid nodes, then the

@@ -109,6 +109,12 @@ int launch_q1_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, 
 template <typename T>
 int launch_q1_tangent(const Geo &g, const VmsConst<T> &k, const T *x, const T *f, const T *s,
                       const uint32_t *mask, const T *dv, T *part, const BrickLayout &bl, hipStream_t st);
+// The whole full Newton tangent (Q1) in one pass of cells: state x = (u, p), source f,
+// direction v = (dv, dp) (Dirichlet entries of dv ignored), per-cell DLM blocks gram (or NULL).
+template <typename T>
+int launch_q1_tangent_fused(const Geo &g, const VmsConst<T> &k, const T *x, const T *f, const T *s,
+                            const uint32_t *mask, const T *gram, const int32_t *occ_index, const T *v,
+                            T *part, const BrickLayout &bl, hipStream_t st);
 template <typename T>
 int launch_q2_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, const T *s,
                     const uint32_t *mask, const T *gram, const int32_t *occ_index, T *part,

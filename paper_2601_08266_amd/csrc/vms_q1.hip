@@ -498,6 +498,130 @@ __device__ __forceinline__ void q1_tangent_cell(const VmsConst<T> &k, const T cu
     }
 }
 
+// The whole full-Newton-tangent contribution of one cell in one pass: the Picard operator with
+// a = u applied to the direction (dv, dp) plus the correction of q1_tangent_cell, whose test
+// fluxes are merged so that each field's moments are accumulated once per point.  cu: state
+// (u, p), cd: direction (dv masked, dp), both in monomial form; lq: the residual's point table
+// (f, tau_m, tau_c); dlm: the cell's DLM block (applied to the nodal direction) or nullptr.
+template <typename T>
+__device__ __forceinline__ void q1_fused_tangent_cell(const VmsConst<T> &k, const T cu[4][8], T cd[4][8],
+                                                      const T *lq, const T *__restrict__ dlm, T out[4][8])
+{
+    T mom[4][8];
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) mom[f][i] = T(0);
+
+#pragma unroll 1
+    for (int pr = 0; pr < 4; ++pr) {
+        const QP<T> q0 = q1_point<T>(2 * pr);
+        T Es[4], Os[4], Ed[4], Od[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            Es[f] = cu[f][0] + cu[f][2] * q0.y + cu[f][4] * q0.z + cu[f][6] * q0.yz;
+            Os[f] = cu[f][1] + cu[f][3] * q0.y + cu[f][5] * q0.z + cu[f][7] * q0.yz;
+            Ed[f] = cd[f][0] + cd[f][2] * q0.y + cd[f][4] * q0.z + cd[f][6] * q0.yz;
+            Od[f] = cd[f][1] + cd[f][3] * q0.y + cd[f][5] * q0.z + cd[f][7] * q0.yz;
+        }
+#pragma unroll
+        for (int ix = 0; ix < 2; ++ix) {
+            const int qi = 2 * pr + ix;
+            const QP<T> q = q1_point<T>(qi);
+            const T *lp = lq + Q1_NQV * qi * Q1_NT;
+            const T tau_m = lp[3 * Q1_NT], tau_c = lp[4 * Q1_NT];
+            // state (s) and direction (d): values and reference derivatives
+            T Us[3], dUs[3][3], Ah[3], D[3], dD[3][3], Dh[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                Us[i] = Es[i] + q.x * Os[i];
+                dUs[i][0] = Os[i];
+                dUs[i][1] = mdy(cu[i], q);
+                dUs[i][2] = mdz(cu[i], q);
+                Ah[i] = Us[i] * k.ih[i];
+                D[i] = Ed[i] + q.x * Od[i];
+                dD[i][0] = Od[i];
+                dD[i][1] = mdy(cd[i], q);
+                dD[i][2] = mdz(cd[i], q);
+                Dh[i] = D[i] * k.ih[i];
+            }
+            const T dPs[3] = {Os[3], mdy(cu[3], q), mdz(cu[3], q)};
+            const T Pd = Ed[3] + q.x * Od[3];
+            const T dPd[3] = {Od[3], mdy(cd[3], q), mdz(cd[3], q)};
+            const T divs = dUs[0][0] * k.ih[0] + dUs[1][1] * k.ih[1] + dUs[2][2] * k.ih[2];
+            const T divd = dD[0][0] * k.ih[0] + dD[1][1] * k.ih[1] + dD[2][2] * k.ih[2];
+            // nu grad(div) of the state and of the direction (mixed second derivatives only)
+            T ngs[3] = {T(0), T(0), T(0)}, ngdd[3] = {T(0), T(0), T(0)};
+            if (k.visc_strong) {
+                ngs[0] = (cu[1][3] + cu[1][7] * q.z) * k.nu_hh[0][1] + (cu[2][5] + cu[2][7] * q.y) * k.nu_hh[0][2];
+                ngs[1] = (cu[0][3] + cu[0][7] * q.z) * k.nu_hh[0][1] + (cu[2][6] + cu[2][7] * q.x) * k.nu_hh[1][2];
+                ngs[2] = (cu[0][5] + cu[0][7] * q.y) * k.nu_hh[0][2] + (cu[1][6] + cu[1][7] * q.x) * k.nu_hh[1][2];
+                ngdd[0] = (cd[1][3] + cd[1][7] * q.z) * k.nu_hh[0][1] + (cd[2][5] + cd[2][7] * q.y) * k.nu_hh[0][2];
+                ngdd[1] = (cd[0][3] + cd[0][7] * q.z) * k.nu_hh[0][1] + (cd[2][6] + cd[2][7] * q.x) * k.nu_hh[1][2];
+                ngdd[2] = (cd[0][5] + cd[0][7] * q.y) * k.nu_hh[0][2] + (cd[1][6] + cd[1][7] * q.x) * k.nu_hh[1][2];
+            }
+            // Picard part on the direction: gm = c_m dv + (u.grad) dv, tr = tau_m r_m(dv, dp)
+            // correction: rho = r_m(u, p) - f, c = (dv.grad)u, sigma = d tau_m, e = tau_m c + sigma rho
+            T gm[3], tr[3], rho[3], c[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                gm[i] = k.c_m * D[i] + (Ah[0] * dD[i][0] + Ah[1] * dD[i][1] + Ah[2] * dD[i][2]);
+                tr[i] = tau_m * ((gm[i] + dPd[i] * k.ih[i]) - ngdd[i]);
+                const T conv = Ah[0] * dUs[i][0] + Ah[1] * dUs[i][1] + Ah[2] * dUs[i][2];
+                rho[i] = ((k.c_m * Us[i] + conv - lp[i * Q1_NT]) + dPs[i] * k.ih[i]) - ngs[i];
+                c[i] = Dh[0] * dUs[i][0] + Dh[1] * dUs[i][1] + Dh[2] * dUs[i][2];
+            }
+            const T B = k.K1 + (Ah[0] * Ah[0] + Ah[1] * Ah[1] + Ah[2] * Ah[2]);
+            const T sigma = -(tau_m / B) * (Ah[0] * Dh[0] + Ah[1] * Dh[1] + Ah[2] * Dh[2]);
+            const T dtc_div = -(tau_c / tau_m) * sigma * divs;
+            const T diag = tau_c * divd - Pd;
+            T e[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) e[i] = tau_m * c[i] + sigma * rho[i];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const T te = tr[i] + e[i], trho = tau_m * rho[i];
+                T G[3];
+#pragma unroll
+                for (int kk = 0; kk < 3; ++kk) {
+                    T fl;
+                    if (kk == i)
+                        fl = T(2) * k.nu_hh[i][i] * dD[i][i] + (diag + dtc_div) * k.ih[i];
+                    else
+                        fl = k.nu_hh[kk][kk] * dD[i][kk] + k.nu_hh[kk][i] * dD[kk][i];
+                    G[kk] = fl + Ah[kk] * te + Dh[kk] * trho;
+                }
+                moments(mom[i], gm[i] + c[i], G[0], G[1], G[2], q);
+            }
+            moments(mom[3], divd, (tr[0] + e[0]) * k.ih[0], (tr[1] + e[1]) * k.ih[1], (tr[2] + e[2]) * k.ih[2], q);
+        }
+    }
+    const T W = k.detJ * T(0.125);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) mom[f][i] *= W;
+        from_moments(mom[f]);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) out[f][i] = mom[f][i];
+    }
+    if (dlm != nullptr) {
+        // DLM block on the nodal (Dirichlet-masked) direction
+#pragma unroll
+        for (int f = 0; f < 3; ++f) from_monomial(cd[f]);
+#pragma unroll
+        for (int A = 0; A < 8; ++A) {
+#pragma unroll
+            for (int C = 0; C < 8; ++C) {
+                const T gAC = dlm[A * 8 + C];
+                out[0][A] += gAC * cd[0][C];
+                out[1][A] += gAC * cd[1][C];
+                out[2][A] += gAC * cd[2][C];
+            }
+        }
+    }
+}
+
 // Brick handled by block bid.  Blocks are dealt to the 8 XCDs round-robin; each XCD is
 // given a contiguous range of bricks (x fastest), so bricks that share face nodes (and
 // the cache lines holding them) mostly run under the same L2.
@@ -509,7 +633,9 @@ __device__ __forceinline__ int64_t xcd_brick(int64_t bid, int64_t nb)
 
 // MODE 0: linear apply (advection field a); 1: step residual (a = u, source f in `a`);
 // 2: full-tangent correction: x = state (u, p), `a` = source f, dv = velocity direction; the
-// result is added to the brick partials that the Picard apply (MODE 0 with a = u) wrote.
+// result is added to the brick partials that the Picard apply (MODE 0 with a = u) wrote;
+// 3: the whole full-Newton tangent in one pass: x = state, `a` = source f, dv = direction
+// (velocity and pressure), gram = the per-cell DLM blocks; the partials are overwritten.
 template <typename T, int MODE>
 __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, const T *__restrict__ x,
                                                     const T *__restrict__ a,
@@ -521,9 +647,10 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
                                                     const T *__restrict__ dv)
 {
     constexpr bool RESID = MODE != 0;
+    constexpr bool DIR = MODE >= 2;   // a direction next to the state
     // LDS, one region used three ways: the brick's nodal fields (staged with coalesced
     // loads), then the lanes' Gauss-point tables, then the lanes' nodal outputs.
-    constexpr int NF = MODE == 2 ? 11 : 8;   // x (4), a or f (3), s (, dv (3))
+    constexpr int NF = MODE == 3 ? 12 : (MODE == 2 ? 11 : 8);   // x (4), a or f (3), s (, dv (3 or 4))
     constexpr int NJ = (Q1_NL + Q1_NT - 1) / Q1_NT;   // staged nodes per lane
     static_assert(8 * Q1_NQV >= 32 && 8 * Q1_NQV * Q1_NT >= NF * Q1_NL, "LDS too small");
     __shared__ T lds[8 * Q1_NQV * Q1_NT];
@@ -571,7 +698,7 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
         }
         if (MODE != 1 && mask != nullptr) {
             // Dirichlet columns: the apply's x, the tangent's direction
-            constexpr int F0 = MODE == 2 ? 8 : 0;
+            constexpr int F0 = DIR ? 8 : 0;
 #pragma unroll
             for (int f = 0; f < 3; ++f)
 #pragma unroll
@@ -588,7 +715,7 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
 
     T cu[4][8];
     T ca[3][8], cs[8];
-    T cd[MODE == 2 ? 3 : 1][8];
+    T cd[MODE == 3 ? 4 : (MODE == 2 ? 3 : 1)][8];
     if (valid) {
 #pragma unroll
         for (int A = 0; A < 8; ++A) {
@@ -598,9 +725,9 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
 #pragma unroll
             for (int d = 0; d < 3; ++d) ca[d][A] = lds[(4 + d) * Q1_NL + l];
             cs[A] = k.has_s ? lds[7 * Q1_NL + l] : T(1);
-            if constexpr (MODE == 2) {
+            if constexpr (DIR) {
 #pragma unroll
-                for (int d = 0; d < 3; ++d) cd[d][A] = lds[(8 + d) * Q1_NL + l];
+                for (int d = 0; d < NF - 8; ++d) cd[d][A] = lds[(8 + d) * Q1_NL + l];
             }
         }
     }
@@ -608,16 +735,19 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
     T out[4][8];
     if (valid) {
         q1_point_table<T, RESID>(k, cu, ca, cs, lds + t);
-        if constexpr (MODE == 2) {
+        const T *dlm = nullptr;
+        if (gram != nullptr) {
+            const int32_t ko = occ_index[cx + (int64_t)g.n[0] * (cy + (int64_t)g.n[1] * cz)];
+            if (ko >= 0) dlm = gram + (int64_t)ko * 64;
+        }
+        if constexpr (DIR) {
 #pragma unroll
-            for (int d = 0; d < 3; ++d) to_monomial(cd[d]);
-            q1_tangent_cell<T>(k, cu, cd, lds + t, out);
+            for (int d = 0; d < NF - 8; ++d) to_monomial(cd[d]);
+            if constexpr (MODE == 3)
+                q1_fused_tangent_cell<T>(k, cu, cd, lds + t, dlm, out);
+            else
+                q1_tangent_cell<T>(k, cu, cd, lds + t, out);
         } else {
-            const T *dlm = nullptr;
-            if (gram != nullptr) {
-                const int32_t ko = occ_index[cx + (int64_t)g.n[0] * (cy + (int64_t)g.n[1] * cz)];
-                if (ko >= 0) dlm = gram + (int64_t)ko * 64;
-            }
             q1_cell<T, RESID>(k, cu, lds + t, dlm, out);
         }
     }
@@ -802,6 +932,25 @@ int launch_q1_tangent(const Geo &g, const VmsConst<T> &k, const T *x, const T *f
     FSI_LAUNCH_CHECK();
     return FSI_OK;
 }
+// The whole full Newton tangent at state x = (u, p), source f, on direction v = (dv, dp), with
+// the per-cell DLM blocks (gram, or NULL): one pass of cells writing the brick partials.
+template <typename T>
+int launch_q1_tangent_fused(const Geo &g, const VmsConst<T> &k, const T *x, const T *f, const T *s,
+                            const uint32_t *mask, const T *gram, const int32_t *occ_index, const T *v,
+                            T *part, const BrickLayout &bl, hipStream_t st)
+{
+    FSI_CHECK_ARG((int64_t)g.nn[0] * g.nn[1] * (Q1_BZ + 1) * (int64_t)sizeof(T) < ((int64_t)1 << 31),
+                  "Q1 grid planes too large (%d x %d nodes)", g.nn[0], g.nn[1]);
+    ProfileScope prof("vms_q1_tangent_fused", st);
+    hipLaunchKernelGGL((vms_q1_cells<T, 3>), dim3((unsigned)bl.nb), dim3(Q1_NT), 0, st, g, k, x, f, s, mask,
+                       gram, occ_index, part, bl.nbx, bl.nby, v);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+template int launch_q1_tangent_fused<float>(const Geo &, const VmsConst<float> &, const float *,
+                                            const float *, const float *, const uint32_t *, const float *,
+                                            const int32_t *, const float *, float *, const BrickLayout &,
+                                            hipStream_t);
 template int launch_q1_tangent<double>(const Geo &, const VmsConst<double> &, const double *, const double *,
                                        const double *, const uint32_t *, const double *, double *,
                                        const BrickLayout &, hipStream_t);

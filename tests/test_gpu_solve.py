@@ -267,8 +267,8 @@ def test_newton_c1_matches_dense_newton(inner):
 @pytest.mark.parametrize("case", ["c1", "ragged", "c2"])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_tangent_apply_matches_oracle(case, dt):
-    """Full Newton tangent (fsi_tangent_apply: Picard cells + tangent-correction cells + node
-    gather) against the oracle's analytic element tangents (pinned by central differences of the
+    """Full Newton tangent (fsi_tangent_apply: in FP64 the Picard cells + the tangent-correction
+    cells, in FP32 one merged pass of cells; then the node gather) against the oracle's analytic element tangents (pinned by central differences of the
     residual), with s, Dirichlet rows/columns and the DLM block; FP32 on FP32-rounded inputs.
     Whole vectors on the 8^3 and ragged grids, sampled rows per field at 64^3 + 200k points."""
     import torch
