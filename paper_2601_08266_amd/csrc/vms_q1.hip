@@ -104,14 +104,16 @@ __device__ __forceinline__ T mdz(const T c[8], const QP<T> &q)
 template <typename T>
 __device__ __forceinline__ void moments(T m[8], T F0, T G0, T G1, T G2, const QP<T> &q)
 {
+    // each product is fused into the running moment (20 operations per point and field
+    // instead of 28 with separately formed sums)
     m[0] += F0;
-    m[1] += F0 * q.x + G0;
-    m[2] += F0 * q.y + G1;
-    m[3] += F0 * q.xy + G0 * q.y + G1 * q.x;
-    m[4] += F0 * q.z + G2;
-    m[5] += F0 * q.xz + G0 * q.z + G2 * q.x;
-    m[6] += F0 * q.yz + G1 * q.z + G2 * q.y;
-    m[7] += F0 * q.xyz + G0 * q.yz + G1 * q.xz + G2 * q.xy;
+    m[1] = fma(F0, q.x, m[1]) + G0;
+    m[2] = fma(F0, q.y, m[2]) + G1;
+    m[3] = fma(G1, q.x, fma(G0, q.y, fma(F0, q.xy, m[3])));
+    m[4] = fma(F0, q.z, m[4]) + G2;
+    m[5] = fma(G2, q.x, fma(G0, q.z, fma(F0, q.xz, m[5])));
+    m[6] = fma(G2, q.y, fma(G1, q.z, fma(F0, q.yz, m[6])));
+    m[7] = fma(G2, q.xy, fma(G1, q.xz, fma(G0, q.yz, fma(F0, q.xyz, m[7]))));
 }
 
 // Buffer loads: one resource per field and block (base = the brick's first node), the
