@@ -634,6 +634,8 @@ int fsi_newton_solid_solve(const fsi_problem *P64, const fsi_problem *P32, const
  *                    Y_f32 receive the result (either may be NULL).
  *                    With W from fsi_conv3d_flip_transpose (Wd[tap][i][o] =
  *                    W[26-tap][o][i]) the same call is the data gradient.
+ *                    X, W, Y_f32 16-byte aligned, Y_bf16 and gate 8-byte
+ *                    aligned, V cin 2 < 2^31 bytes (else FSI_ERR_ARG).
  * fsi_conv3d_wgrad   dW[tap][o][i] = sum_v dY[v][o] X[v+off][i] (float),
  *                    db[o] = sum_v dY[v][o] (float, or db = NULL).  Split over
  *                    voxel ranges summed in a fixed order: deterministic.

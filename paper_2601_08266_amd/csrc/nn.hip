@@ -7,15 +7,13 @@
 // i + nx (j + ny k)); weights [27][Cout][Cin] with tap = dx + 3 (dy + 3 dz)
 // reading the neighbour at offset (dx - 1, dy - 1, dz - 1); zero padding.
 //
-// Forward / data gradient (implicit GEMM): a block owns 128 voxels x 64 output
-// channels, each wave 32 voxels x 64 channels (8 accumulator tiles; 5 waves per
-// SIMD, where 64-voxel waves fit 3 and left the second round of blocks at 65^3
-// mostly empty).  The K loop runs over the 27 taps x Cin/32 chunks; per step the
-// block stages the chunk's 64 x 32 weights in LDS (double buffered, one barrier
-// per step), and each lane loads 8 consecutive input channels of its 2 (shifted)
-// voxels, so a weight fragment feeds 2 MFMAs and an input fragment 4.  The data gradient is
-// the same kernel on flipped, transposed weights, with the ReLU mask of the
-// previous layer applied in the epilogue.
+// Forward / data gradient (implicit GEMM): a block owns a brick of 8 x 8 x 4 voxels
+// x 64 output channels, each wave a 64-voxel z-slice of it x 64 channels (16
+// accumulator tiles).  Per 32-channel input chunk the brick's halo is staged in
+// LDS once and the 27 taps read shifted input fragments from it; each weight
+// fragment (loaded from memory two taps ahead) feeds 4 MFMAs and each input
+// fragment 4.  The data gradient is the same kernel on flipped, transposed
+// weights, with the ReLU mask of the previous layer applied in the epilogue.
 // Weight gradient (split K): block (voxel range, tap) stages 64 voxels of dY
 // and of the shifted input, transposed, in LDS and accumulates the 64x64 tap
 // block with 16 MFMA tiles; ranges are summed in a fixed order afterwards
@@ -52,117 +50,191 @@ __device__ __forceinline__ bf8 zero8()
 }
 
 // ---------------------------------------------------------------- forward / dgrad
-constexpr int CF_MT = 2;                 // 16-voxel M tiles per wave
-constexpr int CF_VB = 64 * CF_MT;        // voxels per block (4 waves)
-constexpr int CF_WS = 40;                // LDS row stride (bf16) of a staged weight chunk: 32 + 8 pad
+// A block owns a brick of 8 x 8 x 4 voxels and 64 output channels; wave w the z-slice w of
+// the brick, as four 16-voxel M tiles (8 x 2 voxel patches: rows y = 2m, 2m + 1).  Per
+// 32-channel input chunk the block stages the brick's halo (10 x 10 x 6 voxels, zero outside
+// the grid) in LDS once; the 27 taps then read their shifted A fragments from it at offsets
+// fixed at compile time, so the tap loop has no address or bounds arithmetic.  The weight
+// fragments (B) come straight from memory (a layer's weights stay in L2), two taps ahead.
+constexpr int CF_BX = 8, CF_BY = 8, CF_BZ = 4;
+constexpr int CF_HX = CF_BX + 2, CF_HY = CF_BY + 2, CF_HZ = CF_BZ + 2;
+constexpr int CF_HV = CF_HX * CF_HY * CF_HZ;   // halo voxels (600)
+constexpr int CF_RS = 32;                      // LDS row (bf16) of a halo voxel or a weight row: 64 bytes,
+                                               // its four 16-byte parts XOR-swizzled (cf_hslot, cf_wslot)
+constexpr int CF_PIECES = CF_HV * 4;           // 16-byte pieces of a staged chunk
+constexpr int CF_PPT = (CF_PIECES + 255) / 256;
 
-// 16 zero bytes that out-of-range fragment loads read instead (a pointer choice before the
-// load, so the loads can stay in flight: no select on the loaded value)
-__device__ __attribute__((aligned(16))) uint16_t cf_zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+// LDS bank spreading: the 16-byte part `part` of halo voxel row (halo x = hx) and of weight row
+// i sits in slot part ^ g.  With these g the fragment reads (16 lanes: an 8 x 2 voxel patch at any
+// shift, or 16 consecutive weight rows) and the staging writes touch every bank once, both with
+// 32 banks per 8 lanes and with 64 banks per 16 lanes.
+__device__ __forceinline__ int cf_hslot(int part, int hx) { return part ^ ((hx >> 1) & 3); }
+__device__ __forceinline__ int cf_wslot(int part, int i) { return part ^ (((i >> 1) ^ (i >> 2)) & 3); }
 
-__global__ __launch_bounds__(256) void conv_fwd_k(int nx, int ny, int nz, int cin, int cout,
-                                                  const uint16_t *__restrict__ X,
-                                                  const uint16_t *__restrict__ W,
-                                                  const float *__restrict__ bias, int relu,
-                                                  const uint16_t *__restrict__ gate,
-                                                  uint16_t *__restrict__ Ybf,
-                                                  float *__restrict__ Yf)
+// Buffer loads of 16 bytes: the resource (base and byte size) in SGPRs, the lane's offset in
+// a VGPR, the uniform part in an SGPR; an offset at or past the size reads zeros.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t cf_rsrc(const void *base, int64_t bytes)
 {
-    // weights of one (tap, 32-channel chunk) for the block's 64 output channels, double buffered
-    __shared__ __attribute__((aligned(16))) uint16_t sW[2][64 * CF_WS];
-    const int64_t V = (int64_t)nx * ny * nz;
+    const int32_t n = bytes > (int64_t)0x7fffffff ? 0x7fffffff : (int32_t)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, n, 0x00020000);
+}
+__device__ __forceinline__ bf8 cf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(bf8, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+constexpr uint32_t CF_OOB = 0x80000000u;   // a lane offset past every resource: the load reads zeros
+
+// Block b -> brick: blocks are dealt to the 8 XCDs round-robin, each XCD gets a contiguous
+// range of bricks (x fastest), so bricks sharing halo voxels mostly run under one L2.
+__device__ __forceinline__ int64_t cf_brick(int64_t b, int64_t nb)
+{
+    const int64_t q = nb / 8, r = nb % 8, xcd = b % 8, idx = b / 8;
+    return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+// X: [V][cin] bf16 with V * cin * 2 < 2^31 bytes (checked by the launcher); W: [27][cout][cin].
+__global__ __launch_bounds__(256, 3) void conv_fwd_k(int nx, int ny, int nz, int cin, int cout,
+                                                     const uint16_t *__restrict__ X,
+                                                     const uint16_t *__restrict__ W,
+                                                     const float *__restrict__ bias, int relu,
+                                                     const uint16_t *__restrict__ gate,
+                                                     uint16_t *__restrict__ Ybf,
+                                                     float *__restrict__ Yf)
+{
+    // the brick's input halo for one 32-channel chunk, and three taps' 64 x 32 weights (buffer
+    // dx for the taps of x shift dx)
+    __shared__ __attribute__((aligned(16))) uint16_t sH[CF_HV * CF_RS];
+    __shared__ __attribute__((aligned(16))) uint16_t sW[3][64 * CF_RS];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int64_t vw = (int64_t)blockIdx.x * CF_VB + 16 * CF_MT * w;   // first voxel of this wave
+    const int nbx = (nx + CF_BX - 1) / CF_BX, nby = (ny + CF_BY - 1) / CF_BY;
+    const int64_t brick = cf_brick(blockIdx.x, gridDim.x);
+    const int bx = (int)(brick % nbx), by = (int)((brick / nbx) % nby), bz = (int)(brick / ((int64_t)nbx * nby));
     const int co0 = blockIdx.y * 64;
     const int ntiles = (cout - co0) >= 64 ? 4 : (cout - co0) / 16;
-    const int kq = 8 * (lane >> 4);
-    int ax[CF_MT], ay[CF_MT], az[CF_MT];
-    bool vin[CF_MT];
+    const int64_t V = (int64_t)nx * ny * nz;
+    const __amdgpu_buffer_rsrc_t rX = cf_rsrc(X, V * cin * 2);
+    const __amdgpu_buffer_rsrc_t rW = cf_rsrc(W, (int64_t)27 * cout * cin * 2);
+    // this lane's A row: voxel (lane & 7, (lane >> 3) & 1) of an 8 x 2 patch, 8 channels
+    // 8 (lane >> 4) .. + 7 (part lane >> 4), whose slot depends on the tap's x shift dx through the halo x
+    const int arow = ((lane & 7) + CF_HX * ((lane >> 3) & 1) + CF_HX * CF_HY * w) * CF_RS;
+    int abase[3];
 #pragma unroll
-    for (int m = 0; m < CF_MT; ++m) {
-        const int64_t va = vw + 16 * m + (lane & 15);
-        vin[m] = va < V;
-        ax[m] = (int)(va % nx);
-        ay[m] = (int)((va / nx) % ny);
-        az[m] = (int)(va / ((int64_t)nx * ny));
-    }
-    f4 acc[CF_MT][4];
+    for (int dx = 0; dx < 3; ++dx) abase[dx] = arow + 8 * cf_hslot(lane >> 4, (lane & 7) + dx);
+    // this lane's B column in LDS: output channel 16 q + (lane & 15), part lane >> 4
+    const int bbase = (lane & 15) * CF_RS + 8 * cf_wslot(lane >> 4, lane & 15);
+    // staging of a tap's weights: thread t brings 8 input channels (t & 3) of output channel t >> 2
+    const int sco = t >> 2, spart = t & 3;
+    const int sslot = sco * CF_RS + 8 * cf_wslot(spart, sco);
+    const bool sval = co0 + sco < cout;
+    const uint32_t svoff = sval ? (uint32_t)(((co0 + sco) * cin + 8 * spart) * 2) : CF_OOB;
+    auto fetch_w = [&](int tap, int c0) { return cf_load(rW, svoff, (uint32_t)((tap * cout * cin + c0) * 2)); };
+    f4 acc[4][4];
 #pragma unroll
-    for (int m = 0; m < CF_MT; ++m)
+    for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[m][q] = (f4){0.f, 0.f, 0.f, 0.f};
-    const int nchunks = cin / 32, nsteps = 27 * nchunks;
-    // software pipeline: the weights of step s+1 and the input fragments of step s+1 are in
-    // flight while step s runs its MFMAs; the weights go to the other LDS buffer at the end
-    // thread t stages 8 channels of output channel co0 + t/4
-    const int sco = t >> 2, sci = (t & 3) * 8;
-    auto load_w = [&](int step) -> bf8 {
-        const int tap = step / nchunks, c0 = (step % nchunks) * 32;
-        const uint16_t *p = co0 + sco < cout ? W + ((int64_t)tap * cout + co0 + sco) * cin + c0 + sci : cf_zero;
-        return load8(p);
-    };
-    auto load_a = [&](int step, bf8 *a) {
-        const int tap = step / nchunks, c0 = (step % nchunks) * 32;
-        const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+    const int gx0 = bx * CF_BX - 1, gy0 = by * CF_BY - 1, gz0 = bz * CF_BZ - 1;
+    for (int c0 = 0; c0 < cin; c0 += 32) {
+        bf8 wn = fetch_w(0, c0);
+        if (c0 > 0) __syncthreads();   // every wave is done with the previous chunk's halo and weights
+        // stage the halo: piece p = 8 channels (16 bytes) of halo voxel p / 4, in two batches
 #pragma unroll
-        for (int m = 0; m < CF_MT; ++m) {
-            const int xs = ax[m] + dx, ys = ay[m] + dy, zs = az[m] + dz;
-            const bool inb = vin[m] && xs >= 0 && xs < nx && ys >= 0 && ys < ny && zs >= 0 && zs < nz;
-            const int64_t vs = xs + (int64_t)nx * (ys + (int64_t)ny * zs);
-            a[m] = load8(inb ? X + vs * cin + c0 + kq : cf_zero);
-        }
-    };
-    *reinterpret_cast<bf8 *>(&sW[0][sco * CF_WS + sci]) = load_w(0);
-    bf8 a0[CF_MT], a1[CF_MT];
-    load_a(0, a0);
-    bf8 w_nxt = nsteps > 1 ? load_w(1) : zero8();
-    __syncthreads();
-    // one step: MFMAs on `a_use` (this step's input fragments) while `a_fill` receives the next
-    // step's; the two register sets swap roles every step (the loop below is unrolled by two)
-    auto run_step = [&](int step, bf8 *a_use, bf8 *a_fill) {
-        const int buf = step & 1;
-        const bool more = step + 1 < nsteps;
-        if (more) load_a(step + 1, a_fill);
-        bf8 bq[4];
+        for (int half = 0; half < 2; ++half) {
+            constexpr int NH = (CF_PPT + 1) / 2;
+            bf8 hv[NH];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            bq[q] = *reinterpret_cast<const bf8 *>(&sW[buf][(16 * q + (lane & 15)) * CF_WS + kq]);
+            for (int j = 0; j < NH; ++j) {
+                const int p = t + 256 * (half * NH + j);
+                const int v = p >> 2, part = p & 3;
+                const int hx = v % CF_HX, hy = (v / CF_HX) % CF_HY, hz = v / (CF_HX * CF_HY);
+                const int gx = gx0 + hx, gy = gy0 + hy, gz = gz0 + hz;
+                const bool inb = p < CF_PIECES && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+                const uint32_t off = (uint32_t)(((gx + (int64_t)nx * (gy + (int64_t)ny * gz)) * cin + 8 * part) * 2);
+                hv[j] = cf_load(rX, inb ? off : CF_OOB, (uint32_t)(c0 * 2));
+            }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (q < ntiles) {
-#pragma unroll
-                for (int m = 0; m < CF_MT; ++m)
-                    acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_use[m], bq[q], acc[m][q], 0, 0, 0);
+            for (int j = 0; j < NH; ++j) {
+                const int p = t + 256 * (half * NH + j);
+                if (half * NH + j < CF_PPT && p < CF_PIECES)
+                    *reinterpret_cast<bf8 *>(&sH[(p >> 2) * CF_RS + 8 * cf_hslot(p & 3, (p >> 2) % CF_HX)]) = hv[j];
             }
         }
-        if (more) {
-            *reinterpret_cast<bf8 *>(&sW[buf ^ 1][sco * CF_WS + sci]) = w_nxt;
-            if (step + 2 < nsteps) w_nxt = load_w(step + 2);
-        }
+        *reinterpret_cast<bf8 *>(&sW[0][sslot]) = wn;
+        wn = fetch_w(1, c0);
         __syncthreads();
-    };
-    for (int step = 0; step < nsteps; step += 2) {
-        run_step(step, a0, a1);
-        if (step + 1 < nsteps) run_step(step + 1, a1, a0);
+        // one (dy, dz) row of three taps per iteration.  Tap t reads its weights from buffer
+        // t % 3 and writes tap t + 1's into the next one, last read in tap t - 2: one barrier per tap
+#pragma unroll 1
+        for (int row = 0; row < 9; ++row) {
+            const int dy = row % 3, dz = row / 3;   // halo offsets (shift + 1)
+            const int roff = (CF_HX * dy + CF_HX * CF_HY * dz) * CF_RS;
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int tap = 3 * row + dx;
+                bf8 a[4], b[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    a[m] = *reinterpret_cast<const bf8 *>(&sH[abase[dx] + roff + (dx + 2 * CF_HX * m) * CF_RS]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    b[q] = q < ntiles ? *reinterpret_cast<const bf8 *>(&sW[dx][bbase + 16 * q * CF_RS]) : zero8();
+                if (tap + 1 < 27) {
+                    *reinterpret_cast<bf8 *>(&sW[(dx + 1) % 3][sslot]) = wn;
+                    if (tap + 2 < 27) wn = fetch_w(tap + 2, c0);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (q < ntiles) {
+#pragma unroll
+                        for (int m = 0; m < 4; ++m)
+                            acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[q], a[m], acc[m][q], 0, 0, 0);
+                    }
+                }
+                __syncthreads();   // the next tap's weights are in place
+            }
+        }
     }
-    // D layout: lane holds rows 4*(lane/16) + e (voxels), column lane%16 (channel)
+    // The products are weights x inputs, so the 16 x 16 tile (m, q) is channels x voxels: lane
+    // holds output channels 16 q + 4 (lane >> 4) + e, e = 0..3, of patch voxel r = lane & 15
+    // (x = r & 7, y = 2 m + (r >> 3)): four consecutive channels, one 8- or 16-byte store.
+    const int oz = bz * CF_BZ + w;
+    const int r = lane & 15;
+    const int cq = 4 * (lane >> 4);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         if (q >= ntiles) continue;
-        const int co = co0 + 16 * q + (lane & 15);
-        const float bv = bias ? bias[co] : 0.f;
+        const int co = co0 + 16 * q + cq;
+        float bv[4] = {0.f, 0.f, 0.f, 0.f};
+        if (bias) {
 #pragma unroll
-        for (int m = 0; m < CF_MT; ++m)
+            for (int e = 0; e < 4; ++e) bv[e] = bias[co + e];
+        }
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t vo = vw + 16 * m + 4 * (lane >> 4) + e;
-                if (vo >= V) continue;
-                float val = acc[m][q][e] + bv;
-                if (gate && !(bf2f(gate[vo * cout + co]) > 0.f)) val = 0.f;
-                if (relu) val = val > 0.f ? val : 0.f;
-                if (Yf) Yf[vo * cout + co] = val;
-                if (Ybf) Ybf[vo * cout + co] = f2bf(val);
+        for (int m = 0; m < 4; ++m) {
+            const int ox = bx * CF_BX + (r & 7), oy = by * CF_BY + 2 * m + (r >> 3);
+            if (ox >= nx || oy >= ny || oz >= nz) continue;
+            const int64_t at = (ox + (int64_t)nx * (oy + (int64_t)ny * oz)) * cout + co;
+            float val[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) val[e] = acc[m][q][e] + bv[e];
+            if (gate) {
+                const uint2 gb = *reinterpret_cast<const uint2 *>(gate + at);
+                const uint16_t gv[4] = {(uint16_t)(gb.x & 0xffffu), (uint16_t)(gb.x >> 16),
+                                        (uint16_t)(gb.y & 0xffffu), (uint16_t)(gb.y >> 16)};
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (!(bf2f(gv[e]) > 0.f)) val[e] = 0.f;
             }
+            if (relu) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) val[e] = val[e] > 0.f ? val[e] : 0.f;
+            }
+            if (Yf) *reinterpret_cast<float4 *>(Yf + at) = make_float4(val[0], val[1], val[2], val[3]);
+            if (Ybf)
+                *reinterpret_cast<uint2 *>(Ybf + at) =
+                    make_uint2((uint32_t)f2bf(val[0]) | ((uint32_t)f2bf(val[1]) << 16),
+                               (uint32_t)f2bf(val[2]) | ((uint32_t)f2bf(val[3]) << 16));
+        }
     }
 }
 
@@ -490,7 +562,18 @@ int nn_conv_fwd(const int32_t *dims, int cin, int cout, const uint16_t *X, const
 {
     ProfileScope prof("conv3d_fwd", st);
     const int64_t V = (int64_t)dims[0] * dims[1] * dims[2];
-    dim3 grid((unsigned)((V + CF_VB - 1) / CF_VB), (unsigned)((cout + 63) / 64));
+    if (((uintptr_t)X | (uintptr_t)W) & 15 || (uintptr_t)Yf & 15 || ((uintptr_t)Ybf | (uintptr_t)gate) & 7) {
+        set_error("conv3d: X, W and Y_f32 must be 16-byte aligned, Y_bf16 and gate 8-byte aligned");
+        return FSI_ERR_ARG;
+    }
+    if (V * cin * 2 >= ((int64_t)1 << 31)) {
+        set_error("conv3d: the input ([V][cin] bf16, %lld bytes) must stay below 2 GiB", (long long)(V * cin * 2));
+        return FSI_ERR_ARG;
+    }
+    // bricks of 8 x 8 x 4 voxels (fewer than the lattice's voxels, which the ABI keeps below 2^31)
+    const int64_t nbk = (int64_t)((dims[0] + CF_BX - 1) / CF_BX) * ((dims[1] + CF_BY - 1) / CF_BY) *
+                        ((dims[2] + CF_BZ - 1) / CF_BZ);
+    dim3 grid((unsigned)nbk, (unsigned)((cout + 63) / 64));
     hipLaunchKernelGGL(conv_fwd_k, grid, dim3(256), 0, st, dims[0], dims[1], dims[2], cin, cout, X, W,
                        bias, relu, gate, Ybf, Yf);
     FSI_LAUNCH_CHECK();
