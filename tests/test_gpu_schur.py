@@ -241,6 +241,12 @@ def test_schur_velocity_steps_match_oracle(name):
     def jac(x):
         return ojac.apply(g, P["prm_o"], P["a"], x, P["cell"], P["xi"], P["kappa"], s=P["s"], mask=P["mask"])
 
+    # FP32 bar of the triangular form: its velocity rows apply the discrete gradient to the FP32
+    # pressure solve, whose rounding-level error e_p is rough (cell-scale), while the pressure
+    # itself is smooth; the gradient amplifies the former relative to the latter by up to about
+    # the cells per unit length n.  So the bar is max(1e-5, 2 n e_p), e_p the pressure field's
+    # FP32 error measured here (block-diagonal form, same input).
+    e_p = None
     for mode, form in (("schur_diag", "diag"), ("schur_tri", "tri")):
         for k in (1, 3):
             ref = oschur.precond_apply(lv, finv, v, form, jac=jac, vel_steps=k)
@@ -249,9 +255,15 @@ def test_schur_velocity_steps_match_oracle(name):
             ref32 = oschur.precond_apply(lv, finv, v32, form, jac=jac, vel_steps=k)
             z32 = fsi.schur_apply(P["J32"], mode, pc, _t(v32, "f32"), vel_steps=k).cpu().numpy()
             e32 = field_rel_err(z32, ref32, 4)
-            print(f"  {mode} k={k}: FP64 {e64:.3e}  FP32 {e32:.3e}", flush=True)
+            if form == "diag":
+                zp, rp = z32.reshape(4, N)[3], ref32.reshape(4, N)[3]
+                e_p = max(e_p or 0.0, np.linalg.norm(zp - rp) / np.linalg.norm(rp))
+                bar32 = 1e-5
+            else:
+                bar32 = max(1e-5, 2 * max(g.n) * e_p)
+            print(f"  {mode} k={k}: FP64 {e64:.3e}  FP32 {e32:.3e} (bar {bar32:.2e})", flush=True)
             assert e64 <= 1e-12
-            assert e32 <= 1e-5
+            assert e32 <= bar32
 
 
 @pytest.mark.parametrize("inner", ["f64", "f32"])
