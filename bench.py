@@ -283,7 +283,9 @@ def time_q2_apply(fsi, torch, steps=20, warmup=5):
 
 def time_dlm(fsi, torch, case, reps=50):
     """Standalone B u and y += B^T (kappa lam) (fsi_dlm_B / fsi_dlm_BT, FP64) on the workload's
-    point set, timed with events on the launch stream over `reps` calls each."""
+    point set, timed with events on the launch stream over `reps` calls each; then the same with
+    the per-point vectors in located order (fsi_dlm_B_located, fsi_dlm_BT with perm = NULL), and
+    the one-off cost of moving 3 fields into located order (fsi_dlm_permute)."""
     g, tab, N = case["prob"].grid, case["tab"], case["N"]
     m = tab.m
     u = case["x"][: 3 * N]
@@ -293,9 +295,15 @@ def time_dlm(fsi, torch, case, reps=50):
     kap = case["prob"].kappa
     ws = torch.empty(int(fsi._lib.lib().fsi_dlm_BT_workspace(ctypes.byref(g), tab.n_occ, 0)) or 1,
                      dtype=torch.uint8, device="cuda")
+    xi_loc = fsi.dlm_permute(tab, tab.xi, 3)
+    kap_loc = fsi.dlm_permute(tab, kap, 1)
+    lam_loc = torch.empty_like(lam)
     out = {}
     for name, fn in (("B", lambda: fsi.dlm_B(g, tab, u, Bu)),
-                     ("BT", lambda: fsi.dlm_BT(g, tab, lam, y, kappa=kap, ws=ws))):
+                     ("BT", lambda: fsi.dlm_BT(g, tab, lam, y, kappa=kap, ws=ws)),
+                     ("B_located", lambda: fsi.dlm_B_located(g, tab, xi_loc, u, Bu)),
+                     ("BT_located", lambda: fsi.dlm_BT(g, tab, lam_loc, y, kappa=kap_loc, ws=ws, xi_loc=xi_loc)),
+                     ("permute3", lambda: fsi.dlm_permute(tab, lam, 3, dst=lam_loc))):
         for _ in range(5):
             fn()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -155,6 +155,29 @@ int fsi_dlm_B(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const int32_t *c
               const void *xi, const void *u, void *Bu, void *stream);
 
 /*
+ * Located order: position j of the cell-sorted point list of fsi_dlm_locate
+ * (the points of occupied cell k at occ_start[k] .. occ_start[k+1] - 1, the
+ * points outside the grid last), i.e. point perm[j].  Per-point vectors kept
+ * in this order are read and written contiguously by fsi_dlm_B_located and by
+ * fsi_dlm_BT with perm = NULL; in point order every point costs scattered
+ * reads through perm.  A caller whose points move little between steps can
+ * keep its per-point arrays in a previous step's located order.
+ *
+ * fsi_dlm_permute - nf fields of M points, T [nf][M]: to located order
+ * (to_point = 0: dst[f][j] = src[f][perm[j]]) or back (to_point = 1:
+ * dst[f][perm[j]] = src[f][j]); dst must not alias src.
+ *
+ * fsi_dlm_B_located - fsi_dlm_B with xi_loc (T [3][M]) and Bu_loc (T [3][M],
+ * out) in located order; the points outside the grid get 0.  Bitwise equal
+ * to fsi_dlm_B followed by fsi_dlm_permute.
+ */
+int fsi_dlm_permute(fsi_dtype dtype, int64_t m, int32_t nf, const int32_t *perm, int32_t to_point,
+                    const void *src, void *dst, void *stream);
+int fsi_dlm_B_located(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const int32_t *occ_cell,
+                      const int32_t *occ_start, int64_t n_occ, const void *xi_loc, const void *u,
+                      void *Bu_loc, void *stream);
+
+/*
  * fsi_dlm_BT - spread point forces to the fluid nodes:
  * y_A += sum_B N_A(xi_B) kappa_B lam_B, per component (section 2.3, eq.
  * fsi_constraint_matrix: C^lambda_AB = N_A(phi(X_B)) I, "force spreading").
@@ -165,6 +188,9 @@ int fsi_dlm_B(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const int32_t *c
  *   lam        T [3][M];  kappa  T [M] or NULL (kappa = 1)
  *   y          T [3][N], ACCUMULATED (y += ...)
  *   ws         at least fsi_dlm_BT_workspace(grid, n_occ, dtype) bytes
+ * perm = NULL: xi, lam and kappa are given in located order (see
+ * fsi_dlm_permute), read without indirection; the result is bitwise that of
+ * the point-order call on the same values.
  */
 size_t fsi_dlm_BT_workspace(const fsi_grid *grid, int64_t n_occ, fsi_dtype dtype);
 int fsi_dlm_BT(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const int32_t *cell,

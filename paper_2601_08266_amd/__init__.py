@@ -21,7 +21,7 @@ from ._lib import (FSI_F32, FSI_F64, FsiError, FsiGrid, FsiNewtonOpts, FsiNewton
 
 __all__ = [
     "FSI_F64", "FSI_F32", "FsiError", "make_grid", "make_params", "version",
-    "vms_apply_workspace", "vms_apply", "PointTables", "dlm_locate", "dlm_B", "dlm_BT",
+    "vms_apply_workspace", "vms_apply", "PointTables", "dlm_locate", "dlm_B", "dlm_BT", "dlm_B_located", "dlm_permute",
     "Problem", "jacobian_apply", "jacobian_workspace", "dlm_gram", "profile_enable",
     "profile_read", "vms_residual", "bjacobi_setup", "bjacobi_apply", "fgmres_solve",
     "schur_size", "schur_info", "schur_setup", "schur_apply", "PRECONDS", "tangent_apply",
@@ -206,21 +206,59 @@ def dlm_B(grid, tables: PointTables, u: torch.Tensor, Bu: Optional[torch.Tensor]
 
 def dlm_BT(grid, tables: PointTables, lam: torch.Tensor, y: torch.Tensor,
            kappa: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
-           stream=None) -> torch.Tensor:
-    """y += B^T (kappa * lam) (fsi_dlm_BT); y: [3][N] (or a [4][N] whose first 3N are used)."""
+           stream=None, xi_loc: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y += B^T (kappa * lam) (fsi_dlm_BT); y: [3][N] (or a [4][N] whose first 3N are used).
+    With xi_loc (the tables' xi in located order, dlm_permute), lam and kappa are taken in
+    located order too and read without indirection (perm = NULL)."""
     g = grid_from(grid)
     dt = tables.xi.dtype
     _need(lam, "lam", dt, 3 * tables.m)
     _need(y, "y", dt)
     if kappa is not None:
         _need(kappa, "kappa", dt, tables.m)
+    if xi_loc is not None:
+        _need(xi_loc, "xi_loc", dt, 3 * tables.m)
     nbytes = int(L.lib().fsi_dlm_BT_workspace(ctypes.byref(g), tables.n_occ, dtype_code(dt)))
     ws = _workspace(nbytes, y.device, ws)
+    xi, perm = (tables.xi, tables.perm) if xi_loc is None else (xi_loc, None)
     L.check("fsi_dlm_BT", L.lib().fsi_dlm_BT(
-        ctypes.byref(g), dtype_code(dt), tables.m, _ptr(tables.cell), _ptr(tables.xi),
-        _ptr(tables.perm), _ptr(tables.occ_cell), _ptr(tables.occ_start), _ptr(tables.occ_index),
+        ctypes.byref(g), dtype_code(dt), tables.m, _ptr(tables.cell), _ptr(xi),
+        _ptr(perm), _ptr(tables.occ_cell), _ptr(tables.occ_start), _ptr(tables.occ_index),
         tables.n_occ, _ptr(lam), _ptr(kappa), _ptr(y), _ptr(ws), ws.numel(), _stream(stream)))
     return y
+
+
+def dlm_permute(tables: PointTables, src: torch.Tensor, nf: int, to_point: bool = False,
+                dst: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """nf fields of the M points ([nf][M]) into located order (dst[f][j] = src[f][perm[j]]) or,
+    with to_point, back (fsi_dlm_permute)."""
+    m = tables.m
+    _need(src, "src", src.dtype, nf * m)
+    if dst is None:
+        dst = torch.empty(max(nf * m, 1), dtype=src.dtype, device=src.device)
+    L.check("fsi_dlm_permute", L.lib().fsi_dlm_permute(
+        dtype_code(src.dtype), m, nf, _ptr(tables.perm), 1 if to_point else 0, _ptr(src), _ptr(dst),
+        _stream(stream)))
+    return dst[:nf * m]
+
+
+def dlm_B_located(grid, tables: PointTables, xi_loc: torch.Tensor, u: torch.Tensor,
+                  Bu_loc: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """B u with xi_loc and the result in located order (fsi_dlm_B_located)."""
+    g = grid_from(grid)
+    N = num_nodes(g)
+    dt = tables.xi.dtype
+    _need(u, "u", dt)
+    _need(xi_loc, "xi_loc", dt, 3 * tables.m)
+    if u.numel() < 3 * N:
+        raise ValueError("u must hold at least 3N values")
+    m = tables.m
+    if Bu_loc is None:
+        Bu_loc = torch.empty(3 * max(m, 1), dtype=dt, device=u.device)
+    L.check("fsi_dlm_B_located", L.lib().fsi_dlm_B_located(
+        ctypes.byref(g), dtype_code(dt), m, _ptr(tables.occ_cell), _ptr(tables.occ_start), tables.n_occ,
+        _ptr(xi_loc), _ptr(u), _ptr(Bu_loc), _stream(stream)))
+    return Bu_loc[:3 * m]
 
 
 def dlm_gram(grid, tables: PointTables, kappa: Optional[torch.Tensor] = None,

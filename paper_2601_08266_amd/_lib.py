@@ -120,6 +120,8 @@ SIGNATURES = {
                                       P, P, ctypes.c_double, ctypes.POINTER(I64),
                                       ctypes.POINTER(I64), P, SZ, P]),
     "fsi_dlm_B": (ctypes.c_int, [ctypes.POINTER(FsiGrid), ctypes.c_int, I64, P, P, P, P, P]),
+    "fsi_dlm_B_located": (ctypes.c_int, [ctypes.POINTER(FsiGrid), ctypes.c_int, I64, P, P, I64, P, P, P, P]),
+    "fsi_dlm_permute": (ctypes.c_int, [ctypes.c_int, I64, ctypes.c_int32, P, ctypes.c_int32, P, P, P]),
     "fsi_dlm_BT_workspace": (SZ, [ctypes.POINTER(FsiGrid), I64, ctypes.c_int]),
     "fsi_dlm_BT": (ctypes.c_int, [ctypes.POINTER(FsiGrid), ctypes.c_int, I64, P, P, P, P, P, P, I64,
                                   P, P, P, P, SZ, P]),

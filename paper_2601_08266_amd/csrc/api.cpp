@@ -332,6 +332,34 @@ FSI_API int fsi_dlm_B(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const in
     return launch_dlm_B(make_geo(*grid), dtype, m, cell, xi, u, nullptr, Bu, as_stream(stream));
 }
 
+FSI_API int fsi_dlm_B_located(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const int32_t *occ_cell,
+                              const int32_t *occ_start, int64_t n_occ, const void *xi_loc, const void *u,
+                              void *Bu_loc, void *stream)
+{
+    clear_error();
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    FSI_CHECK_ARG(dtype_ok(dtype), "bad dtype %d", (int)dtype);
+    FSI_CHECK_ARG(m >= 0 && m < ((int64_t)1 << 31) - 1, "m out of range");
+    const Geo g = make_geo(*grid);
+    FSI_CHECK_ARG(n_occ >= 0 && n_occ <= g.E && n_occ <= m, "n_occ out of range");
+    if (m == 0) return FSI_OK;
+    FSI_CHECK_ARG(occ_cell && occ_start && xi_loc && u && Bu_loc, "point tables, u and Bu must be non-NULL");
+    return launch_dlm_B_located(g, dtype, m, n_occ, occ_cell, occ_start, xi_loc, u, Bu_loc, as_stream(stream));
+}
+
+FSI_API int fsi_dlm_permute(fsi_dtype dtype, int64_t m, int32_t nf, const int32_t *perm, int32_t to_point,
+                            const void *src, void *dst, void *stream)
+{
+    clear_error();
+    FSI_CHECK_ARG(dtype_ok(dtype), "bad dtype %d", (int)dtype);
+    FSI_CHECK_ARG(m >= 0 && m < ((int64_t)1 << 31) - 1, "m out of range");
+    FSI_CHECK_ARG(nf >= 0 && nf <= 64, "nf out of range");
+    if (m == 0 || nf == 0) return FSI_OK;
+    FSI_CHECK_ARG(perm && src && dst && src != dst, "perm, src and dst must be non-NULL, dst not src");
+    return launch_dlm_permute(dtype, m, nf, perm, to_point != 0, src, dst, as_stream(stream));
+}
+
 FSI_API size_t fsi_dlm_BT_workspace(const fsi_grid *grid, int64_t n_occ, fsi_dtype dtype)
 {
     if (check_grid(grid) != FSI_OK || n_occ < 0 || !dtype_ok(dtype)) return 0;
@@ -354,14 +382,14 @@ FSI_API int fsi_dlm_BT(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const i
     FSI_CHECK_ARG(y != nullptr, "y must be non-NULL");
     (void)cell;
     if (n_occ == 0) return FSI_OK;
-    FSI_CHECK_ARG(xi && perm && occ_cell && occ_start && occ_index && lam,
-                  "point tables and lam must be non-NULL");
+    FSI_CHECK_ARG(xi && occ_cell && occ_start && occ_index && lam, "point tables and lam must be non-NULL");
     const size_t need = dlm_csum_bytes(g, n_occ, dtype);
     if (ws == nullptr || ws_bytes < need) {
         set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
         return FSI_ERR_WORKSPACE;
     }
     hipStream_t st = as_stream(stream);
+    // perm NULL: xi, lam and kappa are in located order (no indirection)
     rc = launch_dlm_cell_reduce(g, dtype, false, m, n_occ, occ_cell, occ_start, perm, xi, kappa, lam,
                                 nullptr, ws, st);
     if (rc) return rc;

@@ -17,6 +17,7 @@
 //           cell owns the node) adds the corner sums of the occupied cells
 //           around each node in a fixed order.  No floating-point atomics
 //           anywhere, so results are bitwise reproducible.
+#include <algorithm>
 #include <utility>
 
 #include "dlm.hpp"
@@ -358,6 +359,76 @@ __global__ __launch_bounds__(256) void dlm_B_kernel(Geo g, int64_t m, const int3
 // r stores the entries e = r, r + LPC, ... (fixed order: deterministic).  The sums run in FP64
 // for both precisions (a cell can hold hundreds of points; an FP32 product is rounded once
 // per term and the total once when stored).
+// B u for per-point arrays in located order (position j of the cell-sorted point list, the
+// points of occupied cell k at occ_start[k] .. occ_start[k+1]): LPC lanes per occupied cell
+// load its nodes once, then take its points in turn, so xi and Bu are read and written
+// contiguously.  Per point the same products in the same order as dlm_B_kernel (bitwise equal).
+template <typename T, int P, int LPC>
+__global__ __launch_bounds__(256) void dlm_B_located(Geo g, int64_t m, int64_t n_occ,
+                                                     const int32_t *__restrict__ occ_cell,
+                                                     const int32_t *__restrict__ occ_start,
+                                                     const T *__restrict__ xi, const T *__restrict__ u,
+                                                     T *__restrict__ Bu)
+{
+    constexpr int Q = P + 1, NEN = Q * Q * Q;
+    const int64_t o = ((int64_t)blockIdx.x * 256 + threadIdx.x) / LPC;
+    const int lane = threadIdx.x % LPC;
+    if (o >= n_occ) return;
+    const int32_t c = occ_cell[o];
+    const int cx = c % g.n[0], cy = (c / g.n[0]) % g.n[1], cz = c / (g.n[0] * g.n[1]);
+    T un[3][NEN];
+#pragma unroll
+    for (int A = 0; A < NEN; ++A) {
+        const int ax = A % Q, ay = (A / Q) % Q, az = A / (Q * Q);
+        const int64_t node = (int64_t)(P * cx + ax) + (int64_t)g.nn[0] * ((P * cy + ay) + (int64_t)g.nn[1] * (P * cz + az));
+#pragma unroll
+        for (int f = 0; f < 3; ++f) un[f][A] = u[f * g.N + node];
+    }
+    const int32_t j0 = occ_start[o], j1 = occ_start[o + 1];
+    for (int32_t j = j0 + lane; j < j1; j += LPC) {
+        T Nx[Q], Ny[Q], Nz[Q];
+        lagrange<T, P>(xi[j], Nx);
+        lagrange<T, P>(xi[m + j], Ny);
+        lagrange<T, P>(xi[2 * m + j], Nz);
+        T acc[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int A = 0; A < NEN; ++A) {
+            const T w = Nx[A % Q] * Ny[(A / Q) % Q] * Nz[A / (Q * Q)];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) acc[f] += w * un[f][A];
+        }
+#pragma unroll
+        for (int f = 0; f < 3; ++f) Bu[f * m + j] = acc[f];
+    }
+}
+
+// Bu = 0 at the located positions of the points outside the grid (occ_start[n_occ] .. m - 1)
+template <typename T>
+__global__ __launch_bounds__(256) void dlm_zero_tail(int64_t m, int64_t n_occ, const int32_t *__restrict__ occ_start,
+                                                     T *__restrict__ Bu)
+{
+    const int64_t first = occ_start[n_occ];
+    for (int64_t j = first + (int64_t)blockIdx.x * 256 + threadIdx.x; j < m; j += (int64_t)gridDim.x * 256)
+#pragma unroll
+        for (int f = 0; f < 3; ++f) Bu[f * m + j] = T(0);
+}
+
+// dst[f][j] = src[f][perm[j]] (to located order) or dst[f][perm[j]] = src[f][j] (back)
+template <typename T, bool BACK>
+__global__ __launch_bounds__(256) void dlm_permute_k(int64_t m, int nf, const int32_t *__restrict__ perm,
+                                                     const T *__restrict__ src, T *__restrict__ dst)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= m) return;
+    const int64_t p = perm[j];
+    for (int f = 0; f < nf; ++f) {
+        if (BACK)
+            dst[f * m + p] = src[f * m + j];
+        else
+            dst[f * m + j] = src[f * m + p];
+    }
+}
+
 template <typename T, int P, bool FROM_U, int LPC>
 __global__ __launch_bounds__(256) void dlm_cell_reduce(Geo g, int64_t m, int64_t n_occ,
                                                        const int32_t *__restrict__ occ_cell,
@@ -407,7 +478,8 @@ __global__ __launch_bounds__(256) void dlm_cell_reduce(Geo g, int64_t m, int64_t
 #pragma unroll
         for (int u = 0; u < UB; ++u) {
             const int32_t ju = j + u * LPC;
-            bs[u] = perm[ju < j1 ? ju : j];
+            const int32_t jc = ju < j1 ? ju : j;
+            bs[u] = perm != nullptr ? perm[jc] : jc;   // NULL: per-point arrays in located order
         }
         T xs[UB][3], kbs[UB], ms[UB][3];
 #pragma unroll
@@ -729,6 +801,60 @@ int launch_dlm_B(const Geo &g, fsi_dtype dt, int64_t m, const int32_t *cell, con
     if (dt == FSI_F64)
         return launch_B_t<double>(g, m, cell, (const double *)xi, (const double *)u, mask, (double *)Bu, st);
     return launch_B_t<float>(g, m, cell, (const float *)xi, (const float *)u, mask, (float *)Bu, st);
+}
+
+template <typename T>
+static int launch_B_located_t(const Geo &g, int64_t m, int64_t n_occ, const int32_t *occ_cell,
+                              const int32_t *occ_start, const T *xi, const T *u, T *Bu, hipStream_t st)
+{
+    if (m == 0) return FSI_OK;
+    if (n_occ > 0) {
+        if (g.p == 1)
+            hipLaunchKernelGGL((dlm_B_located<T, 1, 8>), dim3((unsigned)((n_occ + 31) / 32)), dim3(256), 0, st, g, m,
+                               n_occ, occ_cell, occ_start, xi, u, Bu);
+        else
+            hipLaunchKernelGGL((dlm_B_located<T, 2, 64>), dim3((unsigned)((n_occ + 3) / 4)), dim3(256), 0, st, g,
+                               m, n_occ, occ_cell, occ_start, xi, u, Bu);
+        FSI_LAUNCH_CHECK();
+    }
+    const unsigned tb = (unsigned)std::min<int64_t>(nblk(m), 1024);
+    hipLaunchKernelGGL(dlm_zero_tail<T>, dim3(tb), dim3(256), 0, st, m, n_occ, occ_start, Bu);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+
+int launch_dlm_B_located(const Geo &g, fsi_dtype dt, int64_t m, int64_t n_occ, const int32_t *occ_cell,
+                         const int32_t *occ_start, const void *xi, const void *u, void *Bu, hipStream_t st)
+{
+    if (dt == FSI_F64)
+        return launch_B_located_t<double>(g, m, n_occ, occ_cell, occ_start, (const double *)xi, (const double *)u,
+                                          (double *)Bu, st);
+    return launch_B_located_t<float>(g, m, n_occ, occ_cell, occ_start, (const float *)xi, (const float *)u,
+                                     (float *)Bu, st);
+}
+
+int launch_dlm_permute(fsi_dtype dt, int64_t m, int nf, const int32_t *perm, bool back, const void *src, void *dst,
+                       hipStream_t st)
+{
+    if (m == 0 || nf == 0) return FSI_OK;
+    const dim3 grid(nblk(m));
+    if (dt == FSI_F64) {
+        if (back)
+            hipLaunchKernelGGL((dlm_permute_k<double, true>), grid, dim3(256), 0, st, m, nf, perm,
+                               (const double *)src, (double *)dst);
+        else
+            hipLaunchKernelGGL((dlm_permute_k<double, false>), grid, dim3(256), 0, st, m, nf, perm,
+                               (const double *)src, (double *)dst);
+    } else {
+        if (back)
+            hipLaunchKernelGGL((dlm_permute_k<float, true>), grid, dim3(256), 0, st, m, nf, perm,
+                               (const float *)src, (float *)dst);
+        else
+            hipLaunchKernelGGL((dlm_permute_k<float, false>), grid, dim3(256), 0, st, m, nf, perm,
+                               (const float *)src, (float *)dst);
+    }
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
 }
 
 size_t dlm_csum_bytes(const Geo &g, int64_t n_occ, fsi_dtype dt)

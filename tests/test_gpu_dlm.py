@@ -137,6 +137,57 @@ def test_B_BT_parity_and_adjoint(case, dtype):
     assert torch.equal(y1, y2)
 
 
+@pytest.mark.parametrize("case", ["special8", "q2", "c5"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_located_order_bitwise(case, dtype):
+    """Per-point vectors in located order (fsi_dlm_permute, fsi_dlm_B_located, fsi_dlm_BT with
+    perm = NULL) give bitwise the point-order results: the same products in the same order.
+    Includes points outside the grid (their located B u is 0) and a Q2 grid."""
+    import paper_2601_08266_amd as fsi
+    import torch
+    rng = np.random.default_rng(17)
+    if case == "special8":
+        g = W.Grid((8, 8, 8), 1)
+        X = special_cloud(g, rng, 3000)
+        kappa = rng.uniform(0.5, 2.0, X.shape[1])
+    elif case == "q2":
+        g = W.Grid((9, 7, 8), 2)
+        X = rng.uniform(-0.05, 1.05, (3, 4000))
+        kappa = rng.uniform(0.5, 2.0, 4000)
+    else:
+        cfg = W.CONFIGS[case]
+        g = cfg.grid
+        X, kappa = points_for(cfg)
+    N, m = g.num_nodes, X.shape[1]
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    tab = fsi.dlm_locate(g, _t(X), dtype=tdt)
+    print(f"located {case} {dtype}: m {m}, occupied cells {tab.n_occ}", flush=True)
+    u = _t(rng.standard_normal((3, N)), dtype)
+    lam = _t(rng.standard_normal((3, m)), dtype)
+    kap = _t(kappa, dtype)
+    xi_loc = fsi.dlm_permute(tab, tab.xi, 3)
+    lam_loc = fsi.dlm_permute(tab, lam, 3)
+    kap_loc = fsi.dlm_permute(tab, kap, 1)
+    # the permutation and its inverse
+    perm = tab.perm.long()
+    assert torch.equal(lam_loc.view(3, m), lam.view(3, m)[:, perm])
+    assert torch.equal(fsi.dlm_permute(tab, lam_loc, 3, to_point=True), lam)
+    # B: located result = point-order result moved to located order; outside points 0
+    Bu = fsi.dlm_B(g, tab, u)
+    Bu_loc = fsi.dlm_B_located(g, tab, xi_loc, u)
+    assert torch.equal(Bu_loc, fsi.dlm_permute(tab, Bu, 3))
+    outside = (tab.cell.view(-1)[perm] < 0).nonzero().view(-1)
+    if outside.numel():
+        assert torch.all(Bu_loc.view(3, m)[:, outside] == 0)
+    # B^T with perm = NULL on located-order xi, lam and kappa
+    y1 = torch.zeros(3 * N, dtype=tdt, device="cuda")
+    y2 = torch.zeros(3 * N, dtype=tdt, device="cuda")
+    fsi.dlm_BT(g, tab, lam, y1, kappa=kap)
+    fsi.dlm_BT(g, tab, lam_loc, y2, kappa=kap_loc, xi_loc=xi_loc)
+    assert torch.equal(y1, y2)
+    print(f"located {case} {dtype}: bitwise equal ({outside.numel()} outside points)")
+
+
 @pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_dlm_gram_parity(order, dtype):
