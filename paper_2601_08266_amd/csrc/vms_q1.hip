@@ -272,6 +272,23 @@ __device__ __forceinline__ QP<T> q1_point(int q)
     return o;
 }
 
+// The same values selected by the point's index bits (uniform: scalar selects instead of a
+// memory load whose wait would share the LDS counter); used by the apply and residual cells
+template <typename T>
+__device__ __forceinline__ QP<T> q1_point_sel(int q)
+{
+    const bool bx = q & 1, by = (q >> 1) & 1, bz = (q >> 2) & 1;
+    const double x = bx ? GQ1 : GQ0, y = by ? GQ1 : GQ0, z = bz ? GQ1 : GQ0;
+    const double xy = bx ? (by ? GQ1 * GQ1 : GQ1 * GQ0) : (by ? GQ0 * GQ1 : GQ0 * GQ0);
+    const double xz = bx ? (bz ? GQ1 * GQ1 : GQ1 * GQ0) : (bz ? GQ0 * GQ1 : GQ0 * GQ0);
+    const double yz = by ? (bz ? GQ1 * GQ1 : GQ1 * GQ0) : (bz ? GQ0 * GQ1 : GQ0 * GQ0);
+    const double xyz = bz ? (by ? (bx ? GQ1 * GQ1 * GQ1 : GQ0 * GQ1 * GQ1) : (bx ? GQ1 * GQ0 * GQ1 : GQ0 * GQ0 * GQ1))
+                          : (by ? (bx ? GQ1 * GQ1 * GQ0 : GQ0 * GQ1 * GQ0) : (bx ? GQ1 * GQ0 * GQ0 : GQ0 * GQ0 * GQ0));
+    QP<T> o;
+    o.x = T(x); o.y = T(y); o.z = T(z); o.xy = T(xy); o.xz = T(xz); o.yz = T(yz); o.xyz = T(xyz);
+    return o;
+}
+
 // Phase 2: Galerkin + SUPG/PSPG/LSIC weighting at the 8 Gauss points from the monomial
 // coefficients cu and the point table lq; output out[f][A] (nodal).  Derivatives are
 // taken on the reference cell and the 1/h factors folded into the table and the
@@ -282,7 +299,7 @@ __device__ __forceinline__ QP<T> q1_point(int q)
 // step instead of the linear apply: the advection field is the velocity itself (a = u)
 // and the table holds the source f = c_m u_old + body force, whose Galerkin/SUPG/PSPG
 // weighting is subtracted.
-template <typename T, bool RESID>
+template <typename T, bool RESID, bool VS>
 __device__ __forceinline__ void q1_cell(const VmsConst<T> &k, T cu[4][8], const T *lq,
                                         const T *__restrict__ dlm, T out[4][8])
 {
@@ -294,7 +311,7 @@ __device__ __forceinline__ void q1_cell(const VmsConst<T> &k, T cu[4][8], const 
 
 #pragma unroll 1
     for (int pr = 0; pr < 4; ++pr) {
-        const QP<T> q0 = q1_point<T>(2 * pr);
+        const QP<T> q0 = q1_point_sel<T>(2 * pr);
         T E[4], O[4];
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
@@ -305,7 +322,7 @@ __device__ __forceinline__ void q1_cell(const VmsConst<T> &k, T cu[4][8], const 
 #pragma unroll
         for (int ix = 0; ix < 2; ++ix) {
             const int qi = 2 * pr + ix;
-            const QP<T> q = q1_point<T>(qi);
+            const QP<T> q = q1_point_sel<T>(qi);
             const T *lp = lq + Q1_NQV * qi * Q1_NT;
             T Ah[3] = {lp[0], lp[Q1_NT], lp[2 * Q1_NT]};
             const T tau_m = lp[3 * Q1_NT], tau_c = lp[4 * Q1_NT];
@@ -333,7 +350,7 @@ __device__ __forceinline__ void q1_cell(const VmsConst<T> &k, T cu[4][8], const 
             // nu grad(div u) for trilinear fields on Cartesian cells (only mixed second
             // derivatives survive)
             T ngd[3] = {T(0), T(0), T(0)};
-            if (k.visc_strong) {
+            if constexpr (VS) {
                 const T u1xy = (cu[1][3] + cu[1][7] * q.z) * k.nu_hh[0][1];
                 const T u2xz = (cu[2][5] + cu[2][7] * q.y) * k.nu_hh[0][2];
                 const T u0xy = (cu[0][3] + cu[0][7] * q.z) * k.nu_hh[0][1];
@@ -638,7 +655,7 @@ __device__ __forceinline__ int64_t xcd_brick(int64_t bid, int64_t nb)
 // result is added to the brick partials that the Picard apply (MODE 0 with a = u) wrote;
 // 3: the whole full-Newton tangent in one pass: x = state, `a` = source f, dv = direction
 // (velocity and pressure), gram = the per-cell DLM blocks; the partials are overwritten.
-template <typename T, int MODE>
+template <typename T, int MODE, bool VS = true>
 __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, const T *__restrict__ x,
                                                     const T *__restrict__ a,
                                                     const T *__restrict__ s,
@@ -750,7 +767,7 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
             else
                 q1_tangent_cell<T>(k, cu, cd, lds + t, out);
         } else {
-            q1_cell<T, RESID>(k, cu, lds + t, dlm, out);
+            q1_cell<T, RESID, VS>(k, cu, lds + t, dlm, out);
         }
     }
     // element -> node accumulation: every lane parks its 32 nodal outputs in LDS, then each
@@ -912,12 +929,24 @@ int launch_q1_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, 
     FSI_CHECK_ARG((int64_t)g.nn[0] * g.nn[1] * (Q1_BZ + 1) * (int64_t)sizeof(T) < ((int64_t)1 << 31),
                   "Q1 grid planes too large (%d x %d nodes)", g.nn[0], g.nn[1]);
     ProfileScope prof(resid ? "vms_q1_residual" : "vms_q1_cells", st);
-    if (resid)
-        hipLaunchKernelGGL((vms_q1_cells<T, 1>), dim3((unsigned)bl.nb), dim3(Q1_NT), 0, st, g, k, x, a,
-                           s, mask, gram, occ_index, part, bl.nbx, bl.nby, (const T *)nullptr);
-    else
-        hipLaunchKernelGGL((vms_q1_cells<T, 0>), dim3((unsigned)bl.nb), dim3(Q1_NT), 0, st, g, k, x,
-                           a, s, mask, gram, occ_index, part, bl.nbx, bl.nby, (const T *)nullptr);
+    // the strong viscous term as a compile-time switch: no branch inside the Gauss loop
+    const dim3 grid((unsigned)bl.nb), block(Q1_NT);
+    const T *nod = nullptr;
+    if (resid) {
+        if (k.visc_strong)
+            hipLaunchKernelGGL((vms_q1_cells<T, 1, true>), grid, block, 0, st, g, k, x, a, s, mask, gram, occ_index,
+                               part, bl.nbx, bl.nby, nod);
+        else
+            hipLaunchKernelGGL((vms_q1_cells<T, 1, false>), grid, block, 0, st, g, k, x, a, s, mask, gram,
+                               occ_index, part, bl.nbx, bl.nby, nod);
+    } else {
+        if (k.visc_strong)
+            hipLaunchKernelGGL((vms_q1_cells<T, 0, true>), grid, block, 0, st, g, k, x, a, s, mask, gram, occ_index,
+                               part, bl.nbx, bl.nby, nod);
+        else
+            hipLaunchKernelGGL((vms_q1_cells<T, 0, false>), grid, block, 0, st, g, k, x, a, s, mask, gram,
+                               occ_index, part, bl.nbx, bl.nby, nod);
+    }
     FSI_LAUNCH_CHECK();
     return FSI_OK;
 }
