@@ -86,9 +86,9 @@ constexpr uint32_t CF_OOB = 0x80000000u;   // a lane offset past every resource:
 
 // Block b -> brick: blocks are dealt to the 8 XCDs round-robin, each XCD gets a contiguous
 // range of bricks (x fastest), so bricks sharing halo voxels mostly run under one L2.
-__device__ __forceinline__ int64_t cf_brick(int64_t b, int64_t nb)
+__device__ __forceinline__ uint32_t cf_brick(uint32_t b, uint32_t nb)
 {
-    const int64_t q = nb / 8, r = nb % 8, xcd = b % 8, idx = b / 8;
+    const uint32_t q = nb >> 3, r = nb & 7u, xcd = b & 7u, idx = b >> 3;
     return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
@@ -107,8 +107,9 @@ __global__ __launch_bounds__(256, 3) void conv_fwd_k(int nx, int ny, int nz, int
     __shared__ __attribute__((aligned(16))) uint16_t sW[3][64 * CF_RS];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int nbx = (nx + CF_BX - 1) / CF_BX, nby = (ny + CF_BY - 1) / CF_BY;
-    const int64_t brick = cf_brick(blockIdx.x, gridDim.x);
-    const int bx = (int)(brick % nbx), by = (int)((brick / nbx) % nby), bz = (int)(brick / ((int64_t)nbx * nby));
+    const uint32_t brick = cf_brick(blockIdx.x, gridDim.x);
+    const uint32_t bxy = brick / (uint32_t)nbx;
+    const int bx = (int)(brick - bxy * (uint32_t)nbx), by = (int)(bxy % (uint32_t)nby), bz = (int)(bxy / (uint32_t)nby);
     const int co0 = blockIdx.y * 64;
     const int ntiles = (cout - co0) >= 64 ? 4 : (cout - co0) / 16;
     const int64_t V = (int64_t)nx * ny * nz;

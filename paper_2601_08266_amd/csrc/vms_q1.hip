@@ -644,9 +644,10 @@ __device__ __forceinline__ void q1_fused_tangent_cell(const VmsConst<T> &k, cons
 // Brick handled by block bid.  Blocks are dealt to the 8 XCDs round-robin; each XCD is
 // given a contiguous range of bricks (x fastest), so bricks that share face nodes (and
 // the cache lines holding them) mostly run under the same L2.
-__device__ __forceinline__ int64_t xcd_brick(int64_t bid, int64_t nb)
+// (32-bit: a launch has fewer than 2^32 blocks, and 64-bit divisions are long scalar sequences)
+__device__ __forceinline__ uint32_t xcd_brick(uint32_t bid, uint32_t nb)
 {
-    const int64_t q = nb / 8, r = nb % 8, xcd = bid % 8, idx = bid / 8;
+    const uint32_t q = nb >> 3, r = nb & 7u, xcd = bid & 7u, idx = bid >> 3;
     return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
@@ -674,8 +675,9 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
     static_assert(8 * Q1_NQV >= 32 && 8 * Q1_NQV * Q1_NT >= NF * Q1_NL, "LDS too small");
     __shared__ T lds[8 * Q1_NQV * Q1_NT];
     const int t = threadIdx.x;
-    const int64_t bid = xcd_brick(blockIdx.x, gridDim.x);
-    const int bx = (int)(bid % nbx), by = (int)((bid / nbx) % nby), bz = (int)(bid / ((int64_t)nbx * nby));
+    const uint32_t bid = xcd_brick(blockIdx.x, gridDim.x);
+    const uint32_t bxy = bid / (uint32_t)nbx;
+    const int bx = (int)(bid - bxy * (uint32_t)nbx), by = (int)(bxy % (uint32_t)nby), bz = (int)(bxy / (uint32_t)nby);
     const int tx = t % Q1_BX, ty = (t / Q1_BX) % Q1_BY, tz = t / (Q1_BX * Q1_BY);
     const int cx = bx * Q1_BX + tx, cy = by * Q1_BY + ty, cz = bz * Q1_BZ + tz;
     const bool valid = cx < g.n[0] && cy < g.n[1] && cz < g.n[2];
