@@ -98,7 +98,7 @@ const char *fsi_version(void);
  *              are Dirichlet: their columns are treated as zero and their rows
  *              as the identity (y_k = x_k).
  *   x          T [4][N] input (device);  y  T [4][N] output, overwritten.
- *              x and y must not overlap.
+ *              y must not overlap x, a or s.
  *   ws         workspace of at least fsi_vms_apply_workspace(grid, dtype) bytes.
  * Deterministic: identical inputs give bitwise identical outputs.
  */
@@ -291,8 +291,8 @@ typedef struct {
 } fsi_problem;
 
 /*
- * fsi_jacobian_apply - y = J x for the problem above (x, y: T [4][N] device,
- * not overlapping).  ws: at least fsi_jacobian_workspace(problem) bytes.
+ * fsi_jacobian_apply - y = J x for the problem above (x, y: T [4][N] device;
+ * y overlaps neither x nor the problem's arrays).  ws: at least fsi_jacobian_workspace(problem) bytes.
  * Deterministic.
  */
 size_t fsi_jacobian_workspace(const fsi_problem *problem);

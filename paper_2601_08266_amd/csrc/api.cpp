@@ -279,7 +279,7 @@ FSI_API int fsi_vms_apply(const fsi_grid *grid, const fsi_vms_params *prm, fsi_d
     if (rc) return rc;
     FSI_CHECK_ARG(dtype_ok(dtype), "bad dtype %d", (int)dtype);
     FSI_CHECK_ARG(a && x && y, "a, x and y must be non-NULL");
-    FSI_CHECK_ARG(x != y, "x and y must not alias");
+    FSI_CHECK_ARG(x != y && a != y && s != y, "y must not alias x, a or s");
     const Geo g = make_geo(*grid);
     const size_t need = vms_workspace_bytes(g, dtype);
     if (ws == nullptr || ws_bytes < need) {
@@ -468,7 +468,7 @@ FSI_API int fsi_jacobian_apply(const fsi_problem *p, const void *x, void *y, voi
     int rc = check_problem(p);
     if (rc) return rc;
     FSI_CHECK_ARG(x && y, "x and y must be non-NULL");
-    FSI_CHECK_ARG(x != y, "x and y must not alias");
+    FSI_CHECK_ARG(x != y && p->a != y && p->s != y, "y must not alias x or the problem's a or s");
     const Geo g = make_geo(p->grid);
     const size_t need = problem_ws(p);
     if (ws == nullptr || ws_bytes < need) {
