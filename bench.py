@@ -39,8 +39,8 @@ PEAK_HBM_GBS = 8000.0
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads
 # for a plain 512 MiB device copy (FETCH_SIZE reads half the copied bytes, WRITE_SIZE all).
 # Valid only for the kernel sources it was taken on: the hash covers them.
-CELL_TRAFFIC = {"workload": "c5", "sources_sha256_16": "2c66fbfe7f8f326e", "fetch_kib": 379848.5, "write_kib": 352165.0,
-                "fetch_scale": 524288.0 / 262170.4375, "write_scale": 1.0}
+CELL_TRAFFIC = {"workload": "c5", "sources_sha256_16": "89bf0f9646c774fe", "fetch_kib": 379829.8, "write_kib": 352002.1,
+                "fetch_scale": 524288.0 / 262172.0625, "write_scale": 1.0}
 CELL_SOURCES = ("vms_q1.hip", "kernels.hpp", "common.hpp")
 
 
