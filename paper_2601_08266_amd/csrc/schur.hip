@@ -314,7 +314,7 @@ __global__ __launch_bounds__(256) void sc_vel_apply(int64_t N, const T *__restri
 }
 
 // ---- minimal-residual steps on the velocity block ----
-constexpr int MR_NB = 512;   // blocks of the dot-product pass
+constexpr int MR_NB = 2048;  // blocks of the dot-product pass (8 waves per SIMD)
 
 // r = v_u - yt_u (yt = J (0, z_p) in the block-triangular form, or nullptr)
 template <typename T, typename TV>
@@ -335,7 +335,21 @@ __global__ __launch_bounds__(256) void sc_mr_dots(int64_t n3, const T *__restric
 {
     __shared__ double sh[2][256];
     double qr = 0.0, qq = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (int64_t)gridDim.x * 256) {
+    // 16-byte loads (the vectors are 16-byte aligned workspace slices), then the tail
+    typedef T T16 __attribute__((ext_vector_type(16 / sizeof(T))));
+    constexpr int L = 16 / sizeof(T);
+    const int64_t nv = n3 / L, stride = (int64_t)gridDim.x * 256;
+    const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    for (int64_t i = i0; i < nv; i += stride) {
+        const T16 a = reinterpret_cast<const T16 *>(q)[i], b = reinterpret_cast<const T16 *>(r)[i];
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const double av = (double)a[l];
+            qr += av * (double)b[l];
+            qq += av * av;
+        }
+    }
+    for (int64_t i = nv * L + i0; i < n3; i += stride) {
         const double a = (double)q[i];
         qr += a * (double)r[i];
         qq += a * a;
