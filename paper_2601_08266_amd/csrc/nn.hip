@@ -257,7 +257,13 @@ __global__ __launch_bounds__(256) void conv_wgrad_k(int nx, int ny, int nz, int 
     __shared__ __attribute__((aligned(16))) uint16_t sdy[2][64 * WG_S];
     __shared__ __attribute__((aligned(16))) uint16_t sx[2][64 * WG_S];
     const int64_t V = (int64_t)nx * ny * nz;
-    const int r = blockIdx.x, tap = blockIdx.y;
+    // block -> (range, tap): the 27 taps of a voxel range are consecutive blocks of one XCD
+    // (blocks are dealt to the 8 XCDs round-robin), so the range's dY and input tiles come from
+    // that XCD's L2 after the first tap instead of from memory 27 times
+    const int xcd = blockIdx.x & 7, t2 = blockIdx.x >> 3;
+    const int tap = t2 % 27, r = (t2 / 27) * 8 + xcd;
+    const int nr = (int)((V + range - 1) / range);
+    if (r >= nr) return;
     const int co0 = blockIdx.z / ((cin + 63) / 64) * 64;
     const int ci0 = blockIdx.z % ((cin + 63) / 64) * 64;
     const int mco = cout - co0 < 64 ? cout - co0 : 64;
@@ -600,7 +606,8 @@ int nn_conv_wgrad(const int32_t *dims, int cin, int cout, const uint16_t *dY, co
     float *bpart = reinterpret_cast<float *>(reinterpret_cast<char *>(ws) +
                                              align_up((size_t)nr * 27 * cin * cout * sizeof(float)));
     const int groups = ((cout + 63) / 64) * ((cin + 63) / 64);
-    hipLaunchKernelGGL(conv_wgrad_k, dim3(nr, 27, groups), dim3(256), 0, st, dims[0], dims[1], dims[2], cin,
+    const unsigned nrt = (unsigned)(8 * 27 * ((nr + 7) / 8));   // (range, tap) blocks, ranges padded to 8
+    hipLaunchKernelGGL(conv_wgrad_k, dim3(nrt, 1, groups), dim3(256), 0, st, dims[0], dims[1], dims[2], cin,
                        cout, NN_WG_RANGE, dY, X, part);
     FSI_LAUNCH_CHECK();
     const int64_t nw = (int64_t)27 * cin * cout;
