@@ -10,14 +10,16 @@
 // Forward / data gradient (implicit GEMM): a block owns a brick of 8 x 8 x 4 voxels
 // x 64 output channels, each wave a 64-voxel z-slice of it x 64 channels (16
 // accumulator tiles).  Per 32-channel input chunk the brick's halo is staged in
-// LDS once and the 27 taps read shifted input fragments from it; each weight
-// fragment (loaded from memory two taps ahead) feeds 4 MFMAs and each input
-// fragment 4.  The data gradient is the same kernel on flipped, transposed
+// LDS once and the 27 taps read shifted input fragments from it; each tap's
+// weights are staged in LDS once per block (one load per thread, fetched a tap
+// ahead) and each weight fragment feeds 4 MFMAs, each input fragment 4.  The
+// products are weights x inputs, so a lane ends with 4 consecutive channels of
+// one voxel.  The data gradient is the same kernel on flipped, transposed
 // weights, with the ReLU mask of the previous layer applied in the epilogue.
 // Weight gradient (split K): block (voxel range, tap) stages 64 voxels of dY
 // and of the shifted input, transposed, in LDS and accumulates the 64x64 tap
-// block with 16 MFMA tiles; ranges are summed in a fixed order afterwards
-// (deterministic).
+// block with 16 MFMA tiles; the 27 tap blocks of a range run together on one
+// XCD; ranges are summed in a fixed order afterwards (deterministic).
 #include "nn.hpp"
 #include "profile.hpp"
 
