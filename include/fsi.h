@@ -206,7 +206,8 @@ int fsi_dlm_BT(const fsi_grid *grid, fsi_dtype dtype, int64_t m, const int32_t *
  * the library holds on each GPU it runs on until the process ends, of
  * fsi_dlm_BT_noalloc_max_bytes() bytes (32 MiB: up to 174,762 occupied Q1
  * cells in FP64, 349,525 in FP32).  Same arguments and result as fsi_dlm_BT
- * (bitwise: the same kernels); n_occ whose corner sums exceed the array ->
+ * in point order (perm non-NULL; bitwise: the same kernels); n_occ whose
+ * corner sums exceed the array ->
  * FSI_ERR_WORKSPACE before any device work.  It allocates nothing.  Calls that
  * overlap on one GPU (other streams or threads) share the array and race: keep
  * them in one stream order.
