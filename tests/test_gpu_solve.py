@@ -230,6 +230,30 @@ def test_residual_matches_oracle(case):
     assert err <= 1e-12
 
 
+def test_residual_weak_viscous_form():
+    """The step residual without the strong viscous term (visc_strong = 0) on the ragged
+    multi-brick grid, whole vector, FP64."""
+    import torch
+    import paper_2601_08266_amd as fsi
+    cfg, g, P, X, g_pts, u_old, mask, gD, x0 = _step_case("ragged")
+    N = g.num_nodes
+    rng = np.random.default_rng(19)
+    x = x0 + 0.01 * rng.standard_normal(x0.shape)
+    x[:3][mask] = gD[mask]
+    f = cfg.c_m * u_old
+    J = P["J64"]
+    Pw = fsi.Problem(g, fsi.make_params(cfg.nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I, visc_strong=False), J.a,
+                     J.tables, J.kappa, s=J.s, mask=J.mask, gram=J.gram)
+    lamg = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
+    fsi.dlm_BT(g, J.tables, _t(g_pts), lamg, kappa=_t(P["kappa"]))
+    R = fsi.vms_residual(Pw, _t(f), _t(x), gD=_t(gD), lamg=lamg).cpu().numpy()
+    ref = onewton.residual(g, P["prm_o"], x, u_old, P["cell"], P["xi"], P["kappa"], g_pts, s=P["s"],
+                           mask=mask, gD=gD, visc_strong=False).ravel()
+    err = field_rel_err(R, ref, 4)
+    print(f"residual weak viscous form: {err:.3e}")
+    assert err <= 1e-12
+
+
 @pytest.mark.parametrize("inner", ["f64", "f32"])
 def test_newton_c1_matches_dense_newton(inner):
     import torch

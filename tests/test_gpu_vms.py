@@ -90,6 +90,36 @@ def test_vms_q1_ragged_grids(dtype, n):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_vms_q1_weak_viscous_form(dtype):
+    """The operator without the strong viscous term in the stabilisation residuals
+    (visc_strong = 0, the kernel's other compiled variant) on a ragged multi-brick grid with s
+    and Dirichlet rows."""
+    import paper_2601_08266_amd as fsi
+    cfg = W.CONFIGS["c1"]
+    grid = W.Grid((11, 9, 6), 1, x0=(0.1, -0.2, 0.05), h=(0.07, 0.09, 0.11))
+    g, a, x, s, mask, t, prm_o, _ = setup_case(cfg, dtype, with_s=False, with_mask=True, grid=grid)
+    rng = np.random.default_rng(23)
+    s = rng.uniform(1.0, 100.0, size=grid.num_nodes)
+    if dtype == "f32":
+        s = s.astype(np.float32).astype(np.float64)
+    torch = _torch()
+    ts = torch.tensor(s, dtype=t["x"].dtype, device="cuda")
+    # a viscosity at which the strong viscous term matters (nu / h^2 comparable to c_m)
+    nu = 0.5
+    prm_o = ovms.params_array(nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I)
+    prm_w = fsi.make_params(nu, cfg.c_m, cfg.dt, cfg.C_T, cfg.C_I, visc_strong=False)
+    y = fsi.vms_apply(g, prm_w, t["a"], t["x"], s=ts, mask=t["mask"]).cpu().numpy()
+    ref = ovms.apply(g, prm_o, a, x, s=s, mask=mask, visc_strong=False)
+    err = field_rel_err(y, ref, 4)
+    # not vacuous: the strong form differs by far more than the bar
+    ref_s = ovms.apply(g, prm_o, a, x, s=s, mask=mask, visc_strong=True)
+    diff = field_rel_err(ref_s, ref, 4)
+    print(f"weak viscous form {dtype}: rel err {err:.3e} (strong vs weak {diff:.2e})")
+    assert err <= TOL[dtype]
+    assert diff > 100 * TOL["f32"]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_vms_q1_c2_sampled_rows(dtype):
     """Full 64^3 size, bench launch configuration; oracle recomputes sampled rows."""
     import paper_2601_08266_amd as fsi
