@@ -301,6 +301,24 @@ int fsi_jacobian_apply(const fsi_problem *problem, const void *x, void *y, void 
                        size_t ws_bytes, void *stream);
 
 /*
+ * fsi_jacobian_apply_block - the velocity rows of J on one block of the input, the
+ * products with J's sub-matrices that the block preconditioners of section 2.4 take
+ * (J = [[F, G], [D, C]], velocity rows first):
+ *   block FSI_BLOCK_F: y_u = F x_u          = [J (x_u, 0)]_u   (x_p is not read)
+ *   block FSI_BLOCK_G: y_u = G x_p          = [J (0, x_p)]_u   (x_u is not read; the DLM
+ *                                             block, a function of the velocity, adds nothing)
+ * x, y: T [4][N] device, as for fsi_jacobian_apply; only y's velocity part y[0..3N) is
+ * written, its pressure part is left as it was.  Dirichlet velocity rows: x_u (block F),
+ * 0 (block G).  Same workspace and aliasing rules as fsi_jacobian_apply.  Q1 grids only:
+ * FSI_ERR_UNSUPPORTED for Q2.  Deterministic; equal to the corresponding rows of
+ * fsi_jacobian_apply on the zero-padded input up to rounding order.
+ */
+#define FSI_BLOCK_F 1
+#define FSI_BLOCK_G 2
+int fsi_jacobian_apply_block(const fsi_problem *problem, int32_t block, const void *x, void *y,
+                             void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Hyperelastic solid block (section 2.4's C^lambda dR^s/dU (C^lambda)^T with the
  * solid's own tangent in place of the per-point stand-in kappa_B I).  The solid
  * weak form is section 2.2's eq. solid_weak_form, the material the nearly-

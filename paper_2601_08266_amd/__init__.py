@@ -22,7 +22,7 @@ from ._lib import (FSI_F32, FSI_F64, FsiError, FsiGrid, FsiNewtonOpts, FsiNewton
 __all__ = [
     "FSI_F64", "FSI_F32", "FsiError", "make_grid", "make_params", "version",
     "vms_apply_workspace", "vms_apply", "PointTables", "dlm_locate", "dlm_B", "dlm_BT", "dlm_B_located", "dlm_permute",
-    "Problem", "jacobian_apply", "jacobian_workspace", "dlm_gram", "profile_enable",
+    "Problem", "jacobian_apply", "jacobian_apply_block", "BLOCK_F", "BLOCK_G", "jacobian_workspace", "dlm_gram", "profile_enable",
     "profile_read", "vms_residual", "bjacobi_setup", "bjacobi_apply", "fgmres_solve",
     "schur_size", "schur_info", "schur_setup", "schur_apply", "PRECONDS", "tangent_apply",
     "newton_solve", "solve_opts", "newton_opts", "Solid", "solid_apply", "jacobian_solid_workspace",
@@ -357,6 +357,23 @@ def jacobian_apply(problem: Problem, x: torch.Tensor, y: Optional[torch.Tensor] 
     ws = _workspace(problem.workspace_bytes(), x.device, ws)
     L.check("fsi_jacobian_apply", L.lib().fsi_jacobian_apply(
         ctypes.byref(problem.struct), _ptr(x), _ptr(y), _ptr(ws), ws.numel(), _stream(stream)))
+    return y
+
+
+BLOCK_F, BLOCK_G = 1, 2
+
+
+def jacobian_apply_block(problem: Problem, block: int, x: torch.Tensor, y: Optional[torch.Tensor] = None,
+                         ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Velocity rows of J on one input block (fsi_jacobian_apply_block): block BLOCK_F gives
+    y_u = [J (x_u, 0)]_u, BLOCK_G gives y_u = [J (0, x_p)]_u; y's pressure part is not written."""
+    _need(x, "x", problem.dtype, 4 * problem.N)
+    if y is None:
+        y = torch.zeros_like(x)
+    _need(y, "y", problem.dtype, 4 * problem.N)
+    ws = _workspace(problem.workspace_bytes(), x.device, ws)
+    L.check("fsi_jacobian_apply_block", L.lib().fsi_jacobian_apply_block(
+        ctypes.byref(problem.struct), int(block), _ptr(x), _ptr(y), _ptr(ws), ws.numel(), _stream(stream)))
     return y
 
 

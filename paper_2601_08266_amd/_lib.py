@@ -132,6 +132,7 @@ SIGNATURES = {
                                           P, P, P, P]),
     "fsi_jacobian_workspace": (SZ, [ctypes.POINTER(FsiProblem)]),
     "fsi_jacobian_apply": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, P, SZ, P]),
+    "fsi_jacobian_apply_block": (ctypes.c_int, [ctypes.POINTER(FsiProblem), ctypes.c_int32, P, P, P, SZ, P]),
     "fsi_vms_residual": (ctypes.c_int, [ctypes.POINTER(FsiProblem), P, P, P, P, P, P, SZ, P]),
     "fsi_solid_setup": (ctypes.c_int, [I64, I64, P, P, P, P]),
     "fsi_solid_workspace": (SZ, [I64, ctypes.c_int]),

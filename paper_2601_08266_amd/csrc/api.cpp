@@ -110,8 +110,12 @@ size_t vms_workspace_bytes(const Geo &g, fsi_dtype dt)
 template <typename T>
 static int vms_apply_t(const Geo &g, const fsi_vms_params &prm, const T *a, const T *s,
                        const uint32_t *mask, const T *x, T *y, const DlmView *dlm, void *ws,
-                       hipStream_t st, const T *tstate = nullptr, const T *tsrc = nullptr)
+                       hipStream_t st, const T *tstate = nullptr, const T *tsrc = nullptr, int blk = 0)
 {
+    // blk: 0 the whole apply; 1, 2 the velocity rows on (x_u, 0) / (0, x_p) (Q1, Picard form)
+    if (blk != 0 && (g.p != 1 || tstate != nullptr)) return FSI_ERR_UNSUPPORTED;
+    // on (0, x_p) the DLM block (a function of the velocity only) adds nothing
+    if (blk == 2) dlm = nullptr;
     const BrickLayout bl = brick_layout(g);
     const VmsConst<T> k = make_vms_const<T>(g, prm, s != nullptr);
     T *part = reinterpret_cast<T *>(ws);
@@ -129,7 +133,9 @@ static int vms_apply_t(const Geo &g, const fsi_vms_params &prm, const T *a, cons
         if (tstate != nullptr)
             rc = launch_q1_tangent_fused<T>(g, k, tstate, tsrc, s, mask, gram, gidx, x, part, bl, st);
     }
-    if (tstate == nullptr || sizeof(T) == 8) {
+    if (blk != 0) {
+        rc = launch_q1_block<T>(g, k, blk, x, a, s, mask, gram, gidx, part, bl, st);
+    } else if (tstate == nullptr || sizeof(T) == 8) {
         if (g.p == 1)
             rc = launch_q1_cells<T>(g, k, x, a, s, mask, gram, gidx, part, bl, st, false);
         else
@@ -166,8 +172,9 @@ static int vms_apply_t(const Geo &g, const fsi_vms_params &prm, const T *a, cons
     GatherOpts<T> o;
     o.csum = csum;
     o.occ_index = csum ? dlm->occ_index : nullptr;
+    o.rows = blk != 0 ? 3 : 4;
     if (g.p == 1)
-        return launch_gather<T, 1, Q1_BX, Q1_BY, Q1_BZ>(g, part, bl, x, mask, y, o, st);
+        return launch_gather<T, 1, Q1_BX, Q1_BY, Q1_BZ>(g, part, bl, blk == 2 ? nullptr : x, mask, y, o, st);
     return launch_gather<T, 2, Q2_BX, Q2_BY, Q2_BZ>(g, part, bl, x, mask, y, o, st);
 }
 
@@ -233,6 +240,22 @@ int launch_vms_apply(const Geo &g, const fsi_vms_params &prm, fsi_dtype dt, cons
                                    (const double *)x, (double *)y, dlm, ws, st);
     return vms_apply_t<float>(g, prm, (const float *)a, (const float *)s, mask, (const float *)x,
                               (float *)y, dlm, ws, st);
+}
+
+int launch_vms_apply_block(const Geo &g, const fsi_vms_params &prm, fsi_dtype dt, int blk, const void *a,
+                           const void *s, const uint32_t *mask, const void *x, void *y, const DlmView *dlm,
+                           void *ws, hipStream_t st)
+{
+    if (blk != 1 && blk != 2) {
+        set_error("operator block %d (1: velocity on (u, 0), 2: velocity rows on (0, p))", blk);
+        return FSI_ERR_ARG;
+    }
+    if (g.p != 1) return FSI_ERR_UNSUPPORTED;
+    if (dt == FSI_F64)
+        return vms_apply_t<double>(g, prm, (const double *)a, (const double *)s, mask, (const double *)x,
+                                   (double *)y, dlm, ws, st, nullptr, nullptr, blk);
+    return vms_apply_t<float>(g, prm, (const float *)a, (const float *)s, mask, (const float *)x, (float *)y,
+                              dlm, ws, st, nullptr, nullptr, blk);
 }
 
 }  // namespace fsi
@@ -478,6 +501,30 @@ FSI_API int fsi_jacobian_apply(const fsi_problem *p, const void *x, void *y, voi
     const DlmView v = view_of(p);
     return launch_vms_apply(g, p->prm, p->dtype, p->a, p->s, p->dir_mask, x, y,
                             p->n_occ > 0 ? &v : nullptr, ws, ws_bytes, as_stream(stream));
+}
+
+FSI_API int fsi_jacobian_apply_block(const fsi_problem *p, int32_t block, const void *x, void *y, void *ws,
+                                     size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_problem(p);
+    if (rc) return rc;
+    FSI_CHECK_ARG(block == FSI_BLOCK_F || block == FSI_BLOCK_G, "block must be FSI_BLOCK_F or FSI_BLOCK_G");
+    FSI_CHECK_ARG(x && y, "x and y must be non-NULL");
+    FSI_CHECK_ARG(x != y && p->a != y && p->s != y, "y must not alias x or the problem's a or s");
+    const Geo g = make_geo(p->grid);
+    if (g.p != 1) {
+        set_error("the block products are implemented for Q1 grids");
+        return FSI_ERR_UNSUPPORTED;
+    }
+    const size_t need = problem_ws(p);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+        return FSI_ERR_WORKSPACE;
+    }
+    const DlmView v = view_of(p);
+    return launch_vms_apply_block(g, p->prm, p->dtype, block, p->a, p->s, p->dir_mask, x, y,
+                                  p->n_occ > 0 ? &v : nullptr, ws, as_stream(stream));
 }
 
 // ---- hyperelastic solid block ----
@@ -818,6 +865,11 @@ FSI_API int fsi_fgmres_solve(const fsi_problem *J64, const fsi_problem *J32, con
         return launch_vms_apply(g, J64->prm, FSI_F64, J64->a, J64->s, J64->dir_mask, xx, yy,
                                 J64->n_occ > 0 ? &v64 : nullptr, w, jw, s);
     }};
+    if (g.p == 1)
+        c64.block = [&](int blk, const void *xx, void *yy, void *w, hipStream_t s) {
+            return launch_vms_apply_block(g, J64->prm, FSI_F64, blk, J64->a, J64->s, J64->dir_mask, xx, yy,
+                                          J64->n_occ > 0 ? &v64 : nullptr, w, s);
+        };
     DlmView v32{};
     JacobianCall c32;
     if (o->inner == FSI_F32) {
@@ -826,6 +878,11 @@ FSI_API int fsi_fgmres_solve(const fsi_problem *J64, const fsi_problem *J32, con
             return launch_vms_apply(g, J32->prm, FSI_F32, J32->a, J32->s, J32->dir_mask, xx, yy,
                                     J32->n_occ > 0 ? &v32 : nullptr, w, jw, s);
         };
+        if (g.p == 1)
+            c32.block = [&](int blk, const void *xx, void *yy, void *w, hipStream_t s) {
+                return launch_vms_apply_block(g, J32->prm, FSI_F32, blk, J32->a, J32->s, J32->dir_mask, xx, yy,
+                                              J32->n_occ > 0 ? &v32 : nullptr, w, s);
+            };
     }
     Precond pc;
     const JacobianCall *Jin = o->inner == FSI_F32 ? &c32 : &c64;
@@ -920,6 +977,11 @@ FSI_API int fsi_schur_apply(const fsi_problem *J, int32_t mode, int32_t vel_step
         return launch_vms_apply(g, J->prm, J->dtype, J->a, J->s, J->dir_mask, xx, yy,
                                 J->n_occ > 0 ? &dv : nullptr, w, jw, s);
     }};
+    if (g.p == 1)
+        c.block = [&](int blk, const void *xx, void *yy, void *w, hipStream_t s) {
+            return launch_vms_apply_block(g, J->prm, J->dtype, blk, J->a, J->s, J->dir_mask, xx, yy,
+                                          J->n_occ > 0 ? &dv : nullptr, w, s);
+        };
     return schur_apply(g, J->dtype, false, mode == FSI_PC_SCHUR_DIAG ? 1 : 2, vel_steps, pc, v, z, &c, ws,
                        as_stream(stream));
 }

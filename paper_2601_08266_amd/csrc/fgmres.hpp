@@ -10,6 +10,10 @@ namespace fsi {
 // A bound Jacobian apply y = J x (x, y in the call's precision) with its workspace.
 struct JacobianCall {
     std::function<int(const void *x, void *y, void *ws, hipStream_t st)> apply;
+    // optional: velocity rows of the operator on one input block, blk = 1: (x_u, 0), blk = 2:
+    // (0, x_p) (the other block of x is not read; the pressure part of y is not written).  Empty
+    // where not available: callers then apply the whole operator to a zero-padded input.
+    std::function<int(int blk, const void *x, void *y, void *ws, hipStream_t st)> block;
 };
 
 // A bound preconditioner z = P^{-1} v: v is an FP64 [4][N] basis vector, z is written in the

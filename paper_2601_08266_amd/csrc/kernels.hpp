@@ -39,6 +39,7 @@ struct GatherOpts {
     const int32_t *occ_index = nullptr;
     const T *sub3 = nullptr;          // [3][N] subtracted from the momentum rows
     const T *gD = nullptr;            // [3][N]: Dirichlet rows become x - gD instead of x
+    int rows = 4;                     // 3: velocity rows only (three partial fields)
 };
 
 // Brick partial sums: bricks whose indices have equal parities (mod 2 per axis) share no
@@ -97,12 +98,25 @@ int launch_vms_apply(const Geo &g, const fsi_vms_params &prm, fsi_dtype dt, cons
                      const void *s, const uint32_t *mask, const void *x, void *y,
                      const DlmView *dlm, void *ws, size_t ws_bytes, hipStream_t st);
 
+// Velocity rows of the same apply for one input block: blk = 1: y_u = [J (x_u, 0)]_u (x_p not
+// read), blk = 2: y_u = [J (0, x_p)]_u (x_u not read, Dirichlet rows 0).  The pressure part of y
+// is not written.  Q1 only: FSI_ERR_UNSUPPORTED, with nothing launched, for Q2.
+int launch_vms_apply_block(const Geo &g, const fsi_vms_params &prm, fsi_dtype dt, int blk, const void *a,
+                           const void *s, const uint32_t *mask, const void *x, void *y, const DlmView *dlm,
+                           void *ws, hipStream_t st);
+
 size_t dlm_csum_bytes(const Geo &g, int64_t n_occ, fsi_dtype dt);
 
 template <typename T>
 int launch_q1_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, const T *s,
                     const uint32_t *mask, const T *gram, const int32_t *occ_index, T *part,
                     const BrickLayout &bl, hipStream_t st, bool resid);
+// Velocity rows of the Q1 apply on (x_u, 0) (blk = 1) or (0, x_p) (blk = 2): brick partials of
+// the three momentum fields (gather with rows = 3).
+template <typename T>
+int launch_q1_block(const Geo &g, const VmsConst<T> &k, int blk, const T *x, const T *a, const T *s,
+                    const uint32_t *mask, const T *gram, const int32_t *occ_index, T *part,
+                    const BrickLayout &bl, hipStream_t st);
 // Full-tangent correction (Q1): adds to the brick partials of a Picard apply with a = u the
 // derivative terms that the Picard operator drops, for state x = (u, p), source f and
 // velocity direction dv (Dirichlet entries of dv ignored).

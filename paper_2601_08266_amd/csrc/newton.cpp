@@ -198,6 +198,17 @@ int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, c
             return launch_vms_apply(g, J32.prm, FSI_F32, J32.a, J32.s, J32.dir_mask, xx, yy,
                                     J32.n_occ > 0 ? &v32 : nullptr, w, jws, s2);
         }};
+        if (g.p == 1) {
+            // the Schur preconditioner's products with the velocity and pressure-gradient blocks
+            c64.block = [&](int blk, const void *xx, void *yy, void *w, hipStream_t s2) {
+                return launch_vms_apply_block(g, J64.prm, FSI_F64, blk, J64.a, J64.s, J64.dir_mask, xx, yy,
+                                              J64.n_occ > 0 ? &v64 : nullptr, w, s2);
+            };
+            c32.block = [&](int blk, const void *xx, void *yy, void *w, hipStream_t s2) {
+                return launch_vms_apply_block(g, J32.prm, FSI_F32, blk, J32.a, J32.s, J32.dir_mask, xx, yy,
+                                              J32.n_occ > 0 ? &v32 : nullptr, w, s2);
+            };
+        }
         const JacobianCall *Jin = o.inner == FSI_F32 ? &c32 : &c64;
         const int mode = o.precond == FSI_PC_SCHUR_DIAG ? 1 : 2;
         Precond pc;

@@ -685,9 +685,16 @@ int apply_t(const Geo &g, const ScPlan &p, int mode, int vel_steps, char *base, 
     if (rc) return rc;
     const T *yt = nullptr;
     if (mode == 2) {
-        FSI_HIP(hipMemsetAsync(z, 0, (size_t)3 * N * sizeof(TZ), st));
+        // yt = velocity rows of J (0, z_p): the pressure-gradient block where the operator has
+        // one, else the whole operator on z with its velocity part cleared (z_u is written
+        // below without being read)
         T *y = reinterpret_cast<T *>(base + p.yt);
-        rc = J->apply(z, y, jws, st);
+        if (J->block) {
+            rc = J->block(2, z, y, jws, st);
+        } else {
+            FSI_HIP(hipMemsetAsync(z, 0, (size_t)3 * N * sizeof(TZ), st));
+            rc = J->apply(z, y, jws, st);
+        }
         if (rc) return rc;
         yt = y;
     }
@@ -708,12 +715,14 @@ int apply_t(const Geo &g, const ScPlan &p, int mode, int vel_steps, char *base, 
     const unsigned ub = (unsigned)std::min<int64_t>(blocks_for(n3), 4096);
     hipLaunchKernelGGL((sc_vel_resid<T, TV>), dim3(ub), dim3(256), 0, st, n3, v, yt, r);
     FSI_LAUNCH_CHECK();
-    FSI_HIP(hipMemsetAsync(xin + n3, 0, (size_t)N * sizeof(T), st));
+    // F xin = velocity rows of J (xin_u, 0): the velocity block where the operator has one, else
+    // the whole operator on xin with a zero pressure part
+    if (!J->block) FSI_HIP(hipMemsetAsync(xin + n3, 0, (size_t)N * sizeof(T), st));
     for (int it = 0; it < vel_steps; ++it) {
         hipLaunchKernelGGL((sc_vel_apply<T, T, T>), dim3(blocks_for(N)), dim3(256), 0, st, N, finv, r, (const T *)nullptr,
                            xin);
         FSI_LAUNCH_CHECK();
-        rc = J->apply(xin, q, jws, st);
+        rc = J->block ? J->block(1, xin, q, jws, st) : J->apply(xin, q, jws, st);
         if (rc) return rc;
         hipLaunchKernelGGL((sc_mr_dots<T>), dim3(MR_NB), dim3(256), 0, st, n3, q, r, part);
         FSI_LAUNCH_CHECK();

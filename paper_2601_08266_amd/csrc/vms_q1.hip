@@ -116,6 +116,19 @@ __device__ __forceinline__ void moments(T m[8], T F0, T G0, T G1, T G2, const QP
     m[7] = fma(G2, q.xy, fma(G1, q.xz, fma(G0, q.yz, fma(F0, q.xyz, m[7]))));
 }
 
+// the same with F0 = 0 (a test side that carries only gradient terms)
+template <typename T>
+__device__ __forceinline__ void moments_grad(T m[8], T G0, T G1, T G2, const QP<T> &q)
+{
+    m[1] += G0;
+    m[2] += G1;
+    m[3] = fma(G1, q.x, fma(G0, q.y, m[3]));
+    m[4] += G2;
+    m[5] = fma(G2, q.x, fma(G0, q.z, m[5]));
+    m[6] = fma(G2, q.y, fma(G1, q.z, m[6]));
+    m[7] = fma(G2, q.xy, fma(G1, q.xz, fma(G0, q.yz, m[7])));
+}
+
 // Buffer loads: one resource per field and block (base = the brick's first node), the
 // lane's node offset in a VGPR and the cell-corner offset, uniform, in an SGPR.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t field_rsrc(const void *base, int64_t bytes)
@@ -298,11 +311,14 @@ __device__ __forceinline__ QP<T> q1_point_sel(int q)
 // velocity and added to the momentum rows.  RESID = true: nonlinear residual of a time
 // step instead of the linear apply: the advection field is the velocity itself (a = u)
 // and the table holds the source f = c_m u_old + body force, whose Galerkin/SUPG/PSPG
-// weighting is subtracted.
-template <typename T, bool RESID, bool VS>
+// weighting is subtracted.  VB = true (apply only): the velocity rows of the operator applied
+// to (u, 0): the pressure coefficients are not read and the continuity row is not formed.
+template <typename T, bool RESID, bool VS, bool VB = false>
 __device__ __forceinline__ void q1_cell(const VmsConst<T> &k, T cu[4][8], const T *lq,
                                         const T *__restrict__ dlm, T out[4][8])
 {
+    static_assert(!(RESID && VB), "the velocity block is a part of the linear apply");
+    constexpr int NI = VB ? 3 : 4;   // input fields used, output rows formed
     T mom[4][8];
 #pragma unroll
     for (int f = 0; f < 4; ++f)
@@ -314,7 +330,7 @@ __device__ __forceinline__ void q1_cell(const VmsConst<T> &k, T cu[4][8], const 
         const QP<T> q0 = q1_point_sel<T>(2 * pr);
         T E[4], O[4];
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
+        for (int f = 0; f < NI; ++f) {
             const T *c = cu[f];
             E[f] = c[0] + c[2] * q0.y + c[4] * q0.z + c[6] * q0.yz;
             O[f] = c[1] + c[3] * q0.y + c[5] * q0.z + c[7] * q0.yz;
@@ -336,8 +352,13 @@ __device__ __forceinline__ void q1_cell(const VmsConst<T> &k, T cu[4][8], const 
                 dU[i][1] = mdy(cu[i], q);
                 dU[i][2] = mdz(cu[i], q);
             }
-            const T P = E[3] + q.x * O[3];
-            const T dP[3] = {O[3], mdy(cu[3], q), mdz(cu[3], q)};
+            T P = T(0), dP[3] = {T(0), T(0), T(0)};
+            if constexpr (!VB) {
+                P = E[3] + q.x * O[3];
+                dP[0] = O[3];
+                dP[1] = mdy(cu[3], q);
+                dP[2] = mdz(cu[3], q);
+            }
             T Fs[3] = {T(0), T(0), T(0)};
             if constexpr (RESID) {
 #pragma unroll
@@ -367,10 +388,18 @@ __device__ __forceinline__ void q1_cell(const VmsConst<T> &k, T cu[4][8], const 
                 T gm = k.c_m * U[i] + (Ah[0] * dU[i][0] + Ah[1] * dU[i][1] + Ah[2] * dU[i][2]);
                 if constexpr (RESID) gm -= Fs[i];
                 F0[i] = gm;
-                const T r = (gm + dP[i] * k.ih[i]) - ngd[i];
+                T r;
+                if constexpr (VB)
+                    r = gm - ngd[i];
+                else
+                    r = (gm + dP[i] * k.ih[i]) - ngd[i];
                 tr[i] = tau_m * r;
             }
-            const T diag = tau_c * div - P;
+            T diag;
+            if constexpr (VB)
+                diag = tau_c * div;
+            else
+                diag = tau_c * div - P;
             // test-side fluxes, already multiplied by 1/h_k:
             //   nu (d_k u_i + d_i u_k) + a_k tau_m r_i + delta_ik (tau_c div u - p)
 #pragma unroll
@@ -387,12 +416,12 @@ __device__ __forceinline__ void q1_cell(const VmsConst<T> &k, T cu[4][8], const 
                 }
                 moments(mom[i], F0[i], G[0], G[1], G[2], q);
             }
-            moments(mom[3], div, tr[0] * k.ih[0], tr[1] * k.ih[1], tr[2] * k.ih[2], q);
+            if constexpr (!VB) moments(mom[3], div, tr[0] * k.ih[0], tr[1] * k.ih[1], tr[2] * k.ih[2], q);
         }
     }
     const T W = k.detJ * T(0.125);
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < NI; ++f) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) mom[f][i] *= W;
         from_moments(mom[f]);
@@ -413,6 +442,54 @@ __device__ __forceinline__ void q1_cell(const VmsConst<T> &k, T cu[4][8], const 
                 out[2][A] += gAC * cu[2][C];
             }
         }
+    }
+}
+
+// Velocity rows of the operator applied to (0, p): with u = 0 the momentum residual is the
+// pressure gradient, div u = 0, and the Galerkin, viscous and DLM terms vanish, so per Gauss
+// point the momentum test w carries -p div w + ((a.grad) w) . tau_m grad p.  cp: the pressure in
+// monomial form; lq: the apply's point table (a/h, tau_m, tau_c).
+template <typename T>
+__device__ __forceinline__ void q1_cell_grad_p(const VmsConst<T> &k, const T cp[8], const T *lq, T out[3][8])
+{
+    T mom[3][8];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) mom[f][i] = T(0);
+
+#pragma unroll 1
+    for (int pr = 0; pr < 4; ++pr) {
+        const QP<T> q0 = q1_point_sel<T>(2 * pr);
+        const T E = cp[0] + cp[2] * q0.y + cp[4] * q0.z + cp[6] * q0.yz;
+        const T O = cp[1] + cp[3] * q0.y + cp[5] * q0.z + cp[7] * q0.yz;
+#pragma unroll
+        for (int ix = 0; ix < 2; ++ix) {
+            const int qi = 2 * pr + ix;
+            const QP<T> q = q1_point_sel<T>(qi);
+            const T *lp = lq + Q1_NQV * qi * Q1_NT;
+            const T Ah[3] = {lp[0], lp[Q1_NT], lp[2 * Q1_NT]};
+            const T tau_m = lp[3 * Q1_NT];
+            const T P = E + q.x * O;
+            const T dP[3] = {O, mdy(cp, q), mdz(cp, q)};
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const T tr = tau_m * (dP[i] * k.ih[i]);
+                T G[3];
+#pragma unroll
+                for (int kk = 0; kk < 3; ++kk) G[kk] = kk == i ? -P * k.ih[i] + Ah[kk] * tr : Ah[kk] * tr;
+                moments_grad(mom[i], G[0], G[1], G[2], q);
+            }
+        }
+    }
+    const T W = k.detJ * T(0.125);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) mom[f][i] *= W;
+        from_moments(mom[f]);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) out[f][i] = mom[f][i];
     }
 }
 
@@ -655,7 +732,9 @@ __device__ __forceinline__ uint32_t xcd_brick(uint32_t bid, uint32_t nb)
 // 2: full-tangent correction: x = state (u, p), `a` = source f, dv = velocity direction; the
 // result is added to the brick partials that the Picard apply (MODE 0 with a = u) wrote;
 // 3: the whole full-Newton tangent in one pass: x = state, `a` = source f, dv = direction
-// (velocity and pressure), gram = the per-cell DLM blocks; the partials are overwritten.
+// (velocity and pressure), gram = the per-cell DLM blocks; the partials are overwritten;
+// 4: velocity rows of the apply on (x_u, 0) (x_p is not read); 5: velocity rows of the apply on
+// (0, x_p) (x_u is not read, no DLM block).  Modes 4 and 5 write three partial fields.
 template <typename T, int MODE, bool VS = true>
 __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, const T *__restrict__ x,
                                                     const T *__restrict__ a,
@@ -666,8 +745,10 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
                                                     T *__restrict__ part, int nbx, int nby,
                                                     const T *__restrict__ dv)
 {
-    constexpr bool RESID = MODE != 0;
-    constexpr bool DIR = MODE >= 2;   // a direction next to the state
+    constexpr bool RESID = MODE >= 1 && MODE <= 3;
+    constexpr bool DIR = MODE == 2 || MODE == 3;   // a direction next to the state
+    constexpr bool XU = MODE != 5, XP = MODE != 4;   // velocity / pressure of x read
+    constexpr int NO = MODE >= 4 ? 3 : 4;            // output rows
     // LDS, one region used three ways: the brick's nodal fields (staged with coalesced
     // loads), then the lanes' Gauss-point tables, then the lanes' nodal outputs.
     constexpr int NF = MODE == 3 ? 12 : (MODE == 2 ? 11 : 8);   // x (4), a or f (3), s (, dv (3 or 4))
@@ -707,6 +788,7 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
         T v[NF][NJ];
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
+            if ((f < 3 && !XU) || (f == 3 && !XP)) continue;
             if (f == 7 && !k.has_s) {
 #pragma unroll
                 for (int j = 0; j < NJ; ++j) v[f][j] = T(1);
@@ -717,7 +799,7 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
 #pragma unroll
             for (int j = 0; j < NJ; ++j) v[f][j] = buf_load<T>(r, voff[j], 0u);
         }
-        if (MODE != 1 && mask != nullptr) {
+        if (MODE != 1 && MODE != 5 && mask != nullptr) {
             // Dirichlet columns: the apply's x, the tangent's direction
             constexpr int F0 = DIR ? 8 : 0;
 #pragma unroll
@@ -727,10 +809,12 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
                     if (inb[j] && mask_bit(mask, f * N + node[j])) v[F0 + f][j] = T(0);
         }
 #pragma unroll
-        for (int f = 0; f < NF; ++f)
+        for (int f = 0; f < NF; ++f) {
+            if ((f < 3 && !XU) || (f == 3 && !XP)) continue;
 #pragma unroll
             for (int j = 0; j < NJ; ++j)
                 if (t + Q1_NT * j < Q1_NL) lds[f * Q1_NL + t + Q1_NT * j] = inb[j] ? v[f][j] : T(0);
+        }
     }
     __syncthreads();
 
@@ -742,7 +826,7 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
         for (int A = 0; A < 8; ++A) {
             const int l = (tx + (A & 1)) + LX * ((ty + ((A >> 1) & 1)) + LY * (tz + (A >> 2)));
 #pragma unroll
-            for (int f = 0; f < 4; ++f) cu[f][A] = lds[f * Q1_NL + l];
+            for (int f = 0; f < 4; ++f) cu[f][A] = (f < 3 ? XU : XP) ? lds[f * Q1_NL + l] : T(0);
 #pragma unroll
             for (int d = 0; d < 3; ++d) ca[d][A] = lds[(4 + d) * Q1_NL + l];
             cs[A] = k.has_s ? lds[7 * Q1_NL + l] : T(1);
@@ -757,7 +841,7 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
     if (valid) {
         q1_point_table<T, RESID>(k, cu, ca, cs, lds + t);
         const T *dlm = nullptr;
-        if (gram != nullptr) {
+        if (MODE != 5 && gram != nullptr) {
             const int32_t ko = occ_index[cx + (int64_t)g.n[0] * (cy + (int64_t)g.n[1] * cz)];
             if (ko >= 0) dlm = gram + (int64_t)ko * 64;
         }
@@ -768,15 +852,17 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
                 q1_fused_tangent_cell<T>(k, cu, cd, lds + t, dlm, out);
             else
                 q1_tangent_cell<T>(k, cu, cd, lds + t, out);
+        } else if constexpr (MODE == 5) {
+            q1_cell_grad_p<T>(k, cu[3], lds + t, out);
         } else {
-            q1_cell<T, RESID, VS>(k, cu, lds + t, dlm, out);
+            q1_cell<T, RESID, VS, MODE == 4>(k, cu, lds + t, dlm, out);
         }
     }
     // element -> node accumulation: every lane parks its 32 nodal outputs in LDS, then each
     // brick node sums the corners of the (up to 8) cells around it in a fixed order
     __syncthreads();
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
+    for (int f = 0; f < NO; ++f)
 #pragma unroll
         for (int A = 0; A < 8; ++A) lds[(f * 8 + A) * Q1_NT + t] = valid ? out[f][A] : T(0);
     __syncthreads();
@@ -800,7 +886,7 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
                         const int A = (1 - i) + 2 * (1 - j) + 4 * (1 - kk);
                         const int lane = cxl + Q1_BX * (cyl + Q1_BY * czl);
 #pragma unroll
-                        for (int f = 0; f < 4; ++f) sum[f] += lds[(f * 8 + A) * Q1_NT + lane];
+                        for (int f = 0; f < NO; ++f) sum[f] += lds[(f * 8 + A) * Q1_NT + lane];
                     }
                 }
             }
@@ -813,7 +899,7 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
                 for (int f = 0; f < 4; ++f) pc[f * pi.field] += sum[f];
             } else {
 #pragma unroll
-                for (int f = 0; f < 4; ++f) pc[f * pi.field] = sum[f];
+                for (int f = 0; f < NO; ++f) pc[f * pi.field] = sum[f];
             }
         }
     }
@@ -824,8 +910,9 @@ __global__ __launch_bounds__(Q1_NT) void vms_q1_cells(Geo g, VmsConst<T> k, cons
 // Node gather shared by all orders: sums the brick partials (bricks of BXxBYxBZ cells of
 // order P; part holds one x-packed [4][nn2][nn1][lx] array per brick parity class, so the
 // reads are coalesced and dense) and, optionally, DLM corner sums of occupied neighbour
-// cells; then Dirichlet rows.
-template <typename T, int P, int BX, int BY, int BZ>
+// cells; then Dirichlet rows.  NR = 3: only the velocity rows (partials of three fields; the
+// pressure part of y is not written).
+template <typename T, int P, int BX, int BY, int BZ, int NR = 4>
 __global__ __launch_bounds__(256) void vms_gather(Geo g, const T *__restrict__ part, int nbx,
                                                   int nby, int nbz, const T *__restrict__ x,
                                                   const uint32_t *__restrict__ mask,
@@ -871,7 +958,7 @@ __global__ __launch_bounds__(256) void vms_gather(Geo g, const T *__restrict__ p
                     const int cls = (bxs[ix] & 1) + 2 * (bys[iy] & 1) + 4 * (bzs[iz] & 1);
                     const T *pc = part + pi.at(cls, bxs[ix], gx, gy, gz);
 #pragma unroll
-                    for (int f = 0; f < 4; ++f) pv[iz][iy][ix][f] = pc[f * pi.field];
+                    for (int f = 0; f < NR; ++f) pv[iz][iy][ix][f] = pc[f * pi.field];
                 }
 #pragma unroll
     for (int iz = 0; iz < 2; ++iz)
@@ -881,7 +968,7 @@ __global__ __launch_bounds__(256) void vms_gather(Geo g, const T *__restrict__ p
             for (int ix = 0; ix < 2; ++ix)
                 if (iz < nzb && iy < nyb && ix < nxb) {
 #pragma unroll
-                    for (int f = 0; f < 4; ++f) acc[f] += pv[iz][iy][ix][f];
+                    for (int f = 0; f < NR; ++f) acc[f] += pv[iz][iy][ix][f];
                 }
     if (csum != nullptr) {
         // cells containing the node along each axis: c with P c <= g <= P c + P
@@ -910,12 +997,13 @@ __global__ __launch_bounds__(256) void vms_gather(Geo g, const T *__restrict__ p
                 }
     }
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < NR; ++f) {
         T v = acc[f];
         if (f < 3 && o.sub3 != nullptr) v -= o.sub3[f * g.N + node];
         if (f < 3 && mask_bit(mask, f * g.N + node)) {
-            // Dirichlet rows: identity (apply) or u - g_D (residual)
-            v = x[f * g.N + node];
+            // Dirichlet rows: identity (apply; on a zero velocity when x is NULL) or u - g_D
+            // (residual)
+            v = x != nullptr ? x[f * g.N + node] : T(0);
             if (o.gD != nullptr) v -= o.gD[f * g.N + node];
         }
         y[f * g.N + node] = v;
@@ -952,6 +1040,38 @@ int launch_q1_cells(const Geo &g, const VmsConst<T> &k, const T *x, const T *a, 
     FSI_LAUNCH_CHECK();
     return FSI_OK;
 }
+
+// Velocity rows of the apply on (x_u, 0) (blk = 1) or on (0, x_p) (blk = 2): brick partials of
+// the three momentum fields.
+template <typename T>
+int launch_q1_block(const Geo &g, const VmsConst<T> &k, int blk, const T *x, const T *a, const T *s,
+                    const uint32_t *mask, const T *gram, const int32_t *occ_index, T *part,
+                    const BrickLayout &bl, hipStream_t st)
+{
+    FSI_CHECK_ARG((int64_t)g.nn[0] * g.nn[1] * (Q1_BZ + 1) * (int64_t)sizeof(T) < ((int64_t)1 << 31),
+                  "Q1 grid planes too large (%d x %d nodes)", g.nn[0], g.nn[1]);
+    FSI_CHECK_ARG(blk == 1 || blk == 2, "operator block %d (1: velocity, 2: pressure gradient)", blk);
+    ProfileScope prof(blk == 1 ? "vms_q1_block_u" : "vms_q1_block_p", st);
+    const dim3 grid((unsigned)bl.nb), block(Q1_NT);
+    const T *nod = nullptr;
+    if (blk == 2)
+        hipLaunchKernelGGL((vms_q1_cells<T, 5>), grid, block, 0, st, g, k, x, a, s, mask, gram, occ_index, part,
+                           bl.nbx, bl.nby, nod);
+    else if (k.visc_strong)
+        hipLaunchKernelGGL((vms_q1_cells<T, 4, true>), grid, block, 0, st, g, k, x, a, s, mask, gram, occ_index,
+                           part, bl.nbx, bl.nby, nod);
+    else
+        hipLaunchKernelGGL((vms_q1_cells<T, 4, false>), grid, block, 0, st, g, k, x, a, s, mask, gram, occ_index,
+                           part, bl.nbx, bl.nby, nod);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+template int launch_q1_block<double>(const Geo &, const VmsConst<double> &, int, const double *, const double *,
+                                     const double *, const uint32_t *, const double *, const int32_t *, double *,
+                                     const BrickLayout &, hipStream_t);
+template int launch_q1_block<float>(const Geo &, const VmsConst<float> &, int, const float *, const float *,
+                                    const float *, const uint32_t *, const float *, const int32_t *, float *,
+                                    const BrickLayout &, hipStream_t);
 
 template <typename T>
 int launch_q1_tangent(const Geo &g, const VmsConst<T> &k, const T *x, const T *f, const T *s,
@@ -999,8 +1119,12 @@ int launch_gather(const Geo &g, const T *part, const BrickLayout &bl, const T *x
                   "grid too large for the node gather (%d x %d x %d nodes)", g.nn[0], g.nn[1], g.nn[2]);
     const unsigned blocks = (unsigned)(((int64_t)g.nn[0] * g.nn[1] + 255) / 256);
     ProfileScope prof("vms_gather", st);
-    hipLaunchKernelGGL((vms_gather<T, P, BX, BY, BZ>), dim3(blocks, (unsigned)g.nn[2]), dim3(256), 0, st, g, part,
-                       bl.nbx, bl.nby, bl.nbz, x, mask, y, o);
+    if (o.rows == 3)
+        hipLaunchKernelGGL((vms_gather<T, P, BX, BY, BZ, 3>), dim3(blocks, (unsigned)g.nn[2]), dim3(256), 0, st, g,
+                           part, bl.nbx, bl.nby, bl.nbz, x, mask, y, o);
+    else
+        hipLaunchKernelGGL((vms_gather<T, P, BX, BY, BZ>), dim3(blocks, (unsigned)g.nn[2]), dim3(256), 0, st, g,
+                           part, bl.nbx, bl.nby, bl.nbz, x, mask, y, o);
     FSI_LAUNCH_CHECK();
     return FSI_OK;
 }
