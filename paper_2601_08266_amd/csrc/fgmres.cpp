@@ -232,7 +232,9 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
                     }
                     ProfileScope pa("fgmres_apply", st);
                     TRY(J32->apply(Zj, t32b, jws, st));
-                    TRY(kry_cast_f32_f64(n, t32b, w64, st));
+                    // the fused Gram-Schmidt passes read the FP32 product and widen it as they
+                    // go; the unfused ones take it widened
+                    if (j + 1 > KRY_FUSED_MAXK) TRY(kry_cast_f32_f64(n, t32b, w64, st));
                 } else {
                     {
                         ProfileScope pp("fgmres_precond", st);
@@ -249,7 +251,10 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
                 double *d_ab = hdev, *d_h = hdev + 2 * (m + 1), *d_hn = hdev + 3 * (m + 1);
                 {
                     ProfileScope po("fgmres_orth", st);
-                    if (j + 1 <= KRY_FUSED_MAXK) {
+                    if (j + 1 <= KRY_FUSED_MAXK && inner == FSI_F32) {
+                        TRY(kry_cgs_project_f32w(n, j + 1, V, n, t32b, Vj, partial, d_ab, Gdev, m + 1, d_h, st));
+                        TRY(kry_axpy_norm_f32w(n, j + 1, V, n, d_h, t32b, w64, partial, d_hn, st));
+                    } else if (j + 1 <= KRY_FUSED_MAXK) {
                         TRY(kry_cgs_project(n, j + 1, V, n, w64, Vj, partial, d_ab, Gdev, m + 1, d_h, st));
                         TRY(kry_axpy_norm(n, j + 1, V, n, d_h, w64, partial, d_hn, st));
                     } else {

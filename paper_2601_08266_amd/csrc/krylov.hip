@@ -33,9 +33,9 @@ __global__ __launch_bounds__(KT) void scale_k(int64_t n, double alpha, const dou
         y[i] = alpha * x[i];
 }
 
-// out = x * s, s = 1 / dev[0] computed on the device side
-__global__ __launch_bounds__(KT) void scale_inv_k(int64_t n, const double *__restrict__ x,
-                                                  const double *__restrict__ dev, double *__restrict__ out)
+// out = x * s, s = 1 / dev[0] computed on the device side (out may be x)
+__global__ __launch_bounds__(KT) void scale_inv_k(int64_t n, const double *x, const double *__restrict__ dev,
+                                                  double *out)
 {
     const double s = 1.0 / dev[0];
     for (int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x; i < n; i += (int64_t)gridDim.x * KT)
@@ -258,13 +258,22 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// two consecutive entries as FP64 (w in FP64, or the FP32 product of the inner precision,
+// widened exactly)
+__device__ __forceinline__ double2 load2(const double *p) { return *reinterpret_cast<const double2 *>(p); }
+__device__ __forceinline__ double2 load2(const float *p)
+{
+    const float2 v = *reinterpret_cast<const float2 *>(p);
+    return make_double2((double)v.x, (double)v.y);
+}
+
 // Projection pass of classical Gram-Schmidt with re-orthogonalisation through the Gram matrix:
 // per-block partials of V[k] . w and V[k] . u (u = V[nk-1], the newest basis vector), k < nk, in
 // one read of V: wave wv of a block takes the vectors k = wv + 4q, q < KQ = ceil(nk / 4), and
 // issues their loads together (past nk the last vector is re-read and not accumulated).
-template <int KQ>
+template <int KQ, typename TW>
 __global__ __launch_bounds__(KT) void cgs_project_k(int64_t n, int nk, const double *__restrict__ V,
-                                                    int64_t ldv, const double *__restrict__ w,
+                                                    int64_t ldv, const TW *__restrict__ w,
                                                     const double *__restrict__ u,
                                                     double *__restrict__ partial)
 {
@@ -284,7 +293,7 @@ __global__ __launch_bounds__(KT) void cgs_project_k(int64_t n, int nk, const dou
 #pragma unroll
     for (int q = 0; q < KQ; ++q) aw[q] = au[q] = 0.0;
     for (int64_t i = lo + 2 * lane; i < hi; i += 128) {
-        const double2 wi = *reinterpret_cast<const double2 *>(w + i);
+        const double2 wi = load2(w + i);
         const double2 ui = *reinterpret_cast<const double2 *>(u + i);
         double2 v[KQ];
 #pragma unroll
@@ -309,11 +318,12 @@ __global__ __launch_bounds__(KT) void cgs_project_k(int64_t n, int nk, const dou
     }
 }
 
-// w -= V h (nk vectors, in groups of 8 whose loads are issued together) and per-block partials
-// of ||w||^2 (new w).
+// out = w - V h (nk vectors, in groups of 8 whose loads are issued together) and per-block
+// partials of ||out||^2; out may be w itself (TW = double).
+template <typename TW>
 __global__ __launch_bounds__(KT) void axpy_norm_k(int64_t n, int nk, const double *__restrict__ V,
                                                   int64_t ldv, const double *__restrict__ h,
-                                                  double *__restrict__ w, double *__restrict__ partial)
+                                                  const TW *w, double *out, double *__restrict__ partial)
 {
     constexpr int KB = 8;
     __shared__ double red[CG_WAVES];
@@ -323,7 +333,7 @@ __global__ __launch_bounds__(KT) void axpy_norm_k(int64_t n, int nk, const doubl
     const int64_t hi = lo + chunk < n ? lo + chunk : n;
     double acc = 0.0;
     for (int64_t i = lo + 2 * threadIdx.x; i < hi; i += 2 * KT) {
-        double2 s = *reinterpret_cast<const double2 *>(w + i);
+        double2 s = load2(w + i);
         for (int k0 = 0; k0 < nk; k0 += KB) {
             double2 v[KB];
             double hk[KB];
@@ -340,7 +350,7 @@ __global__ __launch_bounds__(KT) void axpy_norm_k(int64_t n, int nk, const doubl
                 s.y -= hk[q] * v[q].y;
             }
         }
-        *reinterpret_cast<double2 *>(w + i) = s;
+        *reinterpret_cast<double2 *>(out + i) = s;
         acc += s.x * s.x;
         acc += s.y * s.y;
     }
@@ -449,18 +459,19 @@ int kry_multidot2(int64_t n, int nk, const double *V, int64_t ldv, const double 
     return FSI_OK;
 }
 
-int kry_cgs_project(int64_t n, int nk, const double *V, int64_t ldv, const double *w, const double *u,
-                    double *partial, double *ab, double *G, int ldg, double *h, hipStream_t st)
+template <typename TW>
+static int cgs_project_t(int64_t n, int nk, const double *V, int64_t ldv, const TW *w, const double *u,
+                         double *partial, double *ab, double *G, int ldg, double *h, hipStream_t st)
 {
-    if ((n | ldv) & 1 || ((uintptr_t)V | (uintptr_t)w | (uintptr_t)u) & 15) {
-        set_error("CGS projection needs even lengths and 16-byte aligned vectors");
+    if ((n | ldv) & 1 || ((uintptr_t)V | (uintptr_t)u) & 15 || (uintptr_t)w & (2 * sizeof(TW) - 1)) {
+        set_error("CGS projection needs even lengths and aligned vectors");
         return FSI_ERR_ARG;
     }
     switch ((nk + CG_WAVES - 1) / CG_WAVES) {
 #define FSI_CGS_CASE(KQ)                                                                           \
     case KQ:                                                                                       \
-        hipLaunchKernelGGL(cgs_project_k<KQ>, dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, w, u,   \
-                           partial);                                                               \
+        hipLaunchKernelGGL((cgs_project_k<KQ, TW>), dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, w, \
+                           u, partial);                                                            \
         break;
         FSI_CGS_CASE(1) FSI_CGS_CASE(2) FSI_CGS_CASE(3) FSI_CGS_CASE(4) FSI_CGS_CASE(5)
         FSI_CGS_CASE(6) FSI_CGS_CASE(7) FSI_CGS_CASE(8) FSI_CGS_CASE(9) FSI_CGS_CASE(10)
@@ -478,18 +489,43 @@ int kry_cgs_project(int64_t n, int nk, const double *V, int64_t ldv, const doubl
     return FSI_OK;
 }
 
-int kry_axpy_norm(int64_t n, int nk, const double *V, int64_t ldv, const double *h, double *w,
-                  double *partial, double *out, hipStream_t st)
+int kry_cgs_project(int64_t n, int nk, const double *V, int64_t ldv, const double *w, const double *u,
+                    double *partial, double *ab, double *G, int ldg, double *h, hipStream_t st)
 {
-    if ((n | ldv) & 1 || ((uintptr_t)V | (uintptr_t)w) & 15) {
-        set_error("CGS update needs even lengths and 16-byte aligned vectors");
+    return cgs_project_t<double>(n, nk, V, ldv, w, u, partial, ab, G, ldg, h, st);
+}
+
+int kry_cgs_project_f32w(int64_t n, int nk, const double *V, int64_t ldv, const float *w, const double *u,
+                         double *partial, double *ab, double *G, int ldg, double *h, hipStream_t st)
+{
+    return cgs_project_t<float>(n, nk, V, ldv, w, u, partial, ab, G, ldg, h, st);
+}
+
+template <typename TW>
+static int axpy_norm_t(int64_t n, int nk, const double *V, int64_t ldv, const double *h, const TW *w,
+                       double *wout, double *partial, double *out, hipStream_t st)
+{
+    if ((n | ldv) & 1 || ((uintptr_t)V | (uintptr_t)wout) & 15 || (uintptr_t)w & (2 * sizeof(TW) - 1)) {
+        set_error("CGS update needs even lengths and aligned vectors");
         return FSI_ERR_ARG;
     }
-    hipLaunchKernelGGL(axpy_norm_k, dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, h, w, partial);
+    hipLaunchKernelGGL((axpy_norm_k<TW>), dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, h, w, wout, partial);
     FSI_LAUNCH_CHECK();
     hipLaunchKernelGGL(reduce_partials_k, dim3(1), dim3(KT), 0, st, 1, KRY_NB, partial, out, 1);
     FSI_LAUNCH_CHECK();
     return FSI_OK;
+}
+
+int kry_axpy_norm(int64_t n, int nk, const double *V, int64_t ldv, const double *h, double *w,
+                  double *partial, double *out, hipStream_t st)
+{
+    return axpy_norm_t<double>(n, nk, V, ldv, h, w, w, partial, out, st);
+}
+
+int kry_axpy_norm_f32w(int64_t n, int nk, const double *V, int64_t ldv, const double *h, const float *w,
+                       double *wout, double *partial, double *out, hipStream_t st)
+{
+    return axpy_norm_t<float>(n, nk, V, ldv, h, w, wout, partial, out, st);
 }
 
 int kry_gram_coeffs(int nk, const double *ab, double *G, int ldg, double *h, hipStream_t st)

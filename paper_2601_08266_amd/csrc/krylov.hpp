@@ -33,6 +33,12 @@ int kry_cgs_project(int64_t n, int nk, const double *V, int64_t ldv, const doubl
 // w -= V h and out[0] = ||w||
 int kry_axpy_norm(int64_t n, int nk, const double *V, int64_t ldv, const double *h, double *w,
                   double *partial, double *out, hipStream_t st);
+// the same two passes on a w given in FP32 (the inner-precision product, widened exactly as it
+// is read): the projection reads it, the update writes w - V h to wout in FP64
+int kry_cgs_project_f32w(int64_t n, int nk, const double *V, int64_t ldv, const float *w, const double *u,
+                         double *partial, double *ab, double *G, int ldg, double *h, hipStream_t st);
+int kry_axpy_norm_f32w(int64_t n, int nk, const double *V, int64_t ldv, const double *h, const float *w,
+                       double *wout, double *partial, double *out, hipStream_t st);
 int kry_update(int64_t n, int nk, fsi_dtype dz, const void *Z, int64_t ldz, const double *y, double *x,
                hipStream_t st);
 
