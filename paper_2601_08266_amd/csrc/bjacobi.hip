@@ -3,13 +3,16 @@
 // the nodal (u,v,w,p) diagonal blocks are the simplest such choice).
 //
 //  bj_qp    one lane per (cell, quadrature point): advection, s (clamped), tau_m
-//           and tau_c at the point -> a small per-point table.
+//           and tau_c at the point -> a small per-point table, stored value- and
+//           point-major ([5][nq][E]) so that lanes on consecutive cells read and write
+//           consecutive entries.
 //  bj_node  one lane per node: sums, over the (up to 8) cells holding the node and
 //           their quadrature points, the node's own 4x4 entries of the element
 //           matrix (same terms as the operator), adds the diagonal of the DLM block
 //           (gram[o][A][A] kappa N_A^2 sums) of occupied neighbour cells, replaces
 //           Dirichlet rows/columns by the identity, and inverts the block in FP64
-//           (Gauss-Jordan with partial pivoting).  No atomics: deterministic.
+//           (Gauss-Jordan with partial pivoting) when an inverse is asked for.  No
+//           atomics in the sums: deterministic.
 //  bj_apply z = P^{-1} v, one lane per node, blocks stored [16][N].
 #include "bjacobi.hpp"
 #include "profile.hpp"
@@ -54,7 +57,7 @@ __device__ __forceinline__ void basis1d(int a, double t, double &n, double &d, d
     }
 }
 
-// per-point table: a0 a1 a2 tau_m tau_c
+// per-point table: a0 a1 a2 tau_m tau_c; entry f of point q of cell e at tab[(f NQ3 + q) E + e]
 template <int P>
 __global__ __launch_bounds__(256) void bj_qp(Geo g, VmsConst<double> k, const double *__restrict__ a,
                                              const double *__restrict__ s, double *__restrict__ tab)
@@ -62,9 +65,11 @@ __global__ __launch_bounds__(256) void bj_qp(Geo g, VmsConst<double> k, const do
     constexpr int Q = P + 1, NQ = Rule<P>::NQ, NQ3 = NQ * NQ * NQ;
     const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (id >= g.E * NQ3) return;
-    const int64_t e = id / NQ3;
-    const int q = (int)(id % NQ3);
-    const int cx = (int)(e % g.n[0]), cy = (int)((e / g.n[0]) % g.n[1]), cz = (int)(e / ((int64_t)g.n[0] * g.n[1]));
+    const int q = (int)(id / g.E);
+    const int64_t e = id - (int64_t)q * g.E;
+    const int64_t row = e / g.n[0];   // one 64-bit division, the rest in 32 bits
+    const int cx = (int)(e - row * g.n[0]), cy = (int)((uint32_t)row % (uint32_t)g.n[1]),
+              cz = (int)((uint32_t)row / (uint32_t)g.n[1]);
     const double t[3] = {Rule<P>::pt(q % NQ), Rule<P>::pt((q / NQ) % NQ), Rule<P>::pt(q / (NQ * NQ))};
     double A[3] = {0.0, 0.0, 0.0}, S = 0.0, smin = 0.0;
     bool first = true;
@@ -88,12 +93,12 @@ __global__ __launch_bounds__(256) void bj_qp(Geo g, VmsConst<double> k, const do
     else S = S < smin ? smin : S;
     const double tb = S * (k.K1 + A[0] * A[0] * k.ih2[0] + A[1] * A[1] * k.ih2[1] + A[2] * A[2] * k.ih2[2]);
     const double sq = sqrt(tb);
-    double *o = tab + id * 5;
-    o[0] = A[0];
-    o[1] = A[1];
-    o[2] = A[2];
-    o[3] = 1.0 / sq;
-    o[4] = sq * k.inv_trG;
+    const int64_t fs = (int64_t)NQ3 * g.E;   // stride between the table's values
+    tab[id] = A[0];
+    tab[id + fs] = A[1];
+    tab[id + 2 * fs] = A[2];
+    tab[id + 3 * fs] = 1.0 / sq;
+    tab[id + 4 * fs] = sq * k.inv_trG;
 }
 
 // 4x4 inverse, Gauss-Jordan with partial pivoting; returns false if singular
@@ -163,6 +168,8 @@ __global__ __launch_bounds__(256) void bj_node(Geo g, VmsConst<double> k, const 
             for (int ix = 0; ix < nc[0]; ++ix) {
                 const int64_t cell = cs[0][ix] + (int64_t)g.n[0] * (cs[1][iy] + (int64_t)g.n[1] * cs[2][iz]);
                 const int la[3] = {as[0][ix], as[1][iy], as[2][iz]};
+                // points not unrolled: unrolled, the trilinear case needs 262 registers (1 wave)
+#pragma unroll 1
                 for (int q = 0; q < NQ3; ++q) {
                     const int qi[3] = {q % NQ, (q / NQ) % NQ, q / (NQ * NQ)};
                     double n1[3], d1[3], dd1[3];
@@ -185,9 +192,10 @@ __global__ __launch_bounds__(256) void bj_node(Geo g, VmsConst<double> k, const 
                             }
                             H[i][j] = v;
                         }
-                    const double *tq = tab + (cell * NQ3 + q) * 5;
-                    const double A[3] = {tq[0], tq[1], tq[2]};
-                    const double tau_m = tq[3], tau_c = tq[4];
+                    const int64_t fs = (int64_t)NQ3 * g.E;
+                    const double *tq = tab + (int64_t)q * g.E + cell;
+                    const double A[3] = {tq[0], tq[fs], tq[2 * fs]};
+                    const double tau_m = tq[3 * fs], tau_c = tq[4 * fs];
                     const double adN = A[0] * dN[0] + A[1] * dN[1] + A[2] * dN[2];
                     const double lap = H[0][0] + H[1][1] + H[2][2];
                     const double gg = dN[0] * dN[0] + dN[1] * dN[1] + dN[2] * dN[2];
@@ -231,9 +239,10 @@ __global__ __launch_bounds__(256) void bj_node(Geo g, VmsConst<double> k, const 
             }
     if (raw != nullptr)
         for (int i = 0; i < 16; ++i) raw[(int64_t)i * g.N + node] = Bk[i / 4][i % 4];
+    if (pinv64 == nullptr && pinv32 == nullptr && nsing == nullptr) return;   // the blocks only
     double R[4][4];
     if (!inv4(Bk, R)) {
-        atomicAdd(nsing, 1);
+        if (nsing != nullptr) atomicAdd(nsing, 1);
         for (int i = 0; i < 4; ++i)
             for (int j = 0; j < 4; ++j) R[i][j] = (i == j) ? 1.0 : 0.0;
     }
@@ -280,7 +289,11 @@ int launch_bjacobi_setup(const Geo &g, const fsi_vms_params &prm, const double *
     double *tab = reinterpret_cast<double *>(ws);
     int32_t *cnt = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(ws) +
                                                align_up((size_t)g.E * nq * 5 * sizeof(double)));
-    FSI_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t), st));
+    // the singular-block count is kept only when it is asked for (or an inverse is)
+    if (n_singular != nullptr || pinv64 != nullptr || pinv32 != nullptr)
+        FSI_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t), st));
+    else
+        cnt = nullptr;
     const unsigned b1 = (unsigned)((g.E * nq + 255) / 256);
     const unsigned b2 = (unsigned)((g.N + 255) / 256);
     if (g.p == 1) {

@@ -479,8 +479,9 @@ __global__ __launch_bounds__(256) void sc_dmask0(Geo g, const uint32_t *__restri
     const int64_t node = (int64_t)blockIdx.x * 256 + threadIdx.x;
     int flag = 0;
     if (node < g.N) {
-        const int gv[3] = {(int)(node % g.nn[0]), (int)((node / g.nn[0]) % g.nn[1]),
-                           (int)(node / ((int64_t)g.nn[0] * g.nn[1]))};
+        const int64_t row = node / g.nn[0];   // one 64-bit division, the rest in 32 bits
+        const int gv[3] = {(int)(node - row * g.nn[0]), (int)((uint32_t)row % (uint32_t)g.nn[1]),
+                           (int)((uint32_t)row / (uint32_t)g.nn[1])};
         bool bnd = false;
         for (int d = 0; d < 3; ++d) bnd = bnd || gv[d] == 0 || gv[d] == g.nn[d] - 1;
         const bool all = mask_bit(mask, node) && mask_bit(mask, g.N + node) && mask_bit(mask, 2 * g.N + node);
@@ -762,6 +763,11 @@ int sc_plan(const Geo &g, ScPlan &p)
             v.l[d] = l[d];
             v.N *= v.nn[d];
             v.C *= v.nc[d];
+        }
+        if (v.N >= ((int64_t)1 << 31)) {   // the level kernels index nodes in 32 bits
+            set_error("the Schur preconditioner supports fewer than 2^31 lattice nodes (got %lld)",
+                      (long long)v.N);
+            return FSI_ERR_ARG;
         }
         const double vol = l[0] * l[1] * l[2];
         for (int pat = 0; pat < 8; ++pat) {

@@ -33,7 +33,7 @@ IN_CH = 8
 
 
 class LearnedWarmStart:
-    def __init__(self, run: ChannelRun, hidden=64, n_hidden=8, seed=0, line_search=True):
+    def __init__(self, run: ChannelRun, hidden=64, n_hidden=2, seed=0, line_search=True):
         self.run = run
         self.line_search = line_search
         self.last_step = 1.0
