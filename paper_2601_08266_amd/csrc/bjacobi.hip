@@ -137,6 +137,54 @@ __device__ __forceinline__ bool inv4(double M[4][4], double R[4][4])
     return true;
 }
 
+// One Gauss point's contribution to a node's 4x4 block on a trilinear cell (the general
+// formulas below with what vanishes for trilinear shape functions taken out: no second
+// derivative along a single axis, so the Laplacian of the shape function is zero and its
+// Hessian is the symmetric off-diagonal mixed derivatives; the velocity-velocity part is then
+// symmetric off the diagonal).  la: the node's corner in the cell, q: the point.
+__device__ __forceinline__ void node_q1_point(const VmsConst<double> &k, const double *__restrict__ tab,
+                                              int64_t E, int64_t cell, int q, const int la[3], double Bk[4][4])
+{
+    double n1[3], d1[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double t = Rule<1>::pt((q >> d) & 1);
+        n1[d] = la[d] == 0 ? 1.0 - t : t;
+        d1[d] = (la[d] == 0 ? -1.0 : 1.0) * k.ih[d];   // physical derivative of the 1D factor
+    }
+    const double W = k.detJ * 0.125;
+    const double N = n1[0] * n1[1] * n1[2];
+    const double dN[3] = {d1[0] * n1[1] * n1[2], n1[0] * d1[1] * n1[2], n1[0] * n1[1] * d1[2]};
+    const double H01 = d1[0] * d1[1] * n1[2], H02 = d1[0] * d1[2] * n1[1], H12 = d1[1] * d1[2] * n1[0];
+    const int64_t fs = 8 * E;
+    const double *tq = tab + (int64_t)q * E + cell;
+    const double A0 = tq[0], A1 = tq[fs], A2 = tq[2 * fs];
+    const double tau_m = tq[3 * fs], tau_c = tq[4 * fs];
+    const double nu = k.nu, c_m = k.c_m;
+    const double adN = A0 * dN[0] + A1 * dN[1] + A2 * dN[2];
+    const double gg = dN[0] * dN[0] + dN[1] * dN[1] + dN[2] * dN[2];
+    const double nt = nu + tau_c, tma = tau_m * adN, rr = c_m * N + adN;
+    const double D = c_m * N * N + N * adN + nu * gg + tma * rr;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Bk[i][i] += W * (nt * dN[i] * dN[i] + D);
+    // off the diagonal: nu and tau_c grad-grad terms, the SUPG-weighted strong viscous term
+    const double vs = k.visc_strong ? nu : 0.0;
+    const double o01 = W * (nt * dN[0] * dN[1] - tma * vs * H01);
+    const double o02 = W * (nt * dN[0] * dN[2] - tma * vs * H02);
+    const double o12 = W * (nt * dN[1] * dN[2] - tma * vs * H12);
+    Bk[0][1] += o01; Bk[1][0] += o01;
+    Bk[0][2] += o02; Bk[2][0] += o02;
+    Bk[1][2] += o12; Bk[2][1] += o12;
+    // pressure column (Galerkin -div w p, SUPG) and row (continuity, PSPG)
+    const double hv[3] = {dN[1] * H01 + dN[2] * H02, dN[0] * H01 + dN[2] * H12, dN[0] * H02 + dN[1] * H12};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        Bk[i][3] += W * (dN[i] * (tma - N));
+        Bk[3][i] += W * (N * dN[i] + tau_m * (dN[i] * rr - vs * hv[i]));
+    }
+    Bk[3][3] += W * tau_m * gg;
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void bj_node(Geo g, VmsConst<double> k, const double *__restrict__ tab,
                                                const uint32_t *__restrict__ mask,
@@ -171,6 +219,10 @@ __global__ __launch_bounds__(256) void bj_node(Geo g, VmsConst<double> k, const 
                 // points not unrolled: unrolled, the trilinear case needs 262 registers (1 wave)
 #pragma unroll 1
                 for (int q = 0; q < NQ3; ++q) {
+                    if constexpr (P == 1) {
+                        node_q1_point(k, tab, g.E, cell, q, la, Bk);
+                        continue;
+                    }
                     const int qi[3] = {q % NQ, (q / NQ) % NQ, q / (NQ * NQ)};
                     double n1[3], d1[3], dd1[3];
                     double W = k.detJ;

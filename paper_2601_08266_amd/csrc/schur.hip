@@ -764,11 +764,6 @@ int sc_plan(const Geo &g, ScPlan &p)
             v.N *= v.nn[d];
             v.C *= v.nc[d];
         }
-        if (v.N >= ((int64_t)1 << 31)) {   // the level kernels index nodes in 32 bits
-            set_error("the Schur preconditioner supports fewer than 2^31 lattice nodes (got %lld)",
-                      (long long)v.N);
-            return FSI_ERR_ARG;
-        }
         const double vol = l[0] * l[1] * l[2];
         for (int pat = 0; pat < 8; ++pat) {
             double s = 0.0;
