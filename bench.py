@@ -39,8 +39,8 @@ PEAK_HBM_GBS = 8000.0
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads
 # for a plain 512 MiB device copy (FETCH_SIZE reads half the copied bytes, WRITE_SIZE all).
 # Valid only for the kernel sources it was taken on: the hash covers them.
-CELL_TRAFFIC = {"workload": "c5", "sources_sha256_16": "89bf0f9646c774fe", "fetch_kib": 379829.8, "write_kib": 352002.1,
-                "fetch_scale": 524288.0 / 262172.0625, "write_scale": 1.0}
+CELL_TRAFFIC = {"workload": "c5", "sources_sha256_16": "97e17f3a7b1ed8d9", "fetch_kib": 379826.6, "write_kib": 351971.9,
+                "fetch_scale": 524288.0 / 262171.5625, "write_scale": 1.0}
 CELL_SOURCES = ("vms_q1.hip", "kernels.hpp", "common.hpp")
 
 
@@ -348,6 +348,39 @@ def time_applies(fsi, torch, case, steps, warmup, profile, kernels=("vms_q1_cell
             kern[name] = (tot / n if n else 0.0, n)
         fsi.profile_enable(False)
     return ms, wall / steps * 1e3, kern
+
+
+def time_blocks(fsi, torch, case, steps, warmup):
+    """The Schur preconditioner's block products on the same problem: velocity rows of J on
+    (x_u, 0) (block F) and on (0, x_p) (block G), `steps` back-to-back calls each, then the same
+    again with the library's per-kernel events (cell pass and three-row gather)."""
+    prob, x, y, ws = case["prob"], case["x"], case["y"], case["ws"]
+    out = {}
+    for name, blk, cell in (("F", fsi.BLOCK_F, "vms_q1_block_u"), ("G", fsi.BLOCK_G, "vms_q1_block_p")):
+        def call():
+            fsi.jacobian_apply_block(prob, blk, x, y, ws)
+        for _ in range(warmup):
+            call()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(steps):
+            call()
+        stop.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / steps
+        fsi.profile_enable(True)
+        for _ in range(steps):
+            call()
+        torch.cuda.synchronize()
+        kern = {}
+        for k in (cell, "vms_gather"):
+            tot, n = fsi.profile_read(k)
+            kern[k] = round(tot / n, 6) if n else 0.0
+        fsi.profile_enable(False)
+        out[name] = {"us": round(ms * 1e3, 2), "kernels_ms": kern}
+    return out
 
 
 def time_cold(torch, case, reps=20):
@@ -666,6 +699,8 @@ def main(argv=None):
     pw["ws"] = torch.empty(pw["prob"].workspace_bytes(), dtype=torch.uint8, device=dev)
     ms_pw, _, kern_pw = time_applies(fsi, torch, pw, args.steps, args.warmup, profile=False)
     del pw
+    blocks = {"f64": time_blocks(fsi, torch, case64, args.steps, args.warmup),
+              "f32": time_blocks(fsi, torch, case32, args.steps, args.warmup)} if g.order == 1 else None
 
     resident = 4 * N * 8 * 4 < 256e6
     cold64 = time_cold(torch, case64) if resident else None
@@ -718,6 +753,9 @@ def main(argv=None):
             # blocks, which are built once per point set (dlm_gram) and reused by every apply
             "pointwise_dlm_gdofs_f64": round(4 * N / (ms_pw * 1e-3) / 1e9, 4),
             "pointwise_dlm_ms_per_step_f64": round(ms_pw, 6),
+            # the preconditioner's products with the velocity block F and the pressure-gradient
+            # block G (velocity rows of J on (x_u, 0) and on (0, x_p))
+            "block_products": blocks,
             "locate_ms": round(case64["locate_ms"], 3),
             "dlm_gram_ms": round(case64["gram_ms"], 3),
             "dlm_gram_in_applies": round(case64["gram_ms"] / ms64, 3),

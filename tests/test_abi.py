@@ -86,3 +86,23 @@ def test_solid_entry_points_reject_bad_arguments_without_gpu():
     s.C0 = float("nan")
     rc = lib.fsi_solid_apply(ctypes.byref(s), 0, None, 1.0, 1.0, 1.0, None, None, None, 0, None)
     assert rc == L.FSI_ERR_ARG and b"finite" in lib.fsi_last_error()
+
+
+def test_block_products_reject_bad_arguments_without_gpu():
+    # host-only checks of fsi_jacobian_apply_block: a block id other than F (1) or G (2), and a Q2
+    # grid, are rejected before any device work (the pointers below are never dereferenced)
+    import paper_2601_08266_amd as fsi
+    import paper_2601_08266_amd._lib as L
+    lib = L.lib()
+    p = L.FsiProblem()
+    p.grid = fsi.make_grid((8, 8, 8), 1)
+    p.prm = fsi.make_params(0.01, 1000.0, 1e-3, 4.0, 36.0)
+    p.dtype = L.FSI_F64
+    p.a = 16
+    x, y = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+    assert lib.fsi_jacobian_apply_block(ctypes.byref(p), 3, x, y, None, 0, None) == L.FSI_ERR_ARG
+    assert b"FSI_BLOCK_F" in lib.fsi_last_error()
+    assert lib.fsi_jacobian_apply_block(ctypes.byref(p), fsi.BLOCK_G, x, x, None, 0, None) == L.FSI_ERR_ARG
+    p.grid = fsi.make_grid((4, 4, 4), 2)
+    assert lib.fsi_jacobian_apply_block(ctypes.byref(p), fsi.BLOCK_F, x, y, None, 0, None) == L.FSI_ERR_UNSUPPORTED
+    assert b"Q1" in lib.fsi_last_error()
