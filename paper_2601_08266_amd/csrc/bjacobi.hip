@@ -57,13 +57,22 @@ __device__ __forceinline__ void basis1d(int a, double t, double &n, double &d, d
     }
 }
 
+// Block index -> position in the lattice: blocks are dealt to the 8 XCDs round-robin, and each
+// XCD is given a contiguous range of positions, so the neighbouring rows and planes that one
+// block's lanes and the next blocks share are read under the same L2.
+__device__ __forceinline__ uint32_t xcd_range(uint32_t bid, uint32_t nb)
+{
+    const uint32_t q = nb >> 3, r = nb & 7u, xcd = bid & 7u, idx = bid >> 3;
+    return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
 // per-point table: a0 a1 a2 tau_m tau_c; entry f of point q of cell e at tab[(f NQ3 + q) E + e]
 template <int P>
 __global__ __launch_bounds__(256) void bj_qp(Geo g, VmsConst<double> k, const double *__restrict__ a,
                                              const double *__restrict__ s, double *__restrict__ tab)
 {
     constexpr int Q = P + 1, NQ = Rule<P>::NQ, NQ3 = NQ * NQ * NQ;
-    const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t id = (int64_t)xcd_range(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     if (id >= g.E * NQ3) return;
     const int q = (int)(id / g.E);
     const int64_t e = id - (int64_t)q * g.E;
@@ -194,7 +203,7 @@ __global__ __launch_bounds__(256) void bj_node(Geo g, VmsConst<double> k, const 
                                                float *__restrict__ pinv32, int32_t *__restrict__ nsing)
 {
     constexpr int Q = P + 1, NQ = Rule<P>::NQ, NQ3 = NQ * NQ * NQ, NEN = Q * Q * Q;
-    const int64_t node = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t node = (int64_t)xcd_range(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     if (node >= g.N) return;
     const int gv[3] = {(int)(node % g.nn[0]), (int)((node / g.nn[0]) % g.nn[1]),
                        (int)(node / ((int64_t)g.nn[0] * g.nn[1]))};
