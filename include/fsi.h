@@ -592,11 +592,15 @@ typedef struct {
     int32_t restart, max_krylov;
     fsi_dtype inner;          /* inner precision of the Krylov cycles */
     double inner_reduction;
-    int32_t precond;          /* fsi_precond: block-Jacobi (0) or a Schur form, rebuilt per iteration */
+    int32_t precond;          /* fsi_precond: block-Jacobi (0) or a Schur form (see pc_reuse) */
     int32_t vel_steps;        /* Schur forms: minimal-residual steps on the velocity block */
     int32_t tangent;          /* 0: Picard/Oseen J(u_k); 1: full Newton tangent (fsi_tangent_apply) */
     double *host_ring;        /* passed to every FGMRES solve (fsi_solve_opts), or NULL */
     int64_t host_ring_len;
+    int32_t pc_reuse;         /* 0: the preconditioner is rebuilt at every Newton iterate; 1: it is
+                                 built at the first iterate of the call and reused (a lagged
+                                 preconditioner: FGMRES accepts any preconditioner, the operator
+                                 stays J(u_k), so only the Krylov counts can change) */
 } fsi_newton_opts;
 
 typedef struct {

@@ -588,7 +588,7 @@ def fgmres_solve(J64: Problem, b: torch.Tensor, x: torch.Tensor, opts: FsiSolveO
 
 def newton_opts(tol_abs, max_newton=20, eta=1e-3, restart=50, max_krylov=2000,
                 inner=torch.float32, inner_reduction=1e-5, precond="bjacobi", vel_steps=0,
-                tangent="picard", pinned=True) -> FsiNewtonOpts:
+                tangent="picard", pinned=True, pc_reuse=False) -> FsiNewtonOpts:
     o = FsiNewtonOpts()
     o.max_newton, o.tol_abs, o.eta = int(max_newton), float(tol_abs), float(eta)
     o.restart, o.max_krylov = int(restart), int(max_krylov)
@@ -597,6 +597,7 @@ def newton_opts(tol_abs, max_newton=20, eta=1e-3, restart=50, max_krylov=2000,
     o.precond = _precond_code(precond)
     o.vel_steps = int(vel_steps)
     o.tangent = {"picard": 0, "full": 1}[tangent] if isinstance(tangent, str) else int(tangent)
+    o.pc_reuse = 1 if pc_reuse else 0
     _attach_host_ring(o, restart, pinned)
     return o
 

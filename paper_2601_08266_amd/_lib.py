@@ -73,7 +73,8 @@ class FsiNewtonOpts(ctypes.Structure):
                 ("max_krylov", ctypes.c_int32), ("inner", ctypes.c_int),
                 ("inner_reduction", ctypes.c_double), ("precond", ctypes.c_int32),
                 ("vel_steps", ctypes.c_int32), ("tangent", ctypes.c_int32),
-                ("host_ring", ctypes.c_void_p), ("host_ring_len", ctypes.c_int64)]
+                ("host_ring", ctypes.c_void_p), ("host_ring_len", ctypes.c_int64),
+                ("pc_reuse", ctypes.c_int32)]
 
 
 class FsiNewtonStats(ctypes.Structure):

@@ -1003,6 +1003,7 @@ static int check_newton(const fsi_problem *P64, const fsi_problem *P32, const fs
                   "unknown preconditioner %d", (int)o->precond);
     FSI_CHECK_ARG(o->vel_steps >= 0 && o->vel_steps <= 16, "vel_steps must be in [0, 16]");
     FSI_CHECK_ARG(o->tangent == 0 || o->tangent == 1, "tangent must be 0 (Picard) or 1 (full)");
+    FSI_CHECK_ARG(o->pc_reuse == 0 || o->pc_reuse == 1, "pc_reuse must be 0 or 1");
     if (o->precond != FSI_PC_BJACOBI) {
         ScPlan sp;
         rc = sc_plan(make_geo(P64->grid), sp);

@@ -151,13 +151,15 @@ int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, c
         fsi_problem J64 = P64;
         J64.a = x;
         const double *gram64 = J64.n_occ > 0 ? (const double *)J64.dlm_gram : nullptr;
-        if (schur) {
+        // the preconditioner at u_k, or (pc_reuse) the one built at the call's first iterate
+        const bool build_pc = it == 0 || !o.pc_reuse;
+        if (build_pc && schur) {
             rc = launch_bjacobi_setup(g, J64.prm, x, (const double *)J64.s, J64.dir_mask, gram64, J64.occ_index,
                                       blocks, nullptr, nullptr, nullptr, bjws, st);
             if (rc) break;
             rc = schur_setup(g, J64.prm, x, (const double *)J64.s, J64.dir_mask, gram64, J64.occ_index, blocks,
                              pcobj, st);
-        } else {
+        } else if (build_pc) {
             rc = launch_bjacobi_setup(g, J64.prm, x, (const double *)J64.s, J64.dir_mask, gram64, J64.occ_index,
                                       nullptr, pinv64, o.inner == FSI_F32 ? pinv32 : nullptr, nullptr, bjws,
                                       st);

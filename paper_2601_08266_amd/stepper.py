@@ -59,11 +59,12 @@ class StepRecord:
 class ChannelRun:
     def __init__(self, cfg, device="cuda", inner=torch.float32, eta=1e-3, restart=50,
                  rel_tol=1e-8, period=0.8, amp_deg=20.0, max_krylov=4000, precond="bjacobi",
-                 integrator="be", rho_inf=0.5, vel_steps=0, tangent="picard"):
+                 integrator="be", rho_inf=0.5, vel_steps=0, tangent="picard", pc_reuse=False):
         self.cfg = cfg
         self.precond = precond
         self.vel_steps = vel_steps
         self.tangent = tangent
+        self.pc_reuse = pc_reuse   # build the preconditioner once per step (at the guess) and reuse it
         # time integrator: backward Euler, or generalized-alpha (section 2.4) in stage variables:
         # the stage residual at t_n + alpha_f dt is the backward-Euler-form residual with mass
         # coefficient alpha_m / (gamma dt alpha_f) and source c V_n - (1 - alpha_m/gamma) Vdot_n;
@@ -187,7 +188,7 @@ class ChannelRun:
         return out
 
     def step(self, guess_fn: Optional[Callable] = None, inner=None, record=True, precond=None, vel_steps=None,
-             tangent=None):
+             tangent=None, pc_reuse=None):
         """Advance one step.  guess_fn(run, ctx) -> FP64 [4][N] guess or None; ctx holds the
         step's FP64 problem, lamg, the inflow value, s and the extrapolated guess with its
         residual (x_ex, R_ex, rn_ex; None before two states exist)."""
@@ -244,7 +245,8 @@ class ChannelRun:
                            max_krylov=self.max_krylov, inner=inner,
                            precond=precond if precond is not None else self.precond,
                            vel_steps=vel_steps if vel_steps is not None else self.vel_steps,
-                           tangent=tangent if tangent is not None else self.tangent)
+                           tangent=tangent if tangent is not None else self.tangent,
+                           pc_reuse=pc_reuse if pc_reuse is not None else self.pc_reuse)
         x_new = x0.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -130,8 +130,12 @@ def test_fgmres_with_schur_c1_matches_dense_lu(mode, inner):
     assert err <= 1e-6
 
 
-@pytest.mark.parametrize("mode", ["schur_diag", "schur_tri"])
-def test_newton_with_schur_c1_matches_dense_newton(mode):
+@pytest.mark.parametrize("mode,pc_reuse", [("schur_diag", False), ("schur_tri", False), ("schur_tri", True),
+                                           ("bjacobi", True)])
+def test_newton_with_schur_c1_matches_dense_newton(mode, pc_reuse):
+    """Newton with the Schur (or block-Jacobi) preconditioner rebuilt at every iterate, or built at
+    the first iterate and reused (pc_reuse): the same converged state as the oracle's dense
+    Newton, within the common residual tolerance."""
     import torch
     import paper_2601_08266_amd as fsi
     cfg = W.CONFIGS["c1"]
@@ -149,12 +153,12 @@ def test_newton_with_schur_c1_matches_dense_newton(mode):
     lamg = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
     fsi.dlm_BT(g, P["J64"].tables, _t(g_pts), lamg, kappa=_t(kappa))
     x = _t(x0)
-    opts = fsi.newton_opts(tol_abs=tol, inner=torch.float32, precond=mode)
+    opts = fsi.newton_opts(tol_abs=tol, inner=torch.float32, precond=mode, pc_reuse=pc_reuse)
     rc, st = fsi.newton_solve(P["J64"], _t(cfg.c_m * u_old), x, opts, P32=P["J32"], lamg=lamg, gD=_t(gD))
     xs = x.cpu().numpy()
     R = onewton.residual(g, P["prm_o"], xs, u_old, P["cell"], P["xi"], kappa, g_pts, s=P["s"],
                          mask=mask, gD=gD)
-    print(f"newton c1 {mode}: {st.newton_iters} Newton / {st.krylov_iters} Krylov, {st.t_total_ms:.1f} ms, "
+    print(f"newton c1 {mode} reuse={pc_reuse}: {st.newton_iters} Newton / {st.krylov_iters} Krylov, {st.t_total_ms:.1f} ms, "
           f"oracle ||R|| {np.linalg.norm(R):.3e} (tol {tol:.3e})")
     assert np.linalg.norm(R) <= tol * 1.01
     assert np.linalg.norm(xs - x_ref.ravel()) <= 1e-6 * np.linalg.norm(x_ref)
