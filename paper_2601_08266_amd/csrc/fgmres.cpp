@@ -77,7 +77,7 @@ size_t fgmres_workspace_bytes(int64_t ndof, int restart, fsi_dtype inner, size_t
 
 int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32, const Precond *pc,
                  const double *b, double *x, const fsi_solve_opts &o, fsi_solve_stats *stats,
-                 void *ws, size_t jws_bytes, hipStream_t st)
+                 void *ws, size_t jws_bytes, hipStream_t st, bool x_zero)
 {
     ProfileScope prof("fgmres_solve", st);
     const auto t_start = std::chrono::steady_clock::now();
@@ -145,16 +145,23 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
         TRY(events.create(m));
         std::vector<hipEvent_t> &ev = events.ev;
         for (;;) {
-            // true residual r = b - J64 x in FP64 (stored in V[0])
-            {
-                ProfileScope pr("fgmres_residual", st);
-                TRY(J64.apply(x, w64, jws, st));
-                FSI_HIP(hipMemcpyAsync(V, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
-                TRY(kry_axpby(n, -1.0, w64, 1.0, V, st));
-            }
+            // true residual r = b - J64 x in FP64 (stored in V[0]); b itself while x is still the
+            // zero the caller guaranteed (then its norm is the one already computed)
             double beta = 0.0;
-            TRY(kry_norm(n, V, partial, hdev, st));
-            TRY(fetch(&beta, hdev, 1));
+            if (x_zero && S.cycles == 0) {
+                // hdev[0] still holds ||b|| from the norm above, which the scaling below reads
+                FSI_HIP(hipMemcpyAsync(V, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+                beta = bnorm;
+            } else {
+                {
+                    ProfileScope pr("fgmres_residual", st);
+                    TRY(J64.apply(x, w64, jws, st));
+                    FSI_HIP(hipMemcpyAsync(V, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+                    TRY(kry_axpby(n, -1.0, w64, 1.0, V, st));
+                }
+                TRY(kry_norm(n, V, partial, hdev, st));
+                TRY(fetch(&beta, hdev, 1));
+            }
             if (S.cycles == 0) S.res0 = beta;
             S.res_final = beta;
             if (!std::isfinite(beta)) {

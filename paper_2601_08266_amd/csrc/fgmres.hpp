@@ -23,8 +23,9 @@ struct Precond {
 };
 
 size_t fgmres_workspace_bytes(int64_t ndof, int restart, fsi_dtype inner, size_t jws_bytes);
+// x_zero: the caller guarantees x = 0 on entry (the first cycle's residual is then b itself)
 int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32, const Precond *pc,
                  const double *b, double *x, const fsi_solve_opts &o, fsi_solve_stats *stats,
-                 void *ws, size_t jws_bytes, hipStream_t st);
+                 void *ws, size_t jws_bytes, hipStream_t st, bool x_zero = false);
 
 }  // namespace fsi

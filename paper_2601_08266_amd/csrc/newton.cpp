@@ -240,7 +240,8 @@ int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, c
         }};
         const JacobianCall &op64 = o.tangent ? t64 : c64;
         const JacobianCall &op32 = o.tangent ? t32 : c32;
-        rc = fgmres_solve(g, op64, o.inner == FSI_F32 ? &op32 : nullptr, &pc, R, dx, so, &ks, kws, jws, st);
+        rc = fgmres_solve(g, op64, o.inner == FSI_F32 ? &op32 : nullptr, &pc, R, dx, so, &ks, kws, jws, st,
+                          true);   // dx = 0 (cleared above)
         S.krylov_iters += ks.iters;
         S.t_krylov_ms += ms_since(tk);
         if (rc == FSI_ERR_NOT_CONVERGED) rc = FSI_OK;   // inexact Newton: take the step anyway
