@@ -571,6 +571,7 @@ int fsi_fgmres_solve(const fsi_problem *J64, const fsi_problem *J32, const void 
  * fsi_newton_solve - one implicit time step: Newton's method on
  * R(x) = 0 (fsi_vms_residual), each correction from J(u_k) dx = -R(x_k)
  * solved by fsi_fgmres_solve with the preconditioner opts->precond of J(u_k)
+ * (of J(u_0) at every iterate with opts->pc_reuse), from dx = 0
  * (section 2.4: Newton iterations on the monolithic system, each solving the
  * reduced block system).  J(u_k) is the Picard/Oseen linearisation: the
  * operator of fsi_vms_apply with advection field u_k plus the DLM block.
