@@ -549,7 +549,8 @@ def cpu_baseline(cfg, case, one_core=True):
 NEWTON_MODES_C5 = ["plain_f64_st2", "plain_mixed_st2", "extrap_mixed_st2", "extrap_mixed_st2_ft", "nn_mixed_st2"]
 
 
-def newton_block(workload="c5", train_end=20, eval_steps=2, epochs=20, modes=None, eta=5e-3, pc_reuse=True):
+def newton_block(workload="c5", train_end=20, eval_steps=2, epochs=20, modes=None, eta=5e-3, pc_reuse=True,
+                 basis32=True):
     """Newton steps of the rotating-plates channel on the workload's grid (192^3 by default):
     the run is advanced train_end steps (mixed precision, Schur block-triangular preconditioner
     with two velocity steps); the warm-start network is trained on its steps 2..train_end with
@@ -560,7 +561,9 @@ def newton_block(workload="c5", train_end=20, eval_steps=2, epochs=20, modes=Non
     same in every mode; 5e-3 gave the shortest steps of 1e-3 ... 2e-2 for plain FP64 and for
     mixed precision at 192^3 and 64^3.  pc_reuse: the preconditioner is built at the first Newton
     iterate of each step and reused (the same Krylov counts as rebuilding it at every iterate at
-    192^3 and 64^3, without three of the four setups), in every mode."""
+    192^3 and 64^3, without three of the four setups), in every mode.  basis32: the mixed modes
+    keep the Krylov basis in FP32 (their inner solves stop at the FP32 level anyway; the FP64
+    modes keep an FP64 basis)."""
     import statistics
 
     import fsi_workloads as W
@@ -571,7 +574,7 @@ def newton_block(workload="c5", train_end=20, eval_steps=2, epochs=20, modes=Non
     modes = list(modes or NEWTON_MODES_C5)
     cfg = W.CONFIGS[workload]
     t0 = time.perf_counter()
-    run = ChannelRun(cfg, precond="schur_tri", vel_steps=2, eta=eta, pc_reuse=pc_reuse)
+    run = ChannelRun(cfg, precond="schur_tri", vel_steps=2, eta=eta, pc_reuse=pc_reuse, basis32=basis32)
     run.record_extrap = True
     for _ in range(train_end):
         run.step()
@@ -597,7 +600,8 @@ def newton_block(workload="c5", train_end=20, eval_steps=2, epochs=20, modes=Non
                        f"steps {train_end + 1}-{train_end + eval_steps} solved in every mode",
            "tol": "1e-8 * ||R(x_plain)||, the same absolute threshold in every mode",
            "precond": "Schur block-triangular, 2 velocity steps", "forcing_eta": eta,
-           "precond_setup": "once per step" if pc_reuse else "every Newton iterate", "dof": 4 * g.num_nodes,
+           "precond_setup": "once per step" if pc_reuse else "every Newton iterate",
+           "krylov_basis_mixed": "f32" if basis32 else "f64", "dof": 4 * g.num_nodes,
            "simulate_s": round(sim_s, 1)}
     if lw is not None:
         out.update({"train_ms": round(lw.train_ms, 1), "epochs": epochs, "train_samples": len(ks),
@@ -633,6 +637,8 @@ def main(argv=None):
     ap.add_argument("--newton-eta", type=float, default=5e-3, help="Newton forcing of the linear solves")
     ap.add_argument("--newton-pc-rebuild", action="store_true",
                     help="rebuild the preconditioner at every Newton iterate (default: once per step)")
+    ap.add_argument("--newton-basis64", action="store_true",
+                    help="keep an FP64 Krylov basis in the mixed modes too (default: FP32 there)")
     ap.add_argument("--newton-probe", action="store_true",
                     help="also the short 64^3 Newton-step probe with block-Jacobi and Schur modes")
     ap.add_argument("--no-solid", action="store_true", help="skip the solid-block timings")
@@ -783,7 +789,8 @@ def main(argv=None):
                                           train_end=args.newton_train_end, epochs=args.newton_epochs,
                                           eval_steps=args.newton_eval_steps,
                                           modes=args.newton_modes.split(",") if args.newton_modes else None,
-                                          eta=args.newton_eta, pc_reuse=not args.newton_pc_rebuild)
+                                          eta=args.newton_eta, pc_reuse=not args.newton_pc_rebuild,
+                                          basis32=not args.newton_basis64)
     if args.newton_probe:
         out["newton_probe_64cube"] = newton_step_probe()
     if not args.no_cpu_baseline:

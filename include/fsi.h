@@ -517,7 +517,11 @@ int fsi_schur_apply(const fsi_problem *J, int32_t mode, int32_t vel_steps, void 
  * preconditioner (section 2.4: the reduced system is solved iteratively with
  * block preconditioners).
  * FP64: Krylov basis, classical Gram-Schmidt with re-orthogonalisation, Givens
- * rotations, x, and the residual b - J x recomputed at every restart.
+ * rotations, x, and the residual b - J x recomputed at every restart.  With
+ * opts->basis = FSI_F32 (only with inner = FSI_F32 and restart <= 52) the basis
+ * vectors are stored rounded to FP32 while every product and sum of the
+ * Gram-Schmidt passes, and the Gram matrix of the stored vectors, stay FP64
+ * (half the bytes per pass; a cycle stops at the FP32 level anyway).
  * Inner precision (opts->inner): the preconditioner and Jacobian applies of
  * each cycle and the stored preconditioned vectors; with FSI_F32 the restarts
  * are iterative-refinement steps (a cycle stops once its residual estimate
@@ -553,6 +557,7 @@ typedef struct {
     int32_t vel_steps;        /* Schur forms: minimal-residual steps on the velocity block */
     double *host_ring;        /* pinned host ring of the caller, or NULL (see below) */
     int64_t host_ring_len;    /* doubles in host_ring */
+    fsi_dtype basis;          /* storage of the Krylov basis: FSI_F64 (0) or FSI_F32 (see above) */
 } fsi_solve_opts;
 
 typedef struct {
@@ -602,6 +607,7 @@ typedef struct {
                                  built at the first iterate of the call and reused (a lagged
                                  preconditioner: FGMRES accepts any preconditioner, the operator
                                  stays J(u_k), so only the Krylov counts can change) */
+    fsi_dtype basis;          /* Krylov basis storage of every FGMRES solve (fsi_solve_opts) */
 } fsi_newton_opts;
 
 typedef struct {

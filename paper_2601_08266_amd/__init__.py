@@ -555,8 +555,12 @@ def _attach_host_ring(o, restart, pinned):
 
 
 def solve_opts(restart=50, max_iters=2000, rtol=1e-10, inner=torch.float32,
-               inner_reduction=1e-5, precond="bjacobi", vel_steps=0, pinned=True) -> FsiSolveOpts:
+               inner_reduction=1e-5, precond="bjacobi", vel_steps=0, pinned=True,
+               basis=torch.float64) -> FsiSolveOpts:
+    """basis: storage of the Krylov basis (torch.float32 only with inner=torch.float32 and
+    restart <= 52; the Gram-Schmidt arithmetic stays FP64)."""
     o = FsiSolveOpts()
+    o.basis = dtype_code(basis)
     o.restart, o.max_iters, o.rtol = int(restart), int(max_iters), float(rtol)
     o.inner = dtype_code(inner)
     o.inner_reduction = float(inner_reduction)
@@ -588,8 +592,9 @@ def fgmres_solve(J64: Problem, b: torch.Tensor, x: torch.Tensor, opts: FsiSolveO
 
 def newton_opts(tol_abs, max_newton=20, eta=1e-3, restart=50, max_krylov=2000,
                 inner=torch.float32, inner_reduction=1e-5, precond="bjacobi", vel_steps=0,
-                tangent="picard", pinned=True, pc_reuse=False) -> FsiNewtonOpts:
+                tangent="picard", pinned=True, pc_reuse=False, basis=torch.float64) -> FsiNewtonOpts:
     o = FsiNewtonOpts()
+    o.basis = dtype_code(basis)
     o.max_newton, o.tol_abs, o.eta = int(max_newton), float(tol_abs), float(eta)
     o.restart, o.max_krylov = int(restart), int(max_krylov)
     o.inner = dtype_code(inner)

@@ -58,7 +58,7 @@ class FsiSolveOpts(ctypes.Structure):
                 ("rtol", ctypes.c_double), ("inner", ctypes.c_int),
                 ("inner_reduction", ctypes.c_double), ("precond", ctypes.c_int32),
                 ("vel_steps", ctypes.c_int32), ("host_ring", ctypes.c_void_p),
-                ("host_ring_len", ctypes.c_int64)]
+                ("host_ring_len", ctypes.c_int64), ("basis", ctypes.c_int32)]
 
 
 class FsiSolveStats(ctypes.Structure):
@@ -74,7 +74,7 @@ class FsiNewtonOpts(ctypes.Structure):
                 ("inner_reduction", ctypes.c_double), ("precond", ctypes.c_int32),
                 ("vel_steps", ctypes.c_int32), ("tangent", ctypes.c_int32),
                 ("host_ring", ctypes.c_void_p), ("host_ring_len", ctypes.c_int64),
-                ("pc_reuse", ctypes.c_int32)]
+                ("pc_reuse", ctypes.c_int32), ("basis", ctypes.c_int32)]
 
 
 class FsiNewtonStats(ctypes.Structure):

@@ -805,6 +805,18 @@ FSI_API int fsi_bjacobi_apply(const fsi_grid *grid, fsi_dtype dtype, const void 
     return launch_bjacobi_apply(make_geo(*grid).N, dtype, pinv, v, z, as_stream(stream));
 }
 
+// storage precision of the Krylov basis: FP64, or FP32 with an FP32 inner precision and a basis
+// the fused Gram-Schmidt kernels hold
+static int check_basis(fsi_dtype basis, fsi_dtype inner, int restart)
+{
+    FSI_CHECK_ARG(dtype_ok(basis), "bad basis dtype");
+    if (basis == FSI_F32) {
+        FSI_CHECK_ARG(inner == FSI_F32, "an FP32 Krylov basis needs the FP32 inner precision");
+        FSI_CHECK_ARG(restart <= KRY_FUSED_MAXK, "an FP32 Krylov basis needs restart <= %d", KRY_FUSED_MAXK);
+    }
+    return FSI_OK;
+}
+
 static int check_solve(const fsi_problem *J64, const fsi_problem *J32, const fsi_solve_opts *o)
 {
     int rc = check_problem(J64);
@@ -830,6 +842,8 @@ static int check_solve(const fsi_problem *J64, const fsi_problem *J32, const fsi
                           o->inner_reduction < 1.0,
                       "inner_reduction must be in (0,1)");
     }
+    rc = check_basis(o->basis, o->inner, o->restart);
+    if (rc) return rc;
     return FSI_OK;
 }
 
@@ -841,7 +855,7 @@ FSI_API size_t fsi_fgmres_workspace(const fsi_problem *J64, const fsi_problem *J
     if (check_solve(J64, J32, o) != FSI_OK) return 0;
     size_t jw = jac_ws(J64);
     if (o->inner == FSI_F32) jw = std::max(jw, jac_ws(J32));
-    return fgmres_workspace_bytes(4 * make_geo(J64->grid).N, o->restart, o->inner, jw);
+    return fgmres_workspace_bytes(4 * make_geo(J64->grid).N, o->restart, o->inner, o->basis, jw);
 }
 
 FSI_API int fsi_fgmres_solve(const fsi_problem *J64, const fsi_problem *J32, const void *pinv,
@@ -855,7 +869,7 @@ FSI_API int fsi_fgmres_solve(const fsi_problem *J64, const fsi_problem *J32, con
     size_t jw = jac_ws(J64);
     if (o->inner == FSI_F32) jw = std::max(jw, jac_ws(J32));
     const Geo g = make_geo(J64->grid);
-    const size_t need = fgmres_workspace_bytes(4 * g.N, o->restart, o->inner, jw);
+    const size_t need = fgmres_workspace_bytes(4 * g.N, o->restart, o->inner, o->basis, jw);
     if (ws == nullptr || ws_bytes < need) {
         set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
         return FSI_ERR_WORKSPACE;
@@ -890,13 +904,15 @@ FSI_API int fsi_fgmres_solve(const fsi_problem *J64, const fsi_problem *J32, con
         FSI_CHECK_ARG(pinv != nullptr, "the Schur preconditioner object (fsi_schur_setup) is required");
         void *obj = const_cast<void *>(pinv);
         const int mode = o->precond == FSI_PC_SCHUR_DIAG ? 1 : 2;
-        pc.apply = [&, obj, mode](const double *v, void *z, void *w, hipStream_t s) {
-            return schur_apply(g, o->inner, true, mode, o->vel_steps, obj, v, z, Jin, w, s);
+        const bool basis64 = o->basis != FSI_F32;
+        pc.apply = [&, obj, mode, basis64](const void *v, void *z, void *w, hipStream_t s) {
+            return schur_apply(g, o->inner, basis64, mode, o->vel_steps, obj, v, z, Jin, w, s);
         };
     } else if (pinv != nullptr) {
-        pc.apply = [&](const double *v, void *z, void *, hipStream_t s) {
+        pc.apply = [&](const void *v, void *z, void *, hipStream_t s) {
+            if (o->basis == FSI_F32) return launch_bjacobi_apply(g.N, FSI_F32, pinv, v, z, s);
             if (o->inner == FSI_F32)
-                return launch_bjacobi_apply_f64_to_f32(g.N, (const float *)pinv, v, (float *)z, s);
+                return launch_bjacobi_apply_f64_to_f32(g.N, (const float *)pinv, (const double *)v, (float *)z, s);
             return launch_bjacobi_apply(g.N, FSI_F64, pinv, v, z, s);
         };
     }
@@ -1030,6 +1046,8 @@ static int check_newton(const fsi_problem *P64, const fsi_problem *P32, const fs
                           o->inner_reduction < 1.0,
                       "inner_reduction must be in (0,1)");
     }
+    rc = check_basis(o->basis, o->inner, o->restart);
+    if (rc) return rc;
     return FSI_OK;
 }
 

@@ -6,6 +6,11 @@
 // run in the inner precision (FP32 or FP64) and the preconditioned vectors Z
 // are stored in that precision.  Every restart begins from the true FP64
 // residual, so the FP32 inner cycles act as iterative refinement steps.
+// With an FP32 inner precision the basis may also be stored in FP32
+// (opts.basis): the Gram-Schmidt passes then read half the bytes, while
+// their products and sums, and the Gram matrix of the stored vectors that
+// the second projection uses, stay FP64; a cycle already stops at the FP32
+// level (inner_reduction), which such a basis resolves.
 // Section 2.4 solves the reduced block system with block-preconditioned
 // Krylov iterations; this is that loop, with the preconditioner passed in as a callable
 // (nodal block-Jacobi or the Schur-complement block preconditioner).
@@ -26,7 +31,7 @@ struct Layout {
     size_t V, Z, w64, t32b, partial, hdev, gram, jws, total;
 };
 
-Layout layout(int64_t n, int m, fsi_dtype inner, size_t jws_bytes)
+Layout layout(int64_t n, int m, fsi_dtype inner, fsi_dtype basis, size_t jws_bytes)
 {
     Layout L{};
     size_t off = 0;
@@ -35,7 +40,7 @@ Layout layout(int64_t n, int m, fsi_dtype inner, size_t jws_bytes)
         off += align_up(bytes);
         return o;
     };
-    L.V = take((size_t)(m + 1) * n * sizeof(double));
+    L.V = take((size_t)(m + 1) * n * (basis == FSI_F32 ? sizeof(float) : sizeof(double)));
     L.Z = take((size_t)m * n * (inner == FSI_F64 ? sizeof(double) : sizeof(float)));
     L.w64 = take((size_t)n * sizeof(double));
     L.t32b = take((size_t)n * sizeof(float));
@@ -70,9 +75,9 @@ struct StepEvents {
 
 }  // namespace
 
-size_t fgmres_workspace_bytes(int64_t ndof, int restart, fsi_dtype inner, size_t jws_bytes)
+size_t fgmres_workspace_bytes(int64_t ndof, int restart, fsi_dtype inner, fsi_dtype basis, size_t jws_bytes)
 {
-    return layout(ndof, restart, inner, jws_bytes).total;
+    return layout(ndof, restart, inner, basis, jws_bytes).total;
 }
 
 int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32, const Precond *pc,
@@ -84,9 +89,11 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
     const int64_t n = 4 * g.N;
     const int m = o.restart;
     const fsi_dtype inner = o.inner;
-    const Layout L = layout(n, m, inner, jws_bytes);
+    const bool b32 = o.basis == FSI_F32;   // basis stored in FP32 (the caller checked inner = FP32)
+    const Layout L = layout(n, m, inner, o.basis, jws_bytes);
     char *base = reinterpret_cast<char *>(ws);
     double *V = reinterpret_cast<double *>(base + L.V);
+    float *V32 = reinterpret_cast<float *>(base + L.V);
     void *Z = base + L.Z;
     double *w64 = reinterpret_cast<double *>(base + L.w64);
     float *t32b = reinterpret_cast<float *>(base + L.t32b);
@@ -147,19 +154,26 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
         for (;;) {
             // true residual r = b - J64 x in FP64 (stored in V[0]); b itself while x is still the
             // zero the caller guaranteed (then its norm is the one already computed)
+            // (with an FP32 basis the residual is formed in w64 and rounded as it is scaled)
             double beta = 0.0;
+            const double *r0 = b32 ? w64 : V;
             if (x_zero && S.cycles == 0) {
                 // hdev[0] still holds ||b|| from the norm above, which the scaling below reads
-                FSI_HIP(hipMemcpyAsync(V, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+                if (b32) r0 = b;
+                else FSI_HIP(hipMemcpyAsync(V, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
                 beta = bnorm;
             } else {
                 {
                     ProfileScope pr("fgmres_residual", st);
                     TRY(J64.apply(x, w64, jws, st));
-                    FSI_HIP(hipMemcpyAsync(V, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
-                    TRY(kry_axpby(n, -1.0, w64, 1.0, V, st));
+                    if (b32) {
+                        TRY(kry_axpby(n, 1.0, b, -1.0, w64, st));
+                    } else {
+                        FSI_HIP(hipMemcpyAsync(V, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+                        TRY(kry_axpby(n, -1.0, w64, 1.0, V, st));
+                    }
                 }
-                TRY(kry_norm(n, V, partial, hdev, st));
+                TRY(kry_norm(n, r0, partial, hdev, st));
                 TRY(fetch(&beta, hdev, 1));
             }
             if (S.cycles == 0) S.res0 = beta;
@@ -182,7 +196,8 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
                 goto done;
             }
             prev_beta = beta;
-            TRY(kry_scale_inv(n, V, hdev, V, st));
+            if (b32) TRY(kry_scale_inv_to_f32(n, r0, hdev, V32, st));
+            else TRY(kry_scale_inv(n, V, hdev, V, st));
             std::fill(gv.begin(), gv.end(), 0.0);
             gv[0] = beta;
             // an FP32 inner cycle cannot resolve much below its own rounding level
@@ -230,18 +245,21 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
             };
             for (int j = 0; j < m && !stop && S.iters + (enq - kk) < o.max_iters; ++j) {
                 double *Vj = V + (size_t)j * n;
+                float *Vj32 = V32 + (size_t)j * n;
                 char *Zj = reinterpret_cast<char *>(Z) + (size_t)j * n * zel;
                 if (inner == FSI_F32) {
                     {
                         ProfileScope pp("fgmres_precond", st);
-                        if (pc) TRY(pc->apply(Vj, Zj, jws, st));
+                        if (pc) TRY(pc->apply(b32 ? (const void *)Vj32 : (const void *)Vj, Zj, jws, st));
+                        else if (b32)
+                            FSI_HIP(hipMemcpyAsync(Zj, Vj32, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
                         else TRY(kry_cast_f64_f32(n, Vj, reinterpret_cast<float *>(Zj), st));
                     }
                     ProfileScope pa("fgmres_apply", st);
                     TRY(J32->apply(Zj, t32b, jws, st));
                     // the fused Gram-Schmidt passes read the FP32 product and widen it as they
                     // go; the unfused ones take it widened
-                    if (j + 1 > KRY_FUSED_MAXK) TRY(kry_cast_f32_f64(n, t32b, w64, st));
+                    if (j + 1 > KRY_FUSED_MAXK && !b32) TRY(kry_cast_f32_f64(n, t32b, w64, st));
                 } else {
                     {
                         ProfileScope pp("fgmres_precond", st);
@@ -258,7 +276,12 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
                 double *d_ab = hdev, *d_h = hdev + 2 * (m + 1), *d_hn = hdev + 3 * (m + 1);
                 {
                     ProfileScope po("fgmres_orth", st);
-                    if (j + 1 <= KRY_FUSED_MAXK && inner == FSI_F32) {
+                    if (b32) {
+                        // w - V h goes straight into the next basis slot, rounded to FP32
+                        TRY(kry_cgs_project_b32(n, j + 1, V32, n, t32b, Vj32, partial, d_ab, Gdev, m + 1, d_h, st));
+                        TRY(kry_axpy_norm_b32(n, j + 1, V32, n, d_h, t32b, V32 + (size_t)(j + 1) * n, partial, d_hn,
+                                              st));
+                    } else if (j + 1 <= KRY_FUSED_MAXK && inner == FSI_F32) {
                         TRY(kry_cgs_project_f32w(n, j + 1, V, n, t32b, Vj, partial, d_ab, Gdev, m + 1, d_h, st));
                         TRY(kry_axpy_norm_f32w(n, j + 1, V, n, d_h, t32b, w64, partial, d_hn, st));
                     } else if (j + 1 <= KRY_FUSED_MAXK) {
@@ -275,7 +298,8 @@ int fgmres_solve(const Geo &g, const JacobianCall &J64, const JacobianCall *J32,
                 FSI_HIP(hipEventRecord(ev[j], st));
                 if (!pinned) FSI_HIP(hipEventSynchronize(ev[j]));
                 // next basis vector (if ||w|| = 0 the step ends the cycle and this vector is unused)
-                TRY(kry_scale_inv(n, w64, d_hn, V + (size_t)(j + 1) * n, st));
+                if (b32) TRY(kry_scale_inv_f32(n, V32 + (size_t)(j + 1) * n, d_hn, V32 + (size_t)(j + 1) * n, st));
+                else TRY(kry_scale_inv(n, w64, d_hn, V + (size_t)(j + 1) * n, st));
                 ++enq;
                 if (j >= 1) TRY(process(j - 1));
             }

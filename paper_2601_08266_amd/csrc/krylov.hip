@@ -33,13 +33,14 @@ __global__ __launch_bounds__(KT) void scale_k(int64_t n, double alpha, const dou
         y[i] = alpha * x[i];
 }
 
-// out = x * s, s = 1 / dev[0] computed on the device side (out may be x)
-__global__ __launch_bounds__(KT) void scale_inv_k(int64_t n, const double *x, const double *__restrict__ dev,
-                                                  double *out)
+// out = x * s, s = 1 / dev[0] computed on the device side in FP64 (out may be x)
+template <typename TI, typename TO>
+__global__ __launch_bounds__(KT) void scale_inv_k(int64_t n, const TI *x, const double *__restrict__ dev,
+                                                  TO *out)
 {
     const double s = 1.0 / dev[0];
     for (int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x; i < n; i += (int64_t)gridDim.x * KT)
-        out[i] = x[i] * s;
+        out[i] = (TO)((double)x[i] * s);
 }
 
 // partial[k][block] = sum over this block's contiguous chunk of V[k][i] * w[i], k < nk
@@ -258,23 +259,29 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// two consecutive entries as FP64 (w in FP64, or the FP32 product of the inner precision,
-// widened exactly)
+// two consecutive entries as FP64 (FP64 vectors, or FP32 ones widened exactly: the inner
+// precision's product, or a basis stored in FP32)
 __device__ __forceinline__ double2 load2(const double *p) { return *reinterpret_cast<const double2 *>(p); }
 __device__ __forceinline__ double2 load2(const float *p)
 {
     const float2 v = *reinterpret_cast<const float2 *>(p);
     return make_double2((double)v.x, (double)v.y);
 }
+__device__ __forceinline__ void store2(double *p, double2 v) { *reinterpret_cast<double2 *>(p) = v; }
+__device__ __forceinline__ void store2(float *p, double2 v)
+{
+    *reinterpret_cast<float2 *>(p) = make_float2((float)v.x, (float)v.y);
+}
 
 // Projection pass of classical Gram-Schmidt with re-orthogonalisation through the Gram matrix:
 // per-block partials of V[k] . w and V[k] . u (u = V[nk-1], the newest basis vector), k < nk, in
 // one read of V: wave wv of a block takes the vectors k = wv + 4q, q < KQ = ceil(nk / 4), and
-// issues their loads together (past nk the last vector is re-read and not accumulated).
-template <int KQ, typename TW>
-__global__ __launch_bounds__(KT) void cgs_project_k(int64_t n, int nk, const double *__restrict__ V,
+// issues their loads together (past nk the last vector is re-read and not accumulated).  The
+// basis (TV) and w (TW) are FP64 or FP32; products and sums are FP64.
+template <int KQ, typename TW, typename TV>
+__global__ __launch_bounds__(KT) void cgs_project_k(int64_t n, int nk, const TV *__restrict__ V,
                                                     int64_t ldv, const TW *__restrict__ w,
-                                                    const double *__restrict__ u,
+                                                    const TV *__restrict__ u,
                                                     double *__restrict__ partial)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -283,7 +290,7 @@ __global__ __launch_bounds__(KT) void cgs_project_k(int64_t n, int nk, const dou
     const int64_t chunk = ((n + gridDim.x - 1) / gridDim.x + 1) & ~(int64_t)1;
     const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = lo + chunk < n ? lo + chunk : n;
-    const double *vk[KQ];
+    const TV *vk[KQ];
 #pragma unroll
     for (int q = 0; q < KQ; ++q) {
         const int k = wv + CG_WAVES * q;
@@ -294,10 +301,10 @@ __global__ __launch_bounds__(KT) void cgs_project_k(int64_t n, int nk, const dou
     for (int q = 0; q < KQ; ++q) aw[q] = au[q] = 0.0;
     for (int64_t i = lo + 2 * lane; i < hi; i += 128) {
         const double2 wi = load2(w + i);
-        const double2 ui = *reinterpret_cast<const double2 *>(u + i);
+        const double2 ui = load2(u + i);
         double2 v[KQ];
 #pragma unroll
-        for (int q = 0; q < KQ; ++q) v[q] = *reinterpret_cast<const double2 *>(vk[q] + i);
+        for (int q = 0; q < KQ; ++q) v[q] = load2(vk[q] + i);
         __builtin_amdgcn_sched_barrier(0);   // keep the loads in flight together
 #pragma unroll
         for (int q = 0; q < KQ; ++q) {
@@ -319,11 +326,12 @@ __global__ __launch_bounds__(KT) void cgs_project_k(int64_t n, int nk, const dou
 }
 
 // out = w - V h (nk vectors, in groups of 8 whose loads are issued together) and per-block
-// partials of ||out||^2; out may be w itself (TW = double).
-template <typename TW>
-__global__ __launch_bounds__(KT) void axpy_norm_k(int64_t n, int nk, const double *__restrict__ V,
+// partials of ||out||^2 (of the FP64 sums, before out is rounded to TO); out may be w itself
+// (TW = TO).
+template <typename TW, typename TV, typename TO>
+__global__ __launch_bounds__(KT) void axpy_norm_k(int64_t n, int nk, const TV *__restrict__ V,
                                                   int64_t ldv, const double *__restrict__ h,
-                                                  const TW *w, double *out, double *__restrict__ partial)
+                                                  const TW *w, TO *out, double *__restrict__ partial)
 {
     constexpr int KB = 8;
     __shared__ double red[CG_WAVES];
@@ -340,7 +348,7 @@ __global__ __launch_bounds__(KT) void axpy_norm_k(int64_t n, int nk, const doubl
 #pragma unroll
             for (int q = 0; q < KB; ++q) {
                 const int k = k0 + q;
-                v[q] = *reinterpret_cast<const double2 *>(V + (int64_t)(k < nk ? k : nk - 1) * ldv + i);
+                v[q] = load2(V + (int64_t)(k < nk ? k : nk - 1) * ldv + i);
                 hk[q] = k < nk ? h[k] : 0.0;
             }
             __builtin_amdgcn_sched_barrier(0);   // keep the loads in flight together
@@ -350,7 +358,7 @@ __global__ __launch_bounds__(KT) void axpy_norm_k(int64_t n, int nk, const doubl
                 s.y -= hk[q] * v[q].y;
             }
         }
-        *reinterpret_cast<double2 *>(out + i) = s;
+        store2(out + i, s);
         acc += s.x * s.x;
         acc += s.y * s.y;
     }
@@ -402,7 +410,21 @@ int kry_scale(int64_t n, double alpha, const double *x, double *y, hipStream_t s
 
 int kry_scale_inv(int64_t n, const double *x, const double *dev_scalar, double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(scale_inv_k, dim3(grid_for(n)), dim3(KT), 0, st, n, x, dev_scalar, out);
+    hipLaunchKernelGGL((scale_inv_k<double, double>), dim3(grid_for(n)), dim3(KT), 0, st, n, x, dev_scalar, out);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+
+int kry_scale_inv_to_f32(int64_t n, const double *x, const double *dev_scalar, float *out, hipStream_t st)
+{
+    hipLaunchKernelGGL((scale_inv_k<double, float>), dim3(grid_for(n)), dim3(KT), 0, st, n, x, dev_scalar, out);
+    FSI_LAUNCH_CHECK();
+    return FSI_OK;
+}
+
+int kry_scale_inv_f32(int64_t n, const float *x, const double *dev_scalar, float *out, hipStream_t st)
+{
+    hipLaunchKernelGGL((scale_inv_k<float, float>), dim3(grid_for(n)), dim3(KT), 0, st, n, x, dev_scalar, out);
     FSI_LAUNCH_CHECK();
     return FSI_OK;
 }
@@ -459,18 +481,19 @@ int kry_multidot2(int64_t n, int nk, const double *V, int64_t ldv, const double 
     return FSI_OK;
 }
 
-template <typename TW>
-static int cgs_project_t(int64_t n, int nk, const double *V, int64_t ldv, const TW *w, const double *u,
+template <typename TW, typename TV>
+static int cgs_project_t(int64_t n, int nk, const TV *V, int64_t ldv, const TW *w, const TV *u,
                          double *partial, double *ab, double *G, int ldg, double *h, hipStream_t st)
 {
-    if ((n | ldv) & 1 || ((uintptr_t)V | (uintptr_t)u) & 15 || (uintptr_t)w & (2 * sizeof(TW) - 1)) {
+    if ((n | ldv) & 1 || ((uintptr_t)V | (uintptr_t)u) & (2 * sizeof(TV) - 1) ||
+        (uintptr_t)w & (2 * sizeof(TW) - 1)) {
         set_error("CGS projection needs even lengths and aligned vectors");
         return FSI_ERR_ARG;
     }
     switch ((nk + CG_WAVES - 1) / CG_WAVES) {
 #define FSI_CGS_CASE(KQ)                                                                           \
     case KQ:                                                                                       \
-        hipLaunchKernelGGL((cgs_project_k<KQ, TW>), dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, w, \
+        hipLaunchKernelGGL((cgs_project_k<KQ, TW, TV>), dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, w, \
                            u, partial);                                                            \
         break;
         FSI_CGS_CASE(1) FSI_CGS_CASE(2) FSI_CGS_CASE(3) FSI_CGS_CASE(4) FSI_CGS_CASE(5)
@@ -492,24 +515,32 @@ static int cgs_project_t(int64_t n, int nk, const double *V, int64_t ldv, const 
 int kry_cgs_project(int64_t n, int nk, const double *V, int64_t ldv, const double *w, const double *u,
                     double *partial, double *ab, double *G, int ldg, double *h, hipStream_t st)
 {
-    return cgs_project_t<double>(n, nk, V, ldv, w, u, partial, ab, G, ldg, h, st);
+    return cgs_project_t<double, double>(n, nk, V, ldv, w, u, partial, ab, G, ldg, h, st);
 }
 
 int kry_cgs_project_f32w(int64_t n, int nk, const double *V, int64_t ldv, const float *w, const double *u,
                          double *partial, double *ab, double *G, int ldg, double *h, hipStream_t st)
 {
-    return cgs_project_t<float>(n, nk, V, ldv, w, u, partial, ab, G, ldg, h, st);
+    return cgs_project_t<float, double>(n, nk, V, ldv, w, u, partial, ab, G, ldg, h, st);
 }
 
-template <typename TW>
-static int axpy_norm_t(int64_t n, int nk, const double *V, int64_t ldv, const double *h, const TW *w,
-                       double *wout, double *partial, double *out, hipStream_t st)
+int kry_cgs_project_b32(int64_t n, int nk, const float *V, int64_t ldv, const float *w, const float *u,
+                        double *partial, double *ab, double *G, int ldg, double *h, hipStream_t st)
 {
-    if ((n | ldv) & 1 || ((uintptr_t)V | (uintptr_t)wout) & 15 || (uintptr_t)w & (2 * sizeof(TW) - 1)) {
+    return cgs_project_t<float, float>(n, nk, V, ldv, w, u, partial, ab, G, ldg, h, st);
+}
+
+template <typename TW, typename TV, typename TO>
+static int axpy_norm_t(int64_t n, int nk, const TV *V, int64_t ldv, const double *h, const TW *w,
+                       TO *wout, double *partial, double *out, hipStream_t st)
+{
+    if ((n | ldv) & 1 || (uintptr_t)V & (2 * sizeof(TV) - 1) || (uintptr_t)wout & (2 * sizeof(TO) - 1) ||
+        (uintptr_t)w & (2 * sizeof(TW) - 1)) {
         set_error("CGS update needs even lengths and aligned vectors");
         return FSI_ERR_ARG;
     }
-    hipLaunchKernelGGL((axpy_norm_k<TW>), dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, h, w, wout, partial);
+    hipLaunchKernelGGL((axpy_norm_k<TW, TV, TO>), dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, h, w, wout,
+                       partial);
     FSI_LAUNCH_CHECK();
     hipLaunchKernelGGL(reduce_partials_k, dim3(1), dim3(KT), 0, st, 1, KRY_NB, partial, out, 1);
     FSI_LAUNCH_CHECK();
@@ -519,13 +550,19 @@ static int axpy_norm_t(int64_t n, int nk, const double *V, int64_t ldv, const do
 int kry_axpy_norm(int64_t n, int nk, const double *V, int64_t ldv, const double *h, double *w,
                   double *partial, double *out, hipStream_t st)
 {
-    return axpy_norm_t<double>(n, nk, V, ldv, h, w, w, partial, out, st);
+    return axpy_norm_t<double, double, double>(n, nk, V, ldv, h, w, w, partial, out, st);
 }
 
 int kry_axpy_norm_f32w(int64_t n, int nk, const double *V, int64_t ldv, const double *h, const float *w,
                        double *wout, double *partial, double *out, hipStream_t st)
 {
-    return axpy_norm_t<float>(n, nk, V, ldv, h, w, wout, partial, out, st);
+    return axpy_norm_t<float, double, double>(n, nk, V, ldv, h, w, wout, partial, out, st);
+}
+
+int kry_axpy_norm_b32(int64_t n, int nk, const float *V, int64_t ldv, const double *h, const float *w,
+                      float *wout, double *partial, double *out, hipStream_t st)
+{
+    return axpy_norm_t<float, float, float>(n, nk, V, ldv, h, w, wout, partial, out, st);
 }
 
 int kry_gram_coeffs(int nk, const double *ab, double *G, int ldg, double *h, hipStream_t st)

@@ -13,6 +13,9 @@ int kry_cast_f32_f64(int64_t n, const float *in, double *out, hipStream_t st);
 int kry_axpby(int64_t n, double alpha, const double *x, double beta, double *y, hipStream_t st);
 int kry_scale(int64_t n, double alpha, const double *x, double *y, hipStream_t st);
 int kry_scale_inv(int64_t n, const double *x, const double *dev_scalar, double *out, hipStream_t st);
+// the same scaling (FP64 arithmetic) into an FP32 vector, from FP64 or FP32 (out may be x)
+int kry_scale_inv_to_f32(int64_t n, const double *x, const double *dev_scalar, float *out, hipStream_t st);
+int kry_scale_inv_f32(int64_t n, const float *x, const double *dev_scalar, float *out, hipStream_t st);
 int kry_multidot(int64_t n, int nk, const double *V, int64_t ldv, const double *w, double *partial,
                  double *out, hipStream_t st);
 int kry_norm(int64_t n, const double *w, double *partial, double *out, hipStream_t st);
@@ -39,6 +42,12 @@ int kry_cgs_project_f32w(int64_t n, int nk, const double *V, int64_t ldv, const 
                          double *partial, double *ab, double *G, int ldg, double *h, hipStream_t st);
 int kry_axpy_norm_f32w(int64_t n, int nk, const double *V, int64_t ldv, const double *h, const float *w,
                        double *wout, double *partial, double *out, hipStream_t st);
+// both passes with the basis stored in FP32 (V, u, w and the new vector wout in FP32; every
+// product and sum in FP64)
+int kry_cgs_project_b32(int64_t n, int nk, const float *V, int64_t ldv, const float *w, const float *u,
+                        double *partial, double *ab, double *G, int ldg, double *h, hipStream_t st);
+int kry_axpy_norm_b32(int64_t n, int nk, const float *V, int64_t ldv, const double *h, const float *w,
+                      float *wout, double *partial, double *out, hipStream_t st);
 int kry_update(int64_t n, int nk, fsi_dtype dz, const void *Z, int64_t ldz, const double *y, double *x,
                hipStream_t st);
 

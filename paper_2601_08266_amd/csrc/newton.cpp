@@ -52,7 +52,7 @@ NLayout nlayout(const Geo &g, const fsi_newton_opts &o, size_t jws)
     L.f32 = o.tangent ? take((size_t)3 * g.N * sizeof(float)) : 0;
     L.scratch = take((size_t)(KRY_NB + 16) * sizeof(double));
     L.bjws = take(bjacobi_workspace_bytes(g));
-    L.kws = take(fgmres_workspace_bytes(4 * g.N, o.restart, o.inner, jws));
+    L.kws = take(fgmres_workspace_bytes(4 * g.N, o.restart, o.inner, o.basis, jws));
     L.total = off;
     return L;
 }
@@ -192,6 +192,7 @@ int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, c
         if (so.rtol >= 1.0) so.rtol = 0.5;
         so.inner = o.inner;
         so.inner_reduction = o.inner_reduction;
+        so.basis = o.basis;
         JacobianCall c64{[&](const void *xx, void *yy, void *w, hipStream_t s2) {
             return launch_vms_apply(g, J64.prm, FSI_F64, J64.a, J64.s, J64.dir_mask, xx, yy,
                                     J64.n_occ > 0 ? &v64 : nullptr, w, jws, s2);
@@ -214,13 +215,16 @@ int newton_solve(const Geo &g, const fsi_problem &P64, const fsi_problem *P32, c
         const JacobianCall *Jin = o.inner == FSI_F32 ? &c32 : &c64;
         const int mode = o.precond == FSI_PC_SCHUR_DIAG ? 1 : 2;
         Precond pc;
+        const bool basis64 = o.basis != FSI_F32;   // the basis vectors the preconditioner reads
         if (schur)
-            pc.apply = [&](const double *v, void *z, void *w, hipStream_t s2) {
-                return schur_apply(g, o.inner, true, mode, o.vel_steps, pcobj, v, z, Jin, w, s2);
+            pc.apply = [&](const void *v, void *z, void *w, hipStream_t s2) {
+                return schur_apply(g, o.inner, basis64, mode, o.vel_steps, pcobj, v, z, Jin, w, s2);
             };
         else
-            pc.apply = [&](const double *v, void *z, void *, hipStream_t s2) {
-                if (o.inner == FSI_F32) return launch_bjacobi_apply_f64_to_f32(g.N, pinv32, v, (float *)z, s2);
+            pc.apply = [&](const void *v, void *z, void *, hipStream_t s2) {
+                if (!basis64) return launch_bjacobi_apply(g.N, FSI_F32, pinv32, v, z, s2);
+                if (o.inner == FSI_F32)
+                    return launch_bjacobi_apply_f64_to_f32(g.N, pinv32, (const double *)v, (float *)z, s2);
                 return launch_bjacobi_apply(g.N, FSI_F64, pinv64, v, z, s2);
             };
         so.precond = o.precond;

@@ -59,12 +59,14 @@ class StepRecord:
 class ChannelRun:
     def __init__(self, cfg, device="cuda", inner=torch.float32, eta=1e-3, restart=50,
                  rel_tol=1e-8, period=0.8, amp_deg=20.0, max_krylov=4000, precond="bjacobi",
-                 integrator="be", rho_inf=0.5, vel_steps=0, tangent="picard", pc_reuse=False):
+                 integrator="be", rho_inf=0.5, vel_steps=0, tangent="picard", pc_reuse=False,
+                 basis32=False):
         self.cfg = cfg
         self.precond = precond
         self.vel_steps = vel_steps
         self.tangent = tangent
         self.pc_reuse = pc_reuse   # build the preconditioner once per step (at the guess) and reuse it
+        self.basis32 = basis32     # FP32 inner solves keep their Krylov basis in FP32
         # time integrator: backward Euler, or generalized-alpha (section 2.4) in stage variables:
         # the stage residual at t_n + alpha_f dt is the backward-Euler-form residual with mass
         # coefficient alpha_m / (gamma dt alpha_f) and source c V_n - (1 - alpha_m/gamma) Vdot_n;
@@ -246,7 +248,8 @@ class ChannelRun:
                            precond=precond if precond is not None else self.precond,
                            vel_steps=vel_steps if vel_steps is not None else self.vel_steps,
                            tangent=tangent if tangent is not None else self.tangent,
-                           pc_reuse=pc_reuse if pc_reuse is not None else self.pc_reuse)
+                           pc_reuse=pc_reuse if pc_reuse is not None else self.pc_reuse,
+                           basis=torch.float32 if self.basis32 and inner == torch.float32 else torch.float64)
         x_new = x0.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -106,3 +106,41 @@ def test_block_products_reject_bad_arguments_without_gpu():
     p.grid = fsi.make_grid((4, 4, 4), 2)
     assert lib.fsi_jacobian_apply_block(ctypes.byref(p), fsi.BLOCK_F, x, y, None, 0, None) == L.FSI_ERR_UNSUPPORTED
     assert b"Q1" in lib.fsi_last_error()
+
+
+def test_fp32_krylov_basis_options_without_gpu():
+    # host-only: the FP32 Krylov basis needs the FP32 inner precision and restart <= 52, and it
+    # shrinks the FGMRES workspace by the basis' half (the pointers are never dereferenced)
+    import torch
+
+    import paper_2601_08266_amd as fsi
+    import paper_2601_08266_amd._lib as L
+    lib = L.lib()
+    probs = []
+    for dt in (L.FSI_F64, L.FSI_F32):
+        p = L.FsiProblem()
+        p.grid = fsi.make_grid((8, 8, 8), 1)
+        p.prm = fsi.make_params(0.01, 1000.0, 1e-3, 4.0, 36.0)
+        p.dtype = dt
+        p.a = 16
+        probs.append(p)
+    p64, p32 = (ctypes.byref(p) for p in probs)
+    n = 4 * 9 ** 3
+    o = fsi.solve_opts(restart=50, inner=torch.float32, pinned=False)
+    w64 = lib.fsi_fgmres_workspace(p64, p32, ctypes.byref(o))
+    o.basis = L.FSI_F32
+    w32 = lib.fsi_fgmres_workspace(p64, p32, ctypes.byref(o))
+    assert w64 > 0 and w32 > 0
+    assert abs((w64 - w32) - 51 * n * 4) <= 512
+    o.restart = 53
+    assert lib.fsi_fgmres_workspace(p64, p32, ctypes.byref(o)) == 0
+    assert b"restart" in lib.fsi_last_error()
+    o.restart, o.inner = 50, L.FSI_F64
+    assert lib.fsi_fgmres_workspace(p64, None, ctypes.byref(o)) == 0
+    assert b"inner" in lib.fsi_last_error()
+    o.inner, o.basis = L.FSI_F32, 7
+    assert lib.fsi_fgmres_workspace(p64, p32, ctypes.byref(o)) == 0
+    no = fsi.newton_opts(tol_abs=1e-8, restart=60, inner=torch.float32, basis=torch.float32, pinned=False)
+    assert lib.fsi_newton_workspace(p64, p32, ctypes.byref(no)) == 0
+    no.restart = 50
+    assert lib.fsi_newton_workspace(p64, p32, ctypes.byref(no)) > 0

@@ -103,8 +103,11 @@ def test_schur_levels_and_applies_match_oracle(name):
         assert e32 <= 1e-5
 
 
-@pytest.mark.parametrize("mode,inner", [("schur_diag", "f64"), ("schur_tri", "f64"), ("schur_tri", "f32")])
+@pytest.mark.parametrize("mode,inner", [("schur_diag", "f64"), ("schur_tri", "f64"), ("schur_tri", "f32"),
+                                        ("schur_tri", "f32b")])
 def test_fgmres_with_schur_c1_matches_dense_lu(mode, inner):
+    """inner f32b: FP32 inner precision with the Krylov basis stored in FP32 (the preconditioner
+    then reads FP32 basis vectors)."""
     import torch
     import paper_2601_08266_amd as fsi
     cfg = W.CONFIGS["c1"]
@@ -119,8 +122,9 @@ def test_fgmres_with_schur_c1_matches_dense_lu(mode, inner):
     pc = fsi.schur_setup(P["J64"], blocks)
     x = torch.zeros(4 * N, dtype=torch.float64, device="cuda")
     tdt = torch.float64 if inner == "f64" else torch.float32
-    opts = fsi.solve_opts(restart=50, max_iters=3000, rtol=1e-10, inner=tdt, precond=mode)
-    rc, st = fsi.fgmres_solve(P["J64"], _t(b), x, opts, J32=P["J32"] if inner == "f32" else None, pinv=pc)
+    opts = fsi.solve_opts(restart=50, max_iters=3000, rtol=1e-10, inner=tdt, precond=mode,
+                          basis=torch.float32 if inner == "f32b" else torch.float64)
+    rc, st = fsi.fgmres_solve(P["J64"], _t(b), x, opts, J32=P["J32"] if inner != "f64" else None, pinv=pc)
     xs = x.cpu().numpy()
     res = np.linalg.norm(b - J @ xs) / np.linalg.norm(b)
     err = np.linalg.norm(xs - x_ref) / np.linalg.norm(x_ref)
@@ -130,12 +134,14 @@ def test_fgmres_with_schur_c1_matches_dense_lu(mode, inner):
     assert err <= 1e-6
 
 
-@pytest.mark.parametrize("mode,pc_reuse", [("schur_diag", False), ("schur_tri", False), ("schur_tri", True),
-                                           ("bjacobi", True)])
-def test_newton_with_schur_c1_matches_dense_newton(mode, pc_reuse):
+@pytest.mark.parametrize("mode,pc_reuse,basis", [("schur_diag", False, "f64"), ("schur_tri", False, "f64"),
+                                                 ("schur_tri", True, "f64"), ("bjacobi", True, "f64"),
+                                                 ("schur_tri", True, "f32"), ("bjacobi", False, "f32")])
+def test_newton_with_schur_c1_matches_dense_newton(mode, pc_reuse, basis):
     """Newton with the Schur (or block-Jacobi) preconditioner rebuilt at every iterate, or built at
-    the first iterate and reused (pc_reuse): the same converged state as the oracle's dense
-    Newton, within the common residual tolerance."""
+    the first iterate and reused (pc_reuse), with the Krylov basis of the FP32 inner solves in
+    FP64 or FP32: the same converged state as the oracle's dense Newton, within the common
+    residual tolerance."""
     import torch
     import paper_2601_08266_amd as fsi
     cfg = W.CONFIGS["c1"]
@@ -153,12 +159,13 @@ def test_newton_with_schur_c1_matches_dense_newton(mode, pc_reuse):
     lamg = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
     fsi.dlm_BT(g, P["J64"].tables, _t(g_pts), lamg, kappa=_t(kappa))
     x = _t(x0)
-    opts = fsi.newton_opts(tol_abs=tol, inner=torch.float32, precond=mode, pc_reuse=pc_reuse)
+    opts = fsi.newton_opts(tol_abs=tol, inner=torch.float32, precond=mode, pc_reuse=pc_reuse,
+                           basis=torch.float32 if basis == "f32" else torch.float64)
     rc, st = fsi.newton_solve(P["J64"], _t(cfg.c_m * u_old), x, opts, P32=P["J32"], lamg=lamg, gD=_t(gD))
     xs = x.cpu().numpy()
     R = onewton.residual(g, P["prm_o"], xs, u_old, P["cell"], P["xi"], kappa, g_pts, s=P["s"],
                          mask=mask, gD=gD)
-    print(f"newton c1 {mode} reuse={pc_reuse}: {st.newton_iters} Newton / {st.krylov_iters} Krylov, {st.t_total_ms:.1f} ms, "
+    print(f"newton c1 {mode} reuse={pc_reuse} basis={basis}: {st.newton_iters} Newton / {st.krylov_iters} Krylov, {st.t_total_ms:.1f} ms, "
           f"oracle ||R|| {np.linalg.norm(R):.3e} (tol {tol:.3e})")
     assert np.linalg.norm(R) <= tol * 1.01
     assert np.linalg.norm(xs - x_ref.ravel()) <= 1e-6 * np.linalg.norm(x_ref)

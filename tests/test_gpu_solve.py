@@ -82,8 +82,9 @@ def test_bjacobi_blocks_and_inverse(case):
     assert np.abs(z - zr).max() <= 1e-12 * np.abs(zr).max()
 
 
-@pytest.mark.parametrize("inner,restart", [("f64", 50), ("f32", 50), ("f64", 80), ("f32", 64)])
+@pytest.mark.parametrize("inner,restart", [("f64", 50), ("f32", 50), ("f64", 80), ("f32", 64), ("f32b", 50)])
 def test_fgmres_c1_matches_dense_lu(inner, restart):
+    """inner f32b: FP32 inner precision with the Krylov basis stored in FP32."""
     import torch
     import paper_2601_08266_amd as fsi
     cfg = W.CONFIGS["c1"]
@@ -99,9 +100,10 @@ def test_fgmres_c1_matches_dense_lu(inner, restart):
     tdt = torch.float64 if inner == "f64" else torch.float32
     # restarts of 64 and 80 take the unfused CGS kernels past 52 basis vectors (restarts below
     # about 45 stagnate on this problem, in the oracle's textbook FGMRES as well)
-    opts = fsi.solve_opts(restart=restart, max_iters=6000, rtol=1e-10, inner=tdt)
-    rc, st = fsi.fgmres_solve(P["J64"], _t(b), x, opts, J32=P["J32"] if inner == "f32" else None,
-                              pinv=pinv32 if inner == "f32" else pinv64)
+    opts = fsi.solve_opts(restart=restart, max_iters=6000, rtol=1e-10, inner=tdt,
+                          basis=torch.float32 if inner == "f32b" else torch.float64)
+    rc, st = fsi.fgmres_solve(P["J64"], _t(b), x, opts, J32=P["J32"] if inner != "f64" else None,
+                              pinv=pinv32 if inner != "f64" else pinv64)
     xs = x.cpu().numpy()
     res = np.linalg.norm(b - J @ xs) / np.linalg.norm(b)
     err = np.linalg.norm(xs - x_ref) / np.linalg.norm(x_ref)
@@ -111,9 +113,11 @@ def test_fgmres_c1_matches_dense_lu(inner, restart):
     assert err <= 1e-6
 
 
-def test_fgmres_c2_mixed_precision_reaches_1e10():
+@pytest.mark.parametrize("basis", ["f64", "f32"])
+def test_fgmres_c2_mixed_precision_reaches_1e10(basis):
     """64^3, 200k points, channel boundary conditions: FP32-inner FGMRES to 1e-10 (FP64 residual),
-    the final residual re-checked with the oracle's own full Jacobian apply."""
+    the final residual re-checked with the oracle's own full Jacobian apply; with the Krylov basis
+    in FP64 and in FP32."""
     import torch
     import paper_2601_08266_amd as fsi
     cfg = W.CONFIGS["c2"]
@@ -124,13 +128,14 @@ def test_fgmres_c2_mixed_precision_reaches_1e10():
     b[:3 * N][P["mask"].ravel()] = 0.0
     pinv64, pinv32, _, _ = fsi.bjacobi_setup(P["J64"])
     x = torch.zeros(4 * N, dtype=torch.float64, device="cuda")
-    opts = fsi.solve_opts(restart=50, max_iters=4000, rtol=1e-10, inner=torch.float32)
+    opts = fsi.solve_opts(restart=50, max_iters=4000, rtol=1e-10, inner=torch.float32,
+                          basis=torch.float32 if basis == "f32" else torch.float64)
     rc, st = fsi.fgmres_solve(P["J64"], _t(b), x, opts, J32=P["J32"], pinv=pinv32)
     xs = x.cpu().numpy()
     Jx = ojac.apply(g, P["prm_o"], P["a"], xs, P["cell"], P["xi"], P["kappa"], s=P["s"],
                     mask=P["mask"]).ravel()
     res = np.linalg.norm(b - Jx) / np.linalg.norm(b)
-    print(f"fgmres c2 mixed: iters {st.iters} cycles {st.cycles} {st.t_total_ms:.1f} ms, "
+    print(f"fgmres c2 mixed (basis {basis}): iters {st.iters} cycles {st.cycles} {st.t_total_ms:.1f} ms, "
           f"oracle residual {res:.3e}, solver residual {st.res_final / st.bnorm:.3e}")
     assert res <= 2e-10
 
