@@ -273,21 +273,58 @@ __device__ __forceinline__ void store2(float *p, double2 v)
     *reinterpret_cast<float2 *>(p) = make_float2((float)v.x, (float)v.y);
 }
 
+// E consecutive entries per lane as FP64: pairs (16-byte loads of FP64 data, 8-byte loads of
+// FP32 data alongside an FP64 basis) or quadruples of FP32 data (16-byte loads, an FP32 basis)
+template <int E>
+struct DV {
+    double v[E];
+};
+template <int E, typename T>
+__device__ __forceinline__ DV<E> loadv(const T *p)
+{
+    DV<E> o;
+    if constexpr (E == 2) {
+        const double2 t = load2(p);
+        o.v[0] = t.x;
+        o.v[1] = t.y;
+    } else {
+        static_assert(E == 4 && sizeof(T) == 4, "quadruples are FP32 data");
+        const float4 t = *reinterpret_cast<const float4 *>(p);
+        o.v[0] = t.x;
+        o.v[1] = t.y;
+        o.v[2] = t.z;
+        o.v[3] = t.w;
+    }
+    return o;
+}
+template <int E, typename T>
+__device__ __forceinline__ void storev(T *p, const DV<E> &s)
+{
+    if constexpr (E == 2) {
+        store2(p, make_double2(s.v[0], s.v[1]));
+    } else {
+        static_assert(E == 4 && sizeof(T) == 4, "quadruples are FP32 data");
+        *reinterpret_cast<float4 *>(p) = make_float4((float)s.v[0], (float)s.v[1], (float)s.v[2], (float)s.v[3]);
+    }
+}
+
 // Projection pass of classical Gram-Schmidt with re-orthogonalisation through the Gram matrix:
 // per-block partials of V[k] . w and V[k] . u (u = V[nk-1], the newest basis vector), k < nk, in
 // one read of V: wave wv of a block takes the vectors k = wv + 4q, q < KQ = ceil(nk / 4), and
-// issues their loads together (past nk the last vector is re-read and not accumulated).  The
-// basis (TV) and w (TW) are FP64 or FP32; products and sums are FP64.
+// issues their loads together (past nk it loads nothing and accumulates nothing).  The
+// basis (TV) and w (TW) are FP64 or FP32; products and sums are FP64.  Each lane moves E
+// entries per vector and step (16-byte loads of the basis; E = 4 for an FP32 basis).
 template <int KQ, typename TW, typename TV>
 __global__ __launch_bounds__(KT) void cgs_project_k(int64_t n, int nk, const TV *__restrict__ V,
                                                     int64_t ldv, const TW *__restrict__ w,
                                                     const TV *__restrict__ u,
                                                     double *__restrict__ partial)
 {
+    constexpr int E = sizeof(TV) == 4 ? 4 : 2;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    // chunks of an even number of elements: the loop moves pairs (16-byte loads; n, ldv and
-    // the vector bases are even / 16-byte aligned)
-    const int64_t chunk = ((n + gridDim.x - 1) / gridDim.x + 1) & ~(int64_t)1;
+    // chunks of a multiple of E elements (n, ldv and the vector bases are multiples of E /
+    // 16-byte aligned, checked by the host wrappers)
+    const int64_t chunk = ((n + gridDim.x - 1) / gridDim.x + E - 1) & ~(int64_t)(E - 1);
     const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = lo + chunk < n ? lo + chunk : n;
     const TV *vk[KQ];
@@ -299,19 +336,21 @@ __global__ __launch_bounds__(KT) void cgs_project_k(int64_t n, int nk, const TV 
     double aw[KQ], au[KQ];
 #pragma unroll
     for (int q = 0; q < KQ; ++q) aw[q] = au[q] = 0.0;
-    for (int64_t i = lo + 2 * lane; i < hi; i += 128) {
-        const double2 wi = load2(w + i);
-        const double2 ui = load2(u + i);
-        double2 v[KQ];
+    for (int64_t i = lo + E * lane; i < hi; i += 64 * E) {
+        const DV<E> wi = loadv<E>(w + i);
+        const DV<E> ui = loadv<E>(u + i);
+        DV<E> v[KQ];
 #pragma unroll
-        for (int q = 0; q < KQ; ++q) v[q] = load2(vk[q] + i);
+        for (int q = 0; q < KQ; ++q)   // past nk (uniform over the wave) nothing is loaded
+            v[q] = wv + CG_WAVES * q < nk ? loadv<E>(vk[q] + i) : DV<E>{};
         __builtin_amdgcn_sched_barrier(0);   // keep the loads in flight together
 #pragma unroll
         for (int q = 0; q < KQ; ++q) {
-            aw[q] += v[q].x * wi.x;
-            au[q] += v[q].x * ui.x;
-            aw[q] += v[q].y * wi.y;
-            au[q] += v[q].y * ui.y;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                aw[q] += v[q].v[e] * wi.v[e];
+                au[q] += v[q].v[e] * ui.v[e];
+            }
         }
     }
 #pragma unroll
@@ -327,40 +366,42 @@ __global__ __launch_bounds__(KT) void cgs_project_k(int64_t n, int nk, const TV 
 
 // out = w - V h (nk vectors, in groups of 8 whose loads are issued together) and per-block
 // partials of ||out||^2 (of the FP64 sums, before out is rounded to TO); out may be w itself
-// (TW = TO).
+// (TW = TO).  E entries per lane and step as in the projection.
 template <typename TW, typename TV, typename TO>
 __global__ __launch_bounds__(KT) void axpy_norm_k(int64_t n, int nk, const TV *__restrict__ V,
                                                   int64_t ldv, const double *__restrict__ h,
                                                   const TW *w, TO *out, double *__restrict__ partial)
 {
     constexpr int KB = 8;
+    constexpr int E = sizeof(TV) == 4 ? 4 : 2;
     __shared__ double red[CG_WAVES];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t chunk = ((n + gridDim.x - 1) / gridDim.x + 1) & ~(int64_t)1;
+    const int64_t chunk = ((n + gridDim.x - 1) / gridDim.x + E - 1) & ~(int64_t)(E - 1);
     const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = lo + chunk < n ? lo + chunk : n;
     double acc = 0.0;
-    for (int64_t i = lo + 2 * threadIdx.x; i < hi; i += 2 * KT) {
-        double2 s = load2(w + i);
+    for (int64_t i = lo + E * threadIdx.x; i < hi; i += E * KT) {
+        DV<E> s = loadv<E>(w + i);
         for (int k0 = 0; k0 < nk; k0 += KB) {
-            double2 v[KB];
+            DV<E> v[KB];
             double hk[KB];
 #pragma unroll
             for (int q = 0; q < KB; ++q) {
+                // past nk (a condition uniform over the block) nothing is loaded and the term is 0
                 const int k = k0 + q;
-                v[q] = load2(V + (int64_t)(k < nk ? k : nk - 1) * ldv + i);
+                v[q] = k < nk ? loadv<E>(V + (int64_t)k * ldv + i) : DV<E>{};
                 hk[q] = k < nk ? h[k] : 0.0;
             }
             __builtin_amdgcn_sched_barrier(0);   // keep the loads in flight together
 #pragma unroll
             for (int q = 0; q < KB; ++q) {
-                s.x -= hk[q] * v[q].x;
-                s.y -= hk[q] * v[q].y;
+#pragma unroll
+                for (int e = 0; e < E; ++e) s.v[e] -= hk[q] * v[q].v[e];
             }
         }
-        store2(out + i, s);
-        acc += s.x * s.x;
-        acc += s.y * s.y;
+        storev<E>(out + i, s);
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc += s.v[e] * s.v[e];
     }
     acc = wave_sum(acc);
     if (lane == 0) red[wv] = acc;
@@ -485,9 +526,9 @@ template <typename TW, typename TV>
 static int cgs_project_t(int64_t n, int nk, const TV *V, int64_t ldv, const TW *w, const TV *u,
                          double *partial, double *ab, double *G, int ldg, double *h, hipStream_t st)
 {
-    if ((n | ldv) & 1 || ((uintptr_t)V | (uintptr_t)u) & (2 * sizeof(TV) - 1) ||
-        (uintptr_t)w & (2 * sizeof(TW) - 1)) {
-        set_error("CGS projection needs even lengths and aligned vectors");
+    constexpr int64_t E = sizeof(TV) == 4 ? 4 : 2;
+    if ((n | ldv) & (E - 1) || ((uintptr_t)V | (uintptr_t)u) & 15 || (uintptr_t)w & (E * sizeof(TW) - 1)) {
+        set_error("CGS projection needs lengths divisible by its entries per lane and aligned vectors");
         return FSI_ERR_ARG;
     }
     switch ((nk + CG_WAVES - 1) / CG_WAVES) {
@@ -534,9 +575,10 @@ template <typename TW, typename TV, typename TO>
 static int axpy_norm_t(int64_t n, int nk, const TV *V, int64_t ldv, const double *h, const TW *w,
                        TO *wout, double *partial, double *out, hipStream_t st)
 {
-    if ((n | ldv) & 1 || (uintptr_t)V & (2 * sizeof(TV) - 1) || (uintptr_t)wout & (2 * sizeof(TO) - 1) ||
-        (uintptr_t)w & (2 * sizeof(TW) - 1)) {
-        set_error("CGS update needs even lengths and aligned vectors");
+    constexpr int64_t E = sizeof(TV) == 4 ? 4 : 2;
+    if ((n | ldv) & (E - 1) || (uintptr_t)V & 15 || (uintptr_t)wout & (E * sizeof(TO) - 1) ||
+        (uintptr_t)w & (E * sizeof(TW) - 1)) {
+        set_error("CGS update needs lengths divisible by its entries per lane and aligned vectors");
         return FSI_ERR_ARG;
     }
     hipLaunchKernelGGL((axpy_norm_k<TW, TV, TO>), dim3(KRY_NB), dim3(KT), 0, st, n, nk, V, ldv, h, w, wout,
