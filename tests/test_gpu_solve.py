@@ -235,6 +235,71 @@ def test_residual_matches_oracle(case):
     assert err <= 1e-12
 
 
+_RAGGED_REF = {}
+
+
+def _ragged_newton_reference(g, P, x0, u_old, g_pts, mask, gD):
+    """The oracle's dense Newton state of the ragged step, its tolerance, and the smallest singular
+    value of the oracle's dense full tangent there (computed once per session)."""
+    if not _RAGGED_REF:
+        kappa = P["kappa"]
+        R0 = onewton.residual(g, P["prm_o"], x0, u_old, P["cell"], P["xi"], kappa, g_pts, s=P["s"],
+                              mask=mask, gD=gD)
+        tol = 1e-8 * np.linalg.norm(R0)
+        x_ref, info = onewton.solve_step(g, P["prm_o"], x0, u_old, P["cell"], P["xi"], kappa, g_pts,
+                                         s=P["s"], mask=mask, gD=gD, tol_abs=tol, linear="dense")
+        assert info["converged"]
+        T = onewton.tangent_dense(g, P["prm_o"], x_ref, u_old, P["cell"], P["xi"], kappa, s=P["s"], mask=mask)
+        smin = np.linalg.svd(T, compute_uv=False)[-1]
+        R_ref = onewton.residual(g, P["prm_o"], x_ref, u_old, P["cell"], P["xi"], kappa, g_pts, s=P["s"],
+                                 mask=mask, gD=gD)
+        _RAGGED_REF.update(x_ref=x_ref.ravel(), tol=tol, smin=smin, r_ref=np.linalg.norm(R_ref))
+    return _RAGGED_REF
+
+
+@pytest.mark.parametrize("precond,inner,basis", [("bjacobi", "f64", "f64"), ("schur_tri", "f64", "f64"),
+                                                 ("schur_tri", "f32", "f32")])
+def test_newton_ragged_matches_dense_newton(precond, inner, basis):
+    """One implicit step on the ragged 11x9x6 multi-brick grid (partial bricks in every direction,
+    2500 random points, Dirichlet rows, s): the library's Newton (block-Jacobi, or the Schur form
+    with two velocity steps built once per step, FP64 or FP32 inner solves with an FP32 basis)
+    meets the oracle's residual tolerance, and its state differs from the oracle's dense Newton
+    state by no more than the two residuals allow to first order, (||R(x)|| + ||R(x_ref)||) /
+    sigma_min of the oracle's full tangent.  (This step is badly conditioned, sigma_min about
+    2e-7 with the pressure near 1e5, so a fixed relative bar on the state would not follow from
+    the residual tolerance.)"""
+    import torch
+    import paper_2601_08266_amd as fsi
+    print(f"newton ragged {precond} {inner} basis {basis}", flush=True)
+    cfg, g, P, X, g_pts, u_old, mask, gD, x0 = _step_case("ragged")
+    N = g.num_nodes
+    kappa = P["kappa"]
+    ref = _ragged_newton_reference(g, P, x0, u_old, g_pts, mask, gD)
+    tol = ref["tol"]
+    lamg = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
+    fsi.dlm_BT(g, P["J64"].tables, _t(g_pts), lamg, kappa=_t(kappa))
+    x = _t(x0)
+    tdt = torch.float64 if inner == "f64" else torch.float32
+    opts = fsi.newton_opts(tol_abs=tol, inner=tdt, precond=precond, vel_steps=2 if precond != "bjacobi" else 0,
+                           pc_reuse=precond != "bjacobi",
+                           basis=torch.float32 if basis == "f32" else torch.float64)
+    rc, st = fsi.newton_solve(P["J64"], _t(cfg.c_m * u_old), x, opts,
+                              P32=P["J32"] if inner == "f32" else None, lamg=lamg, gD=_t(gD))
+    xs = x.cpu().numpy()
+    R = onewton.residual(g, P["prm_o"], xs, u_old, P["cell"], P["xi"], kappa, g_pts, s=P["s"],
+                         mask=mask, gD=gD)
+    rn = np.linalg.norm(R)
+    d = xs - ref["x_ref"]
+    bound = (rn + ref["r_ref"]) / ref["smin"]
+    per_field = [float(np.linalg.norm(d.reshape(4, N)[f])) for f in range(4)]
+    print(f"newton ragged {precond} {inner}: {st.newton_iters} Newton / {st.krylov_iters} Krylov, "
+          f"oracle ||R|| {rn:.3e} (tol {tol:.3e}); state difference {np.linalg.norm(d):.3e} "
+          f"(per field {['%.2e' % v for v in per_field]}), first-order bound {bound:.3e}")
+    assert rc == 0
+    assert rn <= tol * 1.01
+    assert np.linalg.norm(d) <= 1.05 * bound
+
+
 def test_residual_weak_viscous_form():
     """The step residual without the strong viscous term (visc_strong = 0) on the ragged
     multi-brick grid, whole vector, FP64."""
