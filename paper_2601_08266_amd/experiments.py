@@ -237,7 +237,10 @@ def solve_c3(rtol=1e-10, restart=50, max_iters=6000, profile=True, chunk=1000, m
     bt = t(b)
     bnorm = norm2(bt)
     y = torch.empty_like(bt)
-    for inner, pinv, name in ((torch.float32, pinv32, "mixed"), (torch.float64, pinv64, "f64")):
+    # mixed_b32: FP32 inner solves that also keep the Krylov basis in FP32
+    sols = {}
+    for inner, pinv, name in ((torch.float32, pinv32, "mixed"), (torch.float32, pinv32, "mixed_b32"),
+                              (torch.float64, pinv64, "f64")):
         if name not in modes:
             continue
         x = torch.zeros(4 * N, dtype=torch.float64, device=dev)
@@ -250,7 +253,8 @@ def solve_c3(rtol=1e-10, restart=50, max_iters=6000, profile=True, chunk=1000, m
         rc = -4
         while iters < max_iters:
             opts = solve_opts(restart=restart, max_iters=min(chunk, max_iters - iters), rtol=rtol,
-                              inner=inner, precond=precond, vel_steps=vel_steps)
+                              inner=inner, precond=precond, vel_steps=vel_steps,
+                              basis=torch.float32 if name == "mixed_b32" else torch.float64)
             rc, st = fgmres_solve(P64, bt, x, opts, J32=P32 if inner == torch.float32 else None,
                                   pinv=pinv, check=False)
             iters += st.iters
@@ -270,12 +274,14 @@ def solve_c3(rtol=1e-10, restart=50, max_iters=6000, profile=True, chunk=1000, m
                "ms_per_iter": round(ms / max(iters, 1), 3), "history": hist}
         _log(f"c3 {name}: rc {rc} iters {iters} cycles {cycles} {ms:.0f} ms residual {res:.3e}")
         out[name] = row
-        if name == "mixed":
-            x_mixed = x.clone()
-        elif "mixed" in out:
-            d = x.clone()
-            axpby(-1.0, x_mixed, 1.0, d)
-            out["rel_diff_mixed_vs_f64"] = norm2(d) / norm2(x)
+        sols[name] = x.clone()
+    # the mixed-precision solutions against the FP64 one (or the FP32-basis one against the FP64-basis one)
+    ref_name = "f64" if "f64" in sols else ("mixed" if "mixed_b32" in sols else None)
+    for name in ("mixed", "mixed_b32"):
+        if ref_name is not None and name in sols and name != ref_name:
+            d = sols[name].clone()
+            axpby(-1.0, sols[ref_name], 1.0, d)
+            out[f"rel_diff_{name}_vs_{ref_name}"] = norm2(d) / norm2(sols[ref_name])
     if profile:
         # per-phase GPU time of 500 iterations of one more mixed solve, from the library's per-range events
         x = torch.zeros(4 * N, dtype=torch.float64, device=dev)
@@ -292,8 +298,9 @@ def solve_c3(rtol=1e-10, restart=50, max_iters=6000, profile=True, chunk=1000, m
             ph[name] = {"ms_total": round(tot, 2), "calls": n}
         profile_enable(False)
         out["phases_mixed"] = ph
-    if "mixed" in out and "f64" in out:
-        out["speedup_mixed_vs_f64"] = round(out["f64"]["ms"] / out["mixed"]["ms"], 3)
+    for m in ("mixed", "mixed_b32"):
+        if m in out and "f64" in out:
+            out[f"speedup_{m}_vs_f64"] = round(out["f64"]["ms"] / out[m]["ms"], 3)
     return out
 
 
