@@ -651,6 +651,8 @@ def main(argv=None):
     ap.add_argument("--exp-modes", default=None,
                     help="comma list: c3 inner precisions (mixed,f64); c5/probe Newton modes "
                          "(plain|extrap|nn _ mixed|f64, suffix _st / _sd for the Schur preconditioner)")
+    ap.add_argument("--exp-basis32", action="store_true",
+                    help="solid_steps: FP32 inner solves keep their Krylov basis in FP32")
     ap.add_argument("--exp-precond", default="bjacobi", choices=["bjacobi", "schur_diag", "schur_tri"],
                     help="preconditioner of the c3 solve and of the warmstart run's Newton steps")
     ap.add_argument("--exp-restart", type=int, default=50, help="c3 FGMRES restart length")
@@ -848,7 +850,8 @@ def run_experiment(args):
                                            vel_steps=args.exp_vel_steps, workload=args.workload,
                                            c_stiff=args.exp_c_stiff, integrator=args.exp_integrator,
                                            rho_inf=args.exp_rho_inf, inflow=args.exp_inflow,
-                                           gravity=(0.0, 0.0, -args.exp_gravity) if args.exp_gravity else None)}))
+                                           gravity=(0.0, 0.0, -args.exp_gravity) if args.exp_gravity else None,
+                                           basis32=args.exp_basis32)}))
         return 0
     if args.experiment == "probe":
         print(json.dumps({"experiment": "newton_probe",

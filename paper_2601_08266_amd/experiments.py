@@ -394,7 +394,7 @@ def solid_solve(rtol=1e-8, restart=50, max_iters=3000, precond="schur_tri", vel_
 
 
 def solid_steps(steps=3, precond="schur_tri", vel_steps=8, inner="f32", workload="c2", inflow=1.0, c_stiff=0.0,
-                integrator="be", rho_inf=0.5, gravity=None):
+                integrator="be", rho_inf=0.5, gravity=None, basis32=False):
     """Coupled time steps with the elastic plates moving with the fluid (the configuration's
     channel, the plates meshed by hexahedra with about the configuration's point count, stress
     free at rest; inflow u_x = `inflow` on x = 0 from a fluid at rest) through
@@ -408,7 +408,8 @@ def solid_steps(steps=3, precond="schur_tri", vel_steps=8, inner="f32", workload
     n_t, n_f = W.solid_mesh_size(cfg.m_points)
     X0, conn = W.plate_solid_mesh(n_t, n_f)
     run = SolidChannel(cfg, X0, conn, integrator=integrator, rho_inf=rho_inf, precond=precond, vel_steps=vel_steps,
-                       inner=inner, inflow=inflow, kappa=solid_kappa(cfg, X0.shape[1], c_stiff), gravity=gravity)
+                       inner=inner, inflow=inflow, kappa=solid_kappa(cfg, X0.shape[1], c_stiff), gravity=gravity,
+                       basis32=basis32)
     rows = []
     for _ in range(steps):
         rec = run.step()

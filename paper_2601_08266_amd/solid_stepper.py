@@ -36,10 +36,12 @@ class SolidChannel:
     walls) with a solid mesh (X0 [3][M], conn [E][8]) that starts at rest and stress free."""
 
     def __init__(self, cfg, X0, conn, integrator="be", rho_inf=0.5, precond="schur_tri", vel_steps=8,
-                 inner="f32", inflow=1.0, kappa=None, rel_tol=1e-8, max_krylov=6000, gravity=None):
+                 inner="f32", inflow=1.0, kappa=None, rel_tol=1e-8, max_krylov=6000, gravity=None,
+                 basis32=False):
         dev = torch.device("cuda")
         self.cfg, self.g = cfg, cfg.grid
         self.dev = dev
+        self.basis32 = basis32   # FP32 inner solves keep their Krylov basis in FP32
         g = self.g
         N = g.num_nodes
         self.N, self.M = N, X0.shape[1]
@@ -114,7 +116,8 @@ class SolidChannel:
         U_st = torch.empty_like(self.U)
         Vs_st = torch.empty_like(self.Vs)
         opts = newton_opts(tol, max_newton=30, inner=self.inner, precond=self.precond, vel_steps=self.vel_steps,
-                           max_krylov=self.max_krylov)
+                           max_krylov=self.max_krylov,
+                           basis=torch.float32 if self.basis32 and self.inner == torch.float32 else torch.float64)
         t1 = time.perf_counter()
         rc, st = newton_solid_solve(probs[0], self.solid, state, f, x_st, U_st, Vs_st, opts,
                                     P32=probs[1] if self.inner == torch.float32 else None, gD=self.gD, check=False)
